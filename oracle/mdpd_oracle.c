@@ -1,0 +1,653 @@
+/*
+ * mdpd_oracle.c -- plain FP64 CPU reference of one many-body DPD (mDPD)
+ * timestep, used ONLY as test infrastructure: the parity tests, the smoke
+ * check and the CPU-baseline leg of the benchmark call it.  The GPU library
+ * never links, includes or calls anything in this directory, and this file
+ * shares no code, header, table or constant with the GPU library.
+ *
+ * Everything here is written for clarity, not speed: O(N^2) brute-force pair
+ * search (the definition), plus an independently written naive linked-cell
+ * search that must return exactly the same neighbour lists (so exactly the
+ * same sums), used for large systems.  Neighbours of particle i are always
+ * visited in increasing index order, so every per-particle sum has one fixed
+ * order regardless of search mode or thread count.
+ *
+ * What it computes follows the paper (Xia et al., "A GPU-accelerated package
+ * for simulation of flow in nanoporous source rocks with many-body
+ * dissipative particle dynamics"):
+ *   - pair forces F = F^C + F^D + F^R, dissipative and random parts with the
+ *     fluctuation-dissipation relation sigma^2 = 2 gamma kT, w^D = (w^R)^2,
+ *     w^R = w^C = 1 - r/r_c                                  (Sec. 2.1)
+ *   - mDPD conservative force A w^C rhat + B (rho_i + rho_j) w_d rhat with
+ *     w_d = 1 - r/r_d, r_d < r_c                              (Sec. 2.1, Eq. 1)
+ *   - many-body density rho_i = sum_{j != i} w_rho(r_ij),
+ *     w_rho = 15/(2 pi r_d^3) (1 - r/r_d)^2, normalised so that the integral
+ *     of 4 pi r^2 w_rho over r is one                        (Sec. 2.1)
+ *   - velocity-Verlet in the order x(t+dt), phi, rho, f(t+dt), v(t+dt)
+ *                                                             (Sec. 3.2, Alg. 1)
+ *   - wall treatment: boundary volume fraction phi of a fluid particle from
+ *     local frozen (wall) particles and a predictor-corrector that rejects
+ *     a predicted position that penetrates the wall          (Sec. 2.2, 3.2)
+ *
+ * Readings where the paper is silent (each is listed with its reason in the
+ * design notes of the repository):
+ *   R1  xi_ij = theta_ij / sqrt(dt), theta uniform on [-sqrt3, sqrt3] (zero
+ *       mean, unit variance), drawn from Threefry-2x32-20 (Salmon et al.,
+ *       SC'11) with key (seed, step) and counter (min(i,j), max(i,j)).
+ *   R2  The dissipative force uses the half-step velocity of the standard
+ *       velocity-Verlet loop; frozen particles have v = 0.
+ *   R3  Cutoffs are strict (r < r_c, r < r_d); a coincident pair (r = 0)
+ *       contributes w_rho(0) to the density and no pair force.
+ *   R4  phi_i = sum_{frozen j, r<r_c} w_c^2 / sum_{j != i, r<r_c} w_c^2;
+ *       if phi_i(x*) > phi_c the predicted step is rejected: x* <- x(t),
+ *       v_half <- -v_half (bounce-back, no-slip).
+ *   R5  Mass m; body force acts on fluid as m*g.
+ * parity pinned: every function here is checked by tests/test_oracle_pins.py
+ * against known-answer vectors, closed forms, conservation laws and the
+ * equations of state the paper prints.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXT 8
+
+typedef struct {
+    double L[3];
+    double rc, rd, kT, dt, mass;
+    double g[3];
+    double phi_c;
+    double A[ORC_MAXT * ORC_MAXT];
+    double B[ORC_MAXT * ORC_MAXT];
+    double gamma[ORC_MAXT * ORC_MAXT];
+    uint32_t seed;
+    int32_t ntypes;
+    int32_t wall_model; /* 0: no wall treatment, 1: phi + predictor-corrector */
+    int32_t search;     /* 0: brute force O(N^2), 1: naive linked cells   */
+} orc_params;
+
+/* ------------------------------------------------------------------------ */
+/* Threefry-2x32 with 20 rounds (Salmon, Moraes, Dror, Shaw, SC'11).         */
+/* Key schedule: ks2 = 0x1BD11BDA ^ k0 ^ k1; key injection after every four  */
+/* rounds adds ks[s%3], ks[(s+1)%3] and the injection counter s.             */
+/* ------------------------------------------------------------------------ */
+static uint32_t orc_rotl32(uint32_t x, unsigned r) { return (x << r) | (x >> (32u - r)); }
+
+void orc_threefry2x32_20(const uint32_t ctr[2], const uint32_t key[2], uint32_t out[2])
+{
+    static const unsigned rot[8] = {13, 15, 26, 6, 17, 29, 16, 24};
+    uint32_t ks[3];
+    ks[0] = key[0];
+    ks[1] = key[1];
+    ks[2] = 0x1BD11BDAu ^ key[0] ^ key[1];
+    uint32_t x0 = ctr[0] + ks[0];
+    uint32_t x1 = ctr[1] + ks[1];
+    for (int r = 0; r < 20; ++r) {
+        x0 += x1;
+        x1 = orc_rotl32(x1, rot[r % 8]);
+        x1 ^= x0;
+        if (r % 4 == 3) {
+            uint32_t s = (uint32_t)(r / 4 + 1);
+            x0 += ks[s % 3];
+            x1 += ks[(s + 1) % 3] + s;
+        }
+    }
+    out[0] = x0;
+    out[1] = x1;
+}
+
+/* theta_ij: the first output word of Threefry with key (seed, step) and
+ * counter (min id, max id); its top 24 bits k give the odd-centred uniform
+ * t = (2k + 1 - 2^24) / 2^24 in (-1, 1), exact in binary, and
+ * theta = sqrt(3) * t has zero mean and unit variance (reading R1). */
+double orc_theta(uint32_t seed, uint32_t step, uint32_t i, uint32_t j)
+{
+    uint32_t ctr[2], key[2], out[2];
+    ctr[0] = i < j ? i : j;
+    ctr[1] = i < j ? j : i;
+    key[0] = seed;
+    key[1] = step;
+    orc_threefry2x32_20(ctr, key, out);
+    double k = (double)(out[0] >> 8);
+    double t = (2.0 * k + 1.0 - 16777216.0) / 16777216.0;
+    return sqrt(3.0) * t;
+}
+
+/* SplitMix64 output function (Steele, Lea, Flood, OOPSLA'14) used as the
+ * element mixer of an order-independent neighbour-set hash. */
+uint64_t orc_mix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry: minimum image by branch, squared distance without contraction. */
+/* ------------------------------------------------------------------------ */
+static double orc_min_image(double d, double L)
+{
+    if (d > 0.5 * L)
+        d -= L;
+    else if (d < -0.5 * L)
+        d += L;
+    return d;
+}
+
+static void orc_delta(const double *x, int64_t i, int64_t j, const double L[3], double d[3])
+{
+    for (int a = 0; a < 3; ++a) d[a] = orc_min_image(x[3 * i + a] - x[3 * j + a], L[a]);
+}
+
+static double orc_r2(const double d[3])
+{
+    double s = d[0] * d[0];
+    s = s + d[1] * d[1];
+    s = s + d[2] * d[2];
+    return s;
+}
+
+/* Wrap one coordinate that lies in [-L, 2L) into [0, L). */
+double orc_wrap(double x, double L)
+{
+    if (x < 0.0) x += L;
+    if (x >= L) x -= L;
+    return x;
+}
+
+/* Normalised many-body density weight (Sec. 2.1): 15/(2 pi r_d^3)(1-r/r_d)^2
+ * for r < r_d, zero beyond. */
+double orc_w_rho(double r, double rd)
+{
+    if (r >= rd) return 0.0;
+    double u = 1.0 - r / rd;
+    return 15.0 / (2.0 * M_PI * rd * rd * rd) * u * u;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbour lists: for every i, all j != i with r_ij^2 < cutoff^2, in     */
+/* increasing j.                                                            */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;
+    int32_t *cnt;
+    int32_t **idx;
+} orc_nlist;
+
+static void orc_nlist_free(orc_nlist *nl)
+{
+    if (!nl->idx) return;
+    for (int64_t i = 0; i < nl->n; ++i) free(nl->idx[i]);
+    free(nl->idx);
+    free(nl->cnt);
+    nl->idx = NULL;
+    nl->cnt = NULL;
+}
+
+static int orc_cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+static void orc_push(int32_t **buf, int32_t *cap, int32_t *len, int32_t v)
+{
+    if (*len == *cap) {
+        *cap = *cap ? 2 * *cap : 64;
+        *buf = (int32_t *)realloc(*buf, (size_t)*cap * sizeof(int32_t));
+    }
+    (*buf)[(*len)++] = v;
+}
+
+static void orc_build_bruteforce(const double *x, int64_t n, const double L[3], double cut2,
+                                 orc_nlist *nl)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t *buf = NULL, cap = 0, len = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            orc_delta(x, i, j, L, d);
+            if (orc_r2(d) < cut2) orc_push(&buf, &cap, &len, (int32_t)j);
+        }
+        nl->cnt[i] = len;
+        nl->idx[i] = buf;
+    }
+}
+
+/* Naive linked cells: cells no smaller than the cutoff (with a relative
+ * margin far above rounding), 27-cell stencil, hits sorted by index so the
+ * lists equal the brute-force ones. */
+static int orc_build_cells(const double *x, int64_t n, const double L[3], double cutoff,
+                           double cut2, orc_nlist *nl)
+{
+    int nc[3];
+    for (int a = 0; a < 3; ++a) {
+        nc[a] = (int)floor(L[a] / (cutoff * (1.0 + 1e-10)));
+        if (nc[a] < 3) return 0;
+    }
+    int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    int64_t *head = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
+    int64_t *next = (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
+    int32_t *cell = (int32_t *)malloc((size_t)(n ? n : 1) * 3 * sizeof(int32_t));
+    for (int64_t c = 0; c < ncell; ++c) head[c] = -1;
+    for (int64_t i = n - 1; i >= 0; --i) {
+        int c3[3];
+        for (int a = 0; a < 3; ++a) {
+            int c = (int)floor(x[3 * i + a] / (L[a] / nc[a]));
+            if (c < 0) c = 0;
+            if (c >= nc[a]) c = nc[a] - 1;
+            c3[a] = c;
+            cell[3 * i + a] = c;
+        }
+        int64_t lin = c3[0] + (int64_t)nc[0] * (c3[1] + (int64_t)nc[1] * c3[2]);
+        next[i] = head[lin];
+        head[lin] = i;
+    }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t *buf = NULL, cap = 0, len = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int cx = (cell[3 * i] + dx + nc[0]) % nc[0];
+                    int cy = (cell[3 * i + 1] + dy + nc[1]) % nc[1];
+                    int cz = (cell[3 * i + 2] + dz + nc[2]) % nc[2];
+                    int64_t lin = cx + (int64_t)nc[0] * (cy + (int64_t)nc[1] * cz);
+                    for (int64_t j = head[lin]; j >= 0; j = next[j]) {
+                        if (j == i) continue;
+                        double d[3];
+                        orc_delta(x, i, j, L, d);
+                        if (orc_r2(d) < cut2) orc_push(&buf, &cap, &len, (int32_t)j);
+                    }
+                }
+        if (len > 1) qsort(buf, (size_t)len, sizeof(int32_t), orc_cmp_i32);
+        nl->cnt[i] = len;
+        nl->idx[i] = buf;
+    }
+    free(head);
+    free(next);
+    free(cell);
+    return 1;
+}
+
+static void orc_build(const double *x, int64_t n, const double L[3], double cutoff, int search,
+                      orc_nlist *nl)
+{
+    nl->n = n;
+    nl->cnt = (int32_t *)calloc((size_t)(n ? n : 1), sizeof(int32_t));
+    nl->idx = (int32_t **)calloc((size_t)(n ? n : 1), sizeof(int32_t *));
+    double cut2 = cutoff * cutoff;
+    if (search == 1 && orc_build_cells(x, n, L, cutoff, cut2, nl)) return;
+    orc_build_bruteforce(x, n, L, cut2, nl);
+}
+
+/* Per-particle neighbour count and order-independent set hash
+ * (sum over j of mix64(j), modulo 2^64). */
+void orc_neighbors(const orc_params *p, int64_t n, const double *x, double cutoff,
+                   int64_t *count, uint64_t *hash)
+{
+    orc_nlist nl;
+    orc_build(x, n, p->L, cutoff, p->search, &nl);
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t h = 0;
+        for (int32_t k = 0; k < nl.cnt[i]; ++k) h += orc_mix64((uint64_t)nl.idx[i][k]);
+        count[i] = nl.cnt[i];
+        hash[i] = h;
+    }
+    orc_nlist_free(&nl);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Many-body density (Sec. 2.1) for every particle, fluid and frozen alike */
+/* (Alg. 1 computes rho for all local particles).                          */
+/* ------------------------------------------------------------------------ */
+static void orc_density_nl(const orc_params *p, int64_t n, const double *x, const orc_nlist *nl,
+                           double *rho)
+{
+    double rd2 = p->rd * p->rd;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int32_t k = 0; k < nl->cnt[i]; ++k) {
+            int64_t j = nl->idx[i][k];
+            double d[3];
+            orc_delta(x, i, j, p->L, d);
+            double r2 = orc_r2(d);
+            if (r2 < rd2) s += orc_w_rho(sqrt(r2), p->rd);
+        }
+        rho[i] = s;
+    }
+}
+
+void orc_density(const orc_params *p, int64_t n, const double *x, double *rho)
+{
+    orc_nlist nl;
+    orc_build(x, n, p->L, p->rc, p->search, &nl);
+    orc_density_nl(p, n, x, &nl, rho);
+    orc_nlist_free(&nl);
+}
+
+/* Boundary volume fraction of fluid particles (reading R4); frozen: 0. */
+static void orc_phi_nl(const orc_params *p, int64_t n, const double *x, const uint8_t *frozen,
+                       const orc_nlist *nl, double *phi)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        if (frozen[i]) {
+            phi[i] = 0.0;
+            continue;
+        }
+        double num = 0.0, den = 0.0;
+        for (int32_t k = 0; k < nl->cnt[i]; ++k) {
+            int64_t j = nl->idx[i][k];
+            double d[3];
+            orc_delta(x, i, j, p->L, d);
+            double w = 1.0 - sqrt(orc_r2(d)) / p->rc;
+            den += w * w;
+            if (frozen[j]) num += w * w;
+        }
+        phi[i] = den > 0.0 ? num / den : 0.0;
+    }
+}
+
+void orc_phi(const orc_params *p, int64_t n, const double *x, const uint8_t *frozen, double *phi)
+{
+    orc_nlist nl;
+    orc_build(x, n, p->L, p->rc, p->search, &nl);
+    orc_phi_nl(p, n, x, frozen, &nl, phi);
+    orc_nlist_free(&nl);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pair forces (Sec. 2.1, Eq. 1) on every fluid particle; frozen: 0.        */
+/* virial = sum over fluid i, j in N_c(i) of c_ij r_ij F^C_ij, c_ij = 1/2   */
+/* if j is fluid (pair seen from both sides) and 1 if j is frozen; epair is */
+/* the same weighted sum of the A-term pair potential (A r_c / 2) w_c^2.    */
+/* ------------------------------------------------------------------------ */
+static void orc_forces_nl(const orc_params *p, int64_t n, const double *x, const double *vh,
+                          const int32_t *type, const uint8_t *frozen, const double *rho,
+                          uint32_t step, const orc_nlist *nl, double *F, double *virial,
+                          double *epair)
+{
+    const int T = p->ntypes;
+    const double rc = p->rc, rd = p->rd, rd2 = rd * rd;
+    const double m = p->mass;
+    double vir = 0.0, ep = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : vir, ep)
+    for (int64_t i = 0; i < n; ++i) {
+        if (frozen[i]) {
+            F[3 * i] = F[3 * i + 1] = F[3 * i + 2] = 0.0;
+            continue;
+        }
+        double f[3] = {0.0, 0.0, 0.0};
+        double vir_i = 0.0, ep_i = 0.0;
+        for (int32_t k = 0; k < nl->cnt[i]; ++k) {
+            int64_t j = nl->idx[i][k];
+            double d[3];
+            orc_delta(x, i, j, p->L, d);
+            double r2 = orc_r2(d);
+            if (r2 == 0.0) continue;
+            double r = sqrt(r2);
+            double e[3] = {d[0] / r, d[1] / r, d[2] / r};
+            int tt = type[i] * T + type[j];
+            double wc = 1.0 - r / rc;
+            /* conservative, Eq. 1 */
+            double fc = p->A[tt] * wc;
+            if (r2 < rd2) fc += p->B[tt] * (rho[i] + rho[j]) * (1.0 - r / rd);
+            /* dissipative: -gamma w^D (rhat . v_ij), w^D = wc^2 */
+            double vj[3] = {0.0, 0.0, 0.0};
+            if (!frozen[j])
+                for (int a = 0; a < 3; ++a) vj[a] = vh[3 * j + a];
+            double ev = e[0] * (vh[3 * i] - vj[0]) + e[1] * (vh[3 * i + 1] - vj[1]) +
+                        e[2] * (vh[3 * i + 2] - vj[2]);
+            double fd = -p->gamma[tt] * wc * wc * ev;
+            /* random: sigma w^R xi, sigma^2 = 2 gamma kT, xi = theta / sqrt(dt) */
+            double sigma = sqrt(2.0 * p->gamma[tt] * p->kT);
+            double fr = sigma * wc * orc_theta(p->seed, step, (uint32_t)i, (uint32_t)j) / sqrt(p->dt);
+            double fs = fc + fd + fr;
+            for (int a = 0; a < 3; ++a) f[a] += fs * e[a];
+            double c = frozen[j] ? 1.0 : 0.5;
+            vir_i += c * r * fc;
+            ep_i += c * 0.5 * p->A[tt] * rc * wc * wc;
+        }
+        for (int a = 0; a < 3; ++a) F[3 * i + a] = f[a] + m * p->g[a];
+        vir += vir_i;
+        ep += ep_i;
+    }
+    if (virial) *virial = vir;
+    if (epair) *epair = ep;
+}
+
+void orc_forces(const orc_params *p, int64_t n, const double *x, const double *vh,
+                const int32_t *type, const uint8_t *frozen, const double *rho, uint32_t step,
+                double *F, double *virial, double *epair)
+{
+    orc_nlist nl;
+    orc_build(x, n, p->L, p->rc, p->search, &nl);
+    orc_forces_nl(p, n, x, vh, type, frozen, rho, step, &nl, F, virial, epair);
+    orc_nlist_free(&nl);
+}
+
+/* ------------------------------------------------------------------------ */
+/* A whole system advanced by velocity-Verlet in the order of Alg. 1.       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    orc_params p;
+    int64_t n, nfluid;
+    double *x, *v, *vh, *F, *rho, *phi, *xprev;
+    int32_t *type;
+    uint8_t *frozen;
+    uint32_t step;
+    int64_t ncorr_last, ncorr_total;
+    double virial, epair;
+} orc_system;
+
+static void orc_eval(orc_system *s)
+{
+    /* rho for all particles, then forces at the current step's noise */
+    orc_nlist nl;
+    orc_build(s->x, s->n, s->p.L, s->p.rc, s->p.search, &nl);
+    orc_density_nl(&s->p, s->n, s->x, &nl, s->rho);
+    orc_forces_nl(&s->p, s->n, s->x, s->vh, s->type, s->frozen, s->rho, s->step, &nl, s->F,
+                  &s->virial, &s->epair);
+    orc_nlist_free(&nl);
+}
+
+void orc_destroy(orc_system *s)
+{
+    if (!s) return;
+    free(s->x);
+    free(s->v);
+    free(s->vh);
+    free(s->F);
+    free(s->rho);
+    free(s->phi);
+    free(s->xprev);
+    free(s->type);
+    free(s->frozen);
+    free(s);
+}
+
+/* Positions must lie in [-L, 2L) per axis; they are wrapped into [0, L).
+ * Forces at creation use the given velocities and noise step 0. */
+orc_system *orc_create(const orc_params *p, int64_t n, const double *x, const double *v,
+                       const int32_t *type, const uint8_t *frozen)
+{
+    orc_system *s = (orc_system *)calloc(1, sizeof(orc_system));
+    size_t nn = (size_t)(n ? n : 1);
+    s->p = *p;
+    s->n = n;
+    s->x = (double *)malloc(nn * 3 * sizeof(double));
+    s->v = (double *)malloc(nn * 3 * sizeof(double));
+    s->vh = (double *)malloc(nn * 3 * sizeof(double));
+    s->F = (double *)malloc(nn * 3 * sizeof(double));
+    s->xprev = (double *)malloc(nn * 3 * sizeof(double));
+    s->rho = (double *)malloc(nn * sizeof(double));
+    s->phi = (double *)calloc(nn, sizeof(double));
+    s->type = (int32_t *)malloc(nn * sizeof(int32_t));
+    s->frozen = (uint8_t *)malloc(nn);
+    for (int64_t i = 0; i < n; ++i) {
+        s->type[i] = type[i];
+        s->frozen[i] = frozen[i] ? 1 : 0;
+        if (!s->frozen[i]) s->nfluid++;
+        for (int a = 0; a < 3; ++a) {
+            s->x[3 * i + a] = orc_wrap(x[3 * i + a], p->L[a]);
+            double va = s->frozen[i] ? 0.0 : v[3 * i + a];
+            s->v[3 * i + a] = va;
+            s->vh[3 * i + a] = va;
+        }
+    }
+    s->step = 0;
+    orc_eval(s);
+    return s;
+}
+
+void orc_step(orc_system *s, int64_t nsteps)
+{
+    const int64_t n = s->n;
+    const double hdtm = 0.5 * s->p.dt / s->p.mass;
+    for (int64_t it = 0; it < nsteps; ++it) {
+        /* v(t+dt/2) and predicted x(t+dt) for fluid; frozen stay put */
+        for (int64_t i = 0; i < n; ++i) {
+            for (int a = 0; a < 3; ++a) s->xprev[3 * i + a] = s->x[3 * i + a];
+            if (s->frozen[i]) continue;
+            for (int a = 0; a < 3; ++a) {
+                s->vh[3 * i + a] = s->v[3 * i + a] + hdtm * s->F[3 * i + a];
+                s->x[3 * i + a] = orc_wrap(s->x[3 * i + a] + s->p.dt * s->vh[3 * i + a], s->p.L[a]);
+            }
+        }
+        /* phi for fluid at the predicted positions, then the corrector */
+        s->ncorr_last = 0;
+        if (s->p.wall_model) {
+            orc_phi(&s->p, n, s->x, s->frozen, s->phi);
+            for (int64_t i = 0; i < n; ++i) {
+                if (s->frozen[i] || !(s->phi[i] > s->p.phi_c)) continue;
+                for (int a = 0; a < 3; ++a) {
+                    s->x[3 * i + a] = s->xprev[3 * i + a];
+                    s->vh[3 * i + a] = -s->vh[3 * i + a];
+                }
+                s->ncorr_last++;
+            }
+            s->ncorr_total += s->ncorr_last;
+        }
+        /* rho, f(t+dt), v(t+dt) */
+        s->step += 1;
+        orc_eval(s);
+        for (int64_t i = 0; i < n; ++i) {
+            if (s->frozen[i]) continue;
+            for (int a = 0; a < 3; ++a) s->v[3 * i + a] = s->vh[3 * i + a] + hdtm * s->F[3 * i + a];
+        }
+    }
+}
+
+void orc_get(const orc_system *s, double *x, double *v, double *F, double *rho, double *vh)
+{
+    size_t n = (size_t)s->n;
+    if (x) memcpy(x, s->x, n * 3 * sizeof(double));
+    if (v) memcpy(v, s->v, n * 3 * sizeof(double));
+    if (F) memcpy(F, s->F, n * 3 * sizeof(double));
+    if (rho) memcpy(rho, s->rho, n * sizeof(double));
+    if (vh) memcpy(vh, s->vh, n * 3 * sizeof(double));
+}
+
+/* Observables at the current step:
+ * out[0] step, [1] KE = m/2 sum_f |v|^2, [2] kT = 2 KE / (3 dof) with dof =
+ * N_f - 1 for a periodic fluid without walls or body force (momentum is then
+ * conserved) and N_f otherwise, [3] P = (sum_f m|v|^2 + virial) / (3V),
+ * [4..6] momentum, [7] Epot = epair + sum_i (pi r_d^4 B_ii / 30) rho_i^2,
+ * [8] mean rho over fluid, [9] corrections in the last step, [10] total
+ * corrections, [11] virial. */
+void orc_observables(const orc_system *s, double *out)
+{
+    const int64_t n = s->n;
+    double ke2 = 0.0, mom[3] = {0.0, 0.0, 0.0}, rho_sum = 0.0, emb = 0.0;
+    int driven = (s->p.g[0] != 0.0 || s->p.g[1] != 0.0 || s->p.g[2] != 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        int t = s->type[i];
+        double B = s->p.B[t * s->p.ntypes + t];
+        emb += M_PI * pow(s->p.rd, 4) * B / 30.0 * s->rho[i] * s->rho[i];
+        if (s->frozen[i]) continue;
+        for (int a = 0; a < 3; ++a) {
+            ke2 += s->p.mass * s->v[3 * i + a] * s->v[3 * i + a];
+            mom[a] += s->p.mass * s->v[3 * i + a];
+        }
+        rho_sum += s->rho[i];
+    }
+    double dof = (double)s->nfluid;
+    if (s->nfluid == n && !driven) dof -= 1.0;
+    double V = s->p.L[0] * s->p.L[1] * s->p.L[2];
+    out[0] = (double)s->step;
+    out[1] = 0.5 * ke2;
+    out[2] = dof > 0 ? ke2 / (3.0 * dof) : 0.0;
+    out[3] = (ke2 + s->virial) / (3.0 * V);
+    out[4] = mom[0];
+    out[5] = mom[1];
+    out[6] = mom[2];
+    out[7] = s->epair + emb;
+    out[8] = s->nfluid ? rho_sum / (double)s->nfluid : 0.0;
+    out[9] = (double)s->ncorr_last;
+    out[10] = (double)s->ncorr_total;
+    out[11] = s->virial;
+}
+
+/* Bin profiles of fluid particles along one axis (bins of L/nbins).
+ * quantity 0: number density; 1..3: mean velocity component x, y, z;
+ * 4: kinetic temperature from velocities relative to the bin mean;
+ * 5: mean many-body density.  Empty bins give 0. */
+void orc_profile(const orc_system *s, int axis, int nbins, int quantity, double *out)
+{
+    double *cnt = (double *)calloc((size_t)nbins, sizeof(double));
+    double *sv = (double *)calloc((size_t)nbins * 3, sizeof(double));
+    double *acc = (double *)calloc((size_t)nbins, sizeof(double));
+    double La = s->p.L[axis];
+    for (int64_t i = 0; i < s->n; ++i) {
+        if (s->frozen[i]) continue;
+        int b = (int)floor(s->x[3 * i + axis] / La * nbins);
+        if (b < 0) b = 0;
+        if (b >= nbins) b = nbins - 1;
+        cnt[b] += 1.0;
+        for (int a = 0; a < 3; ++a) sv[3 * b + a] += s->v[3 * i + a];
+        acc[b] += s->rho[i];
+    }
+    double vol = s->p.L[0] * s->p.L[1] * s->p.L[2] / nbins;
+    if (quantity == 4) {
+        double *ss = (double *)calloc((size_t)nbins, sizeof(double));
+        for (int64_t i = 0; i < s->n; ++i) {
+            if (s->frozen[i]) continue;
+            int b = (int)floor(s->x[3 * i + axis] / La * nbins);
+            if (b < 0) b = 0;
+            if (b >= nbins) b = nbins - 1;
+            for (int a = 0; a < 3; ++a) {
+                double u = s->v[3 * i + a] - sv[3 * b + a] / cnt[b];
+                ss[b] += s->p.mass * u * u;
+            }
+        }
+        for (int b = 0; b < nbins; ++b) out[b] = cnt[b] > 0 ? ss[b] / (3.0 * cnt[b]) : 0.0;
+        free(ss);
+    } else {
+        for (int b = 0; b < nbins; ++b) {
+            if (quantity == 0)
+                out[b] = cnt[b] / vol;
+            else if (quantity >= 1 && quantity <= 3)
+                out[b] = cnt[b] > 0 ? sv[3 * b + quantity - 1] / cnt[b] : 0.0;
+            else
+                out[b] = cnt[b] > 0 ? acc[b] / cnt[b] : 0.0;
+        }
+    }
+    free(cnt);
+    free(sv);
+    free(acc);
+}
+
+uint32_t orc_current_step(const orc_system *s) { return s->step; }
+
+/* theta for many (i, j) pairs at once (statistics checks). */
+void orc_theta_many(uint32_t seed, uint32_t step, int64_t m, const uint32_t *i, const uint32_t *j,
+                    double *out)
+{
+    for (int64_t k = 0; k < m; ++k) out[k] = orc_theta(seed, step, i[k], j[k]);
+}

@@ -1,0 +1,311 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test ties part of the oracle to a value the paper prints, a closed form,
+a conservation law, a library routine or a published known-answer vector, so
+that a plausible mistake (dropped term, wrong sign, wrong index, wrong
+constant) fails at least one of them.  CPU only.
+"""
+import numpy as np
+import pytest
+from scipy import integrate, spatial, stats
+
+from paper_1903_10134_amd import workloads as W
+
+SQRT3 = np.sqrt(3.0)
+
+
+def _params(orc, w, **over):
+    kw = w.param_kwargs()
+    kw.update(over)
+    search = kw.pop("search", 1)
+    return orc.make_params(**kw, search=search)
+
+
+# --------------------------------------------------------------------------
+# Random numbers: Threefry-2x32-20 known answers and the theta distribution
+# --------------------------------------------------------------------------
+def test_threefry_known_answer_vectors(orc):
+    # Known-answer vectors published with the Random123 distribution of
+    # Threefry-2x32 at 20 rounds (Salmon et al., SC'11): (counter, key) -> out.
+    kat = [((0x00000000, 0x00000000), (0x00000000, 0x00000000), (0x6B200159, 0x99BA4EFE)),
+           ((0xFFFFFFFF, 0xFFFFFFFF), (0xFFFFFFFF, 0xFFFFFFFF), (0x1CB996FC, 0xBB002BE7)),
+           ((0x243F6A88, 0x85A308D3), (0x13198A2E, 0x03707344), (0xC4923A9C, 0x483DF7A0))]
+    for ctr, key, out in kat:
+        assert orc.threefry2x32_20(ctr, key) == out
+
+
+def test_theta_symmetric_keyed_and_unit_variance(orc):
+    rng = np.random.default_rng(5)
+    i = rng.integers(0, 2**31 - 1, 400_000, dtype=np.int64)
+    j = rng.integers(0, 2**31 - 1, 400_000, dtype=np.int64)
+    t = orc.theta_many(7, 3, i, j)
+    # symmetric in (i, j): the pair draws one number, so F^R_ij = -F^R_ji
+    assert np.array_equal(t, orc.theta_many(7, 3, j, i))
+    # keyed on step and seed
+    assert np.mean(t == orc.theta_many(7, 4, i, j)) < 1e-3
+    assert np.mean(t == orc.theta_many(8, 3, i, j)) < 1e-3
+    n = t.size
+    assert abs(t.mean()) < 3.0 / np.sqrt(n)
+    # uniform on [-sqrt3, sqrt3]: variance 1, var(theta^2) = 9/5 - 1
+    assert abs(t.var() - 1.0) < 3.0 * np.sqrt(0.8 / n)
+    assert t.min() > -SQRT3 and t.max() < SQRT3
+    assert stats.kstest(t, stats.uniform(loc=-SQRT3, scale=2 * SQRT3).cdf).pvalue > 1e-3
+
+
+# --------------------------------------------------------------------------
+# Density weight and the many-body density (Sec. 2.1)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("rd", [0.75, 0.6, 1.0])
+def test_w_rho_normalised_to_one(orc, rd):
+    # The paper requires int_0^inf 4 pi r^2 w_rho(r) dr = 1.
+    val, _ = integrate.quad(lambda r: 4 * np.pi * r * r * orc.w_rho(r, rd), 0.0, rd,
+                            epsabs=1e-13, epsrel=1e-13)
+    assert abs(val - 1.0) < 1e-10
+    assert orc.w_rho(rd, rd) == 0.0 and orc.w_rho(1.5 * rd, rd) == 0.0
+    r = np.linspace(0, rd, 50)
+    w = np.array([orc.w_rho(v, rd) for v in r])
+    assert np.all(np.diff(w) <= 0)
+
+
+def test_uniform_random_mean_density(orc):
+    # For independent uniform positions E[rho_i] = (N - 1) / V exactly,
+    # because w_rho integrates to one.
+    w = W.bulk(L=20.0, density=6.0, seed=11)
+    p = _params(orc, w, search=1)
+    rho = orc.density(p, w.x)
+    expect = (w.n - 1) / 20.0 ** 3
+    assert abs(rho.mean() - expect) < 0.01 * expect
+
+
+def test_two_particles_across_the_periodic_boundary(orc):
+    w = W.bulk(L=5.0, n=2)
+    p = _params(orc, w, search=0)
+    for r in (0.1, 0.5, 0.74):
+        x = np.array([[0.5 * r - 1e-3, 2.0, 2.0], [5.0 - 0.5 * r - 1e-3, 2.0, 2.0]])
+        rho = orc.density(p, x)
+        assert np.allclose(rho, orc.w_rho(r, 0.75), rtol=1e-12, atol=0)
+    x = np.array([[0.2, 2.0, 2.0], [4.2, 2.0, 2.0]])  # r = 1.0 >= r_d
+    assert np.all(orc.density(p, x) == 0.0)
+
+
+def test_lattice_densities(orc):
+    # simple cubic at n = 6: the six nearest neighbours at a = 6^(-1/3) are
+    # the only ones within r_d = 0.75 (next shell at a sqrt2 = 0.778)
+    x, L = W.lattice_sc(6, 6.0)
+    p = orc.make_params(L, -40.0, 25.0, 4.5, search=0)
+    rho = orc.density(p, x)
+    a = 6.0 ** (-1.0 / 3.0)
+    assert np.allclose(rho, 6 * orc.w_rho(a, 0.75), rtol=1e-12)
+    # fcc at n = 6: twelve nearest neighbours at a_cubic / sqrt2 = 0.6177
+    acub = (4.0 / 6.0) ** (1.0 / 3.0)
+    x, L = W.lattice_fcc(4, acub)
+    p = orc.make_params(L, -40.0, 25.0, 4.5, search=1)
+    rho = orc.density(p, x)
+    assert np.allclose(rho, 12 * orc.w_rho(acub / np.sqrt(2.0), 0.75), rtol=1e-12)
+    # fcc with spacing r_c, as in the slab set-up of Sec. 4.1: 12 at 0.7071
+    x, L = W.lattice_fcc(4, 1.0)
+    rho = orc.density(orc.make_params(L, -50.0, 25.0, 12.4, search=0), x)
+    assert np.allclose(rho, 12 * orc.w_rho(np.sqrt(0.5), 0.75), rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Neighbour sets against an independent library routine
+# --------------------------------------------------------------------------
+def _mix64_np(z):
+    z = z.astype(np.uint64) + np.uint64(0x9E3779B97F4A7C15)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def _kdtree_sets(x, L, cut):
+    tree = spatial.cKDTree(x, boxsize=L)
+    pairs = tree.query_pairs(cut, output_type="ndarray")
+    n = x.shape[0]
+    cnt = np.bincount(pairs[:, 0], minlength=n) + np.bincount(pairs[:, 1], minlength=n)
+    h = np.zeros(n, np.uint64)
+    with np.errstate(over="ignore"):
+        np.add.at(h, pairs[:, 0], _mix64_np(pairs[:, 1]))
+        np.add.at(h, pairs[:, 1], _mix64_np(pairs[:, 0]))
+    return cnt, h
+
+
+@pytest.mark.parametrize("search", [0, 1])
+@pytest.mark.parametrize("cut", [1.0, 0.75])
+def test_neighbor_sets_match_kdtree(orc, search, cut):
+    w = W.bulk(L=7.0, density=6.0, seed=3)
+    p = _params(orc, w, search=search)
+    cnt, h = orc.neighbors(p, w.x, cut)
+    kc, kh = _kdtree_sets(w.x, 7.0, cut)
+    assert np.array_equal(cnt, kc)
+    assert np.array_equal(h, kh)
+
+
+def test_linked_cells_equal_bruteforce_on_edges(orc):
+    # particles on cell faces, at 0 and just below L, exact-cutoff pairs
+    L = 5.0
+    rng = np.random.default_rng(2)
+    x = rng.random((600, 3)) * L
+    x[:50, 0] = np.floor(x[:50, 0])            # on cell faces (cells of size 1)
+    x[50:60, 1] = 0.0
+    x[60:70, 1] = np.nextafter(L, 0.0)
+    x[70] = [1.0, 1.0, 1.0]
+    x[71] = [2.0, 1.0, 1.0]                     # r = r_c exactly: not a neighbour
+    p0 = orc.make_params(L, -40.0, 25.0, 4.5, search=0)
+    p1 = orc.make_params(L, -40.0, 25.0, 4.5, search=1)
+    c0, h0 = orc.neighbors(p0, x, 1.0)
+    c1, h1 = orc.neighbors(p1, x, 1.0)
+    assert np.array_equal(c0, c1) and np.array_equal(h0, h1)
+    assert orc.mix64(71) != 0
+    kc, kh = _kdtree_sets(x, L, np.nextafter(1.0, 0.0))
+    assert np.array_equal(c0, kc) and np.array_equal(h0, kh)
+
+
+# --------------------------------------------------------------------------
+# Forces (Sec. 2.1, Eq. 1)
+# --------------------------------------------------------------------------
+def _hamiltonian(orc, p, x, B):
+    """A-term pair potential (A r_c / 2) w_c^2 summed over pairs, plus the
+    many-body term (pi r_d^4 B / 30) rho_i^2 summed over particles."""
+    n = x.shape[0]
+    _, _, epair = orc.forces(p, x, np.zeros((n, 3)), np.zeros(n), np.zeros(n), orc.density(p, x), 0)
+    rho = orc.density(p, x)
+    return epair + np.pi * p.rd ** 4 * B / 30.0 * np.sum(rho * rho)
+
+
+def test_conservative_force_is_minus_energy_gradient(orc):
+    w = W.bulk(L=4.0, density=6.0, seed=4)
+    p = _params(orc, w, search=0, gamma=np.zeros((1, 1)), kT=0.0)
+    n = w.n
+    rho = orc.density(p, w.x)
+    F, _, _ = orc.forces(p, w.x, np.zeros((n, 3)), np.zeros(n), np.zeros(n), rho, 0)
+    h = 1e-6
+    for i in (0, 17, 101, 250):
+        for a in range(3):
+            xp = w.x.copy()
+            xm = w.x.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            g = (_hamiltonian(orc, p, xp, 25.0) - _hamiltonian(orc, p, xm, 25.0)) / (2 * h)
+            assert abs(-g - F[i, a]) < 1e-5 * (1.0 + abs(F[i, a])), (i, a, -g, F[i, a])
+
+
+def test_pair_forces_cancel(orc):
+    # antisymmetric pair forces (shared noise per pair): sum_i F_i = 0
+    w = W.bulk(L=6.0, density=6.0, seed=8)
+    p = _params(orc, w, search=1)
+    rho = orc.density(p, w.x)
+    F, _, _ = orc.forces(p, w.x, w.v, w.types, w.frozen, rho, 5)
+    assert np.all(np.abs(F.sum(axis=0)) < 1e-10 * np.abs(F).sum())
+    s = orc.System(p, w.x, w.v)
+    m0 = np.array([s.observables()[k] for k in ("px", "py", "pz")])
+    s.step(50)
+    m1 = np.array([s.observables()[k] for k in ("px", "py", "pz")])
+    assert np.all(np.abs(m1 - m0) < 1e-9)
+
+
+def test_dissipation_alone_cools(orc):
+    w = W.bulk(L=5.0, density=6.0, seed=9, A=0.0, B=0.0)
+    p = _params(orc, w, search=1, kT=0.0)
+    s = orc.System(p, w.x, w.v)
+    ke = []
+    for _ in range(30):
+        s.step(1)
+        ke.append(s.observables()["ke"])
+    assert np.all(np.diff(ke) < 0)
+
+
+# --------------------------------------------------------------------------
+# Integration: velocity-Verlet
+# --------------------------------------------------------------------------
+def test_energy_conserved_with_second_order_error(orc):
+    # gamma = sigma = 0: H = KE + Epot is conserved by the exact flow and
+    # velocity-Verlet keeps its error bounded with amplitude ~ dt^2.
+    w = W.bulk(L=5.0, density=3.0, seed=1)
+    spread = []
+    for dt in (0.005, 0.0025):
+        p = _params(orc, w, search=0, gamma=np.zeros((1, 1)), kT=0.0, dt=dt)
+        s = orc.System(p, w.x, w.v)
+        E = []
+        for _ in range(int(round(1.0 / dt))):
+            s.step(1)
+            o = s.observables()
+            E.append(o["ke"] + o["epot"])
+        E = np.array(E)
+        assert E.std() < 0.02 * abs(E.mean())
+        spread.append(E.std())
+    ratio = spread[0] / spread[1]
+    assert 3.0 < ratio < 5.5, ratio
+
+
+def test_body_force_adds_momentum_linearly(orc):
+    w = W.bulk(L=5.0, density=6.0, seed=12)
+    g = (0.02, -0.01, 0.005)
+    p = _params(orc, w, search=1, g=g)
+    s = orc.System(p, w.x, w.v)
+    P0 = np.array([s.observables()[k] for k in ("px", "py", "pz")])
+    s.step(40)
+    P1 = np.array([s.observables()[k] for k in ("px", "py", "pz")])
+    expect = P0 + w.n * np.array(g) * 40 * 0.01
+    assert np.allclose(P1, expect, rtol=0, atol=1e-9 * w.n)
+
+
+# --------------------------------------------------------------------------
+# Thermostat (fluctuation-dissipation, Sec. 2.1) and equations of state
+# --------------------------------------------------------------------------
+def _run_avg(orc, w, nsteps, start, **over):
+    p = _params(orc, w, search=1, **over)
+    s = orc.System(p, w.x, w.v)
+    P, T = [], []
+    for k in range(nsteps):
+        s.step(1)
+        if k >= start:
+            o = s.observables()
+            P.append(o["pressure"])
+            T.append(o["kT"])
+    return float(np.mean(P)), float(np.mean(T))
+
+
+@pytest.mark.parametrize("A,B,dt,kT", [(-40.0, 25.0, 0.01, 1.0), (-40.0, 25.0, 0.005, 1.0),
+                                       (0.0, 0.0, 0.01, 1.0), (-40.0, 25.0, 0.01, 2.0)])
+def test_temperature_equilibrates(orc, A, B, dt, kT):
+    w = W.bulk(L=6.0, density=6.0, seed=21, A=A, B=B, dt=dt, kT=kT)
+    steps = int(round(8.0 / dt))
+    _, T = _run_avg(orc, w, steps, steps // 2)
+    assert abs(T / kT - 1.0) < 0.02, T
+
+
+def test_dpd_equation_of_state(orc):
+    # B = 0, a = 25 is the original DPD model; the paper prints its EOS as
+    # p = rho kT + 0.1 a r_c^4 rho^2 (EOS figure, panel a).
+    rho = 5.0
+    w = W.bulk(L=6.0, density=rho, seed=22, A=25.0, B=0.0)
+    P, _ = _run_avg(orc, w, 1000, 400)
+    assert abs(P - (rho + 0.1 * 25.0 * rho ** 2)) < 0.03 * (rho + 0.1 * 25.0 * rho ** 2), P
+
+
+@pytest.mark.parametrize("rho", [7.0, 8.0])
+def test_mdpd_equation_of_state(orc, rho):
+    # EOS figure, panel b: p = rho kT + alpha A rho^2 + 2 alpha B r_d^4
+    # (rho^3 - c rho^2 + d) with alpha = 0.101, c = 4.16, d = 18 for A = -40,
+    # B = 25, r_d = 0.75 (the caption's "2 rho B" is read as "2 alpha B").
+    al, c, d, A, B, rd = 0.101, 4.16, 18.0, -40.0, 25.0, 0.75
+    fit = rho + al * A * rho ** 2 + 2 * al * B * rd ** 4 * (rho ** 3 - c * rho ** 2 + d)
+    w = W.bulk(L=6.0, density=rho, seed=23)
+    P, _ = _run_avg(orc, w, 1000, 400)
+    assert abs(P - fit) < 0.03 * abs(al * A * rho ** 2), (P, fit)
+
+
+# --------------------------------------------------------------------------
+# Wrapping
+# --------------------------------------------------------------------------
+def test_wrap_edges(orc):
+    L = 7.5
+    assert orc.wrap(-1e-300, L) == 0.0 or orc.wrap(-1e-300, L) < L
+    assert orc.wrap(-1e-20, L) == 0.0          # -tiny + L rounds to L, then 0
+    assert orc.wrap(L, L) == 0.0
+    assert orc.wrap(-0.25, L) == L - 0.25
+    assert orc.wrap(L + 0.25, L) == 0.25
+    for v in np.linspace(-L, 2 * L - 1e-9, 101):
+        r = orc.wrap(v, L)
+        assert 0.0 <= r < L
