@@ -1,0 +1,176 @@
+"""Benchmark of the mDPD timestep on one MI355X.
+
+Workload: periodic bulk mDPD liquid, 56 x 56 x 56 box at number density 6
+(1,053,696 particles), A = -40, B = 25, r_c = 1, r_d = 0.75, gamma = 4.5,
+kT = 1, dt = 0.01, uniform-random start, Maxwell velocities (seed 0).  One
+"step" is one full timestep of the hot path: bin + sort, neighbour list,
+density pass, force pass with the velocity-Verlet epilogue.
+
+Prints ONE JSON line: particle-steps/s of the FP32-forces form (value) next
+to the all-FP64 form, the roofline of the force kernel (its average launch
+duration measured with HIP events on the library's stream inside the timed
+region), and the FP64 oracle timed on the host's cores on a bounded sample
+(cpu_baseline).
+
+    python bench.py [--gpus 1] [--steps 1000] [--warmup 100] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks: HBM3E 8 TB/s; VALU 256 CUs x 64 lanes x 2.4 GHz
+# = 39.32 T lane-instructions/s (one FP32/FP64/int32 op per lane per clock,
+# no packed math; FP64 FMA is full rate on CDNA4: 78.6 TFLOP/s = 2 x 39.3 T).
+PEAK_HBM_GBS = 8000.0
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+# Algorithmic VALU operations per unique pair within r_c for the force pass
+# (geometry 13, weights 2, conservative 5, dissipative 9, Threefry-2x32-20
+# first word and the noise scaling 77, accumulation into both particles 8),
+# per unique pair within r_d for the density (14) and per particle for the
+# velocity-Verlet update (20).  Derivation in the design notes.
+OPS_FORCE_PAIR = 114
+OPS_DENSITY_PAIR = 14
+OPS_VV_PARTICLE = 20
+# Algorithmic HBM bytes per particle-step of the whole step (every array
+# touched once): read x 24, v_half 24, tag 4, type 1; write x' 24, v 24,
+# v_half' 24, rho 4 (write) + 4 (read), plus the reorder of x, v_half, tag,
+# type (53 read + 53 write): 263 B (FP32 form; +8 for FP64 rho).
+BYTES_STEP_FP32 = 263
+BYTES_STEP_FP64 = 271
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--L", type=float, default=56.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--lanes", type=str, default="", help="n,d,f lanes per particle")
+    return ap.parse_args()
+
+
+def run_form(mdpd, w, precision, steps, warmup, stream, lanes):
+    import torch
+    s = mdpd.System(w, precision=precision, stream=stream, device_inputs=True)
+    if lanes:
+        for k, v in enumerate(lanes):
+            s.set_lanes(k, v)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    mdpd.mdpd_set_kernel_timing(s.h, True)
+    for k in range(5):
+        mdpd.mdpd_read_kernel_timing(s.h, k)  # reset
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ktime = {name: mdpd.mdpd_read_kernel_timing(s.h, k) for k, name in enumerate(mdpd.KERNELS)}
+    mdpd.mdpd_set_kernel_timing(s.h, False)
+    obs = s.observables()
+    cnt_c, _ = s.neighbors(w.rc)
+    cnt_d, _ = s.neighbors(w.rd)
+    s.close()
+    return dict(sec=t1 - t0, ktime=ktime, obs=obs, pairs_c=int(cnt_c.sum()) // 2,
+                pairs_d=int(cnt_d.sum()) // 2)
+
+
+def cpu_baseline(w, nsteps):
+    import oracle
+    p = oracle.make_params(**w.param_kwargs(), search=1)
+    t0 = time.perf_counter()
+    o = oracle.System(p, w.x, w.v)
+    t1 = time.perf_counter()
+    o.step(nsteps)
+    t2 = time.perf_counter()
+    return dict(value=w.n * nsteps / (t2 - t1), unit="particle-steps/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"{nsteps} steps of the same {w.n}-particle workload with the oracle's "
+                       f"linked-cell search (FP64, OpenMP over particles), after a "
+                       f"{t1 - t0:.1f} s creation")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1903_10134_amd as mdpd
+    from paper_1903_10134_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    w = W.bulk(L=a.L, seed=0)
+    lanes = [int(v) for v in a.lanes.split(",")] if a.lanes else []
+    res = {}
+    for name, prec in (("fp32_forces", mdpd.FP32_FORCES), ("fp64", mdpd.FP64)):
+        res[name] = run_form(mdpd, w, prec, a.steps, a.warmup, stream, lanes)
+        r = res[name]
+        print(f"# {name}: {r['sec'] * 1e3 / a.steps:.3f} ms/step, "
+              + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f} us" for k, v in r["ktime"].items() if v[1]),
+              file=sys.stderr, flush=True)
+
+    head = res["fp32_forces"]
+    n = w.n
+    value = n * a.steps / head["sec"]
+    fms, fcnt = head["ktime"]["force"]
+    favg = fms / max(fcnt, 1) * 1e-3
+    ops_force = head["pairs_c"] * OPS_FORCE_PAIR + n * OPS_VV_PARTICLE
+    achieved = ops_force / favg / 1e12
+    out = {
+        "metric": "mDPD particle-steps/s at 1M particles, FP32 vs FP64 form; adjoint/forward ratio",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": head["sec"] * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"bulk mDPD liquid, periodic {a.L:g}^3 box, {n} particles at density 6",
+                   "n": n, "box": a.L, "A": -40.0, "B": 25.0, "rc": 1.0, "rd": 0.75, "gamma": 4.5,
+                   "kT": 1.0, "dt": 0.01, "form": "FP32 pair forces + FP64 integration"},
+        "forms": {},
+        "roofline": {"bound": "alu", "kernel": "k_force (FP32 form)", "achieved": achieved,
+                     "peak": PEAK_VALU_TOPS, "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_VALU_TOPS,
+                     "traffic": None, "avg_launch_us": favg * 1e6,
+                     "ops_per_launch": ops_force},
+    }
+    for name, r in res.items():
+        bpp = BYTES_STEP_FP32 if name == "fp32_forces" else BYTES_STEP_FP64
+        v = n * a.steps / r["sec"]
+        ops_step = r["pairs_c"] * OPS_FORCE_PAIR + r["pairs_d"] * OPS_DENSITY_PAIR + n * OPS_VV_PARTICLE
+        out["forms"][name] = {
+            "particle_steps_per_s": v,
+            "ms_per_step": r["sec"] * 1e3 / a.steps,
+            "kernel_us": {k: (t[0] / max(t[1], 1) * 1e3) for k, t in r["ktime"].items() if t[1]},
+            "step_valu_frac": ops_step / (r["sec"] / a.steps) / 1e12 / PEAK_VALU_TOPS,
+            "step_hbm_frac": bpp * v / 1e9 / PEAK_HBM_GBS,
+            "pairs_rc": r["pairs_c"], "pairs_rd": r["pairs_d"],
+            "kT": r["obs"]["kT"], "pressure": r["obs"]["pressure"], "mean_rho": r["obs"]["mean_rho"],
+        }
+    out["fp32_over_fp64"] = out["forms"]["fp32_forces"]["particle_steps_per_s"] / \
+        out["forms"]["fp64"]["particle_steps_per_s"]
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * mdpd.h -- C ABI of the MI355X (gfx950) many-body DPD timestep library.
+ *
+ * One timestep of many-body dissipative particle dynamics (mDPD) on one GPU:
+ * cell binning and sort, the many-body density pass, the pair-force pass
+ * (attractive A w_c, density-dependent repulsive B (rho_i + rho_j) w_d,
+ * dissipative and random terms), the wall treatment for fluid against frozen
+ * solid particles, and velocity-Verlet integration.  Model and algorithm:
+ * Xia et al., "A GPU-accelerated package for simulation of flow in
+ * nanoporous source rocks with many-body dissipative particle dynamics",
+ * Sec. 2.1 (Eq. 1 and the density weight), Sec. 2.2 (walls), Sec. 3.2 and
+ * Alg. 1 (order of the timestep).
+ *
+ * Conventions for every call:
+ *   - Every function returns an mdpd_status; MDPD_OK is 0, errors are
+ *     negative.  A human-readable message for the last error of the calling
+ *     thread is returned by mdpd_last_error().  No C++ exception crosses the
+ *     ABI.
+ *   - Particle ids are input indices 0..n-1.  All per-particle outputs are
+ *     returned in input (id) order, whatever the internal sort order.
+ *   - Arrays named "pos", "vel", "force" are n x 3, row-major (x, y, z of
+ *     particle 0 first), float64.
+ *   - mem_kind says where caller arrays live: MDPD_MEM_HOST (pageable or
+ *     pinned host memory) or MDPD_MEM_DEVICE (device memory on the current
+ *     HIP device).  Caller arrays are borrowed for the duration of the call
+ *     only; the library copies what it keeps.
+ *   - All device work is enqueued on the stream given to mdpd_create (NULL
+ *     means the default stream).  Calls that return data to the host
+ *     synchronise that stream.  A handle must not be used from two threads
+ *     at once.
+ */
+#ifndef MDPD_H
+#define MDPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MDPD_MAX_TYPES 8
+
+typedef int32_t mdpd_status;
+
+enum {
+    MDPD_OK = 0,
+    MDPD_E_INVALID = -1,     /* bad argument (size, range, NULL, non-finite)   */
+    MDPD_E_OOM = -2,         /* device or host allocation failed               */
+    MDPD_E_HIP = -3,         /* a HIP runtime call failed                      */
+    MDPD_E_NONFINITE = -4,   /* a non-finite position or velocity appeared     */
+    MDPD_E_STATE = -5,       /* call not valid in the system's current state   */
+    MDPD_E_UNSUPPORTED = -6  /* valid input this build does not handle         */
+};
+
+enum { MDPD_MEM_HOST = 0, MDPD_MEM_DEVICE = 1 };
+
+/* Arithmetic of the pair passes.  In both forms the neighbour test
+ * (r^2 < r_c^2, r^2 < r_d^2) is done in FP64 on FP64 positions, so the
+ * neighbour sets do not depend on the form, and positions, velocities,
+ * velocity-Verlet and global sums are FP64.
+ *   MDPD_FP64         pair math, density and per-particle force sums in FP64
+ *   MDPD_FP32_FORCES  pair math, density and per-particle force sums in FP32 */
+enum { MDPD_FP64 = 0, MDPD_FP32_FORCES = 1 };
+
+/* Wall treatment (Sec. 2.2, Sec. 3.2):
+ *   MDPD_WALL_OFF   frozen particles interact like any other, nothing else
+ *   MDPD_WALL_BVF   boundary volume fraction phi of each fluid particle at its
+ *                   predicted position, phi_i = sum_{frozen j, r<r_c} w_c^2 /
+ *                   sum_{j != i, r<r_c} w_c^2; if phi_i > phi_c the predicted
+ *                   step is rejected (x <- x(t), half-step velocity negated). */
+enum { MDPD_WALL_OFF = 0, MDPD_WALL_BVF = 1 };
+
+typedef struct {
+    double box[3];        /* periodic box edges L_x, L_y, L_z; each >= 3 r_c      */
+    double rc;            /* cutoff of w_c = 1 - r/r_c (Sec. 2.1)                 */
+    double rd;            /* cutoff of w_d = 1 - r/r_d and of w_rho; 0 < r_d <= r_c */
+    double kT;            /* target temperature; sigma^2 = 2 gamma kT             */
+    double dt;            /* timestep                                             */
+    double mass;          /* particle mass (all particles)                        */
+    double body_force[3]; /* acceleration g on fluid particles (force m g)        */
+    double phi_c;         /* wall threshold for MDPD_WALL_BVF                     */
+    double A[MDPD_MAX_TYPES * MDPD_MAX_TYPES];     /* A[t_i*ntypes + t_j], symmetric */
+    double B[MDPD_MAX_TYPES * MDPD_MAX_TYPES];     /* B >= 0, symmetric             */
+    double gamma[MDPD_MAX_TYPES * MDPD_MAX_TYPES]; /* gamma >= 0, symmetric         */
+    uint32_t seed;        /* key word 0 of the pair noise generator               */
+    int32_t ntypes;       /* 1..MDPD_MAX_TYPES                                    */
+    int32_t precision;    /* MDPD_FP64 or MDPD_FP32_FORCES                        */
+    int32_t wall_model;   /* MDPD_WALL_OFF or MDPD_WALL_BVF                       */
+} mdpd_params;
+
+/* Observables at the current step (all FP64 sums in a fixed order):
+ *   ke        = m/2 sum over fluid |v|^2
+ *   kT        = 2 ke / (3 dof), dof = N_f - 1 for a periodic fluid with no
+ *               frozen particles and no body force, N_f otherwise
+ *   pressure  = (sum over fluid m |v|^2 + virial) / (3 V)
+ *   virial    = sum over fluid i and neighbours j of c_ij r_ij F^C_ij,
+ *               c_ij = 1/2 for fluid j, 1 for frozen j
+ *   epot      = the same weighted sum of (A r_c / 2) w_c^2 plus
+ *               sum over all particles (pi r_d^4 B_ii / 30) rho_i^2
+ *   mean_rho  = mean many-body density of fluid particles
+ *   ncorr_*   = wall corrections in the last step and since creation */
+typedef struct {
+    int64_t step;
+    int64_t n, n_fluid;
+    int64_t ncorr_last, ncorr_total;
+    double ke, kT, pressure, virial, epot, mean_rho;
+    double momentum[3];
+} mdpd_observables;
+
+typedef struct mdpd_system mdpd_system; /* opaque; owned by the library */
+
+/* Create a system and evaluate density and forces at t = 0 with the given
+ * velocities and noise step 0.
+ *   p       parameters, copied.  box >= 3 r_c per axis, 0 < rd <= rc, dt > 0,
+ *           mass > 0, kT >= 0, symmetric tables with B, gamma >= 0.
+ *   n       number of particles, 0 <= n < 2^31 (n = 0 gives an empty system)
+ *   pos     n x 3 positions, each coordinate in [-L, 2L); wrapped into [0, L)
+ *   vel     n x 3 velocities (ignored for frozen particles, which get 0)
+ *   type    n type indices in [0, ntypes)
+ *   frozen  n flags, nonzero = frozen wall particle (never moves)
+ *   stream  hipStream_t to enqueue on (NULL: default stream)
+ *   out     receives the handle; *out is NULL on error.
+ * Errors: MDPD_E_INVALID (arguments), MDPD_E_UNSUPPORTED (box < 3 r_c),
+ * MDPD_E_OOM, MDPD_E_HIP. */
+mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, const double *vel,
+                        const int32_t *type, const uint8_t *frozen, int32_t mem_kind,
+                        void *stream, mdpd_system **out);
+
+/* Advance nsteps >= 0 timesteps in the order of Alg. 1: half kick and drift
+ * x(t+dt), [wall: phi and corrector], rho for all particles, forces
+ * f(t+dt) with noise step = the new step number, v(t+dt).  Synchronises the
+ * stream at the end and returns MDPD_E_NONFINITE if any position or
+ * velocity became non-finite (the state is then undefined). */
+mdpd_status mdpd_step(mdpd_system *s, int64_t nsteps);
+
+/* Observables of the current state (see mdpd_observables). */
+mdpd_status mdpd_read_observables(mdpd_system *s, mdpd_observables *out);
+
+/* Profile of fluid particles in nbins (1..4096) equal bins of L_axis along
+ * axis (0..2).  quantity 0: number density; 1..3: mean velocity x, y, z;
+ * 4: kinetic temperature of velocities relative to the bin mean; 5: mean
+ * many-body density.  Empty bins give 0.  out: nbins doubles, host. */
+mdpd_status mdpd_read_profile(mdpd_system *s, int32_t axis, int32_t nbins, int32_t quantity,
+                              double *out);
+
+/* Current positions (wrapped into [0, L)), velocities v(t) and, if rho is
+ * not NULL, many-body densities (n), in input order, into caller arrays. */
+mdpd_status mdpd_get_state(mdpd_system *s, double *pos, double *vel, double *rho,
+                           int32_t mem_kind);
+
+/* Neighbour sets of the hot path at the current positions: for each
+ * particle the number of j != i with r_ij^2 < cutoff^2 (0 < cutoff <= r_c)
+ * and the order-independent hash sum_j mix64(j) mod 2^64, where mix64 is the
+ * SplitMix64 output function.  count and hash: n entries, host. */
+mdpd_status mdpd_debug_neighbors(mdpd_system *s, double cutoff, int64_t *count, uint64_t *hash);
+
+/* Total force (pairs plus body force) on each particle from the last force
+ * evaluation, n x 3, host; zero for frozen particles. */
+mdpd_status mdpd_debug_forces(mdpd_system *s, double *force);
+
+/* Kernel timing with HIP events on the system's stream.  enable = 1 records
+ * an event pair around every launch of each timed kernel from then on;
+ * mdpd_read_kernel_timing returns the summed duration in milliseconds and
+ * the number of launches of kernel class k (0: sort, 1: neighbour list,
+ * 2: density, 3: force, 4: wall) and resets the counters. */
+mdpd_status mdpd_set_kernel_timing(mdpd_system *s, int32_t enable);
+mdpd_status mdpd_read_kernel_timing(mdpd_system *s, int32_t kernel, double *total_ms,
+                                    int64_t *launches);
+
+/* Work split of the pair passes: lanes (1, 2, 4, 8 or 16) of a 64-wide
+ * wavefront cooperate on one particle in pass 0 (neighbour list), 1 (density
+ * and wall fraction) or 2 (force).  Results do not depend on pass 0's
+ * setting; passes 1 and 2 change only the summation order. */
+mdpd_status mdpd_set_lanes(mdpd_system *s, int32_t pass, int32_t lanes);
+
+/* Release the system and its device memory.  NULL is ignored. */
+void mdpd_destroy(mdpd_system *s);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *mdpd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDPD_H */

@@ -86,6 +86,8 @@ def lib():
         L.orc_observables.argtypes = [ctypes.c_void_p, P(d)]
         L.orc_profile.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(d)]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = ctypes.c_int
         L.orc_current_step.argtypes = [ctypes.c_void_p]
         L.orc_current_step.restype = ctypes.c_uint32
         _lib = L
@@ -120,6 +122,11 @@ def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=
     p.wall_model = int(wall_model)
     p.search = int(search)
     return p
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(lib().orc_num_threads())
 
 
 def threefry2x32_20(ctr, key):

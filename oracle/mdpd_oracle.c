@@ -651,3 +651,16 @@ void orc_theta_many(uint32_t seed, uint32_t step, int64_t m, const uint32_t *i, 
 {
     for (int64_t k = 0; k < m; ++k) out[k] = orc_theta(seed, step, i[k], j[k]);
 }
+
+/* Number of threads the OpenMP loops above use (1 without OpenMP). */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

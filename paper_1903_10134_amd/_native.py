@@ -1,0 +1,301 @@
+"""ctypes binding of ``libmdpd.so`` (the C ABI in ``include/mdpd.h``).
+
+Argument marshalling only: every step of the timestep runs in the library's
+HIP kernels.  Host arrays are numpy; device arrays are torch CUDA tensors
+(their ``data_ptr`` is passed with MDPD_MEM_DEVICE).  If the library is not
+built this module raises on first use; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmdpd.so")
+
+MAX_TYPES = 8
+MEM_HOST, MEM_DEVICE = 0, 1
+FP64, FP32_FORCES = 0, 1
+WALL_OFF, WALL_BVF = 0, 1
+STATUS = {0: "MDPD_OK", -1: "MDPD_E_INVALID", -2: "MDPD_E_OOM", -3: "MDPD_E_HIP",
+          -4: "MDPD_E_NONFINITE", -5: "MDPD_E_STATE", -6: "MDPD_E_UNSUPPORTED"}
+KERNELS = ("sort", "nlist", "density", "force", "wall")
+
+
+class MdpdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("box", ctypes.c_double * 3),
+        ("rc", ctypes.c_double), ("rd", ctypes.c_double), ("kT", ctypes.c_double),
+        ("dt", ctypes.c_double), ("mass", ctypes.c_double),
+        ("body_force", ctypes.c_double * 3),
+        ("phi_c", ctypes.c_double),
+        ("A", ctypes.c_double * (MAX_TYPES * MAX_TYPES)),
+        ("B", ctypes.c_double * (MAX_TYPES * MAX_TYPES)),
+        ("gamma", ctypes.c_double * (MAX_TYPES * MAX_TYPES)),
+        ("seed", ctypes.c_uint32),
+        ("ntypes", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("wall_model", ctypes.c_int32),
+    ]
+
+
+class Observables(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("n", ctypes.c_int64), ("n_fluid", ctypes.c_int64),
+        ("ncorr_last", ctypes.c_int64), ("ncorr_total", ctypes.c_int64),
+        ("ke", ctypes.c_double), ("kT", ctypes.c_double), ("pressure", ctypes.c_double),
+        ("virial", ctypes.c_double), ("epot", ctypes.c_double), ("mean_rho", ctypes.c_double),
+        ("momentum", ctypes.c_double * 3),
+    ]
+
+
+_lib = None
+
+_SIGS = {
+    "mdpd_create": ([ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                     ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int32),
+    "mdpd_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int32),
+    "mdpd_read_observables": ([ctypes.c_void_p, ctypes.POINTER(Observables)], ctypes.c_int32),
+    "mdpd_read_profile": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                           ctypes.c_void_p], ctypes.c_int32),
+    "mdpd_get_state": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                        ctypes.c_int32], ctypes.c_int32),
+    "mdpd_debug_neighbors": ([ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p],
+                             ctypes.c_int32),
+    "mdpd_debug_forces": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int32),
+    "mdpd_set_kernel_timing": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
+    "mdpd_read_kernel_timing": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
+    "mdpd_set_lanes": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
+    "mdpd_destroy": ([ctypes.c_void_p], None),
+    "mdpd_last_error": ([], ctypes.c_char_p),
+}
+
+
+def lib():
+    """Load libmdpd.so; raises if it is not built (no fallback path exists).
+
+    torch is imported first when it is installed: its bundled HIP runtime has
+    the same soname as the system one, so the library then binds to it and the
+    process holds a single HIP runtime (torch device pointers and streams are
+    valid in the library)."""
+    global _lib
+    if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "(hipcc --offload-arch=gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise MdpdError(status, lib().mdpd_last_error().decode())
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=(0.0, 0.0, 0.0),
+                seed=0, wall_model=0, phi_c=0.5, precision=FP64) -> Params:
+    """Parameter block; A, B, gamma are scalars or T x T tables."""
+    A = np.atleast_2d(np.asarray(A, dtype=np.float64))
+    B = np.atleast_2d(np.asarray(B, dtype=np.float64))
+    G = np.atleast_2d(np.asarray(gamma, dtype=np.float64))
+    T = A.shape[0]
+    p = Params()
+    p.box[:] = [float(v) for v in (box if np.ndim(box) else (box, box, box))]
+    p.rc, p.rd, p.kT, p.dt, p.mass = rc, rd, kT, dt, mass
+    p.body_force[:] = [float(v) for v in g]
+    p.phi_c = phi_c
+    for name, M in (("A", A), ("B", B), ("gamma", G)):
+        if M.shape != (T, T):
+            raise ValueError("A, B and gamma must have the same T x T shape")
+        arr = getattr(p, name)
+        for a in range(T):
+            for b in range(T):
+                arr[a * T + b] = M[a, b]
+    p.seed = int(seed) & 0xFFFFFFFF
+    p.ntypes = T
+    p.precision = int(precision)
+    p.wall_model = int(wall_model)
+    return p
+
+
+def mdpd_create(params: Params, pos, vel, types, frozen, stream=None):
+    """Create a system; host numpy arrays or torch CUDA tensors (all on one side)."""
+    if _is_torch(pos):
+        import torch
+        n = int(pos.shape[0])
+        pos = pos.to(torch.float64).contiguous()
+        vel = vel.to(torch.float64).contiguous()
+        types = types.to(torch.int32).contiguous()
+        frozen = frozen.to(torch.uint8).contiguous()
+        keep = (pos, vel, types, frozen)
+        ptrs = [t.data_ptr() for t in keep]
+        mem = MEM_DEVICE
+    else:
+        pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
+        n = int(pos.shape[0])
+        vel = np.ascontiguousarray(np.asarray(vel, dtype=np.float64).reshape(n, 3))
+        types = np.ascontiguousarray(np.asarray(types, dtype=np.int32).reshape(n))
+        frozen = np.ascontiguousarray(np.asarray(frozen, dtype=np.uint8).reshape(n))
+        keep = (pos, vel, types, frozen)
+        ptrs = [a.ctypes.data for a in keep]
+        mem = MEM_HOST
+    if stream is None:
+        st = None
+    elif isinstance(stream, int):
+        st = stream
+    else:
+        st = int(stream.cuda_stream)
+    h = ctypes.c_void_p()
+    _check(lib().mdpd_create(ctypes.byref(params), n, *ptrs, mem, st, ctypes.byref(h)))
+    del keep
+    return h.value
+
+
+def mdpd_step(h, nsteps: int) -> None:
+    _check(lib().mdpd_step(h, int(nsteps)))
+
+
+def mdpd_read_observables(h) -> dict:
+    o = Observables()
+    _check(lib().mdpd_read_observables(h, ctypes.byref(o)))
+    d = {k: getattr(o, k) for k, _ in Observables._fields_ if k != "momentum"}
+    d["momentum"] = tuple(o.momentum)
+    return d
+
+
+def mdpd_read_profile(h, axis: int, nbins: int, quantity: int):
+    out = np.zeros(nbins)
+    _check(lib().mdpd_read_profile(h, axis, nbins, quantity, out.ctypes.data))
+    return out
+
+
+def mdpd_get_state(h, n: int, with_rho: bool = True, device=None):
+    """Positions, velocities (n x 3) and densities in input order.  With
+    device = a torch device, returns CUDA tensors written by the library."""
+    if device is not None:
+        import torch
+        pos = torch.empty((n, 3), dtype=torch.float64, device=device)
+        vel = torch.empty((n, 3), dtype=torch.float64, device=device)
+        rho = torch.empty((n,), dtype=torch.float64, device=device) if with_rho else None
+        _check(lib().mdpd_get_state(h, pos.data_ptr(), vel.data_ptr(),
+                                    rho.data_ptr() if rho is not None else None, MEM_DEVICE))
+        return pos, vel, rho
+    pos = np.zeros((n, 3))
+    vel = np.zeros((n, 3))
+    rho = np.zeros(n) if with_rho else None
+    _check(lib().mdpd_get_state(h, pos.ctypes.data, vel.ctypes.data,
+                                rho.ctypes.data if rho is not None else None, MEM_HOST))
+    return pos, vel, rho
+
+
+def mdpd_debug_neighbors(h, n: int, cutoff: float):
+    cnt = np.zeros(n, dtype=np.int64)
+    hs = np.zeros(n, dtype=np.uint64)
+    _check(lib().mdpd_debug_neighbors(h, float(cutoff), cnt.ctypes.data, hs.ctypes.data))
+    return cnt, hs
+
+
+def mdpd_debug_forces(h, n: int):
+    F = np.zeros((n, 3))
+    _check(lib().mdpd_debug_forces(h, F.ctypes.data))
+    return F
+
+
+def mdpd_set_kernel_timing(h, enable: bool) -> None:
+    _check(lib().mdpd_set_kernel_timing(h, 1 if enable else 0))
+
+
+def mdpd_read_kernel_timing(h, kernel: int):
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(lib().mdpd_read_kernel_timing(h, int(kernel), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+def mdpd_set_lanes(h, pass_: int, lanes: int) -> None:
+    _check(lib().mdpd_set_lanes(h, int(pass_), int(lanes)))
+
+
+def mdpd_destroy(h) -> None:
+    if h:
+        lib().mdpd_destroy(h)
+
+
+def mdpd_last_error() -> str:
+    return lib().mdpd_last_error().decode()
+
+
+class System:
+    """Owning wrapper around one mdpd_system handle."""
+
+    def __init__(self, workload=None, precision=FP64, stream=None, device_inputs=False, params=None,
+                 x=None, v=None, types=None, frozen=None):
+        if workload is not None:
+            params = make_params(**workload.param_kwargs(), precision=precision)
+            x, v, types, frozen = workload.x, workload.v, workload.types, workload.frozen
+        self.params = params
+        self.n = int(np.asarray(x).shape[0]) if not _is_torch(x) else int(x.shape[0])
+        if device_inputs and not _is_torch(x):
+            import torch
+            dev = torch.device("cuda")
+            x = torch.as_tensor(np.asarray(x), device=dev)
+            v = torch.as_tensor(np.asarray(v), device=dev)
+            types = torch.as_tensor(np.asarray(types, dtype=np.int32), device=dev)
+            frozen = torch.as_tensor(np.asarray(frozen, dtype=np.uint8), device=dev)
+        self.h = None
+        self.h = mdpd_create(params, x, v, types, frozen, stream=stream)
+
+    def step(self, nsteps: int = 1):
+        mdpd_step(self.h, nsteps)
+
+    def observables(self) -> dict:
+        return mdpd_read_observables(self.h)
+
+    def profile(self, axis, nbins, quantity):
+        return mdpd_read_profile(self.h, axis, nbins, quantity)
+
+    def state(self, with_rho=True):
+        return mdpd_get_state(self.h, self.n, with_rho)
+
+    def neighbors(self, cutoff):
+        return mdpd_debug_neighbors(self.h, self.n, cutoff)
+
+    def forces(self):
+        return mdpd_debug_forces(self.h, self.n)
+
+    def set_lanes(self, pass_, lanes):
+        mdpd_set_lanes(self.h, pass_, lanes)
+
+    def close(self):
+        if self.h:
+            mdpd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

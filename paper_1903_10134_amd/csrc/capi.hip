@@ -1,0 +1,603 @@
+// capi.hip -- the C ABI declared in include/mdpd.h: system lifecycle, the
+// timestep schedule (Alg. 1) and the read-out calls.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "mdpd.h"
+#include "mdpd_internal.h"
+
+using namespace mdpd;
+
+namespace {
+
+thread_local std::string g_err;
+
+mdpd_status fail(mdpd_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(MDPD_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));         \
+    } while (0)
+
+constexpr int kTimedKernels = 5;  // sort, neighbour list, density, force, wall
+
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+};
+
+}  // namespace
+
+struct mdpd_system {
+    mdpd_params p{};
+    hipStream_t st = nullptr;
+    int n = 0;
+    bool fp32 = false;
+    bool walls = false;
+    int lanes[3] = {4, 4, 4};  // neighbour list, density (and phi), force
+    Geom g{};
+    PairConst pc{};
+    int cur = 0;
+    int64_t step = 0;
+
+    Soa3 xs[2]{}, vh[2]{}, xpred{}, vpred{}, v{}, F{}, xprev{};
+    uint32_t *tag[2]{};
+    uint8_t *typ[2]{};
+    void *rho = nullptr;
+    int *key = nullptr, *slot = nullptr, *counts = nullptr, *cstart = nullptr, *bsum = nullptr;
+    int *ncnt = nullptr, *nl = nullptr;
+    uint32_t *tmpid = nullptr;
+    double *fpart = nullptr;
+    int nfpart = 0;       // capacity of fpart in blocks
+    int nfpart_used = 0;  // blocks written by the last force launch
+    int *status = nullptr;
+    int *corr = nullptr;  // [0]: corrections this step, [1..n]: flags
+    unsigned long long *ncorr_total = nullptr;
+    double *tab = nullptr;
+    double *obs = nullptr;
+    double *io = nullptr;   // n x 3 staging for exports and host inputs
+    double *io2 = nullptr;  // second n x 3 staging
+    double *work = nullptr;
+
+    bool timing = false;
+    EventPool pool[kTimedKernels];
+    std::vector<void *> allocs;
+
+    ~mdpd_system()
+    {
+        for (auto &pl : pool)
+            for (auto e : pl.ev) (void)hipEventDestroy(e);
+        for (void *a : allocs) (void)hipFree(a);
+    }
+
+    template <typename T>
+    mdpd_status alloc(T **out, size_t count)
+    {
+        void *ptr = nullptr;
+        size_t bytes = count * sizeof(T);
+        if (bytes == 0) bytes = 16;
+        hipError_t e = hipMalloc(&ptr, bytes);
+        if (e != hipSuccess) {
+            *out = nullptr;
+            return fail(MDPD_E_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+        }
+        allocs.push_back(ptr);
+        *out = (T *)ptr;
+        return MDPD_OK;
+    }
+
+    mdpd_status alloc3(Soa3 *a, size_t count)
+    {
+        double *base = nullptr;
+        mdpd_status s = alloc(&base, 3 * count);
+        if (s) return s;
+        a->x = base;
+        a->y = base + count;
+        a->z = base + 2 * count;
+        return MDPD_OK;
+    }
+
+    // Timing: event pair around a launch of kernel class k.
+    void tic(int k)
+    {
+        if (!timing) return;
+        EventPool &pl = pool[k];
+        while (pl.ev.size() < pl.used + 2) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            pl.ev.push_back(e);
+        }
+        (void)hipEventRecord(pl.ev[pl.used], st);
+    }
+    void toc(int k)
+    {
+        if (!timing) return;
+        EventPool &pl = pool[k];
+        if (pl.ev.size() < pl.used + 2) return;
+        (void)hipEventRecord(pl.ev[pl.used + 1], st);
+        pl.used += 2;
+    }
+
+    void set_step_keys(uint32_t stepno)
+    {
+        const uint32_t k0 = p.seed, k1 = stepno;
+        const uint32_t ks[3] = {k0, k1, 0x1BD11BDAu ^ k0 ^ k1};
+        pc.ks0 = ks[0];
+        pc.ks1 = ks[1];
+        for (uint32_t s = 1; s <= 5; ++s) {
+            pc.inj0[s - 1] = ks[s % 3];
+            pc.inj1[s - 1] = ks[(s + 1) % 3] + s;
+        }
+    }
+
+    Soa3c xprev_view() const { return walls ? cview(xprev) : Soa3c{nullptr, nullptr, nullptr}; }
+
+    // Sort predicted state (xpred, vpred, tag[cur], typ[cur]) into the other
+    // buffer set; with walls also carry x(t) from xs[cur] into xprev.
+    void sort_predicted()
+    {
+        const int o = 1 - cur;
+        tic(0);
+        launch_sort(st, n, g, cview(xpred), cview(vpred), walls ? cview(xs[cur]) : Soa3c{nullptr, nullptr, nullptr},
+                    tag[cur], typ[cur], xs[o], vh[o], xprev, tag[o], typ[o], key, slot, tmpid, counts,
+                    cstart, bsum, nullptr);
+        toc(0);
+        cur = o;
+    }
+
+    void evaluate(uint32_t stepno, int initial)
+    {
+        set_step_keys(stepno);
+        tic(1);
+        launch_nlist(st, lanes[0], n, g, cview(xs[cur]), cstart, ncnt, nl, nullptr);
+        toc(1);
+        if (walls && !initial) {
+            launch_zero_int(st, corr, 1);
+            tic(4);
+            launch_phi(st, lanes[1], n, pc, g, cview(xs[cur]), cview(xprev), xs[cur], vh[cur], tag[cur],
+                       cstart, ncnt, nl, corr, ncorr_total);
+            toc(4);
+            // re-sort and re-list only if a particle was moved back
+            const int o = 1 - cur;
+            tic(0);
+            launch_sort(st, n, g, cview(xs[cur]), cview(vh[cur]), Soa3c{nullptr, nullptr, nullptr}, tag[cur],
+                        typ[cur], xs[o], vh[o], Soa3{nullptr, nullptr, nullptr}, tag[o], typ[o], key, slot,
+                        tmpid, counts, cstart, bsum, corr);
+            toc(0);
+            cur = o;
+            tic(1);
+            launch_nlist(st, lanes[0], n, g, cview(xs[cur]), cstart, ncnt, nl, corr);
+            toc(1);
+        }
+        tic(2);
+        launch_density(st, lanes[1], fp32, n, pc, g, cview(xs[cur]), cstart, ncnt, nl, rho);
+        toc(2);
+        nfpart_used = n > 0 ? force_blocks(lanes[2], n) : 0;
+        tic(3);
+        launch_force(st, lanes[2], fp32, n, pc, g, cview(xs[cur]), cview(vh[cur]), rho, tag[cur], typ[cur],
+                     cstart, ncnt, nl, v, F, vpred, xpred, fpart, status, initial);
+        toc(3);
+    }
+};
+
+namespace {
+
+bool finite(double x) { return isfinite(x) != 0; }
+
+mdpd_status validate(const mdpd_params *p, int64_t n)
+{
+    if (!p) return fail(MDPD_E_INVALID, "params is NULL");
+    if (n < 0 || n >= (int64_t)1 << 31) return fail(MDPD_E_INVALID, "n = %lld out of range", (long long)n);
+    if (p->ntypes < 1 || p->ntypes > MDPD_MAX_TYPES)
+        return fail(MDPD_E_INVALID, "ntypes = %d not in 1..%d", p->ntypes, MDPD_MAX_TYPES);
+    const double sc[] = {p->rc, p->rd, p->kT, p->dt, p->mass, p->phi_c, p->box[0], p->box[1], p->box[2],
+                         p->body_force[0], p->body_force[1], p->body_force[2]};
+    for (double v : sc)
+        if (!finite(v)) return fail(MDPD_E_INVALID, "non-finite scalar parameter");
+    if (!(p->rc > 0.0) || !(p->rd > 0.0) || p->rd > p->rc)
+        return fail(MDPD_E_INVALID, "need 0 < rd <= rc (rc = %g, rd = %g)", p->rc, p->rd);
+    if (!(p->dt > 0.0) || !(p->mass > 0.0) || p->kT < 0.0)
+        return fail(MDPD_E_INVALID, "need dt > 0, mass > 0, kT >= 0");
+    if (p->precision != MDPD_FP64 && p->precision != MDPD_FP32_FORCES)
+        return fail(MDPD_E_INVALID, "unknown precision %d", p->precision);
+    if (p->wall_model != MDPD_WALL_OFF && p->wall_model != MDPD_WALL_BVF)
+        return fail(MDPD_E_INVALID, "unknown wall_model %d", p->wall_model);
+    const int T = p->ntypes;
+    for (int a = 0; a < T; ++a)
+        for (int b = 0; b < T; ++b) {
+            const int ab = a * T + b, ba = b * T + a;
+            if (!finite(p->A[ab]) || !finite(p->B[ab]) || !finite(p->gamma[ab]))
+                return fail(MDPD_E_INVALID, "non-finite pair table entry");
+            if (p->A[ab] != p->A[ba] || p->B[ab] != p->B[ba] || p->gamma[ab] != p->gamma[ba])
+                return fail(MDPD_E_INVALID, "pair tables must be symmetric");
+            if (p->B[ab] < 0.0 || p->gamma[ab] < 0.0) return fail(MDPD_E_INVALID, "need B, gamma >= 0");
+        }
+    for (int a = 0; a < 3; ++a)
+        if (!(p->box[a] > 0.0)) return fail(MDPD_E_INVALID, "box edges must be positive");
+    return MDPD_OK;
+}
+
+// Cells per axis: the largest nc >= 3 whose edge L/nc is at least r_c with a
+// relative margin of 1e-12 over rounding, or exactly r_c when binning is
+// exact (nc/L a power of two, so x * nc/L is computed without rounding).
+mdpd_status make_geom(const mdpd_params *p, Geom *g)
+{
+    long long total = 1;
+    for (int a = 0; a < 3; ++a) {
+        const double L = p->box[a];
+        int nc = (int)floor(L / p->rc);
+        while (nc >= 3) {
+            const double cs = L / nc, s = nc / L;
+            int e;
+            const bool pow2 = frexp(s, &e) == 0.5;
+            if (cs >= p->rc * (1.0 + 1e-12) || (pow2 && cs >= p->rc && L * s == (double)nc)) break;
+            --nc;
+        }
+        if (nc < 3)
+            return fail(MDPD_E_UNSUPPORTED, "box edge %g holds fewer than 3 cells of r_c = %g", L, p->rc);
+        g->L[a] = L;
+        g->nc[a] = nc;
+        g->s[a] = nc / L;
+        total *= nc;
+    }
+    if (total > (long long)4096 * 4096) return fail(MDPD_E_UNSUPPORTED, "more than 2^24 cells");
+    g->ncells = (int)total;
+    g->rc2 = p->rc * p->rc;
+    g->rd2 = p->rd * p->rd;
+    return MDPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mdpd_last_error(void) { return g_err.c_str(); }
+
+void mdpd_destroy(mdpd_system *s)
+{
+    if (!s) return;
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    else (void)hipDeviceSynchronize();
+    delete s;
+}
+
+mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, const double *vel,
+                        const int32_t *type, const uint8_t *frozen, int32_t mem_kind, void *stream,
+                        mdpd_system **out)
+{
+    if (!out) return fail(MDPD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    mdpd_status rc = validate(p, n);
+    if (rc) return rc;
+    if (n > 0 && (!pos || !vel || !type || !frozen)) return fail(MDPD_E_INVALID, "NULL particle array");
+    if (mem_kind != MDPD_MEM_HOST && mem_kind != MDPD_MEM_DEVICE)
+        return fail(MDPD_E_INVALID, "unknown mem_kind %d", mem_kind);
+    Geom g;
+    rc = make_geom(p, &g);
+    if (rc) return rc;
+
+    mdpd_system *s = new mdpd_system();
+    s->p = *p;
+    s->st = (hipStream_t)stream;
+    s->n = (int)n;
+    s->g = g;
+    s->fp32 = p->precision == MDPD_FP32_FORCES;
+    s->walls = p->wall_model == MDPD_WALL_BVF;
+
+    // pair constants
+    PairConst &pc = s->pc;
+    for (int a = 0; a < 3; ++a) {
+        pc.L[a] = p->box[a];
+        pc.invL[a] = 1.0 / p->box[a];
+        pc.mg[a] = p->mass * p->body_force[a];
+    }
+    pc.rc = p->rc;
+    pc.inv_rc = 1.0 / p->rc;
+    pc.rd = p->rd;
+    pc.inv_rd = 1.0 / p->rd;
+    pc.rd2 = p->rd * p->rd;
+    pc.wrho = 15.0 / (2.0 * M_PI * p->rd * p->rd * p->rd);
+    pc.hdtm = 0.5 * p->dt / p->mass;
+    pc.dt = p->dt;
+    pc.phi_c = p->phi_c;
+    pc.ntypes = p->ntypes;
+    const double rdt = 1.0 / sqrt(p->dt);
+    pc.A = p->A[0];
+    pc.B = p->B[0];
+    pc.gamma = p->gamma[0];
+    pc.sig = sqrt(2.0 * p->gamma[0] * p->kT) * rdt;
+    pc.Arc2 = 0.5 * p->A[0] * p->rc;
+
+    const size_t N = (size_t)(n > 0 ? n : 1);
+    const int nb_scan = (g.ncells + 4095) / 4096;
+    s->nfpart = force_blocks(16, (int)N);
+#define ALLOC(call)                 \
+    do {                            \
+        mdpd_status e_ = (call);    \
+        if (e_) {                   \
+            delete s;               \
+            return e_;              \
+        }                           \
+    } while (0)
+    for (int k = 0; k < 2; ++k) {
+        ALLOC(s->alloc3(&s->xs[k], N));
+        ALLOC(s->alloc3(&s->vh[k], N));
+        ALLOC(s->alloc(&s->tag[k], N));
+        ALLOC(s->alloc(&s->typ[k], N));
+    }
+    ALLOC(s->alloc3(&s->xpred, N));
+    ALLOC(s->alloc3(&s->vpred, N));
+    ALLOC(s->alloc3(&s->v, N));
+    ALLOC(s->alloc3(&s->F, N));
+    if (s->walls) ALLOC(s->alloc3(&s->xprev, N));
+    {
+        double *r = nullptr;
+        ALLOC(s->alloc(&r, N));
+        s->rho = r;
+    }
+    ALLOC(s->alloc(&s->key, N));
+    ALLOC(s->alloc(&s->slot, N));
+    ALLOC(s->alloc(&s->tmpid, N));
+    ALLOC(s->alloc(&s->ncnt, N));
+    ALLOC(s->alloc(&s->nl, N * kListCap));
+    ALLOC(s->alloc(&s->counts, (size_t)g.ncells));
+    ALLOC(s->alloc(&s->cstart, (size_t)g.ncells + 1));
+    ALLOC(s->alloc(&s->bsum, (size_t)nb_scan + 1));
+    ALLOC(s->alloc(&s->fpart, 2 * (size_t)s->nfpart));
+    ALLOC(s->alloc(&s->status, 4));
+    ALLOC(s->alloc(&s->corr, N + 1));
+    ALLOC(s->alloc(&s->ncorr_total, 1));
+    ALLOC(s->alloc(&s->tab, 320));
+    ALLOC(s->alloc(&s->obs, 16 + 1024 * 8));
+    ALLOC(s->alloc(&s->io, 3 * N));
+    ALLOC(s->alloc(&s->io2, 3 * N));
+    ALLOC(s->alloc(&s->work, 9 * 4096));
+#undef ALLOC
+
+    // type-pair tables: A | B | gamma | sig | A r_c / 2
+    {
+        double h[320] = {0};
+        const int T = p->ntypes;
+        for (int k = 0; k < T * T; ++k) {
+            h[k] = p->A[k];
+            h[64 + k] = p->B[k];
+            h[128 + k] = p->gamma[k];
+            h[192 + k] = sqrt(2.0 * p->gamma[k] * p->kT) * rdt;
+            h[256 + k] = 0.5 * p->A[k] * p->rc;
+        }
+        hipError_t e = hipMemcpyAsync(s->tab, h, sizeof h, hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+        if (e != hipSuccess) {
+            delete s;
+            return fail(MDPD_E_HIP, "upload of pair tables failed: %s", hipGetErrorString(e));
+        }
+        pc.tab = s->tab;
+    }
+
+    auto bail = [&](mdpd_status st) {
+        delete s;
+        return st;
+    };
+    hipError_t e = hipSuccess;
+    launch_zero_int(s->st, s->status, 4);
+    launch_zero_int(s->st, (int *)s->ncorr_total, 2);
+    launch_zero_int(s->st, s->counts, g.ncells);
+    launch_zero_int(s->st, s->corr, (int)N + 1);
+
+    // inputs: stage host arrays in device memory
+    const double *dpos = pos, *dvel = vel;
+    const int32_t *dtype = type;
+    const uint8_t *dfz = frozen;
+    int32_t *stype = nullptr;
+    uint8_t *sfz = nullptr;
+    if (n > 0 && mem_kind == MDPD_MEM_HOST) {
+        if (s->alloc(&stype, N) || s->alloc(&sfz, N)) return bail(MDPD_E_OOM);
+        e = hipMemcpyAsync(s->io, pos, 3 * N * sizeof(double), hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess) e = hipMemcpyAsync(s->io2, vel, 3 * N * sizeof(double), hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess) e = hipMemcpyAsync(stype, type, N * sizeof(int32_t), hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess) e = hipMemcpyAsync(sfz, frozen, N, hipMemcpyHostToDevice, s->st);
+        if (e != hipSuccess) return bail(fail(MDPD_E_HIP, "input upload failed: %s", hipGetErrorString(e)));
+        dpos = s->io;
+        dvel = s->io2;
+        dtype = stype;
+        dfz = sfz;
+    }
+    s->cur = 0;
+    launch_ingest(s->st, n, dpos, dvel, dtype, dfz, g, p->ntypes, s->xpred, s->vpred, s->tag[0], s->typ[0],
+                  s->status);
+    int hstatus = 0;
+    e = hipMemcpyAsync(&hstatus, s->status, sizeof(int), hipMemcpyDeviceToHost, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    if (e != hipSuccess) return bail(fail(MDPD_E_HIP, "ingest failed: %s", hipGetErrorString(e)));
+    if (hstatus & 2)
+        return bail(fail(MDPD_E_INVALID,
+                         "input has a non-finite value, a position outside [-L, 2L) or a bad type"));
+
+    // t = 0: sort, density, forces with the given velocities and noise step 0
+    s->sort_predicted();
+    s->evaluate(0, 1);
+    e = hipMemcpyAsync(&hstatus, s->status, sizeof(int), hipMemcpyDeviceToHost, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    if (e != hipSuccess) return bail(fail(MDPD_E_HIP, "initial evaluation failed: %s", hipGetErrorString(e)));
+    if (hstatus) return bail(fail(MDPD_E_NONFINITE, "non-finite state after the initial evaluation"));
+    *out = s;
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_step(mdpd_system *s, int64_t nsteps)
+{
+    if (!s) return fail(MDPD_E_INVALID, "system is NULL");
+    if (nsteps < 0) return fail(MDPD_E_INVALID, "nsteps < 0");
+    for (int64_t k = 0; k < nsteps; ++k) {
+        s->step += 1;
+        s->sort_predicted();
+        s->evaluate((uint32_t)s->step, 0);
+    }
+    int hstatus = 0;
+    HIPCHK(hipMemcpyAsync(&hstatus, s->status, sizeof(int), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    HIPCHK(hipGetLastError());
+    if (hstatus) return fail(MDPD_E_NONFINITE, "non-finite or out-of-box state at step %lld", (long long)s->step);
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_read_observables(mdpd_system *s, mdpd_observables *out)
+{
+    if (!s || !out) return fail(MDPD_E_INVALID, "NULL argument");
+    launch_observables(s->st, s->fp32, s->n, s->pc, cview(s->v), s->rho, s->tag[s->cur], s->typ[s->cur],
+                       s->fpart, s->nfpart_used, s->obs);
+    double h[10];
+    unsigned long long tot = 0;
+    int last = 0;
+    HIPCHK(hipMemcpyAsync(h, s->obs, sizeof h, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(&tot, s->ncorr_total, sizeof tot, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(&last, s->corr, sizeof last, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    const mdpd_params &p = s->p;
+    const double m = p.mass;
+    const int64_t nf = (int64_t)llround(h[6]);
+    const bool driven = p.body_force[0] != 0.0 || p.body_force[1] != 0.0 || p.body_force[2] != 0.0;
+    double dof = (double)nf;
+    if (nf == s->n && !driven) dof -= 1.0;
+    const double V = p.box[0] * p.box[1] * p.box[2];
+    memset(out, 0, sizeof *out);
+    out->step = s->step;
+    out->n = s->n;
+    out->n_fluid = nf;
+    out->ke = 0.5 * m * h[0];
+    out->kT = dof > 0 ? m * h[0] / (3.0 * dof) : 0.0;
+    out->virial = h[8];
+    out->pressure = (m * h[0] + h[8]) / (3.0 * V);
+    out->momentum[0] = m * h[1];
+    out->momentum[1] = m * h[2];
+    out->momentum[2] = m * h[3];
+    out->epot = h[9] + M_PI * pow(p.rd, 4) / 30.0 * h[5];
+    out->mean_rho = nf > 0 ? h[4] / (double)nf : 0.0;
+    out->ncorr_last = s->walls && s->step > 0 ? last : 0;
+    out->ncorr_total = (int64_t)tot;
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_read_profile(mdpd_system *s, int32_t axis, int32_t nbins, int32_t quantity, double *out)
+{
+    if (!s || !out) return fail(MDPD_E_INVALID, "NULL argument");
+    if (axis < 0 || axis > 2 || nbins < 1 || nbins > 4096 || quantity < 0 || quantity > 5)
+        return fail(MDPD_E_INVALID, "bad profile request (axis %d, nbins %d, quantity %d)", axis, nbins,
+                    quantity);
+    const double binvol = s->p.box[0] * s->p.box[1] * s->p.box[2] / nbins;
+    double *res = s->work + 9 * nbins;
+    if ((size_t)(10 * nbins) > (size_t)9 * 4096) res = s->io;  // large nbins: use staging
+    launch_profile(s->st, s->fp32, s->n, axis, nbins, quantity, s->p.box[axis], binvol, s->p.mass,
+                   cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur], s->work, res);
+    HIPCHK(hipMemcpyAsync(out, res, nbins * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_get_state(mdpd_system *s, double *pos, double *vel, double *rho, int32_t mem_kind)
+{
+    if (!s) return fail(MDPD_E_INVALID, "system is NULL");
+    if (mem_kind != MDPD_MEM_HOST && mem_kind != MDPD_MEM_DEVICE)
+        return fail(MDPD_E_INVALID, "unknown mem_kind %d", mem_kind);
+    const size_t N = (size_t)s->n;
+    if (N == 0) return MDPD_OK;
+    if (mem_kind == MDPD_MEM_DEVICE) {
+        launch_export(s->st, s->fp32, s->n, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur], pos,
+                      vel, rho);
+        HIPCHK(hipStreamSynchronize(s->st));
+        return MDPD_OK;
+    }
+    launch_export(s->st, s->fp32, s->n, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur],
+                  pos ? s->io : nullptr, vel ? s->io2 : nullptr, nullptr);
+    if (pos) HIPCHK(hipMemcpyAsync(pos, s->io, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    if (vel) HIPCHK(hipMemcpyAsync(vel, s->io2, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    if (rho) {
+        launch_export(s->st, s->fp32, s->n, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur],
+                      nullptr, nullptr, s->io);
+        HIPCHK(hipMemcpyAsync(rho, s->io, N * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+    }
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_debug_forces(mdpd_system *s, double *force)
+{
+    if (!s || !force) return fail(MDPD_E_INVALID, "NULL argument");
+    const size_t N = (size_t)s->n;
+    if (N == 0) return MDPD_OK;
+    launch_export(s->st, false, s->n, cview(s->F), Soa3c{nullptr, nullptr, nullptr}, nullptr, s->tag[s->cur],
+                  s->io, nullptr, nullptr);
+    HIPCHK(hipMemcpyAsync(force, s->io, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_debug_neighbors(mdpd_system *s, double cutoff, int64_t *count, uint64_t *hash)
+{
+    if (!s || !count || !hash) return fail(MDPD_E_INVALID, "NULL argument");
+    if (!(cutoff > 0.0) || cutoff > s->p.rc) return fail(MDPD_E_INVALID, "cutoff must be in (0, rc]");
+    const size_t N = (size_t)s->n;
+    if (N == 0) return MDPD_OK;
+    int64_t *dc = (int64_t *)s->io;
+    uint64_t *dh = (uint64_t *)s->io2;
+    launch_debug_neighbors(s->st, s->n, s->g, s->pc, cutoff * cutoff, cview(s->xs[s->cur]), s->tag[s->cur],
+                           s->cstart, s->ncnt, s->nl, dc, dh);
+    HIPCHK(hipMemcpyAsync(count, dc, N * sizeof(int64_t), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(hash, dh, N * sizeof(uint64_t), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_set_kernel_timing(mdpd_system *s, int32_t enable)
+{
+    if (!s) return fail(MDPD_E_INVALID, "system is NULL");
+    s->timing = enable != 0;
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_read_kernel_timing(mdpd_system *s, int32_t kernel, double *total_ms, int64_t *launches)
+{
+    if (!s || !total_ms || !launches) return fail(MDPD_E_INVALID, "NULL argument");
+    if (kernel < 0 || kernel >= kTimedKernels) return fail(MDPD_E_INVALID, "kernel class %d", kernel);
+    HIPCHK(hipStreamSynchronize(s->st));
+    EventPool &pl = s->pool[kernel];
+    double tot = 0.0;
+    for (size_t k = 0; k + 1 < pl.used; k += 2) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, pl.ev[k], pl.ev[k + 1]));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)(pl.used / 2);
+    pl.used = 0;
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_set_lanes(mdpd_system *s, int32_t pass, int32_t lanes)
+{
+    if (!s) return fail(MDPD_E_INVALID, "system is NULL");
+    if (pass < 0 || pass > 2) return fail(MDPD_E_INVALID, "pass %d not in 0..2", pass);
+    if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16)
+        return fail(MDPD_E_INVALID, "lanes %d not in {1, 2, 4, 8, 16}", lanes);
+    s->lanes[pass] = lanes;
+    return MDPD_OK;
+}
+
+}  // extern "C"

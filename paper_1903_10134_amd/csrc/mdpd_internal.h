@@ -1,0 +1,174 @@
+// mdpd_internal.h -- shared declarations of the gfx950 mDPD library.
+//
+// Data layout in device memory (all arrays indexed by the current sorted
+// slot k, particles ordered by cell, x fastest, then y, then z, and by
+// particle id inside a cell):
+//   positions, velocities, forces : three FP64 planes (SoA), x | y | z
+//   tag                           : uint32, particle id in bits 0..30,
+//                                   bit 31 set for frozen wall particles
+//   type                          : uint8
+//   rho                           : FP64 (FP64 form) or FP32 (FP32 form)
+//   neighbour list                : int32 slot indices, kListCap per particle,
+//                                   particle-major, plus a count per particle
+//   cell_start                    : ncells + 1 offsets into the sorted order
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mdpd {
+
+constexpr int kListCap = 64;   // neighbour-list slots per particle
+constexpr int kBlock = 256;    // threads per block of the particle kernels
+constexpr uint32_t kFrozenBit = 0x80000000u;
+constexpr uint32_t kIdMask = 0x7fffffffu;
+
+struct Soa3 {
+    double *x, *y, *z;
+};
+struct Soa3c {
+    const double *x, *y, *z;
+};
+inline Soa3c cview(const Soa3 &a) { return Soa3c{a.x, a.y, a.z}; }
+
+// Cell lattice: nc[a] cells of edge L[a]/nc[a] >= r_c per axis.
+struct Geom {
+    double L[3];
+    double s[3];  // cells per unit length, nc / L
+    int nc[3];
+    int ncells;
+    double rc2, rd2;
+};
+
+// Scalars of one pair pass (one launch).
+struct PairConst {
+    double L[3], invL[3];
+    double rc, inv_rc, rd, inv_rd, rd2;
+    double wrho;        // 15 / (2 pi r_d^3)
+    double hdtm, dt;    // dt / (2 m), dt
+    double mg[3];       // body force m g on fluid
+    double A, B, gamma, sig, Arc2;  // single-type values; sig = sqrt(2 gamma kT / dt)
+    double phi_c;
+    const double *tab;  // ntypes > 1: A | B | gamma | sig | Arc2 planes of 64
+    int ntypes;
+    uint32_t ks0, ks1;  // Threefry key words added to the counter
+    uint32_t inj0[5], inj1[5];  // Threefry key injections after rounds 4, 8, ..., 20
+};
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+// Cell index along one axis, clamped to [0, nc - 1]; a non-finite coordinate
+// (a run that blew up, reported through the status word) maps to cell 0, so
+// no launch can index outside the cell arrays.
+__device__ __forceinline__ int cell_coord(double x, double s, int nc)
+{
+    double t = x * s;
+    if (!(t >= 0.0)) t = 0.0;
+    const int c = t < (double)nc ? (int)t : nc - 1;
+    return c;
+}
+
+// Squared distance with no fused multiply-add, evaluated ((dx dx + dy dy) + dz dz):
+// the neighbour test must round exactly like a plain sequence of products and sums.
+__device__ __forceinline__ double exact_r2(double dx, double dy, double dz)
+{
+#pragma clang fp contract(off)
+    double a = dx * dx;
+    double b = dy * dy;
+    double c = dz * dz;
+    double s = a + b;
+    s = s + c;
+    return s;
+}
+
+// Minimum image of a difference |d| < L: d - L * rint(d / L).  For pairs
+// closer than L/2 the multiple is -1, 0 or +1, L*k is exact, so the result is
+// the correctly rounded d - L, d or d + L.
+__device__ __forceinline__ double min_image(double d, double L, double invL)
+{
+    return fma(-L, rint(d * invL), d);
+}
+
+// 1/sqrt(a) for a > 0 to full double precision: hardware estimate and two
+// Newton steps.
+__device__ __forceinline__ double rsqrt_f64(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+    double h = 0.5 * a;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+__device__ __forceinline__ uint32_t rotl32(uint32_t x, int r) { return (x << r) | (x >> (32 - r)); }
+
+// First output word of Threefry-2x32 with 20 rounds (Salmon et al., SC'11),
+// counter (c0, c1); the key enters through ks0, ks1 and the five injections
+// precomputed on the host from (seed, step).
+__device__ __forceinline__ uint32_t threefry2x32_20_w0(uint32_t c0, uint32_t c1, const PairConst &k)
+{
+    uint32_t x0 = c0 + k.ks0, x1 = c1 + k.ks1;
+#define MDPD_TF_ROUND(R) \
+    x0 += x1;            \
+    x1 = rotl32(x1, R);  \
+    x1 ^= x0;
+    MDPD_TF_ROUND(13) MDPD_TF_ROUND(15) MDPD_TF_ROUND(26) MDPD_TF_ROUND(6)
+    x0 += k.inj0[0]; x1 += k.inj1[0];
+    MDPD_TF_ROUND(17) MDPD_TF_ROUND(29) MDPD_TF_ROUND(16) MDPD_TF_ROUND(24)
+    x0 += k.inj0[1]; x1 += k.inj1[1];
+    MDPD_TF_ROUND(13) MDPD_TF_ROUND(15) MDPD_TF_ROUND(26) MDPD_TF_ROUND(6)
+    x0 += k.inj0[2]; x1 += k.inj1[2];
+    MDPD_TF_ROUND(17) MDPD_TF_ROUND(29) MDPD_TF_ROUND(16) MDPD_TF_ROUND(24)
+    x0 += k.inj0[3]; x1 += k.inj1[3];
+    MDPD_TF_ROUND(13) MDPD_TF_ROUND(15) MDPD_TF_ROUND(26) MDPD_TF_ROUND(6)
+    x0 += k.inj0[4];
+#undef MDPD_TF_ROUND
+    return x0;
+}
+
+// Pair noise: top 24 bits k of the first Threefry word with counter
+// (min id, max id) give t = (2k + 1 - 2^24) 2^-24, exact in both FP32 and
+// FP64; theta = sqrt(3) t is uniform with zero mean and unit variance.
+__device__ __forceinline__ int theta_int(uint32_t ida, uint32_t idb, const PairConst &k)
+{
+    uint32_t lo = ida < idb ? ida : idb;
+    uint32_t hi = ida < idb ? idb : ida;
+    uint32_t w = threefry2x32_20_w0(lo, hi, k);
+    return (int)((w >> 8) << 1) + 1 - 16777216;
+}
+
+// Host-side launchers (defined in the .hip files).
+void launch_ingest(hipStream_t st, int64_t n, const double *pos, const double *vel,
+                   const int32_t *type, const uint8_t *frozen, Geom g, int ntypes, Soa3 xp,
+                   Soa3 vp, uint32_t *tag, uint8_t *typ, int *status);
+void launch_sort(hipStream_t st, int n, Geom g, Soa3c xin, Soa3c vin, Soa3c xprev_in,
+                 const uint32_t *tag_in, const uint8_t *typ_in, Soa3 xout, Soa3 vout,
+                 Soa3 xprev_out, uint32_t *tag_out, uint8_t *typ_out, int *key, int *slot,
+                 uint32_t *tmpid, int *counts, int *cstart, int *bsum, const int *gate);
+void launch_nlist(hipStream_t st, int lanes, int n, Geom g, Soa3c xs, const int *cstart,
+                  int *ncnt, int *nl, const int *gate);
+void launch_density(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g,
+                    Soa3c xs, const int *cstart, const int *ncnt, const int *nl, void *rho);
+void launch_phi(hipStream_t st, int lanes, int n, const PairConst &pc, Geom g, Soa3c xs,
+                Soa3c xprev, Soa3 xfix, Soa3 vfix, const uint32_t *tag, const int *cstart,
+                const int *ncnt, const int *nl, int *ncorr, unsigned long long *ncorr_total);
+void launch_force(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g,
+                  Soa3c xs, Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ,
+                  const int *cstart, const int *ncnt, const int *nl, Soa3 vout, Soa3 fout,
+                  Soa3 vpred, Soa3 xpred, double *part, int *status, int initial);
+int force_blocks(int lanes, int n);
+void launch_observables(hipStream_t st, bool fp32, int n, const PairConst &pc, Soa3c v,
+                        const void *rho, const uint32_t *tag, const uint8_t *typ,
+                        const double *fpart, int nfpart, double *out16);
+void launch_profile(hipStream_t st, bool fp32, int n, int axis, int nbins, int quantity, double La,
+                    double binvol, double mass, Soa3c x, Soa3c v, const void *rho,
+                    const uint32_t *tag, double *work, double *out);
+void launch_export(hipStream_t st, bool fp32, int n, Soa3c x, Soa3c v, const void *rho,
+                   const uint32_t *tag, double *pos, double *vel, double *rho_out);
+void launch_debug_neighbors(hipStream_t st, int n, Geom g, const PairConst &pc, double cutoff2,
+                            Soa3c xs, const uint32_t *tag, const int *cstart, const int *ncnt,
+                            const int *nl, int64_t *count, uint64_t *hash);
+void launch_zero_int(hipStream_t st, int *p, int n);
+
+}  // namespace mdpd

@@ -1,0 +1,273 @@
+// sort.hip -- cell binning and the deterministic stable reorder into SoA.
+//
+// Every step the predicted positions are binned into cells of edge >= r_c and
+// all per-particle arrays are rewritten in (cell, particle id) order:
+//   k_bin          cell key per particle and its arrival slot in the cell
+//                  (integer atomics: the counts are exact, the slots are not
+//                  ordered)
+//   k_scan_*       exclusive scan of the cell counts -> cell_start[ncells + 1]
+//                  (the counts are cleared as they are read)
+//   k_scatter_id   writes each particle's id at its arrival slot
+//   k_rank_gather  rank of the particle inside its cell = number of particles
+//                  of that cell with a smaller id; moves every array to
+//                  cell_start + rank.
+// The result depends only on positions and ids, not on the previous order or
+// the atomics' arrival order, so runs and restarts are bitwise reproducible.
+#include "mdpd_internal.h"
+
+namespace mdpd {
+
+namespace {
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 4;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+inline int blocks_for(int64_t threads) { return (int)((threads + kBlock - 1) / kBlock); }
+
+__global__ __launch_bounds__(kBlock) void k_bin(int n, Geom g, Soa3c x, int *__restrict__ key,
+                                                int *__restrict__ slot, int *__restrict__ counts,
+                                                const int *__restrict__ gate)
+{
+    if (gate && *gate == 0) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int cx = cell_coord(x.x[i], g.s[0], g.nc[0]);
+    const int cy = cell_coord(x.y[i], g.s[1], g.nc[1]);
+    const int cz = cell_coord(x.z[i], g.s[2], g.nc[2]);
+    const int c = cx + g.nc[0] * (cy + g.nc[1] * cz);
+    key[i] = c;
+    slot[i] = atomicAdd(&counts[c], 1);
+}
+
+// Inclusive scan across one block of kScanThreads threads; returns the
+// inclusive prefix of v and the block total in *total.
+__device__ __forceinline__ int block_inclusive_scan(int v, int *sh, int *total)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) sh[wave] = v;
+    __syncthreads();
+    if (wave == 0) {
+        constexpr int nw = kScanThreads / 64;
+        int w = lane < nw ? sh[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < nw; o <<= 1) {
+            const int u = __shfl_up(w, o, 64);
+            if (lane >= o) w += u;
+        }
+        if (lane < nw) sh[lane] = w;
+    }
+    __syncthreads();
+    if (wave > 0) v += sh[wave - 1];
+    *total = sh[kScanThreads / 64 - 1];
+    return v;
+}
+
+// Local exclusive scan of tile b of counts into out; clears counts.
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(int m, int *__restrict__ counts,
+                                                             int *__restrict__ out,
+                                                             int *__restrict__ bsum,
+                                                             const int *__restrict__ gate)
+{
+    if (gate && *gate == 0) return;
+    __shared__ int sh[kScanThreads / 64];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    int v[kScanPer];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int idx = base + k;
+        v[k] = idx < m ? counts[idx] : 0;
+        if (idx < m) counts[idx] = 0;
+        s += v[k];
+    }
+    int total;
+    const int incl = block_inclusive_scan(s, sh, &total);
+    int run = incl - s;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int idx = base + k;
+        if (idx < m) out[idx] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// Exclusive scan of the block totals (at most kScanTile of them) in place;
+// out[m] receives the grand total.
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int nb, int m, int *__restrict__ bsum,
+                                                           int *__restrict__ out,
+                                                           const int *__restrict__ gate)
+{
+    if (gate && *gate == 0) return;
+    __shared__ int sh[kScanThreads / 64];
+    const int base = threadIdx.x * kScanPer;
+    int v[kScanPer];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        v[k] = base + k < nb ? bsum[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    const int incl = block_inclusive_scan(s, sh, &total);
+    int run = incl - s;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < nb) bsum[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) out[m] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int m, const int *__restrict__ bsum,
+                                                           int *__restrict__ out,
+                                                           const int *__restrict__ gate)
+{
+    if (gate && *gate == 0) return;
+    const int add = bsum[blockIdx.x];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+        if (base + k < m) out[base + k] += add;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_id(int n, const int *__restrict__ key,
+                                                       const int *__restrict__ slot,
+                                                       const int *__restrict__ cstart,
+                                                       const uint32_t *__restrict__ tag,
+                                                       uint32_t *__restrict__ tmpid,
+                                                       const int *__restrict__ gate)
+{
+    if (gate && *gate == 0) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    tmpid[cstart[key[i]] + slot[i]] = tag[i] & kIdMask;
+}
+
+// With gate == 0 (nothing moved since the last sort) the arrays are copied in
+// place order so the caller's buffer swap stays valid.
+__global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const int *__restrict__ key,
+                                                        const int *__restrict__ cstart,
+                                                        const uint32_t *__restrict__ tmpid, Soa3c xin,
+                                                        Soa3c vin, Soa3c pin,
+                                                        const uint32_t *__restrict__ tag_in,
+                                                        const uint8_t *__restrict__ typ_in, Soa3 xout,
+                                                        Soa3 vout, Soa3 pout,
+                                                        uint32_t *__restrict__ tag_out,
+                                                        uint8_t *__restrict__ typ_out,
+                                                        const int *__restrict__ gate)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t tg = tag_in[i];
+    int dst = i;
+    if (!(gate && *gate == 0)) {
+        const int c = key[i];
+        const int b = cstart[c], e = cstart[c + 1];
+        const uint32_t id = tg & kIdMask;
+        int rank = 0;
+        for (int k = b; k < e; ++k) rank += tmpid[k] < id ? 1 : 0;
+        dst = b + rank;
+    }
+    xout.x[dst] = xin.x[i];
+    xout.y[dst] = xin.y[i];
+    xout.z[dst] = xin.z[i];
+    vout.x[dst] = vin.x[i];
+    vout.y[dst] = vin.y[i];
+    vout.z[dst] = vin.z[i];
+    if (pin.x) {
+        pout.x[dst] = pin.x[i];
+        pout.y[dst] = pin.y[i];
+        pout.z[dst] = pin.z[i];
+    }
+    tag_out[dst] = tg;
+    typ_out[dst] = typ_in[i];
+}
+
+// Input arrays (AoS n x 3, caller order) to SoA predicted state; validates.
+__global__ __launch_bounds__(kBlock) void k_ingest(int n, const double *__restrict__ pos,
+                                                   const double *__restrict__ vel,
+                                                   const int32_t *__restrict__ type,
+                                                   const uint8_t *__restrict__ frozen, Geom g,
+                                                   int ntypes, Soa3 xp, Soa3 vp,
+                                                   uint32_t *__restrict__ tag,
+                                                   uint8_t *__restrict__ typ, int *__restrict__ status)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const bool fz = frozen[i] != 0;
+    double q[3], w[3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+        double x = pos[3 * (size_t)i + a];
+        const double L = g.L[a];
+        ok = ok && __builtin_isfinite(x) && x >= -L && x < 2.0 * L;
+        if (x < 0.0) x += L;
+        if (x >= L) x -= L;
+        q[a] = x;
+        const double v = vel[3 * (size_t)i + a];
+        ok = ok && __builtin_isfinite(v);
+        w[a] = fz ? 0.0 : v;
+    }
+    const int t = type[i];
+    ok = ok && t >= 0 && t < ntypes;
+    if (!ok) atomicOr(status, 2);
+    xp.x[i] = q[0];
+    xp.y[i] = q[1];
+    xp.z[i] = q[2];
+    vp.x[i] = w[0];
+    vp.y[i] = w[1];
+    vp.z[i] = w[2];
+    tag[i] = (uint32_t)i | (fz ? kFrozenBit : 0u);
+    typ[i] = (uint8_t)(t >= 0 && t < ntypes ? t : 0);
+}
+
+__global__ void k_zero_int(int *p, int n)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+void launch_zero_int(hipStream_t st, int *p, int n)
+{
+    if (n > 0) k_zero_int<<<blocks_for(n), kBlock, 0, st>>>(p, n);
+}
+
+void launch_ingest(hipStream_t st, int64_t n, const double *pos, const double *vel, const int32_t *type,
+                   const uint8_t *frozen, Geom g, int ntypes, Soa3 xp, Soa3 vp, uint32_t *tag,
+                   uint8_t *typ, int *status)
+{
+    if (n <= 0) return;
+    k_ingest<<<blocks_for(n), kBlock, 0, st>>>((int)n, pos, vel, type, frozen, g, ntypes, xp, vp, tag,
+                                               typ, status);
+}
+
+void launch_sort(hipStream_t st, int n, Geom g, Soa3c xin, Soa3c vin, Soa3c xprev_in,
+                 const uint32_t *tag_in, const uint8_t *typ_in, Soa3 xout, Soa3 vout, Soa3 xprev_out,
+                 uint32_t *tag_out, uint8_t *typ_out, int *key, int *slot, uint32_t *tmpid, int *counts,
+                 int *cstart, int *bsum, const int *gate)
+{
+    const int m = g.ncells;
+    const int nb = (m + kScanTile - 1) / kScanTile;
+    if (n > 0) k_bin<<<blocks_for(n), kBlock, 0, st>>>(n, g, xin, key, slot, counts, gate);
+    k_scan_local<<<nb, kScanThreads, 0, st>>>(m, counts, cstart, bsum, gate);
+    k_scan_top<<<1, kScanThreads, 0, st>>>(nb, m, bsum, cstart, gate);
+    k_scan_add<<<nb, kScanThreads, 0, st>>>(m, bsum, cstart, gate);
+    if (n > 0) {
+        k_scatter_id<<<blocks_for(n), kBlock, 0, st>>>(n, key, slot, cstart, tag_in, tmpid, gate);
+        k_rank_gather<<<blocks_for(n), kBlock, 0, st>>>(n, key, cstart, tmpid, xin, vin, xprev_in,
+                                                        tag_in, typ_in, xout, vout, xprev_out, tag_out,
+                                                        typ_out, gate);
+    }
+}
+
+}  // namespace mdpd

@@ -1,0 +1,308 @@
+"""GPU parity of the HIP hot path against the FP64 oracle (needs an MI355X).
+
+Bars (per the target of this path):
+  * neighbour sets (r < r_c and r < r_d) bit-exact: count and set hash equal
+  * FP64 form: per-particle forces within 1e-12 of the oracle, measured as
+    max_i |F_i - F_i^oracle| / rms_k |F_k^oracle|; densities within 1e-12
+    relative; positions and velocities within 1e-12 absolute after few steps
+  * FP32-forces form: forces within 1e-5 by the same measure, densities within
+    1e-5 relative
+Every case prints its name first so that a failing run names it.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_10134_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def mdpd():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1903_10134_amd as m
+    m.lib()
+    return m
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def force_err(F, Fo):
+    rms = np.sqrt(np.mean(np.sum(Fo * Fo, axis=1)))
+    return float(np.abs(F - Fo).max() / rms) if F.size else 0.0
+
+
+def rel_err(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)) if a.size else 0.0
+
+
+def pdiff(x, xo, box):
+    """Largest periodic (minimum-image) coordinate difference."""
+    d = x - xo
+    L = np.asarray(box, dtype=np.float64)
+    d -= np.round(d / L) * L
+    return float(np.abs(d).max()) if d.size else 0.0
+
+
+def state_tols(precision, w, F_rms):
+    """Position / velocity tolerances after one step implied by the force bar:
+    a force error dF moves v by dt dF / m and x by dt^2 dF / (2 m)."""
+    if precision == "fp64":
+        return 1e-12, 1e-11
+    dF = FP32_TOL * F_rms
+    return 2.0 * (0.5 * w.dt ** 2 / w.mass * dF) + 1e-12, 2.0 * (w.dt / w.mass * dF) + 1e-11
+
+
+def orc_params(w, search=0):
+    return oracle.make_params(**w.param_kwargs(), search=search)
+
+
+def dense_cluster(seed=4):
+    """Background fluid plus 300 particles inside one cell: overflows the
+    fixed-capacity neighbour list and exercises the direct-scan path.  Soft
+    parameters and a short timestep keep the packed cell from exploding."""
+    w = W.bulk(L=6.0, density=3.0, seed=seed, A=-4.0, B=2.0, gamma=0.45, dt=0.001)
+    rng = np.random.default_rng(seed)
+    extra = 2.0 + rng.random((300, 3)) * 0.9
+    w.x = np.concatenate([w.x, extra])
+    w.v = np.concatenate([w.v, rng.normal(size=(300, 3))])
+    w.types = np.zeros(w.x.shape[0], np.int32)
+    w.frozen = np.zeros(w.x.shape[0], np.uint8)
+    w.name = "dense_cluster"
+    return w
+
+
+def mixed_types(seed=5):
+    """Two types, a quarter of the particles frozen, walls off."""
+    w = W.bulk(L=7.0, density=6.0, seed=seed)
+    rng = np.random.default_rng(seed)
+    w.types = (rng.random(w.n) < 0.3).astype(np.int32)
+    w.frozen = (rng.random(w.n) < 0.25).astype(np.uint8)
+    w.A = np.array([[-40.0, -30.0], [-30.0, -20.0]])
+    w.B = np.array([[25.0, 22.0], [22.0, 28.0]])
+    w.gamma = np.array([[4.5, 6.0], [6.0, 3.0]])
+    w.g = (0.02, 0.0, -0.01)
+    w.name = "mixed_types"
+    return w
+
+
+def small_cases():
+    return {
+        "bulk_L10_n6000": W.bulk(L=10.0, seed=0),
+        "ragged_L7.3_n1000": W.bulk(L=7.3, n=1000, seed=1),
+        "three_cells_L3.2": W.bulk(L=3.2, n=150, seed=2),
+        "box_5x3.5x8.25": W.bulk(box=(5.0, 3.5, 8.25), n=900, seed=3),
+        "dense_cluster": dense_cluster(),
+        "mixed_types": mixed_types(),
+    }
+
+
+CASES = small_cases()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_neighbor_sets_bit_exact(mdpd, name):
+    w = CASES[name]
+    say("neighbor sets", name, w.n)
+    s = mdpd.System(w)
+    p = orc_params(w, search=0)
+    for cut in (w.rc, w.rd, 0.5):
+        c, h = s.neighbors(cut)
+        co, ho = oracle.neighbors(p, w.x, cut)
+        assert np.array_equal(c, co), (name, cut, int(np.sum(c != co)))
+        assert np.array_equal(h, ho), (name, cut, int(np.sum(h != ho)))
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_density_and_forces_step0_and_step1(mdpd, name, precision):
+    w = CASES[name]
+    say("step0/1", name, precision, w.n)
+    prec = mdpd.FP64 if precision == "fp64" else mdpd.FP32_FORCES
+    tol = FP64_TOL if precision == "fp64" else FP32_TOL
+    s = mdpd.System(w, precision=prec)
+    o = oracle.System(orc_params(w), w.x, w.v, w.types, w.frozen)
+    F_rms = 0.0
+    for step in (0, 1):
+        if step:
+            s.step(1)
+            o.step(1)
+        st = o.state()
+        x, v, rho = s.state()
+        F = s.forces()
+        assert rel_err(rho, st["rho"]) < tol, (step, rel_err(rho, st["rho"]))
+        assert force_err(F, st["F"]) < tol, (step, force_err(F, st["F"]))
+        F_rms = max(F_rms, float(np.sqrt(np.mean(np.sum(st["F"] ** 2, axis=1)))))
+        xtol, vtol = state_tols(precision, w, F_rms)
+        assert pdiff(x, st["x"], w.box) < xtol, (step, pdiff(x, st["x"], w.box), xtol)
+        assert np.abs(v - st["v"]).max() < vtol, (step, np.abs(v - st["v"]).max(), vtol)
+    s.close()
+
+
+def test_short_trajectory_fp64(mdpd):
+    w = CASES["bulk_L10_n6000"]
+    say("trajectory 20 steps", w.name)
+    s = mdpd.System(w)
+    o = oracle.System(orc_params(w), w.x, w.v)
+    s.step(20)
+    o.step(20)
+    st = o.state()
+    x, v, rho = s.state()
+    assert pdiff(x, st["x"], w.box) < 1e-10
+    assert np.abs(v - st["v"]).max() < 1e-9
+    assert force_err(s.forces(), st["F"]) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["bulk_L10_n6000", "mixed_types"])
+def test_observables_match(mdpd, name):
+    w = CASES[name]
+    say("observables", name)
+    s = mdpd.System(w)
+    o = oracle.System(orc_params(w), w.x, w.v, w.types, w.frozen)
+    for k in (0, 5):
+        if k:
+            s.step(k)
+            o.step(k)
+        a, b = s.observables(), o.observables()
+        assert a["step"] == b["step"]
+        for key in ("ke", "kT", "pressure", "epot", "mean_rho", "virial"):
+            assert abs(a[key] - b[key]) <= 1e-11 * max(1.0, abs(b[key])), (key, a[key], b[key])
+        for c, key in enumerate(("px", "py", "pz")):
+            assert abs(a["momentum"][c] - b[key]) < 1e-9, key
+
+
+def test_determinism_bitwise(mdpd):
+    w = CASES["bulk_L10_n6000"]
+    say("determinism", w.name)
+    out = []
+    for _ in range(2):
+        s = mdpd.System(w, precision=mdpd.FP32_FORCES)
+        s.step(10)
+        x, v, rho = s.state()
+        out.append((x, v, rho))
+        s.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 8, 16])
+def test_lane_splits_agree(mdpd, lanes):
+    w = CASES["dense_cluster"]
+    say("lanes", lanes)
+    s = mdpd.System(w)
+    for pss in range(3):
+        s.set_lanes(pss, lanes)
+    o = oracle.System(orc_params(w), w.x, w.v)
+    s.step(2)
+    o.step(2)
+    st = o.state()
+    assert force_err(s.forces(), st["F"]) < FP64_TOL
+    c, h = s.neighbors(w.rc)
+    co, ho = oracle.neighbors(orc_params(w), st["x"], w.rc)
+    assert np.array_equal(c, co) and np.array_equal(h, ho)
+
+
+def test_empty_and_single_particle(mdpd):
+    say("empty / single")
+    w = W.bulk(L=5.0, n=0)
+    s = mdpd.System(w)
+    s.step(3)
+    o = s.observables()
+    assert o["n"] == 0 and o["ke"] == 0.0
+    s.close()
+    w = W.bulk(L=5.0, n=1, seed=3)
+    s = mdpd.System(w)
+    s.step(3)
+    x, v, _ = s.state()
+    assert np.allclose(s.forces(), 0.0)
+    assert np.allclose(v, w.v)
+    s.close()
+
+
+def test_invalid_inputs_are_rejected(mdpd):
+    say("invalid inputs")
+    w = W.bulk(L=5.0, n=50, seed=1)
+    p = mdpd.make_params(**w.param_kwargs())
+    bad = w.x.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(mdpd.MdpdError) as e:
+        mdpd.mdpd_create(p, bad, w.v, w.types, w.frozen)
+    assert e.value.status == -1
+    bad = w.x.copy()
+    bad[4, 0] = 2.5 * 5.0
+    with pytest.raises(mdpd.MdpdError):
+        mdpd.mdpd_create(p, bad, w.v, w.types, w.frozen)
+    t = w.types.copy()
+    t[0] = 3
+    with pytest.raises(mdpd.MdpdError):
+        mdpd.mdpd_create(p, w.x, w.v, t, w.frozen)
+    small = mdpd.make_params(**{**w.param_kwargs(), "box": (2.5, 5.0, 5.0)})
+    with pytest.raises(mdpd.MdpdError) as e:
+        mdpd.mdpd_create(small, w.x * 0.4, w.v, w.types, w.frozen)
+    assert e.value.status == -6
+    p2 = mdpd.make_params(**{**w.param_kwargs(), "rd": 1.5})
+    with pytest.raises(mdpd.MdpdError):
+        mdpd.mdpd_create(p2, w.x, w.v, w.types, w.frozen)
+
+
+def test_device_inputs_equal_host_inputs(mdpd):
+    import torch
+    w = CASES["ragged_L7.3_n1000"]
+    say("device inputs")
+    a = mdpd.System(w)
+    b = mdpd.System(w, device_inputs=True, stream=torch.cuda.current_stream())
+    a.step(3)
+    b.step(3)
+    for u, v in zip(a.state(), b.state()):
+        assert np.array_equal(u, v)
+
+
+# ---------------------------------------------------------------------------
+# Full size: 1,053,696 particles (56^3 cells at number density 6), the launch
+# configuration the benchmark times.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def full():
+    w = W.bulk(L=56.0, seed=0)
+    o = oracle.System(orc_params(w, search=1), w.x, w.v)
+    st0 = o.state()
+    o.step(1)
+    st1 = o.state()
+    return w, st0, st1
+
+
+def test_full_size_neighbor_sets(mdpd, full):
+    w, st0, _ = full
+    say("full size neighbor sets", w.n)
+    s = mdpd.System(w, precision=mdpd.FP32_FORCES)
+    p = orc_params(w, search=1)
+    for cut in (w.rc, w.rd):
+        c, h = s.neighbors(cut)
+        co, ho = oracle.neighbors(p, w.x, cut)
+        assert np.array_equal(c, co) and np.array_equal(h, ho), cut
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_size_forces(mdpd, full, precision):
+    w, st0, st1 = full
+    say("full size forces", precision, w.n)
+    prec = mdpd.FP64 if precision == "fp64" else mdpd.FP32_FORCES
+    tol = FP64_TOL if precision == "fp64" else FP32_TOL
+    s = mdpd.System(w, precision=prec)
+    assert force_err(s.forces(), st0["F"]) < tol
+    s.step(1)
+    x, v, rho = s.state()
+    assert force_err(s.forces(), st1["F"]) < tol
+    assert rel_err(rho, st1["rho"]) < tol
+    F_rms = float(np.sqrt(np.mean(np.sum(st0["F"] ** 2, axis=1))))
+    xtol, vtol = state_tols(precision, w, F_rms)
+    assert pdiff(x, st1["x"], w.box) < xtol
+    assert np.abs(v - st1["v"]).max() < 2 * vtol
