@@ -58,7 +58,22 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--lanes", type=str, default="", help="n,d,f lanes per particle")
+    ap.add_argument("--forms", type=str, default="fp32_forces,fp64")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="only run a plain device copy of this size 5 times (counter scaling)")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """A plain copy kernel of known size: reads and writes mib MiB per launch."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": n * 4, "launches": 5}), flush=True)
 
 
 def run_form(mdpd, w, precision, steps, warmup, stream, lanes):
@@ -108,6 +123,10 @@ def main():
         sys.exit(2)
     import torch
 
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
+
     import paper_1903_10134_amd as mdpd
     from paper_1903_10134_amd import workloads as W
 
@@ -116,7 +135,9 @@ def main():
     w = W.bulk(L=a.L, seed=0)
     lanes = [int(v) for v in a.lanes.split(",")] if a.lanes else []
     res = {}
-    for name, prec in (("fp32_forces", mdpd.FP32_FORCES), ("fp64", mdpd.FP64)):
+    forms = [f for f in (("fp32_forces", mdpd.FP32_FORCES), ("fp64", mdpd.FP64))
+             if f[0] in a.forms.split(",")]
+    for name, prec in forms:
         res[name] = run_form(mdpd, w, prec, a.steps, a.warmup, stream, lanes)
         r = res[name]
         print(f"# {name}: {r['sec'] * 1e3 / a.steps:.3f} ms/step, "
@@ -165,8 +186,9 @@ def main():
             "pairs_rc": r["pairs_c"], "pairs_rd": r["pairs_d"],
             "kT": r["obs"]["kT"], "pressure": r["obs"]["pressure"], "mean_rho": r["obs"]["mean_rho"],
         }
-    out["fp32_over_fp64"] = out["forms"]["fp32_forces"]["particle_steps_per_s"] / \
-        out["forms"]["fp64"]["particle_steps_per_s"]
+    if "fp64" in res:
+        out["fp32_over_fp64"] = out["forms"]["fp32_forces"]["particle_steps_per_s"] / \
+            out["forms"]["fp64"]["particle_steps_per_s"]
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
     print(json.dumps(out), flush=True)
