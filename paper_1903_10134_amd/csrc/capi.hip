@@ -61,7 +61,9 @@ struct mdpd_system {
     uint8_t *typ[2]{};
     void *rho = nullptr;
     int *key = nullptr, *slot = nullptr, *counts = nullptr, *cstart = nullptr, *bsum = nullptr;
-    int *ncnt = nullptr, *nl = nullptr;
+    int *ncnt = nullptr;
+    uint32_t *nl = nullptr;
+    void *nlr2 = nullptr;
     uint32_t *tmpid = nullptr;
     double *fpart = nullptr;
     int nfpart = 0;       // capacity of fpart in blocks
@@ -165,7 +167,7 @@ struct mdpd_system {
     {
         set_step_keys(stepno);
         tic(1);
-        launch_nlist(st, lanes[0], n, g, cview(xs[cur]), cstart, ncnt, nl, nullptr);
+        launch_nlist(st, fp32, n, g, cview(xs[cur]), cstart, ncnt, nl, nlr2, nullptr);
         toc(1);
         if (walls && !initial) {
             launch_zero_int(st, corr, 1);
@@ -182,11 +184,11 @@ struct mdpd_system {
             toc(0);
             cur = o;
             tic(1);
-            launch_nlist(st, lanes[0], n, g, cview(xs[cur]), cstart, ncnt, nl, corr);
+            launch_nlist(st, fp32, n, g, cview(xs[cur]), cstart, ncnt, nl, nlr2, corr);
             toc(1);
         }
         tic(2);
-        launch_density(st, lanes[1], fp32, n, pc, g, cview(xs[cur]), cstart, ncnt, nl, rho);
+        launch_density(st, lanes[1], fp32, n, pc, g, cview(xs[cur]), cstart, ncnt, nl, nlr2, rho);
         toc(2);
         nfpart_used = n > 0 ? force_blocks(lanes[2], n) : 0;
         tic(3);
@@ -254,10 +256,12 @@ mdpd_status make_geom(const mdpd_params *p, Geom *g)
         g->L[a] = L;
         g->nc[a] = nc;
         g->s[a] = nc / L;
+        g->cs[a] = L / nc;
         total *= nc;
     }
     if (total > (long long)4096 * 4096) return fail(MDPD_E_UNSUPPORTED, "more than 2^24 cells");
     g->ncells = (int)total;
+    g->rc = p->rc;
     g->rc2 = p->rc * p->rc;
     g->rd2 = p->rd * p->rd;
     return MDPD_OK;
@@ -356,6 +360,11 @@ mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, cons
     ALLOC(s->alloc(&s->tmpid, N));
     ALLOC(s->alloc(&s->ncnt, N));
     ALLOC(s->alloc(&s->nl, N * kListCap));
+    {
+        double *r2 = nullptr;
+        ALLOC(s->alloc(&r2, s->fp32 ? N * kListCap / 2 : N * kListCap));
+        s->nlr2 = r2;
+    }
     ALLOC(s->alloc(&s->counts, (size_t)g.ncells));
     ALLOC(s->alloc(&s->cstart, (size_t)g.ncells + 1));
     ALLOC(s->alloc(&s->bsum, (size_t)nb_scan + 1));

@@ -8,8 +8,11 @@
 //                                   bit 31 set for frozen wall particles
 //   type                          : uint8
 //   rho                           : FP64 (FP64 form) or FP32 (FP32 form)
-//   neighbour list                : int32 slot indices, kListCap per particle,
-//                                   particle-major, plus a count per particle
+//   neighbour list                : kListCap entries per particle, particle-major:
+//                                   u32 slot of the neighbour (bits 0..30) with
+//                                   bit 31 set when r < r_d, a parallel array of
+//                                   the pair's r^2 (FP32 or FP64 as rho), and a
+//                                   count per particle
 //   cell_start                    : ncells + 1 offsets into the sorted order
 #pragma once
 
@@ -34,10 +37,11 @@ inline Soa3c cview(const Soa3 &a) { return Soa3c{a.x, a.y, a.z}; }
 // Cell lattice: nc[a] cells of edge L[a]/nc[a] >= r_c per axis.
 struct Geom {
     double L[3];
-    double s[3];  // cells per unit length, nc / L
+    double s[3];   // cells per unit length, nc / L
+    double cs[3];  // cell edge, L / nc
     int nc[3];
     int ncells;
-    double rc2, rd2;
+    double rc, rc2, rd2;
 };
 
 // Scalars of one pair pass (one launch).
@@ -146,16 +150,17 @@ void launch_sort(hipStream_t st, int n, Geom g, Soa3c xin, Soa3c vin, Soa3c xpre
                  const uint32_t *tag_in, const uint8_t *typ_in, Soa3 xout, Soa3 vout,
                  Soa3 xprev_out, uint32_t *tag_out, uint8_t *typ_out, int *key, int *slot,
                  uint32_t *tmpid, int *counts, int *cstart, int *bsum, const int *gate);
-void launch_nlist(hipStream_t st, int lanes, int n, Geom g, Soa3c xs, const int *cstart,
-                  int *ncnt, int *nl, const int *gate);
+void launch_nlist(hipStream_t st, bool fp32, int n, Geom g, Soa3c xs, const int *cstart,
+                  int *ncnt, uint32_t *nl, void *nlr2, const int *gate);
 void launch_density(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g,
-                    Soa3c xs, const int *cstart, const int *ncnt, const int *nl, void *rho);
+                    Soa3c xs, const int *cstart, const int *ncnt, const uint32_t *nl,
+                    const void *nlr2, void *rho);
 void launch_phi(hipStream_t st, int lanes, int n, const PairConst &pc, Geom g, Soa3c xs,
                 Soa3c xprev, Soa3 xfix, Soa3 vfix, const uint32_t *tag, const int *cstart,
-                const int *ncnt, const int *nl, int *ncorr, unsigned long long *ncorr_total);
+                const int *ncnt, const uint32_t *nl, int *ncorr, unsigned long long *ncorr_total);
 void launch_force(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g,
                   Soa3c xs, Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ,
-                  const int *cstart, const int *ncnt, const int *nl, Soa3 vout, Soa3 fout,
+                  const int *cstart, const int *ncnt, const uint32_t *nl, Soa3 vout, Soa3 fout,
                   Soa3 vpred, Soa3 xpred, double *part, int *status, int initial);
 int force_blocks(int lanes, int n);
 void launch_observables(hipStream_t st, bool fp32, int n, const PairConst &pc, Soa3c v,
@@ -168,7 +173,7 @@ void launch_export(hipStream_t st, bool fp32, int n, Soa3c x, Soa3c v, const voi
                    const uint32_t *tag, double *pos, double *vel, double *rho_out);
 void launch_debug_neighbors(hipStream_t st, int n, Geom g, const PairConst &pc, double cutoff2,
                             Soa3c xs, const uint32_t *tag, const int *cstart, const int *ncnt,
-                            const int *nl, int64_t *count, uint64_t *hash);
+                            const uint32_t *nl, int64_t *count, uint64_t *hash);
 void launch_zero_int(hipStream_t st, int *p, int n);
 
 }  // namespace mdpd

@@ -1,23 +1,23 @@
 // pair.hip -- the pair passes of one mDPD timestep on gfx950.
 //
-//   k_nlist    cell scan: for every particle the neighbours within r_c (exact
-//              FP64 test on FP64 positions), written to a fixed-capacity list
-//   k_density  many-body density rho_i = sum_{j != i, r < r_d} w_rho(r_ij)
-//              (Sec. 2.1) over the list
-//   k_phi      boundary volume fraction of fluid particles at the predicted
-//              positions and the predictor-corrector flag (Sec. 2.2, Sec. 3.2)
-//   k_force    Eq. 1 conservative force, dissipative and random forces
-//              (Sec. 2.1), body force, and the velocity-Verlet update fused in
-//              the epilogue: v(t+dt), the next half-step velocity and the next
-//              predicted position (Alg. 1)
+//   k_nlist_cell  one wavefront per cell: the neighbours within r_c of every
+//                 particle of the cell (exact FP64 test on FP64 positions),
+//                 written to a fixed-capacity list; each entry carries a flag
+//                 for r < r_d, and the pair's r^2 is stored beside it
+//   k_density     many-body density rho_i = sum_{j != i, r < r_d} w_rho(r_ij)
+//                 (Sec. 2.1) from the stored r^2 of the flagged entries
+//   k_phi         boundary volume fraction of fluid particles at the predicted
+//                 positions and the predictor-corrector flag (Sec. 2.2, 3.2)
+//   k_force       Eq. 1 conservative force, dissipative and random forces
+//                 (Sec. 2.1), body force, and the velocity-Verlet update fused
+//                 in the epilogue: v(t+dt), the next half-step velocity and the
+//                 next predicted position (Alg. 1)
 //
-// Work decomposition: P lanes of a 64-wide wavefront cooperate on one
-// particle i (P = 1, 2, 4, 8 or 16).  In the cell scan the P lanes stride
-// through each contiguous run of candidate slots (three x-adjacent cells are
-// contiguous in the sorted order), and a wavefront ballot compacts the hits
-// into the list in scan order.  In the list passes the P lanes split the
-// list entries and combine their partial sums with a butterfly of lane
-// shuffles inside the group, so every sum has one fixed order.
+// In the list passes P lanes of a 64-wide wavefront cooperate on one particle
+// (P = 1, 2, 4, 8 or 16): they split its list entries and combine their partial
+// sums with a butterfly of lane shuffles inside the group, so every sum has
+// one fixed order.  A particle with more than kListCap neighbours is served by
+// a direct scan of the cells with the same exact test.
 #include "mdpd_internal.h"
 
 namespace mdpd {
@@ -26,50 +26,76 @@ namespace {
 
 constexpr double kSqrt3Scaled = 1.7320508075688772 / 16777216.0;  // sqrt(3) 2^-24
 constexpr float kSqrt3ScaledF = 1.7320508075688772f / 16777216.0f;
+constexpr uint32_t kNearBit = 0x80000000u;  // list entry flag: r < r_d
+constexpr uint32_t kSlotMask = 0x7fffffffu;
+constexpr int kWavesPerBlock = kBlock / 64;
 
-// Calls fn(begin, end, sx, sy, sz) for the contiguous slot ranges holding the
-// 27 cells around the cell of (xi, yi, zi); (sx, sy, sz) is the periodic shift
-// to add to x_i - x_j for candidates of that range.
+// Element idx of an array addressed with a 32-bit byte offset, so that the
+// load can take the array base in scalar registers.
+template <typename T>
+__device__ __forceinline__ T ld(const T *__restrict__ base, int idx)
+{
+    return *(const T *)((const char *)base + (uint32_t)idx * (uint32_t)sizeof(T));
+}
+
+__device__ __forceinline__ int wrap_index(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+// Calls fn(begin, end, sx, sy, sz) for the contiguous slot ranges of the
+// cells around the cell of (xi, yi, zi) that can hold a particle closer than
+// r_c; (sx, sy, sz) is the periodic shift to add to x_i - x_j for candidates of
+// that range.  Rows (dy, dz) whose nearest face is already r_c away are
+// skipped, and in each row the x-neighbour cells are kept only when their
+// facing side is closer than the row's remaining reach sqrt(r_c^2 - dy^2 -
+// dz^2).  The clipping margin (1e-9) is far above rounding, so it never drops
+// a pair that the exact test would keep.
 template <typename Fn>
 __device__ __forceinline__ void for_each_row(const Geom &g, double xi, double yi, double zi,
                                              const int *__restrict__ cstart, Fn &&fn)
 {
+    constexpr double kMargin = 1e-9;
     const int nx = g.nc[0], ny = g.nc[1], nz = g.nc[2];
     const int cx = cell_coord(xi, g.s[0], nx);
     const int cy = cell_coord(yi, g.s[1], ny);
     const int cz = cell_coord(zi, g.s[2], nz);
+    const double lox = xi - cx * g.cs[0], hix = (cx + 1) * g.cs[0] - xi;
+    const double loy = yi - cy * g.cs[1], hiy = (cy + 1) * g.cs[1] - yi;
+    const double loz = zi - cz * g.cs[2], hiz = (cz + 1) * g.cs[2] - zi;
     for (int dz = -1; dz <= 1; ++dz) {
-        int zz = cz + dz;
-        double sz = 0.0;
-        if (zz < 0) {
-            zz += nz;
-            sz = g.L[2];
-        } else if (zz >= nz) {
-            zz -= nz;
-            sz = -g.L[2];
-        }
+        const double ez = dz == 0 ? 0.0 : fmax(0.0, (dz < 0 ? loz : hiz) - kMargin);
+        if (ez >= g.rc) continue;
+        const int zz = wrap_index(cz + dz, nz);
+        const double sz = cz + dz < 0 ? g.L[2] : (cz + dz >= nz ? -g.L[2] : 0.0);
         for (int dy = -1; dy <= 1; ++dy) {
-            int yy = cy + dy;
-            double sy = 0.0;
-            if (yy < 0) {
-                yy += ny;
-                sy = g.L[1];
-            } else if (yy >= ny) {
-                yy -= ny;
-                sy = -g.L[1];
-            }
+            const double ey = dy == 0 ? 0.0 : fmax(0.0, (dy < 0 ? loy : hiy) - kMargin);
+            const double q = ey * ey + ez * ez;
+            if (q >= g.rc2) continue;
+            const double reach = __builtin_sqrt(g.rc2 - q) + kMargin;
+            const int yy = wrap_index(cy + dy, ny);
+            const double sy = cy + dy < 0 ? g.L[1] : (cy + dy >= ny ? -g.L[1] : 0.0);
             const int base = nx * (yy + ny * zz);
-            if (cx > 0 && cx < nx - 1) {
-                fn(cstart[base + cx - 1], cstart[base + cx + 2], 0.0, sy, sz);
-            } else if (cx == 0) {
+            const int xa = cx - (lox < reach ? 1 : 0);
+            const int xb = cx + (hix < reach ? 1 : 0);
+            if (xa >= 0 && xb < nx) {
+                fn(cstart[base + xa], cstart[base + xb + 1], 0.0, sy, sz);
+            } else if (xa < 0) {
                 fn(cstart[base + nx - 1], cstart[base + nx], g.L[0], sy, sz);
-                fn(cstart[base], cstart[base + 2], 0.0, sy, sz);
+                fn(cstart[base], cstart[base + xb + 1], 0.0, sy, sz);
             } else {
-                fn(cstart[base + nx - 2], cstart[base + nx], 0.0, sy, sz);
+                fn(cstart[base + xa], cstart[base + nx], 0.0, sy, sz);
                 fn(cstart[base], cstart[base + 1], -g.L[0], sy, sz);
             }
         }
     }
+}
+
+// Hardware dispatches workgroups to the 8 XCDs round robin; remap so that
+// each XCD (and its L2) works through one contiguous chunk of the sorted
+// particles, whose neighbour data it then reuses.
+__device__ __forceinline__ int xcd_block()
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int per = nb >> 3, rem = nb & 7, x = b & 7, k = b >> 3;
+    return x * per + (x < rem ? x : rem) + k;
 }
 
 // Sum over the P lanes of a group (butterfly, fixed order).
@@ -81,22 +107,39 @@ __device__ __forceinline__ T group_sum(T v)
     return v;
 }
 
+// Broadcast of lane u's value (u wave-uniform) through the scalar unit.
+__device__ __forceinline__ int bcast_i(int v, int u) { return __builtin_amdgcn_readlane(v, u); }
+__device__ __forceinline__ double bcast_d(double v, int u)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, u);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), u);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ int lanes_below(unsigned long long m)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
 // Visits every neighbour j (r_ij < r_c, j != i) of slot i: from the list when
 // it did not overflow, else by a direct cell scan with the same exact test.
-// fn(j, dx, dy, dz) receives the minimum-image difference x_i - x_j.
+// fn(j, dx, dy, dz, near) receives the minimum-image difference x_i - x_j and
+// whether r_ij < r_d.
 template <int P, typename Fn>
 __device__ __forceinline__ void for_each_neighbor(const PairConst &pc, const Geom &g, int i, int sub,
                                                   double xi, double yi, double zi, Soa3c xs,
                                                   const int *__restrict__ cstart, int cnt,
-                                                  const int *__restrict__ lst, Fn &&fn)
+                                                  const uint32_t *__restrict__ lst, Fn &&fn)
 {
     if (cnt <= kListCap) {
         for (int k = sub; k < cnt; k += P) {
-            const int j = lst[k];
-            const double dx = min_image(xi - xs.x[j], pc.L[0], pc.invL[0]);
-            const double dy = min_image(yi - xs.y[j], pc.L[1], pc.invL[1]);
-            const double dz = min_image(zi - xs.z[j], pc.L[2], pc.invL[2]);
-            fn(j, dx, dy, dz);
+            const uint32_t e = lst[k];
+            const int j = (int)(e & kSlotMask);
+            const double dx = min_image(xi - ld(xs.x, j), pc.L[0], pc.invL[0]);
+            const double dy = min_image(yi - ld(xs.y, j), pc.L[1], pc.invL[1]);
+            const double dz = min_image(zi - ld(xs.z, j), pc.L[2], pc.invL[2]);
+            fn(j, dx, dy, dz, (e & kNearBit) != 0);
         }
     } else {
         for_each_row(g, xi, yi, zi, cstart, [&](int b, int e, double sx, double sy, double sz) {
@@ -105,52 +148,206 @@ __device__ __forceinline__ void for_each_neighbor(const PairConst &pc, const Geo
                 const double dx = (xi - xs.x[j]) + sx;
                 const double dy = (yi - xs.y[j]) + sy;
                 const double dz = (zi - xs.z[j]) + sz;
-                if (exact_r2(dx, dy, dz) < g.rc2) fn(j, dx, dy, dz);
+                const double r2 = exact_r2(dx, dy, dz);
+                if (r2 < g.rc2) fn(j, dx, dy, dz, r2 < g.rd2);
             }
         });
     }
 }
 
 // ---------------------------------------------------------------------------
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_nlist(Geom g, int n, Soa3c xs,
-                                                  const int *__restrict__ cstart,
-                                                  int *__restrict__ ncnt, int *__restrict__ nl,
-                                                  const int *__restrict__ gate)
+// Neighbour list: one wavefront per cell.
+//
+// Interior cells (no periodic image in the stencil): the 27 stencil cells are
+// 9 rows of 3 x-adjacent cells, each row contiguous in the sorted order.  The
+// rows of one dz form a batch of up to 128 candidates held in two register
+// slots (lane q holds candidate q and q + 64), so all candidates of the cell
+// are loaded once.  The wave then loops uniformly over the particles i of the
+// cell, broadcasts i's position, and tests the batches with the exact FP64
+// test, 64 pairs per instruction.  A ballot and mbcnt append the hits to i's
+// list in candidate order; i's count is a wave-uniform scalar.
+//
+// Other cells (a periodic image, or a batch above 128 candidates) take the
+// general path: batches are walked 64 candidates at a time with the shifts of
+// each row piece, and i's running count lives in lane (i mod 64).
+//
+// Each entry is the neighbour's slot, with kNearBit set when r < r_d, and the
+// exact r^2 is stored at the same position of a parallel array (R2 = FP32 or
+// FP64, the arithmetic of the density pass).
+template <typename R2>
+__device__ __forceinline__ void emit_hit(uint32_t *__restrict__ out, R2 *__restrict__ outr, int pos,
+                                         int slot, double r2, double rd2)
+{
+    if (pos < kListCap) {
+        out[pos] = (uint32_t)slot | (r2 < rd2 ? kNearBit : 0u);
+        outr[pos] = (R2)r2;
+    }
+}
+
+template <typename R2>
+__global__ __launch_bounds__(kBlock) void k_nlist_cell(Geom g, int n, Soa3c xs,
+                                                       const int *__restrict__ cstart,
+                                                       int *__restrict__ ncnt, uint32_t *__restrict__ nl,
+                                                       R2 *__restrict__ nlr2, const int *__restrict__ gate)
 {
     if (gate && *gate == 0) return;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    const int i = t / P;
-    const int sub = t & (P - 1);
-    if (i >= n) return;
-    const int gbase = (threadIdx.x & 63) & ~(P - 1);
-    const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
-    int *out = nl + (size_t)i * kListCap;
-    int cnt = 0;
-    for_each_row(g, xi, yi, zi, cstart, [&](int b, int e, double sx, double sy, double sz) {
-        for (int j0 = b; j0 < e; j0 += P) {
-            const int j = j0 + sub;
-            bool hit = false;
-            if (j < e && j != i) {
-                const double dx = (xi - xs.x[j]) + sx;
-                const double dy = (yi - xs.y[j]) + sy;
-                const double dz = (zi - xs.z[j]) + sz;
-                hit = exact_r2(dx, dy, dz) < g.rc2;
-            }
-            const unsigned long long m = __ballot(hit);
-            const unsigned long long gm =
-                P == 64 ? m : ((m >> gbase) & ((1ull << (P & 63)) - 1ull));
-            const int pre = __popcll(gm & ((1ull << sub) - 1ull));
-            if (hit && cnt + pre < kListCap) out[cnt + pre] = j;
-            cnt += __popcll(gm);
+    const int lane = threadIdx.x & 63;
+    const int c = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    if (c >= g.ncells) return;
+    const int i0 = cstart[c], ni = cstart[c + 1] - i0;
+    if (ni == 0) return;
+    const int nx = g.nc[0], ny = g.nc[1], nz = g.nc[2];
+    const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
+    const double rc2 = g.rc2, rd2 = g.rd2;
+
+    bool fast = cx > 0 && cx < nx - 1 && cy > 0 && cy < ny - 1 && cz > 0 && cz < nz - 1;
+    int rb[9], rl[9], qz[3];
+    if (fast) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            const int base = nx * ((cy + r % 3 - 1) + ny * (cz + r / 3 - 1)) + cx;
+            rb[r] = cstart[base - 1];
+            rl[r] = cstart[base + 2] - rb[r];
         }
-    });
-    if (sub == 0) ncnt[i] = cnt;
+#pragma unroll
+        for (int z = 0; z < 3; ++z) {
+            qz[z] = rl[3 * z] + rl[3 * z + 1] + rl[3 * z + 2];
+            if (qz[z] > 128) fast = false;
+        }
+    }
+    if (fast) {
+        double cxj[6], cyj[6], czj[6];
+        int cs[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            const int z = s >> 1;
+            const int q = (s & 1) * 64 + lane;
+            int slot = -1;
+            if (q < qz[z]) {
+                const int l0 = rl[3 * z], l1 = rl[3 * z + 1];
+                slot = q < l0 ? rb[3 * z] + q
+                              : (q < l0 + l1 ? rb[3 * z + 1] + (q - l0) : rb[3 * z + 2] + (q - l0 - l1));
+            }
+            cs[s] = slot;
+            const int js = slot >= 0 ? slot : i0;
+            cxj[s] = ld(xs.x, js);
+            cyj[s] = ld(xs.y, js);
+            czj[s] = ld(xs.z, js);
+        }
+        for (int ib = 0; ib < ni; ib += 64) {
+            const int nic = ni - ib < 64 ? ni - ib : 64;
+            const int me = i0 + ib + (lane < nic ? lane : 0);
+            const double pxi = ld(xs.x, me), pyi = ld(xs.y, me), pzi = ld(xs.z, me);
+            for (int u = 0; u < nic; ++u) {
+                const double xi = bcast_d(pxi, u), yi = bcast_d(pyi, u), zi = bcast_d(pzi, u);
+                const int i = i0 + ib + u;
+                uint32_t *out = nl + (size_t)i * kListCap;
+                R2 *outr = nlr2 + (size_t)i * kListCap;
+                int cnt = 0;
+#pragma unroll
+                for (int s = 0; s < 6; ++s) {
+                    if ((s & 1) && qz[s >> 1] <= 64) continue;
+                    const double r2 = exact_r2(xi - cxj[s], yi - cyj[s], zi - czj[s]);
+                    const bool hit = cs[s] >= 0 && cs[s] != i && r2 < rc2;
+                    const unsigned long long m = __ballot(hit);
+                    if (m) {
+                        if (hit) emit_hit<R2>(out, outr, cnt + lanes_below(m), cs[s], r2, rd2);
+                        cnt += __popcll(m);
+                    }
+                }
+                if (lane == 0) ncnt[i] = cnt;
+            }
+        }
+        return;
+    }
+
+    // general path
+    const bool wl = cx == 0, wr = cx == nx - 1;  // the row wraps on the left / right
+    for (int ib = 0; ib < ni; ib += 64) {
+        const int nic = ni - ib < 64 ? ni - ib : 64;
+        const int me = i0 + ib + (lane < nic ? lane : 0);
+        const double pxi = ld(xs.x, me), pyi = ld(xs.y, me), pzi = ld(xs.z, me);
+        int cnt = 0;
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int zz = wrap_index(cz + dz, nz);
+            const double sz = cz + dz < 0 ? g.L[2] : (cz + dz >= nz ? -g.L[2] : 0.0);
+            // six pieces (wave-uniform): per row dy, piece A then piece B
+            int pb[6], pl[6];
+            double psx[6], psy[6];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int dy = r - 1;
+                const int yy = wrap_index(cy + dy, ny);
+                const double sy = cy + dy < 0 ? g.L[1] : (cy + dy >= ny ? -g.L[1] : 0.0);
+                const int base = nx * (yy + ny * zz);
+                int a0, a1, b0, b1;
+                double asx = 0.0, bsx = 0.0;
+                if (wl) {         // cells nx-1 (shifted +L), then 0, 1
+                    a0 = base + nx - 1;
+                    a1 = base + nx;
+                    asx = g.L[0];
+                    b0 = base;
+                    b1 = base + 2;
+                } else if (wr) {  // cells nx-2, nx-1, then 0 (shifted -L)
+                    a0 = base + nx - 2;
+                    a1 = base + nx;
+                    b0 = base;
+                    b1 = base + 1;
+                    bsx = -g.L[0];
+                } else {          // cells cx-1 .. cx+1
+                    a0 = base + cx - 1;
+                    a1 = base + cx + 2;
+                    b0 = b1 = base;
+                }
+                pb[2 * r] = cstart[a0];
+                pl[2 * r] = cstart[a1] - pb[2 * r];
+                pb[2 * r + 1] = cstart[b0];
+                pl[2 * r + 1] = cstart[b1] - pb[2 * r + 1];
+                psx[2 * r] = asx;
+                psx[2 * r + 1] = bsx;
+                psy[2 * r] = sy;
+                psy[2 * r + 1] = sy;
+            }
+            int Q = 0;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Q += pl[k];
+            for (int q0 = 0; q0 < Q; q0 += 64) {
+                int off = q0 + lane, slot = -1;
+                double sx = 0.0, sy = 0.0;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    if (off >= 0 && off < pl[k]) {
+                        slot = pb[k] + off;
+                        sx = psx[k];
+                        sy = psy[k];
+                    }
+                    off -= pl[k];
+                }
+                const int js = slot >= 0 ? slot : i0;
+                const double xj = ld(xs.x, js), yj = ld(xs.y, js), zj = ld(xs.z, js);
+                for (int u = 0; u < nic; ++u) {
+                    const double xi = bcast_d(pxi, u), yi = bcast_d(pyi, u), zi = bcast_d(pzi, u);
+                    const int i = i0 + ib + u;
+                    const double r2 = exact_r2((xi - xj) + sx, (yi - yj) + sy, (zi - zj) + sz);
+                    const bool hit = slot >= 0 && slot != i && r2 < rc2;
+                    const unsigned long long m = __ballot(hit);
+                    if (m) {
+                        const int base = bcast_i(cnt, u);
+                        if (hit)
+                            emit_hit<R2>(nl + (size_t)i * kListCap, nlr2 + (size_t)i * kListCap,
+                                         base + lanes_below(m), slot, r2, rd2);
+                        if (lane == u) cnt += __popcll(m);
+                    }
+                }
+            }
+        }
+        if (lane < nic) ncnt[i0 + ib + lane] = cnt;
+    }
 }
 
 // ---------------------------------------------------------------------------
 template <typename R>
-__device__ __forceinline__ R w_rho(const PairConst &pc, double r2);
+__device__ __forceinline__ R w_rho(const PairConst &pc, R r2);
 
 template <>
 __device__ __forceinline__ double w_rho<double>(const PairConst &pc, double r2)
@@ -161,9 +358,9 @@ __device__ __forceinline__ double w_rho<double>(const PairConst &pc, double r2)
 }
 
 template <>
-__device__ __forceinline__ float w_rho<float>(const PairConst &pc, double r2)
+__device__ __forceinline__ float w_rho<float>(const PairConst &pc, float r2)
 {
-    const float r = __builtin_sqrtf((float)r2);
+    const float r = __builtin_sqrtf(r2);
     const float u = 1.0f - r * (float)pc.inv_rd;
     return (float)pc.wrho * u * u;
 }
@@ -172,19 +369,30 @@ template <int P, typename R>
 __global__ __launch_bounds__(kBlock) void k_density(PairConst pc, Geom g, int n, Soa3c xs,
                                                     const int *__restrict__ cstart,
                                                     const int *__restrict__ ncnt,
-                                                    const int *__restrict__ nl, R *__restrict__ rho)
+                                                    const uint32_t *__restrict__ nl,
+                                                    const R *__restrict__ nlr2, R *__restrict__ rho)
 {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int t = xcd_block() * kBlock + threadIdx.x;
     const int i = t / P;
     const int sub = t & (P - 1);
     if (i >= n) return;
-    const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
+    const int cnt = ncnt[i];
     R acc = 0;
-    for_each_neighbor<P>(pc, g, i, sub, xi, yi, zi, xs, cstart, ncnt[i], nl + (size_t)i * kListCap,
-                         [&](int, double dx, double dy, double dz) {
-                             const double r2 = exact_r2(dx, dy, dz);
-                             if (r2 < pc.rd2) acc += w_rho<R>(pc, r2);
-                         });
+    if (cnt <= kListCap) {
+        const uint32_t *lst = nl + (size_t)i * kListCap;
+        const R *lr = nlr2 + (size_t)i * kListCap;
+        for (int k = sub; k < cnt; k += P)
+            if (lst[k] & kNearBit) acc += w_rho<R>(pc, lr[k]);
+    } else {
+        const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
+        for_each_row(g, xi, yi, zi, cstart, [&](int b, int e, double sx, double sy, double sz) {
+            for (int j = b + sub; j < e; j += P) {
+                if (j == i) continue;
+                const double r2 = exact_r2((xi - xs.x[j]) + sx, (yi - xs.y[j]) + sy, (zi - xs.z[j]) + sz);
+                if (r2 < g.rd2) acc += w_rho<R>(pc, (R)r2);
+            }
+        });
+    }
     acc = group_sum<P>(acc);
     if (sub == 0) rho[i] = acc;
 }
@@ -197,9 +405,9 @@ __global__ __launch_bounds__(kBlock) void k_phi(PairConst pc, Geom g, int n, Soa
                                                 const uint32_t *__restrict__ tag,
                                                 const int *__restrict__ cstart,
                                                 const int *__restrict__ ncnt,
-                                                const int *__restrict__ nl, int *__restrict__ flag)
+                                                const uint32_t *__restrict__ nl, int *__restrict__ flag)
 {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int t = xcd_block() * kBlock + threadIdx.x;
     const int i = t / P;
     const int sub = t & (P - 1);
     if (i >= n) return;
@@ -210,7 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_phi(PairConst pc, Geom g, int n, Soa
     const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
     double num = 0.0, den = 0.0;
     for_each_neighbor<P>(pc, g, i, sub, xi, yi, zi, xs, cstart, ncnt[i], nl + (size_t)i * kListCap,
-                         [&](int j, double dx, double dy, double dz) {
+                         [&](int j, double dx, double dy, double dz, bool) {
                              const double r = __builtin_sqrt(exact_r2(dx, dy, dz));
                              const double w = 1.0 - r * pc.inv_rc;
                              den += w * w;
@@ -246,16 +454,57 @@ __global__ __launch_bounds__(kBlock) void k_correct(int n, const int *__restrict
 
 // ---------------------------------------------------------------------------
 // Force pass with the velocity-Verlet epilogue.
-template <typename R>
-struct Acc3 {
-    R x, y, z;
-};
-
 __device__ __forceinline__ double wrap_coord(double x, double L)
 {
     if (x < 0.0) x += L;
     if (x >= L) x -= L;
     return x;
+}
+
+// Force of one neighbour j on i (Eq. 1 + dissipative + random), added to f;
+// the conservative virial and the A-term pair energy, with weight c, to vir
+// and ep.  d = x_i - x_j (minimum image), dv = v_half,i - v_half,j.  A
+// coincident pair (r = 0) contributes nothing.
+template <typename R>
+__device__ __forceinline__ void pair_force(const PairConst &pc, double A, double B, double gam, double sig,
+                                           double Arc2, double dx, double dy, double dz, double dvx,
+                                           double dvy, double dvz, bool near, R rhoij, int th, double c,
+                                           R &fx, R &fy, R &fz, double &vir, double &ep)
+{
+    if constexpr (sizeof(R) == 8) {
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const bool pos = r2 > 0.0;
+        const double rinv = pos ? rsqrt_f64(r2) : 0.0;
+        const double r = r2 * rinv;
+        const double wc = 1.0 - r * pc.inv_rc;
+        double fc = A * wc;
+        if (near) fc += B * rhoij * (1.0 - r * pc.inv_rd);
+        const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+        const double ev = ex * dvx + ey * dvy + ez * dvz;
+        const double fs = fc - gam * wc * wc * ev + sig * wc * ((double)th * kSqrt3Scaled);
+        fx += fs * ex;
+        fy += fs * ey;
+        fz += fs * ez;
+        vir += c * fc * r;
+        ep += pos ? c * Arc2 * wc * wc : 0.0;
+    } else {
+        const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+        const float r2 = fdx * fdx + fdy * fdy + fdz * fdz;
+        const bool pos = r2 > 0.0f;
+        const float rinv = pos ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+        const float r = r2 * rinv;
+        const float wc = 1.0f - r * (float)pc.inv_rc;
+        float fc = (float)A * wc;
+        if (near) fc += (float)B * rhoij * (1.0f - r * (float)pc.inv_rd);
+        const float ex = fdx * rinv, ey = fdy * rinv, ez = fdz * rinv;
+        const float ev = ex * (float)dvx + ey * (float)dvy + ez * (float)dvz;
+        const float fs = fc - (float)gam * wc * wc * ev + (float)sig * wc * ((float)th * kSqrt3ScaledF);
+        fx += fs * ex;
+        fy += fs * ey;
+        fz += fs * ez;
+        vir += c * (double)(fc * r);
+        ep += pos ? c * Arc2 * (double)(wc * wc) : 0.0;
+    }
 }
 
 template <int P, bool MT, typename R>
@@ -265,13 +514,13 @@ __global__ __launch_bounds__(kBlock) void k_force(PairConst pc, Geom g, int n, S
                                                   const uint8_t *__restrict__ typ,
                                                   const int *__restrict__ cstart,
                                                   const int *__restrict__ ncnt,
-                                                  const int *__restrict__ nl, Soa3 vout, Soa3 fout,
+                                                  const uint32_t *__restrict__ nl, Soa3 vout, Soa3 fout,
                                                   Soa3 vpred, Soa3 xpred, double *__restrict__ part,
                                                   int *__restrict__ status, int initial)
 {
     __shared__ double red_v[kBlock];
     __shared__ double red_e[kBlock];
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int t = xcd_block() * kBlock + threadIdx.x;
     const int i = t / P;
     const int sub = t & (P - 1);
     double vir = 0.0, ep = 0.0;
@@ -285,61 +534,37 @@ __global__ __launch_bounds__(kBlock) void k_force(PairConst pc, Geom g, int n, S
             const int T = pc.ntypes;
             const int ti = MT ? (int)typ[i] : 0;
             R fx = 0, fy = 0, fz = 0;
-            for_each_neighbor<P>(
-                pc, g, i, sub, xi, yi, zi, xs, cstart, ncnt[i], nl + (size_t)i * kListCap,
-                [&](int j, double dx, double dy, double dz) {
-                    const double r2 = exact_r2(dx, dy, dz);
-                    if (r2 == 0.0) return;  // coincident pair: no direction, no force
-                    const uint32_t tgj = tag[j];
-                    double A = pc.A, B = pc.B, gam = pc.gamma, sig = pc.sig, Arc2 = pc.Arc2;
-                    if (MT) {
-                        const int tt = ti * T + (int)typ[j];
-                        A = pc.tab[tt];
-                        B = pc.tab[64 + tt];
-                        gam = pc.tab[128 + tt];
-                        sig = pc.tab[192 + tt];
-                        Arc2 = pc.tab[256 + tt];
-                    }
-                    const int th = theta_int(idi, tgj & kIdMask, pc);
-                    const double dvx = vxi - vh.x[j], dvy = vyi - vh.y[j], dvz = vzi - vh.z[j];
-                    const bool near = r2 < pc.rd2;
-                    double fc_d;  // conservative magnitude, kept in FP64 for the virial
-                    double wc_d;
-                    if constexpr (sizeof(R) == 8) {
-                        const double rinv = rsqrt_f64(r2);
-                        const double r = r2 * rinv;
-                        const double wc = 1.0 - r * pc.inv_rc;
-                        double fc = A * wc;
-                        if (near) fc += B * (rhoi + rho[j]) * (1.0 - r * pc.inv_rd);
-                        const double ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
-                        const double ev = ex * dvx + ey * dvy + ez * dvz;
-                        const double fs = fc - gam * wc * wc * ev + sig * wc * ((double)th * kSqrt3Scaled);
-                        fx += fs * ex;
-                        fy += fs * ey;
-                        fz += fs * ez;
-                        fc_d = fc * r;
-                        wc_d = wc;
-                    } else {
-                        const float r2f = (float)r2;
-                        const float rinv = __builtin_amdgcn_rsqf(r2f);
-                        const float r = r2f * rinv;
-                        const float wc = 1.0f - r * (float)pc.inv_rc;
-                        float fc = (float)A * wc;
-                        if (near) fc += (float)B * (rhoi + rho[j]) * (1.0f - r * (float)pc.inv_rd);
-                        const float ex = (float)dx * rinv, ey = (float)dy * rinv, ez = (float)dz * rinv;
-                        const float ev = ex * (float)dvx + ey * (float)dvy + ez * (float)dvz;
-                        const float fs = fc - (float)gam * wc * wc * ev +
-                                         (float)sig * wc * ((float)th * kSqrt3ScaledF);
-                        fx += fs * ex;
-                        fy += fs * ey;
-                        fz += fs * ez;
-                        fc_d = (double)(fc * r);
-                        wc_d = (double)wc;
-                    }
-                    const double c = (tgj & kFrozenBit) ? 1.0 : 0.5;
-                    vir += c * fc_d;
-                    ep += c * Arc2 * wc_d * wc_d;
-                });
+            auto one = [&](int j, double dx, double dy, double dz, bool near) {
+                const uint32_t tgj = ld(tag, j);
+                const double dvx = vxi - ld(vh.x, j), dvy = vyi - ld(vh.y, j), dvz = vzi - ld(vh.z, j);
+                const R rhoij = rhoi + ld(rho, j);
+                double A = pc.A, B = pc.B, gam = pc.gamma, sig = pc.sig, Arc2 = pc.Arc2;
+                if (MT) {
+                    const int tt = ti * T + (int)ld(typ, j);
+                    A = pc.tab[tt];
+                    B = pc.tab[64 + tt];
+                    gam = pc.tab[128 + tt];
+                    sig = pc.tab[192 + tt];
+                    Arc2 = pc.tab[256 + tt];
+                }
+                const int th = theta_int(idi, tgj & kIdMask, pc);
+                const double c = (tgj & kFrozenBit) ? 1.0 : 0.5;
+                pair_force<R>(pc, A, B, gam, sig, Arc2, dx, dy, dz, dvx, dvy, dvz, near, rhoij, th, c, fx, fy,
+                              fz, vir, ep);
+            };
+            const int cnt = ncnt[i];
+            if (cnt <= kListCap) {
+                const uint32_t *lst = nl + (size_t)i * kListCap;
+                for (int k = sub; k < cnt; k += P) {
+                    const uint32_t e = lst[k];
+                    const int j = (int)(e & kSlotMask);
+                    const double xj = ld(xs.x, j), yj = ld(xs.y, j), zj = ld(xs.z, j);
+                    one(j, min_image(xi - xj, pc.L[0], pc.invL[0]), min_image(yi - yj, pc.L[1], pc.invL[1]),
+                        min_image(zi - zj, pc.L[2], pc.invL[2]), (e & kNearBit) != 0);
+                }
+            } else {
+                for_each_neighbor<P>(pc, g, i, sub, xi, yi, zi, xs, cstart, cnt, nullptr, one);
+            }
             fx = group_sum<P>(fx);
             fy = group_sum<P>(fy);
             fz = group_sum<P>(fz);
@@ -396,8 +621,8 @@ __global__ __launch_bounds__(kBlock) void k_force(PairConst pc, Geom g, int n, S
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = red_v[0];
-        part[2 * blockIdx.x + 1] = red_e[0];
+        part[2 * xcd_block()] = red_v[0];
+        part[2 * xcd_block() + 1] = red_e[0];
     }
 }
 
@@ -414,7 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_debug_neighbors(PairConst pc, Geom g
                                                             Soa3c xs, const uint32_t *__restrict__ tag,
                                                             const int *__restrict__ cstart,
                                                             const int *__restrict__ ncnt,
-                                                            const int *__restrict__ nl,
+                                                            const uint32_t *__restrict__ nl,
                                                             int64_t *__restrict__ count,
                                                             uint64_t *__restrict__ hash)
 {
@@ -424,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_debug_neighbors(PairConst pc, Geom g
     int64_t c = 0;
     uint64_t h = 0;
     for_each_neighbor<1>(pc, g, i, 0, xi, yi, zi, xs, cstart, ncnt[i], nl + (size_t)i * kListCap,
-                         [&](int j, double dx, double dy, double dz) {
+                         [&](int j, double dx, double dy, double dz, bool) {
                              if (exact_r2(dx, dy, dz) < cut2) {
                                  ++c;
                                  h += mix64((uint64_t)(tag[j] & kIdMask));
@@ -453,50 +678,50 @@ inline int blocks_for(int64_t threads) { return (int)((threads + kBlock - 1) / k
 
 int force_blocks(int lanes, int n) { return blocks_for((int64_t)n * lanes); }
 
-void launch_nlist(hipStream_t st, int lanes, int n, Geom g, Soa3c xs, const int *cstart, int *ncnt,
-                  int *nl, const int *gate)
+void launch_nlist(hipStream_t st, bool fp32, int n, Geom g, Soa3c xs, const int *cstart, int *ncnt,
+                  uint32_t *nl, void *nlr2, const int *gate)
 {
     if (n <= 0) return;
-    launch_lanes(lanes, [&](auto P) {
-        k_nlist<decltype(P)::value><<<blocks_for((int64_t)n * P), kBlock, 0, st>>>(g, n, xs, cstart,
-                                                                                   ncnt, nl, gate);
-    });
+    const int blocks = (g.ncells + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (fp32)
+        k_nlist_cell<float><<<blocks, kBlock, 0, st>>>(g, n, xs, cstart, ncnt, nl, (float *)nlr2, gate);
+    else
+        k_nlist_cell<double><<<blocks, kBlock, 0, st>>>(g, n, xs, cstart, ncnt, nl, (double *)nlr2, gate);
 }
 
-void launch_density(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g,
-                    Soa3c xs, const int *cstart, const int *ncnt, const int *nl, void *rho)
+void launch_density(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g, Soa3c xs,
+                    const int *cstart, const int *ncnt, const uint32_t *nl, const void *nlr2, void *rho)
 {
     if (n <= 0) return;
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
         if (fp32)
             k_density<L, float><<<blocks_for((int64_t)n * L), kBlock, 0, st>>>(
-                pc, g, n, xs, cstart, ncnt, nl, (float *)rho);
+                pc, g, n, xs, cstart, ncnt, nl, (const float *)nlr2, (float *)rho);
         else
             k_density<L, double><<<blocks_for((int64_t)n * L), kBlock, 0, st>>>(
-                pc, g, n, xs, cstart, ncnt, nl, (double *)rho);
+                pc, g, n, xs, cstart, ncnt, nl, (const double *)nlr2, (double *)rho);
     });
 }
 
 void launch_phi(hipStream_t st, int lanes, int n, const PairConst &pc, Geom g, Soa3c xs, Soa3c xprev,
                 Soa3 xfix, Soa3 vfix, const uint32_t *tag, const int *cstart, const int *ncnt,
-                const int *nl, int *flag_and_count, unsigned long long *ncorr_total)
+                const uint32_t *nl, int *flag_and_count, unsigned long long *ncorr_total)
 {
     if (n <= 0) return;
     int *ncorr = flag_and_count;       // [0]: corrections this step
     int *flag = flag_and_count + 1;    // [1..n]: per-slot flags
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
-        k_phi<L><<<blocks_for((int64_t)n * L), kBlock, 0, st>>>(pc, g, n, xs, tag, cstart, ncnt, nl,
-                                                                flag);
+        k_phi<L><<<blocks_for((int64_t)n * L), kBlock, 0, st>>>(pc, g, n, xs, tag, cstart, ncnt, nl, flag);
     });
     k_correct<<<blocks_for(n), kBlock, 0, st>>>(n, flag, xprev, xfix, vfix, ncorr, ncorr_total);
 }
 
 void launch_force(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g, Soa3c xs,
-                  Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ,
-                  const int *cstart, const int *ncnt, const int *nl, Soa3 vout, Soa3 fout,
-                  Soa3 vpred, Soa3 xpred, double *part, int *status, int initial)
+                  Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ, const int *cstart,
+                  const int *ncnt, const uint32_t *nl, Soa3 vout, Soa3 fout, Soa3 vpred, Soa3 xpred,
+                  double *part, int *status, int initial)
 {
     if (n <= 0) return;
     const bool mt = pc.ntypes > 1;
@@ -525,9 +750,9 @@ void launch_force(hipStream_t st, int lanes, bool fp32, int n, const PairConst &
     });
 }
 
-void launch_debug_neighbors(hipStream_t st, int n, Geom g, const PairConst &pc, double cutoff2,
-                            Soa3c xs, const uint32_t *tag, const int *cstart, const int *ncnt,
-                            const int *nl, int64_t *count, uint64_t *hash)
+void launch_debug_neighbors(hipStream_t st, int n, Geom g, const PairConst &pc, double cutoff2, Soa3c xs,
+                            const uint32_t *tag, const int *cstart, const int *ncnt, const uint32_t *nl,
+                            int64_t *count, uint64_t *hash)
 {
     if (n <= 0) return;
     k_debug_neighbors<<<blocks_for(n), kBlock, 0, st>>>(pc, g, n, cutoff2, xs, tag, cstart, ncnt, nl,

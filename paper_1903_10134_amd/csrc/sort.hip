@@ -25,19 +25,42 @@ constexpr int kScanTile = kScanThreads * kScanPer;
 
 inline int blocks_for(int64_t threads) { return (int)((threads + kBlock - 1) / kBlock); }
 
+// Cell key and arrival slot.  Particles arrive almost in cell order (they
+// were sorted one step ago), so lanes whose key equals the previous lane's
+// form runs; the first lane of a run reserves the whole run with one atomic
+// and the others take consecutive slots after it.
 __global__ __launch_bounds__(kBlock) void k_bin(int n, Geom g, Soa3c x, int *__restrict__ key,
                                                 int *__restrict__ slot, int *__restrict__ counts,
                                                 const int *__restrict__ gate)
 {
     if (gate && *gate == 0) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int cx = cell_coord(x.x[i], g.s[0], g.nc[0]);
-    const int cy = cell_coord(x.y[i], g.s[1], g.nc[1]);
-    const int cz = cell_coord(x.z[i], g.s[2], g.nc[2]);
-    const int c = cx + g.nc[0] * (cy + g.nc[1] * cz);
-    key[i] = c;
-    slot[i] = atomicAdd(&counts[c], 1);
+    const int lane = threadIdx.x & 63;
+    int c = -1;
+    if (i < n) {
+        const int cx = cell_coord(x.x[i], g.s[0], g.nc[0]);
+        const int cy = cell_coord(x.y[i], g.s[1], g.nc[1]);
+        const int cz = cell_coord(x.z[i], g.s[2], g.nc[2]);
+        c = cx + g.nc[0] * (cy + g.nc[1] * cz);
+        key[i] = c;
+    }
+    const int prev = __shfl_up(c, 1, 64);
+    const bool head = i < n && (lane == 0 || prev != c);
+    const unsigned long long heads = __ballot(head);
+    // first lane of my run, and the first lane of the next run (or 64)
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int first = 63 - __clzll(heads & upto);
+    const unsigned long long after = heads & ~upto;
+    const int next = after ? __ffsll((long long)after) - 1 : 64;
+    int base = 0;
+    if (head) {
+        int len = next - lane;
+        const int last_valid = n - 1 - (i - lane);  // lanes beyond n are not in any run
+        if (lane + len - 1 > last_valid) len = last_valid - lane + 1;
+        base = atomicAdd(&counts[c], len);
+    }
+    base = __shfl(base, first, 64);
+    if (i < n) slot[i] = base + (lane - first);
 }
 
 // Inclusive scan across one block of kScanThreads threads; returns the
