@@ -90,6 +90,9 @@ def lib():
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_current_step.argtypes = [ctypes.c_void_p]
         L.orc_current_step.restype = ctypes.c_uint32
+        L.orc_tangent.argtypes = [P(Params), i64, P(d), P(d), P(i32), P(u8), P(d), P(d), P(d), P(d), P(d),
+                                  i64, P(d), ctypes.c_int, P(d)]
+        L.orc_tangent.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -260,3 +263,56 @@ class System:
         if h:
             lib().orc_destroy(h)
             self._h = None
+
+
+def _opt(a, shape):
+    if a is None:
+        return None
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape))
+
+
+def tangent(p: Params, x0, v0, types, frozen, nsteps, w, avg=False, dx0=None, dv0=None, dA=None, dB=None,
+            dgamma=None):
+    """Loss L and its derivative dL along the direction (dx0, dv0, dA, dB,
+    dgamma) by forward-mode differentiation of the trajectory (walls off).
+    L = w0 mean_fluid(rho) + w1 P + w2 mean_fluid(v_x) of the final state,
+    or its mean over steps 1..nsteps when avg."""
+    x0 = _c3(x0)
+    v0 = _c3(v0)
+    n = x0.shape[0]
+    T = p.ntypes
+    t = np.ascontiguousarray(np.asarray(types, np.int32))
+    fz = np.ascontiguousarray(np.asarray(frozen, np.uint8))
+    d = ctypes.c_double
+    arrs = [_opt(dx0, (n, 3)), _opt(dv0, (n, 3))] + [_opt(q, (T * T,)) for q in (dA, dB, dgamma)]
+    ptrs = [None if a is None else _ptr(a, d) for a in arrs]
+    wv = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    out = np.zeros(2)
+    rc = lib().orc_tangent(ctypes.byref(p), n, _ptr(x0, d), _ptr(v0, d), _ptr(t, ctypes.c_int32),
+                           _ptr(fz, ctypes.c_uint8), *ptrs, int(nsteps), _ptr(wv, d), 1 if avg else 0,
+                           _ptr(out, d))
+    if rc != 0:
+        raise ValueError("orc_tangent: walls must be off and nsteps >= 1 with avg")
+    return float(out[0]), float(out[1])
+
+
+def loss(p: Params, x0, v0, types, frozen, nsteps, w, avg=False):
+    """The same loss from plain orc_step runs and orc_observables (no
+    derivative code involved): the finite-difference reference."""
+    s = System(p, x0, v0, types, frozen)
+
+    def one():
+        o = s.observables()
+        st = s.state()
+        fl = np.asarray(frozen, bool) == 0
+        nf = max(int(fl.sum()), 1)
+        return w[0] * o["mean_rho"] + w[1] * o["pressure"] + w[2] * st["v"][fl, 0].sum() / nf
+
+    if not avg:
+        s.step(nsteps)
+        return one()
+    acc = 0.0
+    for _ in range(nsteps):
+        s.step(1)
+        acc += one()
+    return acc / nsteps

@@ -664,3 +664,235 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Forward-mode derivative (tangent) of a scalar loss of the trajectory.    */
+/*                                                                          */
+/* The state is advanced exactly as orc_step does (walls off: the corrector */
+/* is a discrete event with no derivative), and next to every quantity q    */
+/* its tangent dq, the derivative along one direction in the inputs: the    */
+/* initial positions and velocities (dx0, dv0, n x 3) and the pair tables   */
+/* (dA, dB, dgamma, ntypes^2; dsigma = kT dgamma / sigma).  Any of them may */
+/* be NULL (zero tangent).  The noise theta_ij depends only on (seed, step, */
+/* ids), so it has no tangent; the wrap into [0, L) has derivative one.     */
+/*                                                                          */
+/* Loss of one state: l = w[0] mean_fluid(rho) + w[1] P + w[2] mean_fluid(  */
+/* v_x), with P the virial pressure of orc_observables.  avg = 0: L is l of */
+/* the state after nsteps; avg = 1: L is the mean of l over the states      */
+/* after steps 1..nsteps (nsteps >= 1).  out[0] = L, out[1] = dL.           */
+/* parity pinned against central finite differences of orc_step and        */
+/* exact invariances (uniform translation, Galilean boost).                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const orc_params *p;
+    int64_t n;
+    const int32_t *type;
+    const uint8_t *frozen;
+    const double *dA, *dB, *dg;
+} orc_tan_ctx;
+
+/* rho and its tangent at positions x with tangent dx. */
+static void orc_tan_density(const orc_tan_ctx *c, const double *x, const double *dx, const orc_nlist *nl,
+                            double *rho, double *drho)
+{
+    const orc_params *p = c->p;
+    const double rd = p->rd, rd2 = rd * rd, norm = 15.0 / (2.0 * M_PI * rd * rd * rd);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < c->n; ++i) {
+        double s = 0.0, ds = 0.0;
+        for (int32_t k = 0; k < nl->cnt[i]; ++k) {
+            int64_t j = nl->idx[i][k];
+            double d[3];
+            orc_delta(x, i, j, p->L, d);
+            double r2 = orc_r2(d);
+            if (!(r2 < rd2)) continue;
+            double r = sqrt(r2);
+            double q = 1.0 - r / rd;
+            s += norm * q * q;
+            if (r2 == 0.0) continue;
+            double dr = 0.0;
+            for (int a = 0; a < 3; ++a) dr += d[a] / r * (dx[3 * i + a] - dx[3 * j + a]);
+            ds += norm * 2.0 * q * (-dr / rd);
+        }
+        rho[i] = s;
+        drho[i] = ds;
+    }
+}
+
+/* Forces and their tangent (fluid particles; frozen get 0), the virial and
+ * its tangent. */
+static void orc_tan_forces(const orc_tan_ctx *c, const double *x, const double *dx, const double *vh,
+                           const double *dvh, const double *rho, const double *drho, uint32_t step,
+                           const orc_nlist *nl, double *F, double *dF, double *vir_out, double *dvir_out)
+{
+    const orc_params *p = c->p;
+    const int T = p->ntypes;
+    const double rc = p->rc, rd = p->rd, rd2 = rd * rd, sdt = sqrt(p->dt);
+    double vir = 0.0, dvir = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : vir, dvir)
+    for (int64_t i = 0; i < c->n; ++i) {
+        double f[3] = {0, 0, 0}, df[3] = {0, 0, 0};
+        if (!c->frozen[i]) {
+            for (int32_t k = 0; k < nl->cnt[i]; ++k) {
+                int64_t j = nl->idx[i][k];
+                double d[3], dd[3];
+                orc_delta(x, i, j, p->L, d);
+                double r2 = orc_r2(d);
+                if (r2 == 0.0) continue;
+                double r = sqrt(r2);
+                double e[3], de[3], dr = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    dd[a] = dx[3 * i + a] - dx[3 * j + a];
+                    e[a] = d[a] / r;
+                    dr += e[a] * dd[a];
+                }
+                for (int a = 0; a < 3; ++a) de[a] = (dd[a] - e[a] * dr) / r;
+                int tt = c->type[i] * T + c->type[j];
+                double A = p->A[tt], B = p->B[tt], gam = p->gamma[tt];
+                double dA = c->dA ? c->dA[tt] : 0.0, dB = c->dB ? c->dB[tt] : 0.0;
+                double dgam = c->dg ? c->dg[tt] : 0.0;
+                double wc = 1.0 - r / rc, dwc = -dr / rc;
+                /* conservative */
+                double fc = A * wc, dfc = dA * wc + A * dwc;
+                if (r2 < rd2) {
+                    double wd = 1.0 - r / rd, dwd = -dr / rd;
+                    double rs = rho[i] + rho[j], drs = drho[i] + drho[j];
+                    fc += B * rs * wd;
+                    dfc += dB * rs * wd + B * drs * wd + B * rs * dwd;
+                }
+                /* dissipative with the half-step velocities (frozen: v = 0) */
+                double vij[3], dvij[3], ev = 0.0, dev = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    double vj = c->frozen[j] ? 0.0 : vh[3 * j + a];
+                    double dvj = c->frozen[j] ? 0.0 : dvh[3 * j + a];
+                    vij[a] = vh[3 * i + a] - vj;
+                    dvij[a] = dvh[3 * i + a] - dvj;
+                    ev += e[a] * vij[a];
+                    dev += de[a] * vij[a] + e[a] * dvij[a];
+                }
+                double fd = -gam * wc * wc * ev;
+                double dfd = -dgam * wc * wc * ev - gam * 2.0 * wc * dwc * ev - gam * wc * wc * dev;
+                /* random */
+                double sigma = sqrt(2.0 * gam * p->kT);
+                double dsigma = sigma > 0.0 ? p->kT * dgam / sigma : 0.0;
+                double th = orc_theta(p->seed, step, (uint32_t)i, (uint32_t)j) / sdt;
+                double fr = sigma * wc * th, dfr = (dsigma * wc + sigma * dwc) * th;
+                double fs = fc + fd + fr, dfs = dfc + dfd + dfr;
+                for (int a = 0; a < 3; ++a) {
+                    f[a] += fs * e[a];
+                    df[a] += dfs * e[a] + fs * de[a];
+                }
+                double cw = c->frozen[j] ? 1.0 : 0.5;
+                vir += cw * r * fc;
+                dvir += cw * (dr * fc + r * dfc);
+            }
+            for (int a = 0; a < 3; ++a) f[a] += p->mass * p->g[a];
+        }
+        for (int a = 0; a < 3; ++a) {
+            F[3 * i + a] = f[a];
+            dF[3 * i + a] = df[a];
+        }
+    }
+    *vir_out = vir;
+    *dvir_out = dvir;
+}
+
+/* l and dl of one state (see above). */
+static void orc_tan_loss(const orc_tan_ctx *c, const double *v, const double *dv, const double *rho,
+                         const double *drho, double vir, double dvir, const double w[3], double *l,
+                         double *dl)
+{
+    const orc_params *p = c->p;
+    double nf = 0.0, sr = 0.0, dsr = 0.0, k2 = 0.0, dk2 = 0.0, svx = 0.0, dsvx = 0.0;
+    for (int64_t i = 0; i < c->n; ++i) {
+        if (c->frozen[i]) continue;
+        nf += 1.0;
+        sr += rho[i];
+        dsr += drho[i];
+        for (int a = 0; a < 3; ++a) {
+            k2 += p->mass * v[3 * i + a] * v[3 * i + a];
+            dk2 += 2.0 * p->mass * v[3 * i + a] * dv[3 * i + a];
+        }
+        svx += v[3 * i];
+        dsvx += dv[3 * i];
+    }
+    const double V3 = 3.0 * p->L[0] * p->L[1] * p->L[2];
+    const double inf = nf > 0.0 ? 1.0 / nf : 0.0;
+    *l = w[0] * sr * inf + w[1] * (k2 + vir) / V3 + w[2] * svx * inf;
+    *dl = w[0] * dsr * inf + w[1] * (dk2 + dvir) / V3 + w[2] * dsvx * inf;
+}
+
+int orc_tangent(const orc_params *p, int64_t n, const double *x0, const double *v0, const int32_t *type,
+                const uint8_t *frozen, const double *dx0, const double *dv0, const double *dA,
+                const double *dB, const double *dgamma, int64_t nsteps, const double w[3], int avg,
+                double out[2])
+{
+    if (p->wall_model != 0 || nsteps < 0 || (avg && nsteps < 1)) return -1;
+    orc_tan_ctx c = {p, n, type, frozen, dA, dB, dgamma};
+    size_t nn = (size_t)(n ? n : 1);
+    double *x = (double *)malloc(nn * 3 * sizeof(double)), *dx = (double *)malloc(nn * 3 * sizeof(double));
+    double *v = (double *)malloc(nn * 3 * sizeof(double)), *dv = (double *)malloc(nn * 3 * sizeof(double));
+    double *vh = (double *)malloc(nn * 3 * sizeof(double)), *dvh = (double *)malloc(nn * 3 * sizeof(double));
+    double *F = (double *)malloc(nn * 3 * sizeof(double)), *dF = (double *)malloc(nn * 3 * sizeof(double));
+    double *rho = (double *)malloc(nn * sizeof(double)), *drho = (double *)malloc(nn * sizeof(double));
+    const double hdtm = 0.5 * p->dt / p->mass;
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            int k = 3 * (int)i + a;
+            x[k] = orc_wrap(x0[k], p->L[a]);
+            dx[k] = dx0 ? dx0[k] : 0.0;
+            v[k] = frozen[i] ? 0.0 : v0[k];
+            dv[k] = (frozen[i] || !dv0) ? 0.0 : dv0[k];
+            vh[k] = v[k];
+            dvh[k] = dv[k];
+        }
+    double vir = 0.0, dvir = 0.0, L = 0.0, dL = 0.0, l, dl;
+    orc_nlist nl;
+    orc_build(x, n, p->L, p->rc, p->search, &nl);
+    orc_tan_density(&c, x, dx, &nl, rho, drho);
+    orc_tan_forces(&c, x, dx, vh, dvh, rho, drho, 0, &nl, F, dF, &vir, &dvir);
+    orc_nlist_free(&nl);
+    for (int64_t s = 1; s <= nsteps; ++s) {
+        for (int64_t i = 0; i < n; ++i) {
+            if (frozen[i]) continue;
+            for (int a = 0; a < 3; ++a) {
+                int k = 3 * (int)i + a;
+                vh[k] = v[k] + hdtm * F[k];
+                dvh[k] = dv[k] + hdtm * dF[k];
+                x[k] = orc_wrap(x[k] + p->dt * vh[k], p->L[a]);
+                dx[k] = dx[k] + p->dt * dvh[k];
+            }
+        }
+        orc_build(x, n, p->L, p->rc, p->search, &nl);
+        orc_tan_density(&c, x, dx, &nl, rho, drho);
+        orc_tan_forces(&c, x, dx, vh, dvh, rho, drho, (uint32_t)s, &nl, F, dF, &vir, &dvir);
+        orc_nlist_free(&nl);
+        for (int64_t i = 0; i < n; ++i) {
+            if (frozen[i]) continue;
+            for (int a = 0; a < 3; ++a) {
+                int k = 3 * (int)i + a;
+                v[k] = vh[k] + hdtm * F[k];
+                dv[k] = dvh[k] + hdtm * dF[k];
+            }
+        }
+        if (avg) {
+            orc_tan_loss(&c, v, dv, rho, drho, vir, dvir, w, &l, &dl);
+            L += l / (double)nsteps;
+            dL += dl / (double)nsteps;
+        }
+    }
+    if (!avg) orc_tan_loss(&c, v, dv, rho, drho, vir, dvir, w, &L, &dL);
+    out[0] = L;
+    out[1] = dL;
+    free(x);
+    free(dx);
+    free(v);
+    free(dv);
+    free(vh);
+    free(dvh);
+    free(F);
+    free(dF);
+    free(rho);
+    free(drho);
+    return 0;
+}
