@@ -85,7 +85,7 @@ def run_form(mdpd, w, precision, steps, warmup, stream, lanes):
     s.step(warmup)
     torch.cuda.synchronize()
     mdpd.mdpd_set_kernel_timing(s.h, True)
-    for k in range(5):
+    for k in range(len(mdpd.KERNELS)):
         mdpd.mdpd_read_kernel_timing(s.h, k)  # reset
     t0 = time.perf_counter()
     s.step(steps)

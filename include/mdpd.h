@@ -113,7 +113,7 @@ typedef struct mdpd_system mdpd_system; /* opaque; owned by the library */
  * velocities and noise step 0.
  *   p       parameters, copied.  box >= 3 r_c per axis, 0 < rd <= rc, dt > 0,
  *           mass > 0, kT >= 0, symmetric tables with B, gamma >= 0.
- *   n       number of particles, 0 <= n < 2^31 (n = 0 gives an empty system)
+ *   n       number of particles, 0 <= n < 2^30 (n = 0 gives an empty system)
  *   pos     n x 3 positions, each coordinate in [-L, 2L); wrapped into [0, L)
  *   vel     n x 3 velocities (ignored for frozen particles, which get 0)
  *   type    n type indices in [0, ntypes)
@@ -162,7 +162,8 @@ mdpd_status mdpd_debug_forces(mdpd_system *s, double *force);
  * an event pair around every launch of each timed kernel from then on;
  * mdpd_read_kernel_timing returns the summed duration in milliseconds and
  * the number of launches of kernel class k (0: sort, 1: neighbour list,
- * 2: density, 3: force, 4: wall) and resets the counters. */
+ * 2: density, 3: force, 4: wall, 5: adjoint pair passes) and resets the
+ * counters. */
 mdpd_status mdpd_set_kernel_timing(mdpd_system *s, int32_t enable);
 mdpd_status mdpd_read_kernel_timing(mdpd_system *s, int32_t kernel, double *total_ms,
                                     int64_t *launches);
@@ -172,6 +173,61 @@ mdpd_status mdpd_read_kernel_timing(mdpd_system *s, int32_t kernel, double *tota
  * and wall fraction) or 2 (force).  Results do not depend on pass 0's
  * setting; passes 1 and 2 change only the summation order. */
 mdpd_status mdpd_set_lanes(mdpd_system *s, int32_t pass, int32_t lanes);
+
+/* Checkpoint and bitwise resume.  A checkpoint holds the complete dynamical
+ * state after the last completed step (positions, velocities, forces, the
+ * predicted next half-step, densities, ids and types in the internal order,
+ * the cell list, the step counter and the wall-correction counters) and a
+ * copy of the parameters.  Loading it into a system created with the same
+ * parameters and the same n makes every later call return what the saved
+ * system would have returned, bit for bit: the noise is keyed on (seed,
+ * step, ids) and the internal order and summation orders are functions of
+ * the state alone.
+ *   mdpd_checkpoint_size   bytes needed for a checkpoint of s
+ *   mdpd_save_checkpoint   writes it to buf (bytes >= that size), host or
+ *                          device memory per mem_kind
+ *   mdpd_load_checkpoint   replaces the state of s with the checkpoint in buf
+ * Errors: MDPD_E_INVALID (NULL, buffer too small, not a checkpoint, or saved
+ * with other parameters or another n), MDPD_E_HIP. */
+mdpd_status mdpd_checkpoint_size(const mdpd_system *s, uint64_t *bytes);
+mdpd_status mdpd_save_checkpoint(mdpd_system *s, void *buf, uint64_t bytes, int32_t mem_kind);
+mdpd_status mdpd_load_checkpoint(mdpd_system *s, const void *buf, uint64_t bytes, int32_t mem_kind);
+
+/* Adjoint: gradients of trajectory losses by reverse-mode differentiation
+ * of the timestep (Eq. 1 forces, the density of Sec. 2.1 and the
+ * velocity-Verlet order of Alg. 1).  The pair noise depends on (seed, step,
+ * ids) only and is held fixed.  Walls must be off (MDPD_E_UNSUPPORTED
+ * otherwise: the corrector is a discrete event), and the recording starts
+ * from the state given to mdpd_create (MDPD_E_STATE after mdpd_step).
+ *
+ * mdpd_forward_record advances nsteps >= 0 steps from step 0, keeping a
+ * device checkpoint every `every` >= 1 steps, and returns in loss[3]
+ *   loss[0] = mean many-body density of fluid particles,
+ *   loss[1] = virial pressure (as in mdpd_observables),
+ *   loss[2] = mean x-velocity of fluid particles,
+ * of the final state (average = 0) or averaged over the states after steps
+ * 1..nsteps (average = 1, nsteps >= 1).  Afterwards the system stands at
+ * step nsteps.
+ *
+ * mdpd_backward returns the gradient of L = w[0] loss[0] + w[1] loss[1] +
+ * w[2] loss[2] of the last recording with respect to
+ *   dA, dB, dgamma  the pair tables, ntypes x ntypes, host; the derivative of
+ *                   L along a symmetric change D of a table is
+ *                   sum_ab d[ab] D[ab] (at gamma = 0 the noise amplitude
+ *                   sqrt(2 gamma kT) has no derivative and is left out)
+ *   dx0, dv0        the positions and velocities given to mdpd_create, n x 3
+ *                   in id order, host or device per mem_kind (dv0 of frozen
+ *                   particles is 0)
+ * Any output may be NULL.  Each segment of `every` steps is recomputed from
+ * its checkpoint, so the call costs about one forward pass plus the adjoint
+ * passes; memory is one checkpoint (about 170 bytes per particle) per
+ * segment plus every + 1 stored states (about 90 bytes per particle each).
+ * The result is deterministic, and the system is left at the end of the
+ * recording. */
+mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, int32_t average,
+                                double *loss);
+mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *dB, double *dgamma,
+                          double *dx0, double *dv0, int32_t mem_kind);
 
 /* Release the system and its device memory.  NULL is ignored. */
 void mdpd_destroy(mdpd_system *s);

@@ -7,13 +7,17 @@ the seeded synthetic workloads (``workloads``).  The native library is loaded
 on first use and its absence is an error: there is no CPU fallback.
 """
 from ._native import (FP32_FORCES, FP64, KERNELS, MEM_DEVICE, MEM_HOST, WALL_BVF, WALL_OFF,
-                      MdpdError, Params, System, lib, make_params, mdpd_create, mdpd_debug_forces,
-                      mdpd_debug_neighbors, mdpd_destroy, mdpd_get_state, mdpd_last_error,
-                      mdpd_read_kernel_timing, mdpd_read_observables, mdpd_read_profile,
+                      MdpdError, Params, System, lib, make_params, mdpd_backward, mdpd_checkpoint_size, mdpd_create,
+                      mdpd_debug_forces, mdpd_debug_neighbors, mdpd_destroy, mdpd_forward_record,
+                      mdpd_get_state,
+                      mdpd_last_error, mdpd_load_checkpoint, mdpd_read_kernel_timing,
+                      mdpd_read_observables, mdpd_read_profile, mdpd_save_checkpoint,
                       mdpd_set_kernel_timing, mdpd_set_lanes, mdpd_step)
 
 __all__ = ["FP32_FORCES", "FP64", "KERNELS", "MEM_DEVICE", "MEM_HOST", "WALL_BVF", "WALL_OFF",
-           "MdpdError", "Params", "System", "lib", "make_params", "mdpd_create", "mdpd_debug_forces",
-           "mdpd_debug_neighbors", "mdpd_destroy", "mdpd_get_state", "mdpd_last_error",
-           "mdpd_read_kernel_timing", "mdpd_read_observables", "mdpd_read_profile",
+           "MdpdError", "Params", "System", "lib", "make_params", "mdpd_backward", "mdpd_checkpoint_size", "mdpd_create",
+           "mdpd_debug_forces", "mdpd_debug_neighbors", "mdpd_destroy", "mdpd_forward_record",
+           "mdpd_get_state",
+           "mdpd_last_error", "mdpd_load_checkpoint", "mdpd_read_kernel_timing",
+           "mdpd_read_observables", "mdpd_read_profile", "mdpd_save_checkpoint",
            "mdpd_set_kernel_timing", "mdpd_set_lanes", "mdpd_step"]

@@ -21,7 +21,7 @@ FP64, FP32_FORCES = 0, 1
 WALL_OFF, WALL_BVF = 0, 1
 STATUS = {0: "MDPD_OK", -1: "MDPD_E_INVALID", -2: "MDPD_E_OOM", -3: "MDPD_E_HIP",
           -4: "MDPD_E_NONFINITE", -5: "MDPD_E_STATE", -6: "MDPD_E_UNSUPPORTED"}
-KERNELS = ("sort", "nlist", "density", "force", "wall")
+KERNELS = ("sort", "nlist", "density", "force", "wall", "adjoint")
 
 
 class MdpdError(RuntimeError):
@@ -76,6 +76,15 @@ _SIGS = {
     "mdpd_read_kernel_timing": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "mdpd_set_lanes": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
+    "mdpd_checkpoint_size": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
+    "mdpd_save_checkpoint": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32],
+                             ctypes.c_int32),
+    "mdpd_load_checkpoint": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32],
+                             ctypes.c_int32),
+    "mdpd_forward_record": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                             ctypes.c_void_p], ctypes.c_int32),
+    "mdpd_backward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
     "mdpd_destroy": ([ctypes.c_void_p], None),
     "mdpd_last_error": ([], ctypes.c_char_p),
 }
@@ -239,6 +248,55 @@ def mdpd_set_lanes(h, pass_: int, lanes: int) -> None:
     _check(lib().mdpd_set_lanes(h, int(pass_), int(lanes)))
 
 
+def mdpd_checkpoint_size(h) -> int:
+    b = ctypes.c_uint64()
+    _check(lib().mdpd_checkpoint_size(h, ctypes.byref(b)))
+    return b.value
+
+
+def mdpd_save_checkpoint(h):
+    """Checkpoint of the current state as a host uint8 array."""
+    buf = np.zeros(mdpd_checkpoint_size(h), dtype=np.uint8)
+    _check(lib().mdpd_save_checkpoint(h, buf.ctypes.data, buf.nbytes, MEM_HOST))
+    return buf
+
+
+def mdpd_load_checkpoint(h, buf) -> None:
+    """Replace the state with a checkpoint (host uint8 array or CUDA tensor)."""
+    if _is_torch(buf):
+        _check(lib().mdpd_load_checkpoint(h, buf.data_ptr(), buf.numel() * buf.element_size(),
+                                          MEM_DEVICE if buf.is_cuda else MEM_HOST))
+        return
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    _check(lib().mdpd_load_checkpoint(h, buf.ctypes.data, buf.nbytes, MEM_HOST))
+
+
+def mdpd_forward_record(h, nsteps: int, every: int = 10, average: bool = False):
+    """Record a trajectory of nsteps from step 0; returns the loss terms
+    (mean fluid density, virial pressure, mean fluid x-velocity)."""
+    out = np.zeros(3)
+    _check(lib().mdpd_forward_record(h, int(nsteps), int(every), 1 if average else 0, out.ctypes.data))
+    return out
+
+
+def mdpd_backward(h, w, ntypes: int, n: int, device=None):
+    """Gradient of w . loss of the last recording: dict of dA, dB, dgamma
+    (ntypes x ntypes) and dx0, dv0 (n x 3, id order; CUDA tensors when
+    device is given)."""
+    wv = np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(3))
+    tabs = [np.zeros((ntypes, ntypes)) for _ in range(3)]
+    if device is not None:
+        import torch
+        dx = torch.empty((n, 3), dtype=torch.float64, device=device)
+        dv = torch.empty((n, 3), dtype=torch.float64, device=device)
+        ptrs, kind = (dx.data_ptr(), dv.data_ptr()), MEM_DEVICE
+    else:
+        dx, dv = np.zeros((n, 3)), np.zeros((n, 3))
+        ptrs, kind = (dx.ctypes.data, dv.ctypes.data), MEM_HOST
+    _check(lib().mdpd_backward(h, wv.ctypes.data, *[t.ctypes.data for t in tabs], *ptrs, kind))
+    return {"dA": tabs[0], "dB": tabs[1], "dgamma": tabs[2], "dx0": dx, "dv0": dv}
+
+
 def mdpd_destroy(h) -> None:
     if h:
         lib().mdpd_destroy(h)
@@ -288,6 +346,18 @@ class System:
 
     def set_lanes(self, pass_, lanes):
         mdpd_set_lanes(self.h, pass_, lanes)
+
+    def forward_record(self, nsteps, every=10, average=False):
+        return mdpd_forward_record(self.h, nsteps, every, average)
+
+    def backward(self, w, device=None):
+        return mdpd_backward(self.h, w, self.params.ntypes, self.n, device=device)
+
+    def save_checkpoint(self):
+        return mdpd_save_checkpoint(self.h)
+
+    def load_checkpoint(self, buf):
+        mdpd_load_checkpoint(self.h, buf)
 
     def close(self):
         if self.h:

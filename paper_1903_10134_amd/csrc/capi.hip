@@ -35,7 +35,7 @@ mdpd_status fail(mdpd_status st, const char *fmt, ...)
             return fail(MDPD_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));         \
     } while (0)
 
-constexpr int kTimedKernels = 5;  // sort, neighbour list, density, force, wall
+constexpr int kTimedKernels = 6;  // sort, neighbour list, density, force, wall, adjoint pair passes
 
 struct EventPool {
     std::vector<hipEvent_t> ev;
@@ -43,6 +43,28 @@ struct EventPool {
 };
 
 }  // namespace
+
+namespace mdpd {
+// Recorded trajectory for the adjoint: device checkpoints every `every`
+// steps, a tape of up to every + 1 states for the recomputed segment, and
+// the adjoint work arrays.
+struct AdjRec {
+    bool ready = false;
+    int64_t nsteps = 0;
+    int every = 1;
+    int avg = 0;
+    int64_t nfluid = 0;
+    char *ck = nullptr;  // nck checkpoints of ck_bytes each
+    uint64_t ck_bytes = 0;
+    int nck = 0;
+    std::vector<int> ck_nfpart;
+    char *tape = nullptr;  // ntape entries of tape_bytes each
+    uint64_t tape_bytes = 0;
+    int ntape = 0;
+    Soa3 X{}, U{}, fb{}, Xid{}, Uid{};
+    double *rhoA = nullptr, *gp = nullptr, *gpart = nullptr, *gtot = nullptr, *loss = nullptr;
+};
+}  // namespace mdpd
 
 struct mdpd_system {
     mdpd_params p{};
@@ -69,6 +91,8 @@ struct mdpd_system {
     int nfpart = 0;       // capacity of fpart in blocks
     int nfpart_used = 0;  // blocks written by the last force launch
     int *status = nullptr;
+    int *ovf = nullptr;        // [0]: overflow count, [1..n]: queued slots
+    double *ovf_ve = nullptr;  // per slot: virial, pair energy of overflowed particles
     int *corr = nullptr;  // [0]: corrections this step, [1..n]: flags
     unsigned long long *ncorr_total = nullptr;
     double *tab = nullptr;
@@ -80,12 +104,25 @@ struct mdpd_system {
     bool timing = false;
     EventPool pool[kTimedKernels];
     std::vector<void *> allocs;
+    AdjRec adj;
 
     ~mdpd_system()
     {
         for (auto &pl : pool)
             for (auto e : pl.ev) (void)hipEventDestroy(e);
         for (void *a : allocs) (void)hipFree(a);
+    }
+
+    // Free one allocation made by alloc() (NULL is ignored).
+    void release(void *ptr)
+    {
+        if (!ptr) return;
+        for (size_t k = 0; k < allocs.size(); ++k)
+            if (allocs[k] == ptr) {
+                (void)hipFree(ptr);
+                allocs.erase(allocs.begin() + (long)k);
+                return;
+            }
     }
 
     template <typename T>
@@ -158,7 +195,7 @@ struct mdpd_system {
         tic(0);
         launch_sort(st, n, g, cview(xpred), cview(vpred), walls ? cview(xs[cur]) : Soa3c{nullptr, nullptr, nullptr},
                     tag[cur], typ[cur], xs[o], vh[o], xprev, tag[o], typ[o], key, slot, tmpid, counts,
-                    cstart, bsum, nullptr);
+                    cstart, bsum, nullptr, ovf);
         toc(0);
         cur = o;
     }
@@ -180,7 +217,7 @@ struct mdpd_system {
             tic(0);
             launch_sort(st, n, g, cview(xs[cur]), cview(vh[cur]), Soa3c{nullptr, nullptr, nullptr}, tag[cur],
                         typ[cur], xs[o], vh[o], Soa3{nullptr, nullptr, nullptr}, tag[o], typ[o], key, slot,
-                        tmpid, counts, cstart, bsum, corr);
+                        tmpid, counts, cstart, bsum, corr, nullptr);
             toc(0);
             cur = o;
             tic(1);
@@ -190,10 +227,10 @@ struct mdpd_system {
         tic(2);
         launch_density(st, lanes[1], fp32, n, pc, g, cview(xs[cur]), cstart, ncnt, nl, nlr2, rho);
         toc(2);
-        nfpart_used = n > 0 ? force_blocks(lanes[2], n) : 0;
+        nfpart_used = n > 0 ? force_partials(lanes[2], n) : 0;
         tic(3);
         launch_force(st, lanes[2], fp32, n, pc, g, cview(xs[cur]), cview(vh[cur]), rho, tag[cur], typ[cur],
-                     cstart, ncnt, nl, v, F, vpred, xpred, fpart, status, initial);
+                     cstart, ncnt, nl, v, F, vpred, xpred, fpart, status, ovf, ovf + 1, ovf_ve, initial);
         toc(3);
     }
 };
@@ -205,7 +242,7 @@ bool finite(double x) { return isfinite(x) != 0; }
 mdpd_status validate(const mdpd_params *p, int64_t n)
 {
     if (!p) return fail(MDPD_E_INVALID, "params is NULL");
-    if (n < 0 || n >= (int64_t)1 << 31) return fail(MDPD_E_INVALID, "n = %lld out of range", (long long)n);
+    if (n < 0 || n >= (int64_t)1 << 30) return fail(MDPD_E_INVALID, "n = %lld out of range", (long long)n);
     if (p->ntypes < 1 || p->ntypes > MDPD_MAX_TYPES)
         return fail(MDPD_E_INVALID, "ntypes = %d not in 1..%d", p->ntypes, MDPD_MAX_TYPES);
     const double sc[] = {p->rc, p->rd, p->kT, p->dt, p->mass, p->phi_c, p->box[0], p->box[1], p->box[2],
@@ -330,7 +367,7 @@ mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, cons
 
     const size_t N = (size_t)(n > 0 ? n : 1);
     const int nb_scan = (g.ncells + 4095) / 4096;
-    s->nfpart = force_blocks(16, (int)N);
+    s->nfpart = force_partials(16, (int)N);
 #define ALLOC(call)                 \
     do {                            \
         mdpd_status e_ = (call);    \
@@ -371,9 +408,11 @@ mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, cons
     ALLOC(s->alloc(&s->fpart, 2 * (size_t)s->nfpart));
     ALLOC(s->alloc(&s->status, 4));
     ALLOC(s->alloc(&s->corr, N + 1));
+    ALLOC(s->alloc(&s->ovf, N + 1));
+    ALLOC(s->alloc(&s->ovf_ve, 2 * N));
     ALLOC(s->alloc(&s->ncorr_total, 1));
     ALLOC(s->alloc(&s->tab, 320));
-    ALLOC(s->alloc(&s->obs, 16 + 1024 * 8));
+    ALLOC(s->alloc(&s->obs, kObsSlots));
     ALLOC(s->alloc(&s->io, 3 * N));
     ALLOC(s->alloc(&s->io2, 3 * N));
     ALLOC(s->alloc(&s->work, 9 * 4096));
@@ -408,6 +447,7 @@ mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, cons
     launch_zero_int(s->st, (int *)s->ncorr_total, 2);
     launch_zero_int(s->st, s->counts, g.ncells);
     launch_zero_int(s->st, s->corr, (int)N + 1);
+    launch_zero_int(s->st, s->ovf, 1);
 
     // inputs: stage host arrays in device memory
     const double *dpos = pos, *dvel = vel;
@@ -470,7 +510,7 @@ mdpd_status mdpd_read_observables(mdpd_system *s, mdpd_observables *out)
 {
     if (!s || !out) return fail(MDPD_E_INVALID, "NULL argument");
     launch_observables(s->st, s->fp32, s->n, s->pc, cview(s->v), s->rho, s->tag[s->cur], s->typ[s->cur],
-                       s->fpart, s->nfpart_used, s->obs);
+                       s->fpart, s->nfpart_used, s->ncnt, s->ovf_ve, s->obs);
     double h[10];
     unsigned long long tot = 0;
     int last = 0;
@@ -546,6 +586,137 @@ mdpd_status mdpd_get_state(mdpd_system *s, double *pos, double *vel, double *rho
     return MDPD_OK;
 }
 
+}  // extern "C"
+
+// Checkpoint layout: header, parameters, then the arrays in the order of
+// ckpt_fields(); every field starts on a 256-byte boundary.
+namespace {
+
+constexpr uint64_t kCkptMagic = 0x3150544b4350444dull;  // "MDPDCKPT" + version 1
+constexpr uint64_t kCkptAlign = 256;
+
+struct CkptHeader {
+    uint64_t magic;
+    int64_t n;
+    int64_t step;
+    int64_t nfpart_used;
+    int64_t ncells;
+    int64_t reserved[3];
+};
+
+struct CkptField {
+    void *dev;
+    uint64_t bytes;
+};
+
+std::vector<CkptField> ckpt_fields(mdpd_system *s)
+{
+    const uint64_t N = (uint64_t)s->n;
+    const int c = s->cur;
+    const uint64_t rb = s->fp32 ? 4 : 8;
+    return {
+        {s->xs[c].x, 24 * N},          {s->v.x, 24 * N},     {s->F.x, 24 * N},
+        {s->xpred.x, 24 * N},          {s->vpred.x, 24 * N}, {s->rho, rb * N},
+        {s->tag[c], 4 * N},            {s->typ[c], N},       {s->ovf_ve, 16 * N},
+        {s->cstart, 4 * ((uint64_t)s->g.ncells + 1)},        {s->fpart, 16 * (uint64_t)s->nfpart_used},
+        {s->ncorr_total, 8},           {s->corr, 4},
+    };
+}
+
+uint64_t align_up(uint64_t x) { return (x + kCkptAlign - 1) / kCkptAlign * kCkptAlign; }
+
+// Bytes of the state arrays of a checkpoint (without header and parameters).
+uint64_t state_bytes(mdpd_system *s)
+{
+    uint64_t off = 0;
+    for (const CkptField &f : ckpt_fields(s)) off += align_up(f.bytes);
+    return off;
+}
+
+uint64_t ckpt_bytes(mdpd_system *s) { return align_up(sizeof(CkptHeader) + sizeof(mdpd_params)) + state_bytes(s); }
+
+// Enqueue copies of the state arrays to / from dst (kind: the direction).
+hipError_t state_copy(mdpd_system *s, char *buf, bool save, hipMemcpyKind kind)
+{
+    uint64_t off = 0;
+    for (const CkptField &f : ckpt_fields(s)) {
+        if (f.bytes) {
+            hipError_t e = save ? hipMemcpyAsync(buf + off, f.dev, f.bytes, kind, s->st)
+                                : hipMemcpyAsync(f.dev, buf + off, f.bytes, kind, s->st);
+            if (e != hipSuccess) return e;
+        }
+        off += align_up(f.bytes);
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+mdpd_status mdpd_checkpoint_size(const mdpd_system *s, uint64_t *bytes)
+{
+    if (!s || !bytes) return fail(MDPD_E_INVALID, "NULL argument");
+    *bytes = ckpt_bytes(const_cast<mdpd_system *>(s));
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_save_checkpoint(mdpd_system *s, void *buf, uint64_t bytes, int32_t mem_kind)
+{
+    if (!s || !buf) return fail(MDPD_E_INVALID, "NULL argument");
+    if (mem_kind != MDPD_MEM_HOST && mem_kind != MDPD_MEM_DEVICE)
+        return fail(MDPD_E_INVALID, "unknown mem_kind %d", mem_kind);
+    const uint64_t need = ckpt_bytes(s);
+    if (bytes < need) return fail(MDPD_E_INVALID, "checkpoint buffer of %llu bytes, need %llu",
+                                  (unsigned long long)bytes, (unsigned long long)need);
+    const hipMemcpyKind dk = mem_kind == MDPD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    const hipMemcpyKind hk = mem_kind == MDPD_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyHostToDevice;
+    CkptHeader h{};
+    h.magic = kCkptMagic;
+    h.n = s->n;
+    h.step = s->step;
+    h.nfpart_used = s->nfpart_used;
+    h.ncells = s->g.ncells;
+    char *out = (char *)buf;
+    HIPCHK(hipMemcpyAsync(out, &h, sizeof h, hk, s->st));
+    HIPCHK(hipMemcpyAsync(out + sizeof h, &s->p, sizeof s->p, hk, s->st));
+    HIPCHK(state_copy(s, out + align_up(sizeof h + sizeof s->p), true, dk));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_load_checkpoint(mdpd_system *s, const void *buf, uint64_t bytes, int32_t mem_kind)
+{
+    if (!s || !buf) return fail(MDPD_E_INVALID, "NULL argument");
+    if (mem_kind != MDPD_MEM_HOST && mem_kind != MDPD_MEM_DEVICE)
+        return fail(MDPD_E_INVALID, "unknown mem_kind %d", mem_kind);
+    const uint64_t need = ckpt_bytes(s);
+    if (bytes < sizeof(CkptHeader) + sizeof(mdpd_params))
+        return fail(MDPD_E_INVALID, "checkpoint buffer too small");
+    const char *in = (const char *)buf;
+    const hipMemcpyKind hk = mem_kind == MDPD_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
+    const hipMemcpyKind dk = mem_kind == MDPD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    CkptHeader h{};
+    mdpd_params p{};
+    HIPCHK(hipMemcpyAsync(&h, in, sizeof h, hk, s->st));
+    HIPCHK(hipMemcpyAsync(&p, in + sizeof h, sizeof p, hk, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    if (h.magic != kCkptMagic) return fail(MDPD_E_INVALID, "buffer does not hold an mdpd checkpoint");
+    if (h.n != s->n || h.ncells != s->g.ncells || memcmp(&p, &s->p, sizeof p) != 0)
+        return fail(MDPD_E_INVALID, "checkpoint was saved from a system with other parameters or n");
+    if (bytes < need) return fail(MDPD_E_INVALID, "checkpoint buffer of %llu bytes, need %llu",
+                                  (unsigned long long)bytes, (unsigned long long)need);
+    if (h.nfpart_used < 0 || h.nfpart_used > s->nfpart) return fail(MDPD_E_INVALID, "corrupt checkpoint");
+    s->nfpart_used = (int)h.nfpart_used;
+    s->step = h.step;
+    HIPCHK(state_copy(s, const_cast<char *>(in) + align_up(sizeof h + sizeof p), false, dk));
+    // the neighbour list is a function of the positions and the cell list
+    launch_nlist(s->st, s->fp32, s->n, s->g, cview(s->xs[s->cur]), s->cstart, s->ncnt, s->nl, s->nlr2, nullptr);
+    HIPCHK(hipStreamSynchronize(s->st));
+    HIPCHK(hipGetLastError());
+    return MDPD_OK;
+}
+
 mdpd_status mdpd_debug_forces(mdpd_system *s, double *force)
 {
     if (!s || !force) return fail(MDPD_E_INVALID, "NULL argument");
@@ -606,6 +777,282 @@ mdpd_status mdpd_set_lanes(mdpd_system *s, int32_t pass, int32_t lanes)
     if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16)
         return fail(MDPD_E_INVALID, "lanes %d not in {1, 2, 4, 8, 16}", lanes);
     s->lanes[pass] = lanes;
+    return MDPD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Adjoint: recorded trajectory, recomputation per segment, backward steps.
+// ---------------------------------------------------------------------------
+namespace {
+
+// One tape entry: the state of step n in its sorted order, as the backward
+// step needs it (x_n, the half-step velocity u_{n-1} its forces used, v_n,
+// rho_n, tags, types, cell offsets).
+struct TapeEntry {
+    Soa3 x, u, v;
+    void *rho;
+    uint32_t *tag;
+    uint8_t *typ;
+    int *cstart;
+};
+
+uint64_t tape_entry_bytes(mdpd_system *s)
+{
+    const uint64_t N = (uint64_t)(s->n > 0 ? s->n : 1);
+    const uint64_t rb = s->fp32 ? 4 : 8;
+    return 3 * align_up(24 * N) + align_up(rb * N) + align_up(4 * N) + align_up(N) +
+           align_up(4 * ((uint64_t)s->g.ncells + 1));
+}
+
+TapeEntry tape_entry(mdpd_system *s, int k)
+{
+    const uint64_t N = (uint64_t)(s->n > 0 ? s->n : 1);
+    const uint64_t rb = s->fp32 ? 4 : 8;
+    char *b = s->adj.tape + (uint64_t)k * s->adj.tape_bytes;
+    TapeEntry e;
+    Soa3 *planes[3] = {&e.x, &e.u, &e.v};
+    for (Soa3 *pl : planes) {
+        double *d = (double *)b;
+        *pl = Soa3{d, d + N, d + 2 * N};
+        b += align_up(24 * N);
+    }
+    e.rho = b;
+    b += align_up(rb * N);
+    e.tag = (uint32_t *)b;
+    b += align_up(4 * N);
+    e.typ = (uint8_t *)b;
+    b += align_up(N);
+    e.cstart = (int *)b;
+    return e;
+}
+
+// Copy the current state into tape entry k; u is the half-step velocity the
+// last force evaluation used (for the state at creation: v(0)).
+hipError_t tape_record(mdpd_system *s, int k, bool creation)
+{
+    const TapeEntry e = tape_entry(s, k);
+    const size_t N = (size_t)s->n;
+    const int c = s->cur;
+    const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;
+    hipError_t r = hipSuccess;
+    auto cp = [&](void *dst, const void *src, size_t bytes) {
+        if (r == hipSuccess && bytes) r = hipMemcpyAsync(dst, src, bytes, d2d, s->st);
+    };
+    cp(e.x.x, s->xs[c].x, 24 * N);
+    cp(e.u.x, creation ? s->v.x : s->vh[c].x, 24 * N);
+    cp(e.v.x, s->v.x, 24 * N);
+    cp(e.rho, s->rho, (s->fp32 ? 4 : 8) * N);
+    cp(e.tag, s->tag[c], 4 * N);
+    cp(e.typ, s->typ[c], N);
+    cp(e.cstart, s->cstart, 4 * ((size_t)s->g.ncells + 1));
+    return r;
+}
+
+// Advance without synchronising (the caller checks the status word).
+void advance(mdpd_system *s, int64_t nsteps)
+{
+    for (int64_t k = 0; k < nsteps; ++k) {
+        s->step += 1;
+        s->sort_predicted();
+        s->evaluate((uint32_t)s->step, 0);
+    }
+}
+
+hipError_t ckpt_store(mdpd_system *s, int k)
+{
+    s->adj.ck_nfpart[k] = s->nfpart_used;
+    return state_copy(s, s->adj.ck + (uint64_t)k * s->adj.ck_bytes, true, hipMemcpyDeviceToDevice);
+}
+
+hipError_t ckpt_restore(mdpd_system *s, int k, int64_t step)
+{
+    s->nfpart_used = s->adj.ck_nfpart[k];
+    s->step = step;
+    return state_copy(s, s->adj.ck + (uint64_t)k * s->adj.ck_bytes, false, hipMemcpyDeviceToDevice);
+}
+
+int64_t ckpt_step(const AdjRec &a, int k) { return k * (int64_t)a.every < a.nsteps ? k * (int64_t)a.every : a.nsteps; }
+
+// Loss weight of state n: the mean over steps 1..N, or the final state.
+double seed_weight(const AdjRec &a, int64_t n)
+{
+    if (a.avg) return n >= 1 ? 1.0 / (double)a.nsteps : 0.0;
+    return n == a.nsteps ? 1.0 : 0.0;
+}
+
+// Backward step for the state in tape entry k at step n (creation: n = 0
+// and the force adjoint takes h U).
+void adjoint_step(mdpd_system *s, int k, int64_t n, bool creation, const double w[3])
+{
+    AdjRec &a = s->adj;
+    const TapeEntry e = tape_entry(s, k);
+    const double V3 = 3.0 * s->p.box[0] * s->p.box[1] * s->p.box[2];
+    const double inf = a.nfluid > 0 ? 1.0 / (double)a.nfluid : 0.0;
+    const double sw = seed_weight(a, n);
+    AdjConst ac;
+    ac.cU = creation ? s->pc.hdtm : 2.0 * s->pc.hdtm;
+    ac.cv = creation ? 0.0 : s->pc.hdtm;
+    ac.wrho_nf = sw * w[0] * inf;
+    ac.wP_3V = sw * w[1] / V3;
+    ac.wvx_nf = sw * w[2] * inf;
+    ac.mass = s->p.mass;
+    s->set_step_keys((uint32_t)n);
+    launch_adj_seed(s->st, s->n, ac, cview(e.v), e.tag, a.U, a.fb, a.rhoA);
+    launch_nlist(s->st, s->fp32, s->n, s->g, cview(e.x), e.cstart, s->ncnt, s->nl, s->nlr2, nullptr);
+    s->tic(5);
+    launch_adj_force(s->st, s->lanes[2], s->fp32, s->n, s->pc, s->g, ac, cview(e.x), cview(e.u), e.rho, e.tag,
+                     e.typ, e.cstart, s->ncnt, s->nl, cview(a.fb), a.X, a.U, a.rhoA, a.gp);
+    launch_adj_density(s->st, s->lanes[1], s->n, s->pc, s->g, cview(e.x), e.cstart, s->ncnt, s->nl, a.rhoA,
+                       a.X);
+    s->toc(5);
+    launch_adj_params(s->st, s->n, s->p.ntypes, e.typ, a.gp, a.gpart, a.gtot);
+}
+
+}  // namespace
+
+extern "C" {
+
+mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, int32_t average, double *loss)
+{
+    if (!s || !loss) return fail(MDPD_E_INVALID, "NULL argument");
+    if (nsteps < 0 || every < 1) return fail(MDPD_E_INVALID, "need nsteps >= 0 and every >= 1");
+    if (average && nsteps < 1) return fail(MDPD_E_INVALID, "a time average needs nsteps >= 1");
+    if (s->walls) return fail(MDPD_E_UNSUPPORTED, "the adjoint does not differentiate the wall corrector");
+    if (s->step != 0) return fail(MDPD_E_STATE, "recording starts from the state given to mdpd_create");
+    if (s->p.ntypes > MDPD_ADJ_MAX_TYPES) return fail(MDPD_E_UNSUPPORTED, "too many types");
+    AdjRec &a = s->adj;
+    a.ready = false;
+    mdpd_observables o;
+    mdpd_status rc = mdpd_read_observables(s, &o);
+    if (rc) return rc;
+    a.nfluid = o.n_fluid;
+    a.nsteps = nsteps;
+    a.every = every;
+    a.avg = average ? 1 : 0;
+    const int K = (int)((nsteps + every - 1) / every);
+    const size_t N = (size_t)(s->n > 0 ? s->n : 1);
+    // (re)allocate what the recording needs
+    const uint64_t ckb = state_bytes(s), tpb = tape_entry_bytes(s);
+    const int ntape = (int)((nsteps < every ? nsteps : every) + 1);
+    if (!a.ck || a.nck < K + 1 || a.ck_bytes != ckb) {
+        s->release(a.ck);
+        a.ck = nullptr;
+        rc = s->alloc(&a.ck, (size_t)(K + 1) * ckb);
+        if (rc) return rc;
+        a.nck = K + 1;
+        a.ck_bytes = ckb;
+    }
+    a.ck_nfpart.assign((size_t)K + 1, 0);
+    if (!a.tape || a.ntape < ntape || a.tape_bytes != tpb) {
+        s->release(a.tape);
+        a.tape = nullptr;
+        rc = s->alloc(&a.tape, (size_t)ntape * tpb);
+        if (rc) return rc;
+        a.ntape = ntape;
+        a.tape_bytes = tpb;
+    }
+    if (!a.rhoA) {
+        Soa3 *v3[5] = {&a.X, &a.U, &a.fb, &a.Xid, &a.Uid};
+        for (Soa3 *q : v3)
+            if ((rc = s->alloc3(q, N))) return rc;
+        if ((rc = s->alloc(&a.rhoA, N))) return rc;
+        if ((rc = s->alloc(&a.gp, 3 * (size_t)s->p.ntypes * N))) return rc;
+        if ((rc = s->alloc(&a.gpart, (size_t)adj_param_partials(s->p.ntypes)))) return rc;
+        if ((rc = s->alloc(&a.gtot, 3 * 64))) return rc;
+        if ((rc = s->alloc(&a.loss, 4))) return rc;
+    }
+    // run and checkpoint; the loss terms accumulate on the device
+    const double V3 = 3.0 * s->p.box[0] * s->p.box[1] * s->p.box[2];
+    const double inf = a.nfluid > 0 ? 1.0 / (double)a.nfluid : 0.0;
+    HIPCHK(hipMemsetAsync(a.loss, 0, 4 * sizeof(double), s->st));
+    auto accum = [&](int64_t n) {
+        const double sw = seed_weight(a, n);
+        if (sw == 0.0) return;
+        launch_observables(s->st, s->fp32, s->n, s->pc, cview(s->v), s->rho, s->tag[s->cur], s->typ[s->cur],
+                           s->fpart, s->nfpart_used, s->ncnt, s->ovf_ve, s->obs);
+        launch_loss_accum(s->st, s->obs, a.loss, inf, 1.0 / V3, s->p.mass, sw);
+    };
+    HIPCHK(ckpt_store(s, 0));
+    accum(0);
+    for (int k = 1; k <= K; ++k) {
+        const int64_t s0 = ckpt_step(a, k - 1), s1 = ckpt_step(a, k);
+        for (int64_t n = s0 + 1; n <= s1; ++n) {
+            advance(s, 1);
+            accum(n);
+        }
+        HIPCHK(ckpt_store(s, k));
+    }
+    int hstatus = 0;
+    HIPCHK(hipMemcpyAsync(loss, a.loss, 3 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(&hstatus, s->status, sizeof(int), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    HIPCHK(hipGetLastError());
+    if (hstatus) return fail(MDPD_E_NONFINITE, "non-finite or out-of-box state during the recording");
+    a.ready = true;
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *dB, double *dgamma, double *dx0,
+                          double *dv0, int32_t mem_kind)
+{
+    if (!s || !w) return fail(MDPD_E_INVALID, "NULL argument");
+    if (mem_kind != MDPD_MEM_HOST && mem_kind != MDPD_MEM_DEVICE)
+        return fail(MDPD_E_INVALID, "unknown mem_kind %d", mem_kind);
+    AdjRec &a = s->adj;
+    if (!a.ready) return fail(MDPD_E_STATE, "no recorded trajectory (call mdpd_forward_record first)");
+    const size_t N = (size_t)s->n;
+    const int K = (int)((a.nsteps + a.every - 1) / a.every);
+    const int T = s->p.ntypes;
+    HIPCHK(hipMemsetAsync(a.gtot, 0, 3 * 64 * sizeof(double), s->st));
+    if (N > 0) {
+        launch_zero_int(s->st, (int *)a.X.x, (int)(6 * N));
+        launch_zero_int(s->st, (int *)a.U.x, (int)(6 * N));
+    }
+    // segments from the last to the first: recompute, then step back
+    for (int k = K; k >= 1; --k) {
+        const int64_t s0 = ckpt_step(a, k - 1), s1 = ckpt_step(a, k);
+        HIPCHK(ckpt_restore(s, k - 1, s0));
+        HIPCHK(tape_record(s, 0, s0 == 0));
+        for (int m = 1; m <= (int)(s1 - s0); ++m) {
+            advance(s, 1);
+            HIPCHK(tape_record(s, m, false));
+        }
+        for (int m = (int)(s1 - s0); m >= 1; --m) {
+            adjoint_step(s, m, s0 + m, false, w);
+            const TapeEntry cur = tape_entry(s, m), prev = tape_entry(s, m - 1);
+            launch_adj_scatter(s->st, s->n, s->p.dt, cur.tag, cview(a.X), cview(a.U), a.Xid, a.Uid);
+            launch_adj_gather(s->st, s->n, prev.tag, cview(a.Xid), cview(a.Uid), a.X, a.U);
+        }
+    }
+    if (K == 0) {
+        HIPCHK(ckpt_restore(s, 0, 0));
+        HIPCHK(tape_record(s, 0, true));
+    }
+    // the evaluation at creation, then export by id
+    adjoint_step(s, 0, 0, true, w);
+    double g[3 * 64];
+    HIPCHK(hipMemcpyAsync(g, a.gtot, sizeof g, hipMemcpyDeviceToHost, s->st));
+    const hipMemcpyKind dk = mem_kind == MDPD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (N > 0) {
+        // sorted SoA planes to n x 3 rows in id order (U of frozen particles is 0)
+        launch_export(s->st, false, s->n, cview(a.X), cview(a.U), nullptr, tape_entry(s, 0).tag, s->io, s->io2,
+                      nullptr);
+        if (dx0) HIPCHK(hipMemcpyAsync(dx0, s->io, 3 * N * sizeof(double), dk, s->st));
+        if (dv0) HIPCHK(hipMemcpyAsync(dv0, s->io2, 3 * N * sizeof(double), dk, s->st));
+    }
+    HIPCHK(hipStreamSynchronize(s->st));
+    double *outs[3] = {dA, dB, dgamma};
+    for (int q = 0; q < 3; ++q) {
+        if (!outs[q]) continue;
+        for (int ab = 0; ab < T * T; ++ab) outs[q][ab] = g[q * 64 + ab];
+    }
+    // back to the state at the end of the recording
+    HIPCHK(ckpt_restore(s, K, a.nsteps));
+    launch_nlist(s->st, s->fp32, s->n, s->g, cview(s->xs[s->cur]), s->cstart, s->ncnt, s->nl, s->nlr2, nullptr);
+    HIPCHK(hipStreamSynchronize(s->st));
+    HIPCHK(hipGetLastError());
     return MDPD_OK;
 }
 

@@ -142,6 +142,18 @@ __device__ __forceinline__ int theta_int(uint32_t ida, uint32_t idb, const PairC
     return (int)((w >> 8) << 1) + 1 - 16777216;
 }
 
+// Scalars of one backward step of the adjoint (adjoint.hip).  Loss weights
+// are zero at states that carry no loss term.
+#define MDPD_ADJ_MAX_TYPES 8
+struct AdjConst {
+    double cU;       // coefficient of U = dL/du_n in the force adjoint: 2h, or h at creation
+    double cv;       // coefficient of the velocity seed in the force adjoint: h, or 0 at creation
+    double wrho_nf;  // weight of the mean fluid density / N_f
+    double wP_3V;    // weight of the virial pressure / (3 V)
+    double wvx_nf;   // weight of the mean fluid x-velocity / N_f
+    double mass;
+};
+
 // Host-side launchers (defined in the .hip files).
 void launch_ingest(hipStream_t st, int64_t n, const double *pos, const double *vel,
                    const int32_t *type, const uint8_t *frozen, Geom g, int ntypes, Soa3 xp,
@@ -149,7 +161,8 @@ void launch_ingest(hipStream_t st, int64_t n, const double *pos, const double *v
 void launch_sort(hipStream_t st, int n, Geom g, Soa3c xin, Soa3c vin, Soa3c xprev_in,
                  const uint32_t *tag_in, const uint8_t *typ_in, Soa3 xout, Soa3 vout,
                  Soa3 xprev_out, uint32_t *tag_out, uint8_t *typ_out, int *key, int *slot,
-                 uint32_t *tmpid, int *counts, int *cstart, int *bsum, const int *gate);
+                 uint32_t *tmpid, int *counts, int *cstart, int *bsum, const int *gate,
+                 int *ovf_count);
 void launch_nlist(hipStream_t st, bool fp32, int n, Geom g, Soa3c xs, const int *cstart,
                   int *ncnt, uint32_t *nl, void *nlr2, const int *gate);
 void launch_density(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g,
@@ -161,11 +174,33 @@ void launch_phi(hipStream_t st, int lanes, int n, const PairConst &pc, Geom g, S
 void launch_force(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g,
                   Soa3c xs, Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ,
                   const int *cstart, const int *ncnt, const uint32_t *nl, Soa3 vout, Soa3 fout,
-                  Soa3 vpred, Soa3 xpred, double *part, int *status, int initial);
-int force_blocks(int lanes, int n);
+                  Soa3 vpred, Soa3 xpred, double *part, int *status, int *ovf_count, int *ovf,
+                  double *ovf_ve, int initial);
+// Number of virial/energy block partials the force pass writes.
+int force_partials(int lanes, int n);
+void launch_adj_seed(hipStream_t st, int n, const AdjConst &ac, Soa3c v, const uint32_t *tag, Soa3 U,
+                     Soa3 fb, double *rhoA);
+void launch_adj_force(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g,
+                      const AdjConst &ac, Soa3c xs, Soa3c u, const void *rho, const uint32_t *tag,
+                      const uint8_t *typ, const int *cstart, const int *ncnt, const uint32_t *nl,
+                      Soa3c fb, Soa3 X, Soa3 U, double *rhoA, double *gp);
+void launch_adj_density(hipStream_t st, int lanes, int n, const PairConst &pc, Geom g, Soa3c xs,
+                        const int *cstart, const int *ncnt, const uint32_t *nl, const double *rhoA,
+                        Soa3 X);
+void launch_adj_scatter(hipStream_t st, int n, double dt, const uint32_t *tag, Soa3c X, Soa3c U,
+                        Soa3 Xid, Soa3 Uid);
+void launch_adj_gather(hipStream_t st, int n, const uint32_t *tag, Soa3c Xid, Soa3c Uid, Soa3 X,
+                       Soa3 U);
+int adj_param_partials(int ntypes);
+void launch_adj_params(hipStream_t st, int n, int ntypes, const uint8_t *typ, const double *gp,
+                       double *part, double *total);
 void launch_observables(hipStream_t st, bool fp32, int n, const PairConst &pc, Soa3c v,
                         const void *rho, const uint32_t *tag, const uint8_t *typ,
-                        const double *fpart, int nfpart, double *out16);
+                        const double *fpart, int nfpart, const int *ncnt, const double *ovf_ve,
+                        double *out16);
+constexpr int kObsSlots = 16 + 1024 * 10;  // result slots + block partials
+void launch_loss_accum(hipStream_t st, const double *obs16, double *acc, double inv_nf, double inv3V,
+                       double mass, double scale);
 void launch_profile(hipStream_t st, bool fp32, int n, int axis, int nbins, int quantity, double La,
                     double binvol, double mass, Soa3c x, Soa3c v, const void *rho,
                     const uint32_t *tag, double *work, double *out);

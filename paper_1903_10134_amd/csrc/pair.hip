@@ -18,142 +18,11 @@
 // sums with a butterfly of lane shuffles inside the group, so every sum has
 // one fixed order.  A particle with more than kListCap neighbours is served by
 // a direct scan of the cells with the same exact test.
-#include "mdpd_internal.h"
+#include "pair_common.h"
 
 namespace mdpd {
 
 namespace {
-
-constexpr double kSqrt3Scaled = 1.7320508075688772 / 16777216.0;  // sqrt(3) 2^-24
-constexpr float kSqrt3ScaledF = 1.7320508075688772f / 16777216.0f;
-constexpr uint32_t kNearBit = 0x80000000u;  // list entry flag: r < r_d
-constexpr uint32_t kSlotMask = 0x7fffffffu;
-constexpr int kWavesPerBlock = kBlock / 64;
-
-// Element idx of an array addressed with a 32-bit byte offset, so that the
-// load can take the array base in scalar registers.
-template <typename T>
-__device__ __forceinline__ T ld(const T *__restrict__ base, int idx)
-{
-    return *(const T *)((const char *)base + (uint32_t)idx * (uint32_t)sizeof(T));
-}
-
-__device__ __forceinline__ int wrap_index(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
-
-// Calls fn(begin, end, sx, sy, sz) for the contiguous slot ranges of the
-// cells around the cell of (xi, yi, zi) that can hold a particle closer than
-// r_c; (sx, sy, sz) is the periodic shift to add to x_i - x_j for candidates of
-// that range.  Rows (dy, dz) whose nearest face is already r_c away are
-// skipped, and in each row the x-neighbour cells are kept only when their
-// facing side is closer than the row's remaining reach sqrt(r_c^2 - dy^2 -
-// dz^2).  The clipping margin (1e-9) is far above rounding, so it never drops
-// a pair that the exact test would keep.
-template <typename Fn>
-__device__ __forceinline__ void for_each_row(const Geom &g, double xi, double yi, double zi,
-                                             const int *__restrict__ cstart, Fn &&fn)
-{
-    constexpr double kMargin = 1e-9;
-    const int nx = g.nc[0], ny = g.nc[1], nz = g.nc[2];
-    const int cx = cell_coord(xi, g.s[0], nx);
-    const int cy = cell_coord(yi, g.s[1], ny);
-    const int cz = cell_coord(zi, g.s[2], nz);
-    const double lox = xi - cx * g.cs[0], hix = (cx + 1) * g.cs[0] - xi;
-    const double loy = yi - cy * g.cs[1], hiy = (cy + 1) * g.cs[1] - yi;
-    const double loz = zi - cz * g.cs[2], hiz = (cz + 1) * g.cs[2] - zi;
-    for (int dz = -1; dz <= 1; ++dz) {
-        const double ez = dz == 0 ? 0.0 : fmax(0.0, (dz < 0 ? loz : hiz) - kMargin);
-        if (ez >= g.rc) continue;
-        const int zz = wrap_index(cz + dz, nz);
-        const double sz = cz + dz < 0 ? g.L[2] : (cz + dz >= nz ? -g.L[2] : 0.0);
-        for (int dy = -1; dy <= 1; ++dy) {
-            const double ey = dy == 0 ? 0.0 : fmax(0.0, (dy < 0 ? loy : hiy) - kMargin);
-            const double q = ey * ey + ez * ez;
-            if (q >= g.rc2) continue;
-            const double reach = __builtin_sqrt(g.rc2 - q) + kMargin;
-            const int yy = wrap_index(cy + dy, ny);
-            const double sy = cy + dy < 0 ? g.L[1] : (cy + dy >= ny ? -g.L[1] : 0.0);
-            const int base = nx * (yy + ny * zz);
-            const int xa = cx - (lox < reach ? 1 : 0);
-            const int xb = cx + (hix < reach ? 1 : 0);
-            if (xa >= 0 && xb < nx) {
-                fn(cstart[base + xa], cstart[base + xb + 1], 0.0, sy, sz);
-            } else if (xa < 0) {
-                fn(cstart[base + nx - 1], cstart[base + nx], g.L[0], sy, sz);
-                fn(cstart[base], cstart[base + xb + 1], 0.0, sy, sz);
-            } else {
-                fn(cstart[base + xa], cstart[base + nx], 0.0, sy, sz);
-                fn(cstart[base], cstart[base + 1], -g.L[0], sy, sz);
-            }
-        }
-    }
-}
-
-// Hardware dispatches workgroups to the 8 XCDs round robin; remap so that
-// each XCD (and its L2) works through one contiguous chunk of the sorted
-// particles, whose neighbour data it then reuses.
-__device__ __forceinline__ int xcd_block()
-{
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int per = nb >> 3, rem = nb & 7, x = b & 7, k = b >> 3;
-    return x * per + (x < rem ? x : rem) + k;
-}
-
-// Sum over the P lanes of a group (butterfly, fixed order).
-template <int P, typename T>
-__device__ __forceinline__ T group_sum(T v)
-{
-#pragma unroll
-    for (int m = 1; m < P; m <<= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
-
-// Broadcast of lane u's value (u wave-uniform) through the scalar unit.
-__device__ __forceinline__ int bcast_i(int v, int u) { return __builtin_amdgcn_readlane(v, u); }
-__device__ __forceinline__ double bcast_d(double v, int u)
-{
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, u);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), u);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-__device__ __forceinline__ int lanes_below(unsigned long long m)
-{
-    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-}
-
-// Visits every neighbour j (r_ij < r_c, j != i) of slot i: from the list when
-// it did not overflow, else by a direct cell scan with the same exact test.
-// fn(j, dx, dy, dz, near) receives the minimum-image difference x_i - x_j and
-// whether r_ij < r_d.
-template <int P, typename Fn>
-__device__ __forceinline__ void for_each_neighbor(const PairConst &pc, const Geom &g, int i, int sub,
-                                                  double xi, double yi, double zi, Soa3c xs,
-                                                  const int *__restrict__ cstart, int cnt,
-                                                  const uint32_t *__restrict__ lst, Fn &&fn)
-{
-    if (cnt <= kListCap) {
-        for (int k = sub; k < cnt; k += P) {
-            const uint32_t e = lst[k];
-            const int j = (int)(e & kSlotMask);
-            const double dx = min_image(xi - ld(xs.x, j), pc.L[0], pc.invL[0]);
-            const double dy = min_image(yi - ld(xs.y, j), pc.L[1], pc.invL[1]);
-            const double dz = min_image(zi - ld(xs.z, j), pc.L[2], pc.invL[2]);
-            fn(j, dx, dy, dz, (e & kNearBit) != 0);
-        }
-    } else {
-        for_each_row(g, xi, yi, zi, cstart, [&](int b, int e, double sx, double sy, double sz) {
-            for (int j = b + sub; j < e; j += P) {
-                if (j == i) continue;
-                const double dx = (xi - xs.x[j]) + sx;
-                const double dy = (yi - xs.y[j]) + sy;
-                const double dz = (zi - xs.z[j]) + sz;
-                const double r2 = exact_r2(dx, dy, dz);
-                if (r2 < g.rc2) fn(j, dx, dy, dz, r2 < g.rd2);
-            }
-        });
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Neighbour list: one wavefront per cell.
@@ -171,16 +40,25 @@ __device__ __forceinline__ void for_each_neighbor(const PairConst &pc, const Geo
 // general path: batches are walked 64 candidates at a time with the shifts of
 // each row piece, and i's running count lives in lane (i mod 64).
 //
-// Each entry is the neighbour's slot, with kNearBit set when r < r_d, and the
-// exact r^2 is stored at the same position of a parallel array (R2 = FP32 or
-// FP64, the arithmetic of the density pass).
+// Each entry is the neighbour's slot, with kNearBit set when r < r_d and
+// kWrapBit set when the pair is seen through a periodic image (its difference
+// then needs the minimum-image shift).  Entries with r < r_d fill the row from
+// the front and their exact r^2 is stored at the same position of a parallel
+// array (R2 = FP32 or FP64, the arithmetic of the density pass); the other
+// entries fill the row from the back.
+// Near hits go to the front with their r^2, the others to the back; a row
+// whose counts add up to more than kListCap is not read (direct scan).
 template <typename R2>
-__device__ __forceinline__ void emit_hit(uint32_t *__restrict__ out, R2 *__restrict__ outr, int pos,
-                                         int slot, double r2, double rd2)
+__device__ __forceinline__ void emit_hit(uint32_t *__restrict__ out, R2 *__restrict__ outr, bool near,
+                                         int pos, int slot, double r2, bool wrap)
 {
-    if (pos < kListCap) {
-        out[pos] = (uint32_t)slot | (r2 < rd2 ? kNearBit : 0u);
+    if (pos >= kListCap) return;
+    const uint32_t e = (uint32_t)slot | (near ? kNearBit : 0u) | (wrap ? kWrapBit : 0u);
+    if (near) {
+        out[pos] = e;
         outr[pos] = (R2)r2;
+    } else {
+        out[kListCap - 1 - pos] = e;
     }
 }
 
@@ -243,19 +121,24 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Geom g, int n, Soa3c xs,
                 const int i = i0 + ib + u;
                 uint32_t *out = nl + (size_t)i * kListCap;
                 R2 *outr = nlr2 + (size_t)i * kListCap;
-                int cnt = 0;
+                int cn = 0, cf = 0;
 #pragma unroll
                 for (int s = 0; s < 6; ++s) {
                     if ((s & 1) && qz[s >> 1] <= 64) continue;
                     const double r2 = exact_r2(xi - cxj[s], yi - cyj[s], zi - czj[s]);
                     const bool hit = cs[s] >= 0 && cs[s] != i && r2 < rc2;
-                    const unsigned long long m = __ballot(hit);
-                    if (m) {
-                        if (hit) emit_hit<R2>(out, outr, cnt + lanes_below(m), cs[s], r2, rd2);
-                        cnt += __popcll(m);
+                    const bool near = r2 < rd2;
+                    const unsigned long long mn = __ballot(hit && near);
+                    const unsigned long long mf = __ballot(hit && !near);
+                    if (mn | mf) {
+                        if (hit)
+                            emit_hit<R2>(out, outr, near, near ? cn + lanes_below(mn) : cf + lanes_below(mf),
+                                         cs[s], r2, false);
+                        cn += __popcll(mn);
+                        cf += __popcll(mf);
                     }
                 }
-                if (lane == 0) ncnt[i] = cnt;
+                if (lane == 0) ncnt[i] = cn | (cf << 16);
             }
         }
         return;
@@ -267,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Geom g, int n, Soa3c xs,
         const int nic = ni - ib < 64 ? ni - ib : 64;
         const int me = i0 + ib + (lane < nic ? lane : 0);
         const double pxi = ld(xs.x, me), pyi = ld(xs.y, me), pzi = ld(xs.z, me);
-        int cnt = 0;
+        int cnt = 0;  // lane u: near count | far count << 16 of particle i0 + ib + u
         for (int dz = -1; dz <= 1; ++dz) {
             const int zz = wrap_index(cz + dz, nz);
             const double sz = cz + dz < 0 ? g.L[2] : (cz + dz >= nz ? -g.L[2] : 0.0);
@@ -330,13 +213,17 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Geom g, int n, Soa3c xs,
                     const int i = i0 + ib + u;
                     const double r2 = exact_r2((xi - xj) + sx, (yi - yj) + sy, (zi - zj) + sz);
                     const bool hit = slot >= 0 && slot != i && r2 < rc2;
-                    const unsigned long long m = __ballot(hit);
-                    if (m) {
+                    const bool near = r2 < rd2;
+                    const unsigned long long mn = __ballot(hit && near);
+                    const unsigned long long mf = __ballot(hit && !near);
+                    if (mn | mf) {
                         const int base = bcast_i(cnt, u);
                         if (hit)
-                            emit_hit<R2>(nl + (size_t)i * kListCap, nlr2 + (size_t)i * kListCap,
-                                         base + lanes_below(m), slot, r2, rd2);
-                        if (lane == u) cnt += __popcll(m);
+                            emit_hit<R2>(nl + (size_t)i * kListCap, nlr2 + (size_t)i * kListCap, near,
+                                         near ? (base & 0xffff) + lanes_below(mn)
+                                              : (base >> 16) + lanes_below(mf),
+                                         slot, r2, sx != 0.0 || sy != 0.0 || sz != 0.0);
+                        if (lane == u) cnt += __popcll(mn) + (__popcll(mf) << 16);
                     }
                 }
             }
@@ -369,20 +256,18 @@ template <int P, typename R>
 __global__ __launch_bounds__(kBlock) void k_density(PairConst pc, Geom g, int n, Soa3c xs,
                                                     const int *__restrict__ cstart,
                                                     const int *__restrict__ ncnt,
-                                                    const uint32_t *__restrict__ nl,
                                                     const R *__restrict__ nlr2, R *__restrict__ rho)
 {
     const int t = xcd_block() * kBlock + threadIdx.x;
     const int i = t / P;
     const int sub = t & (P - 1);
     if (i >= n) return;
-    const int cnt = ncnt[i];
+    const int packed = ncnt[i];
     R acc = 0;
-    if (cnt <= kListCap) {
-        const uint32_t *lst = nl + (size_t)i * kListCap;
+    if (list_total(packed) <= kListCap) {
+        const int nnear = list_near(packed);
         const R *lr = nlr2 + (size_t)i * kListCap;
-        for (int k = sub; k < cnt; k += P)
-            if (lst[k] & kNearBit) acc += w_rho<R>(pc, lr[k]);
+        for (int k = sub; k < nnear; k += P) acc += w_rho<R>(pc, lr[k]);
     } else {
         const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
         for_each_row(g, xi, yi, zi, cstart, [&](int b, int e, double sx, double sy, double sz) {
@@ -507,109 +392,130 @@ __device__ __forceinline__ void pair_force(const PairConst &pc, double A, double
     }
 }
 
-template <int P, bool MT, typename R>
-__global__ __launch_bounds__(kBlock) void k_force(PairConst pc, Geom g, int n, Soa3c xs, Soa3c vh,
-                                                  const R *__restrict__ rho,
-                                                  const uint32_t *__restrict__ tag,
-                                                  const uint8_t *__restrict__ typ,
-                                                  const int *__restrict__ cstart,
-                                                  const int *__restrict__ ncnt,
-                                                  const uint32_t *__restrict__ nl, Soa3 vout, Soa3 fout,
-                                                  Soa3 vpred, Soa3 xpred, double *__restrict__ part,
-                                                  int *__restrict__ status, int initial)
+// Outputs of the force pass.
+struct ForceOut {
+    Soa3 v, f, vpred, xpred;  // v(t+dt), F(t+dt), next half-step velocity, next predicted x
+    double *part;             // per-block virial and pair-energy partials
+    int *status;              // bit 0: non-finite or out-of-box state
+    int *ovf_count, *ovf;     // particles whose list overflowed, for k_force_overflow
+    int initial;              // 1 at creation: v(t) is the given velocity
+};
+
+// Force on particle i (slot), its velocity-Verlet epilogue, and its share of
+// the virial and pair energy.  SCAN = false: the neighbours come from the
+// list; SCAN = true: from a direct scan of the cells (lists that overflowed).
+// Both are separate instantiations so the list kernel keeps the small
+// register footprint of the list loop.
+template <int P, bool MT, bool SCAN, typename R>
+__device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &g, int i, int sub, Soa3c xs,
+                                               Soa3c vh, const R *__restrict__ rho,
+                                               const uint32_t *__restrict__ tag,
+                                               const uint8_t *__restrict__ typ,
+                                               const int *__restrict__ cstart, int packed,
+                                               const uint32_t *__restrict__ lst, const ForceOut &out,
+                                               double &vir, double &ep)
+{
+    const uint32_t tgi = tag[i];
+    const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
+    if (tgi & kFrozenBit) {
+        if (sub == 0) {
+            out.v.x[i] = out.v.y[i] = out.v.z[i] = 0.0;
+            out.f.x[i] = out.f.y[i] = out.f.z[i] = 0.0;
+            out.vpred.x[i] = out.vpred.y[i] = out.vpred.z[i] = 0.0;
+            out.xpred.x[i] = xi;
+            out.xpred.y[i] = yi;
+            out.xpred.z[i] = zi;
+        }
+        return;
+    }
+    const uint32_t idi = tgi & kIdMask;
+    const double vxi = vh.x[i], vyi = vh.y[i], vzi = vh.z[i];
+    const R rhoi = rho[i];
+    const int T = pc.ntypes;
+    const int ti = MT ? (int)typ[i] : 0;
+    R fx = 0, fy = 0, fz = 0;
+    // pair arithmetic for one neighbour whose data is already loaded
+    auto pair = [&](double dx, double dy, double dz, double vxj, double vyj, double vzj, R rj, uint32_t tgj,
+                    int tj, bool near) {
+        double A = pc.A, B = pc.B, gam = pc.gamma, sig = pc.sig, Arc2 = pc.Arc2;
+        if (MT) {
+            const int tt = ti * T + tj;
+            A = pc.tab[tt];
+            B = pc.tab[64 + tt];
+            gam = pc.tab[128 + tt];
+            sig = pc.tab[192 + tt];
+            Arc2 = pc.tab[256 + tt];
+        }
+        const int th = theta_int(idi, tgj & kIdMask, pc);
+        const double c = (tgj & kFrozenBit) ? 1.0 : 0.5;
+        pair_force<R>(pc, A, B, gam, sig, Arc2, dx, dy, dz, vxi - vxj, vyi - vyj, vzi - vzj, near, rhoi + rj, th,
+                      c, fx, fy, fz, vir, ep);
+    };
+    if constexpr (SCAN) {
+        for_each_neighbor<P>(pc, g, i, sub, xi, yi, zi, xs, cstart, packed, nullptr,
+                             [&](int j, double dx, double dy, double dz, bool near) {
+                                 pair(dx, dy, dz, ld(vh.x, j), ld(vh.y, j), ld(vh.z, j), ld(rho, j), ld(tag, j),
+                                      MT ? (int)ld(typ, j) : 0, near);
+                             });
+    } else {
+        const int cnt = list_total(packed), nnear = list_near(packed);
+        for (int k = sub; k < cnt; k += P) {
+            const uint32_t e = lst[list_pos(k, nnear)];
+            const int j = (int)(e & kSlotMask);
+            // every load of the neighbour first, then the arithmetic; the
+            // minimum-image shift is a select, so no branch splits the loads
+            const double xj = ld(xs.x, j), yj = ld(xs.y, j), zj = ld(xs.z, j);
+            const double vxj = ld(vh.x, j), vyj = ld(vh.y, j), vzj = ld(vh.z, j);
+            const R rj = ld(rho, j);
+            const uint32_t tgj = ld(tag, j);
+            const int tj = MT ? (int)ld(typ, j) : 0;
+            const bool wr = (e & kWrapBit) != 0;
+            double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+            dx = wr ? min_image(dx, pc.L[0], pc.invL[0]) : dx;
+            dy = wr ? min_image(dy, pc.L[1], pc.invL[1]) : dy;
+            dz = wr ? min_image(dz, pc.L[2], pc.invL[2]) : dz;
+            pair(dx, dy, dz, vxj, vyj, vzj, rj, tgj, tj, (e & kNearBit) != 0);
+        }
+    }
+    fx = group_sum<P>(fx);
+    fy = group_sum<P>(fy);
+    fz = group_sum<P>(fz);
+    if (sub != 0) return;
+    const double Fx = (double)fx + pc.mg[0];
+    const double Fy = (double)fy + pc.mg[1];
+    const double Fz = (double)fz + pc.mg[2];
+    const double vx = out.initial ? vxi : vxi + pc.hdtm * Fx;
+    const double vy = out.initial ? vyi : vyi + pc.hdtm * Fy;
+    const double vz = out.initial ? vzi : vzi + pc.hdtm * Fz;
+    const double px = vx + pc.hdtm * Fx;
+    const double py = vy + pc.hdtm * Fy;
+    const double pz = vz + pc.hdtm * Fz;
+    const double qx = wrap_coord(xi + pc.dt * px, pc.L[0]);
+    const double qy = wrap_coord(yi + pc.dt * py, pc.L[1]);
+    const double qz = wrap_coord(zi + pc.dt * pz, pc.L[2]);
+    out.v.x[i] = vx;
+    out.v.y[i] = vy;
+    out.v.z[i] = vz;
+    out.f.x[i] = Fx;
+    out.f.y[i] = Fy;
+    out.f.z[i] = Fz;
+    out.vpred.x[i] = px;
+    out.vpred.y[i] = py;
+    out.vpred.z[i] = pz;
+    out.xpred.x[i] = qx;
+    out.xpred.y[i] = qy;
+    out.xpred.z[i] = qz;
+    const bool ok = __builtin_isfinite(qx) && __builtin_isfinite(qy) && __builtin_isfinite(qz) &&
+                    __builtin_isfinite(px) && __builtin_isfinite(py) && __builtin_isfinite(pz) && qx >= 0.0 &&
+                    qx < pc.L[0] && qy >= 0.0 && qy < pc.L[1] && qz >= 0.0 && qz < pc.L[2];
+    if (!ok) atomicOr(out.status, 1);
+}
+
+// Fixed-order block sum of the per-lane virial and pair-energy partials.
+__device__ __forceinline__ void block_partials(double vir, double ep, double *part, int slot)
 {
     __shared__ double red_v[kBlock];
     __shared__ double red_e[kBlock];
-    const int t = xcd_block() * kBlock + threadIdx.x;
-    const int i = t / P;
-    const int sub = t & (P - 1);
-    double vir = 0.0, ep = 0.0;
-    if (i < n) {
-        const uint32_t tgi = tag[i];
-        const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
-        if (!(tgi & kFrozenBit)) {
-            const uint32_t idi = tgi & kIdMask;
-            const double vxi = vh.x[i], vyi = vh.y[i], vzi = vh.z[i];
-            const R rhoi = rho[i];
-            const int T = pc.ntypes;
-            const int ti = MT ? (int)typ[i] : 0;
-            R fx = 0, fy = 0, fz = 0;
-            auto one = [&](int j, double dx, double dy, double dz, bool near) {
-                const uint32_t tgj = ld(tag, j);
-                const double dvx = vxi - ld(vh.x, j), dvy = vyi - ld(vh.y, j), dvz = vzi - ld(vh.z, j);
-                const R rhoij = rhoi + ld(rho, j);
-                double A = pc.A, B = pc.B, gam = pc.gamma, sig = pc.sig, Arc2 = pc.Arc2;
-                if (MT) {
-                    const int tt = ti * T + (int)ld(typ, j);
-                    A = pc.tab[tt];
-                    B = pc.tab[64 + tt];
-                    gam = pc.tab[128 + tt];
-                    sig = pc.tab[192 + tt];
-                    Arc2 = pc.tab[256 + tt];
-                }
-                const int th = theta_int(idi, tgj & kIdMask, pc);
-                const double c = (tgj & kFrozenBit) ? 1.0 : 0.5;
-                pair_force<R>(pc, A, B, gam, sig, Arc2, dx, dy, dz, dvx, dvy, dvz, near, rhoij, th, c, fx, fy,
-                              fz, vir, ep);
-            };
-            const int cnt = ncnt[i];
-            if (cnt <= kListCap) {
-                const uint32_t *lst = nl + (size_t)i * kListCap;
-                for (int k = sub; k < cnt; k += P) {
-                    const uint32_t e = lst[k];
-                    const int j = (int)(e & kSlotMask);
-                    const double xj = ld(xs.x, j), yj = ld(xs.y, j), zj = ld(xs.z, j);
-                    one(j, min_image(xi - xj, pc.L[0], pc.invL[0]), min_image(yi - yj, pc.L[1], pc.invL[1]),
-                        min_image(zi - zj, pc.L[2], pc.invL[2]), (e & kNearBit) != 0);
-                }
-            } else {
-                for_each_neighbor<P>(pc, g, i, sub, xi, yi, zi, xs, cstart, cnt, nullptr, one);
-            }
-            fx = group_sum<P>(fx);
-            fy = group_sum<P>(fy);
-            fz = group_sum<P>(fz);
-            if (sub == 0) {
-                const double Fx = (double)fx + pc.mg[0];
-                const double Fy = (double)fy + pc.mg[1];
-                const double Fz = (double)fz + pc.mg[2];
-                const double vx = initial ? vxi : vxi + pc.hdtm * Fx;
-                const double vy = initial ? vyi : vyi + pc.hdtm * Fy;
-                const double vz = initial ? vzi : vzi + pc.hdtm * Fz;
-                const double px = vx + pc.hdtm * Fx;
-                const double py = vy + pc.hdtm * Fy;
-                const double pz = vz + pc.hdtm * Fz;
-                const double qx = wrap_coord(xi + pc.dt * px, pc.L[0]);
-                const double qy = wrap_coord(yi + pc.dt * py, pc.L[1]);
-                const double qz = wrap_coord(zi + pc.dt * pz, pc.L[2]);
-                vout.x[i] = vx;
-                vout.y[i] = vy;
-                vout.z[i] = vz;
-                fout.x[i] = Fx;
-                fout.y[i] = Fy;
-                fout.z[i] = Fz;
-                vpred.x[i] = px;
-                vpred.y[i] = py;
-                vpred.z[i] = pz;
-                xpred.x[i] = qx;
-                xpred.y[i] = qy;
-                xpred.z[i] = qz;
-                const bool ok = __builtin_isfinite(qx) && __builtin_isfinite(qy) &&
-                                __builtin_isfinite(qz) && __builtin_isfinite(px) &&
-                                __builtin_isfinite(py) && __builtin_isfinite(pz) &&
-                                qx >= 0.0 && qx < pc.L[0] && qy >= 0.0 && qy < pc.L[1] &&
-                                qz >= 0.0 && qz < pc.L[2];
-                if (!ok) atomicOr(status, 1);
-            }
-        } else if (sub == 0) {
-            vout.x[i] = vout.y[i] = vout.z[i] = 0.0;
-            fout.x[i] = fout.y[i] = fout.z[i] = 0.0;
-            vpred.x[i] = vpred.y[i] = vpred.z[i] = 0.0;
-            xpred.x[i] = xi;
-            xpred.y[i] = yi;
-            xpred.z[i] = zi;
-        }
-    }
-    // block partials of the virial and the pair energy (fixed-order tree)
     red_v[threadIdx.x] = vir;
     red_e[threadIdx.x] = ep;
     __syncthreads();
@@ -621,8 +527,68 @@ __global__ __launch_bounds__(kBlock) void k_force(PairConst pc, Geom g, int n, S
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        part[2 * xcd_block()] = red_v[0];
-        part[2 * xcd_block() + 1] = red_e[0];
+        part[2 * slot] = red_v[0];
+        part[2 * slot + 1] = red_e[0];
+    }
+}
+
+template <int P, bool MT, typename R>
+__global__ __launch_bounds__(kBlock) void k_force(PairConst pc, Geom g, int n, Soa3c xs, Soa3c vh,
+                                                  const R *__restrict__ rho,
+                                                  const uint32_t *__restrict__ tag,
+                                                  const uint8_t *__restrict__ typ,
+                                                  const int *__restrict__ ncnt,
+                                                  const uint32_t *__restrict__ nl, ForceOut out)
+{
+    const int blk = xcd_block();
+    const int t = blk * kBlock + threadIdx.x;
+    const int i = t / P;
+    const int sub = t & (P - 1);
+    double vir = 0.0, ep = 0.0;
+    if (i < n) {
+        const int packed = ncnt[i];
+        if (list_total(packed) <= kListCap) {
+            force_particle<P, MT, false, R>(pc, g, i, sub, xs, vh, rho, tag, typ, nullptr, packed,
+                                            nl + (size_t)i * kListCap, out, vir, ep);
+        } else if (sub == 0) {
+            out.ovf[atomicAdd(out.ovf_count, 1)] = i;  // served by k_force_overflow
+        }
+    }
+    block_partials(vir, ep, out.part, blk);
+}
+
+// Particles whose neighbour list overflowed: a fixed grid walks the queue
+// that k_force filled, scanning the cells directly.  The queue order depends
+// on atomic timing, so each particle's virial and pair-energy share goes to
+// its own slot of ovf_ve (summed per particle in a fixed order) and the
+// observables reduction adds it back in slot order.
+constexpr int kOverflowBlocks = 32;
+
+template <bool MT, typename R>
+__global__ __launch_bounds__(kBlock) void k_force_overflow(PairConst pc, Geom g, Soa3c xs, Soa3c vh,
+                                                           const R *__restrict__ rho,
+                                                           const uint32_t *__restrict__ tag,
+                                                           const uint8_t *__restrict__ typ,
+                                                           const int *__restrict__ cstart,
+                                                           const int *__restrict__ ncnt, ForceOut out,
+                                                           double *__restrict__ ovf_ve)
+{
+    constexpr int P = 4;
+    const int count = *out.ovf_count;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int groups = gridDim.x * (kBlock / P);
+    const int sub = t & (P - 1);
+    for (int q = t / P; q < count; q += groups) {
+        const int i = out.ovf[q];
+        double vir = 0.0, ep = 0.0;
+        force_particle<P, MT, true, R>(pc, g, i, sub, xs, vh, rho, tag, typ, cstart, ncnt[i], nullptr, out, vir,
+                                       ep);
+        vir = group_sum<P>(vir);
+        ep = group_sum<P>(ep);
+        if (sub == 0) {
+            ovf_ve[2 * (size_t)i] = vir;
+            ovf_ve[2 * (size_t)i + 1] = ep;
+        }
     }
 }
 
@@ -660,23 +626,9 @@ __global__ __launch_bounds__(kBlock) void k_debug_neighbors(PairConst pc, Geom g
     hash[id] = h;
 }
 
-template <typename K>
-void launch_lanes(int lanes, K &&k)
-{
-    switch (lanes) {
-    case 1: k(std::integral_constant<int, 1>{}); break;
-    case 2: k(std::integral_constant<int, 2>{}); break;
-    case 4: k(std::integral_constant<int, 4>{}); break;
-    case 8: k(std::integral_constant<int, 8>{}); break;
-    default: k(std::integral_constant<int, 16>{}); break;
-    }
-}
-
-inline int blocks_for(int64_t threads) { return (int)((threads + kBlock - 1) / kBlock); }
-
 }  // namespace
 
-int force_blocks(int lanes, int n) { return blocks_for((int64_t)n * lanes); }
+int force_partials(int lanes, int n) { return blocks_for((int64_t)n * lanes); }
 
 void launch_nlist(hipStream_t st, bool fp32, int n, Geom g, Soa3c xs, const int *cstart, int *ncnt,
                   uint32_t *nl, void *nlr2, const int *gate)
@@ -697,10 +649,11 @@ void launch_density(hipStream_t st, int lanes, bool fp32, int n, const PairConst
         constexpr int L = decltype(P)::value;
         if (fp32)
             k_density<L, float><<<blocks_for((int64_t)n * L), kBlock, 0, st>>>(
-                pc, g, n, xs, cstart, ncnt, nl, (const float *)nlr2, (float *)rho);
+                pc, g, n, xs, cstart, ncnt, (const float *)nlr2, (float *)rho);
         else
             k_density<L, double><<<blocks_for((int64_t)n * L), kBlock, 0, st>>>(
-                pc, g, n, xs, cstart, ncnt, nl, (const double *)nlr2, (double *)rho);
+                pc, g, n, xs, cstart, ncnt, (const double *)nlr2, (double *)rho);
+    (void)nl;
     });
 }
 
@@ -721,31 +674,38 @@ void launch_phi(hipStream_t st, int lanes, int n, const PairConst &pc, Geom g, S
 void launch_force(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g, Soa3c xs,
                   Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ, const int *cstart,
                   const int *ncnt, const uint32_t *nl, Soa3 vout, Soa3 fout, Soa3 vpred, Soa3 xpred,
-                  double *part, int *status, int initial)
+                  double *part, int *status, int *ovf_count, int *ovf, double *ovf_ve, int initial)
 {
     if (n <= 0) return;
     const bool mt = pc.ntypes > 1;
+    const ForceOut out{vout, fout, vpred, xpred, part, status, ovf_count, ovf, initial};
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
         const int nb = blocks_for((int64_t)n * L);
         if (fp32) {
-            if (mt)
-                k_force<L, true, float><<<nb, kBlock, 0, st>>>(pc, g, n, xs, vh, (const float *)rho, tag,
-                                                               typ, cstart, ncnt, nl, vout, fout, vpred,
-                                                               xpred, part, status, initial);
-            else
-                k_force<L, false, float><<<nb, kBlock, 0, st>>>(pc, g, n, xs, vh, (const float *)rho, tag,
-                                                                typ, cstart, ncnt, nl, vout, fout, vpred,
-                                                                xpred, part, status, initial);
+            if (mt) {
+                k_force<L, true, float><<<nb, kBlock, 0, st>>>(pc, g, n, xs, vh, (const float *)rho, tag, typ,
+                                                               ncnt, nl, out);
+                k_force_overflow<true, float><<<kOverflowBlocks, kBlock, 0, st>>>(
+                    pc, g, xs, vh, (const float *)rho, tag, typ, cstart, ncnt, out, ovf_ve);
+            } else {
+                k_force<L, false, float><<<nb, kBlock, 0, st>>>(pc, g, n, xs, vh, (const float *)rho, tag, typ,
+                                                                ncnt, nl, out);
+                k_force_overflow<false, float><<<kOverflowBlocks, kBlock, 0, st>>>(
+                    pc, g, xs, vh, (const float *)rho, tag, typ, cstart, ncnt, out, ovf_ve);
+            }
         } else {
-            if (mt)
-                k_force<L, true, double><<<nb, kBlock, 0, st>>>(pc, g, n, xs, vh, (const double *)rho,
-                                                                tag, typ, cstart, ncnt, nl, vout, fout,
-                                                                vpred, xpred, part, status, initial);
-            else
-                k_force<L, false, double><<<nb, kBlock, 0, st>>>(pc, g, n, xs, vh, (const double *)rho,
-                                                                 tag, typ, cstart, ncnt, nl, vout, fout,
-                                                                 vpred, xpred, part, status, initial);
+            if (mt) {
+                k_force<L, true, double><<<nb, kBlock, 0, st>>>(pc, g, n, xs, vh, (const double *)rho, tag,
+                                                                typ, ncnt, nl, out);
+                k_force_overflow<true, double><<<kOverflowBlocks, kBlock, 0, st>>>(
+                    pc, g, xs, vh, (const double *)rho, tag, typ, cstart, ncnt, out, ovf_ve);
+            } else {
+                k_force<L, false, double><<<nb, kBlock, 0, st>>>(pc, g, n, xs, vh, (const double *)rho, tag,
+                                                                 typ, ncnt, nl, out);
+                k_force_overflow<false, double><<<kOverflowBlocks, kBlock, 0, st>>>(
+                    pc, g, xs, vh, (const double *)rho, tag, typ, cstart, ncnt, out, ovf_ve);
+            }
         }
     });
 }

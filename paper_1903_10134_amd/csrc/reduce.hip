@@ -9,7 +9,7 @@ namespace mdpd {
 namespace {
 
 constexpr int kRed = 256;
-constexpr int kObs = 8;  // partial slots per block
+constexpr int kObs = 10;  // partial slots per block
 
 inline int blocks_for(int64_t threads) { return (int)((threads + kBlock - 1) / kBlock); }
 
@@ -33,11 +33,16 @@ __device__ __forceinline__ void block_tree(double (*sh)[kRed], double *v)
 template <typename R>
 __global__ __launch_bounds__(kRed) void k_obs_partial(int n, PairConst pc, Soa3c v, const R *rho,
                                                       const uint32_t *tag, const uint8_t *typ,
-                                                      double *part)
+                                                      const int *ncnt, const double *ovf_ve, double *part)
 {
     __shared__ double sh[kObs][kRed];
-    double acc[kObs] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[kObs] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int i = blockIdx.x * kRed + threadIdx.x; i < n; i += gridDim.x * kRed) {
+        const int c = ncnt[i];
+        if ((c & 0xffff) + (c >> 16) > kListCap) {  // list overflowed: force pass wrote its share here
+            acc[8] += ovf_ve[2 * (size_t)i];
+            acc[9] += ovf_ve[2 * (size_t)i + 1];
+        }
         const double r = (double)rho[i];
         const int t = pc.ntypes > 1 ? (int)typ[i] : 0;
         const double B = pc.ntypes > 1 ? pc.tab[64 + t * pc.ntypes + t] : pc.B;
@@ -57,7 +62,8 @@ __global__ __launch_bounds__(kRed) void k_obs_partial(int n, PairConst pc, Soa3c
 }
 
 // Final fixed-order sums: out[0..7] observables partials, out[8] virial,
-// out[9] pair energy.
+// out[9] pair energy (force-pass block partials plus the overflowed
+// particles' shares).
 __global__ __launch_bounds__(kRed) void k_obs_final(int nb, const double *part, int nf,
                                                     const double *fpart, double *out)
 {
@@ -154,20 +160,39 @@ __global__ __launch_bounds__(kBlock) void k_export(int n, Soa3c x, Soa3c v, cons
     if (rho_out) rho_out[id] = (double)rho[i];
 }
 
+// acc[0..2] += scale * (mean fluid rho, virial pressure, mean fluid v_x)
+// from the final sums of k_obs_final.
+__global__ void k_loss_accum(const double *obs, double *acc, double inv_nf, double inv3V, double mass,
+                             double scale)
+{
+    if (threadIdx.x != 0) return;
+    acc[0] += scale * obs[4] * inv_nf;
+    acc[1] += scale * (mass * obs[0] + obs[8]) * inv3V;
+    acc[2] += scale * obs[1] * inv_nf;
+}
+
 }  // namespace
+
+void launch_loss_accum(hipStream_t st, const double *obs16, double *acc, double inv_nf, double inv3V,
+                       double mass, double scale)
+{
+    k_loss_accum<<<1, 64, 0, st>>>(obs16, acc, inv_nf, inv3V, mass, scale);
+}
 
 void launch_observables(hipStream_t st, bool fp32, int n, const PairConst &pc, Soa3c v, const void *rho,
                         const uint32_t *tag, const uint8_t *typ, const double *fpart, int nfpart,
-                        double *out16)
+                        const int *ncnt, const double *ovf_ve, double *out16)
 {
-    // out16: 16 result slots followed by up to 1024 x 8 block partials.
+    // out16: 16 result slots followed by up to 1024 x kObs block partials.
     const int nb = n > 0 ? (blocks_for(n) < 1024 ? blocks_for(n) : 1024) : 0;
     double *part = out16 + 16;
     if (nb > 0) {
         if (fp32)
-            k_obs_partial<float><<<nb, kRed, 0, st>>>(n, pc, v, (const float *)rho, tag, typ, part);
+            k_obs_partial<float><<<nb, kRed, 0, st>>>(n, pc, v, (const float *)rho, tag, typ, ncnt, ovf_ve,
+                                                      part);
         else
-            k_obs_partial<double><<<nb, kRed, 0, st>>>(n, pc, v, (const double *)rho, tag, typ, part);
+            k_obs_partial<double><<<nb, kRed, 0, st>>>(n, pc, v, (const double *)rho, tag, typ, ncnt, ovf_ve,
+                                                       part);
     }
     k_obs_final<<<1, kRed, 0, st>>>(nb, part, nfpart, fpart, out16);
 }

@@ -31,10 +31,11 @@ inline int blocks_for(int64_t threads) { return (int)((threads + kBlock - 1) / k
 // and the others take consecutive slots after it.
 __global__ __launch_bounds__(kBlock) void k_bin(int n, Geom g, Soa3c x, int *__restrict__ key,
                                                 int *__restrict__ slot, int *__restrict__ counts,
-                                                const int *__restrict__ gate)
+                                                const int *__restrict__ gate, int *__restrict__ ovf_count)
 {
     if (gate && *gate == 0) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (ovf_count && i == 0) *ovf_count = 0;  // the force pass of this step refills it
     const int lane = threadIdx.x & 63;
     int c = -1;
     if (i < n) {
@@ -277,11 +278,11 @@ void launch_ingest(hipStream_t st, int64_t n, const double *pos, const double *v
 void launch_sort(hipStream_t st, int n, Geom g, Soa3c xin, Soa3c vin, Soa3c xprev_in,
                  const uint32_t *tag_in, const uint8_t *typ_in, Soa3 xout, Soa3 vout, Soa3 xprev_out,
                  uint32_t *tag_out, uint8_t *typ_out, int *key, int *slot, uint32_t *tmpid, int *counts,
-                 int *cstart, int *bsum, const int *gate)
+                 int *cstart, int *bsum, const int *gate, int *ovf_count)
 {
     const int m = g.ncells;
     const int nb = (m + kScanTile - 1) / kScanTile;
-    if (n > 0) k_bin<<<blocks_for(n), kBlock, 0, st>>>(n, g, xin, key, slot, counts, gate);
+    if (n > 0) k_bin<<<blocks_for(n), kBlock, 0, st>>>(n, g, xin, key, slot, counts, gate, ovf_count);
     k_scan_local<<<nb, kScanThreads, 0, st>>>(m, counts, cstart, bsum, gate);
     k_scan_top<<<1, kScanThreads, 0, st>>>(nb, m, bsum, cstart, gate);
     k_scan_add<<<nb, kScanThreads, 0, st>>>(m, bsum, cstart, gate);

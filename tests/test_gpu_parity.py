@@ -306,3 +306,135 @@ def test_full_size_forces(mdpd, full, precision):
     xtol, vtol = state_tols(precision, w, F_rms)
     assert pdiff(x, st1["x"], w.box) < xtol
     assert np.abs(v - st1["v"]).max() < 2 * vtol
+
+
+# ---------------------------------------------------------------------------
+# Wall treatment (boundary volume fraction + predictor-corrector) and profiles
+# ---------------------------------------------------------------------------
+def small_channel(seed=7):
+    """Channel of the Poiseuille set-up at a size the oracle steps quickly."""
+    return W.channel(Lx=8.0, Ly=6.0, Lz=8.0, wall=2.0, seed=seed, gx=0.05)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_wall_corrector_parity(mdpd, precision):
+    w = small_channel()
+    say("walls", precision, w.n)
+    prec = mdpd.FP64 if precision == "fp64" else mdpd.FP32_FORCES
+    s = mdpd.System(w, precision=prec)
+    o = oracle.System(orc_params(w), w.x, w.v, w.types, w.frozen)
+    total = 0
+    for k in range(12):
+        s.step(1)
+        o.step(1)
+        a, b = s.observables(), o.observables()
+        assert a["ncorr_last"] == b["ncorr_last"], (k, a["ncorr_last"], b["ncorr_last"])
+        total += b["ncorr_last"]
+    st = o.state()
+    x, v, rho = s.state()
+    F_rms = float(np.sqrt(np.mean(np.sum(st["F"] ** 2, axis=1))))
+    if precision == "fp64":
+        assert pdiff(x, st["x"], w.box) < 1e-10
+        assert force_err(s.forces(), st["F"]) < 1e-10
+    else:
+        assert pdiff(x, st["x"], w.box) < 1e-4
+        assert force_err(s.forces(), st["F"]) < 1e-3
+    assert a["ncorr_total"] == b["ncorr_total"] == total
+    assert total > 0, "the case should exercise the corrector"
+
+
+def test_profiles_match_oracle(mdpd):
+    w = small_channel(seed=8)
+    say("profiles")
+    s = mdpd.System(w)
+    o = oracle.System(orc_params(w), w.x, w.v, w.types, w.frozen)
+    s.step(5)
+    o.step(5)
+    for axis in (0, 1):
+        for q in range(6):
+            pa, pb = s.profile(axis, 8, q), o.profile(axis, 8, q)
+            assert np.allclose(pa, pb, rtol=1e-9, atol=1e-10), (axis, q, pa, pb)
+
+
+def test_long_run_statistics_match_oracle(mdpd):
+    """1000 steps of the 6,000-particle case: trajectories decorrelate, so the
+    comparison is statistical -- time-averaged density, temperature and
+    many-body density profiles agree within 1% of their scale."""
+    w = W.bulk(L=10.0, seed=0)
+    say("1000-step statistics", w.n)
+    s = mdpd.System(w, precision=mdpd.FP32_FORCES)
+    o = oracle.System(orc_params(w, search=1), w.x, w.v)
+    acc = {"gpu": [], "orc": []}
+    for k in range(100):
+        s.step(10)
+        o.step(10)
+        if k >= 50:
+            for tag, sysm in (("gpu", s), ("orc", o)):
+                acc[tag].append([sysm.profile(0, 5, 0), sysm.profile(0, 5, 4), sysm.profile(0, 5, 5)])
+    g = np.mean(np.array(acc["gpu"]), axis=0)
+    r = np.mean(np.array(acc["orc"]), axis=0)
+    assert np.all(np.abs(g[0] - r[0]) < 0.01 * 6.0), (g[0], r[0])      # number density vs 6
+    assert np.all(np.abs(g[1] - r[1]) < 0.01 * 1.0 * 3), (g[1], r[1])  # kT vs 1 (3x for 5-bin noise)
+    assert np.all(np.abs(g[2] - r[2]) < 0.01 * r[2].mean() * 3), (g[2], r[2])
+    a, b = s.observables(), o.observables()
+    assert abs(a["kT"] - b["kT"]) < 0.05
+
+
+@pytest.mark.parametrize("case,prec", [("bulk_L10_n6000", "fp32"), ("dense_cluster", "fp64"),
+                                       ("small_channel", "fp64"), ("small_channel", "fp32")])
+def test_checkpoint_resume_bitwise(mdpd, case, prec):
+    """A checkpoint loaded into a fresh system continues bit for bit: state,
+    forces, observables and neighbour sets after more steps."""
+    w = small_channel() if case == "small_channel" else CASES[case]
+    p = mdpd.FP32_FORCES if prec == "fp32" else mdpd.FP64
+    say("checkpoint", case, prec)
+    a = mdpd.System(w, precision=p)
+    a.step(7)
+    buf = a.save_checkpoint()
+    obs0 = a.observables()
+    a.step(9)
+    b = mdpd.System(w, precision=p)  # same parameters, fresh state at step 0
+    b.load_checkpoint(buf)
+    assert b.observables() == obs0
+    b.step(9)
+    for u, v in zip(a.state(), b.state()):
+        assert np.array_equal(u, v)
+    assert np.array_equal(a.forces(), b.forces())
+    assert a.observables() == b.observables()
+    for cut in (w.rd, w.rc):
+        ca, ha = a.neighbors(cut)
+        cb, hb = b.neighbors(cut)
+        assert np.array_equal(ca, cb) and np.array_equal(ha, hb)
+    a.close()
+    b.close()
+
+
+def test_checkpoint_rejects_other_systems(mdpd):
+    w = CASES["bulk_L10_n6000"]
+    a = mdpd.System(w)
+    buf = a.save_checkpoint()
+    c = mdpd.System(w, precision=mdpd.FP32_FORCES)  # other parameters
+    with pytest.raises(mdpd.MdpdError):
+        c.load_checkpoint(buf)
+    with pytest.raises(mdpd.MdpdError):
+        a.load_checkpoint(buf[:100])
+    bad = buf.copy()
+    bad[0] ^= 1
+    with pytest.raises(mdpd.MdpdError):
+        a.load_checkpoint(bad)
+    a.load_checkpoint(buf)  # the original still loads
+    a.close()
+    c.close()
+
+
+def test_observables_deterministic_with_list_overflow(mdpd):
+    """dense_cluster overflows the neighbour-list rows; the energy and virial
+    shares of those particles are reduced in a fixed order."""
+    w = CASES["dense_cluster"]
+    outs = []
+    for _ in range(2):
+        s = mdpd.System(w, precision=mdpd.FP32_FORCES)
+        s.step(3)
+        outs.append(s.observables())
+        s.close()
+    assert outs[0] == outs[1]
