@@ -126,6 +126,24 @@ mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, cons
                         const int32_t *type, const uint8_t *frozen, int32_t mem_kind,
                         void *stream, mdpd_system **out);
 
+/* Create a batch of nrep independent replicas (separate periodic boxes, each
+ * with its own parameters, noise seed and particle count) that every call
+ * advances together: each pass of the timestep is one launch over all
+ * replicas.  Replica r owns the particles offsets[r] .. offsets[r+1]-1 of the
+ * input arrays (offsets: nrep + 1 entries, offsets[0] = 0, non-decreasing;
+ * offsets[nrep] < 2^30); inside a replica the particle ids are 0, 1, ...
+ * from offsets[r], so that replica r evolves exactly, bit for bit, as a
+ * system created alone from its own slice of the arrays with params[r].
+ * All replicas need the same precision and wall model.  Per-particle outputs
+ * (mdpd_get_state, mdpd_debug_*) come back in input order over the whole
+ * batch; observables per replica come from mdpd_read_replica_observables.
+ * mdpd_read_observables, mdpd_read_profile and the adjoint need nrep = 1.
+ * Errors as for mdpd_create. */
+mdpd_status mdpd_create_batch(int32_t nrep, const mdpd_params *params, const int64_t *offsets,
+                              const double *pos, const double *vel, const int32_t *type,
+                              const uint8_t *frozen, int32_t mem_kind, void *stream,
+                              mdpd_system **out);
+
 /* Advance nsteps >= 0 timesteps in the order of Alg. 1: half kick and drift
  * x(t+dt), [wall: phi and corrector], rho for all particles, forces
  * f(t+dt) with noise step = the new step number, v(t+dt).  Synchronises the
@@ -133,8 +151,14 @@ mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, cons
  * velocity became non-finite (the state is then undefined). */
 mdpd_status mdpd_step(mdpd_system *s, int64_t nsteps);
 
-/* Observables of the current state (see mdpd_observables). */
+/* Observables of the current state (see mdpd_observables); MDPD_E_STATE
+ * for a batch of more than one replica. */
 mdpd_status mdpd_read_observables(mdpd_system *s, mdpd_observables *out);
+
+/* Observables of replicas first .. first+count-1 of a batch into out[count].
+ * The wall-correction counters are totals over the batch. */
+mdpd_status mdpd_read_replica_observables(mdpd_system *s, int32_t first, int32_t count,
+                                          mdpd_observables *out);
 
 /* Profile of fluid particles in nbins (1..4096) equal bins of L_axis along
  * axis (0..2).  quantity 0: number density; 1..3: mean velocity x, y, z;
@@ -173,6 +197,23 @@ mdpd_status mdpd_read_kernel_timing(mdpd_system *s, int32_t kernel, double *tota
  * and wall fraction) or 2 (force).  Results do not depend on pass 0's
  * setting; passes 1 and 2 change only the summation order. */
 mdpd_status mdpd_set_lanes(mdpd_system *s, int32_t pass, int32_t lanes);
+
+/* Graph mode (enable = 1): mdpd_step replays a HIP graph of two captured
+ * timesteps instead of launching each kernel from the host (an odd last step
+ * runs eagerly).  Results are bit for bit those of eager stepping.  The graph
+ * is captured on first use and again after the lane split or the buffer
+ * parity changed; kernel timing does not see replayed steps.  enable = 0
+ * releases the graph. */
+mdpd_status mdpd_set_graph(mdpd_system *s, int32_t enable);
+
+/* Autotuner: times `steps` >= 1 timesteps (HIP events around each launch on
+ * the system's stream) for every lane count of the density pass and then of
+ * the force pass, keeps the fastest, and restores the state it started from
+ * (the trial steps leave no trace; the result only changes summation
+ * orders).  The choice is cached for the process per (n, cells, replicas,
+ * precision, type count, walls) and reused without timing.  lanes_out
+ * (nullable) receives the lanes of passes 0..2. */
+mdpd_status mdpd_autotune(mdpd_system *s, int32_t steps, int32_t *lanes_out);
 
 /* Checkpoint and bitwise resume.  A checkpoint holds the complete dynamical
  * state after the last completed step (positions, velocities, forces, the

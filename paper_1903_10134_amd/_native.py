@@ -63,6 +63,11 @@ _SIGS = {
     "mdpd_create": ([ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                      ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int32),
+    "mdpd_create_batch": ([ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                           ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int32),
+    "mdpd_read_replica_observables": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p],
+                                      ctypes.c_int32),
     "mdpd_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int32),
     "mdpd_read_observables": ([ctypes.c_void_p, ctypes.POINTER(Observables)], ctypes.c_int32),
     "mdpd_read_profile": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -76,6 +81,8 @@ _SIGS = {
     "mdpd_read_kernel_timing": ([ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "mdpd_set_lanes": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
+    "mdpd_autotune": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p], ctypes.c_int32),
+    "mdpd_set_graph": ([ctypes.c_void_p, ctypes.c_int32], ctypes.c_int32),
     "mdpd_checkpoint_size": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
     "mdpd_save_checkpoint": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32],
                              ctypes.c_int32),
@@ -150,8 +157,8 @@ def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=
     return p
 
 
-def mdpd_create(params: Params, pos, vel, types, frozen, stream=None):
-    """Create a system; host numpy arrays or torch CUDA tensors (all on one side)."""
+def _inputs(pos, vel, types, frozen):
+    """Contiguous inputs, their pointers and memory kind (host numpy or CUDA tensors)."""
     if _is_torch(pos):
         import torch
         n = int(pos.shape[0])
@@ -171,14 +178,37 @@ def mdpd_create(params: Params, pos, vel, types, frozen, stream=None):
         keep = (pos, vel, types, frozen)
         ptrs = [a.ctypes.data for a in keep]
         mem = MEM_HOST
+    return n, keep, ptrs, mem
+
+
+def _stream(stream):
     if stream is None:
-        st = None
-    elif isinstance(stream, int):
-        st = stream
-    else:
-        st = int(stream.cuda_stream)
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def mdpd_create(params: Params, pos, vel, types, frozen, stream=None):
+    """Create a system; host numpy arrays or torch CUDA tensors (all on one side)."""
+    n, keep, ptrs, mem = _inputs(pos, vel, types, frozen)
     h = ctypes.c_void_p()
-    _check(lib().mdpd_create(ctypes.byref(params), n, *ptrs, mem, st, ctypes.byref(h)))
+    _check(lib().mdpd_create(ctypes.byref(params), n, *ptrs, mem, _stream(stream), ctypes.byref(h)))
+    del keep
+    return h.value
+
+
+def mdpd_create_batch(params_list, offsets, pos, vel, types, frozen, stream=None):
+    """Create a batch of replicas: params_list[r] and particles offsets[r] ..
+    offsets[r+1]-1 of the concatenated arrays."""
+    nrep = len(params_list)
+    arr = (Params * nrep)(*params_list)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if off.shape != (nrep + 1,):
+        raise ValueError("offsets must have nrep + 1 entries")
+    n, keep, ptrs, mem = _inputs(pos, vel, types, frozen)
+    h = ctypes.c_void_p()
+    _check(lib().mdpd_create_batch(nrep, arr, off.ctypes.data, *ptrs, mem, _stream(stream), ctypes.byref(h)))
     del keep
     return h.value
 
@@ -187,12 +217,22 @@ def mdpd_step(h, nsteps: int) -> None:
     _check(lib().mdpd_step(h, int(nsteps)))
 
 
-def mdpd_read_observables(h) -> dict:
-    o = Observables()
-    _check(lib().mdpd_read_observables(h, ctypes.byref(o)))
+def _obs_dict(o) -> dict:
     d = {k: getattr(o, k) for k, _ in Observables._fields_ if k != "momentum"}
     d["momentum"] = tuple(o.momentum)
     return d
+
+
+def mdpd_read_observables(h) -> dict:
+    o = Observables()
+    _check(lib().mdpd_read_observables(h, ctypes.byref(o)))
+    return _obs_dict(o)
+
+
+def mdpd_read_replica_observables(h, first: int, count: int) -> list:
+    arr = (Observables * max(count, 1))()
+    _check(lib().mdpd_read_replica_observables(h, int(first), int(count), arr))
+    return [_obs_dict(arr[k]) for k in range(count)]
 
 
 def mdpd_read_profile(h, axis: int, nbins: int, quantity: int):
@@ -297,6 +337,18 @@ def mdpd_backward(h, w, ntypes: int, n: int, device=None):
     return {"dA": tabs[0], "dB": tabs[1], "dgamma": tabs[2], "dx0": dx, "dv0": dv}
 
 
+def mdpd_set_graph(h, enable: bool) -> None:
+    _check(lib().mdpd_set_graph(h, 1 if enable else 0))
+
+
+def mdpd_autotune(h, steps: int = 5):
+    """Pick the fastest lanes per particle for the density and force passes
+    (state unchanged); returns the lanes of passes 0..2."""
+    out = (ctypes.c_int32 * 3)()
+    _check(lib().mdpd_autotune(h, int(steps), out))
+    return tuple(out)
+
+
 def mdpd_destroy(h) -> None:
     if h:
         lib().mdpd_destroy(h)
@@ -353,11 +405,78 @@ class System:
     def backward(self, w, device=None):
         return mdpd_backward(self.h, w, self.params.ntypes, self.n, device=device)
 
+    def autotune(self, steps=5):
+        return mdpd_autotune(self.h, steps)
+
+    def set_graph(self, enable=True):
+        mdpd_set_graph(self.h, enable)
+
     def save_checkpoint(self):
         return mdpd_save_checkpoint(self.h)
 
     def load_checkpoint(self, buf):
         mdpd_load_checkpoint(self.h, buf)
+
+    def close(self):
+        if self.h:
+            mdpd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owning wrapper around a batch of replicas (mdpd_create_batch)."""
+
+    def __init__(self, workloads, precision=FP64, stream=None, device_inputs=False):
+        self.params = [make_params(**w.param_kwargs(), precision=precision) for w in workloads]
+        self.sizes = [int(w.x.shape[0]) for w in workloads]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        x = np.concatenate([w.x for w in workloads]) if workloads else np.zeros((0, 3))
+        v = np.concatenate([w.v for w in workloads]) if workloads else np.zeros((0, 3))
+        t = np.concatenate([np.asarray(w.types, np.int32) for w in workloads]) if workloads else np.zeros(0)
+        f = np.concatenate([np.asarray(w.frozen, np.uint8) for w in workloads]) if workloads else np.zeros(0)
+        self.n = int(self.offsets[-1])
+        if device_inputs:
+            import torch
+            dev = torch.device("cuda")
+            x, v = torch.as_tensor(x, device=dev), torch.as_tensor(v, device=dev)
+            t = torch.as_tensor(t.astype(np.int32), device=dev)
+            f = torch.as_tensor(f.astype(np.uint8), device=dev)
+        self.h = None
+        self.h = mdpd_create_batch(self.params, self.offsets, x, v, t, f, stream=stream)
+
+    @property
+    def nrep(self):
+        return len(self.params)
+
+    def step(self, nsteps: int = 1):
+        mdpd_step(self.h, nsteps)
+
+    def observables(self, first=0, count=None):
+        return mdpd_read_replica_observables(self.h, first, self.nrep - first if count is None else count)
+
+    def state(self, with_rho=True):
+        return mdpd_get_state(self.h, self.n, with_rho)
+
+    def neighbors(self, cutoff):
+        return mdpd_debug_neighbors(self.h, self.n, cutoff)
+
+    def forces(self):
+        return mdpd_debug_forces(self.h, self.n)
+
+    def set_lanes(self, pass_, lanes):
+        mdpd_set_lanes(self.h, pass_, lanes)
+
+    def autotune(self, steps=5):
+        return mdpd_autotune(self.h, steps)
+
+    def set_graph(self, enable=True):
+        mdpd_set_graph(self.h, enable)
 
     def close(self):
         if self.h:

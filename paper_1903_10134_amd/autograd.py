@@ -35,6 +35,8 @@ class TrajectoryLoss(torch.autograd.Function):
         loss = sys_.forward_record(spec["nsteps"], every=spec["every"], average=spec["average"])
         ctx.sys = sys_
         ctx.dev = dev
+        ctx.vdev = v0.device
+        ctx.tdev = [t.device if torch.is_tensor(t) else torch.device("cpu") for t in (A, B, gamma)]
         ctx.tshape = tuple(np.atleast_2d(_host(A)).shape)
         return torch.as_tensor(loss, dtype=torch.float64, device=dev)
 
@@ -46,9 +48,9 @@ class TrajectoryLoss(torch.autograd.Function):
         if not torch.is_tensor(dx0):
             dx0 = torch.from_numpy(dx0)
             dv0 = torch.from_numpy(dv0)
-        tab = [torch.as_tensor(g[k].reshape(ctx.tshape), dtype=torch.float64, device=ctx.dev)
-               for k in ("dA", "dB", "dgamma")]
-        return (dx0.to(ctx.dev), dv0.to(ctx.dev), *tab, None)
+        tab = [torch.as_tensor(g[k].reshape(ctx.tshape), dtype=torch.float64, device=d)
+               for k, d in zip(("dA", "dB", "dgamma"), ctx.tdev)]
+        return (dx0.to(ctx.dev), dv0.to(ctx.vdev), *tab, None)
 
 
 def trajectory_loss(x0, v0, A, B, gamma, types, frozen, box, nsteps, every=10, average=True, rc=1.0,

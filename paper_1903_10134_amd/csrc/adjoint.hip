@@ -70,20 +70,24 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(int n, AdjConst ac, Soa3c v
 }
 
 template <int P, bool MT, typename R>
-__global__ __launch_bounds__(kBlock) void k_adj_force(PairConst pc, Geom g, AdjConst ac, int n, Soa3c xs,
+__global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, AdjConst ac, int n, Soa3c xs,
                                                      Soa3c u, const R *__restrict__ rho,
                                                      const uint32_t *__restrict__ tag,
                                                      const uint8_t *__restrict__ typ,
-                                                     const int *__restrict__ cstart,
+                                                     const int *__restrict__ cstart_all,
                                                      const int *__restrict__ ncnt,
                                                      const uint32_t *__restrict__ nl, Soa3c fb, Soa3 X, Soa3 U,
                                                      double *__restrict__ rhoA, double *__restrict__ gp)
 {
     constexpr int TM = MT ? MDPD_ADJ_MAX_TYPES : 1;
-    const int t = xcd_block() * kBlock + threadIdx.x;
-    const int i = t / P;
-    const int sub = t & (P - 1);
-    if (i >= n) return;  // uniform over the P lanes of particle i
+    const BlockRep br = block_rep<P>(Rp, xcd_block());
+    const int i = br.i0 + (int)threadIdx.x / P;
+    const int sub = threadIdx.x & (P - 1);
+    if (i >= br.i1) return;  // uniform over the P lanes of particle i
+    PairConst pc = cload(Rp.pc, br.r);
+    set_noise_keys(pc, step);
+    const Geom g = cload(Rp.geom, br.r);
+    const int *__restrict__ cstart = cstart_all + cload(Rp.cell_off, br.r);
     const uint32_t tgi = tag[i];
     const bool fzi = (tgi & kFrozenBit) != 0;
     const uint32_t idi = tgi & kIdMask;
@@ -187,16 +191,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_force(PairConst pc, Geom g, AdjC
 }
 
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_adj_density(PairConst pc, Geom g, int n, Soa3c xs,
-                                                       const int *__restrict__ cstart,
+__global__ __launch_bounds__(kBlock) void k_adj_density(Reps Rp, Soa3c xs, const int *__restrict__ cstart_all,
                                                        const int *__restrict__ ncnt,
                                                        const uint32_t *__restrict__ nl,
                                                        const double *__restrict__ rhoA, Soa3 X)
 {
-    const int t = xcd_block() * kBlock + threadIdx.x;
-    const int i = t / P;
-    const int sub = t & (P - 1);
-    if (i >= n) return;
+    const BlockRep br = block_rep<P>(Rp, xcd_block());
+    const int i = br.i0 + (int)threadIdx.x / P;
+    const int sub = threadIdx.x & (P - 1);
+    if (i >= br.i1) return;
+    const PairConst pc = cload(Rp.pc, br.r);
+    const Geom g = cload(Rp.geom, br.r);
+    const int *__restrict__ cstart = cstart_all + cload(Rp.cell_off, br.r);
     const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
     const double rai = rhoA[i];
     const double k2 = -2.0 * pc.wrho * pc.inv_rd;  // w_rho'(r) = k2 (1 - r / r_d)
@@ -314,43 +320,43 @@ void launch_adj_seed(hipStream_t st, int n, const AdjConst &ac, Soa3c v, const u
     if (n > 0) k_adj_seed<<<blocks_for(n), kBlock, 0, st>>>(n, ac, v, tag, U, fb, rhoA);
 }
 
-void launch_adj_force(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g,
+void launch_adj_force(hipStream_t st, int lanes, bool fp32, bool mt, int n, const Reps &R, uint32_t step,
                       const AdjConst &ac, Soa3c xs, Soa3c u, const void *rho, const uint32_t *tag,
                       const uint8_t *typ, const int *cstart, const int *ncnt, const uint32_t *nl, Soa3c fb,
                       Soa3 X, Soa3 U, double *rhoA, double *gp)
 {
     if (n <= 0) return;
-    const bool mt = pc.ntypes > 1;
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
-        const int nb = blocks_for((int64_t)n * L);
+        const int nb = R.nblk[lanes_index(L)];
         if (fp32) {
             if (mt)
-                k_adj_force<L, true, float><<<nb, kBlock, 0, st>>>(pc, g, ac, n, xs, u, (const float *)rho, tag,
+                k_adj_force<L, true, float><<<nb, kBlock, 0, st>>>(R, step, ac, n, xs, u, (const float *)rho, tag,
                                                                    typ, cstart, ncnt, nl, fb, X, U, rhoA, gp);
             else
-                k_adj_force<L, false, float><<<nb, kBlock, 0, st>>>(pc, g, ac, n, xs, u, (const float *)rho, tag,
-                                                                    typ, cstart, ncnt, nl, fb, X, U, rhoA, gp);
+                k_adj_force<L, false, float><<<nb, kBlock, 0, st>>>(R, step, ac, n, xs, u, (const float *)rho,
+                                                                    tag, typ, cstart, ncnt, nl, fb, X, U, rhoA,
+                                                                    gp);
         } else {
             if (mt)
-                k_adj_force<L, true, double><<<nb, kBlock, 0, st>>>(pc, g, ac, n, xs, u, (const double *)rho,
+                k_adj_force<L, true, double><<<nb, kBlock, 0, st>>>(R, step, ac, n, xs, u, (const double *)rho,
                                                                     tag, typ, cstart, ncnt, nl, fb, X, U, rhoA,
                                                                     gp);
             else
-                k_adj_force<L, false, double><<<nb, kBlock, 0, st>>>(pc, g, ac, n, xs, u, (const double *)rho,
+                k_adj_force<L, false, double><<<nb, kBlock, 0, st>>>(R, step, ac, n, xs, u, (const double *)rho,
                                                                      tag, typ, cstart, ncnt, nl, fb, X, U, rhoA,
                                                                      gp);
         }
     });
 }
 
-void launch_adj_density(hipStream_t st, int lanes, int n, const PairConst &pc, Geom g, Soa3c xs,
-                        const int *cstart, const int *ncnt, const uint32_t *nl, const double *rhoA, Soa3 X)
+void launch_adj_density(hipStream_t st, int lanes, const Reps &R, Soa3c xs, const int *cstart, const int *ncnt,
+                        const uint32_t *nl, const double *rhoA, Soa3 X)
 {
-    if (n <= 0) return;
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
-        k_adj_density<L><<<blocks_for((int64_t)n * L), kBlock, 0, st>>>(pc, g, n, xs, cstart, ncnt, nl, rhoA, X);
+        const int nb = R.nblk[lanes_index(L)];
+        if (nb > 0) k_adj_density<L><<<nb, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, rhoA, X);
     });
 }
 

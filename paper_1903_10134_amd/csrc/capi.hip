@@ -5,7 +5,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "mdpd.h"
@@ -57,7 +60,7 @@ struct AdjRec {
     char *ck = nullptr;  // nck checkpoints of ck_bytes each
     uint64_t ck_bytes = 0;
     int nck = 0;
-    std::vector<int> ck_nfpart;
+    std::vector<int> ck_lanes;  // force lane count of each checkpoint's partials
     char *tape = nullptr;  // ntape entries of tape_bytes each
     uint64_t tape_bytes = 0;
     int ntape = 0;
@@ -73,8 +76,14 @@ struct mdpd_system {
     bool fp32 = false;
     bool walls = false;
     int lanes[3] = {4, 4, 4};  // neighbour list, density (and phi), force
-    Geom g{};
-    PairConst pc{};
+    // replicas (a single system is one replica)
+    int nrep = 1;
+    bool mt = false;  // some replica has more than one type
+    std::vector<mdpd_params> params;
+    std::vector<Geom> geoms;
+    std::vector<PairConst> pcs;
+    std::vector<int> cell_off, part_off, blk_off;  // host copies of the tables in R
+    Reps R{};
     int cur = 0;
     int64_t step = 0;
 
@@ -88,15 +97,16 @@ struct mdpd_system {
     void *nlr2 = nullptr;
     uint32_t *tmpid = nullptr;
     double *fpart = nullptr;
-    int nfpart = 0;       // capacity of fpart in blocks
-    int nfpart_used = 0;  // blocks written by the last force launch
+    int force_lanes_used = 4;  // lane count of the last force launch (its partials layout)
     int *status = nullptr;
+    uint32_t *dstep = nullptr;  // noise step of the current force evaluation (advanced by the main sort)
     int *ovf = nullptr;        // [0]: overflow count, [1..n]: queued slots
     double *ovf_ve = nullptr;  // per slot: virial, pair energy of overflowed particles
     int *corr = nullptr;  // [0]: corrections this step, [1..n]: flags
     unsigned long long *ncorr_total = nullptr;
     double *tab = nullptr;
-    double *obs = nullptr;
+    double *obs = nullptr;       // 16 result slots per replica
+    double *obs_part = nullptr;  // block partials of the observables
     double *io = nullptr;   // n x 3 staging for exports and host inputs
     double *io2 = nullptr;  // second n x 3 staging
     double *work = nullptr;
@@ -106,11 +116,72 @@ struct mdpd_system {
     std::vector<void *> allocs;
     AdjRec adj;
 
+    // Graph mode: two timesteps captured once into a HIP graph and replayed
+    // (buffers alternate every step, so a pair of steps ends where it began).
+    bool use_graph = false;
+    hipStream_t cap_st = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_cur = -1;
+    int graph_lanes[3] = {0, 0, 0};
+
     ~mdpd_system()
     {
+        drop_graph();
+        if (cap_st) (void)hipStreamDestroy(cap_st);
         for (auto &pl : pool)
             for (auto e : pl.ev) (void)hipEventDestroy(e);
         for (void *a : allocs) (void)hipFree(a);
+    }
+
+    void drop_graph()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        graph_cur = -1;
+    }
+
+    // Capture two timesteps (device work only: every decision inside a step
+    // is taken on the device) on a private stream.
+    hipError_t capture_pair()
+    {
+        drop_graph();
+        hipError_t e = hipSuccess;
+        if (!cap_st) e = hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        hipStream_t user = st;
+        const bool tm = timing;
+        const int cur0 = cur;
+        st = cap_st;
+        timing = false;
+        e = hipStreamBeginCapture(cap_st, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int k = 0; k < 2; ++k) {
+                sort_predicted();
+                evaluate(0, 0);
+            }
+            e = hipStreamEndCapture(cap_st, &graph);
+        }
+        st = user;
+        timing = tm;
+        if (e == hipSuccess && cur != cur0) e = hipErrorInvalidValue;  // cannot happen: buffers alternate
+        if (e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph();
+            cur = cur0;
+            return e;
+        }
+        graph_cur = cur;
+        for (int k = 0; k < 3; ++k) graph_lanes[k] = lanes[k];
+        return hipSuccess;
+    }
+
+    bool graph_valid() const
+    {
+        return gexec && graph_cur == cur && graph_lanes[0] == lanes[0] && graph_lanes[1] == lanes[1] &&
+               graph_lanes[2] == lanes[2];
     }
 
     // Free one allocation made by alloc() (NULL is ignored).
@@ -173,18 +244,6 @@ struct mdpd_system {
         pl.used += 2;
     }
 
-    void set_step_keys(uint32_t stepno)
-    {
-        const uint32_t k0 = p.seed, k1 = stepno;
-        const uint32_t ks[3] = {k0, k1, 0x1BD11BDAu ^ k0 ^ k1};
-        pc.ks0 = ks[0];
-        pc.ks1 = ks[1];
-        for (uint32_t s = 1; s <= 5; ++s) {
-            pc.inj0[s - 1] = ks[s % 3];
-            pc.inj1[s - 1] = ks[(s + 1) % 3] + s;
-        }
-    }
-
     Soa3c xprev_view() const { return walls ? cview(xprev) : Soa3c{nullptr, nullptr, nullptr}; }
 
     // Sort predicted state (xpred, vpred, tag[cur], typ[cur]) into the other
@@ -193,43 +252,53 @@ struct mdpd_system {
     {
         const int o = 1 - cur;
         tic(0);
-        launch_sort(st, n, g, cview(xpred), cview(vpred), walls ? cview(xs[cur]) : Soa3c{nullptr, nullptr, nullptr},
+        launch_sort(st, n, R, cview(xpred), cview(vpred), walls ? cview(xs[cur]) : Soa3c{nullptr, nullptr, nullptr},
                     tag[cur], typ[cur], xs[o], vh[o], xprev, tag[o], typ[o], key, slot, tmpid, counts,
-                    cstart, bsum, nullptr, ovf);
+                    cstart, bsum, nullptr, ovf, dstep);
         toc(0);
         cur = o;
     }
 
+    // Advance without synchronising (the caller checks the status word).
+    void advance(int64_t nsteps)
+    {
+        for (int64_t k = 0; k < nsteps; ++k) {
+            step += 1;
+            sort_predicted();
+            evaluate((uint32_t)step, 0);
+        }
+    }
+
     void evaluate(uint32_t stepno, int initial)
     {
-        set_step_keys(stepno);
         tic(1);
-        launch_nlist(st, fp32, n, g, cview(xs[cur]), cstart, ncnt, nl, nlr2, nullptr);
+        launch_nlist(st, fp32, R, cview(xs[cur]), cstart, ncnt, nl, nlr2, nullptr);
         toc(1);
         if (walls && !initial) {
             launch_zero_int(st, corr, 1);
             tic(4);
-            launch_phi(st, lanes[1], n, pc, g, cview(xs[cur]), cview(xprev), xs[cur], vh[cur], tag[cur],
-                       cstart, ncnt, nl, corr, ncorr_total);
+            launch_phi(st, lanes[1], n, R, cview(xs[cur]), cview(xprev), xs[cur], vh[cur], tag[cur], cstart,
+                       ncnt, nl, corr, ncorr_total);
             toc(4);
             // re-sort and re-list only if a particle was moved back
             const int o = 1 - cur;
             tic(0);
-            launch_sort(st, n, g, cview(xs[cur]), cview(vh[cur]), Soa3c{nullptr, nullptr, nullptr}, tag[cur],
+            launch_sort(st, n, R, cview(xs[cur]), cview(vh[cur]), Soa3c{nullptr, nullptr, nullptr}, tag[cur],
                         typ[cur], xs[o], vh[o], Soa3{nullptr, nullptr, nullptr}, tag[o], typ[o], key, slot,
-                        tmpid, counts, cstart, bsum, corr, nullptr);
+                        tmpid, counts, cstart, bsum, corr, nullptr, nullptr);
             toc(0);
             cur = o;
             tic(1);
-            launch_nlist(st, fp32, n, g, cview(xs[cur]), cstart, ncnt, nl, nlr2, corr);
+            launch_nlist(st, fp32, R, cview(xs[cur]), cstart, ncnt, nl, nlr2, corr);
             toc(1);
         }
         tic(2);
-        launch_density(st, lanes[1], fp32, n, pc, g, cview(xs[cur]), cstart, ncnt, nl, nlr2, rho);
+        launch_density(st, lanes[1], fp32, R, cview(xs[cur]), cstart, ncnt, nlr2, rho);
         toc(2);
-        nfpart_used = n > 0 ? force_partials(lanes[2], n) : 0;
+        force_lanes_used = lanes[2];
         tic(3);
-        launch_force(st, lanes[2], fp32, n, pc, g, cview(xs[cur]), cview(vh[cur]), rho, tag[cur], typ[cur],
+        (void)stepno;  // the device word dstep holds it
+        launch_force(st, lanes[2], fp32, mt, R, dstep, cview(xs[cur]), cview(vh[cur]), rho, tag[cur], typ[cur],
                      cstart, ncnt, nl, v, F, vpred, xpred, fpart, status, ovf, ovf + 1, ovf_ve, initial);
         toc(3);
     }
@@ -318,31 +387,15 @@ void mdpd_destroy(mdpd_system *s)
     delete s;
 }
 
-mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, const double *vel,
-                        const int32_t *type, const uint8_t *frozen, int32_t mem_kind, void *stream,
-                        mdpd_system **out)
+}  // extern "C"
+
+namespace {
+
+// Pair constants of one replica (device table entry; noise keys are set per
+// launch from seed and step).
+PairConst make_pair_const(const mdpd_params *p, const double *tab)
 {
-    if (!out) return fail(MDPD_E_INVALID, "out is NULL");
-    *out = nullptr;
-    mdpd_status rc = validate(p, n);
-    if (rc) return rc;
-    if (n > 0 && (!pos || !vel || !type || !frozen)) return fail(MDPD_E_INVALID, "NULL particle array");
-    if (mem_kind != MDPD_MEM_HOST && mem_kind != MDPD_MEM_DEVICE)
-        return fail(MDPD_E_INVALID, "unknown mem_kind %d", mem_kind);
-    Geom g;
-    rc = make_geom(p, &g);
-    if (rc) return rc;
-
-    mdpd_system *s = new mdpd_system();
-    s->p = *p;
-    s->st = (hipStream_t)stream;
-    s->n = (int)n;
-    s->g = g;
-    s->fp32 = p->precision == MDPD_FP32_FORCES;
-    s->walls = p->wall_model == MDPD_WALL_BVF;
-
-    // pair constants
-    PairConst &pc = s->pc;
+    PairConst pc{};
     for (int a = 0; a < 3; ++a) {
         pc.L[a] = p->box[a];
         pc.invL[a] = 1.0 / p->box[a];
@@ -364,10 +417,88 @@ mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, cons
     pc.gamma = p->gamma[0];
     pc.sig = sqrt(2.0 * p->gamma[0] * p->kT) * rdt;
     pc.Arc2 = 0.5 * p->A[0] * p->rc;
+    pc.tab = tab;
+    pc.seed = p->seed;
+    return pc;
+}
+
+// Type-pair planes of one replica: A | B | gamma | sig | A r_c / 2.
+void fill_pair_table(const mdpd_params *p, double *h)
+{
+    const double rdt = 1.0 / sqrt(p->dt);
+    for (int k = 0; k < 320; ++k) h[k] = 0.0;
+    for (int k = 0; k < p->ntypes * p->ntypes; ++k) {
+        h[k] = p->A[k];
+        h[64 + k] = p->B[k];
+        h[128 + k] = p->gamma[k];
+        h[192 + k] = sqrt(2.0 * p->gamma[k] * p->kT) * rdt;
+        h[256 + k] = 0.5 * p->A[k] * p->rc;
+    }
+}
+
+mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offsets, const double *pos,
+                        const double *vel, const int32_t *type, const uint8_t *frozen, int32_t mem_kind,
+                        void *stream, mdpd_system **out)
+{
+    if (!out) return fail(MDPD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (nrep < 1 || nrep > 65536) return fail(MDPD_E_INVALID, "nrep = %d not in 1..65536", nrep);
+    if (!ps || !offsets) return fail(MDPD_E_INVALID, "params or offsets is NULL");
+    if (offsets[0] != 0) return fail(MDPD_E_INVALID, "offsets[0] must be 0");
+    for (int r = 0; r < nrep; ++r) {
+        if (offsets[r + 1] < offsets[r]) return fail(MDPD_E_INVALID, "offsets must be non-decreasing");
+        mdpd_status rc = validate(&ps[r], offsets[r + 1] - offsets[r]);
+        if (rc) return rc;
+        if (ps[r].precision != ps[0].precision || ps[r].wall_model != ps[0].wall_model)
+            return fail(MDPD_E_INVALID, "all replicas need the same precision and wall model");
+    }
+    const int64_t n = offsets[nrep];
+    if (n >= (int64_t)1 << 30) return fail(MDPD_E_INVALID, "n = %lld out of range", (long long)n);
+    if (n > 0 && (!pos || !vel || !type || !frozen)) return fail(MDPD_E_INVALID, "NULL particle array");
+    if (mem_kind != MDPD_MEM_HOST && mem_kind != MDPD_MEM_DEVICE)
+        return fail(MDPD_E_INVALID, "unknown mem_kind %d", mem_kind);
+
+    mdpd_system *s = new mdpd_system();
+    s->p = ps[0];
+    s->st = (hipStream_t)stream;
+    s->n = (int)n;
+    s->nrep = nrep;
+    s->fp32 = ps[0].precision == MDPD_FP32_FORCES;
+    s->walls = ps[0].wall_model == MDPD_WALL_BVF;
+    s->params.assign(ps, ps + nrep);
+    s->geoms.resize(nrep);
+    s->cell_off.assign(nrep + 1, 0);
+    s->part_off.assign(nrep + 1, 0);
+    s->blk_off.assign((size_t)kLaneCounts * (nrep + 1), 0);
+    int64_t cells = 0;
+    for (int r = 0; r < nrep; ++r) {
+        mdpd_status rc = make_geom(&ps[r], &s->geoms[r]);
+        if (rc) {
+            delete s;
+            return rc;
+        }
+        cells += s->geoms[r].ncells;
+        if (cells > (int64_t)1 << 26) {
+            delete s;
+            return fail(MDPD_E_UNSUPPORTED, "more than 2^26 cells in total");
+        }
+        s->cell_off[r + 1] = (int)cells;
+        s->part_off[r + 1] = (int)offsets[r + 1];
+        s->mt = s->mt || ps[r].ntypes > 1;
+        for (int li = 0; li < kLaneCounts; ++li) {
+            const int64_t P = (int64_t)1 << li;
+            const int64_t nr = offsets[r + 1] - offsets[r];
+            int *bo = &s->blk_off[(size_t)li * (nrep + 1)];
+            bo[r + 1] = bo[r] + (int)((nr * P + kBlock - 1) / kBlock);
+        }
+    }
 
     const size_t N = (size_t)(n > 0 ? n : 1);
-    const int nb_scan = (g.ncells + 4095) / 4096;
-    s->nfpart = force_partials(16, (int)N);
+    const int nb_scan = (int)((cells + 4095) / 4096);
+    Reps &R = s->R;
+    R.nrep = nrep;
+    R.ncells = (int)cells;
+    for (int li = 0; li < kLaneCounts; ++li) R.nblk[li] = s->blk_off[(size_t)li * (nrep + 1) + nrep];
 #define ALLOC(call)                 \
     do {                            \
         mdpd_status e_ = (call);    \
@@ -402,50 +533,76 @@ mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, cons
         ALLOC(s->alloc(&r2, s->fp32 ? N * kListCap / 2 : N * kListCap));
         s->nlr2 = r2;
     }
-    ALLOC(s->alloc(&s->counts, (size_t)g.ncells));
-    ALLOC(s->alloc(&s->cstart, (size_t)g.ncells + 1));
+    ALLOC(s->alloc(&s->counts, (size_t)cells));
+    ALLOC(s->alloc(&s->cstart, (size_t)cells + 1));
     ALLOC(s->alloc(&s->bsum, (size_t)nb_scan + 1));
-    ALLOC(s->alloc(&s->fpart, 2 * (size_t)s->nfpart));
+    ALLOC(s->alloc(&s->fpart, 2 * (size_t)(R.nblk[kLaneCounts - 1] + 1)));
     ALLOC(s->alloc(&s->status, 4));
+    ALLOC(s->alloc(&s->dstep, 1));
     ALLOC(s->alloc(&s->corr, N + 1));
     ALLOC(s->alloc(&s->ovf, N + 1));
     ALLOC(s->alloc(&s->ovf_ve, 2 * N));
     ALLOC(s->alloc(&s->ncorr_total, 1));
-    ALLOC(s->alloc(&s->tab, 320));
-    ALLOC(s->alloc(&s->obs, kObsSlots));
+    ALLOC(s->alloc(&s->tab, 320 * (size_t)nrep));
+    ALLOC(s->alloc(&s->obs, 16 * (size_t)nrep));
+    ALLOC(s->alloc(&s->obs_part, (size_t)obs_partials(R) + 16));
     ALLOC(s->alloc(&s->io, 3 * N));
     ALLOC(s->alloc(&s->io2, 3 * N));
     ALLOC(s->alloc(&s->work, 9 * 4096));
+    Geom *dgeom = nullptr;
+    PairConst *dpc = nullptr;
+    int *dcell = nullptr, *dpart = nullptr, *dblk = nullptr;
+    ALLOC(s->alloc(&dgeom, (size_t)nrep));
+    ALLOC(s->alloc(&dpc, (size_t)nrep));
+    ALLOC(s->alloc(&dcell, (size_t)nrep + 1));
+    ALLOC(s->alloc(&dpart, (size_t)nrep + 1));
+    ALLOC(s->alloc(&dblk, s->blk_off.size()));
 #undef ALLOC
-
-    // type-pair tables: A | B | gamma | sig | A r_c / 2
-    {
-        double h[320] = {0};
-        const int T = p->ntypes;
-        for (int k = 0; k < T * T; ++k) {
-            h[k] = p->A[k];
-            h[64 + k] = p->B[k];
-            h[128 + k] = p->gamma[k];
-            h[192 + k] = sqrt(2.0 * p->gamma[k] * p->kT) * rdt;
-            h[256 + k] = 0.5 * p->A[k] * p->rc;
-        }
-        hipError_t e = hipMemcpyAsync(s->tab, h, sizeof h, hipMemcpyHostToDevice, s->st);
-        if (e == hipSuccess) e = hipStreamSynchronize(s->st);
-        if (e != hipSuccess) {
-            delete s;
-            return fail(MDPD_E_HIP, "upload of pair tables failed: %s", hipGetErrorString(e));
-        }
-        pc.tab = s->tab;
-    }
+    R.geom = dgeom;
+    R.pc = dpc;
+    R.cell_off = dcell;
+    R.part_off = dpart;
+    R.blk_off = dblk;
 
     auto bail = [&](mdpd_status st) {
         delete s;
         return st;
     };
+    // replica tables
+    {
+        std::vector<double> tabs((size_t)320 * nrep);
+        s->pcs.resize(nrep);
+        for (int r = 0; r < nrep; ++r) {
+            fill_pair_table(&ps[r], &tabs[(size_t)320 * r]);
+            s->pcs[r] = make_pair_const(&ps[r], s->tab + (size_t)320 * r);
+        }
+        hipError_t e = hipMemcpyAsync(s->tab, tabs.data(), tabs.size() * sizeof(double), hipMemcpyHostToDevice,
+                                      s->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dgeom, s->geoms.data(), nrep * sizeof(Geom), hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dpc, s->pcs.data(), nrep * sizeof(PairConst), hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dcell, s->cell_off.data(), (nrep + 1) * sizeof(int), hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dpart, s->part_off.data(), (nrep + 1) * sizeof(int), hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dblk, s->blk_off.data(), s->blk_off.size() * sizeof(int), hipMemcpyHostToDevice,
+                               s->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+        if (e != hipSuccess) return bail(fail(MDPD_E_HIP, "upload of replica tables failed: %s", hipGetErrorString(e)));
+    }
+
     hipError_t e = hipSuccess;
     launch_zero_int(s->st, s->status, 4);
+    {
+        // the sort at creation advances it to step 0
+        static const uint32_t before_first = 0xFFFFFFFFu;
+        e = hipMemcpyAsync(s->dstep, &before_first, sizeof before_first, hipMemcpyHostToDevice, s->st);
+        if (e != hipSuccess) return bail(fail(MDPD_E_HIP, "step counter init failed: %s", hipGetErrorString(e)));
+    }
     launch_zero_int(s->st, (int *)s->ncorr_total, 2);
-    launch_zero_int(s->st, s->counts, g.ncells);
+    launch_zero_int(s->st, s->counts, (int)cells);
     launch_zero_int(s->st, s->corr, (int)N + 1);
     launch_zero_int(s->st, s->ovf, 1);
 
@@ -468,12 +625,15 @@ mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, cons
         dfz = sfz;
     }
     s->cur = 0;
-    launch_ingest(s->st, n, dpos, dvel, dtype, dfz, g, p->ntypes, s->xpred, s->vpred, s->tag[0], s->typ[0],
-                  s->status);
+    launch_ingest(s->st, R, dpos, dvel, dtype, dfz, s->xpred, s->vpred, s->tag[0], s->typ[0], s->status);
     int hstatus = 0;
     e = hipMemcpyAsync(&hstatus, s->status, sizeof(int), hipMemcpyDeviceToHost, s->st);
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
     if (e != hipSuccess) return bail(fail(MDPD_E_HIP, "ingest failed: %s", hipGetErrorString(e)));
+    if (stype) {
+        s->release(stype);
+        s->release(sfz);
+    }
     if (hstatus & 2)
         return bail(fail(MDPD_E_INVALID,
                          "input has a non-finite value, a position outside [-L, 2L) or a bad type"));
@@ -489,15 +649,42 @@ mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, cons
     return MDPD_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, const double *vel,
+                        const int32_t *type, const uint8_t *frozen, int32_t mem_kind, void *stream,
+                        mdpd_system **out)
+{
+    if (n < 0 || n >= (int64_t)1 << 30) {
+        if (out) *out = nullptr;
+        return fail(MDPD_E_INVALID, "n = %lld out of range", (long long)n);
+    }
+    const int64_t offsets[2] = {0, n};
+    return create_impl(1, p, offsets, pos, vel, type, frozen, mem_kind, stream, out);
+}
+
+mdpd_status mdpd_create_batch(int32_t nrep, const mdpd_params *params, const int64_t *offsets, const double *pos,
+                              const double *vel, const int32_t *type, const uint8_t *frozen, int32_t mem_kind,
+                              void *stream, mdpd_system **out)
+{
+    return create_impl(nrep, params, offsets, pos, vel, type, frozen, mem_kind, stream, out);
+}
+
 mdpd_status mdpd_step(mdpd_system *s, int64_t nsteps)
 {
     if (!s) return fail(MDPD_E_INVALID, "system is NULL");
     if (nsteps < 0) return fail(MDPD_E_INVALID, "nsteps < 0");
-    for (int64_t k = 0; k < nsteps; ++k) {
-        s->step += 1;
-        s->sort_predicted();
-        s->evaluate((uint32_t)s->step, 0);
+    if (s->use_graph && s->n > 0) {
+        while (nsteps >= 2) {
+            if (!s->graph_valid()) HIPCHK(s->capture_pair());
+            HIPCHK(hipGraphLaunch(s->gexec, s->st));
+            s->step += 2;
+            nsteps -= 2;
+        }
     }
+    s->advance(nsteps);
     int hstatus = 0;
     HIPCHK(hipMemcpyAsync(&hstatus, s->status, sizeof(int), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
@@ -506,46 +693,64 @@ mdpd_status mdpd_step(mdpd_system *s, int64_t nsteps)
     return MDPD_OK;
 }
 
-mdpd_status mdpd_read_observables(mdpd_system *s, mdpd_observables *out)
+mdpd_status mdpd_read_replica_observables(mdpd_system *s, int32_t first, int32_t count, mdpd_observables *out)
 {
     if (!s || !out) return fail(MDPD_E_INVALID, "NULL argument");
-    launch_observables(s->st, s->fp32, s->n, s->pc, cview(s->v), s->rho, s->tag[s->cur], s->typ[s->cur],
-                       s->fpart, s->nfpart_used, s->ncnt, s->ovf_ve, s->obs);
-    double h[10];
+    if (first < 0 || count < 0 || first + count > s->nrep)
+        return fail(MDPD_E_INVALID, "replicas [%d, %d) outside [0, %d)", first, first + count, s->nrep);
+    launch_observables(s->st, s->fp32, s->R, s->force_lanes_used, cview(s->v), s->rho, s->tag[s->cur],
+                       s->typ[s->cur], s->fpart, s->ncnt, s->ovf_ve, s->obs_part, s->obs);
+    std::vector<double> h((size_t)16 * (count > 0 ? count : 1));
     unsigned long long tot = 0;
     int last = 0;
-    HIPCHK(hipMemcpyAsync(h, s->obs, sizeof h, hipMemcpyDeviceToHost, s->st));
+    if (count > 0)
+        HIPCHK(hipMemcpyAsync(h.data(), s->obs + (size_t)16 * first, (size_t)16 * count * sizeof(double),
+                              hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipMemcpyAsync(&tot, s->ncorr_total, sizeof tot, hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipMemcpyAsync(&last, s->corr, sizeof last, hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
-    const mdpd_params &p = s->p;
-    const double m = p.mass;
-    const int64_t nf = (int64_t)llround(h[6]);
-    const bool driven = p.body_force[0] != 0.0 || p.body_force[1] != 0.0 || p.body_force[2] != 0.0;
-    double dof = (double)nf;
-    if (nf == s->n && !driven) dof -= 1.0;
-    const double V = p.box[0] * p.box[1] * p.box[2];
-    memset(out, 0, sizeof *out);
-    out->step = s->step;
-    out->n = s->n;
-    out->n_fluid = nf;
-    out->ke = 0.5 * m * h[0];
-    out->kT = dof > 0 ? m * h[0] / (3.0 * dof) : 0.0;
-    out->virial = h[8];
-    out->pressure = (m * h[0] + h[8]) / (3.0 * V);
-    out->momentum[0] = m * h[1];
-    out->momentum[1] = m * h[2];
-    out->momentum[2] = m * h[3];
-    out->epot = h[9] + M_PI * pow(p.rd, 4) / 30.0 * h[5];
-    out->mean_rho = nf > 0 ? h[4] / (double)nf : 0.0;
-    out->ncorr_last = s->walls && s->step > 0 ? last : 0;
-    out->ncorr_total = (int64_t)tot;
+    for (int k = 0; k < count; ++k) {
+        const int r = first + k;
+        const double *q = &h[(size_t)16 * k];
+        const mdpd_params &p = s->params[r];
+        const int64_t nr = s->part_off[r + 1] - s->part_off[r];
+        const double m = p.mass;
+        const int64_t nf = (int64_t)llround(q[6]);
+        const bool driven = p.body_force[0] != 0.0 || p.body_force[1] != 0.0 || p.body_force[2] != 0.0;
+        double dof = (double)nf;
+        if (nf == nr && !driven) dof -= 1.0;
+        const double V = p.box[0] * p.box[1] * p.box[2];
+        mdpd_observables &o = out[k];
+        memset(&o, 0, sizeof o);
+        o.step = s->step;
+        o.n = nr;
+        o.n_fluid = nf;
+        o.ke = 0.5 * m * q[0];
+        o.kT = dof > 0 ? m * q[0] / (3.0 * dof) : 0.0;
+        o.virial = q[8];
+        o.pressure = (m * q[0] + q[8]) / (3.0 * V);
+        o.momentum[0] = m * q[1];
+        o.momentum[1] = m * q[2];
+        o.momentum[2] = m * q[3];
+        o.epot = q[9] + M_PI * pow(p.rd, 4) / 30.0 * q[5];
+        o.mean_rho = nf > 0 ? q[4] / (double)nf : 0.0;
+        o.ncorr_last = s->walls && s->step > 0 ? last : 0;
+        o.ncorr_total = (int64_t)tot;
+    }
     return MDPD_OK;
+}
+
+mdpd_status mdpd_read_observables(mdpd_system *s, mdpd_observables *out)
+{
+    if (!s || !out) return fail(MDPD_E_INVALID, "NULL argument");
+    if (s->nrep != 1) return fail(MDPD_E_STATE, "a batch of replicas: use mdpd_read_replica_observables");
+    return mdpd_read_replica_observables(s, 0, 1, out);
 }
 
 mdpd_status mdpd_read_profile(mdpd_system *s, int32_t axis, int32_t nbins, int32_t quantity, double *out)
 {
     if (!s || !out) return fail(MDPD_E_INVALID, "NULL argument");
+    if (s->nrep != 1) return fail(MDPD_E_UNSUPPORTED, "profiles are for single systems");
     if (axis < 0 || axis > 2 || nbins < 1 || nbins > 4096 || quantity < 0 || quantity > 5)
         return fail(MDPD_E_INVALID, "bad profile request (axis %d, nbins %d, quantity %d)", axis, nbins,
                     quantity);
@@ -567,18 +772,18 @@ mdpd_status mdpd_get_state(mdpd_system *s, double *pos, double *vel, double *rho
     const size_t N = (size_t)s->n;
     if (N == 0) return MDPD_OK;
     if (mem_kind == MDPD_MEM_DEVICE) {
-        launch_export(s->st, s->fp32, s->n, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur], pos,
+        launch_export(s->st, s->fp32, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur], pos,
                       vel, rho);
         HIPCHK(hipStreamSynchronize(s->st));
         return MDPD_OK;
     }
-    launch_export(s->st, s->fp32, s->n, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur],
+    launch_export(s->st, s->fp32, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur],
                   pos ? s->io : nullptr, vel ? s->io2 : nullptr, nullptr);
     if (pos) HIPCHK(hipMemcpyAsync(pos, s->io, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s->st));
     if (vel) HIPCHK(hipMemcpyAsync(vel, s->io2, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
     if (rho) {
-        launch_export(s->st, s->fp32, s->n, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur],
+        launch_export(s->st, s->fp32, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur],
                       nullptr, nullptr, s->io);
         HIPCHK(hipMemcpyAsync(rho, s->io, N * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(hipStreamSynchronize(s->st));
@@ -599,9 +804,10 @@ struct CkptHeader {
     uint64_t magic;
     int64_t n;
     int64_t step;
-    int64_t nfpart_used;
+    int64_t force_lanes;
     int64_t ncells;
-    int64_t reserved[3];
+    int64_t nrep;
+    int64_t reserved[2];
 };
 
 struct CkptField {
@@ -618,8 +824,10 @@ std::vector<CkptField> ckpt_fields(mdpd_system *s)
         {s->xs[c].x, 24 * N},          {s->v.x, 24 * N},     {s->F.x, 24 * N},
         {s->xpred.x, 24 * N},          {s->vpred.x, 24 * N}, {s->rho, rb * N},
         {s->tag[c], 4 * N},            {s->typ[c], N},       {s->ovf_ve, 16 * N},
-        {s->cstart, 4 * ((uint64_t)s->g.ncells + 1)},        {s->fpart, 16 * (uint64_t)s->nfpart_used},
+        {s->cstart, 4 * ((uint64_t)s->R.ncells + 1)},
+        {s->fpart, 16 * (uint64_t)s->R.nblk[kLaneCounts - 1]},
         {s->ncorr_total, 8},           {s->corr, 4},
+        {s->dstep, 4},
     };
 }
 
@@ -633,7 +841,20 @@ uint64_t state_bytes(mdpd_system *s)
     return off;
 }
 
-uint64_t ckpt_bytes(mdpd_system *s) { return align_up(sizeof(CkptHeader) + sizeof(mdpd_params)) + state_bytes(s); }
+// Header and the parameters of every replica.
+uint64_t head_bytes(const mdpd_system *s) { return align_up(sizeof(CkptHeader) + s->nrep * sizeof(mdpd_params)); }
+
+uint64_t ckpt_bytes(mdpd_system *s) { return head_bytes(s) + state_bytes(s); }
+
+// The parameters stored in a checkpoint equal the system's, byte for byte.
+bool params_match(mdpd_system *s, const char *in, hipMemcpyKind hk)
+{
+    std::vector<mdpd_params> q(s->nrep);
+    if (hipMemcpyAsync(q.data(), in + sizeof(CkptHeader), s->nrep * sizeof(mdpd_params), hk, s->st) != hipSuccess)
+        return false;
+    if (hipStreamSynchronize(s->st) != hipSuccess) return false;
+    return memcmp(q.data(), s->params.data(), s->nrep * sizeof(mdpd_params)) == 0;
+}
 
 // Enqueue copies of the state arrays to / from dst (kind: the direction).
 hipError_t state_copy(mdpd_system *s, char *buf, bool save, hipMemcpyKind kind)
@@ -675,12 +896,13 @@ mdpd_status mdpd_save_checkpoint(mdpd_system *s, void *buf, uint64_t bytes, int3
     h.magic = kCkptMagic;
     h.n = s->n;
     h.step = s->step;
-    h.nfpart_used = s->nfpart_used;
-    h.ncells = s->g.ncells;
+    h.force_lanes = s->force_lanes_used;
+    h.ncells = s->R.ncells;
+    h.nrep = s->nrep;
     char *out = (char *)buf;
     HIPCHK(hipMemcpyAsync(out, &h, sizeof h, hk, s->st));
-    HIPCHK(hipMemcpyAsync(out + sizeof h, &s->p, sizeof s->p, hk, s->st));
-    HIPCHK(state_copy(s, out + align_up(sizeof h + sizeof s->p), true, dk));
+    HIPCHK(hipMemcpyAsync(out + sizeof h, s->params.data(), s->nrep * sizeof(mdpd_params), hk, s->st));
+    HIPCHK(state_copy(s, out + head_bytes(s), true, dk));
     HIPCHK(hipStreamSynchronize(s->st));
     return MDPD_OK;
 }
@@ -691,27 +913,26 @@ mdpd_status mdpd_load_checkpoint(mdpd_system *s, const void *buf, uint64_t bytes
     if (mem_kind != MDPD_MEM_HOST && mem_kind != MDPD_MEM_DEVICE)
         return fail(MDPD_E_INVALID, "unknown mem_kind %d", mem_kind);
     const uint64_t need = ckpt_bytes(s);
-    if (bytes < sizeof(CkptHeader) + sizeof(mdpd_params))
-        return fail(MDPD_E_INVALID, "checkpoint buffer too small");
+    if (bytes < head_bytes(s)) return fail(MDPD_E_INVALID, "checkpoint buffer too small");
     const char *in = (const char *)buf;
     const hipMemcpyKind hk = mem_kind == MDPD_MEM_HOST ? hipMemcpyHostToHost : hipMemcpyDeviceToHost;
     const hipMemcpyKind dk = mem_kind == MDPD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     CkptHeader h{};
-    mdpd_params p{};
     HIPCHK(hipMemcpyAsync(&h, in, sizeof h, hk, s->st));
-    HIPCHK(hipMemcpyAsync(&p, in + sizeof h, sizeof p, hk, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
     if (h.magic != kCkptMagic) return fail(MDPD_E_INVALID, "buffer does not hold an mdpd checkpoint");
-    if (h.n != s->n || h.ncells != s->g.ncells || memcmp(&p, &s->p, sizeof p) != 0)
+    if (h.n != s->n || h.ncells != s->R.ncells || h.nrep != s->nrep || !params_match(s, in, hk))
         return fail(MDPD_E_INVALID, "checkpoint was saved from a system with other parameters or n");
     if (bytes < need) return fail(MDPD_E_INVALID, "checkpoint buffer of %llu bytes, need %llu",
                                   (unsigned long long)bytes, (unsigned long long)need);
-    if (h.nfpart_used < 0 || h.nfpart_used > s->nfpart) return fail(MDPD_E_INVALID, "corrupt checkpoint");
-    s->nfpart_used = (int)h.nfpart_used;
+    if (h.force_lanes != 1 && h.force_lanes != 2 && h.force_lanes != 4 && h.force_lanes != 8 &&
+        h.force_lanes != 16)
+        return fail(MDPD_E_INVALID, "corrupt checkpoint");
+    s->force_lanes_used = (int)h.force_lanes;
     s->step = h.step;
-    HIPCHK(state_copy(s, const_cast<char *>(in) + align_up(sizeof h + sizeof p), false, dk));
+    HIPCHK(state_copy(s, const_cast<char *>(in) + head_bytes(s), false, dk));
     // the neighbour list is a function of the positions and the cell list
-    launch_nlist(s->st, s->fp32, s->n, s->g, cview(s->xs[s->cur]), s->cstart, s->ncnt, s->nl, s->nlr2, nullptr);
+    launch_nlist(s->st, s->fp32, s->R, cview(s->xs[s->cur]), s->cstart, s->ncnt, s->nl, s->nlr2, nullptr);
     HIPCHK(hipStreamSynchronize(s->st));
     HIPCHK(hipGetLastError());
     return MDPD_OK;
@@ -722,7 +943,7 @@ mdpd_status mdpd_debug_forces(mdpd_system *s, double *force)
     if (!s || !force) return fail(MDPD_E_INVALID, "NULL argument");
     const size_t N = (size_t)s->n;
     if (N == 0) return MDPD_OK;
-    launch_export(s->st, false, s->n, cview(s->F), Soa3c{nullptr, nullptr, nullptr}, nullptr, s->tag[s->cur],
+    launch_export(s->st, false, s->R, cview(s->F), Soa3c{nullptr, nullptr, nullptr}, nullptr, s->tag[s->cur],
                   s->io, nullptr, nullptr);
     HIPCHK(hipMemcpyAsync(force, s->io, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
@@ -732,13 +953,14 @@ mdpd_status mdpd_debug_forces(mdpd_system *s, double *force)
 mdpd_status mdpd_debug_neighbors(mdpd_system *s, double cutoff, int64_t *count, uint64_t *hash)
 {
     if (!s || !count || !hash) return fail(MDPD_E_INVALID, "NULL argument");
-    if (!(cutoff > 0.0) || cutoff > s->p.rc) return fail(MDPD_E_INVALID, "cutoff must be in (0, rc]");
+    for (const mdpd_params &q : s->params)
+        if (!(cutoff > 0.0) || cutoff > q.rc) return fail(MDPD_E_INVALID, "cutoff must be in (0, rc]");
     const size_t N = (size_t)s->n;
     if (N == 0) return MDPD_OK;
     int64_t *dc = (int64_t *)s->io;
     uint64_t *dh = (uint64_t *)s->io2;
-    launch_debug_neighbors(s->st, s->n, s->g, s->pc, cutoff * cutoff, cview(s->xs[s->cur]), s->tag[s->cur],
-                           s->cstart, s->ncnt, s->nl, dc, dh);
+    launch_debug_neighbors(s->st, s->R, cutoff * cutoff, cview(s->xs[s->cur]), s->tag[s->cur], s->cstart,
+                           s->ncnt, s->nl, dc, dh);
     HIPCHK(hipMemcpyAsync(count, dc, N * sizeof(int64_t), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipMemcpyAsync(hash, dh, N * sizeof(uint64_t), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
@@ -770,6 +992,17 @@ mdpd_status mdpd_read_kernel_timing(mdpd_system *s, int32_t kernel, double *tota
     return MDPD_OK;
 }
 
+mdpd_status mdpd_set_graph(mdpd_system *s, int32_t enable)
+{
+    if (!s) return fail(MDPD_E_INVALID, "system is NULL");
+    s->use_graph = enable != 0;
+    if (!s->use_graph) {
+        HIPCHK(s->st ? hipStreamSynchronize(s->st) : hipDeviceSynchronize());
+        s->drop_graph();
+    }
+    return MDPD_OK;
+}
+
 mdpd_status mdpd_set_lanes(mdpd_system *s, int32_t pass, int32_t lanes)
 {
     if (!s) return fail(MDPD_E_INVALID, "system is NULL");
@@ -777,6 +1010,98 @@ mdpd_status mdpd_set_lanes(mdpd_system *s, int32_t pass, int32_t lanes)
     if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16)
         return fail(MDPD_E_INVALID, "lanes %d not in {1, 2, 4, 8, 16}", lanes);
     s->lanes[pass] = lanes;
+    return MDPD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner: lanes per particle of the density and force passes, timed with
+// HIP events on the system's own stream, cached per shape for the process.
+// ---------------------------------------------------------------------------
+namespace {
+
+using TuneKey = std::tuple<int, int, int, int, int, int>;  // n, cells, nrep, fp32, types > 1, walls
+
+std::mutex g_tune_mu;
+std::map<TuneKey, std::vector<int>> g_tune_cache;
+
+TuneKey tune_key(const mdpd_system *s)
+{
+    return TuneKey{s->n, s->R.ncells, s->nrep, s->fp32 ? 1 : 0, s->mt ? 1 : 0, s->walls ? 1 : 0};
+}
+
+}  // namespace
+
+extern "C" {
+
+mdpd_status mdpd_autotune(mdpd_system *s, int32_t steps, int32_t *lanes_out)
+{
+    if (!s) return fail(MDPD_E_INVALID, "system is NULL");
+    if (steps < 1) return fail(MDPD_E_INVALID, "steps must be >= 1");
+    const TuneKey key = tune_key(s);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            for (int k = 0; k < 3; ++k) s->lanes[k] = it->second[k];
+            if (lanes_out)
+                for (int k = 0; k < 3; ++k) lanes_out[k] = s->lanes[k];
+            return MDPD_OK;
+        }
+    }
+    // keep the state: the trial steps must leave no trace
+    char *save = nullptr;
+    mdpd_status rc = s->alloc(&save, state_bytes(s));
+    if (rc) return rc;
+    const int cur0 = s->cur, lanes_used0 = s->force_lanes_used;
+    const int64_t step0 = s->step;
+    const bool timing0 = s->timing;
+    HIPCHK(state_copy(s, save, true, hipMemcpyDeviceToDevice));
+    s->timing = true;
+    const int cand[5] = {1, 2, 4, 8, 16};
+    const int passes[2] = {1, 2}, classes[2] = {2, 3};  // density (and phi), force
+    mdpd_status err = MDPD_OK;
+    for (int q = 0; q < 2 && !err; ++q) {
+        double best = 1e300;
+        int best_l = s->lanes[passes[q]];
+        for (int l : cand) {
+            s->lanes[passes[q]] = l;
+            s->advance(1);  // warm-up of this instantiation
+            double ms = 0.0;
+            int64_t cnt = 0;
+            if ((err = mdpd_read_kernel_timing(s, classes[q], &ms, &cnt))) break;
+            s->advance(steps);
+            if ((err = mdpd_read_kernel_timing(s, classes[q], &ms, &cnt))) break;
+            if (ms < best) {
+                best = ms;
+                best_l = l;
+            }
+        }
+        s->lanes[passes[q]] = best_l;
+    }
+    for (int k = 0; k < kTimedKernels; ++k) {
+        double ms;
+        int64_t cnt;
+        (void)mdpd_read_kernel_timing(s, k, &ms, &cnt);  // clear
+    }
+    s->timing = timing0;
+    s->cur = cur0;
+    s->step = step0;
+    s->force_lanes_used = lanes_used0;
+    HIPCHK(state_copy(s, save, false, hipMemcpyDeviceToDevice));
+    launch_zero_int(s->st, s->status, 1);
+    launch_nlist(s->st, s->fp32, s->R, cview(s->xs[s->cur]), s->cstart, s->ncnt, s->nl, s->nlr2, nullptr);
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->release(save);
+    if (err) return err;
+    s->lanes[0] = s->lanes[1];
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = std::vector<int>{s->lanes[0], s->lanes[1], s->lanes[2]};
+    }
+    if (lanes_out)
+        for (int k = 0; k < 3; ++k) lanes_out[k] = s->lanes[k];
     return MDPD_OK;
 }
 
@@ -803,7 +1128,7 @@ uint64_t tape_entry_bytes(mdpd_system *s)
     const uint64_t N = (uint64_t)(s->n > 0 ? s->n : 1);
     const uint64_t rb = s->fp32 ? 4 : 8;
     return 3 * align_up(24 * N) + align_up(rb * N) + align_up(4 * N) + align_up(N) +
-           align_up(4 * ((uint64_t)s->g.ncells + 1));
+           align_up(4 * ((uint64_t)s->R.ncells + 1));
 }
 
 TapeEntry tape_entry(mdpd_system *s, int k)
@@ -846,29 +1171,19 @@ hipError_t tape_record(mdpd_system *s, int k, bool creation)
     cp(e.rho, s->rho, (s->fp32 ? 4 : 8) * N);
     cp(e.tag, s->tag[c], 4 * N);
     cp(e.typ, s->typ[c], N);
-    cp(e.cstart, s->cstart, 4 * ((size_t)s->g.ncells + 1));
+    cp(e.cstart, s->cstart, 4 * ((size_t)s->R.ncells + 1));
     return r;
-}
-
-// Advance without synchronising (the caller checks the status word).
-void advance(mdpd_system *s, int64_t nsteps)
-{
-    for (int64_t k = 0; k < nsteps; ++k) {
-        s->step += 1;
-        s->sort_predicted();
-        s->evaluate((uint32_t)s->step, 0);
-    }
 }
 
 hipError_t ckpt_store(mdpd_system *s, int k)
 {
-    s->adj.ck_nfpart[k] = s->nfpart_used;
+    s->adj.ck_lanes[k] = s->force_lanes_used;
     return state_copy(s, s->adj.ck + (uint64_t)k * s->adj.ck_bytes, true, hipMemcpyDeviceToDevice);
 }
 
 hipError_t ckpt_restore(mdpd_system *s, int k, int64_t step)
 {
-    s->nfpart_used = s->adj.ck_nfpart[k];
+    s->force_lanes_used = s->adj.ck_lanes[k];
     s->step = step;
     return state_copy(s, s->adj.ck + (uint64_t)k * s->adj.ck_bytes, false, hipMemcpyDeviceToDevice);
 }
@@ -892,20 +1207,19 @@ void adjoint_step(mdpd_system *s, int k, int64_t n, bool creation, const double 
     const double inf = a.nfluid > 0 ? 1.0 / (double)a.nfluid : 0.0;
     const double sw = seed_weight(a, n);
     AdjConst ac;
-    ac.cU = creation ? s->pc.hdtm : 2.0 * s->pc.hdtm;
-    ac.cv = creation ? 0.0 : s->pc.hdtm;
+    const double h = s->pcs[0].hdtm;
+    ac.cU = creation ? h : 2.0 * h;
+    ac.cv = creation ? 0.0 : h;
     ac.wrho_nf = sw * w[0] * inf;
     ac.wP_3V = sw * w[1] / V3;
     ac.wvx_nf = sw * w[2] * inf;
     ac.mass = s->p.mass;
-    s->set_step_keys((uint32_t)n);
     launch_adj_seed(s->st, s->n, ac, cview(e.v), e.tag, a.U, a.fb, a.rhoA);
-    launch_nlist(s->st, s->fp32, s->n, s->g, cview(e.x), e.cstart, s->ncnt, s->nl, s->nlr2, nullptr);
+    launch_nlist(s->st, s->fp32, s->R, cview(e.x), e.cstart, s->ncnt, s->nl, s->nlr2, nullptr);
     s->tic(5);
-    launch_adj_force(s->st, s->lanes[2], s->fp32, s->n, s->pc, s->g, ac, cview(e.x), cview(e.u), e.rho, e.tag,
-                     e.typ, e.cstart, s->ncnt, s->nl, cview(a.fb), a.X, a.U, a.rhoA, a.gp);
-    launch_adj_density(s->st, s->lanes[1], s->n, s->pc, s->g, cview(e.x), e.cstart, s->ncnt, s->nl, a.rhoA,
-                       a.X);
+    launch_adj_force(s->st, s->lanes[2], s->fp32, s->mt, s->n, s->R, (uint32_t)n, ac, cview(e.x), cview(e.u),
+                     e.rho, e.tag, e.typ, e.cstart, s->ncnt, s->nl, cview(a.fb), a.X, a.U, a.rhoA, a.gp);
+    launch_adj_density(s->st, s->lanes[1], s->R, cview(e.x), e.cstart, s->ncnt, s->nl, a.rhoA, a.X);
     s->toc(5);
     launch_adj_params(s->st, s->n, s->p.ntypes, e.typ, a.gp, a.gpart, a.gtot);
 }
@@ -921,6 +1235,7 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
     if (average && nsteps < 1) return fail(MDPD_E_INVALID, "a time average needs nsteps >= 1");
     if (s->walls) return fail(MDPD_E_UNSUPPORTED, "the adjoint does not differentiate the wall corrector");
     if (s->step != 0) return fail(MDPD_E_STATE, "recording starts from the state given to mdpd_create");
+    if (s->nrep != 1) return fail(MDPD_E_UNSUPPORTED, "the adjoint runs on single systems");
     if (s->p.ntypes > MDPD_ADJ_MAX_TYPES) return fail(MDPD_E_UNSUPPORTED, "too many types");
     AdjRec &a = s->adj;
     a.ready = false;
@@ -944,7 +1259,7 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
         a.nck = K + 1;
         a.ck_bytes = ckb;
     }
-    a.ck_nfpart.assign((size_t)K + 1, 0);
+    a.ck_lanes.assign((size_t)K + 1, 4);
     if (!a.tape || a.ntape < ntape || a.tape_bytes != tpb) {
         s->release(a.tape);
         a.tape = nullptr;
@@ -970,8 +1285,8 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
     auto accum = [&](int64_t n) {
         const double sw = seed_weight(a, n);
         if (sw == 0.0) return;
-        launch_observables(s->st, s->fp32, s->n, s->pc, cview(s->v), s->rho, s->tag[s->cur], s->typ[s->cur],
-                           s->fpart, s->nfpart_used, s->ncnt, s->ovf_ve, s->obs);
+        launch_observables(s->st, s->fp32, s->R, s->force_lanes_used, cview(s->v), s->rho, s->tag[s->cur],
+                           s->typ[s->cur], s->fpart, s->ncnt, s->ovf_ve, s->obs_part, s->obs);
         launch_loss_accum(s->st, s->obs, a.loss, inf, 1.0 / V3, s->p.mass, sw);
     };
     HIPCHK(ckpt_store(s, 0));
@@ -979,7 +1294,7 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
     for (int k = 1; k <= K; ++k) {
         const int64_t s0 = ckpt_step(a, k - 1), s1 = ckpt_step(a, k);
         for (int64_t n = s0 + 1; n <= s1; ++n) {
-            advance(s, 1);
+            s->advance(1);
             accum(n);
         }
         HIPCHK(ckpt_store(s, k));
@@ -1016,7 +1331,7 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
         HIPCHK(ckpt_restore(s, k - 1, s0));
         HIPCHK(tape_record(s, 0, s0 == 0));
         for (int m = 1; m <= (int)(s1 - s0); ++m) {
-            advance(s, 1);
+            s->advance(1);
             HIPCHK(tape_record(s, m, false));
         }
         for (int m = (int)(s1 - s0); m >= 1; --m) {
@@ -1037,7 +1352,7 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
     const hipMemcpyKind dk = mem_kind == MDPD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     if (N > 0) {
         // sorted SoA planes to n x 3 rows in id order (U of frozen particles is 0)
-        launch_export(s->st, false, s->n, cview(a.X), cview(a.U), nullptr, tape_entry(s, 0).tag, s->io, s->io2,
+        launch_export(s->st, false, s->R, cview(a.X), cview(a.U), nullptr, tape_entry(s, 0).tag, s->io, s->io2,
                       nullptr);
         if (dx0) HIPCHK(hipMemcpyAsync(dx0, s->io, 3 * N * sizeof(double), dk, s->st));
         if (dv0) HIPCHK(hipMemcpyAsync(dv0, s->io2, 3 * N * sizeof(double), dk, s->st));
@@ -1050,7 +1365,7 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
     }
     // back to the state at the end of the recording
     HIPCHK(ckpt_restore(s, K, a.nsteps));
-    launch_nlist(s->st, s->fp32, s->n, s->g, cview(s->xs[s->cur]), s->cstart, s->ncnt, s->nl, s->nlr2, nullptr);
+    launch_nlist(s->st, s->fp32, s->R, cview(s->xs[s->cur]), s->cstart, s->ncnt, s->nl, s->nlr2, nullptr);
     HIPCHK(hipStreamSynchronize(s->st));
     HIPCHK(hipGetLastError());
     return MDPD_OK;

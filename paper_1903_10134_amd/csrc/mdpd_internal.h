@@ -55,9 +55,72 @@ struct PairConst {
     double phi_c;
     const double *tab;  // ntypes > 1: A | B | gamma | sig | Arc2 planes of 64
     int ntypes;
+    uint32_t seed;      // key word 0 of the pair noise
     uint32_t ks0, ks1;  // Threefry key words added to the counter
     uint32_t inj0[5], inj1[5];  // Threefry key injections after rounds 4, 8, ..., 20
 };
+
+// Replicas: independent periodic systems stored back to back.  Replica r
+// owns the global cells [cell_off[r], cell_off[r+1]) and, since the sort key
+// is replica-major and particles never change replica, the sorted slots
+// [part_off[r], part_off[r+1]).  The particle kernels run replica-aligned
+// blocks: with P lanes per particle, replica r owns the blocks
+// [blk[r], blk[r+1]) of blk = blk_off + lanes_index(P) * (nrep + 1), so every
+// block reads one replica's constants (scalar loads).  A single system is
+// one replica.
+constexpr int kLaneCounts = 5;  // P = 1, 2, 4, 8, 16
+struct Reps {
+    const Geom *geom;       // [nrep]
+    const PairConst *pc;    // [nrep]; noise keys are set per launch from (seed, step)
+    const int *cell_off;    // [nrep + 1]
+    const int *part_off;    // [nrep + 1]
+    const int *blk_off;     // [kLaneCounts][nrep + 1]
+    int nrep;
+    int ncells;             // total cells
+    int nblk[kLaneCounts];  // total blocks per lane count
+};
+
+__host__ __device__ constexpr int lanes_index(int P) { return P == 1 ? 0 : P == 2 ? 1 : P == 4 ? 2 : P == 8 ? 3 : 4; }
+
+// Read-only table entry through the constant address space: the tables
+// never change while a kernel runs, so uniform reads become scalar loads and
+// the values live in scalar registers.
+template <typename T>
+__device__ __forceinline__ T cload(const T *p, int k)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const __attribute__((address_space(4))) T *)p)[k];
+#else
+    return p[k];  // host pass: never called
+#endif
+}
+
+// Largest r with off[r] <= x (off ascending, off[0] = 0 <= x).  With a
+// wave-uniform x the search is uniform.
+__device__ __forceinline__ int find_rep(const int *__restrict__ off, int nrep, int x)
+{
+    int lo = 0, hi = nrep;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cload(off, mid) <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Threefry key schedule for key (seed, step): ks2 = 0x1BD11BDA ^ k0 ^ k1 and
+// the injection after rounds 4s adds (ks[s % 3], ks[(s + 1) % 3] + s).
+__host__ __device__ inline void set_noise_keys(PairConst &pc, uint32_t step)
+{
+    const uint32_t k0 = pc.seed, k1 = step;
+    const uint32_t ks[3] = {k0, k1, 0x1BD11BDAu ^ k0 ^ k1};
+    pc.ks0 = ks[0];
+    pc.ks1 = ks[1];
+    for (uint32_t s = 1; s <= 5; ++s) {
+        pc.inj0[s - 1] = ks[s % 3];
+        pc.inj1[s - 1] = ks[(s + 1) % 3] + s;
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Device helpers
@@ -154,39 +217,40 @@ struct AdjConst {
     double mass;
 };
 
-// Host-side launchers (defined in the .hip files).
-void launch_ingest(hipStream_t st, int64_t n, const double *pos, const double *vel,
-                   const int32_t *type, const uint8_t *frozen, Geom g, int ntypes, Soa3 xp,
-                   Soa3 vp, uint32_t *tag, uint8_t *typ, int *status);
-void launch_sort(hipStream_t st, int n, Geom g, Soa3c xin, Soa3c vin, Soa3c xprev_in,
+// Host-side launchers (defined in the .hip files).  n is the total number
+// of particles over all replicas.
+void launch_ingest(hipStream_t st, const Reps &R, const double *pos, const double *vel,
+                   const int32_t *type, const uint8_t *frozen, Soa3 xp, Soa3 vp, uint32_t *tag,
+                   uint8_t *typ, int *status);
+void launch_sort(hipStream_t st, int n, const Reps &R, Soa3c xin, Soa3c vin, Soa3c xprev_in,
                  const uint32_t *tag_in, const uint8_t *typ_in, Soa3 xout, Soa3 vout,
                  Soa3 xprev_out, uint32_t *tag_out, uint8_t *typ_out, int *key, int *slot,
                  uint32_t *tmpid, int *counts, int *cstart, int *bsum, const int *gate,
-                 int *ovf_count);
-void launch_nlist(hipStream_t st, bool fp32, int n, Geom g, Soa3c xs, const int *cstart,
-                  int *ncnt, uint32_t *nl, void *nlr2, const int *gate);
-void launch_density(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g,
-                    Soa3c xs, const int *cstart, const int *ncnt, const uint32_t *nl,
-                    const void *nlr2, void *rho);
-void launch_phi(hipStream_t st, int lanes, int n, const PairConst &pc, Geom g, Soa3c xs,
-                Soa3c xprev, Soa3 xfix, Soa3 vfix, const uint32_t *tag, const int *cstart,
-                const int *ncnt, const uint32_t *nl, int *ncorr, unsigned long long *ncorr_total);
-void launch_force(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g,
+                 int *ovf_count, uint32_t *step_ctr);
+void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int *cstart, int *ncnt,
+                  uint32_t *nl, void *nlr2, const int *gate);
+void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c xs,
+                    const int *cstart, const int *ncnt, const void *nlr2, void *rho);
+void launch_phi(hipStream_t st, int lanes, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix,
+                Soa3 vfix, const uint32_t *tag, const int *cstart, const int *ncnt,
+                const uint32_t *nl, int *ncorr, unsigned long long *ncorr_total);
+// stepp: device word holding the noise step (advanced by the main sort).
+void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, const uint32_t *stepp,
                   Soa3c xs, Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ,
                   const int *cstart, const int *ncnt, const uint32_t *nl, Soa3 vout, Soa3 fout,
                   Soa3 vpred, Soa3 xpred, double *part, int *status, int *ovf_count, int *ovf,
                   double *ovf_ve, int initial);
-// Number of virial/energy block partials the force pass writes.
-int force_partials(int lanes, int n);
+// Number of virial/energy block partials the force pass writes with this
+// lane count (one per block; replica r owns its blocks' range).
+int force_partials(const Reps &R, int lanes);
 void launch_adj_seed(hipStream_t st, int n, const AdjConst &ac, Soa3c v, const uint32_t *tag, Soa3 U,
                      Soa3 fb, double *rhoA);
-void launch_adj_force(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g,
-                      const AdjConst &ac, Soa3c xs, Soa3c u, const void *rho, const uint32_t *tag,
-                      const uint8_t *typ, const int *cstart, const int *ncnt, const uint32_t *nl,
-                      Soa3c fb, Soa3 X, Soa3 U, double *rhoA, double *gp);
-void launch_adj_density(hipStream_t st, int lanes, int n, const PairConst &pc, Geom g, Soa3c xs,
-                        const int *cstart, const int *ncnt, const uint32_t *nl, const double *rhoA,
-                        Soa3 X);
+void launch_adj_force(hipStream_t st, int lanes, bool fp32, bool mt, int n, const Reps &R,
+                      uint32_t step, const AdjConst &ac, Soa3c xs, Soa3c u, const void *rho,
+                      const uint32_t *tag, const uint8_t *typ, const int *cstart, const int *ncnt,
+                      const uint32_t *nl, Soa3c fb, Soa3 X, Soa3 U, double *rhoA, double *gp);
+void launch_adj_density(hipStream_t st, int lanes, const Reps &R, Soa3c xs, const int *cstart,
+                        const int *ncnt, const uint32_t *nl, const double *rhoA, Soa3 X);
 void launch_adj_scatter(hipStream_t st, int n, double dt, const uint32_t *tag, Soa3c X, Soa3c U,
                         Soa3 Xid, Soa3 Uid);
 void launch_adj_gather(hipStream_t st, int n, const uint32_t *tag, Soa3c Xid, Soa3c Uid, Soa3 X,
@@ -194,20 +258,22 @@ void launch_adj_gather(hipStream_t st, int n, const uint32_t *tag, Soa3c Xid, So
 int adj_param_partials(int ntypes);
 void launch_adj_params(hipStream_t st, int n, int ntypes, const uint8_t *typ, const double *gp,
                        double *part, double *total);
-void launch_observables(hipStream_t st, bool fp32, int n, const PairConst &pc, Soa3c v,
+// Observables per replica: part needs obs_partials(R) doubles, out 16 per
+// replica (sums as listed at k_obs_final).
+int obs_partials(const Reps &R);
+void launch_observables(hipStream_t st, bool fp32, const Reps &R, int force_lanes, Soa3c v,
                         const void *rho, const uint32_t *tag, const uint8_t *typ,
-                        const double *fpart, int nfpart, const int *ncnt, const double *ovf_ve,
-                        double *out16);
-constexpr int kObsSlots = 16 + 1024 * 10;  // result slots + block partials
+                        const double *fpart, const int *ncnt, const double *ovf_ve, double *part,
+                        double *out);
 void launch_loss_accum(hipStream_t st, const double *obs16, double *acc, double inv_nf, double inv3V,
                        double mass, double scale);
 void launch_profile(hipStream_t st, bool fp32, int n, int axis, int nbins, int quantity, double La,
                     double binvol, double mass, Soa3c x, Soa3c v, const void *rho,
                     const uint32_t *tag, double *work, double *out);
-void launch_export(hipStream_t st, bool fp32, int n, Soa3c x, Soa3c v, const void *rho,
+void launch_export(hipStream_t st, bool fp32, const Reps &R, Soa3c x, Soa3c v, const void *rho,
                    const uint32_t *tag, double *pos, double *vel, double *rho_out);
-void launch_debug_neighbors(hipStream_t st, int n, Geom g, const PairConst &pc, double cutoff2,
-                            Soa3c xs, const uint32_t *tag, const int *cstart, const int *ncnt,
+void launch_debug_neighbors(hipStream_t st, const Reps &R, double cutoff2, Soa3c xs,
+                            const uint32_t *tag, const int *cstart, const int *ncnt,
                             const uint32_t *nl, int64_t *count, uint64_t *hash);
 void launch_zero_int(hipStream_t st, int *p, int n);
 

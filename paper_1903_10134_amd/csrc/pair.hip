@@ -63,15 +63,19 @@ __device__ __forceinline__ void emit_hit(uint32_t *__restrict__ out, R2 *__restr
 }
 
 template <typename R2>
-__global__ __launch_bounds__(kBlock) void k_nlist_cell(Geom g, int n, Soa3c xs,
-                                                       const int *__restrict__ cstart,
+__global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const int *__restrict__ cstart_all,
                                                        int *__restrict__ ncnt, uint32_t *__restrict__ nl,
                                                        R2 *__restrict__ nlr2, const int *__restrict__ gate)
 {
     if (gate && *gate == 0) return;
     const int lane = threadIdx.x & 63;
-    const int c = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
-    if (c >= g.ncells) return;
+    const int cg = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    if (cg >= R.ncells) return;
+    // the replica of this cell: its lattice, and its cell offsets (global slots)
+    const int rep = __builtin_amdgcn_readfirstlane(find_rep(R.cell_off, R.nrep, cg));
+    const Geom g = cload(R.geom, rep);
+    const int c = cg - cload(R.cell_off, rep);
+    const int *__restrict__ cstart = cstart_all + cload(R.cell_off, rep);
     const int i0 = cstart[c], ni = cstart[c + 1] - i0;
     if (ni == 0) return;
     const int nx = g.nc[0], ny = g.nc[1], nz = g.nc[2];
@@ -253,15 +257,17 @@ __device__ __forceinline__ float w_rho<float>(const PairConst &pc, float r2)
 }
 
 template <int P, typename R>
-__global__ __launch_bounds__(kBlock) void k_density(PairConst pc, Geom g, int n, Soa3c xs,
-                                                    const int *__restrict__ cstart,
+__global__ __launch_bounds__(kBlock) void k_density(Reps Rp, Soa3c xs, const int *__restrict__ cstart_all,
                                                     const int *__restrict__ ncnt,
                                                     const R *__restrict__ nlr2, R *__restrict__ rho)
 {
-    const int t = xcd_block() * kBlock + threadIdx.x;
-    const int i = t / P;
-    const int sub = t & (P - 1);
-    if (i >= n) return;
+    const BlockRep br = block_rep<P>(Rp, xcd_block());
+    const int i = br.i0 + (int)threadIdx.x / P;
+    const int sub = threadIdx.x & (P - 1);
+    if (i >= br.i1) return;
+    const PairConst pc = cload(Rp.pc, br.r);
+    const Geom g = cload(Rp.geom, br.r);
+    const int *__restrict__ cstart = cstart_all + cload(Rp.cell_off, br.r);
     const int packed = ncnt[i];
     R acc = 0;
     if (list_total(packed) <= kListCap) {
@@ -286,16 +292,18 @@ __global__ __launch_bounds__(kBlock) void k_density(PairConst pc, Geom g, int n,
 // phi_i = sum_{frozen j} w_c^2 / sum_j w_c^2 over neighbours within r_c at the
 // predicted positions; flag[i] = 1 when phi_i > phi_c (fluid only).
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_phi(PairConst pc, Geom g, int n, Soa3c xs,
-                                                const uint32_t *__restrict__ tag,
-                                                const int *__restrict__ cstart,
+__global__ __launch_bounds__(kBlock) void k_phi(Reps R, Soa3c xs, const uint32_t *__restrict__ tag,
+                                                const int *__restrict__ cstart_all,
                                                 const int *__restrict__ ncnt,
                                                 const uint32_t *__restrict__ nl, int *__restrict__ flag)
 {
-    const int t = xcd_block() * kBlock + threadIdx.x;
-    const int i = t / P;
-    const int sub = t & (P - 1);
-    if (i >= n) return;
+    const BlockRep br = block_rep<P>(R, xcd_block());
+    const int i = br.i0 + (int)threadIdx.x / P;
+    const int sub = threadIdx.x & (P - 1);
+    if (i >= br.i1) return;
+    const PairConst pc = cload(R.pc, br.r);
+    const Geom g = cload(R.geom, br.r);
+    const int *__restrict__ cstart = cstart_all + cload(R.cell_off, br.r);
     if (tag[i] & kFrozenBit) {
         if (sub == 0) flag[i] = 0;
         return;
@@ -533,7 +541,7 @@ __device__ __forceinline__ void block_partials(double vir, double ep, double *pa
 }
 
 template <int P, bool MT, typename R>
-__global__ __launch_bounds__(kBlock) void k_force(PairConst pc, Geom g, int n, Soa3c xs, Soa3c vh,
+__global__ __launch_bounds__(kBlock) void k_force(Reps Rp, const uint32_t *__restrict__ stepp, Soa3c xs, Soa3c vh,
                                                   const R *__restrict__ rho,
                                                   const uint32_t *__restrict__ tag,
                                                   const uint8_t *__restrict__ typ,
@@ -541,11 +549,14 @@ __global__ __launch_bounds__(kBlock) void k_force(PairConst pc, Geom g, int n, S
                                                   const uint32_t *__restrict__ nl, ForceOut out)
 {
     const int blk = xcd_block();
-    const int t = blk * kBlock + threadIdx.x;
-    const int i = t / P;
-    const int sub = t & (P - 1);
+    const BlockRep br = block_rep<P>(Rp, blk);
+    const int i = br.i0 + (int)threadIdx.x / P;
+    const int sub = threadIdx.x & (P - 1);
+    PairConst pc = cload(Rp.pc, br.r);
+    set_noise_keys(pc, cload(stepp, 0));
+    const Geom g = cload(Rp.geom, br.r);
     double vir = 0.0, ep = 0.0;
-    if (i < n) {
+    if (i < br.i1) {
         const int packed = ncnt[i];
         if (list_total(packed) <= kListCap) {
             force_particle<P, MT, false, R>(pc, g, i, sub, xs, vh, rho, tag, typ, nullptr, packed,
@@ -565,11 +576,12 @@ __global__ __launch_bounds__(kBlock) void k_force(PairConst pc, Geom g, int n, S
 constexpr int kOverflowBlocks = 32;
 
 template <bool MT, typename R>
-__global__ __launch_bounds__(kBlock) void k_force_overflow(PairConst pc, Geom g, Soa3c xs, Soa3c vh,
+__global__ __launch_bounds__(kBlock) void k_force_overflow(Reps Rp, const uint32_t *__restrict__ stepp, Soa3c xs,
+                                                           Soa3c vh,
                                                            const R *__restrict__ rho,
                                                            const uint32_t *__restrict__ tag,
                                                            const uint8_t *__restrict__ typ,
-                                                           const int *__restrict__ cstart,
+                                                           const int *__restrict__ cstart_all,
                                                            const int *__restrict__ ncnt, ForceOut out,
                                                            double *__restrict__ ovf_ve)
 {
@@ -580,9 +592,13 @@ __global__ __launch_bounds__(kBlock) void k_force_overflow(PairConst pc, Geom g,
     const int sub = t & (P - 1);
     for (int q = t / P; q < count; q += groups) {
         const int i = out.ovf[q];
+        const int r = find_rep(Rp.part_off, Rp.nrep, i);  // per lane: queued particles mix replicas
+        PairConst pc = Rp.pc[r];
+        set_noise_keys(pc, *stepp);
+        const Geom g = Rp.geom[r];
         double vir = 0.0, ep = 0.0;
-        force_particle<P, MT, true, R>(pc, g, i, sub, xs, vh, rho, tag, typ, cstart, ncnt[i], nullptr, out, vir,
-                                       ep);
+        force_particle<P, MT, true, R>(pc, g, i, sub, xs, vh, rho, tag, typ, cstart_all + cload(Rp.cell_off, r),
+                                       ncnt[i], nullptr, out, vir, ep);
         vir = group_sum<P>(vir);
         ep = group_sum<P>(ep);
         if (sub == 0) {
@@ -601,16 +617,20 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
-__global__ __launch_bounds__(kBlock) void k_debug_neighbors(PairConst pc, Geom g, int n, double cut2,
+__global__ __launch_bounds__(kBlock) void k_debug_neighbors(Reps R, double cut2,
                                                             Soa3c xs, const uint32_t *__restrict__ tag,
-                                                            const int *__restrict__ cstart,
+                                                            const int *__restrict__ cstart_all,
                                                             const int *__restrict__ ncnt,
                                                             const uint32_t *__restrict__ nl,
                                                             int64_t *__restrict__ count,
                                                             uint64_t *__restrict__ hash)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+    const BlockRep br = block_rep<1>(R, blockIdx.x);
+    const int i = br.i0 + (int)threadIdx.x;
+    if (i >= br.i1) return;
+    const PairConst pc = cload(R.pc, br.r);
+    const Geom g = cload(R.geom, br.r);
+    const int *__restrict__ cstart = cstart_all + cload(R.cell_off, br.r);
     const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
     int64_t c = 0;
     uint64_t h = 0;
@@ -621,102 +641,96 @@ __global__ __launch_bounds__(kBlock) void k_debug_neighbors(PairConst pc, Geom g
                                  h += mix64((uint64_t)(tag[j] & kIdMask));
                              }
                          });
-    const uint32_t id = tag[i] & kIdMask;
-    count[id] = c;
-    hash[id] = h;
+    const size_t out = (size_t)cload(R.part_off, br.r) + (tag[i] & kIdMask);  // input order
+    count[out] = c;
+    hash[out] = h;
 }
 
 }  // namespace
 
-int force_partials(int lanes, int n) { return blocks_for((int64_t)n * lanes); }
+template <typename T>
+struct Tid {
+    using type = T;
+};
 
-void launch_nlist(hipStream_t st, bool fp32, int n, Geom g, Soa3c xs, const int *cstart, int *ncnt,
+int force_partials(const Reps &R, int lanes) { return R.nblk[lanes_index(lanes)]; }
+
+void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int *cstart, int *ncnt,
                   uint32_t *nl, void *nlr2, const int *gate)
 {
-    if (n <= 0) return;
-    const int blocks = (g.ncells + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (R.ncells <= 0) return;
+    const int blocks = (R.ncells + kWavesPerBlock - 1) / kWavesPerBlock;
     if (fp32)
-        k_nlist_cell<float><<<blocks, kBlock, 0, st>>>(g, n, xs, cstart, ncnt, nl, (float *)nlr2, gate);
+        k_nlist_cell<float><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (float *)nlr2, gate);
     else
-        k_nlist_cell<double><<<blocks, kBlock, 0, st>>>(g, n, xs, cstart, ncnt, nl, (double *)nlr2, gate);
+        k_nlist_cell<double><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (double *)nlr2, gate);
 }
 
-void launch_density(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g, Soa3c xs,
-                    const int *cstart, const int *ncnt, const uint32_t *nl, const void *nlr2, void *rho)
+void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c xs, const int *cstart,
+                    const int *ncnt, const void *nlr2, void *rho)
 {
-    if (n <= 0) return;
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
+        const int nb = R.nblk[lanes_index(L)];
+        if (nb <= 0) return;
         if (fp32)
-            k_density<L, float><<<blocks_for((int64_t)n * L), kBlock, 0, st>>>(
-                pc, g, n, xs, cstart, ncnt, (const float *)nlr2, (float *)rho);
+            k_density<L, float><<<nb, kBlock, 0, st>>>(R, xs, cstart, ncnt, (const float *)nlr2, (float *)rho);
         else
-            k_density<L, double><<<blocks_for((int64_t)n * L), kBlock, 0, st>>>(
-                pc, g, n, xs, cstart, ncnt, (const double *)nlr2, (double *)rho);
-    (void)nl;
+            k_density<L, double><<<nb, kBlock, 0, st>>>(R, xs, cstart, ncnt, (const double *)nlr2,
+                                                        (double *)rho);
     });
 }
 
-void launch_phi(hipStream_t st, int lanes, int n, const PairConst &pc, Geom g, Soa3c xs, Soa3c xprev,
-                Soa3 xfix, Soa3 vfix, const uint32_t *tag, const int *cstart, const int *ncnt,
-                const uint32_t *nl, int *flag_and_count, unsigned long long *ncorr_total)
+void launch_phi(hipStream_t st, int lanes, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix, Soa3 vfix,
+                const uint32_t *tag, const int *cstart, const int *ncnt, const uint32_t *nl,
+                int *flag_and_count, unsigned long long *ncorr_total)
 {
     if (n <= 0) return;
     int *ncorr = flag_and_count;       // [0]: corrections this step
     int *flag = flag_and_count + 1;    // [1..n]: per-slot flags
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
-        k_phi<L><<<blocks_for((int64_t)n * L), kBlock, 0, st>>>(pc, g, n, xs, tag, cstart, ncnt, nl, flag);
+        k_phi<L><<<R.nblk[lanes_index(L)], kBlock, 0, st>>>(R, xs, tag, cstart, ncnt, nl, flag);
     });
     k_correct<<<blocks_for(n), kBlock, 0, st>>>(n, flag, xprev, xfix, vfix, ncorr, ncorr_total);
 }
 
-void launch_force(hipStream_t st, int lanes, bool fp32, int n, const PairConst &pc, Geom g, Soa3c xs,
+void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, const uint32_t *stepp, Soa3c xs,
                   Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ, const int *cstart,
                   const int *ncnt, const uint32_t *nl, Soa3 vout, Soa3 fout, Soa3 vpred, Soa3 xpred,
                   double *part, int *status, int *ovf_count, int *ovf, double *ovf_ve, int initial)
 {
-    if (n <= 0) return;
-    const bool mt = pc.ntypes > 1;
     const ForceOut out{vout, fout, vpred, xpred, part, status, ovf_count, ovf, initial};
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
-        const int nb = blocks_for((int64_t)n * L);
+        const int nb = R.nblk[lanes_index(L)];
+        if (nb <= 0) return;
+        auto go = [&](auto mtc, auto rc) {
+            constexpr bool M = decltype(mtc)::value;
+            using RT = typename decltype(rc)::type;
+            k_force<L, M, RT><<<nb, kBlock, 0, st>>>(R, stepp, xs, vh, (const RT *)rho, tag, typ, ncnt, nl, out);
+            k_force_overflow<M, RT><<<kOverflowBlocks, kBlock, 0, st>>>(R, stepp, xs, vh, (const RT *)rho, tag,
+                                                                        typ, cstart, ncnt, out, ovf_ve);
+        };
+        using T = std::true_type;
+        using F = std::false_type;
         if (fp32) {
-            if (mt) {
-                k_force<L, true, float><<<nb, kBlock, 0, st>>>(pc, g, n, xs, vh, (const float *)rho, tag, typ,
-                                                               ncnt, nl, out);
-                k_force_overflow<true, float><<<kOverflowBlocks, kBlock, 0, st>>>(
-                    pc, g, xs, vh, (const float *)rho, tag, typ, cstart, ncnt, out, ovf_ve);
-            } else {
-                k_force<L, false, float><<<nb, kBlock, 0, st>>>(pc, g, n, xs, vh, (const float *)rho, tag, typ,
-                                                                ncnt, nl, out);
-                k_force_overflow<false, float><<<kOverflowBlocks, kBlock, 0, st>>>(
-                    pc, g, xs, vh, (const float *)rho, tag, typ, cstart, ncnt, out, ovf_ve);
-            }
+            if (mt) go(T{}, Tid<float>{});
+            else go(F{}, Tid<float>{});
         } else {
-            if (mt) {
-                k_force<L, true, double><<<nb, kBlock, 0, st>>>(pc, g, n, xs, vh, (const double *)rho, tag,
-                                                                typ, ncnt, nl, out);
-                k_force_overflow<true, double><<<kOverflowBlocks, kBlock, 0, st>>>(
-                    pc, g, xs, vh, (const double *)rho, tag, typ, cstart, ncnt, out, ovf_ve);
-            } else {
-                k_force<L, false, double><<<nb, kBlock, 0, st>>>(pc, g, n, xs, vh, (const double *)rho, tag,
-                                                                 typ, ncnt, nl, out);
-                k_force_overflow<false, double><<<kOverflowBlocks, kBlock, 0, st>>>(
-                    pc, g, xs, vh, (const double *)rho, tag, typ, cstart, ncnt, out, ovf_ve);
-            }
+            if (mt) go(T{}, Tid<double>{});
+            else go(F{}, Tid<double>{});
         }
     });
 }
 
-void launch_debug_neighbors(hipStream_t st, int n, Geom g, const PairConst &pc, double cutoff2, Soa3c xs,
-                            const uint32_t *tag, const int *cstart, const int *ncnt, const uint32_t *nl,
-                            int64_t *count, uint64_t *hash)
+void launch_debug_neighbors(hipStream_t st, const Reps &R, double cut2, Soa3c xs, const uint32_t *tag,
+                            const int *cstart, const int *ncnt, const uint32_t *nl, int64_t *count,
+                            uint64_t *hash)
 {
-    if (n <= 0) return;
-    k_debug_neighbors<<<blocks_for(n), kBlock, 0, st>>>(pc, g, n, cutoff2, xs, tag, cstart, ncnt, nl,
-                                                        count, hash);
+    const int nb = R.nblk[0];
+    if (nb <= 0) return;
+    k_debug_neighbors<<<nb, kBlock, 0, st>>>(R, cut2, xs, tag, cstart, ncnt, nl, count, hash);
 }
 
 }  // namespace mdpd

@@ -154,6 +154,20 @@ __device__ __forceinline__ void for_each_neighbor(const PairConst &pc, const Geo
     }
 }
 
+// The replica of this (replica-aligned) block and the slot range its P-lane
+// groups cover: particle i0 + threadIdx.x / P, valid while below i1.
+struct BlockRep {
+    int r, i0, i1;
+};
+
+template <int P>
+__device__ __forceinline__ BlockRep block_rep(const Reps &R, int blk)
+{
+    const int *off = R.blk_off + lanes_index(P) * (R.nrep + 1);
+    const int r = __builtin_amdgcn_readfirstlane(find_rep(off, R.nrep, blk));
+    return BlockRep{r, cload(R.part_off, r) + (blk - cload(off, r)) * (kBlock / P), cload(R.part_off, r + 1)};
+}
+
 // Host: instantiate a launch for the lane count P in {1, 2, 4, 8, 16}.
 template <typename K>
 void launch_lanes(int lanes, K &&k)

@@ -30,54 +30,67 @@ __device__ __forceinline__ void block_tree(double (*sh)[kRed], double *v)
     for (int k = 0; k < W; ++k) v[k] = sh[k][0];
 }
 
+// Block partials over one replica-aligned block of kRed particles:
+// [0] sum m-less |v|^2, [1..3] sum v, [4] sum rho, [5] sum B_ii rho^2,
+// [6] fluid count, [8] virial and [9] pair-energy shares of particles whose
+// neighbour list overflowed.
 template <typename R>
-__global__ __launch_bounds__(kRed) void k_obs_partial(int n, PairConst pc, Soa3c v, const R *rho,
-                                                      const uint32_t *tag, const uint8_t *typ,
-                                                      const int *ncnt, const double *ovf_ve, double *part)
+__global__ __launch_bounds__(kRed) void k_obs_partial(Reps Rp, Soa3c v, const R *rho, const uint32_t *tag,
+                                                      const uint8_t *typ, const int *ncnt, const double *ovf_ve,
+                                                      double *part)
 {
     __shared__ double sh[kObs][kRed];
     double acc[kObs] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = blockIdx.x * kRed + threadIdx.x; i < n; i += gridDim.x * kRed) {
+    const int *boff = Rp.blk_off;  // lane count 1
+    const int r = __builtin_amdgcn_readfirstlane(find_rep(boff, Rp.nrep, blockIdx.x));
+    const int i = cload(Rp.part_off, r) + (blockIdx.x - cload(boff, r)) * kRed + threadIdx.x;
+    const PairConst pc = cload(Rp.pc, r);
+    if (i < cload(Rp.part_off, r + 1)) {
         const int c = ncnt[i];
         if ((c & 0xffff) + (c >> 16) > kListCap) {  // list overflowed: force pass wrote its share here
             acc[8] += ovf_ve[2 * (size_t)i];
             acc[9] += ovf_ve[2 * (size_t)i + 1];
         }
-        const double r = (double)rho[i];
+        const double rr = (double)rho[i];
         const int t = pc.ntypes > 1 ? (int)typ[i] : 0;
         const double B = pc.ntypes > 1 ? pc.tab[64 + t * pc.ntypes + t] : pc.B;
-        acc[5] += B * r * r;
-        if (tag[i] & kFrozenBit) continue;
-        const double vx = v.x[i], vy = v.y[i], vz = v.z[i];
-        acc[0] += vx * vx + vy * vy + vz * vz;
-        acc[1] += vx;
-        acc[2] += vy;
-        acc[3] += vz;
-        acc[4] += r;
-        acc[6] += 1.0;
+        acc[5] += B * rr * rr;
+        if (!(tag[i] & kFrozenBit)) {
+            const double vx = v.x[i], vy = v.y[i], vz = v.z[i];
+            acc[0] += vx * vx + vy * vy + vz * vz;
+            acc[1] += vx;
+            acc[2] += vy;
+            acc[3] += vz;
+            acc[4] += rr;
+            acc[6] += 1.0;
+        }
     }
     block_tree<kObs>(sh, acc);
     if (threadIdx.x == 0)
-        for (int k = 0; k < kObs; ++k) part[blockIdx.x * kObs + k] = acc[k];
+        for (int k = 0; k < kObs; ++k) part[(size_t)blockIdx.x * kObs + k] = acc[k];
 }
 
-// Final fixed-order sums: out[0..7] observables partials, out[8] virial,
-// out[9] pair energy (force-pass block partials plus the overflowed
-// particles' shares).
-__global__ __launch_bounds__(kRed) void k_obs_final(int nb, const double *part, int nf,
+// One block per replica, fixed-order sums: out[16 r + 0..7] observables
+// partials, [8] virial, [9] pair energy (force-pass block partials of the
+// replica's blocks plus the overflowed particles' shares).
+__global__ __launch_bounds__(kRed) void k_obs_final(Reps Rp, int force_li, const double *part,
                                                     const double *fpart, double *out)
 {
     __shared__ double sh[10][kRed];
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nb; b += kRed)
-        for (int k = 0; k < kObs; ++k) acc[k] += part[b * kObs + k];
-    for (int b = threadIdx.x; b < nf; b += kRed) {
-        acc[8] += fpart[2 * b];
-        acc[9] += fpart[2 * b + 1];
-    }
+    const int r = blockIdx.x;
+    const int *b1 = Rp.blk_off;
+    const int *bf = Rp.blk_off + force_li * (Rp.nrep + 1);
+    for (int b = b1[r] + threadIdx.x; b < b1[r + 1]; b += kRed)
+        for (int k = 0; k < kObs; ++k) acc[k] += part[(size_t)b * kObs + k];
+    if (fpart)
+        for (int b = bf[r] + threadIdx.x; b < bf[r + 1]; b += kRed) {
+            acc[8] += fpart[2 * (size_t)b];
+            acc[9] += fpart[2 * (size_t)b + 1];
+        }
     block_tree<10>(sh, acc);
     if (threadIdx.x == 0)
-        for (int k = 0; k < 10; ++k) out[k] = acc[k];
+        for (int k = 0; k < 10; ++k) out[16 * r + k] = acc[k];
 }
 
 // Bin sums for one bin per block: count, sum v (3), sum rho, and (second
@@ -139,14 +152,18 @@ __global__ void k_profile_final(int nbins, int quantity, double binvol, double m
     out[b] = r;
 }
 
+// Scatter to input order: replica r's particle with id k goes to row
+// part_off[r] + k.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_export(int n, Soa3c x, Soa3c v, const R *rho,
+__global__ __launch_bounds__(kBlock) void k_export(Reps Rp, Soa3c x, Soa3c v, const R *rho,
                                                    const uint32_t *tag, double *pos, double *vel,
                                                    double *rho_out)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const size_t id = tag[i] & kIdMask;
+    const int *boff = Rp.blk_off;  // lane count 1
+    const int r = __builtin_amdgcn_readfirstlane(find_rep(boff, Rp.nrep, blockIdx.x));
+    const int i = cload(Rp.part_off, r) + (blockIdx.x - cload(boff, r)) * kBlock + threadIdx.x;
+    if (i >= cload(Rp.part_off, r + 1)) return;
+    const size_t id = (size_t)cload(Rp.part_off, r) + (tag[i] & kIdMask);
     if (pos) {
         pos[3 * id] = x.x[i];
         pos[3 * id + 1] = x.y[i];
@@ -179,22 +196,20 @@ void launch_loss_accum(hipStream_t st, const double *obs16, double *acc, double 
     k_loss_accum<<<1, 64, 0, st>>>(obs16, acc, inv_nf, inv3V, mass, scale);
 }
 
-void launch_observables(hipStream_t st, bool fp32, int n, const PairConst &pc, Soa3c v, const void *rho,
-                        const uint32_t *tag, const uint8_t *typ, const double *fpart, int nfpart,
-                        const int *ncnt, const double *ovf_ve, double *out16)
+int obs_partials(const Reps &R) { return R.nblk[0] * kObs; }
+
+void launch_observables(hipStream_t st, bool fp32, const Reps &R, int force_lanes, Soa3c v, const void *rho,
+                        const uint32_t *tag, const uint8_t *typ, const double *fpart, const int *ncnt,
+                        const double *ovf_ve, double *part, double *out)
 {
-    // out16: 16 result slots followed by up to 1024 x kObs block partials.
-    const int nb = n > 0 ? (blocks_for(n) < 1024 ? blocks_for(n) : 1024) : 0;
-    double *part = out16 + 16;
-    if (nb > 0) {
+    if (R.nblk[0] > 0) {
         if (fp32)
-            k_obs_partial<float><<<nb, kRed, 0, st>>>(n, pc, v, (const float *)rho, tag, typ, ncnt, ovf_ve,
-                                                      part);
+            k_obs_partial<float><<<R.nblk[0], kRed, 0, st>>>(R, v, (const float *)rho, tag, typ, ncnt, ovf_ve, part);
         else
-            k_obs_partial<double><<<nb, kRed, 0, st>>>(n, pc, v, (const double *)rho, tag, typ, ncnt, ovf_ve,
-                                                       part);
+            k_obs_partial<double><<<R.nblk[0], kRed, 0, st>>>(R, v, (const double *)rho, tag, typ, ncnt, ovf_ve,
+                                                              part);
     }
-    k_obs_final<<<1, kRed, 0, st>>>(nb, part, nfpart, fpart, out16);
+    k_obs_final<<<R.nrep, kRed, 0, st>>>(R, lanes_index(force_lanes), part, fpart, out);
 }
 
 void launch_profile(hipStream_t st, bool fp32, int n, int axis, int nbins, int quantity, double La,
@@ -219,16 +234,14 @@ void launch_profile(hipStream_t st, bool fp32, int n, int axis, int nbins, int q
     k_profile_final<<<(nbins + 255) / 256, 256, 0, st>>>(nbins, quantity, binvol, mass, wk, out);
 }
 
-void launch_export(hipStream_t st, bool fp32, int n, Soa3c x, Soa3c v, const void *rho, const uint32_t *tag,
-                   double *pos, double *vel, double *rho_out)
+void launch_export(hipStream_t st, bool fp32, const Reps &R, Soa3c x, Soa3c v, const void *rho,
+                   const uint32_t *tag, double *pos, double *vel, double *rho_out)
 {
-    if (n <= 0) return;
+    if (R.nblk[0] <= 0) return;
     if (fp32)
-        k_export<float><<<blocks_for(n), kBlock, 0, st>>>(n, x, v, (const float *)rho, tag, pos, vel,
-                                                          rho_out);
+        k_export<float><<<R.nblk[0], kBlock, 0, st>>>(R, x, v, (const float *)rho, tag, pos, vel, rho_out);
     else
-        k_export<double><<<blocks_for(n), kBlock, 0, st>>>(n, x, v, (const double *)rho, tag, pos, vel,
-                                                           rho_out);
+        k_export<double><<<R.nblk[0], kBlock, 0, st>>>(R, x, v, (const double *)rho, tag, pos, vel, rho_out);
 }
 
 }  // namespace mdpd

@@ -29,20 +29,30 @@ inline int blocks_for(int64_t threads) { return (int)((threads + kBlock - 1) / k
 // were sorted one step ago), so lanes whose key equals the previous lane's
 // form runs; the first lane of a run reserves the whole run with one atomic
 // and the others take consecutive slots after it.
-__global__ __launch_bounds__(kBlock) void k_bin(int n, Geom g, Soa3c x, int *__restrict__ key,
+// Blocks are replica-aligned (kBlock particles of one replica), and the key
+// is the global cell: the replica's first cell plus its local cell.
+__global__ __launch_bounds__(kBlock) void k_bin(Reps R, Soa3c x, int *__restrict__ key,
                                                 int *__restrict__ slot, int *__restrict__ counts,
-                                                const int *__restrict__ gate, int *__restrict__ ovf_count)
+                                                const int *__restrict__ gate, int *__restrict__ ovf_count,
+                                                uint32_t *__restrict__ step_ctr)
 {
     if (gate && *gate == 0) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (ovf_count && i == 0) *ovf_count = 0;  // the force pass of this step refills it
+    const int *boff = R.blk_off;  // lane count 1
+    const int r = __builtin_amdgcn_readfirstlane(find_rep(boff, R.nrep, blockIdx.x));
+    const int i = cload(R.part_off, r) + (blockIdx.x - cload(boff, r)) * kBlock + threadIdx.x;
+    const int n = cload(R.part_off, r + 1);  // end of this replica's slots
+    if (ovf_count && i == 0) {
+        *ovf_count = 0;  // the force pass of this step refills it
+        *step_ctr += 1;  // noise step of this step's force pass
+    }
+    const Geom g = cload(R.geom, r);
     const int lane = threadIdx.x & 63;
     int c = -1;
     if (i < n) {
         const int cx = cell_coord(x.x[i], g.s[0], g.nc[0]);
         const int cy = cell_coord(x.y[i], g.s[1], g.nc[1]);
         const int cz = cell_coord(x.z[i], g.s[2], g.nc[2]);
-        c = cx + g.nc[0] * (cy + g.nc[1] * cz);
+        c = cload(R.cell_off, r) + cx + g.nc[0] * (cy + g.nc[1] * cz);
         key[i] = c;
     }
     const int prev = __shfl_up(c, 1, 64);
@@ -215,17 +225,22 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const int *__rest
     typ_out[dst] = typ_in[i];
 }
 
-// Input arrays (AoS n x 3, caller order) to SoA predicted state; validates.
-__global__ __launch_bounds__(kBlock) void k_ingest(int n, const double *__restrict__ pos,
+// Input arrays (AoS n x 3, caller order: replica after replica) to SoA
+// predicted state; validates against the replica's box and type count.  The
+// id of a particle is its index inside its replica.
+__global__ __launch_bounds__(kBlock) void k_ingest(Reps R, const double *__restrict__ pos,
                                                    const double *__restrict__ vel,
                                                    const int32_t *__restrict__ type,
-                                                   const uint8_t *__restrict__ frozen, Geom g,
-                                                   int ntypes, Soa3 xp, Soa3 vp,
+                                                   const uint8_t *__restrict__ frozen, Soa3 xp, Soa3 vp,
                                                    uint32_t *__restrict__ tag,
                                                    uint8_t *__restrict__ typ, int *__restrict__ status)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+    const int *boff = R.blk_off;  // lane count 1
+    const int r = __builtin_amdgcn_readfirstlane(find_rep(boff, R.nrep, blockIdx.x));
+    const int i = cload(R.part_off, r) + (blockIdx.x - cload(boff, r)) * kBlock + threadIdx.x;
+    if (i >= cload(R.part_off, r + 1)) return;
+    const Geom g = cload(R.geom, r);
+    const int ntypes = cload(R.pc, r).ntypes;
     const bool fz = frozen[i] != 0;
     double q[3], w[3];
     bool ok = true;
@@ -249,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_ingest(int n, const double *__restri
     vp.x[i] = w[0];
     vp.y[i] = w[1];
     vp.z[i] = w[2];
-    tag[i] = (uint32_t)i | (fz ? kFrozenBit : 0u);
+    tag[i] = (uint32_t)(i - cload(R.part_off, r)) | (fz ? kFrozenBit : 0u);
     typ[i] = (uint8_t)(t >= 0 && t < ntypes ? t : 0);
 }
 
@@ -266,23 +281,21 @@ void launch_zero_int(hipStream_t st, int *p, int n)
     if (n > 0) k_zero_int<<<blocks_for(n), kBlock, 0, st>>>(p, n);
 }
 
-void launch_ingest(hipStream_t st, int64_t n, const double *pos, const double *vel, const int32_t *type,
-                   const uint8_t *frozen, Geom g, int ntypes, Soa3 xp, Soa3 vp, uint32_t *tag,
-                   uint8_t *typ, int *status)
+void launch_ingest(hipStream_t st, const Reps &R, const double *pos, const double *vel, const int32_t *type,
+                   const uint8_t *frozen, Soa3 xp, Soa3 vp, uint32_t *tag, uint8_t *typ, int *status)
 {
-    if (n <= 0) return;
-    k_ingest<<<blocks_for(n), kBlock, 0, st>>>((int)n, pos, vel, type, frozen, g, ntypes, xp, vp, tag,
-                                               typ, status);
+    if (R.nblk[0] <= 0) return;
+    k_ingest<<<R.nblk[0], kBlock, 0, st>>>(R, pos, vel, type, frozen, xp, vp, tag, typ, status);
 }
 
-void launch_sort(hipStream_t st, int n, Geom g, Soa3c xin, Soa3c vin, Soa3c xprev_in,
+void launch_sort(hipStream_t st, int n, const Reps &R, Soa3c xin, Soa3c vin, Soa3c xprev_in,
                  const uint32_t *tag_in, const uint8_t *typ_in, Soa3 xout, Soa3 vout, Soa3 xprev_out,
                  uint32_t *tag_out, uint8_t *typ_out, int *key, int *slot, uint32_t *tmpid, int *counts,
-                 int *cstart, int *bsum, const int *gate, int *ovf_count)
+                 int *cstart, int *bsum, const int *gate, int *ovf_count, uint32_t *step_ctr)
 {
-    const int m = g.ncells;
+    const int m = R.ncells;
     const int nb = (m + kScanTile - 1) / kScanTile;
-    if (n > 0) k_bin<<<blocks_for(n), kBlock, 0, st>>>(n, g, xin, key, slot, counts, gate, ovf_count);
+    if (n > 0) k_bin<<<R.nblk[0], kBlock, 0, st>>>(R, xin, key, slot, counts, gate, ovf_count, step_ctr);
     k_scan_local<<<nb, kScanThreads, 0, st>>>(m, counts, cstart, bsum, gate);
     k_scan_top<<<1, kScanThreads, 0, st>>>(nb, m, bsum, cstart, gate);
     k_scan_add<<<nb, kScanThreads, 0, st>>>(m, bsum, cstart, gate);

@@ -65,7 +65,10 @@ def check(mdpd, w, prec, nsteps, every, avg, tol):
     for lname, wts in LOSSES.items():
         gr = s.backward(wts)
         L_o, _ = oracle.tangent(op, w.x, w.v, w.types, w.frozen, nsteps, wts, avg)
-        assert float(np.dot(loss, wts)) == pytest.approx(L_o, rel=max(tol, 1e-11), abs=1e-11), lname
+        # the FP32 form does not conserve momentum exactly (f_ij and f_ji are
+        # rounded separately), so the mean velocity drifts at FP32 rounding
+        floor = 1e-11 if prec == "fp64" else 1e-6
+        assert float(np.dot(loss, wts)) == pytest.approx(L_o, rel=max(tol, 1e-11), abs=floor), lname
         checks = [("x0", float(np.sum(gr["dx0"] * dx)), dict(dx0=dx)),
                   ("v0", float(np.sum(gr["dv0"] * dv)), dict(dv0=dv))]
         for (a, b), E in table_dirs(T):
