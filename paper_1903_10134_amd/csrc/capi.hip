@@ -75,7 +75,7 @@ struct mdpd_system {
     int n = 0;
     bool fp32 = false;
     bool walls = false;
-    int lanes[3] = {4, 4, 4};  // neighbour list, density (and phi), force
+    int lanes[3] = {4, 4, 4};  // neighbour list (unused), density (and phi), force
     // replicas (a single system is one replica)
     int nrep = 1;
     bool mt = false;  // some replica has more than one type
@@ -96,6 +96,7 @@ struct mdpd_system {
     uint32_t *nl = nullptr;
     void *nlr2 = nullptr;
     uint32_t *tmpid = nullptr;
+    PartRec *rec = nullptr;  // packed neighbour records of the current step
     double *fpart = nullptr;
     int force_lanes_used = 4;  // lane count of the last force launch (its partials layout)
     int *status = nullptr;
@@ -293,13 +294,14 @@ struct mdpd_system {
             toc(1);
         }
         tic(2);
-        launch_density(st, lanes[1], fp32, R, cview(xs[cur]), cstart, ncnt, nlr2, rho);
+        launch_density(st, lanes[1], fp32, R, cview(xs[cur]), cview(vh[cur]), tag[cur], typ[cur], cstart, ncnt,
+                       nlr2, rho, rec);
         toc(2);
         force_lanes_used = lanes[2];
         tic(3);
         (void)stepno;  // the device word dstep holds it
         launch_force(st, lanes[2], fp32, mt, R, dstep, cview(xs[cur]), cview(vh[cur]), rho, tag[cur], typ[cur],
-                     cstart, ncnt, nl, v, F, vpred, xpred, fpart, status, ovf, ovf + 1, ovf_ve, initial);
+                     rec, cstart, ncnt, nl, v, F, vpred, xpred, fpart, status, ovf, ovf + 1, ovf_ve, initial);
         toc(3);
     }
 };
@@ -464,6 +466,7 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     s->n = (int)n;
     s->nrep = nrep;
     s->fp32 = ps[0].precision == MDPD_FP32_FORCES;
+    s->lanes[2] = s->fp32 ? 8 : 4;  // measured best force split at 1M particles
     s->walls = ps[0].wall_model == MDPD_WALL_BVF;
     s->params.assign(ps, ps + nrep);
     s->geoms.resize(nrep);
@@ -526,6 +529,7 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     ALLOC(s->alloc(&s->key, N));
     ALLOC(s->alloc(&s->slot, N));
     ALLOC(s->alloc(&s->tmpid, N));
+    ALLOC(s->alloc(&s->rec, N));
     ALLOC(s->alloc(&s->ncnt, N));
     ALLOC(s->alloc(&s->nl, N * kListCap));
     {

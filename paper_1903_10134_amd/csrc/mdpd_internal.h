@@ -34,6 +34,18 @@ struct Soa3c {
 };
 inline Soa3c cview(const Soa3 &a) { return Soa3c{a.x, a.y, a.z}; }
 
+// Everything the force pass reads of a neighbour, packed in one 64-byte
+// record per slot (written by the density pass), so that one neighbour
+// costs one cache-line sector instead of eight scattered ones.
+struct alignas(16) PartRec {
+    double x, y, z;     // position
+    double vx, vy, vz;  // half-step velocity (0 for frozen particles)
+    double rho;         // many-body density (the FP32 form's value, exactly)
+    uint32_t tag;       // id | frozen bit
+    uint32_t typ;       // type
+};
+static_assert(sizeof(PartRec) == 64, "PartRec must be one 64-byte sector");
+
 // Cell lattice: nc[a] cells of edge L[a]/nc[a] >= r_c per axis.
 struct Geom {
     double L[3];
@@ -229,15 +241,18 @@ void launch_sort(hipStream_t st, int n, const Reps &R, Soa3c xin, Soa3c vin, Soa
                  int *ovf_count, uint32_t *step_ctr);
 void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int *cstart, int *ncnt,
                   uint32_t *nl, void *nlr2, const int *gate);
-void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c xs,
-                    const int *cstart, const int *ncnt, const void *nlr2, void *rho);
+// Also writes the packed neighbour records of every slot.
+void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c xs, Soa3c vh,
+                    const uint32_t *tag, const uint8_t *typ, const int *cstart, const int *ncnt,
+                    const void *nlr2, void *rho, PartRec *rec);
 void launch_phi(hipStream_t st, int lanes, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix,
                 Soa3 vfix, const uint32_t *tag, const int *cstart, const int *ncnt,
                 const uint32_t *nl, int *ncorr, unsigned long long *ncorr_total);
 // stepp: device word holding the noise step (advanced by the main sort).
 void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, const uint32_t *stepp,
                   Soa3c xs, Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ,
-                  const int *cstart, const int *ncnt, const uint32_t *nl, Soa3 vout, Soa3 fout,
+                  const PartRec *rec, const int *cstart, const int *ncnt, const uint32_t *nl, Soa3 vout,
+                  Soa3 fout,
                   Soa3 vpred, Soa3 xpred, double *part, int *status, int *ovf_count, int *ovf,
                   double *ovf_ve, int initial);
 // Number of virial/energy block partials the force pass writes with this

@@ -257,9 +257,12 @@ __device__ __forceinline__ float w_rho<float>(const PairConst &pc, float r2)
 }
 
 template <int P, typename R>
-__global__ __launch_bounds__(kBlock) void k_density(Reps Rp, Soa3c xs, const int *__restrict__ cstart_all,
+__global__ __launch_bounds__(kBlock) void k_density(Reps Rp, Soa3c xs, Soa3c vh, const uint32_t *__restrict__ tag,
+                                                    const uint8_t *__restrict__ typ,
+                                                    const int *__restrict__ cstart_all,
                                                     const int *__restrict__ ncnt,
-                                                    const R *__restrict__ nlr2, R *__restrict__ rho)
+                                                    const R *__restrict__ nlr2, R *__restrict__ rho,
+                                                    PartRec *__restrict__ rec)
 {
     const BlockRep br = block_rep<P>(Rp, xcd_block());
     const int i = br.i0 + (int)threadIdx.x / P;
@@ -285,7 +288,22 @@ __global__ __launch_bounds__(kBlock) void k_density(Reps Rp, Soa3c xs, const int
         });
     }
     acc = group_sum<P>(acc);
-    if (sub == 0) rho[i] = acc;
+    if (sub == 0) {
+        rho[i] = acc;
+        const uint32_t tg = tag[i];
+        const bool fz = (tg & kFrozenBit) != 0;
+        PartRec q;
+        q.x = xs.x[i];
+        q.y = xs.y[i];
+        q.z = xs.z[i];
+        q.vx = fz ? 0.0 : vh.x[i];
+        q.vy = fz ? 0.0 : vh.y[i];
+        q.vz = fz ? 0.0 : vh.z[i];
+        q.rho = (double)acc;
+        q.tag = tg;
+        q.typ = typ[i];
+        rec[i] = q;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -420,7 +438,8 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
                                                const uint32_t *__restrict__ tag,
                                                const uint8_t *__restrict__ typ,
                                                const int *__restrict__ cstart, int packed,
-                                               const uint32_t *__restrict__ lst, const ForceOut &out,
+                                               const uint32_t *__restrict__ lst,
+                                               const PartRec *__restrict__ rec, const ForceOut &out,
                                                double &vir, double &ep)
 {
     const uint32_t tgi = tag[i];
@@ -470,19 +489,20 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
         for (int k = sub; k < cnt; k += P) {
             const uint32_t e = lst[list_pos(k, nnear)];
             const int j = (int)(e & kSlotMask);
-            // every load of the neighbour first, then the arithmetic; the
-            // minimum-image shift is a select, so no branch splits the loads
-            const double xj = ld(xs.x, j), yj = ld(xs.y, j), zj = ld(xs.z, j);
-            const double vxj = ld(vh.x, j), vyj = ld(vh.y, j), vzj = ld(vh.z, j);
-            const R rj = ld(rho, j);
-            const uint32_t tgj = ld(tag, j);
-            const int tj = MT ? (int)ld(typ, j) : 0;
+            // the neighbour's packed record: four 16-byte loads of one sector
+            const double2 *q = (const double2 *)(rec + j);
+            const double2 a = q[0], b = q[1], c = q[2];
+            const uint4 d = *(const uint4 *)(q + 3);
+            const R rj = (R)__longlong_as_double((long long)(((unsigned long long)d.y << 32) | d.x));
+            const uint32_t tgj = d.z;
+            const int tj = MT ? (int)d.w : 0;
+            // the minimum-image shift is a select, so no branch splits the loads
             const bool wr = (e & kWrapBit) != 0;
-            double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+            double dx = xi - a.x, dy = yi - a.y, dz = zi - b.x;
             dx = wr ? min_image(dx, pc.L[0], pc.invL[0]) : dx;
             dy = wr ? min_image(dy, pc.L[1], pc.invL[1]) : dy;
             dz = wr ? min_image(dz, pc.L[2], pc.invL[2]) : dz;
-            pair(dx, dy, dz, vxj, vyj, vzj, rj, tgj, tj, (e & kNearBit) != 0);
+            pair(dx, dy, dz, b.y, c.x, c.y, rj, tgj, tj, (e & kNearBit) != 0);
         }
     }
     fx = group_sum<P>(fx);
@@ -545,6 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Reps Rp, const uint32_t *__res
                                                   const R *__restrict__ rho,
                                                   const uint32_t *__restrict__ tag,
                                                   const uint8_t *__restrict__ typ,
+                                                  const PartRec *__restrict__ rec,
                                                   const int *__restrict__ ncnt,
                                                   const uint32_t *__restrict__ nl, ForceOut out)
 {
@@ -560,7 +581,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Reps Rp, const uint32_t *__res
         const int packed = ncnt[i];
         if (list_total(packed) <= kListCap) {
             force_particle<P, MT, false, R>(pc, g, i, sub, xs, vh, rho, tag, typ, nullptr, packed,
-                                            nl + (size_t)i * kListCap, out, vir, ep);
+                                            nl + (size_t)i * kListCap, rec, out, vir, ep);
         } else if (sub == 0) {
             out.ovf[atomicAdd(out.ovf_count, 1)] = i;  // served by k_force_overflow
         }
@@ -598,7 +619,7 @@ __global__ __launch_bounds__(kBlock) void k_force_overflow(Reps Rp, const uint32
         const Geom g = Rp.geom[r];
         double vir = 0.0, ep = 0.0;
         force_particle<P, MT, true, R>(pc, g, i, sub, xs, vh, rho, tag, typ, cstart_all + cload(Rp.cell_off, r),
-                                       ncnt[i], nullptr, out, vir, ep);
+                                       ncnt[i], nullptr, nullptr, out, vir, ep);
         vir = group_sum<P>(vir);
         ep = group_sum<P>(ep);
         if (sub == 0) {
@@ -666,18 +687,20 @@ void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int 
         k_nlist_cell<double><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (double *)nlr2, gate);
 }
 
-void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c xs, const int *cstart,
-                    const int *ncnt, const void *nlr2, void *rho)
+void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c xs, Soa3c vh, const uint32_t *tag,
+                    const uint8_t *typ, const int *cstart, const int *ncnt, const void *nlr2, void *rho,
+                    PartRec *rec)
 {
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
         const int nb = R.nblk[lanes_index(L)];
         if (nb <= 0) return;
         if (fp32)
-            k_density<L, float><<<nb, kBlock, 0, st>>>(R, xs, cstart, ncnt, (const float *)nlr2, (float *)rho);
+            k_density<L, float><<<nb, kBlock, 0, st>>>(R, xs, vh, tag, typ, cstart, ncnt, (const float *)nlr2,
+                                                       (float *)rho, rec);
         else
-            k_density<L, double><<<nb, kBlock, 0, st>>>(R, xs, cstart, ncnt, (const double *)nlr2,
-                                                        (double *)rho);
+            k_density<L, double><<<nb, kBlock, 0, st>>>(R, xs, vh, tag, typ, cstart, ncnt, (const double *)nlr2,
+                                                        (double *)rho, rec);
     });
 }
 
@@ -696,7 +719,8 @@ void launch_phi(hipStream_t st, int lanes, int n, const Reps &R, Soa3c xs, Soa3c
 }
 
 void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, const uint32_t *stepp, Soa3c xs,
-                  Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ, const int *cstart,
+                  Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ, const PartRec *rec,
+                  const int *cstart,
                   const int *ncnt, const uint32_t *nl, Soa3 vout, Soa3 fout, Soa3 vpred, Soa3 xpred,
                   double *part, int *status, int *ovf_count, int *ovf, double *ovf_ve, int initial)
 {
@@ -708,7 +732,8 @@ void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, 
         auto go = [&](auto mtc, auto rc) {
             constexpr bool M = decltype(mtc)::value;
             using RT = typename decltype(rc)::type;
-            k_force<L, M, RT><<<nb, kBlock, 0, st>>>(R, stepp, xs, vh, (const RT *)rho, tag, typ, ncnt, nl, out);
+            k_force<L, M, RT><<<nb, kBlock, 0, st>>>(R, stepp, xs, vh, (const RT *)rho, tag, typ, rec, ncnt, nl,
+                                                     out);
             k_force_overflow<M, RT><<<kOverflowBlocks, kBlock, 0, st>>>(R, stepp, xs, vh, (const RT *)rho, tag,
                                                                         typ, cstart, ncnt, out, ovf_ve);
         };
