@@ -137,7 +137,8 @@ mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, cons
  * All replicas need the same precision and wall model.  Per-particle outputs
  * (mdpd_get_state, mdpd_debug_*) come back in input order over the whole
  * batch; observables per replica come from mdpd_read_replica_observables.
- * mdpd_read_observables, mdpd_read_profile and the adjoint need nrep = 1.
+ * mdpd_read_observables and mdpd_read_profile need nrep = 1; the adjoint
+ * runs per replica (losses and table gradients per replica).
  * Errors as for mdpd_create. */
 mdpd_status mdpd_create_batch(int32_t nrep, const mdpd_params *params, const int64_t *offsets,
                               const double *pos, const double *vel, const int32_t *type,
@@ -242,23 +243,25 @@ mdpd_status mdpd_load_checkpoint(mdpd_system *s, const void *buf, uint64_t bytes
  * from the state given to mdpd_create (MDPD_E_STATE after mdpd_step).
  *
  * mdpd_forward_record advances nsteps >= 0 steps from step 0, keeping a
- * device checkpoint every `every` >= 1 steps, and returns in loss[3]
- *   loss[0] = mean many-body density of fluid particles,
- *   loss[1] = virial pressure (as in mdpd_observables),
- *   loss[2] = mean x-velocity of fluid particles,
+ * device checkpoint every `every` >= 1 steps, and returns in loss[3 nrep]
+ * for each replica r (nrep = 1 for a single system)
+ *   loss[3r]     = mean many-body density of fluid particles,
+ *   loss[3r + 1] = virial pressure (as in mdpd_observables),
+ *   loss[3r + 2] = mean x-velocity of fluid particles,
  * of the final state (average = 0) or averaged over the states after steps
  * 1..nsteps (average = 1, nsteps >= 1).  Afterwards the system stands at
  * step nsteps.
  *
- * mdpd_backward returns the gradient of L = w[0] loss[0] + w[1] loss[1] +
- * w[2] loss[2] of the last recording with respect to
- *   dA, dB, dgamma  the pair tables, ntypes x ntypes, host; the derivative of
+ * mdpd_backward returns the gradient of L = sum_r sum_q w[3r + q] loss[3r + q]
+ * of the last recording with respect to
+ *   dA, dB, dgamma  the pair tables, host: for each replica its ntypes x
+ *                   ntypes entries, replica after replica; the derivative of
  *                   L along a symmetric change D of a table is
  *                   sum_ab d[ab] D[ab] (at gamma = 0 the noise amplitude
  *                   sqrt(2 gamma kT) has no derivative and is left out)
- *   dx0, dv0        the positions and velocities given to mdpd_create, n x 3
- *                   in id order, host or device per mem_kind (dv0 of frozen
- *                   particles is 0)
+ *   dx0, dv0        the positions and velocities given to mdpd_create(_batch),
+ *                   n x 3 in input order, host or device per mem_kind (dv0 of
+ *                   frozen particles is 0)
  * Any output may be NULL.  Each segment of `every` steps is recomputed from
  * its checkpoint, so the call costs about one forward pass plus the adjoint
  * passes; memory is one checkpoint (about 170 bytes per particle) per

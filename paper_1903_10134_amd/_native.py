@@ -311,20 +311,24 @@ def mdpd_load_checkpoint(h, buf) -> None:
     _check(lib().mdpd_load_checkpoint(h, buf.ctypes.data, buf.nbytes, MEM_HOST))
 
 
-def mdpd_forward_record(h, nsteps: int, every: int = 10, average: bool = False):
+def mdpd_forward_record(h, nsteps: int, every: int = 10, average: bool = False, nrep: int = 1):
     """Record a trajectory of nsteps from step 0; returns the loss terms
-    (mean fluid density, virial pressure, mean fluid x-velocity)."""
-    out = np.zeros(3)
+    (mean fluid density, virial pressure, mean fluid x-velocity): shape (3,)
+    for a single system, (nrep, 3) for a batch."""
+    out = np.zeros(3 * nrep)
     _check(lib().mdpd_forward_record(h, int(nsteps), int(every), 1 if average else 0, out.ctypes.data))
-    return out
+    return out if nrep == 1 else out.reshape(nrep, 3)
 
 
-def mdpd_backward(h, w, ntypes: int, n: int, device=None):
-    """Gradient of w . loss of the last recording: dict of dA, dB, dgamma
-    (ntypes x ntypes) and dx0, dv0 (n x 3, id order; CUDA tensors when
-    device is given)."""
-    wv = np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(3))
-    tabs = [np.zeros((ntypes, ntypes)) for _ in range(3)]
+def mdpd_backward(h, w, ntypes, n: int, device=None):
+    """Gradient of sum_r w[r] . loss[r] of the last recording.  ntypes: the
+    type count of each replica (an int for a single system).  Returns dA, dB,
+    dgamma (T x T, or a list of them per replica) and dx0, dv0 (n x 3 in
+    input order; CUDA tensors when device is given)."""
+    tlist = [int(ntypes)] if np.ndim(ntypes) == 0 else [int(t) for t in ntypes]
+    wv = np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(3 * len(tlist)))
+    size = sum(t * t for t in tlist)
+    flat = [np.zeros(size) for _ in range(3)]
     if device is not None:
         import torch
         dx = torch.empty((n, 3), dtype=torch.float64, device=device)
@@ -333,8 +337,16 @@ def mdpd_backward(h, w, ntypes: int, n: int, device=None):
     else:
         dx, dv = np.zeros((n, 3)), np.zeros((n, 3))
         ptrs, kind = (dx.ctypes.data, dv.ctypes.data), MEM_HOST
-    _check(lib().mdpd_backward(h, wv.ctypes.data, *[t.ctypes.data for t in tabs], *ptrs, kind))
-    return {"dA": tabs[0], "dB": tabs[1], "dgamma": tabs[2], "dx0": dx, "dv0": dv}
+    _check(lib().mdpd_backward(h, wv.ctypes.data, *[t.ctypes.data for t in flat], *ptrs, kind))
+
+    def split(v):
+        out, off = [], 0
+        for t in tlist:
+            out.append(v[off:off + t * t].reshape(t, t))
+            off += t * t
+        return out[0] if np.ndim(ntypes) == 0 else out
+
+    return {"dA": split(flat[0]), "dB": split(flat[1]), "dgamma": split(flat[2]), "dx0": dx, "dv0": dv}
 
 
 def mdpd_set_graph(h, enable: bool) -> None:
@@ -403,7 +415,7 @@ class System:
         return mdpd_forward_record(self.h, nsteps, every, average)
 
     def backward(self, w, device=None):
-        return mdpd_backward(self.h, w, self.params.ntypes, self.n, device=device)
+        return mdpd_backward(self.h, w, int(self.params.ntypes), self.n, device=device)
 
     def autotune(self, steps=5):
         return mdpd_autotune(self.h, steps)
@@ -477,6 +489,12 @@ class Batch:
 
     def set_graph(self, enable=True):
         mdpd_set_graph(self.h, enable)
+
+    def forward_record(self, nsteps, every=10, average=False):
+        return mdpd_forward_record(self.h, nsteps, every, average, nrep=self.nrep)
+
+    def backward(self, w, device=None):
+        return mdpd_backward(self.h, w, [int(p.ntypes) for p in self.params], self.n, device=device)
 
     def close(self):
         if self.h:

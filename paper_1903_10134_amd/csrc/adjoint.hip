@@ -46,17 +46,24 @@ __device__ __forceinline__ PairTab pair_tab(const PairConst &pc, int ti, int tj)
     return PairTab{pc.tab[tt], pc.tab[64 + tt], pc.tab[128 + tt], pc.tab[192 + tt]};
 }
 
-__global__ __launch_bounds__(kBlock) void k_adj_seed(int n, AdjConst ac, Soa3c v, const uint32_t *__restrict__ tag,
-                                                    Soa3 U, Soa3 fb, double *__restrict__ rhoA)
+// Replica and slot of thread threadIdx.x in a replica-aligned block of
+// kBlock particles (lane count 1); i >= i1 means no particle.
+__device__ __forceinline__ BlockRep elem_rep(const Reps &R) { return block_rep<1>(R, blockIdx.x); }
+
+__global__ __launch_bounds__(kBlock) void k_adj_seed(Reps Rp, const AdjConst *__restrict__ act, Soa3c v,
+                                                    const uint32_t *__restrict__ tag, Soa3 U, Soa3 fb,
+                                                    double *__restrict__ rhoA)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+    const BlockRep br = elem_rep(Rp);
+    const int i = br.i0 + (int)threadIdx.x;
+    if (i >= br.i1) return;
     if (tag[i] & kFrozenBit) {
         U.x[i] = U.y[i] = U.z[i] = 0.0;
         fb.x[i] = fb.y[i] = fb.z[i] = 0.0;
         rhoA[i] = 0.0;
         return;
     }
+    const AdjConst ac = cload(act, br.r);
     const double kv = 2.0 * ac.mass * ac.wP_3V;
     const double bx = kv * v.x[i] + ac.wvx_nf, by = kv * v.y[i], bz = kv * v.z[i];
     const double ux = U.x[i], uy = U.y[i], uz = U.z[i];
@@ -70,7 +77,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(int n, AdjConst ac, Soa3c v
 }
 
 template <int P, bool MT, typename R>
-__global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, AdjConst ac, int n, Soa3c xs,
+__global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, const AdjConst *__restrict__ act,
+                                                     int n, int tmax, Soa3c xs,
                                                      Soa3c u, const R *__restrict__ rho,
                                                      const uint32_t *__restrict__ tag,
                                                      const uint8_t *__restrict__ typ,
@@ -88,6 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, Ad
     set_noise_keys(pc, step);
     const Geom g = cload(Rp.geom, br.r);
     const int *__restrict__ cstart = cstart_all + cload(Rp.cell_off, br.r);
+    const AdjConst ac = cload(act, br.r);
     const uint32_t tgi = tag[i];
     const bool fzi = (tgi & kFrozenBit) != 0;
     const uint32_t idi = tgi & kIdMask;
@@ -95,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, Ad
     const double uxi = fzi ? 0.0 : u.x[i], uyi = fzi ? 0.0 : u.y[i], uzi = fzi ? 0.0 : u.z[i];
     const double fxi = fb.x[i], fyi = fb.y[i], fzi_ = fb.z[i];
     const double rhoi = (double)rho[i];
-    const int T = MT ? pc.ntypes : 1;
+    const int T = MT ? pc.ntypes : 1;  // this replica's types (shares stored with stride tmax)
     const int ti = MT ? (int)typ[i] : 0;
     const double wP = ac.wP_3V;
     double ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0, ar = 0;
@@ -183,9 +192,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, Ad
 #pragma unroll
     for (int k = 0; k < TM; ++k) {
         if (k < T) {
-            gp[(size_t)(0 * T + k) * n + i] = pA[k];
-            gp[(size_t)(1 * T + k) * n + i] = pB[k];
-            gp[(size_t)(2 * T + k) * n + i] = pG[k];
+            gp[(size_t)(0 * tmax + k) * n + i] = pA[k];
+            gp[(size_t)(1 * tmax + k) * n + i] = pB[k];
+            gp[(size_t)(2 * tmax + k) * n + i] = pG[k];
         }
     }
 }
@@ -228,14 +237,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_density(Reps Rp, Soa3c xs, const
     X.z[i] += az;
 }
 
-// Drift adjoint (U += dt X for fluid) and reorder by particle id.
-__global__ __launch_bounds__(kBlock) void k_adj_scatter(int n, double dt, const uint32_t *__restrict__ tag,
-                                                       Soa3c X, Soa3c U, Soa3 Xid, Soa3 Uid)
+// Drift adjoint (U += dt X for fluid) and reorder into input order (the
+// particle with id k of replica r goes to row part_off[r] + k).
+__global__ __launch_bounds__(kBlock) void k_adj_scatter(Reps Rp, const AdjConst *__restrict__ act,
+                                                       const uint32_t *__restrict__ tag, Soa3c X, Soa3c U,
+                                                       Soa3 Xid, Soa3 Uid)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+    const BlockRep br = elem_rep(Rp);
+    const int i = br.i0 + (int)threadIdx.x;
+    if (i >= br.i1) return;
+    const double dt = cload(act, br.r).dt;
     const uint32_t tg = tag[i];
-    const size_t id = tg & kIdMask;
+    const size_t id = (size_t)cload(Rp.part_off, br.r) + (tg & kIdMask);
     const double x = X.x[i], y = X.y[i], z = X.z[i];
     Xid.x[id] = x;
     Xid.y[id] = y;
@@ -249,12 +262,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_scatter(int n, double dt, const 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_adj_gather(int n, const uint32_t *__restrict__ tag, Soa3c Xid,
+__global__ __launch_bounds__(kBlock) void k_adj_gather(Reps Rp, const uint32_t *__restrict__ tag, Soa3c Xid,
                                                       Soa3c Uid, Soa3 X, Soa3 U)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const size_t id = tag[i] & kIdMask;
+    const BlockRep br = elem_rep(Rp);
+    const int i = br.i0 + (int)threadIdx.x;
+    if (i >= br.i1) return;
+    const size_t id = (size_t)cload(Rp.part_off, br.r) + (tag[i] & kIdMask);
     X.x[i] = Xid.x[id];
     X.y[i] = Xid.y[id];
     X.z[i] = Xid.z[id];
@@ -263,65 +277,62 @@ __global__ __launch_bounds__(kBlock) void k_adj_gather(int n, const uint32_t *__
     U.z[i] = Uid.z[id];
 }
 
-// Parameter shares: for one (quantity q, type a) pass, block partials of
-// sum over particles i of type a of gp[q][b][i], for every b < T.
-constexpr int kAdjRedBlocks = 512;
-
-__global__ __launch_bounds__(kBlock) void k_adj_params(int n, int T, int q, int a, const uint8_t *__restrict__ typ,
+// Parameter shares, first level: for each replica-aligned block of kBlock
+// particles and each (quantity q, type a of i, type b of j) the fixed-order
+// block sum of gp over the block's particles of type a.  part holds
+// 3 * tmax * tmax sums per block.
+__global__ __launch_bounds__(kBlock) void k_adj_params(Reps Rp, int n, int tmax,
+                                                      const uint8_t *__restrict__ typ,
                                                       const double *__restrict__ gp, double *__restrict__ part)
 {
-    __shared__ double sh[MDPD_ADJ_MAX_TYPES][kBlock];
-    double acc[MDPD_ADJ_MAX_TYPES];
-#pragma unroll
-    for (int b = 0; b < MDPD_ADJ_MAX_TYPES; ++b) acc[b] = 0.0;
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        if (T > 1 && (int)typ[i] != a) continue;
-#pragma unroll
-        for (int b = 0; b < MDPD_ADJ_MAX_TYPES; ++b)
-            if (b < T) acc[b] += gp[(size_t)(q * T + b) * n + i];
-    }
-#pragma unroll
-    for (int b = 0; b < MDPD_ADJ_MAX_TYPES; ++b) sh[b][threadIdx.x] = acc[b];
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int b = 0; b < T; ++b) sh[b][threadIdx.x] += sh[b][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int b = 0; b < T; ++b) part[(size_t)b * gridDim.x + blockIdx.x] = sh[b][0];
+    __shared__ double sh[kBlock];
+    const BlockRep br = elem_rep(Rp);
+    const int i = br.i0 + (int)threadIdx.x;
+    const bool in = i < br.i1;
+    const int T = cload(Rp.pc, br.r).ntypes;
+    const int ti = in ? (int)typ[i] : -1;
+    double *out = part + (size_t)blockIdx.x * 3 * tmax * tmax;
+    for (int q = 0; q < 3; ++q)
+        for (int a = 0; a < T; ++a)
+            for (int b = 0; b < T; ++b) {
+                sh[threadIdx.x] = (in && ti == a) ? gp[(size_t)(q * tmax + b) * n + i] : 0.0;
+                __syncthreads();
+                for (int w = kBlock / 2; w > 0; w >>= 1) {
+                    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+                    __syncthreads();
+                }
+                if (threadIdx.x == 0) out[(q * tmax + a) * tmax + b] = sh[0];
+                __syncthreads();
+            }
 }
 
-// total[q][a][b] += sum over blocks (fixed order) of the partials.
-__global__ __launch_bounds__(kBlock) void k_adj_params_final(int nb, int T, int q, int a,
-                                                            const double *__restrict__ part,
-                                                            double *__restrict__ total)
+// Second level, one block per replica: gtot[r][q][a T + b] += sum over the
+// replica's blocks in order.
+__global__ __launch_bounds__(kBlock) void k_adj_params_final(Reps Rp, int tmax, const double *__restrict__ part,
+                                                            double *__restrict__ gtot)
 {
-    __shared__ double sh[kBlock];
-    for (int b = 0; b < T; ++b) {
-        double s = 0.0;
-        for (int k = threadIdx.x; k < nb; k += kBlock) s += part[(size_t)b * nb + k];
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = kBlock / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) total[q * 64 + a * T + b] += sh[0];
-        __syncthreads();
-    }
+    const int r = blockIdx.x;
+    const int T = cload(Rp.pc, r).ntypes;
+    const int *boff = Rp.blk_off;  // lane count 1
+    const int b0 = cload(boff, r), b1 = cload(boff, r + 1);
+    const int e = threadIdx.x;
+    if (e >= 3 * T * T) return;
+    const int q = e / (T * T), a = (e / T) % T, b = e % T;
+    double s = 0.0;
+    for (int k = b0; k < b1; ++k) s += part[(size_t)k * 3 * tmax * tmax + (q * tmax + a) * tmax + b];
+    gtot[(size_t)r * 3 * 64 + q * 64 + a * T + b] += s;
 }
 
 }  // namespace
 
-void launch_adj_seed(hipStream_t st, int n, const AdjConst &ac, Soa3c v, const uint32_t *tag, Soa3 U, Soa3 fb,
-                     double *rhoA)
+void launch_adj_seed(hipStream_t st, const Reps &R, const AdjConst *ac, Soa3c v, const uint32_t *tag, Soa3 U,
+                     Soa3 fb, double *rhoA)
 {
-    if (n > 0) k_adj_seed<<<blocks_for(n), kBlock, 0, st>>>(n, ac, v, tag, U, fb, rhoA);
+    if (R.nblk[0] > 0) k_adj_seed<<<R.nblk[0], kBlock, 0, st>>>(R, ac, v, tag, U, fb, rhoA);
 }
 
-void launch_adj_force(hipStream_t st, int lanes, bool fp32, bool mt, int n, const Reps &R, uint32_t step,
-                      const AdjConst &ac, Soa3c xs, Soa3c u, const void *rho, const uint32_t *tag,
+void launch_adj_force(hipStream_t st, int lanes, bool fp32, bool mt, int n, int tmax, const Reps &R, uint32_t step,
+                      const AdjConst *ac, Soa3c xs, Soa3c u, const void *rho, const uint32_t *tag,
                       const uint8_t *typ, const int *cstart, const int *ncnt, const uint32_t *nl, Soa3c fb,
                       Soa3 X, Soa3 U, double *rhoA, double *gp)
 {
@@ -329,23 +340,18 @@ void launch_adj_force(hipStream_t st, int lanes, bool fp32, bool mt, int n, cons
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
         const int nb = R.nblk[lanes_index(L)];
+        auto go = [&](auto mtc, auto rc) {
+            constexpr bool M = decltype(mtc)::value;
+            using RT = typename decltype(rc)::type;
+            k_adj_force<L, M, RT><<<nb, kBlock, 0, st>>>(R, step, ac, n, tmax, xs, u, (const RT *)rho, tag, typ,
+                                                         cstart, ncnt, nl, fb, X, U, rhoA, gp);
+        };
         if (fp32) {
-            if (mt)
-                k_adj_force<L, true, float><<<nb, kBlock, 0, st>>>(R, step, ac, n, xs, u, (const float *)rho, tag,
-                                                                   typ, cstart, ncnt, nl, fb, X, U, rhoA, gp);
-            else
-                k_adj_force<L, false, float><<<nb, kBlock, 0, st>>>(R, step, ac, n, xs, u, (const float *)rho,
-                                                                    tag, typ, cstart, ncnt, nl, fb, X, U, rhoA,
-                                                                    gp);
+            if (mt) go(std::true_type{}, Tid<float>{});
+            else go(std::false_type{}, Tid<float>{});
         } else {
-            if (mt)
-                k_adj_force<L, true, double><<<nb, kBlock, 0, st>>>(R, step, ac, n, xs, u, (const double *)rho,
-                                                                    tag, typ, cstart, ncnt, nl, fb, X, U, rhoA,
-                                                                    gp);
-            else
-                k_adj_force<L, false, double><<<nb, kBlock, 0, st>>>(R, step, ac, n, xs, u, (const double *)rho,
-                                                                     tag, typ, cstart, ncnt, nl, fb, X, U, rhoA,
-                                                                     gp);
+            if (mt) go(std::true_type{}, Tid<double>{});
+            else go(std::false_type{}, Tid<double>{});
         }
     });
 }
@@ -360,29 +366,25 @@ void launch_adj_density(hipStream_t st, int lanes, const Reps &R, Soa3c xs, cons
     });
 }
 
-void launch_adj_scatter(hipStream_t st, int n, double dt, const uint32_t *tag, Soa3c X, Soa3c U, Soa3 Xid,
-                        Soa3 Uid)
+void launch_adj_scatter(hipStream_t st, const Reps &R, const AdjConst *ac, const uint32_t *tag, Soa3c X, Soa3c U,
+                        Soa3 Xid, Soa3 Uid)
 {
-    if (n > 0) k_adj_scatter<<<blocks_for(n), kBlock, 0, st>>>(n, dt, tag, X, U, Xid, Uid);
+    if (R.nblk[0] > 0) k_adj_scatter<<<R.nblk[0], kBlock, 0, st>>>(R, ac, tag, X, U, Xid, Uid);
 }
 
-void launch_adj_gather(hipStream_t st, int n, const uint32_t *tag, Soa3c Xid, Soa3c Uid, Soa3 X, Soa3 U)
+void launch_adj_gather(hipStream_t st, const Reps &R, const uint32_t *tag, Soa3c Xid, Soa3c Uid, Soa3 X, Soa3 U)
 {
-    if (n > 0) k_adj_gather<<<blocks_for(n), kBlock, 0, st>>>(n, tag, Xid, Uid, X, U);
+    if (R.nblk[0] > 0) k_adj_gather<<<R.nblk[0], kBlock, 0, st>>>(R, tag, Xid, Uid, X, U);
 }
 
-int adj_param_partials(int ntypes) { return kAdjRedBlocks * ntypes; }
+int adj_param_partials(const Reps &R, int tmax) { return (R.nblk[0] + 1) * 3 * tmax * tmax; }
 
-void launch_adj_params(hipStream_t st, int n, int ntypes, const uint8_t *typ, const double *gp, double *part,
-                       double *total)
+void launch_adj_params(hipStream_t st, const Reps &R, int n, int tmax, const uint8_t *typ, const double *gp,
+                       double *part, double *gtot)
 {
-    if (n <= 0) return;
-    const int nb = blocks_for(n) < kAdjRedBlocks ? blocks_for(n) : kAdjRedBlocks;
-    for (int q = 0; q < 3; ++q)
-        for (int a = 0; a < ntypes; ++a) {
-            k_adj_params<<<nb, kBlock, 0, st>>>(n, ntypes, q, a, typ, gp, part);
-            k_adj_params_final<<<1, kBlock, 0, st>>>(nb, ntypes, q, a, part, total);
-        }
+    if (n <= 0 || R.nblk[0] <= 0) return;
+    k_adj_params<<<R.nblk[0], kBlock, 0, st>>>(R, n, tmax, typ, gp, part);
+    k_adj_params_final<<<R.nrep, kBlock, 0, st>>>(R, tmax, part, gtot);
 }
 
 }  // namespace mdpd

@@ -56,7 +56,8 @@ struct AdjRec {
     int64_t nsteps = 0;
     int every = 1;
     int avg = 0;
-    int64_t nfluid = 0;
+    int tmax = 1;                 // largest type count over the replicas
+    std::vector<int64_t> nfluid;  // per replica
     char *ck = nullptr;  // nck checkpoints of ck_bytes each
     uint64_t ck_bytes = 0;
     int nck = 0;
@@ -66,6 +67,10 @@ struct AdjRec {
     int ntape = 0;
     Soa3 X{}, U{}, fb{}, Xid{}, Uid{};
     double *rhoA = nullptr, *gp = nullptr, *gpart = nullptr, *gtot = nullptr, *loss = nullptr;
+    AdjConst *act = nullptr;  // 4 tables of nrep entries: seeded, unseeded, final, creation
+    std::vector<AdjConst> host_act;  // host copy (kept alive while the upload may read it)
+    LossConst *lct = nullptr;
+    size_t gp_n = 0, gpart_n = 0;
 };
 }  // namespace mdpd
 
@@ -1201,31 +1206,43 @@ double seed_weight(const AdjRec &a, int64_t n)
     return n == a.nsteps ? 1.0 : 0.0;
 }
 
-// Backward step for the state in tape entry k at step n (creation: n = 0
-// and the force adjoint takes h U).
-void adjoint_step(mdpd_system *s, int k, int64_t n, bool creation, const double w[3])
+// Per-replica constants of a backward step with seed weight sw (creation:
+// the force adjoint takes h U and there is no drift).
+void fill_adj_table(mdpd_system *s, const double *w, double sw, bool creation, AdjConst *out)
+{
+    for (int r = 0; r < s->nrep; ++r) {
+        const mdpd_params &p = s->params[r];
+        const double V3 = 3.0 * p.box[0] * p.box[1] * p.box[2];
+        const int64_t nf = s->adj.nfluid[r];
+        const double inf = nf > 0 ? 1.0 / (double)nf : 0.0;
+        const double h = 0.5 * p.dt / p.mass;
+        AdjConst &ac = out[r];
+        ac.cU = creation ? h : 2.0 * h;
+        ac.cv = creation ? 0.0 : h;
+        ac.wrho_nf = sw * w[3 * r] * inf;
+        ac.wP_3V = sw * w[3 * r + 1] / V3;
+        ac.wvx_nf = sw * w[3 * r + 2] * inf;
+        ac.mass = p.mass;
+        ac.dt = creation ? 0.0 : p.dt;
+        ac.pad = 0.0;
+    }
+}
+
+// Backward step for the state in tape entry k at step n with the
+// per-replica constants act.
+void adjoint_step(mdpd_system *s, int k, int64_t n, const AdjConst *act)
 {
     AdjRec &a = s->adj;
     const TapeEntry e = tape_entry(s, k);
-    const double V3 = 3.0 * s->p.box[0] * s->p.box[1] * s->p.box[2];
-    const double inf = a.nfluid > 0 ? 1.0 / (double)a.nfluid : 0.0;
-    const double sw = seed_weight(a, n);
-    AdjConst ac;
-    const double h = s->pcs[0].hdtm;
-    ac.cU = creation ? h : 2.0 * h;
-    ac.cv = creation ? 0.0 : h;
-    ac.wrho_nf = sw * w[0] * inf;
-    ac.wP_3V = sw * w[1] / V3;
-    ac.wvx_nf = sw * w[2] * inf;
-    ac.mass = s->p.mass;
-    launch_adj_seed(s->st, s->n, ac, cview(e.v), e.tag, a.U, a.fb, a.rhoA);
+    launch_adj_seed(s->st, s->R, act, cview(e.v), e.tag, a.U, a.fb, a.rhoA);
     launch_nlist(s->st, s->fp32, s->R, cview(e.x), e.cstart, s->ncnt, s->nl, s->nlr2, nullptr);
     s->tic(5);
-    launch_adj_force(s->st, s->lanes[2], s->fp32, s->mt, s->n, s->R, (uint32_t)n, ac, cview(e.x), cview(e.u),
-                     e.rho, e.tag, e.typ, e.cstart, s->ncnt, s->nl, cview(a.fb), a.X, a.U, a.rhoA, a.gp);
+    launch_adj_force(s->st, s->lanes[2], s->fp32, s->mt, s->n, a.tmax, s->R, (uint32_t)n, act, cview(e.x),
+                     cview(e.u), e.rho, e.tag, e.typ, e.cstart, s->ncnt, s->nl, cview(a.fb), a.X, a.U, a.rhoA,
+                     a.gp);
     launch_adj_density(s->st, s->lanes[1], s->R, cview(e.x), e.cstart, s->ncnt, s->nl, a.rhoA, a.X);
     s->toc(5);
-    launch_adj_params(s->st, s->n, s->p.ntypes, e.typ, a.gp, a.gpart, a.gtot);
+    launch_adj_params(s->st, s->R, s->n, a.tmax, e.typ, a.gp, a.gpart, a.gtot);
 }
 
 }  // namespace
@@ -1239,14 +1256,23 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
     if (average && nsteps < 1) return fail(MDPD_E_INVALID, "a time average needs nsteps >= 1");
     if (s->walls) return fail(MDPD_E_UNSUPPORTED, "the adjoint does not differentiate the wall corrector");
     if (s->step != 0) return fail(MDPD_E_STATE, "recording starts from the state given to mdpd_create");
-    if (s->nrep != 1) return fail(MDPD_E_UNSUPPORTED, "the adjoint runs on single systems");
-    if (s->p.ntypes > MDPD_ADJ_MAX_TYPES) return fail(MDPD_E_UNSUPPORTED, "too many types");
     AdjRec &a = s->adj;
     a.ready = false;
-    mdpd_observables o;
-    mdpd_status rc = mdpd_read_observables(s, &o);
+    std::vector<mdpd_observables> o((size_t)s->nrep);
+    mdpd_status rc = mdpd_read_replica_observables(s, 0, s->nrep, o.data());
     if (rc) return rc;
-    a.nfluid = o.n_fluid;
+    a.nfluid.resize((size_t)s->nrep);
+    a.tmax = 1;
+    std::vector<LossConst> lc((size_t)s->nrep);
+    for (int r = 0; r < s->nrep; ++r) {
+        const mdpd_params &p = s->params[r];
+        a.nfluid[r] = o[r].n_fluid;
+        a.tmax = p.ntypes > a.tmax ? p.ntypes : a.tmax;
+        lc[r].inv_nf = o[r].n_fluid > 0 ? 1.0 / (double)o[r].n_fluid : 0.0;
+        lc[r].inv3V = 1.0 / (3.0 * p.box[0] * p.box[1] * p.box[2]);
+        lc[r].mass = p.mass;
+        lc[r].pad = 0.0;
+    }
     a.nsteps = nsteps;
     a.every = every;
     a.avg = average ? 1 : 0;
@@ -1272,26 +1298,38 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
         a.ntape = ntape;
         a.tape_bytes = tpb;
     }
+    const size_t nrep = (size_t)s->nrep;
     if (!a.rhoA) {
         Soa3 *v3[5] = {&a.X, &a.U, &a.fb, &a.Xid, &a.Uid};
         for (Soa3 *q : v3)
             if ((rc = s->alloc3(q, N))) return rc;
         if ((rc = s->alloc(&a.rhoA, N))) return rc;
-        if ((rc = s->alloc(&a.gp, 3 * (size_t)s->p.ntypes * N))) return rc;
-        if ((rc = s->alloc(&a.gpart, (size_t)adj_param_partials(s->p.ntypes)))) return rc;
-        if ((rc = s->alloc(&a.gtot, 3 * 64))) return rc;
-        if ((rc = s->alloc(&a.loss, 4))) return rc;
+        if ((rc = s->alloc(&a.gtot, 3 * 64 * nrep))) return rc;
+        if ((rc = s->alloc(&a.loss, 3 * nrep + 1))) return rc;
+        if ((rc = s->alloc(&a.act, 4 * nrep))) return rc;
+        if ((rc = s->alloc(&a.lct, nrep))) return rc;
+    }
+    if (a.gp_n < 3 * (size_t)a.tmax * N) {
+        s->release(a.gp);
+        a.gp = nullptr;
+        a.gp_n = 3 * (size_t)a.tmax * N;
+        if ((rc = s->alloc(&a.gp, a.gp_n))) return rc;
+    }
+    if (a.gpart_n < (size_t)adj_param_partials(s->R, a.tmax)) {
+        s->release(a.gpart);
+        a.gpart = nullptr;
+        a.gpart_n = (size_t)adj_param_partials(s->R, a.tmax);
+        if ((rc = s->alloc(&a.gpart, a.gpart_n))) return rc;
     }
     // run and checkpoint; the loss terms accumulate on the device
-    const double V3 = 3.0 * s->p.box[0] * s->p.box[1] * s->p.box[2];
-    const double inf = a.nfluid > 0 ? 1.0 / (double)a.nfluid : 0.0;
-    HIPCHK(hipMemsetAsync(a.loss, 0, 4 * sizeof(double), s->st));
+    HIPCHK(hipMemcpyAsync(a.lct, lc.data(), nrep * sizeof(LossConst), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemsetAsync(a.loss, 0, (3 * nrep + 1) * sizeof(double), s->st));
     auto accum = [&](int64_t n) {
         const double sw = seed_weight(a, n);
         if (sw == 0.0) return;
         launch_observables(s->st, s->fp32, s->R, s->force_lanes_used, cview(s->v), s->rho, s->tag[s->cur],
                            s->typ[s->cur], s->fpart, s->ncnt, s->ovf_ve, s->obs_part, s->obs);
-        launch_loss_accum(s->st, s->obs, a.loss, inf, 1.0 / V3, s->p.mass, sw);
+        launch_loss_accum(s->st, s->nrep, s->obs, a.lct, a.loss, sw);
     };
     HIPCHK(ckpt_store(s, 0));
     accum(0);
@@ -1304,7 +1342,7 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
         HIPCHK(ckpt_store(s, k));
     }
     int hstatus = 0;
-    HIPCHK(hipMemcpyAsync(loss, a.loss, 3 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(loss, a.loss, 3 * nrep * sizeof(double), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipMemcpyAsync(&hstatus, s->status, sizeof(int), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
     HIPCHK(hipGetLastError());
@@ -1322,9 +1360,25 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
     AdjRec &a = s->adj;
     if (!a.ready) return fail(MDPD_E_STATE, "no recorded trajectory (call mdpd_forward_record first)");
     const size_t N = (size_t)s->n;
+    const size_t nrep = (size_t)s->nrep;
     const int K = (int)((a.nsteps + a.every - 1) / a.every);
-    const int T = s->p.ntypes;
-    HIPCHK(hipMemsetAsync(a.gtot, 0, 3 * 64 * sizeof(double), s->st));
+    // per-replica constants: steps with the mean-loss weight, steps without a
+    // loss term, the final step, and the evaluation at creation
+    {
+        std::vector<AdjConst> &tab = a.host_act;
+        tab.assign(4 * nrep, AdjConst{});
+        const double wmid = a.avg ? 1.0 / (double)(a.nsteps > 0 ? a.nsteps : 1) : 0.0;
+        fill_adj_table(s, w, wmid, false, &tab[0]);
+        fill_adj_table(s, w, 0.0, false, &tab[nrep]);
+        fill_adj_table(s, w, a.avg ? wmid : 1.0, false, &tab[2 * nrep]);
+        fill_adj_table(s, w, seed_weight(a, 0), true, &tab[3 * nrep]);
+        HIPCHK(hipMemcpyAsync(a.act, tab.data(), tab.size() * sizeof(AdjConst), hipMemcpyHostToDevice, s->st));
+    }
+    auto table = [&](int64_t n) -> const AdjConst * {
+        if (n == a.nsteps) return a.act + 2 * nrep;
+        return seed_weight(a, n) != 0.0 ? a.act : a.act + nrep;
+    };
+    HIPCHK(hipMemsetAsync(a.gtot, 0, 3 * 64 * nrep * sizeof(double), s->st));
     if (N > 0) {
         launch_zero_int(s->st, (int *)a.X.x, (int)(6 * N));
         launch_zero_int(s->st, (int *)a.U.x, (int)(6 * N));
@@ -1339,20 +1393,21 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
             HIPCHK(tape_record(s, m, false));
         }
         for (int m = (int)(s1 - s0); m >= 1; --m) {
-            adjoint_step(s, m, s0 + m, false, w);
+            const AdjConst *act = table(s0 + m);
+            adjoint_step(s, m, s0 + m, act);
             const TapeEntry cur = tape_entry(s, m), prev = tape_entry(s, m - 1);
-            launch_adj_scatter(s->st, s->n, s->p.dt, cur.tag, cview(a.X), cview(a.U), a.Xid, a.Uid);
-            launch_adj_gather(s->st, s->n, prev.tag, cview(a.Xid), cview(a.Uid), a.X, a.U);
+            launch_adj_scatter(s->st, s->R, act, cur.tag, cview(a.X), cview(a.U), a.Xid, a.Uid);
+            launch_adj_gather(s->st, s->R, prev.tag, cview(a.Xid), cview(a.Uid), a.X, a.U);
         }
     }
     if (K == 0) {
         HIPCHK(ckpt_restore(s, 0, 0));
         HIPCHK(tape_record(s, 0, true));
     }
-    // the evaluation at creation, then export by id
-    adjoint_step(s, 0, 0, true, w);
-    double g[3 * 64];
-    HIPCHK(hipMemcpyAsync(g, a.gtot, sizeof g, hipMemcpyDeviceToHost, s->st));
+    // the evaluation at creation, then export in input order
+    adjoint_step(s, 0, 0, a.act + 3 * nrep);
+    std::vector<double> g(3 * 64 * nrep);
+    HIPCHK(hipMemcpyAsync(g.data(), a.gtot, g.size() * sizeof(double), hipMemcpyDeviceToHost, s->st));
     const hipMemcpyKind dk = mem_kind == MDPD_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     if (N > 0) {
         // sorted SoA planes to n x 3 rows in id order (U of frozen particles is 0)
@@ -1362,10 +1417,16 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
         if (dv0) HIPCHK(hipMemcpyAsync(dv0, s->io2, 3 * N * sizeof(double), dk, s->st));
     }
     HIPCHK(hipStreamSynchronize(s->st));
+    // per replica, its ntypes^2 table entries, replica after replica
     double *outs[3] = {dA, dB, dgamma};
     for (int q = 0; q < 3; ++q) {
         if (!outs[q]) continue;
-        for (int ab = 0; ab < T * T; ++ab) outs[q][ab] = g[q * 64 + ab];
+        size_t off = 0;
+        for (size_t r = 0; r < nrep; ++r) {
+            const int T = s->params[r].ntypes;
+            for (int ab = 0; ab < T * T; ++ab) outs[q][off + ab] = g[r * 192 + q * 64 + ab];
+            off += (size_t)T * T;
+        }
     }
     // back to the state at the end of the recording
     HIPCHK(ckpt_restore(s, K, a.nsteps));

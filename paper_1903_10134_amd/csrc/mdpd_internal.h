@@ -217,8 +217,9 @@ __device__ __forceinline__ int theta_int(uint32_t ida, uint32_t idb, const PairC
     return (int)((w >> 8) << 1) + 1 - 16777216;
 }
 
-// Scalars of one backward step of the adjoint (adjoint.hip).  Loss weights
-// are zero at states that carry no loss term.
+// Scalars of one backward step of the adjoint for one replica (adjoint.hip;
+// one table entry per replica).  Loss weights are zero at states that carry
+// no loss term.
 #define MDPD_ADJ_MAX_TYPES 8
 struct AdjConst {
     double cU;       // coefficient of U = dL/du_n in the force adjoint: 2h, or h at creation
@@ -227,6 +228,14 @@ struct AdjConst {
     double wP_3V;    // weight of the virial pressure / (3 V)
     double wvx_nf;   // weight of the mean fluid x-velocity / N_f
     double mass;
+    double dt;       // drift of the step (0 at creation)
+    double pad;
+};
+
+// Per-replica constants of the loss terms (mean fluid density, virial
+// pressure, mean fluid x-velocity) accumulated during a recording.
+struct LossConst {
+    double inv_nf, inv3V, mass, pad;
 };
 
 // Host-side launchers (defined in the .hip files).  n is the total number
@@ -258,21 +267,26 @@ void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, 
 // Number of virial/energy block partials the force pass writes with this
 // lane count (one per block; replica r owns its blocks' range).
 int force_partials(const Reps &R, int lanes);
-void launch_adj_seed(hipStream_t st, int n, const AdjConst &ac, Soa3c v, const uint32_t *tag, Soa3 U,
+// Adjoint launchers: ac is a device table of one AdjConst per replica; gp
+// holds 3 x ntypes parameter shares per slot; gtot accumulates per replica
+// 3 planes of MDPD_ADJ_MAX_TYPES^2 (A, B, gamma) over the backward steps.
+void launch_adj_seed(hipStream_t st, const Reps &R, const AdjConst *ac, Soa3c v, const uint32_t *tag, Soa3 U,
                      Soa3 fb, double *rhoA);
-void launch_adj_force(hipStream_t st, int lanes, bool fp32, bool mt, int n, const Reps &R,
-                      uint32_t step, const AdjConst &ac, Soa3c xs, Soa3c u, const void *rho,
+void launch_adj_force(hipStream_t st, int lanes, bool fp32, bool mt, int n, int tmax, const Reps &R,
+                      uint32_t step, const AdjConst *ac, Soa3c xs, Soa3c u, const void *rho,
                       const uint32_t *tag, const uint8_t *typ, const int *cstart, const int *ncnt,
                       const uint32_t *nl, Soa3c fb, Soa3 X, Soa3 U, double *rhoA, double *gp);
 void launch_adj_density(hipStream_t st, int lanes, const Reps &R, Soa3c xs, const int *cstart,
                         const int *ncnt, const uint32_t *nl, const double *rhoA, Soa3 X);
-void launch_adj_scatter(hipStream_t st, int n, double dt, const uint32_t *tag, Soa3c X, Soa3c U,
-                        Soa3 Xid, Soa3 Uid);
-void launch_adj_gather(hipStream_t st, int n, const uint32_t *tag, Soa3c Xid, Soa3c Uid, Soa3 X,
+void launch_adj_scatter(hipStream_t st, const Reps &R, const AdjConst *ac, const uint32_t *tag, Soa3c X,
+                        Soa3c U, Soa3 Xid, Soa3 Uid);
+void launch_adj_gather(hipStream_t st, const Reps &R, const uint32_t *tag, Soa3c Xid, Soa3c Uid, Soa3 X,
                        Soa3 U);
-int adj_param_partials(int ntypes);
-void launch_adj_params(hipStream_t st, int n, int ntypes, const uint8_t *typ, const double *gp,
-                       double *part, double *total);
+int adj_param_partials(const Reps &R, int tmax);
+void launch_adj_params(hipStream_t st, const Reps &R, int n, int tmax, const uint8_t *typ, const double *gp,
+                       double *part, double *gtot);
+void launch_loss_accum(hipStream_t st, int nrep, const double *obs, const LossConst *lc, double *acc,
+                       double scale);
 // Observables per replica: part needs obs_partials(R) doubles, out 16 per
 // replica (sums as listed at k_obs_final).
 int obs_partials(const Reps &R);
@@ -280,8 +294,6 @@ void launch_observables(hipStream_t st, bool fp32, const Reps &R, int force_lane
                         const void *rho, const uint32_t *tag, const uint8_t *typ,
                         const double *fpart, const int *ncnt, const double *ovf_ve, double *part,
                         double *out);
-void launch_loss_accum(hipStream_t st, const double *obs16, double *acc, double inv_nf, double inv3V,
-                       double mass, double scale);
 void launch_profile(hipStream_t st, bool fp32, int n, int axis, int nbins, int quantity, double La,
                     double binvol, double mass, Soa3c x, Soa3c v, const void *rho,
                     const uint32_t *tag, double *work, double *out);

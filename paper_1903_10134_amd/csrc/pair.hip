@@ -669,11 +669,6 @@ __global__ __launch_bounds__(kBlock) void k_debug_neighbors(Reps R, double cut2,
 
 }  // namespace
 
-template <typename T>
-struct Tid {
-    using type = T;
-};
-
 int force_partials(const Reps &R, int lanes) { return R.nblk[lanes_index(lanes)]; }
 
 void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int *cstart, int *ncnt,

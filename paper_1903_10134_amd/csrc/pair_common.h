@@ -168,6 +168,12 @@ __device__ __forceinline__ BlockRep block_rep(const Reps &R, int blk)
     return BlockRep{r, cload(R.part_off, r) + (blk - cload(off, r)) * (kBlock / P), cload(R.part_off, r + 1)};
 }
 
+// Host: a type tag for dispatching on the arithmetic type of a pass.
+template <typename T>
+struct Tid {
+    using type = T;
+};
+
 // Host: instantiate a launch for the lane count P in {1, 2, 4, 8, 16}.
 template <typename K>
 void launch_lanes(int lanes, K &&k)

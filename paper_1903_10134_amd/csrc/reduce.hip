@@ -177,23 +177,25 @@ __global__ __launch_bounds__(kBlock) void k_export(Reps Rp, Soa3c x, Soa3c v, co
     if (rho_out) rho_out[id] = (double)rho[i];
 }
 
-// acc[0..2] += scale * (mean fluid rho, virial pressure, mean fluid v_x)
-// from the final sums of k_obs_final.
-__global__ void k_loss_accum(const double *obs, double *acc, double inv_nf, double inv3V, double mass,
-                             double scale)
+// acc[3r + 0..2] += scale * (mean fluid rho, virial pressure, mean fluid
+// v_x) of replica r from the final sums of k_obs_final.
+__global__ void k_loss_accum(int nrep, const double *obs, const LossConst *lc, double *acc, double scale)
 {
-    if (threadIdx.x != 0) return;
-    acc[0] += scale * obs[4] * inv_nf;
-    acc[1] += scale * (mass * obs[0] + obs[8]) * inv3V;
-    acc[2] += scale * obs[1] * inv_nf;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
+    const double *o = obs + 16 * (size_t)r;
+    const LossConst c = lc[r];
+    acc[3 * r] += scale * o[4] * c.inv_nf;
+    acc[3 * r + 1] += scale * (c.mass * o[0] + o[8]) * c.inv3V;
+    acc[3 * r + 2] += scale * o[1] * c.inv_nf;
 }
 
 }  // namespace
 
-void launch_loss_accum(hipStream_t st, const double *obs16, double *acc, double inv_nf, double inv3V,
-                       double mass, double scale)
+void launch_loss_accum(hipStream_t st, int nrep, const double *obs, const LossConst *lc, double *acc,
+                       double scale)
 {
-    k_loss_accum<<<1, 64, 0, st>>>(obs16, acc, inv_nf, inv3V, mass, scale);
+    k_loss_accum<<<(nrep + 255) / 256, 256, 0, st>>>(nrep, obs, lc, acc, scale);
 }
 
 int obs_partials(const Reps &R) { return R.nblk[0] * kObs; }

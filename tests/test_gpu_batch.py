@@ -113,7 +113,7 @@ def test_batch_checkpoint_and_limits(mdpd):
     with pytest.raises(mdpd.MdpdError):
         mdpd.mdpd_read_observables(a.h)  # several replicas
     with pytest.raises(mdpd.MdpdError):
-        mdpd.mdpd_forward_record(c.h, 2)  # the adjoint runs on single systems
+        c.forward_record(2)  # recording starts at step 0
     with pytest.raises(mdpd.MdpdError):
         mdpd.mdpd_read_replica_observables(a.h, 2, 2)  # out of range
     a.close()
@@ -141,4 +141,29 @@ def test_autotune_leaves_no_trace(mdpd):
     assert a.observables() == b.observables()
     assert b.autotune(steps=2) == lanes
     a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("avg", [False, True])
+def test_batch_adjoint_equals_standalone(mdpd, avg):
+    """Per-replica losses and gradients of a batch equal, bit for bit, those
+    of each replica recorded and differentiated alone."""
+    reps = W.replicas(count=3, lo=4.0, hi=6.0, seed=4) + [mixed_types(), dense_cluster()]
+    say("batch adjoint", "avg" if avg else "final")
+    rng = np.random.default_rng(3)
+    w = rng.normal(size=(len(reps), 3))
+    b = mdpd.Batch(reps, precision=mdpd.FP32_FORCES)
+    lb = b.forward_record(5, every=2, average=avg)
+    gb = b.backward(w)
+    for r, wl in enumerate(reps):
+        s = mdpd.System(wl, precision=mdpd.FP32_FORCES)
+        ls = s.forward_record(5, every=2, average=avg)
+        gs = s.backward(w[r])
+        assert np.array_equal(lb[r], ls), r
+        sl = slice(b.offsets[r], b.offsets[r + 1])
+        for key in ("dA", "dB", "dgamma"):
+            assert np.array_equal(gb[key][r], gs[key]), (r, key)
+        assert np.array_equal(gb["dx0"][sl], gs["dx0"]), r
+        assert np.array_equal(gb["dv0"][sl], gs["dv0"]), r
+        s.close()
     b.close()
