@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--lanes", type=str, default="", help="n,d,f lanes per particle")
     ap.add_argument("--forms", type=str, default="fp32_forces,fp64")
+    ap.add_argument("--replicas", type=int, default=256, help="replicas of the batched workload (0: skip)")
+    ap.add_argument("--adj-steps", type=int, default=100, help="steps of the batched forward + adjoint")
+    ap.add_argument("--adj-every", type=int, default=10, help="checkpoint spacing of the adjoint")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this size 5 times (counter scaling)")
     return ap.parse_args()
@@ -99,6 +102,49 @@ def run_form(mdpd, w, precision, steps, warmup, stream, lanes):
     s.close()
     return dict(sec=t1 - t0, ktime=ktime, obs=obs, pairs_c=int(cnt_c.sum()) // 2,
                 pairs_d=int(cnt_d.sum()) // 2)
+
+
+def run_batch(mdpd, W, nrep, steps, every):
+    """Batched replicas (edges U[8, 12], A ~ U[-50, -30], B ~ U[20, 30], FP32
+    forces): forward throughput, then a recording of `steps` steps with a
+    checkpoint every `every` and the adjoint of the mean density and pressure
+    (time-averaged) with respect to A, B, gamma of every replica."""
+    import torch
+    reps = W.replicas(count=nrep, lo=8.0, hi=12.0, seed=0)
+    n = sum(r.n for r in reps)
+    b = mdpd.Batch(reps, precision=mdpd.FP32_FORCES, device_inputs=True)
+    b.step(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    b.close()
+    # adjoint: a warm-up cycle allocates the checkpoints and the tape, then
+    # the state at step 0 is restored and the timed cycle runs
+    a = mdpd.Batch(reps, precision=mdpd.FP32_FORCES, device_inputs=True)
+    ck0 = mdpd.mdpd_save_checkpoint(a.h)
+    wts = np.tile([1.0, 0.05, 0.0], (nrep, 1))
+    a.forward_record(steps, every=every, average=True)
+    a.backward(wts)
+    mdpd.mdpd_load_checkpoint(a.h, ck0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = a.forward_record(steps, every=every, average=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = a.backward(wts)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    a.close()
+    return {"workload": f"{nrep} replicas, periodic boxes with edges U[8, 12] at density 6, "
+                        f"A ~ U[-50, -30], B ~ U[20, 30], FP32 forces",
+            "replicas": nrep, "particles": n, "steps": steps, "checkpoint_every": every,
+            "forward_particle_steps_per_s": n * steps / fwd, "forward_ms_per_step": fwd * 1e3 / steps,
+            "record_s": t1 - t0, "backward_s": t2 - t1, "forward_s": fwd,
+            "adjoint_over_forward": (t2 - t1) / fwd,
+            "record_plus_adjoint_over_forward": (t2 - t0) / fwd,
+            "loss_mean_rho_r0": float(loss[0][0]), "dA_r0": float(g["dA"][0][0, 0])}
 
 
 def cpu_baseline(w, nsteps):
@@ -189,6 +235,14 @@ def main():
     if "fp64" in res:
         out["fp32_over_fp64"] = out["forms"]["fp32_forces"]["particle_steps_per_s"] / \
             out["forms"]["fp64"]["particle_steps_per_s"]
+    if a.replicas > 0:
+        bt = run_batch(mdpd, W, a.replicas, a.adj_steps, a.adj_every)
+        out["batched"] = bt
+        out["adjoint_over_forward"] = bt["adjoint_over_forward"]
+        print(f"# batched {bt['replicas']} replicas ({bt['particles']} particles): "
+              f"{bt['forward_ms_per_step']:.3f} ms/step forward, adjoint/forward "
+              f"{bt['adjoint_over_forward']:.2f} (record+adjoint {bt['record_plus_adjoint_over_forward']:.2f})",
+              file=sys.stderr, flush=True)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
     print(json.dumps(out), flush=True)
