@@ -47,6 +47,12 @@ OPS_VV_PARTICLE = 20
 # type (53 read + 53 write): 263 B (FP32 form; +8 for FP64 rho).
 BYTES_STEP_FP32 = 263
 BYTES_STEP_FP64 = 271
+# HBM traffic of one launch of the force kernel (FP32 form, 8 lanes per
+# particle) on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by
+# a plain 256 MiB copy (x2.000 reads, x1.000 writes): the summary and the
+# commands are in profiles/mdpd_step_bulk56_n1053696.md.  Valid for the
+# kernel as profiled; it must be re-measured when the kernel changes.
+FORCE_TRAFFIC_BYTES = {"read": 532476518, "write": 102484685}
 
 
 def parse():
@@ -216,8 +222,10 @@ def main():
         "forms": {},
         "roofline": {"bound": "alu", "kernel": "k_force (FP32 form)", "achieved": achieved,
                      "peak": PEAK_VALU_TOPS, "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_VALU_TOPS,
-                     "traffic": None, "avg_launch_us": favg * 1e6,
-                     "ops_per_launch": ops_force},
+                     "traffic": (FORCE_TRAFFIC_BYTES["read"] + FORCE_TRAFFIC_BYTES["write"]
+                                 if n == 1053696 and not lanes else None),
+                     "traffic_read_write": FORCE_TRAFFIC_BYTES if n == 1053696 and not lanes else None,
+                     "avg_launch_us": favg * 1e6, "ops_per_launch": ops_force},
     }
     for name, r in res.items():
         bpp = BYTES_STEP_FP32 if name == "fp32_forces" else BYTES_STEP_FP64
