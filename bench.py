@@ -66,6 +66,7 @@ def parse():
     ap.add_argument("--lanes", type=str, default="", help="n,d,f lanes per particle")
     ap.add_argument("--forms", type=str, default="fp32_forces,fp64")
     ap.add_argument("--replicas", type=int, default=256, help="replicas of the batched workload (0: skip)")
+    ap.add_argument("--no-walls", action="store_true", help="skip the walled channel and rock workloads")
     ap.add_argument("--adj-steps", type=int, default=100, help="steps of the batched forward + adjoint")
     ap.add_argument("--adj-every", type=int, default=10, help="checkpoint spacing of the adjoint")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -151,6 +152,26 @@ def run_batch(mdpd, W, nrep, steps, every):
             "adjoint_over_forward": (t2 - t1) / fwd,
             "record_plus_adjoint_over_forward": (t2 - t0) / fwd,
             "loss_mean_rho_r0": float(loss[0][0]), "dA_r0": float(g["dA"][0][0, 0])}
+
+
+def run_walled(mdpd, w, steps, warmup):
+    """A walled workload (frozen wall particles, boundary-volume-fraction
+    corrector, body force), FP32 forces: step time and corrector activity."""
+    import torch
+    s = mdpd.System(w, precision=mdpd.FP32_FORCES, device_inputs=True)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    o = s.observables()
+    s.close()
+    nf = int(w.n - int(np.asarray(w.frozen).sum()))
+    return {"particles": w.n, "fluid": nf, "box": list(w.box), "steps": steps,
+            "ms_per_step": sec * 1e3 / steps, "particle_steps_per_s": w.n * steps / sec,
+            "fluid_particle_steps_per_s": nf * steps / sec, "kT": o["kT"],
+            "mean_vx": o["momentum"][0] / max(nf, 1), "corrections_per_step": o["ncorr_total"] / (steps + warmup)}
 
 
 def cpu_baseline(w, nsteps):
@@ -251,6 +272,15 @@ def main():
               f"{bt['forward_ms_per_step']:.3f} ms/step forward, adjoint/forward "
               f"{bt['adjoint_over_forward']:.2f} (record+adjoint {bt['record_plus_adjoint_over_forward']:.2f})",
               file=sys.stderr, flush=True)
+    if not a.no_walls:
+        ch = run_walled(mdpd, W.channel(), 200, 20)
+        ch["workload"] = "Poiseuille channel 64 x 32 x 64, frozen walls of thickness 2, g_x = 0.02"
+        rk = run_walled(mdpd, W.rock(), 50, 5)
+        rk["workload"] = "synthetic rock, 128^3 Gaussian-random-field mask, porosity 0.3, g_x = 0.01"
+        out["walled"] = {"channel": ch, "rock": rk}
+        for k, v in out["walled"].items():
+            print(f"# {k}: {v['particles']} particles ({v['fluid']} fluid), {v['ms_per_step']:.3f} ms/step, "
+                  f"{v['corrections_per_step']:.1f} corrections/step", file=sys.stderr, flush=True)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
     print(json.dumps(out), flush=True)
