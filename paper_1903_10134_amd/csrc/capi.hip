@@ -109,6 +109,7 @@ struct mdpd_system {
     int *ovf = nullptr;        // [0]: overflow count, [1..n]: queued slots
     double *ovf_ve = nullptr;  // per slot: virial, pair energy of overflowed particles
     int *corr = nullptr;  // [0]: corrections this step, [1..n]: flags
+    uint8_t *wnear = nullptr;  // per cell: a frozen particle within the 27-cell stencil
     unsigned long long *ncorr_total = nullptr;
     double *tab = nullptr;
     double *obs = nullptr;       // 16 result slots per replica
@@ -277,16 +278,14 @@ struct mdpd_system {
 
     void evaluate(uint32_t stepno, int initial)
     {
-        tic(1);
-        launch_nlist(st, fp32, R, cview(xs[cur]), cstart, ncnt, nl, nlr2, nullptr);
-        toc(1);
         if (walls && !initial) {
+            // phi at the predicted positions and the corrector, then re-sort
+            // only if a particle was moved back (gated on the device)
             launch_zero_int(st, corr, 1);
             tic(4);
-            launch_phi(st, lanes[1], n, R, cview(xs[cur]), cview(xprev), xs[cur], vh[cur], tag[cur], cstart,
-                       ncnt, nl, corr, ncorr_total);
+            launch_phi(st, lanes[1], n, R, cview(xs[cur]), cview(xprev), xs[cur], vh[cur], tag[cur], cstart, wnear,
+                       corr, ncorr_total);
             toc(4);
-            // re-sort and re-list only if a particle was moved back
             const int o = 1 - cur;
             tic(0);
             launch_sort(st, n, R, cview(xs[cur]), cview(vh[cur]), Soa3c{nullptr, nullptr, nullptr}, tag[cur],
@@ -294,10 +293,10 @@ struct mdpd_system {
                         tmpid, counts, cstart, bsum, corr, nullptr, nullptr);
             toc(0);
             cur = o;
-            tic(1);
-            launch_nlist(st, fp32, R, cview(xs[cur]), cstart, ncnt, nl, nlr2, corr);
-            toc(1);
         }
+        tic(1);
+        launch_nlist(st, fp32, R, cview(xs[cur]), cstart, ncnt, nl, nlr2, nullptr);
+        toc(1);
         tic(2);
         launch_density(st, lanes[1], fp32, R, cview(xs[cur]), cview(vh[cur]), tag[cur], typ[cur], cstart, ncnt,
                        nlr2, rho, rec);
@@ -526,6 +525,7 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     ALLOC(s->alloc3(&s->v, N));
     ALLOC(s->alloc3(&s->F, N));
     if (s->walls) ALLOC(s->alloc3(&s->xprev, N));
+    if (s->walls) ALLOC(s->alloc(&s->wnear, (size_t)cells));
     {
         double *r = nullptr;
         ALLOC(s->alloc(&r, N));
@@ -649,6 +649,11 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
 
     // t = 0: sort, density, forces with the given velocities and noise step 0
     s->sort_predicted();
+    if (s->walls) {
+        hipError_t ez = hipMemsetAsync(s->wnear, 0, (size_t)cells, s->st);
+        if (ez != hipSuccess) return bail(fail(MDPD_E_HIP, "wall mask: %s", hipGetErrorString(ez)));
+        launch_mark_wall_cells(s->st, R, cview(s->xs[s->cur]), s->tag[s->cur], s->wnear);
+    }
     s->evaluate(0, 1);
     e = hipMemcpyAsync(&hstatus, s->status, sizeof(int), hipMemcpyDeviceToHost, s->st);
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
@@ -940,6 +945,10 @@ mdpd_status mdpd_load_checkpoint(mdpd_system *s, const void *buf, uint64_t bytes
     s->force_lanes_used = (int)h.force_lanes;
     s->step = h.step;
     HIPCHK(state_copy(s, const_cast<char *>(in) + head_bytes(s), false, dk));
+    if (s->walls) {  // the wall-cell mask follows the frozen particles of the loaded state
+        HIPCHK(hipMemsetAsync(s->wnear, 0, (size_t)s->R.ncells, s->st));
+        launch_mark_wall_cells(s->st, s->R, cview(s->xs[s->cur]), s->tag[s->cur], s->wnear);
+    }
     // the neighbour list is a function of the positions and the cell list
     launch_nlist(s->st, s->fp32, s->R, cview(s->xs[s->cur]), s->cstart, s->ncnt, s->nl, s->nlr2, nullptr);
     HIPCHK(hipStreamSynchronize(s->st));

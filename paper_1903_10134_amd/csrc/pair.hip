@@ -7,7 +7,8 @@
 //   k_density     many-body density rho_i = sum_{j != i, r < r_d} w_rho(r_ij)
 //                 (Sec. 2.1) from the stored r^2 of the flagged entries
 //   k_phi         boundary volume fraction of fluid particles at the predicted
-//                 positions and the predictor-corrector flag (Sec. 2.2, 3.2)
+//                 positions (direct cell scan, only where a frozen particle is
+//                 in reach) and the predictor-corrector flag (Sec. 2.2, 3.2)
 //   k_force       Eq. 1 conservative force, dissipative and random forces
 //                 (Sec. 2.1), body force, and the velocity-Verlet update fused
 //                 in the epilogue: v(t+dt), the next half-step velocity and the
@@ -307,13 +308,37 @@ __global__ __launch_bounds__(kBlock) void k_density(Reps Rp, Soa3c xs, Soa3c vh,
 }
 
 // ---------------------------------------------------------------------------
+// Cells that can hold a fluid particle with a frozen neighbour within r_c:
+// the 27-cell stencil of every frozen particle's cell.  Frozen particles never
+// move, so the mask is built once (a plain store of 1 from every writer).
+__global__ __launch_bounds__(kBlock) void k_mark_wall_cells(Reps R, Soa3c xs, const uint32_t *__restrict__ tag,
+                                                            uint8_t *__restrict__ wnear)
+{
+    const BlockRep br = block_rep<1>(R, blockIdx.x);
+    const int i = br.i0 + (int)threadIdx.x;
+    if (i >= br.i1 || !(tag[i] & kFrozenBit)) return;
+    const Geom g = cload(R.geom, br.r);
+    const int coff = cload(R.cell_off, br.r);
+    const int cx = cell_coord(xs.x[i], g.s[0], g.nc[0]);
+    const int cy = cell_coord(xs.y[i], g.s[1], g.nc[1]);
+    const int cz = cell_coord(xs.z[i], g.s[2], g.nc[2]);
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int c = wrap_index(cx + dx, g.nc[0]) +
+                              g.nc[0] * (wrap_index(cy + dy, g.nc[1]) + g.nc[1] * wrap_index(cz + dz, g.nc[2]));
+                wnear[coff + c] = 1;
+            }
+}
+
 // phi_i = sum_{frozen j} w_c^2 / sum_j w_c^2 over neighbours within r_c at the
-// predicted positions; flag[i] = 1 when phi_i > phi_c (fluid only).
+// predicted positions, by a direct scan of the cells (the exact test of the
+// neighbour list); flag[i] = 1 when phi_i > phi_c.  Fluid particles in cells
+// with no frozen particle in reach have phi = 0 and are not scanned.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_phi(Reps R, Soa3c xs, const uint32_t *__restrict__ tag,
                                                 const int *__restrict__ cstart_all,
-                                                const int *__restrict__ ncnt,
-                                                const uint32_t *__restrict__ nl, int *__restrict__ flag)
+                                                const uint8_t *__restrict__ wnear, int *__restrict__ flag)
 {
     const BlockRep br = block_rep<P>(R, xcd_block());
     const int i = br.i0 + (int)threadIdx.x / P;
@@ -321,20 +346,26 @@ __global__ __launch_bounds__(kBlock) void k_phi(Reps R, Soa3c xs, const uint32_t
     if (i >= br.i1) return;
     const PairConst pc = cload(R.pc, br.r);
     const Geom g = cload(R.geom, br.r);
-    const int *__restrict__ cstart = cstart_all + cload(R.cell_off, br.r);
-    if (tag[i] & kFrozenBit) {
+    const int coff = cload(R.cell_off, br.r);
+    const int *__restrict__ cstart = cstart_all + coff;
+    const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
+    const int ci = cell_coord(xi, g.s[0], g.nc[0]) +
+                   g.nc[0] * (cell_coord(yi, g.s[1], g.nc[1]) + g.nc[1] * cell_coord(zi, g.s[2], g.nc[2]));
+    if ((tag[i] & kFrozenBit) || !wnear[coff + ci]) {  // uniform over the P lanes of i
         if (sub == 0) flag[i] = 0;
         return;
     }
-    const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
     double num = 0.0, den = 0.0;
-    for_each_neighbor<P>(pc, g, i, sub, xi, yi, zi, xs, cstart, ncnt[i], nl + (size_t)i * kListCap,
-                         [&](int j, double dx, double dy, double dz, bool) {
-                             const double r = __builtin_sqrt(exact_r2(dx, dy, dz));
-                             const double w = 1.0 - r * pc.inv_rc;
-                             den += w * w;
-                             if (tag[j] & kFrozenBit) num += w * w;
-                         });
+    for_each_row(g, xi, yi, zi, cstart, [&](int b, int e, double sx, double sy, double sz) {
+        for (int j = b + sub; j < e; j += P) {
+            if (j == i) continue;
+            const double r2 = exact_r2((xi - xs.x[j]) + sx, (yi - xs.y[j]) + sy, (zi - xs.z[j]) + sz);
+            if (!(r2 < g.rc2)) continue;
+            const double w = 1.0 - __builtin_sqrt(r2) * pc.inv_rc;
+            den += w * w;
+            if (tag[j] & kFrozenBit) num += w * w;
+        }
+    });
     num = group_sum<P>(num);
     den = group_sum<P>(den);
     if (sub == 0) flag[i] = (den > 0.0 && num / den > pc.phi_c) ? 1 : 0;
@@ -699,16 +730,21 @@ void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c x
     });
 }
 
+void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint32_t *tag, uint8_t *wnear)
+{
+    if (R.nblk[0] > 0) k_mark_wall_cells<<<R.nblk[0], kBlock, 0, st>>>(R, xs, tag, wnear);
+}
+
 void launch_phi(hipStream_t st, int lanes, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix, Soa3 vfix,
-                const uint32_t *tag, const int *cstart, const int *ncnt, const uint32_t *nl,
-                int *flag_and_count, unsigned long long *ncorr_total)
+                const uint32_t *tag, const int *cstart, const uint8_t *wnear, int *flag_and_count,
+                unsigned long long *ncorr_total)
 {
     if (n <= 0) return;
     int *ncorr = flag_and_count;       // [0]: corrections this step
     int *flag = flag_and_count + 1;    // [1..n]: per-slot flags
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
-        k_phi<L><<<R.nblk[lanes_index(L)], kBlock, 0, st>>>(R, xs, tag, cstart, ncnt, nl, flag);
+        k_phi<L><<<R.nblk[lanes_index(L)], kBlock, 0, st>>>(R, xs, tag, cstart, wnear, flag);
     });
     k_correct<<<blocks_for(n), kBlock, 0, st>>>(n, flag, xprev, xfix, vfix, ncorr, ncorr_total);
 }
