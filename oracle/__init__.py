@@ -93,6 +93,7 @@ def lib():
         L.orc_tangent.argtypes = [P(Params), i64, P(d), P(d), P(i32), P(u8), P(d), P(d), P(d), P(d), P(d),
                                   i64, P(d), ctypes.c_int, P(d)]
         L.orc_tangent.restype = ctypes.c_int
+        L.orc_stress.argtypes = [ctypes.c_void_p, P(d)]
         _lib = L
     return _lib
 
@@ -252,6 +253,12 @@ class System:
         out = np.zeros(12)
         lib().orc_observables(self._h, _ptr(out, ctypes.c_double))
         return dict(zip(OBS_NAMES, out.tolist()))
+
+    def stress(self):
+        """Pressure tensor (xx, yy, zz, xy, xz, yz), brute-force pair sum."""
+        out = np.zeros(6)
+        lib().orc_stress(self._h, _ptr(out, ctypes.c_double))
+        return out
 
     def profile(self, axis: int, nbins: int, quantity: int):
         out = np.zeros(nbins)

@@ -896,3 +896,53 @@ int orc_tangent(const orc_params *p, int64_t n, const double *x0, const double *
     free(drho);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Pressure tensor of the current state (the tensor form of the virial     */
+/* pressure of orc_observables, used for the stress across an interface):  */
+/*   P_ab = [ sum_fluid m v_a v_b + sum_{fluid i, j in N_c(i)} c_ij         */
+/*            d_a d_b / r F^C(r) ] / V,                                     */
+/* d = x_i - x_j (minimum image), F^C = A w_c + B (rho_i + rho_j) w_d the    */
+/* conservative pair force magnitude (Eq. 1), c_ij = 1/2 for fluid j and 1   */
+/* for frozen j.  out[6] = xx, yy, zz, xy, xz, yz; its trace / 3 is the     */
+/* pressure.  Brute-force pair search over all j (the definition).          */
+/* ------------------------------------------------------------------------ */
+void orc_stress(const orc_system *s, double out[6])
+{
+    const orc_params *p = &s->p;
+    const int T = p->ntypes;
+    const int64_t n = s->n;
+    const double rc2 = p->rc * p->rc, rd2 = p->rd * p->rd;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        if (s->frozen[i]) continue;
+        const double *v = s->v + 3 * i;
+        acc[0] += p->mass * v[0] * v[0];
+        acc[1] += p->mass * v[1] * v[1];
+        acc[2] += p->mass * v[2] * v[2];
+        acc[3] += p->mass * v[0] * v[1];
+        acc[4] += p->mass * v[0] * v[2];
+        acc[5] += p->mass * v[1] * v[2];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            orc_delta(s->x, i, j, p->L, d);
+            double r2 = orc_r2(d);
+            if (!(r2 < rc2) || r2 == 0.0) continue;
+            double r = sqrt(r2);
+            int tt = s->type[i] * T + s->type[j];
+            double fc = p->A[tt] * (1.0 - r / p->rc);
+            if (r2 < rd2) fc += p->B[tt] * (s->rho[i] + s->rho[j]) * (1.0 - r / p->rd);
+            double c = s->frozen[j] ? 1.0 : 0.5;
+            double k = c * fc / r;
+            acc[0] += k * d[0] * d[0];
+            acc[1] += k * d[1] * d[1];
+            acc[2] += k * d[2] * d[2];
+            acc[3] += k * d[0] * d[1];
+            acc[4] += k * d[0] * d[2];
+            acc[5] += k * d[1] * d[2];
+        }
+    }
+    const double V = p->L[0] * p->L[1] * p->L[2];
+    for (int a = 0; a < 6; ++a) out[a] = acc[a] / V;
+}

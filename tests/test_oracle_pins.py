@@ -309,3 +309,41 @@ def test_wrap_edges(orc):
     for v in np.linspace(-L, 2 * L - 1e-9, 101):
         r = orc.wrap(v, L)
         assert 0.0 <= r < L
+
+
+# --------------------------------------------------------------------------
+# Pressure tensor
+# --------------------------------------------------------------------------
+def test_stress_trace_is_the_pressure_and_bulk_is_isotropic(orc):
+    """trace(P)/3 equals the scalar virial pressure (computed by another
+    routine, over the cell-list neighbour lists), and a bulk liquid's
+    off-diagonal components average to zero while the diagonal ones agree."""
+    w = W.bulk(L=6.0, seed=2)
+    p = _params(orc, w, search=0)
+    s = orc.System(p, w.x, w.v)
+    s.step(30)
+    P = s.stress()
+    assert np.sum(P[:3]) / 3.0 == pytest.approx(s.observables()["pressure"], rel=1e-12, abs=1e-12)
+    acc = []
+    for _ in range(30):
+        s.step(5)
+        acc.append(s.stress())
+    m = np.mean(acc, axis=0)
+    scale = abs(np.mean(m[:3])) + 6.0
+    assert np.all(np.abs(m[3:]) < 0.05 * scale)
+    assert np.ptp(m[:3]) < 0.1 * scale
+
+
+def test_stress_of_a_two_particle_system(orc):
+    """Two particles along x at distance r: only P_xx has a pair term,
+    r F^C / V with F^C from Eq. 1 (B term with rho_i = rho_j = w_rho(r))."""
+    L, r = 5.0, 0.6
+    x = np.array([[1.0, 2.0, 2.0], [1.0 + r, 2.0, 2.0]])
+    v = np.zeros((2, 3))
+    p = orc.make_params(box=L, A=-40.0, B=25.0, gamma=0.0, kT=0.0)
+    s = orc.System(p, x, v)
+    P = s.stress()
+    rho = orc.w_rho(r, 0.75)
+    fc = -40.0 * (1 - r) + 25.0 * 2 * rho * (1 - r / 0.75)
+    assert P[0] == pytest.approx(r * fc / L ** 3, rel=1e-13)
+    assert np.allclose(P[1:], 0.0, atol=1e-15)
