@@ -161,6 +161,16 @@ mdpd_status mdpd_read_observables(mdpd_system *s, mdpd_observables *out);
 mdpd_status mdpd_read_replica_observables(mdpd_system *s, int32_t first, int32_t count,
                                           mdpd_observables *out);
 
+/* Pressure tensor of replicas first .. first+count-1 (a single system is
+ * replica 0) at the current state, six values per replica into out[6 count]:
+ * xx, yy, zz, xy, xz, yz of
+ *   P_ab = [sum over fluid m v_a v_b + sum over fluid i, neighbours j of
+ *           c_ij d_a d_b F^C(r) / r] / V
+ * with d = x_i - x_j, F^C = A w_c + B (rho_i + rho_j) w_d (Eq. 1) and c_ij as
+ * for the virial; trace / 3 is the pressure of mdpd_observables.  Used for
+ * the stress difference across an interface (Sec. 4.1). */
+mdpd_status mdpd_read_stress(mdpd_system *s, int32_t first, int32_t count, double *out);
+
 /* Profile of fluid particles in nbins (1..4096) equal bins of L_axis along
  * axis (0..2).  quantity 0: number density; 1..3: mean velocity x, y, z;
  * 4: kinetic temperature of velocities relative to the bin mean; 5: mean

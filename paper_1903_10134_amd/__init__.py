@@ -13,6 +13,7 @@ from ._native import (FP32_FORCES, FP64, KERNELS, MEM_DEVICE, MEM_HOST, WALL_BVF
                       mdpd_get_state,
                       mdpd_last_error, mdpd_load_checkpoint, mdpd_read_kernel_timing,
                       mdpd_read_observables, mdpd_read_profile, mdpd_read_replica_observables,
+                      mdpd_read_stress,
                       mdpd_save_checkpoint,
                       mdpd_set_graph, mdpd_set_kernel_timing, mdpd_set_lanes, mdpd_step)
 
@@ -23,5 +24,6 @@ __all__ = ["FP32_FORCES", "FP64", "KERNELS", "MEM_DEVICE", "MEM_HOST", "WALL_BVF
            "mdpd_get_state",
            "mdpd_last_error", "mdpd_load_checkpoint", "mdpd_read_kernel_timing",
            "mdpd_read_observables", "mdpd_read_profile", "mdpd_read_replica_observables",
+           "mdpd_read_stress",
            "mdpd_save_checkpoint",
            "mdpd_set_graph", "mdpd_set_kernel_timing", "mdpd_set_lanes", "mdpd_step"]

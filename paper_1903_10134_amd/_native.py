@@ -69,6 +69,7 @@ _SIGS = {
     "mdpd_read_replica_observables": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p],
                                       ctypes.c_int32),
     "mdpd_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int32),
+    "mdpd_read_stress": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p], ctypes.c_int32),
     "mdpd_read_observables": ([ctypes.c_void_p, ctypes.POINTER(Observables)], ctypes.c_int32),
     "mdpd_read_profile": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                            ctypes.c_void_p], ctypes.c_int32),
@@ -227,6 +228,13 @@ def mdpd_read_observables(h) -> dict:
     o = Observables()
     _check(lib().mdpd_read_observables(h, ctypes.byref(o)))
     return _obs_dict(o)
+
+
+def mdpd_read_stress(h, first: int = 0, count: int = 1):
+    """Pressure tensor (xx, yy, zz, xy, xz, yz) per replica: shape (count, 6)."""
+    out = np.zeros(6 * max(count, 1))
+    _check(lib().mdpd_read_stress(h, int(first), int(count), out.ctypes.data))
+    return out[:6 * count].reshape(count, 6)
 
 
 def mdpd_read_replica_observables(h, first: int, count: int) -> list:
@@ -398,6 +406,9 @@ class System:
 
     def profile(self, axis, nbins, quantity):
         return mdpd_read_profile(self.h, axis, nbins, quantity)
+
+    def stress(self):
+        return mdpd_read_stress(self.h, 0, 1)[0]
 
     def state(self, with_rho=True):
         return mdpd_get_state(self.h, self.n, with_rho)

@@ -114,6 +114,7 @@ struct mdpd_system {
     double *tab = nullptr;
     double *obs = nullptr;       // 16 result slots per replica
     double *obs_part = nullptr;  // block partials of the observables
+    double *stress = nullptr;    // 6 planes of n (allocated on first use) + 6 per replica
     double *io = nullptr;   // n x 3 staging for exports and host inputs
     double *io2 = nullptr;  // second n x 3 staging
     double *work = nullptr;
@@ -415,6 +416,7 @@ PairConst make_pair_const(const mdpd_params *p, const double *tab)
     pc.wrho = 15.0 / (2.0 * M_PI * p->rd * p->rd * p->rd);
     pc.hdtm = 0.5 * p->dt / p->mass;
     pc.dt = p->dt;
+    pc.mass = p->mass;
     pc.phi_c = p->phi_c;
     pc.ntypes = p->ntypes;
     const double rdt = 1.0 / sqrt(p->dt);
@@ -750,6 +752,34 @@ mdpd_status mdpd_read_replica_observables(mdpd_system *s, int32_t first, int32_t
         o.mean_rho = nf > 0 ? q[4] / (double)nf : 0.0;
         o.ncorr_last = s->walls && s->step > 0 ? last : 0;
         o.ncorr_total = (int64_t)tot;
+    }
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_read_stress(mdpd_system *s, int32_t first, int32_t count, double *out)
+{
+    if (!s || !out) return fail(MDPD_E_INVALID, "NULL argument");
+    if (first < 0 || count < 0 || first + count > s->nrep)
+        return fail(MDPD_E_INVALID, "replicas [%d, %d) outside [0, %d)", first, first + count, s->nrep);
+    const size_t N = (size_t)s->n;
+    if (!s->stress) {
+        mdpd_status rc = s->alloc(&s->stress, 6 * (N > 0 ? N : 1) + 6 * (size_t)s->nrep);
+        if (rc) return rc;
+    }
+    double *sums = s->stress + 6 * (N > 0 ? N : 1);
+    launch_zero_int(s->st, (int *)sums, 12 * s->nrep);
+    launch_stress(s->st, s->fp32, s->mt, s->n, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur],
+                  s->typ[s->cur], s->cstart, s->ncnt, s->nl, s->stress);
+    if (N > 0) launch_stress_sum(s->st, s->R, s->n, s->stress, sums);
+    std::vector<double> h(6 * (size_t)(count > 0 ? count : 1));
+    if (count > 0)
+        HIPCHK(hipMemcpyAsync(h.data(), sums + 6 * (size_t)first, 6 * (size_t)count * sizeof(double),
+                              hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    for (int k = 0; k < count; ++k) {
+        const mdpd_params &p = s->params[first + k];
+        const double V = p.box[0] * p.box[1] * p.box[2];
+        for (int a = 0; a < 6; ++a) out[6 * k + a] = h[6 * (size_t)k + a] / V;
     }
     return MDPD_OK;
 }

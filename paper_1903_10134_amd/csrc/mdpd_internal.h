@@ -62,6 +62,7 @@ struct PairConst {
     double rc, inv_rc, rd, inv_rd, rd2;
     double wrho;        // 15 / (2 pi r_d^3)
     double hdtm, dt;    // dt / (2 m), dt
+    double mass;
     double mg[3];       // body force m g on fluid
     double A, B, gamma, sig, Arc2;  // single-type values; sig = sqrt(2 gamma kT / dt)
     double phi_c;
@@ -306,5 +307,11 @@ void launch_debug_neighbors(hipStream_t st, const Reps &R, double cutoff2, Soa3c
                             const uint32_t *tag, const int *cstart, const int *ncnt,
                             const uint32_t *nl, int64_t *count, uint64_t *hash);
 void launch_zero_int(hipStream_t st, int *p, int n);
+// Pressure tensor: per-slot planes (6 x n, xx yy zz xy xz yz), then per-replica
+// sums into out[6 r + a] (still to be divided by the replica's volume).
+void launch_stress(hipStream_t st, bool fp32, bool mt, int n, const Reps &R, Soa3c xs, Soa3c v,
+                   const void *rho, const uint32_t *tag, const uint8_t *typ, const int *cstart,
+                   const int *ncnt, const uint32_t *nl, double *out);
+void launch_stress_sum(hipStream_t st, const Reps &R, int n, const double *planes, double *out);
 
 }  // namespace mdpd

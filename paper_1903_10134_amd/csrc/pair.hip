@@ -661,6 +661,72 @@ __global__ __launch_bounds__(kBlock) void k_force_overflow(Reps Rp, const uint32
 }
 
 // ---------------------------------------------------------------------------
+// Pressure tensor per slot (read-out, not part of a step): for fluid i,
+// m v_a v_b + sum_j c_ij d_a d_b / r F^C(r), F^C = A w_c + B (rho_i + rho_j)
+// w_d, c_ij = 1/2 for fluid j and 1 for frozen j; frozen slots give 0.
+// out: six FP64 planes (xx, yy, zz, xy, xz, yz) of n entries.
+template <int P, bool MT, typename R>
+__global__ __launch_bounds__(kBlock) void k_stress(Reps Rp, Soa3c xs, Soa3c v, const R *__restrict__ rho,
+                                                   const uint32_t *__restrict__ tag,
+                                                   const uint8_t *__restrict__ typ,
+                                                   const int *__restrict__ cstart_all,
+                                                   const int *__restrict__ ncnt,
+                                                   const uint32_t *__restrict__ nl, int n,
+                                                   double *__restrict__ out)
+{
+    const BlockRep br = block_rep<P>(Rp, xcd_block());
+    const int i = br.i0 + (int)threadIdx.x / P;
+    const int sub = threadIdx.x & (P - 1);
+    if (i >= br.i1) return;
+    const PairConst pc = cload(Rp.pc, br.r);
+    const Geom g = cload(Rp.geom, br.r);
+    const int *__restrict__ cstart = cstart_all + cload(Rp.cell_off, br.r);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (!(tag[i] & kFrozenBit)) {
+        const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
+        const double rhoi = (double)rho[i];
+        const int T = pc.ntypes;
+        const int ti = MT ? (int)typ[i] : 0;
+        for_each_neighbor<P>(pc, g, i, sub, xi, yi, zi, xs, cstart, ncnt[i], nl + (size_t)i * kListCap,
+                             [&](int j, double dx, double dy, double dz, bool near) {
+            const double r2 = exact_r2(dx, dy, dz);
+            if (!(r2 > 0.0)) return;
+            const double r = __builtin_sqrt(r2);
+            double A = pc.A, B = pc.B;
+            if (MT) {
+                const int tt = ti * T + (int)typ[j];
+                A = pc.tab[tt];
+                B = pc.tab[64 + tt];
+            }
+            double fc = A * (1.0 - r * pc.inv_rc);
+            if (near) fc += B * (rhoi + (double)rho[j]) * (1.0 - r * pc.inv_rd);
+            const double k = ((tag[j] & kFrozenBit) ? 1.0 : 0.5) * fc / r;
+            acc[0] += k * dx * dx;
+            acc[1] += k * dy * dy;
+            acc[2] += k * dz * dz;
+            acc[3] += k * dx * dy;
+            acc[4] += k * dx * dz;
+            acc[5] += k * dy * dz;
+        });
+        if (sub == 0) {
+            const double m = pc.mass;
+            const double vx = v.x[i], vy = v.y[i], vz = v.z[i];
+            acc[0] += m * vx * vx;
+            acc[1] += m * vy * vy;
+            acc[2] += m * vz * vz;
+            acc[3] += m * vx * vy;
+            acc[4] += m * vx * vz;
+            acc[5] += m * vy * vz;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) acc[a] = group_sum<P>(acc[a]);
+    if (sub == 0)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) out[(size_t)a * n + i] = acc[a];
+}
+
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t mix64(uint64_t z)
 {
     z += 0x9E3779B97F4A7C15ull;
@@ -778,6 +844,27 @@ void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, 
             else go(F{}, Tid<double>{});
         }
     });
+}
+
+void launch_stress(hipStream_t st, bool fp32, bool mt, int n, const Reps &R, Soa3c xs, Soa3c v, const void *rho,
+                   const uint32_t *tag, const uint8_t *typ, const int *cstart, const int *ncnt, const uint32_t *nl,
+                   double *out)
+{
+    constexpr int L = 4;
+    const int nb = R.nblk[lanes_index(L)];
+    if (nb <= 0) return;
+    auto go = [&](auto mtc, auto rc) {
+        constexpr bool M = decltype(mtc)::value;
+        using RT = typename decltype(rc)::type;
+        k_stress<L, M, RT><<<nb, kBlock, 0, st>>>(R, xs, v, (const RT *)rho, tag, typ, cstart, ncnt, nl, n, out);
+    };
+    if (fp32) {
+        if (mt) go(std::true_type{}, Tid<float>{});
+        else go(std::false_type{}, Tid<float>{});
+    } else {
+        if (mt) go(std::true_type{}, Tid<double>{});
+        else go(std::false_type{}, Tid<double>{});
+    }
 }
 
 void launch_debug_neighbors(hipStream_t st, const Reps &R, double cut2, Soa3c xs, const uint32_t *tag,

@@ -177,6 +177,21 @@ __global__ __launch_bounds__(kBlock) void k_export(Reps Rp, Soa3c x, Soa3c v, co
     if (rho_out) rho_out[id] = (double)rho[i];
 }
 
+// Per-replica sums of the six pressure-tensor planes written by k_stress:
+// one block per replica, fixed order (strided partials, then a tree).
+__global__ __launch_bounds__(kRed) void k_stress_sum(Reps Rp, int n, const double *planes, double *out)
+{
+    __shared__ double sh[6][kRed];
+    const int r = blockIdx.x;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const int b = cload(Rp.part_off, r), e = cload(Rp.part_off, r + 1);
+    for (int i = b + threadIdx.x; i < e; i += kRed)
+        for (int a = 0; a < 6; ++a) acc[a] += planes[(size_t)a * n + i];
+    block_tree<6>(sh, acc);
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 6; ++a) out[6 * r + a] = acc[a];
+}
+
 // acc[3r + 0..2] += scale * (mean fluid rho, virial pressure, mean fluid
 // v_x) of replica r from the final sums of k_obs_final.
 __global__ void k_loss_accum(int nrep, const double *obs, const LossConst *lc, double *acc, double scale)
@@ -191,6 +206,11 @@ __global__ void k_loss_accum(int nrep, const double *obs, const LossConst *lc, d
 }
 
 }  // namespace
+
+void launch_stress_sum(hipStream_t st, const Reps &R, int n, const double *planes, double *out)
+{
+    k_stress_sum<<<R.nrep, kRed, 0, st>>>(R, n, planes, out);
+}
 
 void launch_loss_accum(hipStream_t st, int nrep, const double *obs, const LossConst *lc, double *acc,
                        double scale)
