@@ -154,6 +154,27 @@ def run_batch(mdpd, W, nrep, steps, every):
             "loss_mean_rho_r0": float(loss[0][0]), "dA_r0": float(g["dA"][0][0, 0])}
 
 
+def run_small(mdpd, W, steps):
+    """The 6,000-particle box (L = 10): launch-bound, so stepping by replaying
+    a captured HIP graph is compared with eager launches."""
+    import torch
+    w = W.bulk(L=10.0, seed=0)
+    out = {"workload": "bulk mDPD liquid, periodic 10^3 box, 6000 particles", "particles": w.n, "steps": steps}
+    for mode in ("eager", "graph"):
+        s = mdpd.System(w, precision=mdpd.FP32_FORCES, device_inputs=True)
+        s.set_graph(mode == "graph")
+        s.step(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        s.close()
+        out[f"{mode}_us_per_step"] = sec * 1e6 / steps
+        out[f"{mode}_particle_steps_per_s"] = w.n * steps / sec
+    return out
+
+
 def run_walled(mdpd, w, steps, warmup):
     """A walled workload (frozen wall particles, boundary-volume-fraction
     corrector, body force), FP32 forces: step time and corrector activity."""
@@ -272,6 +293,10 @@ def main():
               f"{bt['forward_ms_per_step']:.3f} ms/step forward, adjoint/forward "
               f"{bt['adjoint_over_forward']:.2f} (record+adjoint {bt['record_plus_adjoint_over_forward']:.2f})",
               file=sys.stderr, flush=True)
+    sm = run_small(mdpd, W, 2000)
+    out["small"] = sm
+    print(f"# small 6000 particles: eager {sm['eager_us_per_step']:.1f} us/step, "
+          f"graph {sm['graph_us_per_step']:.1f} us/step", file=sys.stderr, flush=True)
     if not a.no_walls:
         ch = run_walled(mdpd, W.channel(), 200, 20)
         ch["workload"] = "Poiseuille channel 64 x 32 x 64, frozen walls of thickness 2, g_x = 0.02"
