@@ -517,8 +517,11 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
                              });
     } else {
         const int cnt = list_total(packed), nnear = list_near(packed);
+        // the next entry is loaded one iteration ahead, so a neighbour costs one
+        // memory round trip (its record) instead of two
+        uint32_t e = sub < cnt ? lst[list_pos(sub, nnear)] : 0u;
         for (int k = sub; k < cnt; k += P) {
-            const uint32_t e = lst[list_pos(k, nnear)];
+            const uint32_t en = k + P < cnt ? lst[list_pos(k + P, nnear)] : 0u;
             const int j = (int)(e & kSlotMask);
             // the neighbour's packed record: four 16-byte loads of one sector
             const double2 *q = (const double2 *)(rec + j);
@@ -527,13 +530,14 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
             const R rj = (R)__longlong_as_double((long long)(((unsigned long long)d.y << 32) | d.x));
             const uint32_t tgj = d.z;
             const int tj = MT ? (int)d.w : 0;
-            // the minimum-image shift is a select, so no branch splits the loads
-            const bool wr = (e & kWrapBit) != 0;
             double dx = xi - a.x, dy = yi - a.y, dz = zi - b.x;
-            dx = wr ? min_image(dx, pc.L[0], pc.invL[0]) : dx;
-            dy = wr ? min_image(dy, pc.L[1], pc.invL[1]) : dy;
-            dz = wr ? min_image(dz, pc.L[2], pc.invL[2]) : dz;
+            if (e & kWrapBit) {  // pairs through a periodic image (border cells only)
+                dx = min_image(dx, pc.L[0], pc.invL[0]);
+                dy = min_image(dy, pc.L[1], pc.invL[1]);
+                dz = min_image(dz, pc.L[2], pc.invL[2]);
+            }
             pair(dx, dy, dz, b.y, c.x, c.y, rj, tgj, tj, (e & kNearBit) != 0);
+            e = en;
         }
     }
     fx = group_sum<P>(fx);
