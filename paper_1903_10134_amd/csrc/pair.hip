@@ -47,19 +47,27 @@ namespace {
 // the front and their exact r^2 is stored at the same position of a parallel
 // array (R2 = FP32 or FP64, the arithmetic of the density pass); the other
 // entries fill the row from the back.
-// Near hits go to the front with their r^2, the others to the back; a row
-// whose counts add up to more than kListCap is not read (direct scan).
+
+// Hits of one 64-candidate test for particle i: hm marks the lanes whose
+// candidate is within r_c, nm those within r_d; cn / cf are i's near / far
+// counts before this test.  A near hit goes to position cn + (near hits in
+// lower lanes) with its r^2 beside it, a far hit to kListCap-1 - (cf + far
+// hits in lower lanes).  The far position is formed as pn - t with
+// t = cn + cf - (kListCap-1) + (hits in lower lanes), since the far hits below
+// are the hits below minus the near hits below.  A row whose counts add up to
+// more than kListCap is never read (direct scan); its writes only have to stay
+// inside the row, hence the mask.
 template <typename R2>
-__device__ __forceinline__ void emit_hit(uint32_t *__restrict__ out, R2 *__restrict__ outr, bool near,
-                                         int pos, int slot, double r2, bool wrap)
+__device__ __forceinline__ void emit_hits(uint32_t *__restrict__ out, R2 *__restrict__ outr, unsigned long long hm,
+                                          unsigned long long nm, int cn, int cf, uint32_t e, double r2)
 {
-    if (pos >= kListCap) return;
-    const uint32_t e = (uint32_t)slot | (near ? kNearBit : 0u) | (wrap ? kWrapBit : 0u);
-    if (near) {
-        out[pos] = e;
-        outr[pos] = (R2)r2;
-    } else {
-        out[kListCap - 1 - pos] = e;
+    if (__builtin_amdgcn_inverse_ballot_w64(hm)) {
+        const bool near = __builtin_amdgcn_inverse_ballot_w64(nm);
+        const int pn = lanes_below(hm & nm, cn);
+        const int t = lanes_below(hm, cn + cf - (kListCap - 1));
+        const int k = (near ? pn : pn - t) & (kListCap - 1);
+        out[k] = e | (near ? kNearBit : 0u);
+        if (near) outr[k] = (R2)r2;
     }
 }
 
@@ -101,6 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const i
     if (fast) {
         double cxj[6], cyj[6], czj[6];
         int cs[6];
+        unsigned long long vm[6];  // the lanes of each slot that hold a candidate
 #pragma unroll
         for (int s = 0; s < 6; ++s) {
             const int z = s >> 1;
@@ -112,11 +121,15 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const i
                               : (q < l0 + l1 ? rb[3 * z + 1] + (q - l0) : rb[3 * z + 2] + (q - l0 - l1));
             }
             cs[s] = slot;
+            vm[s] = __builtin_amdgcn_ballot_w64(slot >= 0);
             const int js = slot >= 0 ? slot : i0;
             cxj[s] = ld(xs.x, js);
             cyj[s] = ld(xs.y, js);
             czj[s] = ld(xs.z, js);
         }
+        // the own cell is the middle cell of row 4 (dy = dz = 0): particle i is
+        // candidate selfq0 + i of the dz = 0 batch
+        const int selfq0 = rl[3] - rb[4];
         for (int ib = 0; ib < ni; ib += 64) {
             const int nic = ni - ib < 64 ? ni - ib : 64;
             const int me = i0 + ib + (lane < nic ? lane : 0);
@@ -124,6 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const i
             for (int u = 0; u < nic; ++u) {
                 const double xi = bcast_d(pxi, u), yi = bcast_d(pyi, u), zi = bcast_d(pzi, u);
                 const int i = i0 + ib + u;
+                const int sq = selfq0 + i;
                 uint32_t *out = nl + (size_t)i * kListCap;
                 R2 *outr = nlr2 + (size_t)i * kListCap;
                 int cn = 0, cf = 0;
@@ -131,16 +145,13 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const i
                 for (int s = 0; s < 6; ++s) {
                     if ((s & 1) && qz[s >> 1] <= 64) continue;
                     const double r2 = exact_r2(xi - cxj[s], yi - cyj[s], zi - czj[s]);
-                    const bool hit = cs[s] >= 0 && cs[s] != i && r2 < rc2;
-                    const bool near = r2 < rd2;
-                    const unsigned long long mn = __ballot(hit && near);
-                    const unsigned long long mf = __ballot(hit && !near);
-                    if (mn | mf) {
-                        if (hit)
-                            emit_hit<R2>(out, outr, near, near ? cn + lanes_below(mn) : cf + lanes_below(mf),
-                                         cs[s], r2, false);
-                        cn += __popcll(mn);
-                        cf += __popcll(mf);
+                    unsigned long long hm = __builtin_amdgcn_ballot_w64(r2 < rc2) & vm[s];
+                    if ((s >> 1) == 1 && (sq >> 6) == (s & 1)) hm &= ~(1ull << (sq & 63));
+                    if (hm) {
+                        const unsigned long long nm = __builtin_amdgcn_ballot_w64(r2 < rd2);
+                        emit_hits<R2>(out, outr, hm, nm, cn, cf, (uint32_t)cs[s], r2);
+                        cn += __popcll(hm & nm);
+                        cf += __popcll(hm & ~nm);
                     }
                 }
                 if (lane == 0) ncnt[i] = cn | (cf << 16);
@@ -217,18 +228,14 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const i
                     const double xi = bcast_d(pxi, u), yi = bcast_d(pyi, u), zi = bcast_d(pzi, u);
                     const int i = i0 + ib + u;
                     const double r2 = exact_r2((xi - xj) + sx, (yi - yj) + sy, (zi - zj) + sz);
-                    const bool hit = slot >= 0 && slot != i && r2 < rc2;
-                    const bool near = r2 < rd2;
-                    const unsigned long long mn = __ballot(hit && near);
-                    const unsigned long long mf = __ballot(hit && !near);
-                    if (mn | mf) {
+                    const unsigned long long hm = __builtin_amdgcn_ballot_w64(slot >= 0 && slot != i && r2 < rc2);
+                    if (hm) {
+                        const unsigned long long nm = __builtin_amdgcn_ballot_w64(r2 < rd2);
                         const int base = bcast_i(cnt, u);
-                        if (hit)
-                            emit_hit<R2>(nl + (size_t)i * kListCap, nlr2 + (size_t)i * kListCap, near,
-                                         near ? (base & 0xffff) + lanes_below(mn)
-                                              : (base >> 16) + lanes_below(mf),
-                                         slot, r2, sx != 0.0 || sy != 0.0 || sz != 0.0);
-                        if (lane == u) cnt += __popcll(mn) + (__popcll(mf) << 16);
+                        emit_hits<R2>(nl + (size_t)i * kListCap, nlr2 + (size_t)i * kListCap, hm, nm, base & 0xffff,
+                                      base >> 16, (uint32_t)slot | (sx != 0.0 || sy != 0.0 || sz != 0.0 ? kWrapBit : 0u),
+                                      r2);
+                        if (lane == u) cnt += __popcll(hm & nm) + (__popcll(hm & ~nm) << 16);
                     }
                 }
             }

@@ -103,9 +103,10 @@ __device__ __forceinline__ double bcast_d(double v, int u)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-__device__ __forceinline__ int lanes_below(unsigned long long m)
+// base + the number of set bits of m in the lanes below this one
+__device__ __forceinline__ int lanes_below(unsigned long long m, int base = 0)
 {
-    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, (unsigned)base));
 }
 
 // List row layout: the kListCap entries of particle i hold its neighbours
