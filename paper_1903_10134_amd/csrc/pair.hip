@@ -48,6 +48,30 @@ namespace {
 // array (R2 = FP32 or FP64, the arithmetic of the density pass); the other
 // entries fill the row from the back.
 
+// Stores into one list row go through a buffer resource whose range is the
+// row: a lane with nothing to store gives an offset past the range, and the
+// hardware drops the store, so the emission needs no branch.
+constexpr int kDropOffset = (int)0x80000000;
+constexpr int kRawBufferConfig = 0x00020000;  // 32-bit data format, no swizzle
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(void *row, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(row, (short)0, bytes, kRawBufferConfig);
+}
+
+__device__ __forceinline__ void store_r2(__amdgpu_buffer_rsrc_t r, int k, bool keep, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, keep ? k * 4 : kDropOffset, 0, 0);
+}
+
+__device__ __forceinline__ void store_r2(__amdgpu_buffer_rsrc_t r, int k, bool keep, double v)
+{
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const u32x2 w = {(unsigned)b, (unsigned)(b >> 32)};
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, keep ? k * 8 : kDropOffset, 0, 0);
+}
+
 // Hits of one 64-candidate test for particle i: hm marks the lanes whose
 // candidate is within r_c, nm those within r_d; cn / cf are i's near / far
 // counts before this test.  A near hit goes to position cn + (near hits in
@@ -58,17 +82,17 @@ namespace {
 // more than kListCap is never read (direct scan); its writes only have to stay
 // inside the row, hence the mask.
 template <typename R2>
-__device__ __forceinline__ void emit_hits(uint32_t *__restrict__ out, R2 *__restrict__ outr, unsigned long long hm,
+__device__ __forceinline__ void emit_hits(__amdgpu_buffer_rsrc_t ro, __amdgpu_buffer_rsrc_t rr, unsigned long long hm,
                                           unsigned long long nm, int cn, int cf, uint32_t e, double r2)
 {
-    if (__builtin_amdgcn_inverse_ballot_w64(hm)) {
-        const bool near = __builtin_amdgcn_inverse_ballot_w64(nm);
-        const int pn = lanes_below(hm & nm, cn);
-        const int t = lanes_below(hm, cn + cf - (kListCap - 1));
-        const int k = (near ? pn : pn - t) & (kListCap - 1);
-        out[k] = e | (near ? kNearBit : 0u);
-        if (near) outr[k] = (R2)r2;
-    }
+    const bool hit = __builtin_amdgcn_inverse_ballot_w64(hm);
+    const bool near = __builtin_amdgcn_inverse_ballot_w64(nm);
+    const bool hit_near = __builtin_amdgcn_inverse_ballot_w64(hm & nm);
+    const int pn = lanes_below(hm & nm, cn);
+    const int t = lanes_below(hm, cn + cf - (kListCap - 1));
+    const int k = (near ? pn : pn - t) & (kListCap - 1);
+    __builtin_amdgcn_raw_buffer_store_b32(e | (near ? kNearBit : 0u), ro, hit ? k * 4 : kDropOffset, 0, 0);
+    store_r2(rr, k, hit_near, (R2)r2);
 }
 
 template <typename R2>
@@ -138,8 +162,8 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const i
                 const double xi = bcast_d(pxi, u), yi = bcast_d(pyi, u), zi = bcast_d(pzi, u);
                 const int i = i0 + ib + u;
                 const int sq = selfq0 + i;
-                uint32_t *out = nl + (size_t)i * kListCap;
-                R2 *outr = nlr2 + (size_t)i * kListCap;
+                const __amdgpu_buffer_rsrc_t ro = row_rsrc(nl + (size_t)i * kListCap, kListCap * 4);
+                const __amdgpu_buffer_rsrc_t rr = row_rsrc(nlr2 + (size_t)i * kListCap, kListCap * (int)sizeof(R2));
                 int cn = 0, cf = 0;
 #pragma unroll
                 for (int s = 0; s < 6; ++s) {
@@ -147,12 +171,10 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const i
                     const double r2 = exact_r2(xi - cxj[s], yi - cyj[s], zi - czj[s]);
                     unsigned long long hm = __builtin_amdgcn_ballot_w64(r2 < rc2) & vm[s];
                     if ((s >> 1) == 1 && (sq >> 6) == (s & 1)) hm &= ~(1ull << (sq & 63));
-                    if (hm) {
-                        const unsigned long long nm = __builtin_amdgcn_ballot_w64(r2 < rd2);
-                        emit_hits<R2>(out, outr, hm, nm, cn, cf, (uint32_t)cs[s], r2);
-                        cn += __popcll(hm & nm);
-                        cf += __popcll(hm & ~nm);
-                    }
+                    const unsigned long long nm = __builtin_amdgcn_ballot_w64(r2 < rd2);
+                    emit_hits<R2>(ro, rr, hm, nm, cn, cf, (uint32_t)cs[s], r2);
+                    cn += __popcll(hm & nm);
+                    cf += __popcll(hm & ~nm);
                 }
                 if (lane == 0) ncnt[i] = cn | (cf << 16);
             }
@@ -232,9 +254,10 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const i
                     if (hm) {
                         const unsigned long long nm = __builtin_amdgcn_ballot_w64(r2 < rd2);
                         const int base = bcast_i(cnt, u);
-                        emit_hits<R2>(nl + (size_t)i * kListCap, nlr2 + (size_t)i * kListCap, hm, nm, base & 0xffff,
-                                      base >> 16, (uint32_t)slot | (sx != 0.0 || sy != 0.0 || sz != 0.0 ? kWrapBit : 0u),
-                                      r2);
+                        emit_hits<R2>(row_rsrc(nl + (size_t)i * kListCap, kListCap * 4),
+                                      row_rsrc(nlr2 + (size_t)i * kListCap, kListCap * (int)sizeof(R2)), hm, nm,
+                                      base & 0xffff, base >> 16,
+                                      (uint32_t)slot | (sx != 0.0 || sy != 0.0 || sz != 0.0 ? kWrapBit : 0u), r2);
                         if (lane == u) cnt += __popcll(hm & nm) + (__popcll(hm & ~nm) << 16);
                     }
                 }
