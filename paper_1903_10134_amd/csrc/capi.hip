@@ -370,6 +370,7 @@ mdpd_status make_geom(const mdpd_params *p, Geom *g)
         g->nc[a] = nc;
         g->s[a] = nc / L;
         g->cs[a] = L / nc;
+        g->inv_nc[a] = 1.0 / nc;
         total *= nc;
     }
     if (total > (long long)4096 * 4096) return fail(MDPD_E_UNSUPPORTED, "more than 2^24 cells");

@@ -52,6 +52,7 @@ struct Geom {
     double L[3];
     double s[3];   // cells per unit length, nc / L
     double cs[3];  // cell edge, L / nc
+    double inv_nc[3];  // 1 / nc: splits a cell index into its coordinates
     int nc[3];
     int ncells;
     double rc, rc2, rd2;

@@ -80,7 +80,7 @@ __device__ __forceinline__ void store_r2(__amdgpu_buffer_rsrc_t r, int k, bool k
 // t = cn + cf - (kListCap-1) + (hits in lower lanes), since the far hits below
 // are the hits below minus the near hits below.  A row whose counts add up to
 // more than kListCap is never read (direct scan); its writes only have to stay
-// inside the row, hence the mask.
+// inside the row.
 template <typename R2>
 __device__ __forceinline__ void emit_hits(__amdgpu_buffer_rsrc_t ro, __amdgpu_buffer_rsrc_t rr, unsigned long long hm,
                                           unsigned long long nm, int cn, int cf, uint32_t e, double r2)
@@ -90,7 +90,9 @@ __device__ __forceinline__ void emit_hits(__amdgpu_buffer_rsrc_t ro, __amdgpu_bu
     const bool hit_near = __builtin_amdgcn_inverse_ballot_w64(hm & nm);
     const int pn = lanes_below(hm & nm, cn);
     const int t = lanes_below(hm, cn + cf - (kListCap - 1));
-    const int k = (near ? pn : pn - t) & (kListCap - 1);
+    // a position outside the row gives a byte offset outside the range (a
+    // negative one reads as a huge unsigned offset): such a store is dropped
+    const int k = near ? pn : pn - t;
     __builtin_amdgcn_raw_buffer_store_b32(e | (near ? kNearBit : 0u), ro, hit ? k * 4 : kDropOffset, 0, 0);
     store_r2(rr, k, hit_near, (R2)r2);
 }
@@ -112,15 +114,21 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const i
     const int i0 = cstart[c], ni = cstart[c + 1] - i0;
     if (ni == 0) return;
     const int nx = g.nc[0], ny = g.nc[1], nz = g.nc[2];
-    const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
+    // cell coordinates: the quotients are exact in FP64 (at most 2^24 cells),
+    // which avoids integer division
+    const int cyz = __builtin_amdgcn_readfirstlane((int)(((double)c + 0.5) * g.inv_nc[0]));
+    const int cz = __builtin_amdgcn_readfirstlane((int)(((double)cyz + 0.5) * g.inv_nc[1]));
+    const int cx = c - cyz * nx, cy = cyz - cz * ny;
     const double rc2 = g.rc2, rd2 = g.rd2;
 
     bool fast = cx > 0 && cx < nx - 1 && cy > 0 && cy < ny - 1 && cz > 0 && cz < nz - 1;
     int rb[9], rl[9], qz[3];
     if (fast) {
+        // row r = (dy + 1) + 3 (dz + 1) spans the cells c + dy nx + dz nx ny - 1 .. + 1
+        const int nxy = nx * ny;
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
-            const int base = nx * ((cy + r % 3 - 1) + ny * (cz + r / 3 - 1)) + cx;
+            const int base = c + (r % 3 - 1) * nx + (r / 3 - 1) * nxy;
             rb[r] = cstart[base - 1];
             rl[r] = cstart[base + 2] - rb[r];
         }
