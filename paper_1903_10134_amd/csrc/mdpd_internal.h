@@ -22,7 +22,7 @@
 namespace mdpd {
 
 constexpr int kListCap = 64;   // neighbour-list slots per particle
-static_assert((kListCap & (kListCap - 1)) == 0, "row positions wrap with a mask");
+static_assert((kListCap & (kListCap - 1)) == 0, "far-buffer positions wrap with a mask");
 constexpr int kBlock = 256;    // threads per block of the particle kernels
 constexpr uint32_t kFrozenBit = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7fffffffu;

@@ -43,10 +43,12 @@ namespace {
 //
 // Each entry is the neighbour's slot, with kNearBit set when r < r_d and
 // kWrapBit set when the pair is seen through a periodic image (its difference
-// then needs the minimum-image shift).  Entries with r < r_d fill the row from
-// the front and their exact r^2 is stored at the same position of a parallel
-// array (R2 = FP32 or FP64, the arithmetic of the density pass); the other
-// entries fill the row from the back.
+// then needs the minimum-image shift).  A row holds the entries with r < r_d
+// first, their exact r^2 at the same positions of a parallel array (R2 = FP32
+// or FP64, the arithmetic of the density pass), then the other entries, with
+// no gap: a row of the usual ~25 entries is one 128-byte line.  Near hits are
+// stored as they are found; far hits wait in LDS until the particle's near
+// count is known.
 
 // Stores into one list row go through a buffer resource whose range is the
 // row: a lane with nothing to store gives an offset past the range, and the
@@ -72,30 +74,43 @@ __device__ __forceinline__ void store_r2(__amdgpu_buffer_rsrc_t r, int k, bool k
     __builtin_amdgcn_raw_buffer_store_b64(w, r, keep ? k * 8 : kDropOffset, 0, 0);
 }
 
-// Hits of one 64-candidate test for particle i: hm marks the lanes whose
-// candidate is within r_c, nm those within r_d; cn / cf are i's near / far
-// counts before this test.  A near hit goes to position cn + (near hits in
-// lower lanes) with its r^2 beside it, a far hit to kListCap-1 - (cf + far
-// hits in lower lanes).  The far position is formed as pn - t with
-// t = cn + cf - (kListCap-1) + (hits in lower lanes), since the far hits below
-// are the hits below minus the near hits below.  A row whose counts add up to
-// more than kListCap is never read (direct scan); its writes only have to stay
-// inside the row.
+// Hits of one 64-candidate test for particle i: mn marks the lanes whose
+// candidate is within r_d, mf those within r_c but not r_d; cn / cf are i's
+// near / far counts before this test.  A near hit goes to row position
+// cn + (near hits in lower lanes) with its r^2 beside it; a far hit goes to
+// position cf + (far hits in lower lanes) of the far buffer fb (lanes
+// without one write to their own slot of dump).  A row whose counts
+// add up to more than kListCap is never read (direct scan): its positions past
+// the row are dropped by the store range check, and the far buffer index is
+// kept inside the buffer.
 template <typename R2>
-__device__ __forceinline__ void emit_hits(__amdgpu_buffer_rsrc_t ro, __amdgpu_buffer_rsrc_t rr, unsigned long long hm,
-                                          unsigned long long nm, int cn, int cf, uint32_t e, double r2)
+__device__ __forceinline__ void emit_hits(__amdgpu_buffer_rsrc_t ro, __amdgpu_buffer_rsrc_t rr, uint32_t *fb,
+                                          uint32_t *dump, unsigned long long mn, unsigned long long mf, int cn,
+                                          int cf, uint32_t e, double r2)
 {
-    const bool hit = __builtin_amdgcn_inverse_ballot_w64(hm);
-    const bool near = __builtin_amdgcn_inverse_ballot_w64(nm);
-    const bool hit_near = __builtin_amdgcn_inverse_ballot_w64(hm & nm);
-    const int pn = lanes_below(hm & nm, cn);
-    const int t = lanes_below(hm, cn + cf - (kListCap - 1));
-    // a position outside the row gives a byte offset outside the range (a
-    // negative one reads as a huge unsigned offset): such a store is dropped
-    const int k = near ? pn : pn - t;
-    __builtin_amdgcn_raw_buffer_store_b32(e | (near ? kNearBit : 0u), ro, hit ? k * 4 : kDropOffset, 0, 0);
-    store_r2(rr, k, hit_near, (R2)r2);
+    const int lane = threadIdx.x & 63;
+    const bool near = __builtin_amdgcn_inverse_ballot_w64(mn);
+    const bool far = __builtin_amdgcn_inverse_ballot_w64(mf);
+    const int pn = lanes_below(mn, cn);
+    const int pf = lanes_below(mf, cf) & (kListCap - 1);
+    __builtin_amdgcn_raw_buffer_store_b32(e | kNearBit, ro, near ? pn * 4 : kDropOffset, 0, 0);
+    store_r2(rr, pn, near, (R2)r2);
+    *(far ? fb + pf : dump + lane) = e;
 }
+
+// The far hits of particle i, held in fb[0 .. cf), appended to its row after
+// its cn near hits.
+__device__ __forceinline__ void flush_far(__amdgpu_buffer_rsrc_t ro, const uint32_t *fb, int cn, int cf)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t e = fb[lane];
+    __builtin_amdgcn_raw_buffer_store_b32(e, ro, lane < cf ? (cn + lane) * 4 : kDropOffset, 0, 0);
+}
+
+// LDS of one wavefront: the far buffers of up to kGenBatch particles (one in
+// the interior path) and one slot per lane for lanes without a far hit.
+constexpr int kGenBatch = 8;
+constexpr int kFarLds = (kGenBatch + 1) * kListCap;
 
 template <typename R2>
 __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const int *__restrict__ cstart_all,
@@ -103,7 +118,10 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const i
                                                        R2 *__restrict__ nlr2, const int *__restrict__ gate)
 {
     if (gate && *gate == 0) return;
+    __shared__ uint32_t lds[kWavesPerBlock * kFarLds];
     const int lane = threadIdx.x & 63;
+    uint32_t *const far_lds = lds + (threadIdx.x >> 6) * kFarLds;
+    uint32_t *const dump = far_lds + kGenBatch * kListCap;
     const int cg = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
     if (cg >= R.ncells) return;
     // the replica of this cell: its lattice, and its cell offsets (global slots)
@@ -180,10 +198,12 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const i
                     unsigned long long hm = __builtin_amdgcn_ballot_w64(r2 < rc2) & vm[s];
                     if ((s >> 1) == 1 && (sq >> 6) == (s & 1)) hm &= ~(1ull << (sq & 63));
                     const unsigned long long nm = __builtin_amdgcn_ballot_w64(r2 < rd2);
-                    emit_hits<R2>(ro, rr, hm, nm, cn, cf, (uint32_t)cs[s], r2);
-                    cn += __popcll(hm & nm);
-                    cf += __popcll(hm & ~nm);
+                    const unsigned long long mn = hm & nm, mf = hm & ~nm;
+                    emit_hits<R2>(ro, rr, far_lds, dump, mn, mf, cn, cf, (uint32_t)cs[s], r2);
+                    cn += __popcll(mn);
+                    cf += __popcll(mf);
                 }
+                flush_far(ro, far_lds, cn, cf);
                 if (lane == 0) ncnt[i] = cn | (cf << 16);
             }
         }
@@ -192,8 +212,9 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const i
 
     // general path
     const bool wl = cx == 0, wr = cx == nx - 1;  // the row wraps on the left / right
-    for (int ib = 0; ib < ni; ib += 64) {
-        const int nic = ni - ib < 64 ? ni - ib : 64;
+    // particles in batches of kGenBatch, each with its far buffer
+    for (int ib = 0; ib < ni; ib += kGenBatch) {
+        const int nic = ni - ib < kGenBatch ? ni - ib : kGenBatch;
         const int me = i0 + ib + (lane < nic ? lane : 0);
         const double pxi = ld(xs.x, me), pyi = ld(xs.y, me), pzi = ld(xs.z, me);
         int cnt = 0;  // lane u: near count | far count << 16 of particle i0 + ib + u
@@ -261,15 +282,21 @@ __global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const i
                     const unsigned long long hm = __builtin_amdgcn_ballot_w64(slot >= 0 && slot != i && r2 < rc2);
                     if (hm) {
                         const unsigned long long nm = __builtin_amdgcn_ballot_w64(r2 < rd2);
+                        const unsigned long long mn = hm & nm, mf = hm & ~nm;
                         const int base = bcast_i(cnt, u);
                         emit_hits<R2>(row_rsrc(nl + (size_t)i * kListCap, kListCap * 4),
-                                      row_rsrc(nlr2 + (size_t)i * kListCap, kListCap * (int)sizeof(R2)), hm, nm,
-                                      base & 0xffff, base >> 16,
+                                      row_rsrc(nlr2 + (size_t)i * kListCap, kListCap * (int)sizeof(R2)),
+                                      far_lds + u * kListCap, dump, mn, mf, base & 0xffff, base >> 16,
                                       (uint32_t)slot | (sx != 0.0 || sy != 0.0 || sz != 0.0 ? kWrapBit : 0u), r2);
-                        if (lane == u) cnt += __popcll(hm & nm) + (__popcll(hm & ~nm) << 16);
+                        if (lane == u) cnt += __popcll(mn) + (__popcll(mf) << 16);
                     }
                 }
             }
+        }
+        for (int u = 0; u < nic; ++u) {
+            const int i = i0 + ib + u, c2 = bcast_i(cnt, u);
+            flush_far(row_rsrc(nl + (size_t)i * kListCap, kListCap * 4), far_lds + u * kListCap, c2 & 0xffff,
+                      c2 >> 16);
         }
         if (lane < nic) ncnt[i0 + ib + lane] = cnt;
     }
@@ -554,12 +581,12 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
                                       MT ? (int)ld(typ, j) : 0, near);
                              });
     } else {
-        const int cnt = list_total(packed), nnear = list_near(packed);
+        const int cnt = list_total(packed);
         // the next entry is loaded one iteration ahead, so a neighbour costs one
         // memory round trip (its record) instead of two
-        uint32_t e = sub < cnt ? lst[list_pos(sub, nnear)] : 0u;
+        uint32_t e = sub < cnt ? lst[sub] : 0u;
         for (int k = sub; k < cnt; k += P) {
-            const uint32_t en = k + P < cnt ? lst[list_pos(k + P, nnear)] : 0u;
+            const uint32_t en = k + P < cnt ? lst[k + P] : 0u;
             const int j = (int)(e & kSlotMask);
             // the neighbour's packed record: four 16-byte loads of one sector
             const double2 *q = (const double2 *)(rec + j);

@@ -110,13 +110,11 @@ __device__ __forceinline__ int lanes_below(unsigned long long m, int base = 0)
 }
 
 // List row layout: the kListCap entries of particle i hold its neighbours
-// with r < r_d from the front (positions 0, 1, ...) and the others from the
-// back (positions kListCap-1, kListCap-2, ...); the count word packs the two
-// counts (near in bits 0..15, far in bits 16..31).  Entry k of the row in
-// visiting order (near first, then far) sits at list_pos(k).
+// with r < r_d first and then the others, with no gap; the count word packs
+// the two counts (near in bits 0..15, far in bits 16..31).  A row whose counts
+// add up to more than kListCap is not valid.
 __device__ __forceinline__ int list_near(int packed) { return packed & 0xffff; }
 __device__ __forceinline__ int list_total(int packed) { return (packed & 0xffff) + (packed >> 16); }
-__device__ __forceinline__ int list_pos(int k, int nnear) { return k < nnear ? k : kListCap - 1 - (k - nnear); }
 
 // Visits every neighbour j (r_ij < r_c, j != i) of slot i: from the list when
 // it did not overflow, else by a direct cell scan with the same exact test.
@@ -128,10 +126,10 @@ __device__ __forceinline__ void for_each_neighbor(const PairConst &pc, const Geo
                                                   const int *__restrict__ cstart, int packed,
                                                   const uint32_t *__restrict__ lst, Fn &&fn)
 {
-    const int cnt = list_total(packed), nnear = list_near(packed);
+    const int cnt = list_total(packed);
     if (cnt <= kListCap) {
         for (int k = sub; k < cnt; k += P) {
-            const uint32_t e = lst[list_pos(k, nnear)];
+            const uint32_t e = lst[k];
             const int j = (int)(e & kSlotMask);
             double dx = xi - ld(xs.x, j), dy = yi - ld(xs.y, j), dz = zi - ld(xs.z, j);
             if (e & kWrapBit) {
