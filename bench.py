@@ -47,12 +47,12 @@ OPS_VV_PARTICLE = 20
 # type (53 read + 53 write): 263 B (FP32 form; +8 for FP64 rho).
 BYTES_STEP_FP32 = 263
 BYTES_STEP_FP64 = 271
-# HBM traffic of one launch of the force kernel (FP32 form, 8 lanes per
+# HBM traffic of one launch of the force kernel (FP32 form, 4 lanes per
 # particle) on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by
 # a plain 256 MiB copy (x2.000 reads, x1.000 writes): the summary and the
 # commands are in profiles/mdpd_step_bulk56_n1053696.md.  Valid for the
 # kernel as profiled; it must be re-measured when the kernel changes.
-FORCE_TRAFFIC_BYTES = {"read": 532425532, "write": 102325322}
+FORCE_TRAFFIC_BYTES = {"read": 402805238, "write": 101515486}
 
 
 def parse():

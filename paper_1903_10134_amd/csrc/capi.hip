@@ -80,7 +80,7 @@ struct mdpd_system {
     int n = 0;
     bool fp32 = false;
     bool walls = false;
-    int lanes[3] = {4, 4, 4};  // neighbour list (unused), density (and phi), force
+    int lanes[3] = {4, 4, 4};  // neighbour list (unused), density (and phi), force: best at 1M particles
     // replicas (a single system is one replica)
     int nrep = 1;
     bool mt = false;  // some replica has more than one type
@@ -473,7 +473,6 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     s->n = (int)n;
     s->nrep = nrep;
     s->fp32 = ps[0].precision == MDPD_FP32_FORCES;
-    s->lanes[2] = s->fp32 ? 8 : 4;  // measured best force split at 1M particles
     s->walls = ps[0].wall_model == MDPD_WALL_BVF;
     s->params.assign(ps, ps + nrep);
     s->geoms.resize(nrep);
