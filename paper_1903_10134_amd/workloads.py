@@ -22,6 +22,11 @@ Workloads (all in DPD units, r_c = 1):
                 not available.
 * ``replicas``  independent periodic boxes with edges uniform in [8, 12],
                 A ~ U[-50, -30], B ~ U[20, 30], one random stream per replica.
+* ``slit_pore`` the static contact-angle set-up of Sec. 4.2: a 60 x 10 x 5
+                box, 3,500 frozen particles in two wall layers of thickness
+                r_c (y in [0, 1) and [9, 10), uniform random), 4,000 fluid
+                particles uniform in x in [17, 43), y in [1, 9); two types
+                (fluid 0, solid 1) with A_SS = A_LL = -40 and a chosen A_SL.
 """
 from __future__ import annotations
 
@@ -203,3 +208,27 @@ def lattice_fcc(m=4, a=1.0):
     cells = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
     x = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3) + 0.25 * a
     return x, m * a
+
+
+def slit_pore(A_SL=-35.0, seed=0, n_solid=3500, n_fluid=4000, B=25.0, gamma=4.5, kT=1.0, dt=0.01):
+    """Sec. 4.2 slit nano channel: the paper's domain x in [-30, 30],
+    y in [-5, 5], z in [-2.5, 2.5] shifted to [0, 60) x [0, 10) x [0, 5).
+    Solid particles fill y in [0, 1) and [9, 10) (half each; the two layers
+    meet across the periodic y boundary), fluid starts in x in [17, 43),
+    y in [1, 9).  Types: fluid 0, solid 1; A_SS = A_LL = -40, A_SL varies,
+    B = 25 for every pair, r_d = 0.75.  Walls use the boundary-volume-
+    fraction model."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    box = (60.0, 10.0, 5.0)
+    h = n_solid // 2
+    lo = rng.random((h, 3)) * np.array([60.0, 1.0, 5.0])
+    hi = rng.random((n_solid - h, 3)) * np.array([60.0, 1.0, 5.0]) + np.array([0.0, 9.0, 0.0])
+    xf = rng.random((n_fluid, 3)) * np.array([26.0, 8.0, 5.0]) + np.array([17.0, 1.0, 0.0])
+    x = np.concatenate([xf, lo, hi])
+    frozen = np.concatenate([np.zeros(n_fluid, np.uint8), np.ones(n_solid, np.uint8)])
+    types = frozen.astype(np.int32)
+    v = _maxwell(rng, x.shape[0], kT, 1.0, frozen)
+    A = np.array([[-40.0, A_SL], [A_SL, -40.0]])
+    return Workload(name=f"slit_pore_ASL{A_SL:g}", box=box, x=x, v=v, types=types, frozen=frozen, A=A,
+                    B=_table(B, 2), gamma=_table(gamma, 2), kT=kT, dt=dt, seed=seed, wall_model=1,
+                    info=dict(n_fluid=n_fluid, n_wall=n_solid, pore_y=(1.0, 9.0)))
