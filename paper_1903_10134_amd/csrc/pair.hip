@@ -528,6 +528,10 @@ struct ForceOut {
 // list; SCAN = true: from a direct scan of the cells (lists that overflowed).
 // Both are separate instantiations so the list kernel keeps the small
 // register footprint of the list loop.
+// LDS bytes per quad for the regrouping of four 64-byte records (padded
+// against bank conflicts)
+constexpr int kQuadXch = 4 * 64 + 16;
+
 template <int P, bool MT, bool SCAN, typename R>
 __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &g, int i, int sub, Soa3c xs,
                                                Soa3c vh, const R *__restrict__ rho,
@@ -580,6 +584,48 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
                                  pair(dx, dy, dz, ld(vh.x, j), ld(vh.y, j), ld(vh.z, j), ld(rho, j), ld(tag, j),
                                       MT ? (int)ld(typ, j) : 0, near);
                              });
+    } else if constexpr (P >= 4) {
+        // Each quad of lanes loads its four neighbours' records together: lane
+        // q of the quad fetches bytes [16 q, 16 q + 16) of all four, so a load
+        // instruction touches one 64-byte sector per quad instead of one per
+        // lane, and the pieces are regrouped through the quad's LDS slice.  A
+        // quad lies inside one particle's lane group, so its lanes run the
+        // same number of iterations.
+        __shared__ __align__(16) unsigned char xch[(kBlock / 4) * kQuadXch];
+        unsigned char *const qb = xch + (threadIdx.x >> 2) * kQuadXch;
+        const int q = threadIdx.x & 3;
+        const int cnt = list_total(packed);
+        for (int k0 = 0; k0 < cnt; k0 += P) {
+            const int k = k0 + sub;
+            const uint32_t e = k < cnt ? lst[k] : 0u;  // slot 0 stands in for a missing entry
+            const int j = (int)(e & kSlotMask);
+            const int jq[4] = {__builtin_amdgcn_mov_dpp(j, 0x00, 0xF, 0xF, false),
+                               __builtin_amdgcn_mov_dpp(j, 0x55, 0xF, 0xF, false),
+                               __builtin_amdgcn_mov_dpp(j, 0xAA, 0xF, 0xF, false),
+                               __builtin_amdgcn_mov_dpp(j, 0xFF, 0xF, 0xF, false)};
+            uint4 piece[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) piece[t] = *((const uint4 *)(rec + jq[t]) + q);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) *(uint4 *)(qb + t * 64 + q * 16) = piece[t];
+            const uint4 *mine = (const uint4 *)(qb + q * 64);
+            const uint4 p0 = mine[0], p1 = mine[1], p2 = mine[2], p3 = mine[3];
+            if (k < cnt) {
+                const double2 a = __builtin_bit_cast(double2, p0);  // x, y
+                const double2 b = __builtin_bit_cast(double2, p1);  // z, v_x
+                const double2 c = __builtin_bit_cast(double2, p2);  // v_y, v_z
+                const R rj = (R)__longlong_as_double((long long)(((unsigned long long)p3.y << 32) | p3.x));
+                const uint32_t tgj = p3.z;
+                const int tj = MT ? (int)p3.w : 0;
+                double dx = xi - a.x, dy = yi - a.y, dz = zi - b.x;
+                if (e & kWrapBit) {  // pairs through a periodic image (border cells only)
+                    dx = min_image(dx, pc.L[0], pc.invL[0]);
+                    dy = min_image(dy, pc.L[1], pc.invL[1]);
+                    dz = min_image(dz, pc.L[2], pc.invL[2]);
+                }
+                pair(dx, dy, dz, b.y, c.x, c.y, rj, tgj, tj, (e & kNearBit) != 0);
+            }
+        }
     } else {
         const int cnt = list_total(packed);
         // the next entry is loaded one iteration ahead, so a neighbour costs one
