@@ -1163,12 +1163,17 @@ namespace {
 // One tape entry: the state of step n in its sorted order, as the backward
 // step needs it (x_n, the half-step velocity u_{n-1} its forces used, v_n,
 // rho_n, tags, types, cell offsets).
+// One recomputed state of a segment: positions, velocities, densities, ids,
+// types, cell offsets, and the neighbour list the forward step built for it
+// (the backward step reads the same list instead of building it again).
 struct TapeEntry {
     Soa3 x, u, v;
     void *rho;
     uint32_t *tag;
     uint8_t *typ;
     int *cstart;
+    int *ncnt;
+    uint32_t *nl;
 };
 
 uint64_t tape_entry_bytes(mdpd_system *s)
@@ -1176,7 +1181,7 @@ uint64_t tape_entry_bytes(mdpd_system *s)
     const uint64_t N = (uint64_t)(s->n > 0 ? s->n : 1);
     const uint64_t rb = s->fp32 ? 4 : 8;
     return 3 * align_up(24 * N) + align_up(rb * N) + align_up(4 * N) + align_up(N) +
-           align_up(4 * ((uint64_t)s->R.ncells + 1));
+           align_up(4 * ((uint64_t)s->R.ncells + 1)) + align_up(4 * N) + align_up(4 * N * kListCap);
 }
 
 TapeEntry tape_entry(mdpd_system *s, int k)
@@ -1198,7 +1203,30 @@ TapeEntry tape_entry(mdpd_system *s, int k)
     e.typ = (uint8_t *)b;
     b += align_up(N);
     e.cstart = (int *)b;
+    b += align_up(4 * ((uint64_t)s->R.ncells + 1));
+    e.ncnt = (int *)b;
+    b += align_up(4 * N);
+    e.nl = (uint32_t *)b;
     return e;
+}
+
+// Restores the system's list buffers when it goes out of scope.
+struct ListRedirect {
+    mdpd_system *s;
+    int *ncnt;
+    uint32_t *nl;
+    ~ListRedirect()
+    {
+        s->ncnt = ncnt;
+        s->nl = nl;
+    }
+};
+
+// Builds the neighbour list of tape entry k from its positions.
+void tape_list(mdpd_system *s, int k)
+{
+    const TapeEntry e = tape_entry(s, k);
+    launch_nlist(s->st, s->fp32, s->R, cview(e.x), e.cstart, e.ncnt, e.nl, s->nlr2, nullptr);
 }
 
 // Copy the current state into tape entry k; u is the half-step velocity the
@@ -1274,12 +1302,11 @@ void adjoint_step(mdpd_system *s, int k, int64_t n, const AdjConst *act)
     AdjRec &a = s->adj;
     const TapeEntry e = tape_entry(s, k);
     launch_adj_seed(s->st, s->R, act, cview(e.v), e.tag, a.U, a.fb, a.rhoA);
-    launch_nlist(s->st, s->fp32, s->R, cview(e.x), e.cstart, s->ncnt, s->nl, s->nlr2, nullptr);
     s->tic(5);
     launch_adj_force(s->st, s->lanes[2], s->fp32, s->mt, s->n, a.tmax, s->R, (uint32_t)n, act, cview(e.x),
-                     cview(e.u), e.rho, e.tag, e.typ, e.cstart, s->ncnt, s->nl, cview(a.fb), a.X, a.U, a.rhoA,
+                     cview(e.u), e.rho, e.tag, e.typ, e.cstart, e.ncnt, e.nl, cview(a.fb), a.X, a.U, a.rhoA,
                      a.gp);
-    launch_adj_density(s->st, s->lanes[1], s->R, cview(e.x), e.cstart, s->ncnt, s->nl, a.rhoA, a.X);
+    launch_adj_density(s->st, s->lanes[1], s->R, cview(e.x), e.cstart, e.ncnt, e.nl, a.rhoA, a.X);
     s->toc(5);
     launch_adj_params(s->st, s->R, s->n, a.tmax, e.typ, a.gp, a.gpart, a.gtot);
 }
@@ -1427,9 +1454,18 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
         const int64_t s0 = ckpt_step(a, k - 1), s1 = ckpt_step(a, k);
         HIPCHK(ckpt_restore(s, k - 1, s0));
         HIPCHK(tape_record(s, 0, s0 == 0));
-        for (int m = 1; m <= (int)(s1 - s0); ++m) {
-            s->advance(1);
-            HIPCHK(tape_record(s, m, false));
+        tape_list(s, 0);
+        {
+            // each recomputed step builds its list straight into its tape
+            // entry; the system's own list buffers are back at scope exit
+            const ListRedirect keep{s, s->ncnt, s->nl};
+            for (int m = 1; m <= (int)(s1 - s0); ++m) {
+                const TapeEntry e = tape_entry(s, m);
+                s->ncnt = e.ncnt;
+                s->nl = e.nl;
+                s->advance(1);
+                HIPCHK(tape_record(s, m, false));
+            }
         }
         for (int m = (int)(s1 - s0); m >= 1; --m) {
             const AdjConst *act = table(s0 + m);
@@ -1442,6 +1478,7 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
     if (K == 0) {
         HIPCHK(ckpt_restore(s, 0, 0));
         HIPCHK(tape_record(s, 0, true));
+        tape_list(s, 0);
     }
     // the evaluation at creation, then export in input order
     adjoint_step(s, 0, 0, a.act + 3 * nrep);
