@@ -41,6 +41,10 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 OPS_FORCE_PAIR = 114
 OPS_DENSITY_PAIR = 14
 OPS_VV_PARTICLE = 20
+# Algorithmic VALU operations of the cell-list neighbour search per candidate
+# pair (every particle of the 27-cell stencil): three differences, three
+# squares, two sums and the r_c / r_d comparisons of the exact FP64 test.
+OPS_LIST_CANDIDATE = 10
 # Algorithmic HBM bytes per particle-step of the whole step (every array
 # touched once): read x 24, v_half 24, tag 4, type 1; write x' 24, v 24,
 # v_half' 24, rho 4 (write) + 4 (read), plus the reorder of x, v_half, tag,
@@ -53,6 +57,24 @@ BYTES_STEP_FP64 = 271
 # commands are in profiles/mdpd_step_bulk56_n1053696.md.  Valid for the
 # kernel as profiled; it must be re-measured when the kernel changes.
 FORCE_TRAFFIC_BYTES = {"read": 414343861, "write": 101509360}
+# The same for one launch of the neighbour-list kernel.
+NLIST_TRAFFIC_BYTES = {"read": 80359221, "write": 183313494}
+
+
+def list_candidates(x, box, rc=1.0):
+    """Number of (i, j != i) candidate pairs the cell-list search tests: every
+    particle of the 27 cells around (and including) i's cell, cells of edge
+    L / floor(L / r_c) per axis, periodic."""
+    nc = [int(np.floor(L / rc)) for L in box]
+    c = [np.minimum((x[:, a] * nc[a] / box[a]).astype(np.int64), nc[a] - 1) for a in range(3)]
+    cnt = np.zeros(nc, np.int64)
+    np.add.at(cnt, (c[0], c[1], c[2]), 1)
+    stencil = np.zeros_like(cnt)
+    for dx in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                stencil += np.roll(cnt, (dx, dy, dz), axis=(0, 1, 2))
+    return int((cnt * stencil).sum()) - x.shape[0]
 
 
 def parse():
@@ -107,9 +129,10 @@ def run_form(mdpd, w, precision, steps, warmup, stream, lanes):
     obs = s.observables()
     cnt_c, _ = s.neighbors(w.rc)
     cnt_d, _ = s.neighbors(w.rd)
+    x, _, _ = s.state()
     s.close()
     return dict(sec=t1 - t0, ktime=ktime, obs=obs, pairs_c=int(cnt_c.sum()) // 2,
-                pairs_d=int(cnt_d.sum()) // 2)
+                pairs_d=int(cnt_d.sum()) // 2, candidates=list_candidates(np.asarray(x), w.box, w.rc))
 
 
 def run_batch(mdpd, W, nrep, steps, every):
@@ -242,10 +265,23 @@ def main():
     head = res["fp32_forces"]
     n = w.n
     value = n * a.steps / head["sec"]
-    fms, fcnt = head["ktime"]["force"]
-    favg = fms / max(fcnt, 1) * 1e-3
-    ops_force = head["pairs_c"] * OPS_FORCE_PAIR + n * OPS_VV_PARTICLE
-    achieved = ops_force / favg / 1e12
+    full = n == 1053696 and not lanes  # the profiled configuration
+
+    def kernel_roofline(kind, name, ops, traffic):
+        ms, cnt = head["ktime"][kind]
+        avg = ms / max(cnt, 1) * 1e-3
+        achieved = ops / avg / 1e12
+        return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": PEAK_VALU_TOPS,
+                "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_VALU_TOPS,
+                "traffic": traffic["read"] + traffic["write"] if full else None,
+                "traffic_read_write": traffic if full else None, "avg_launch_us": avg * 1e6,
+                "ops_per_launch": ops}
+
+    rl = {"nlist": kernel_roofline("nlist", "k_nlist_cell (FP32 form)", head["candidates"] * OPS_LIST_CANDIDATE,
+                                   NLIST_TRAFFIC_BYTES),
+          "force": kernel_roofline("force", "k_force (FP32 form)",
+                                   head["pairs_c"] * OPS_FORCE_PAIR + n * OPS_VV_PARTICLE, FORCE_TRAFFIC_BYTES)}
+    dominant = max(rl, key=lambda k: rl[k]["avg_launch_us"])
     out = {
         "metric": "mDPD particle-steps/s at 1M particles, FP32 vs FP64 form; adjoint/forward ratio",
         "value": value,
@@ -263,12 +299,8 @@ def main():
                    "n": n, "box": a.L, "A": -40.0, "B": 25.0, "rc": 1.0, "rd": 0.75, "gamma": 4.5,
                    "kT": 1.0, "dt": 0.01, "form": "FP32 pair forces + FP64 integration"},
         "forms": {},
-        "roofline": {"bound": "alu", "kernel": "k_force (FP32 form)", "achieved": achieved,
-                     "peak": PEAK_VALU_TOPS, "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_VALU_TOPS,
-                     "traffic": (FORCE_TRAFFIC_BYTES["read"] + FORCE_TRAFFIC_BYTES["write"]
-                                 if n == 1053696 and not lanes else None),
-                     "traffic_read_write": FORCE_TRAFFIC_BYTES if n == 1053696 and not lanes else None,
-                     "avg_launch_us": favg * 1e6, "ops_per_launch": ops_force},
+        "roofline": rl[dominant],
+        "roofline_kernels": rl,
     }
     for name, r in res.items():
         bpp = BYTES_STEP_FP32 if name == "fp32_forces" else BYTES_STEP_FP64
