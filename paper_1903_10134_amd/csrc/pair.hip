@@ -113,7 +113,7 @@ constexpr int kGenBatch = 8;
 constexpr int kFarLds = (kGenBatch + 1) * kListCap;
 
 template <typename R2>
-__global__ __launch_bounds__(kBlock) void k_nlist_cell(Reps R, Soa3c xs, const int *__restrict__ cstart_all,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_nlist_cell(Reps R, Soa3c xs, const int *__restrict__ cstart_all,
                                                        int *__restrict__ ncnt, uint32_t *__restrict__ nl,
                                                        R2 *__restrict__ nlr2, const int *__restrict__ gate)
 {
@@ -323,7 +323,7 @@ __device__ __forceinline__ float w_rho<float>(const PairConst &pc, float r2)
 }
 
 template <int P, typename R>
-__global__ __launch_bounds__(kBlock) void k_density(Reps Rp, Soa3c xs, Soa3c vh, const uint32_t *__restrict__ tag,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_density(Reps Rp, Soa3c xs, Soa3c vh, const uint32_t *__restrict__ tag,
                                                     const uint8_t *__restrict__ typ,
                                                     const int *__restrict__ cstart_all,
                                                     const int *__restrict__ ncnt,

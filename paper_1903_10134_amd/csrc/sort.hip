@@ -6,7 +6,8 @@
 //                  (integer atomics: the counts are exact, the slots are not
 //                  ordered)
 //   k_scan_*       exclusive scan of the cell counts -> cell_start[ncells + 1]
-//                  (the counts are cleared as they are read)
+//                  in two passes: tiles, then tile offsets (the counts are
+//                  cleared as they are read)
 //   k_scatter_id   writes each particle's id at its arrival slot
 //   k_rank_gather  rank of the particle inside its cell = number of particles
 //                  of that cell with a smaller id; moves every array to
@@ -133,39 +134,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_local(int m, int *__restr
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-// Exclusive scan of the block totals (at most kScanTile of them) in place;
-// out[m] receives the grand total.
-__global__ __launch_bounds__(kScanThreads) void k_scan_top(int nb, int m, int *__restrict__ bsum,
+// Adds to tile b of out the sum of the totals of tiles 0 .. b-1 (the first
+// wavefront sums them; integer sums do not depend on the order); the last
+// tile also writes the grand total to out[m].
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int m, int nb, const int *__restrict__ bsum,
                                                            int *__restrict__ out,
                                                            const int *__restrict__ gate)
 {
     if (gate && *gate == 0) return;
-    __shared__ int sh[kScanThreads / 64];
-    const int base = threadIdx.x * kScanPer;
-    int v[kScanPer];
-    int s = 0;
+    __shared__ int sh;
+    if (threadIdx.x < 64) {
+        int v = 0;
+        for (int k = (int)threadIdx.x; k < (int)blockIdx.x; k += 64) v += bsum[k];
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-        v[k] = base + k < nb ? bsum[base + k] : 0;
-        s += v[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (threadIdx.x == 0) {
+            sh = v;
+            if ((int)blockIdx.x == nb - 1) out[m] = v + bsum[nb - 1];
+        }
     }
-    int total;
-    const int incl = block_inclusive_scan(s, sh, &total);
-    int run = incl - s;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-        if (base + k < nb) bsum[base + k] = run;
-        run += v[k];
-    }
-    if (threadIdx.x == 0) out[m] = total;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(int m, const int *__restrict__ bsum,
-                                                           int *__restrict__ out,
-                                                           const int *__restrict__ gate)
-{
-    if (gate && *gate == 0) return;
-    const int add = bsum[blockIdx.x];
+    __syncthreads();
+    const int add = sh;
     const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k)
@@ -297,8 +286,7 @@ void launch_sort(hipStream_t st, int n, const Reps &R, Soa3c xin, Soa3c vin, Soa
     const int nb = (m + kScanTile - 1) / kScanTile;
     if (n > 0) k_bin<<<R.nblk[0], kBlock, 0, st>>>(R, xin, key, slot, counts, gate, ovf_count, step_ctr);
     k_scan_local<<<nb, kScanThreads, 0, st>>>(m, counts, cstart, bsum, gate);
-    k_scan_top<<<1, kScanThreads, 0, st>>>(nb, m, bsum, cstart, gate);
-    k_scan_add<<<nb, kScanThreads, 0, st>>>(m, bsum, cstart, gate);
+    k_scan_add<<<nb, kScanThreads, 0, st>>>(m, nb, bsum, cstart, gate);
     if (n > 0) {
         k_scatter_id<<<blocks_for(n), kBlock, 0, st>>>(n, key, slot, cstart, tag_in, tmpid, gate);
         k_rank_gather<<<blocks_for(n), kBlock, 0, st>>>(n, key, cstart, tmpid, xin, vin, xprev_in,
