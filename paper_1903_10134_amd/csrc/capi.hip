@@ -371,6 +371,7 @@ mdpd_status make_geom(const mdpd_params *p, Geom *g)
         g->s[a] = nc / L;
         g->cs[a] = L / nc;
         g->inv_nc[a] = 1.0 / nc;
+        g->invL[a] = 1.0 / L;
         total *= nc;
     }
     if (total > (long long)4096 * 4096) return fail(MDPD_E_UNSUPPORTED, "more than 2^24 cells");
@@ -502,11 +503,23 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
         }
     }
 
+    // border cells (a periodic image in their 27-cell stencil), replica after
+    // replica in cell order: the list kernel handles them in a launch of their own
+    std::vector<int> bcells;
+    for (int r = 0; r < nrep; ++r) {
+        const int *nc = s->geoms[r].nc;
+        for (int cz = 0; cz < nc[2]; ++cz)
+            for (int cy = 0; cy < nc[1]; ++cy)
+                for (int cx = 0; cx < nc[0]; ++cx)
+                    if (cx == 0 || cx == nc[0] - 1 || cy == 0 || cy == nc[1] - 1 || cz == 0 || cz == nc[2] - 1)
+                        bcells.push_back(s->cell_off[r] + cx + nc[0] * (cy + nc[1] * cz));
+    }
     const size_t N = (size_t)(n > 0 ? n : 1);
     const int nb_scan = (int)((cells + 4095) / 4096);
     Reps &R = s->R;
     R.nrep = nrep;
     R.ncells = (int)cells;
+    R.nbcells = (int)bcells.size();
     for (int li = 0; li < kLaneCounts; ++li) R.nblk[li] = s->blk_off[(size_t)li * (nrep + 1) + nrep];
 #define ALLOC(call)                 \
     do {                            \
@@ -562,7 +575,8 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     ALLOC(s->alloc(&s->work, 9 * 4096));
     Geom *dgeom = nullptr;
     PairConst *dpc = nullptr;
-    int *dcell = nullptr, *dpart = nullptr, *dblk = nullptr;
+    int *dcell = nullptr, *dpart = nullptr, *dblk = nullptr, *dbcells = nullptr;
+    ALLOC(s->alloc(&dbcells, bcells.size() + 1));
     ALLOC(s->alloc(&dgeom, (size_t)nrep));
     ALLOC(s->alloc(&dpc, (size_t)nrep));
     ALLOC(s->alloc(&dcell, (size_t)nrep + 1));
@@ -574,6 +588,7 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     R.cell_off = dcell;
     R.part_off = dpart;
     R.blk_off = dblk;
+    R.bcells = dbcells;
 
     auto bail = [&](mdpd_status st) {
         delete s;
@@ -600,6 +615,8 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
         if (e == hipSuccess)
             e = hipMemcpyAsync(dblk, s->blk_off.data(), s->blk_off.size() * sizeof(int), hipMemcpyHostToDevice,
                                s->st);
+        if (e == hipSuccess && !bcells.empty())
+            e = hipMemcpyAsync(dbcells, bcells.data(), bcells.size() * sizeof(int), hipMemcpyHostToDevice, s->st);
         if (e == hipSuccess) e = hipStreamSynchronize(s->st);
         if (e != hipSuccess) return bail(fail(MDPD_E_HIP, "upload of replica tables failed: %s", hipGetErrorString(e)));
     }

@@ -53,6 +53,7 @@ struct Geom {
     double s[3];   // cells per unit length, nc / L
     double cs[3];  // cell edge, L / nc
     double inv_nc[3];  // 1 / nc: splits a cell index into its coordinates
+    double invL[3];    // 1 / L
     int nc[3];
     int ncells;
     double rc, rc2, rd2;
@@ -90,8 +91,10 @@ struct Reps {
     const int *cell_off;    // [nrep + 1]
     const int *part_off;    // [nrep + 1]
     const int *blk_off;     // [kLaneCounts][nrep + 1]
+    const int *bcells;      // [nbcells] global indices of the border cells (a periodic image in the stencil)
     int nrep;
     int ncells;             // total cells
+    int nbcells;
     int nblk[kLaneCounts];  // total blocks per lane count
 };
 

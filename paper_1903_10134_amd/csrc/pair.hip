@@ -112,18 +112,17 @@ __device__ __forceinline__ void flush_far(__amdgpu_buffer_rsrc_t ro, const uint3
 constexpr int kGenBatch = 8;
 constexpr int kFarLds = (kGenBatch + 1) * kListCap;
 
-template <typename R2>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_nlist_cell(Reps R, Soa3c xs, const int *__restrict__ cstart_all,
-                                                       int *__restrict__ ncnt, uint32_t *__restrict__ nl,
-                                                       R2 *__restrict__ nlr2, const int *__restrict__ gate)
+// The list of global cell cg, built by one wavefront.  far_lds: the
+// wavefront's kFarLds words of LDS.  The interior instantiation
+// (BORDER = false) returns at once for a border cell; the border one is only
+// given border cells.
+template <typename R2, bool BORDER>
+__device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, const int *__restrict__ cstart_all,
+                                           int *__restrict__ ncnt, uint32_t *__restrict__ nl,
+                                           R2 *__restrict__ nlr2, uint32_t *far_lds)
 {
-    if (gate && *gate == 0) return;
-    __shared__ uint32_t lds[kWavesPerBlock * kFarLds];
     const int lane = threadIdx.x & 63;
-    uint32_t *const far_lds = lds + (threadIdx.x >> 6) * kFarLds;
     uint32_t *const dump = far_lds + kGenBatch * kListCap;
-    const int cg = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
-    if (cg >= R.ncells) return;
     // the replica of this cell: its lattice, and its cell offsets (global slots)
     const int rep = __builtin_amdgcn_readfirstlane(find_rep(R.cell_off, R.nrep, cg));
     const Geom g = cload(R.geom, rep);
@@ -139,9 +138,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     const int cx = c - cyz * nx, cy = cyz - cz * ny;
     const double rc2 = g.rc2, rd2 = g.rd2;
 
-    bool fast = cx > 0 && cx < nx - 1 && cy > 0 && cy < ny - 1 && cz > 0 && cz < nz - 1;
-    int rb[9], rl[9], qz[3];
-    if (fast) {
+    const bool interior = cx > 0 && cx < nx - 1 && cy > 0 && cy < ny - 1 && cz > 0 && cz < nz - 1;
+    if (!BORDER && !interior) return;
+    // Border cells take the register path too when every axis has at least
+    // five cells: a candidate seen through a boundary then lies more than L/2
+    // away in coordinates, so the minimum image by rounding picks exactly the
+    // pairs through a boundary and gives the same difference as the general
+    // path's explicit shift.
+    bool fast = interior || (nx >= 5 && ny >= 5 && nz >= 5);
+    int qz[3] = {0, 0, 0};
+    int rb[9], rl[9];                 // interior: the 9 rows of 3 cells
+    int pb[18], pl[18];               // border: per dz, per dy, piece A then piece B
+    uint32_t pwrap = 0;               // border: bit k = piece k is seen through a boundary
+    int left = 0;                     // border: candidates of the own row before the own cell
+    if (fast && interior) {
         // row r = (dy + 1) + 3 (dz + 1) spans the cells c + dy nx + dz nx ny - 1 .. + 1
         const int nxy = nx * ny;
 #pragma unroll
@@ -151,11 +161,54 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
             rl[r] = cstart[base + 2] - rb[r];
         }
 #pragma unroll
+        for (int z = 0; z < 3; ++z) qz[z] = rl[3 * z] + rl[3 * z + 1] + rl[3 * z + 2];
+    } else if (fast) {
+        // the rows of a border cell: a row that wraps in x is two pieces
+#pragma unroll
         for (int z = 0; z < 3; ++z) {
-            qz[z] = rl[3 * z] + rl[3 * z + 1] + rl[3 * z + 2];
-            if (qz[z] > 128) fast = false;
+            const int zz = wrap_index(cz + z - 1, nz);
+            const bool wz = cz + z - 1 < 0 || cz + z - 1 >= nz;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int yy = wrap_index(cy + r - 1, ny);
+                const bool wy = cy + r - 1 < 0 || cy + r - 1 >= ny;
+                const int base = nx * (yy + ny * zz);
+                int a0, a1, b0, b1;
+                bool wa = wz || wy, wb = wz || wy;
+                if (cx == 0) {           // cells nx-1 (through the boundary), then 0, 1
+                    a0 = base + nx - 1;
+                    a1 = base + nx;
+                    b0 = base;
+                    b1 = base + 2;
+                    wa = true;
+                } else if (cx == nx - 1) {  // cells nx-2, nx-1, then 0 (through the boundary)
+                    a0 = base + nx - 2;
+                    a1 = base + nx;
+                    b0 = base;
+                    b1 = base + 1;
+                    wb = true;
+                } else {                 // cells cx-1 .. cx+1
+                    a0 = base + cx - 1;
+                    a1 = base + cx + 2;
+                    b0 = b1 = base;
+                }
+                const int k = 6 * z + 2 * r;
+                pb[k] = cstart[a0];
+                pl[k] = cstart[a1] - pb[k];
+                pb[k + 1] = cstart[b0];
+                pl[k + 1] = cstart[b1] - pb[k + 1];
+                pwrap |= (wa ? 1u : 0u) << k;
+                pwrap |= (wb ? 1u : 0u) << (k + 1);
+                qz[z] += pl[k] + pl[k + 1];
+            }
         }
+        // the own row (dz = dy = 0) starts with the cell left of the own cell
+        const int cl = nx * cyz + (cx == 0 ? nx - 1 : cx - 1);
+        left = cstart[cl + 1] - cstart[cl];
     }
+#pragma unroll
+    for (int z = 0; z < 3; ++z)
+        if (qz[z] > 128) fast = false;
     if (fast) {
         double cxj[6], cyj[6], czj[6];
         int cs[6];
@@ -165,21 +218,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
             const int z = s >> 1;
             const int q = (s & 1) * 64 + lane;
             int slot = -1;
+            uint32_t wrap = 0;
             if (q < qz[z]) {
-                const int l0 = rl[3 * z], l1 = rl[3 * z + 1];
-                slot = q < l0 ? rb[3 * z] + q
-                              : (q < l0 + l1 ? rb[3 * z + 1] + (q - l0) : rb[3 * z + 2] + (q - l0 - l1));
+                if (interior) {
+                    const int l0 = rl[3 * z], l1 = rl[3 * z + 1];
+                    slot = q < l0 ? rb[3 * z] + q
+                                  : (q < l0 + l1 ? rb[3 * z + 1] + (q - l0) : rb[3 * z + 2] + (q - l0 - l1));
+                } else {
+                    int off = q;
+#pragma unroll
+                    for (int k = 6 * z; k < 6 * z + 6; ++k) {
+                        if (off >= 0 && off < pl[k]) {
+                            slot = pb[k] + off;
+                            wrap = (pwrap >> k) & 1u ? kWrapBit : 0u;
+                        }
+                        off -= pl[k];
+                    }
+                }
             }
-            cs[s] = slot;
             vm[s] = __builtin_amdgcn_ballot_w64(slot >= 0);
             const int js = slot >= 0 ? slot : i0;
+            cs[s] = slot >= 0 ? (int)((uint32_t)slot | wrap) : -1;
             cxj[s] = ld(xs.x, js);
             cyj[s] = ld(xs.y, js);
             czj[s] = ld(xs.z, js);
         }
-        // the own cell is the middle cell of row 4 (dy = dz = 0): particle i is
-        // candidate selfq0 + i of the dz = 0 batch
-        const int selfq0 = rl[3] - rb[4];
+        // particle i is candidate selfq0 + i of the dz = 0 batch: after the
+        // dy = -1 row and the own row's cells left of the own cell
+        const int selfq0 = interior ? rl[3] - rb[4] : pl[6] + pl[7] + left - i0;
         for (int ib = 0; ib < ni; ib += 64) {
             const int nic = ni - ib < 64 ? ni - ib : 64;
             const int me = i0 + ib + (lane < nic ? lane : 0);
@@ -194,7 +260,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 #pragma unroll
                 for (int s = 0; s < 6; ++s) {
                     if ((s & 1) && qz[s >> 1] <= 64) continue;
-                    const double r2 = exact_r2(xi - cxj[s], yi - cyj[s], zi - czj[s]);
+                    double dx = xi - cxj[s], dy = yi - cyj[s], dz = zi - czj[s];
+                    if (!interior) {
+                        dx = min_image(dx, g.L[0], g.invL[0]);
+                        dy = min_image(dy, g.L[1], g.invL[1]);
+                        dz = min_image(dz, g.L[2], g.invL[2]);
+                    }
+                    const double r2 = exact_r2(dx, dy, dz);
                     unsigned long long hm = __builtin_amdgcn_ballot_w64(r2 < rc2) & vm[s];
                     if ((s >> 1) == 1 && (sq >> 6) == (s & 1)) hm &= ~(1ull << (sq & 63));
                     const unsigned long long nm = __builtin_amdgcn_ballot_w64(r2 < rd2);
@@ -300,6 +372,32 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         }
         if (lane < nic) ncnt[i0 + ib + lane] = cnt;
     }
+}
+
+// Interior cells (and, for the border kernel, border cells) at eight waves
+// per SIMD: the interior path fits in 64 VGPRs.
+template <typename R2>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_nlist_cell(
+    Reps R, Soa3c xs, const int *__restrict__ cstart_all, int *__restrict__ ncnt, uint32_t *__restrict__ nl,
+    R2 *__restrict__ nlr2, const int *__restrict__ gate)
+{
+    if (gate && *gate == 0) return;
+    __shared__ uint32_t lds[kWavesPerBlock * kFarLds];
+    const int cg = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    if (cg >= R.ncells) return;
+    nlist_cell<R2, false>(R, cg, xs, cstart_all, ncnt, nl, nlr2, lds + (threadIdx.x >> 6) * kFarLds);
+}
+
+template <typename R2>
+__global__ __launch_bounds__(kBlock) void k_nlist_border(Reps R, Soa3c xs, const int *__restrict__ cstart_all,
+                                                         int *__restrict__ ncnt, uint32_t *__restrict__ nl,
+                                                         R2 *__restrict__ nlr2, const int *__restrict__ gate)
+{
+    if (gate && *gate == 0) return;
+    __shared__ uint32_t lds[kWavesPerBlock * kFarLds];
+    const int w = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    if (w >= R.nbcells) return;
+    nlist_cell<R2, true>(R, cload(R.bcells, w), xs, cstart_all, ncnt, nl, nlr2, lds + (threadIdx.x >> 6) * kFarLds);
 }
 
 // ---------------------------------------------------------------------------
@@ -888,10 +986,16 @@ void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int 
 {
     if (R.ncells <= 0) return;
     const int blocks = (R.ncells + kWavesPerBlock - 1) / kWavesPerBlock;
-    if (fp32)
+    const int bblocks = (R.nbcells + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (fp32) {
         k_nlist_cell<float><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (float *)nlr2, gate);
-    else
+        if (bblocks > 0)
+            k_nlist_border<float><<<bblocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (float *)nlr2, gate);
+    } else {
         k_nlist_cell<double><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (double *)nlr2, gate);
+        if (bblocks > 0)
+            k_nlist_border<double><<<bblocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (double *)nlr2, gate);
+    }
 }
 
 void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c xs, Soa3c vh, const uint32_t *tag,
