@@ -56,9 +56,10 @@ BYTES_STEP_FP64 = 271
 # a plain 256 MiB copy (x2.000 reads, x1.000 writes): the summary and the
 # commands are in profiles/mdpd_step_bulk56_n1053696.md.  Valid for the
 # kernel as profiled; it must be re-measured when the kernel changes.
-FORCE_TRAFFIC_BYTES = {"read": 414343861, "write": 101509360}
-# The same for one launch of the neighbour-list kernel.
-NLIST_TRAFFIC_BYTES = {"read": 80359221, "write": 183313494}
+FORCE_TRAFFIC_BYTES = {"read": 414629284, "write": 101510242}
+# The same for the two neighbour-list launches of a step (interior and border
+# cells).
+NLIST_TRAFFIC_BYTES = {"read": 86578579, "write": 183474367}
 
 
 def list_candidates(x, box, rc=1.0):
@@ -277,7 +278,8 @@ def main():
                 "traffic_read_write": traffic if full else None, "avg_launch_us": avg * 1e6,
                 "ops_per_launch": ops}
 
-    rl = {"nlist": kernel_roofline("nlist", "k_nlist_cell (FP32 form)", head["candidates"] * OPS_LIST_CANDIDATE,
+    rl = {"nlist": kernel_roofline("nlist", "k_nlist_cell + k_nlist_border (FP32 form)",
+                                   head["candidates"] * OPS_LIST_CANDIDATE,
                                    NLIST_TRAFFIC_BYTES),
           "force": kernel_roofline("force", "k_force (FP32 form)",
                                    head["pairs_c"] * OPS_FORCE_PAIR + n * OPS_VV_PARTICLE, FORCE_TRAFFIC_BYTES)}
