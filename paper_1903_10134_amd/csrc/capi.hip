@@ -504,14 +504,18 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     }
 
     // border cells (a periodic image in their 27-cell stencil), replica after
-    // replica in cell order: the list kernel handles them in a launch of their own
+    // replica in cell order: the list kernel handles them in a launch of their
+    // own.  A small system takes all its cells in that one launch (the second
+    // launch would cost more than it saves).
     std::vector<int> bcells;
+    const bool one_launch = cells <= kOneListLaunchCells;
     for (int r = 0; r < nrep; ++r) {
         const int *nc = s->geoms[r].nc;
         for (int cz = 0; cz < nc[2]; ++cz)
             for (int cy = 0; cy < nc[1]; ++cy)
                 for (int cx = 0; cx < nc[0]; ++cx)
-                    if (cx == 0 || cx == nc[0] - 1 || cy == 0 || cy == nc[1] - 1 || cz == 0 || cz == nc[2] - 1)
+                    if (one_launch || cx == 0 || cx == nc[0] - 1 || cy == 0 || cy == nc[1] - 1 || cz == 0 ||
+                        cz == nc[2] - 1)
                         bcells.push_back(s->cell_off[r] + cx + nc[0] * (cy + nc[1] * cz));
     }
     const size_t N = (size_t)(n > 0 ? n : 1);
@@ -520,6 +524,7 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     R.nrep = nrep;
     R.ncells = (int)cells;
     R.nbcells = (int)bcells.size();
+    R.list_interior = one_launch ? 0 : 1;
     for (int li = 0; li < kLaneCounts; ++li) R.nblk[li] = s->blk_off[(size_t)li * (nrep + 1) + nrep];
 #define ALLOC(call)                 \
     do {                            \

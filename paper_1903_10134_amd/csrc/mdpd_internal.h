@@ -22,6 +22,7 @@
 namespace mdpd {
 
 constexpr int kListCap = 64;   // neighbour-list slots per particle
+constexpr int kOneListLaunchCells = 8192;  // up to this many cells the list is one launch
 static_assert((kListCap & (kListCap - 1)) == 0, "far-buffer positions wrap with a mask");
 constexpr int kBlock = 256;    // threads per block of the particle kernels
 constexpr uint32_t kFrozenBit = 0x80000000u;
@@ -95,6 +96,7 @@ struct Reps {
     int nrep;
     int ncells;             // total cells
     int nbcells;
+    int list_interior;      // 1: interior cells have a list launch of their own; 0: bcells holds every cell
     int nblk[kLaneCounts];  // total blocks per lane count
 };
 

@@ -114,8 +114,8 @@ constexpr int kFarLds = (kGenBatch + 1) * kListCap;
 
 // The list of global cell cg, built by one wavefront.  far_lds: the
 // wavefront's kFarLds words of LDS.  The interior instantiation
-// (BORDER = false) returns at once for a border cell; the border one is only
-// given border cells.
+// (BORDER = false) returns at once for a border cell; the border one is given
+// the border cells (every cell of a small system, interior ones included).
 template <typename R2, bool BORDER>
 __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, const int *__restrict__ cstart_all,
                                            int *__restrict__ ncnt, uint32_t *__restrict__ nl,
@@ -988,11 +988,13 @@ void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int 
     const int blocks = (R.ncells + kWavesPerBlock - 1) / kWavesPerBlock;
     const int bblocks = (R.nbcells + kWavesPerBlock - 1) / kWavesPerBlock;
     if (fp32) {
-        k_nlist_cell<float><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (float *)nlr2, gate);
+        if (R.list_interior)
+            k_nlist_cell<float><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (float *)nlr2, gate);
         if (bblocks > 0)
             k_nlist_border<float><<<bblocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (float *)nlr2, gate);
     } else {
-        k_nlist_cell<double><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (double *)nlr2, gate);
+        if (R.list_interior)
+            k_nlist_cell<double><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (double *)nlr2, gate);
         if (bblocks > 0)
             k_nlist_border<double><<<bblocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (double *)nlr2, gate);
     }
