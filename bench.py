@@ -217,7 +217,8 @@ def run_walled(mdpd, w, steps, warmup):
     return {"particles": w.n, "fluid": nf, "box": list(w.box), "steps": steps,
             "ms_per_step": sec * 1e3 / steps, "particle_steps_per_s": w.n * steps / sec,
             "fluid_particle_steps_per_s": nf * steps / sec, "kT": o["kT"],
-            "mean_vx": o["momentum"][0] / max(nf, 1), "corrections_per_step": o["ncorr_total"] / (steps + warmup)}
+            "mean_v": [m / max(nf, 1) for m in o["momentum"]],
+            "corrections_per_step": o["ncorr_total"] / (steps + warmup)}
 
 
 def cpu_baseline(w, nsteps):
@@ -338,7 +339,10 @@ def main():
         ch["workload"] = "Poiseuille channel 64 x 32 x 64, frozen walls of thickness 2, g_x = 0.02"
         rk = run_walled(mdpd, W.rock(), 50, 5)
         rk["workload"] = "synthetic rock, 128^3 Gaussian-random-field mask, porosity 0.3, g_x = 0.01"
-        out["walled"] = {"channel": ch, "rock": rk}
+        rg = run_walled(mdpd, W.ring_cells(n=16, layers=2), 200, 20)
+        rg["workload"] = ("manufactured homogeneous porous medium (ring cells 16 x 2 x 16, solid density 8, "
+                          "fluid 6.2, g_z = 0.02): 16 x 16 cells, 2 layers")
+        out["walled"] = {"channel": ch, "rock": rk, "ring_cells": rg}
         for k, v in out["walled"].items():
             print(f"# {k}: {v['particles']} particles ({v['fluid']} fluid), {v['ms_per_step']:.3f} ms/step, "
                   f"{v['corrections_per_step']:.1f} corrections/step", file=sys.stderr, flush=True)

@@ -22,6 +22,9 @@ Workloads (all in DPD units, r_c = 1):
                 not available.
 * ``replicas``  independent periodic boxes with edges uniform in [8, 12],
                 A ~ U[-50, -30], B ~ U[20, 30], one random stream per replica.
+* ``ring_cells`` the manufactured homogeneous porous medium of Sec. 5.1 (the
+                paper's scaling benchmark): 16 x 2 x 16 cells with a ring wall,
+                stacked twice along y; 16 x 16 cells hold ~1M particles.
 * ``slit_pore`` the static contact-angle set-up of Sec. 4.2: a 60 x 10 x 5
                 box, 3,500 frozen particles in two wall layers of thickness
                 r_c (y in [0, 1) and [9, 10), uniform random), 4,000 fluid
@@ -232,3 +235,58 @@ def slit_pore(A_SL=-35.0, seed=0, n_solid=3500, n_fluid=4000, B=25.0, gamma=4.5,
     return Workload(name=f"slit_pore_ASL{A_SL:g}", box=box, x=x, v=v, types=types, frozen=frozen, A=A,
                     B=_table(B, 2), gamma=_table(gamma, 2), kT=kT, dt=dt, seed=seed, wall_model=1,
                     info=dict(n_fluid=n_fluid, n_wall=n_solid, pore_y=(1.0, 9.0)))
+
+
+def ring_cells(n=16, layers=2, seed=0, solid_density=8.0, fluid_density=6.2, gz=0.02, B=25.0, gamma=4.5,
+               kT=1.0, dt=0.01):
+    """Sec. 5.1 manufactured homogeneous porous medium: square cells of
+    16 x 2 x 16 (x, y, z), each with a ring-shaped solid wall (outer radius 7,
+    inner radius 6, axis along y) at number density 8 and fluid at density 6.2
+    outside the ring; n x n cells in the x-z plane, the cells of every other
+    row (in z) shifted by half a cell in x; periodic in all directions, body
+    force g_z on the fluid.  The paper's cell is 2 thick in y; ``layers``
+    copies of it are stacked along y (the cell list needs at least three
+    cells of r_c per axis).  Particles are placed uniformly at random in
+    their regions (the paper equilibrates them first).  Types: fluid 0, solid
+    1, A = -40 between all pairs, B = 25, r_d = 0.75."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    C, H = 16.0, 2.0 * layers
+    box = (C * n, H, C * n)
+    r_out, r_in = 7.0, 6.0
+    ring_area = np.pi * (r_out ** 2 - r_in ** 2)
+    fluid_area = C * C - np.pi * r_out ** 2
+    n_solid = int(round(solid_density * ring_area * H))
+    n_fluid = int(round(fluid_density * fluid_area * H))
+
+    def ring(count):
+        # uniform in the annulus: radius from the area-weighted distribution
+        rad = np.sqrt(rng.uniform(r_in ** 2, r_out ** 2, count))
+        ang = rng.uniform(0.0, 2.0 * np.pi, count)
+        return np.stack([C / 2 + rad * np.cos(ang), rng.uniform(0.0, H, count), C / 2 + rad * np.sin(ang)], 1)
+
+    def outside(count):
+        pts = np.empty((0, 3))
+        while pts.shape[0] < count:
+            p = rng.random((2 * count, 3)) * np.array([C, H, C])
+            keep = (p[:, 0] - C / 2) ** 2 + (p[:, 2] - C / 2) ** 2 >= r_out ** 2
+            pts = np.concatenate([pts, p[keep]])
+        return pts[:count]
+
+    xs, xf = [], []
+    for iz in range(n):
+        for ix in range(n):
+            off = np.array([C * ix + (C / 2 if iz % 2 == 1 else 0.0), 0.0, C * iz])
+            xs.append(ring(n_solid) + off)
+            xf.append(outside(n_fluid) + off)
+    xf = np.concatenate(xf)
+    xs = np.concatenate(xs)
+    x = np.concatenate([xf, xs])
+    x[:, 0] %= box[0]
+    frozen = np.concatenate([np.zeros(xf.shape[0], np.uint8), np.ones(xs.shape[0], np.uint8)])
+    types = frozen.astype(np.int32)
+    v = _maxwell(rng, x.shape[0], kT, 1.0, frozen)
+    return Workload(name=f"ring_cells_{n}x{n}", box=box, x=x, v=v, types=types, frozen=frozen,
+                    A=_table(-40.0, 2), B=_table(B, 2), gamma=_table(gamma, 2), kT=kT, dt=dt,
+                    g=(0.0, 0.0, gz), seed=seed, wall_model=1,
+                    info=dict(n_fluid=int(xf.shape[0]), n_wall=int(xs.shape[0]), cells=n * n,
+                              per_cell=(n_solid, n_fluid)))
