@@ -141,11 +141,13 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
     const bool interior = cx > 0 && cx < nx - 1 && cy > 0 && cy < ny - 1 && cz > 0 && cz < nz - 1;
     if (!BORDER && !interior) return;
     // Border cells take the register path too when every axis has at least
-    // five cells: a candidate seen through a boundary then lies more than L/2
-    // away in coordinates, so the minimum image by rounding picks exactly the
-    // pairs through a boundary and gives the same difference as the general
-    // path's explicit shift.
-    bool fast = interior || (nx >= 5 && ny >= 5 && nz >= 5);
+    // four cells: a stencil candidate then differs by less than L/2 in a
+    // coordinate unless it is seen through that boundary, and by more than L/2
+    // if it is, so the minimum image by rounding picks exactly the pairs
+    // through a boundary and gives the same difference as the general path's
+    // explicit shift (a pair whose difference rounds to L/2 itself is more
+    // than r_c apart either way).
+    bool fast = interior || (nx >= 4 && ny >= 4 && nz >= 4);
     int qz[3] = {0, 0, 0};
     int rb[9], rl[9];                 // interior: the 9 rows of 3 cells
     int pb[18], pl[18];               // border: per dz, per dy, piece A then piece B
