@@ -108,7 +108,7 @@ struct mdpd_system {
     uint32_t *dstep = nullptr;  // noise step of the current force evaluation (advanced by the main sort)
     int *ovf = nullptr;        // [0]: overflow count, [1..n]: queued slots
     double *ovf_ve = nullptr;  // per slot: virial, pair energy of overflowed particles
-    int *corr = nullptr;  // [0]: corrections this step, [1..n]: flags
+    int *corr = nullptr;  // [0]: corrections this step, [1..n]: flags, then per-block counts
     uint8_t *wnear = nullptr;  // per cell: a frozen particle within the 27-cell stencil
     unsigned long long *ncorr_total = nullptr;
     double *tab = nullptr;
@@ -568,7 +568,7 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     ALLOC(s->alloc(&s->fpart, 2 * (size_t)(R.nblk[kLaneCounts - 1] + 1)));
     ALLOC(s->alloc(&s->status, 4));
     ALLOC(s->alloc(&s->dstep, 1));
-    ALLOC(s->alloc(&s->corr, N + 1));
+    ALLOC(s->alloc(&s->corr, N + 1 + (N + kBlock - 1) / kBlock));
     ALLOC(s->alloc(&s->ovf, N + 1));
     ALLOC(s->alloc(&s->ovf_ve, 2 * N));
     ALLOC(s->alloc(&s->ncorr_total, 1));

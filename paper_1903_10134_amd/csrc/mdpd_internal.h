@@ -265,6 +265,8 @@ void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c x
 // Walls: the per-cell mask of cells with a frozen particle in reach (once),
 // and phi + corrector for one step (cell scan at the predicted positions).
 void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint32_t *tag, uint8_t *wnear);
+// ncorr: [0] corrections of this step (written), [1..n] per-slot flags,
+// then one count per kBlock slots (scratch); ncorr_total accumulates.
 void launch_phi(hipStream_t st, int lanes, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix,
                 Soa3 vfix, const uint32_t *tag, const int *cstart, const uint8_t *wnear, int *ncorr,
                 unsigned long long *ncorr_total);

@@ -536,11 +536,12 @@ __global__ __launch_bounds__(kBlock) void k_phi(Reps R, Soa3c xs, const uint32_t
     if (sub == 0) flag[i] = (den > 0.0 && num / den > pc.phi_c) ? 1 : 0;
 }
 
-// Applies the corrector to flagged particles: x <- x(t), v_half <- -v_half.
+// Applies the corrector to flagged particles: x <- x(t), v_half <- -v_half;
+// each block writes its number of corrections to part[blockIdx.x].
 __global__ __launch_bounds__(kBlock) void k_correct(int n, const int *__restrict__ flag, Soa3c xprev,
-                                                    Soa3 xs, Soa3 vh, int *__restrict__ ncorr,
-                                                    unsigned long long *__restrict__ ncorr_total)
+                                                    Soa3 xs, Soa3 vh, int *__restrict__ part)
 {
+    __shared__ int cnt[kWavesPerBlock];
     const int i = blockIdx.x * kBlock + threadIdx.x;
     int hit = 0;
     if (i < n && flag[i]) {
@@ -552,10 +553,34 @@ __global__ __launch_bounds__(kBlock) void k_correct(int n, const int *__restrict
         vh.z[i] = -vh.z[i];
         hit = 1;
     }
-    const unsigned long long m = __ballot(hit);
-    if ((threadIdx.x & 63) == 0 && m) {
-        atomicAdd(ncorr, (int)__popcll(m));
-        atomicAdd(ncorr_total, (unsigned long long)__popcll(m));
+    const int w = (int)__popcll(__ballot(hit));
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int k = 0; k < kWavesPerBlock; ++k) t += cnt[k];
+        part[blockIdx.x] = t;
+    }
+}
+
+// The step's number of corrections (the re-sort gate) and the running total,
+// from the block counts of k_correct (one block, no atomics).
+__global__ __launch_bounds__(kBlock) void k_correct_sum(int nb, const int *__restrict__ part,
+                                                        int *__restrict__ ncorr,
+                                                        unsigned long long *__restrict__ ncorr_total)
+{
+    __shared__ int cnt[kWavesPerBlock];
+    int t = 0;
+    for (int k = (int)threadIdx.x; k < nb; k += kBlock) t += part[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int sum = 0;
+        for (int k = 0; k < kWavesPerBlock; ++k) sum += cnt[k];
+        *ncorr = sum;
+        *ncorr_total += (unsigned long long)sum;
     }
 }
 
@@ -1031,11 +1056,14 @@ void launch_phi(hipStream_t st, int lanes, int n, const Reps &R, Soa3c xs, Soa3c
     if (n <= 0) return;
     int *ncorr = flag_and_count;       // [0]: corrections this step
     int *flag = flag_and_count + 1;    // [1..n]: per-slot flags
+    int *part = flag + n;              // [n+1 ..]: corrections per block of k_correct
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
         k_phi<L><<<R.nblk[lanes_index(L)], kBlock, 0, st>>>(R, xs, tag, cstart, wnear, flag);
     });
-    k_correct<<<blocks_for(n), kBlock, 0, st>>>(n, flag, xprev, xfix, vfix, ncorr, ncorr_total);
+    const int nb = blocks_for(n);
+    k_correct<<<nb, kBlock, 0, st>>>(n, flag, xprev, xfix, vfix, part);
+    k_correct_sum<<<1, kBlock, 0, st>>>(nb, part, ncorr, ncorr_total);
 }
 
 void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, const uint32_t *stepp, Soa3c xs,
