@@ -78,7 +78,7 @@ typedef struct {
     double dt;            /* timestep                                             */
     double mass;          /* particle mass (all particles)                        */
     double body_force[3]; /* acceleration g on fluid particles (force m g)        */
-    double phi_c;         /* wall threshold for MDPD_WALL_BVF                     */
+    double phi_c;         /* wall threshold for MDPD_WALL_BVF, >= 0               */
     double A[MDPD_MAX_TYPES * MDPD_MAX_TYPES];     /* A[t_i*ntypes + t_j], symmetric */
     double B[MDPD_MAX_TYPES * MDPD_MAX_TYPES];     /* B >= 0, symmetric             */
     double gamma[MDPD_MAX_TYPES * MDPD_MAX_TYPES]; /* gamma >= 0, symmetric         */

@@ -109,7 +109,8 @@ struct mdpd_system {
     int *ovf = nullptr;        // [0]: overflow count, [1..n]: queued slots
     double *ovf_ve = nullptr;  // per slot: virial, pair energy of overflowed particles
     int *corr = nullptr;  // [0]: corrections this step, [1..n]: flags, then per-block counts
-    uint8_t *wnear = nullptr;  // per cell: a frozen particle within the 27-cell stencil
+    uint8_t *wmask = nullptr;  // per wall sub-cell: a frozen particle within r_c of its box
+    size_t wmask_bytes = 0;
     unsigned long long *ncorr_total = nullptr;
     double *tab = nullptr;
     double *obs = nullptr;       // 16 result slots per replica
@@ -284,7 +285,7 @@ struct mdpd_system {
             // only if a particle was moved back (gated on the device)
             launch_zero_int(st, corr, 1);
             tic(4);
-            launch_phi(st, lanes[1], n, R, cview(xs[cur]), cview(xprev), xs[cur], vh[cur], tag[cur], cstart, wnear,
+            launch_phi(st, lanes[1], n, R, cview(xs[cur]), cview(xprev), xs[cur], vh[cur], tag[cur], cstart, wmask,
                        corr, ncorr_total);
             toc(4);
             const int o = 1 - cur;
@@ -329,6 +330,8 @@ mdpd_status validate(const mdpd_params *p, int64_t n)
         return fail(MDPD_E_INVALID, "need 0 < rd <= rc (rc = %g, rd = %g)", p->rc, p->rd);
     if (!(p->dt > 0.0) || !(p->mass > 0.0) || p->kT < 0.0)
         return fail(MDPD_E_INVALID, "need dt > 0, mass > 0, kT >= 0");
+    if (p->wall_model == MDPD_WALL_BVF && !(p->phi_c >= 0.0))
+        return fail(MDPD_E_INVALID, "need phi_c >= 0 with MDPD_WALL_BVF (phi_c = %g)", p->phi_c);
     if (p->precision != MDPD_FP64 && p->precision != MDPD_FP32_FORCES)
         return fail(MDPD_E_INVALID, "unknown precision %d", p->precision);
     if (p->wall_model != MDPD_WALL_OFF && p->wall_model != MDPD_WALL_BVF)
@@ -545,7 +548,12 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     ALLOC(s->alloc3(&s->v, N));
     ALLOC(s->alloc3(&s->F, N));
     if (s->walls) ALLOC(s->alloc3(&s->xprev, N));
-    if (s->walls) ALLOC(s->alloc(&s->wnear, (size_t)cells));
+    if (s->walls) {
+        // wall mask: 4 sub-cells per cell edge while it stays within 64 MiB
+        R.wsub = cells <= ((int64_t)1 << 20) ? 4 : cells <= ((int64_t)1 << 23) ? 2 : 1;
+        s->wmask_bytes = (size_t)cells * (size_t)(R.wsub * R.wsub * R.wsub);
+        ALLOC(s->alloc(&s->wmask, s->wmask_bytes));
+    }
     {
         double *r = nullptr;
         ALLOC(s->alloc(&r, N));
@@ -674,9 +682,9 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     // t = 0: sort, density, forces with the given velocities and noise step 0
     s->sort_predicted();
     if (s->walls) {
-        hipError_t ez = hipMemsetAsync(s->wnear, 0, (size_t)cells, s->st);
+        hipError_t ez = hipMemsetAsync(s->wmask, 0, s->wmask_bytes, s->st);
         if (ez != hipSuccess) return bail(fail(MDPD_E_HIP, "wall mask: %s", hipGetErrorString(ez)));
-        launch_mark_wall_cells(s->st, R, cview(s->xs[s->cur]), s->tag[s->cur], s->wnear);
+        launch_mark_wall_cells(s->st, R, cview(s->xs[s->cur]), s->tag[s->cur], s->wmask);
     }
     s->evaluate(0, 1);
     e = hipMemcpyAsync(&hstatus, s->status, sizeof(int), hipMemcpyDeviceToHost, s->st);
@@ -997,9 +1005,9 @@ mdpd_status mdpd_load_checkpoint(mdpd_system *s, const void *buf, uint64_t bytes
     s->force_lanes_used = (int)h.force_lanes;
     s->step = h.step;
     HIPCHK(state_copy(s, const_cast<char *>(in) + head_bytes(s), false, dk));
-    if (s->walls) {  // the wall-cell mask follows the frozen particles of the loaded state
-        HIPCHK(hipMemsetAsync(s->wnear, 0, (size_t)s->R.ncells, s->st));
-        launch_mark_wall_cells(s->st, s->R, cview(s->xs[s->cur]), s->tag[s->cur], s->wnear);
+    if (s->walls) {  // the wall mask follows the frozen particles of the loaded state
+        HIPCHK(hipMemsetAsync(s->wmask, 0, s->wmask_bytes, s->st));
+        launch_mark_wall_cells(s->st, s->R, cview(s->xs[s->cur]), s->tag[s->cur], s->wmask);
     }
     // the neighbour list is a function of the positions and the cell list
     launch_nlist(s->st, s->fp32, s->R, cview(s->xs[s->cur]), s->cstart, s->ncnt, s->nl, s->nlr2, nullptr);

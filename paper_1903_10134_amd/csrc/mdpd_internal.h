@@ -97,6 +97,7 @@ struct Reps {
     int ncells;             // total cells
     int nbcells;
     int list_interior;      // 1: interior cells have a list launch of their own; 0: bcells holds every cell
+    int wsub;               // wall mask: sub-cells per cell edge (walls on)
     int nblk[kLaneCounts];  // total blocks per lane count
 };
 
@@ -262,13 +263,13 @@ void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int 
 void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c xs, Soa3c vh,
                     const uint32_t *tag, const uint8_t *typ, const int *cstart, const int *ncnt,
                     const void *nlr2, void *rho, PartRec *rec);
-// Walls: the per-cell mask of cells with a frozen particle in reach (once),
-// and phi + corrector for one step (cell scan at the predicted positions).
-void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint32_t *tag, uint8_t *wnear);
+// Walls: the sub-cell mask of where a frozen particle is in reach (once), and
+// phi + corrector for one step (cell scan at the predicted positions).
+void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint32_t *tag, uint8_t *wmask);
 // ncorr: [0] corrections of this step (written), [1..n] per-slot flags,
 // then one count per kBlock slots (scratch); ncorr_total accumulates.
 void launch_phi(hipStream_t st, int lanes, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix,
-                Soa3 vfix, const uint32_t *tag, const int *cstart, const uint8_t *wnear, int *ncorr,
+                Soa3 vfix, const uint32_t *tag, const int *cstart, const uint8_t *wmask, int *ncorr,
                 unsigned long long *ncorr_total);
 // stepp: device word holding the noise step (advanced by the main sort).
 void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, const uint32_t *stepp,

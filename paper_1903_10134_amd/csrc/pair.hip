@@ -7,8 +7,9 @@
 //   k_density     many-body density rho_i = sum_{j != i, r < r_d} w_rho(r_ij)
 //                 (Sec. 2.1) from the stored r^2 of the flagged entries
 //   k_phi         boundary volume fraction of fluid particles at the predicted
-//                 positions (direct cell scan, only where a frozen particle is
-//                 in reach) and the predictor-corrector flag (Sec. 2.2, 3.2)
+//                 positions (direct cell scan, only where a sub-cell mask puts
+//                 a frozen particle in reach) and the predictor-corrector flag
+//                 (Sec. 2.2, 3.2)
 //   k_force       Eq. 1 conservative force, dissipative and random forces
 //                 (Sec. 2.1), body force, and the velocity-Verlet update fused
 //                 in the epilogue: v(t+dt), the next half-step velocity and the
@@ -473,67 +474,116 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 }
 
 // ---------------------------------------------------------------------------
-// Cells that can hold a fluid particle with a frozen neighbour within r_c:
-// the 27-cell stencil of every frozen particle's cell.  Frozen particles never
-// move, so the mask is built once (a plain store of 1 from every writer).
+// Wall mask: the cell lattice refined R.wsub times per axis; a sub-cell is
+// marked when its box comes closer than r_c (plus a relative margin of 1e-6
+// that covers the rounding of the sub-cell coordinate) to a frozen particle
+// or one of its periodic images.  A fluid particle in an unmarked sub-cell has
+// no frozen neighbour within r_c, so phi = 0 and it is never flagged.  Frozen
+// particles never move, so the mask is built once (a plain store of 1 from
+// every writer).
+__device__ __forceinline__ int wrap_any(int a, int n)
+{
+    const int m = a % n;
+    return m < 0 ? m + n : m;
+}
+
+__device__ __forceinline__ double box_gap(double p, int a, double h)
+{
+    return fmax(0.0, fmax(a * h - p, p - (a + 1) * h));
+}
+
 __global__ __launch_bounds__(kBlock) void k_mark_wall_cells(Reps R, Soa3c xs, const uint32_t *__restrict__ tag,
-                                                            uint8_t *__restrict__ wnear)
+                                                            uint8_t *__restrict__ wmask)
 {
     const BlockRep br = block_rep<1>(R, blockIdx.x);
     const int i = br.i0 + (int)threadIdx.x;
     if (i >= br.i1 || !(tag[i] & kFrozenBit)) return;
     const Geom g = cload(R.geom, br.r);
-    const int coff = cload(R.cell_off, br.r);
-    const int cx = cell_coord(xs.x[i], g.s[0], g.nc[0]);
-    const int cy = cell_coord(xs.y[i], g.s[1], g.nc[1]);
-    const int cz = cell_coord(xs.z[i], g.s[2], g.nc[2]);
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int c = wrap_index(cx + dx, g.nc[0]) +
-                              g.nc[0] * (wrap_index(cy + dy, g.nc[1]) + g.nc[1] * wrap_index(cz + dz, g.nc[2]));
-                wnear[coff + c] = 1;
+    const int k = R.wsub;
+    uint8_t *const m = wmask + (size_t)cload(R.cell_off, br.r) * (size_t)(k * k * k);
+    const double reach = g.rc * (1.0 + 1e-6), reach2 = reach * reach;
+    const double p[3] = {xs.x[i], xs.y[i], xs.z[i]};
+    int lo[3], hi[3], N[3];
+    double h[3];
+    for (int a = 0; a < 3; ++a) {
+        N[a] = g.nc[a] * k;
+        h[a] = g.cs[a] / k;
+        lo[a] = (int)floor((p[a] - reach) / h[a]);
+        hi[a] = (int)floor((p[a] + reach) / h[a]);
+    }
+    for (int az = lo[2]; az <= hi[2]; ++az) {
+        const double ez = box_gap(p[2], az, h[2]);
+        const int wz = wrap_any(az, N[2]);
+        for (int ay = lo[1]; ay <= hi[1]; ++ay) {
+            const double ey = box_gap(p[1], ay, h[1]);
+            const double q = ey * ey + ez * ez;
+            if (!(q < reach2)) continue;
+            const size_t row = (size_t)N[0] * (wrap_any(ay, N[1]) + (size_t)N[1] * wz);
+            for (int ax = lo[0]; ax <= hi[0]; ++ax) {
+                const double ex = box_gap(p[0], ax, h[0]);
+                if (ex * ex + q < reach2) m[row + wrap_any(ax, N[0])] = 1;
             }
+        }
+    }
 }
 
 // phi_i = sum_{frozen j} w_c^2 / sum_j w_c^2 over neighbours within r_c at the
 // predicted positions, by a direct scan of the cells (the exact test of the
-// neighbour list); flag[i] = 1 when phi_i > phi_c.  Fluid particles in cells
-// with no frozen particle in reach have phi = 0 and are not scanned.
+// neighbour list); flag[i] = 1 when phi_i > phi_c.  Frozen particles and
+// fluid particles in unmarked sub-cells have flag 0 and are not scanned.  Each
+// wavefront takes 64 slots, packs the ones to scan in LDS, and runs them in
+// rounds of 64 / P particles with P lanes each, so skipped particles leave no
+// idle lanes.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_phi(Reps R, Soa3c xs, const uint32_t *__restrict__ tag,
                                                 const int *__restrict__ cstart_all,
-                                                const uint8_t *__restrict__ wnear, int *__restrict__ flag)
+                                                const uint8_t *__restrict__ wmask, int *__restrict__ flag)
 {
-    const BlockRep br = block_rep<P>(R, xcd_block());
-    const int i = br.i0 + (int)threadIdx.x / P;
-    const int sub = threadIdx.x & (P - 1);
-    if (i >= br.i1) return;
-    const PairConst pc = cload(R.pc, br.r);
+    __shared__ int pick[kBlock];
+    const BlockRep br = block_rep<1>(R, xcd_block());
+    const int lane = (int)threadIdx.x & 63;
+    int *const wp = pick + ((int)threadIdx.x & ~63);
+    const int i = br.i0 + (int)threadIdx.x;
     const Geom g = cload(R.geom, br.r);
     const int coff = cload(R.cell_off, br.r);
-    const int *__restrict__ cstart = cstart_all + coff;
-    const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
-    const int ci = cell_coord(xi, g.s[0], g.nc[0]) +
-                   g.nc[0] * (cell_coord(yi, g.s[1], g.nc[1]) + g.nc[1] * cell_coord(zi, g.s[2], g.nc[2]));
-    if ((tag[i] & kFrozenBit) || !wnear[coff + ci]) {  // uniform over the P lanes of i
-        if (sub == 0) flag[i] = 0;
-        return;
-    }
-    double num = 0.0, den = 0.0;
-    for_each_row(g, xi, yi, zi, cstart, [&](int b, int e, double sx, double sy, double sz) {
-        for (int j = b + sub; j < e; j += P) {
-            if (j == i) continue;
-            const double r2 = exact_r2((xi - xs.x[j]) + sx, (yi - xs.y[j]) + sy, (zi - xs.z[j]) + sz);
-            if (!(r2 < g.rc2)) continue;
-            const double w = 1.0 - __builtin_sqrt(r2) * pc.inv_rc;
-            den += w * w;
-            if (tag[j] & kFrozenBit) num += w * w;
+    bool scan = false;
+    if (i < br.i1) {
+        if (!(tag[i] & kFrozenBit)) {
+            const int k = R.wsub;
+            const int sx = cell_coord(xs.x[i], g.s[0] * k, g.nc[0] * k);
+            const int sy = cell_coord(xs.y[i], g.s[1] * k, g.nc[1] * k);
+            const int sz = cell_coord(xs.z[i], g.s[2] * k, g.nc[2] * k);
+            scan = wmask[(size_t)coff * (size_t)(k * k * k) + sx +
+                         (size_t)g.nc[0] * k * (sy + (size_t)g.nc[1] * k * sz)] != 0;
         }
-    });
-    num = group_sum<P>(num);
-    den = group_sum<P>(den);
-    if (sub == 0) flag[i] = (den > 0.0 && num / den > pc.phi_c) ? 1 : 0;
+        if (!scan) flag[i] = 0;
+    }
+    const uint64_t m = __builtin_amdgcn_ballot_w64(scan);
+    if (m == 0) return;
+    if (scan) wp[lanes_below(m)] = i;
+    __builtin_amdgcn_wave_barrier();
+    const int cnt = (int)__popcll(m);
+    const PairConst pc = cload(R.pc, br.r);
+    const int *__restrict__ cstart = cstart_all + coff;
+    const int sub = lane & (P - 1);
+    for (int q = lane / P; q < cnt; q += 64 / P) {  // uniform over the P lanes of a particle
+        const int ii = wp[q];
+        const double xi = xs.x[ii], yi = xs.y[ii], zi = xs.z[ii];
+        double num = 0.0, den = 0.0;
+        for_each_row(g, xi, yi, zi, cstart, [&](int b, int e, double sx, double sy, double sz) {
+            for (int j = b + sub; j < e; j += P) {
+                if (j == ii) continue;
+                const double r2 = exact_r2((xi - xs.x[j]) + sx, (yi - xs.y[j]) + sy, (zi - xs.z[j]) + sz);
+                if (!(r2 < g.rc2)) continue;
+                const double w = 1.0 - __builtin_sqrt(r2) * pc.inv_rc;
+                den += w * w;
+                if (tag[j] & kFrozenBit) num += w * w;
+            }
+        });
+        num = group_sum<P>(num);
+        den = group_sum<P>(den);
+        if (sub == 0) flag[ii] = (den > 0.0 && num / den > pc.phi_c) ? 1 : 0;
+    }
 }
 
 // Applies the corrector to flagged particles: x <- x(t), v_half <- -v_half;
@@ -1044,13 +1094,13 @@ void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c x
     });
 }
 
-void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint32_t *tag, uint8_t *wnear)
+void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint32_t *tag, uint8_t *wmask)
 {
-    if (R.nblk[0] > 0) k_mark_wall_cells<<<R.nblk[0], kBlock, 0, st>>>(R, xs, tag, wnear);
+    if (R.nblk[0] > 0) k_mark_wall_cells<<<R.nblk[0], kBlock, 0, st>>>(R, xs, tag, wmask);
 }
 
 void launch_phi(hipStream_t st, int lanes, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix, Soa3 vfix,
-                const uint32_t *tag, const int *cstart, const uint8_t *wnear, int *flag_and_count,
+                const uint32_t *tag, const int *cstart, const uint8_t *wmask, int *flag_and_count,
                 unsigned long long *ncorr_total)
 {
     if (n <= 0) return;
@@ -1059,7 +1109,7 @@ void launch_phi(hipStream_t st, int lanes, int n, const Reps &R, Soa3c xs, Soa3c
     int *part = flag + n;              // [n+1 ..]: corrections per block of k_correct
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
-        k_phi<L><<<R.nblk[lanes_index(L)], kBlock, 0, st>>>(R, xs, tag, cstart, wnear, flag);
+        if (R.nblk[0] > 0) k_phi<L><<<R.nblk[0], kBlock, 0, st>>>(R, xs, tag, cstart, wmask, flag);
     });
     const int nb = blocks_for(n);
     k_correct<<<nb, kBlock, 0, st>>>(n, flag, xprev, xfix, vfix, part);

@@ -251,6 +251,10 @@ def test_invalid_inputs_are_rejected(mdpd):
     p2 = mdpd.make_params(**{**w.param_kwargs(), "rd": 1.5})
     with pytest.raises(mdpd.MdpdError):
         mdpd.mdpd_create(p2, w.x, w.v, w.types, w.frozen)
+    p3 = mdpd.make_params(**{**w.param_kwargs(), "wall_model": 1, "phi_c": -0.1})
+    with pytest.raises(mdpd.MdpdError) as e:
+        mdpd.mdpd_create(p3, w.x, w.v, w.types, w.frozen)
+    assert e.value.status == -1
 
 
 def test_device_inputs_equal_host_inputs(mdpd):
