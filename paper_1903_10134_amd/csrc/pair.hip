@@ -38,8 +38,12 @@ namespace {
 // test, 64 pairs per instruction.  A ballot and mbcnt append the hits to i's
 // list in candidate order; i's count is a wave-uniform scalar.
 //
-// Other cells (a periodic image, or a batch above 128 candidates) take the
-// general path: batches are walked 64 candidates at a time with the shifts of
+// Border cells (a periodic image in the stencil) take the same register path
+// when every axis has at least four cells: away from the x faces their rows
+// are still contiguous (wrapped in y and z), on an x face a row is two pieces,
+// and the minimum image is taken on the axes where the cell touches the
+// boundary.  Otherwise (fewer cells, or a batch above 128 candidates) the
+// general path walks the batches 64 candidates at a time with the shifts of
 // each row piece, and i's running count lives in lane (i mod 64).
 //
 // Each entry is the neighbour's slot, with kNearBit set when r < r_d and
@@ -149,24 +153,31 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
     // explicit shift (a pair whose difference rounds to L/2 itself is more
     // than r_c apart either way).
     bool fast = interior || (nx >= 4 && ny >= 4 && nz >= 4);
+    // away from the x faces the stencil is 9 rows of 3 x-adjacent cells, each
+    // contiguous in the sorted order
+    const bool xin = cx > 0 && cx < nx - 1;
     int qz[3] = {0, 0, 0};
-    int rb[9], rl[9];                 // interior: the 9 rows of 3 cells
-    int pb[18], pl[18];               // border: per dz, per dy, piece A then piece B
-    uint32_t pwrap = 0;               // border: bit k = piece k is seen through a boundary
-    int left = 0;                     // border: candidates of the own row before the own cell
-    if (fast && interior) {
-        // row r = (dy + 1) + 3 (dz + 1) spans the cells c + dy nx + dz nx ny - 1 .. + 1
-        const int nxy = nx * ny;
+    int rb[9], rl[9];                 // rows: the 9 rows of 3 cells
+    uint32_t rwrap = 0;               // rows: bit r = row r is seen through a y or z boundary
+    int pb[18], pl[18];               // x faces: per dz, per dy, piece A then piece B
+    uint32_t pwrap = 0;               // x faces: bit k = piece k is seen through a boundary
+    int left = 0;                     // x faces: candidates of the own row before the own cell
+    if (fast && xin) {
+        // row r = (dy + 1) + 3 (dz + 1) spans the cells cx - 1 .. cx + 1 of
+        // the (wrapped) row cy + dy, cz + dz
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
-            const int base = c + (r % 3 - 1) * nx + (r / 3 - 1) * nxy;
+            const int yy = cy + r % 3 - 1, zz = cz + r / 3 - 1;
+            const bool w = yy < 0 || yy >= ny || zz < 0 || zz >= nz;
+            const int base = cx + nx * (wrap_index(yy, ny) + ny * wrap_index(zz, nz));
             rb[r] = cstart[base - 1];
             rl[r] = cstart[base + 2] - rb[r];
+            rwrap |= (w ? 1u : 0u) << r;
         }
 #pragma unroll
         for (int z = 0; z < 3; ++z) qz[z] = rl[3 * z] + rl[3 * z + 1] + rl[3 * z + 2];
     } else if (fast) {
-        // the rows of a border cell: a row that wraps in x is two pieces
+        // the rows of a cell on an x face: a row that wraps in x is two pieces
 #pragma unroll
         for (int z = 0; z < 3; ++z) {
             const int zz = wrap_index(cz + z - 1, nz);
@@ -223,10 +234,12 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
             int slot = -1;
             uint32_t wrap = 0;
             if (q < qz[z]) {
-                if (interior) {
+                if (xin) {
                     const int l0 = rl[3 * z], l1 = rl[3 * z + 1];
+                    const int row = q < l0 ? 3 * z : (q < l0 + l1 ? 3 * z + 1 : 3 * z + 2);
                     slot = q < l0 ? rb[3 * z] + q
                                   : (q < l0 + l1 ? rb[3 * z + 1] + (q - l0) : rb[3 * z + 2] + (q - l0 - l1));
+                    if constexpr (BORDER) wrap = (rwrap >> row) & 1u ? kWrapBit : 0u;
                 } else {
                     int off = q;
 #pragma unroll
@@ -248,38 +261,61 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
         }
         // particle i is candidate selfq0 + i of the dz = 0 batch: after the
         // dy = -1 row and the own row's cells left of the own cell
-        const int selfq0 = interior ? rl[3] - rb[4] : pl[6] + pl[7] + left - i0;
-        for (int ib = 0; ib < ni; ib += 64) {
-            const int nic = ni - ib < 64 ? ni - ib : 64;
-            const int me = i0 + ib + (lane < nic ? lane : 0);
-            const double pxi = ld(xs.x, me), pyi = ld(xs.y, me), pzi = ld(xs.z, me);
-            for (int u = 0; u < nic; ++u) {
-                const double xi = bcast_d(pxi, u), yi = bcast_d(pyi, u), zi = bcast_d(pzi, u);
-                const int i = i0 + ib + u;
-                const int sq = selfq0 + i;
-                const __amdgpu_buffer_rsrc_t ro = row_rsrc(nl + (size_t)i * kListCap, kListCap * 4);
-                const __amdgpu_buffer_rsrc_t rr = row_rsrc(nlr2 + (size_t)i * kListCap, kListCap * (int)sizeof(R2));
-                int cn = 0, cf = 0;
+        const int selfq0 = xin ? rl[3] - rb[4] : pl[6] + pl[7] + left - i0;
+        // the sweep over the particles of the cell, with the minimum image
+        // taken only on the axes where the cell touches the boundary (on the
+        // others every stencil candidate is less than L/2 away, where the
+        // minimum image is the identity)
+        auto sweep = [&](auto WX, auto WY, auto WZ) {
+            for (int ib = 0; ib < ni; ib += 64) {
+                const int nic = ni - ib < 64 ? ni - ib : 64;
+                const int me = i0 + ib + (lane < nic ? lane : 0);
+                const double pxi = ld(xs.x, me), pyi = ld(xs.y, me), pzi = ld(xs.z, me);
+                for (int u = 0; u < nic; ++u) {
+                    const double xi = bcast_d(pxi, u), yi = bcast_d(pyi, u), zi = bcast_d(pzi, u);
+                    const int i = i0 + ib + u;
+                    const int sq = selfq0 + i;
+                    const __amdgpu_buffer_rsrc_t ro = row_rsrc(nl + (size_t)i * kListCap, kListCap * 4);
+                    const __amdgpu_buffer_rsrc_t rr = row_rsrc(nlr2 + (size_t)i * kListCap, kListCap * (int)sizeof(R2));
+                    int cn = 0, cf = 0;
 #pragma unroll
-                for (int s = 0; s < 6; ++s) {
-                    if ((s & 1) && qz[s >> 1] <= 64) continue;
-                    double dx = xi - cxj[s], dy = yi - cyj[s], dz = zi - czj[s];
-                    if (!interior) {
-                        dx = min_image(dx, g.L[0], g.invL[0]);
-                        dy = min_image(dy, g.L[1], g.invL[1]);
-                        dz = min_image(dz, g.L[2], g.invL[2]);
+                    for (int s = 0; s < 6; ++s) {
+                        if ((s & 1) && qz[s >> 1] <= 64) continue;
+                        double dx = xi - cxj[s], dy = yi - cyj[s], dz = zi - czj[s];
+                        if constexpr (decltype(WX)::value) dx = min_image(dx, g.L[0], g.invL[0]);
+                        if constexpr (decltype(WY)::value) dy = min_image(dy, g.L[1], g.invL[1]);
+                        if constexpr (decltype(WZ)::value) dz = min_image(dz, g.L[2], g.invL[2]);
+                        const double r2 = exact_r2(dx, dy, dz);
+                        unsigned long long hm = __builtin_amdgcn_ballot_w64(r2 < rc2) & vm[s];
+                        if ((s >> 1) == 1 && (sq >> 6) == (s & 1)) hm &= ~(1ull << (sq & 63));
+                        const unsigned long long nm = __builtin_amdgcn_ballot_w64(r2 < rd2);
+                        const unsigned long long mn = hm & nm, mf = hm & ~nm;
+                        emit_hits<R2>(ro, rr, far_lds, dump, mn, mf, cn, cf, (uint32_t)cs[s], r2);
+                        cn += __popcll(mn);
+                        cf += __popcll(mf);
                     }
-                    const double r2 = exact_r2(dx, dy, dz);
-                    unsigned long long hm = __builtin_amdgcn_ballot_w64(r2 < rc2) & vm[s];
-                    if ((s >> 1) == 1 && (sq >> 6) == (s & 1)) hm &= ~(1ull << (sq & 63));
-                    const unsigned long long nm = __builtin_amdgcn_ballot_w64(r2 < rd2);
-                    const unsigned long long mn = hm & nm, mf = hm & ~nm;
-                    emit_hits<R2>(ro, rr, far_lds, dump, mn, mf, cn, cf, (uint32_t)cs[s], r2);
-                    cn += __popcll(mn);
-                    cf += __popcll(mf);
+                    flush_far(ro, far_lds, cn, cf);
+                    if (lane == 0) ncnt[i] = cn | (cf << 16);
                 }
-                flush_far(ro, far_lds, cn, cf);
-                if (lane == 0) ncnt[i] = cn | (cf << 16);
+            }
+        };
+        using T = std::true_type;
+        using F = std::false_type;
+        if constexpr (!BORDER) {
+            sweep(F{}, F{}, F{});
+        } else {
+            const bool bx = !interior && (cx == 0 || cx == nx - 1);
+            const bool by = !interior && (cy == 0 || cy == ny - 1);
+            const bool bz = !interior && (cz == 0 || cz == nz - 1);
+            switch ((bx ? 1 : 0) | (by ? 2 : 0) | (bz ? 4 : 0)) {
+            case 0: sweep(F{}, F{}, F{}); break;
+            case 1: sweep(T{}, F{}, F{}); break;
+            case 2: sweep(F{}, T{}, F{}); break;
+            case 3: sweep(T{}, T{}, F{}); break;
+            case 4: sweep(F{}, F{}, T{}); break;
+            case 5: sweep(T{}, F{}, T{}); break;
+            case 6: sweep(F{}, T{}, T{}); break;
+            default: sweep(T{}, T{}, T{}); break;
             }
         }
         return;
