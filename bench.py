@@ -56,10 +56,10 @@ BYTES_STEP_FP64 = 271
 # a plain 256 MiB copy (x2.000 reads, x1.000 writes): the summary and the
 # commands are in profiles/mdpd_step_bulk56_n1053696.md.  Valid for the
 # kernel as profiled; it must be re-measured when the kernel changes.
-FORCE_TRAFFIC_BYTES = {"read": 414629284, "write": 101510242}
+FORCE_TRAFFIC_BYTES = {"read": 414667127, "write": 101510251}
 # The same for the two neighbour-list launches of a step (interior and border
 # cells).
-NLIST_TRAFFIC_BYTES = {"read": 86578579, "write": 183474367}
+NLIST_TRAFFIC_BYTES = {"read": 86814967, "write": 183474382}
 
 
 def list_candidates(x, box, rc=1.0):
@@ -91,6 +91,10 @@ def parse():
     ap.add_argument("--replicas", type=int, default=256, help="replicas of the batched workload (0: skip)")
     ap.add_argument("--no-walls", action="store_true", help="skip the walled channel and rock workloads")
     ap.add_argument("--no-small", action="store_true", help="skip the 6,000-particle eager vs graph workload")
+    ap.add_argument("--walled", type=str, default="channel,rock,ring_cells",
+                    help="walled workloads to run (comma list of channel, rock, ring_cells)")
+    ap.add_argument("--walled-only", action="store_true",
+                    help="run only the walled workloads and print their results (for profiling them)")
     ap.add_argument("--adj-steps", type=int, default=100, help="steps of the batched forward + adjoint")
     ap.add_argument("--adj-every", type=int, default=10, help="checkpoint spacing of the adjoint")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -221,6 +225,29 @@ def run_walled(mdpd, w, steps, warmup):
             "corrections_per_step": o["ncorr_total"] / (steps + warmup)}
 
 
+WALLED = {
+    "channel": (lambda W: W.channel(), 200, 20,
+                "Poiseuille channel 64 x 32 x 64, frozen walls of thickness 2, g_x = 0.02"),
+    "rock": (lambda W: W.rock(), 50, 5,
+             "synthetic rock, 128^3 Gaussian-random-field mask, porosity 0.3, g_x = 0.01"),
+    "ring_cells": (lambda W: W.ring_cells(n=16, layers=2), 200, 20,
+                   "manufactured homogeneous porous medium (ring cells 16 x 2 x 16, solid density 8, "
+                   "fluid 6.2, g_z = 0.02): 16 x 16 cells, 2 layers"),
+}
+
+
+def run_walled_set(mdpd, W, names):
+    out = {}
+    for k in [v for v in names.split(",") if v]:
+        make, steps, warmup, desc = WALLED[k]
+        out[k] = run_walled(mdpd, make(W), steps, warmup)
+        out[k]["workload"] = desc
+        v = out[k]
+        print(f"# {k}: {v['particles']} particles ({v['fluid']} fluid), {v['ms_per_step']:.3f} ms/step, "
+              f"{v['corrections_per_step']:.1f} corrections/step", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(w, nsteps):
     import oracle
     p = oracle.make_params(**w.param_kwargs(), search=1)
@@ -251,6 +278,9 @@ def main():
     from paper_1903_10134_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if a.walled_only:
+        print(json.dumps({"walled": run_walled_set(mdpd, W, a.walled)}), flush=True)
+        return
     stream = torch.cuda.current_stream()
     w = W.bulk(L=a.L, seed=0)
     lanes = [int(v) for v in a.lanes.split(",")] if a.lanes else []
@@ -335,17 +365,7 @@ def main():
         print(f"# small 6000 particles: eager {sm['eager_us_per_step']:.1f} us/step, "
               f"graph {sm['graph_us_per_step']:.1f} us/step", file=sys.stderr, flush=True)
     if not a.no_walls:
-        ch = run_walled(mdpd, W.channel(), 200, 20)
-        ch["workload"] = "Poiseuille channel 64 x 32 x 64, frozen walls of thickness 2, g_x = 0.02"
-        rk = run_walled(mdpd, W.rock(), 50, 5)
-        rk["workload"] = "synthetic rock, 128^3 Gaussian-random-field mask, porosity 0.3, g_x = 0.01"
-        rg = run_walled(mdpd, W.ring_cells(n=16, layers=2), 200, 20)
-        rg["workload"] = ("manufactured homogeneous porous medium (ring cells 16 x 2 x 16, solid density 8, "
-                          "fluid 6.2, g_z = 0.02): 16 x 16 cells, 2 layers")
-        out["walled"] = {"channel": ch, "rock": rk, "ring_cells": rg}
-        for k, v in out["walled"].items():
-            print(f"# {k}: {v['particles']} particles ({v['fluid']} fluid), {v['ms_per_step']:.3f} ms/step, "
-                  f"{v['corrections_per_step']:.1f} corrections/step", file=sys.stderr, flush=True)
+        out["walled"] = run_walled_set(mdpd, W, a.walled)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
     print(json.dumps(out), flush=True)
