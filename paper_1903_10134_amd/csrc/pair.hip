@@ -751,7 +751,7 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
                                                const int *__restrict__ cstart, int packed,
                                                const uint32_t *__restrict__ lst,
                                                const PartRec *__restrict__ rec, const ForceOut &out,
-                                               double &vir, double &ep)
+                                               const double *__restrict__ tab, double &vir, double &ep)
 {
     const uint32_t tgi = tag[i];
     const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
@@ -778,11 +778,11 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
         double A = pc.A, B = pc.B, gam = pc.gamma, sig = pc.sig, Arc2 = pc.Arc2;
         if (MT) {
             const int tt = ti * T + tj;
-            A = pc.tab[tt];
-            B = pc.tab[64 + tt];
-            gam = pc.tab[128 + tt];
-            sig = pc.tab[192 + tt];
-            Arc2 = pc.tab[256 + tt];
+            A = tab[tt];
+            B = tab[64 + tt];
+            gam = tab[128 + tt];
+            sig = tab[192 + tt];
+            Arc2 = tab[256 + tt];
         }
         const int th = theta_int(idi, tgj & kIdMask, pc);
         const double c = (tgj & kFrozenBit) ? 1.0 : 0.5;
@@ -933,12 +933,18 @@ __global__ __launch_bounds__(kBlock) void k_force(Reps Rp, const uint32_t *__res
     PairConst pc = cload(Rp.pc, br.r);
     set_noise_keys(pc, cload(stepp, 0));
     const Geom g = cload(Rp.geom, br.r);
+    // the type-pair planes of the block's replica, staged in LDS
+    __shared__ double ptab[MT ? 320 : 1];
+    if constexpr (MT) {
+        for (int k = (int)threadIdx.x; k < 320; k += kBlock) ptab[k] = pc.tab[k];
+        __syncthreads();
+    }
     double vir = 0.0, ep = 0.0;
     if (i < br.i1) {
         const int packed = ncnt[i];
         if (list_total(packed) <= kListCap) {
             force_particle<P, MT, false, R>(pc, g, i, sub, xs, vh, rho, tag, typ, nullptr, packed,
-                                            nl + (size_t)i * kListCap, rec, out, vir, ep);
+                                            nl + (size_t)i * kListCap, rec, out, ptab, vir, ep);
         } else if (sub == 0) {
             out.ovf[atomicAdd(out.ovf_count, 1)] = i;  // served by k_force_overflow
         }
@@ -976,7 +982,7 @@ __global__ __launch_bounds__(kBlock) void k_force_overflow(Reps Rp, const uint32
         const Geom g = Rp.geom[r];
         double vir = 0.0, ep = 0.0;
         force_particle<P, MT, true, R>(pc, g, i, sub, xs, vh, rho, tag, typ, cstart_all + cload(Rp.cell_off, r),
-                                       ncnt[i], nullptr, nullptr, out, vir, ep);
+                                       ncnt[i], nullptr, nullptr, out, pc.tab, vir, ep);
         vir = group_sum<P>(vir);
         ep = group_sum<P>(ep);
         if (sub == 0) {
