@@ -67,7 +67,15 @@ enum { MDPD_FP64 = 0, MDPD_FP32_FORCES = 1 };
  *   MDPD_WALL_BVF   boundary volume fraction phi of each fluid particle at its
  *                   predicted position, phi_i = sum_{frozen j, r<r_c} w_c^2 /
  *                   sum_{j != i, r<r_c} w_c^2; if phi_i > phi_c the predicted
- *                   step is rejected (x <- x(t), half-step velocity negated). */
+ *                   step is rejected: x <- x(t), and the half-step velocity
+ *                   is reflected.  With wall_slip = 0 it is negated
+ *                   (bounce-back, no slip); otherwise, with the wall normal
+ *                   n = unit(sum_{frozen j, r<r_c} w_c^2 (x_i - x_j) / r) at
+ *                   the predicted position, the normal part is negated and
+ *                   the tangential part scaled by 2 wall_slip - 1: 1 gives
+ *                   specular reflection (full slip), 0.5 drops the
+ *                   tangential velocity (a zero normal sum falls back to
+ *                   bounce-back). */
 enum { MDPD_WALL_OFF = 0, MDPD_WALL_BVF = 1 };
 
 typedef struct {
@@ -86,6 +94,7 @@ typedef struct {
     int32_t ntypes;       /* 1..MDPD_MAX_TYPES                                    */
     int32_t precision;    /* MDPD_FP64 or MDPD_FP32_FORCES                        */
     int32_t wall_model;   /* MDPD_WALL_OFF or MDPD_WALL_BVF                       */
+    double wall_slip;     /* MDPD_WALL_BVF reflection, 0 (no slip) .. 1 (full)    */
 } mdpd_params;
 
 /* Observables at the current step (all FP64 sums in a fixed order):

@@ -41,6 +41,7 @@ class Params(ctypes.Structure):
         ("dt", ctypes.c_double), ("mass", ctypes.c_double),
         ("g", ctypes.c_double * 3),
         ("phi_c", ctypes.c_double),
+        ("wall_slip", ctypes.c_double),
         ("A", ctypes.c_double * (MAXT * MAXT)),
         ("B", ctypes.c_double * (MAXT * MAXT)),
         ("gamma", ctypes.c_double * (MAXT * MAXT)),
@@ -103,7 +104,7 @@ def _ptr(a, ct):
 
 
 def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=(0.0, 0.0, 0.0),
-                seed=0, wall_model=0, phi_c=0.5, search=0) -> Params:
+                seed=0, wall_model=0, phi_c=0.5, search=0, wall_slip=0.0) -> Params:
     """Build the oracle's parameter block.  A, B, gamma: scalars or T x T."""
     A = np.atleast_2d(np.asarray(A, dtype=np.float64))
     B = np.atleast_2d(np.asarray(B, dtype=np.float64))
@@ -116,6 +117,7 @@ def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=
     p.rc, p.rd, p.kT, p.dt, p.mass = rc, rd, kT, dt, mass
     p.g[:] = [float(v) for v in g]
     p.phi_c = phi_c
+    p.wall_slip = float(wall_slip)
     for name, M in (("A", A), ("B", B), ("gamma", G)):
         arr = getattr(p, name)
         for a in range(T):

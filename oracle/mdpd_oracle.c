@@ -40,7 +40,11 @@
  *       contributes w_rho(0) to the density and no pair force.
  *   R4  phi_i = sum_{frozen j, r<r_c} w_c^2 / sum_{j != i, r<r_c} w_c^2;
  *       if phi_i(x*) > phi_c the predicted step is rejected: x* <- x(t),
- *       v_half <- -v_half (bounce-back, no-slip).
+ *       v_half <- -v_half (bounce-back, no-slip) when wall_slip = 0; for
+ *       wall_slip > 0 v_half is reflected about the unit wall normal
+ *       n = unit(sum_{frozen j, r<r_c} w_c^2 (x_i - x_j)/r) at x*: normal
+ *       part negated, tangential part times (2 wall_slip - 1); a zero normal
+ *       sum falls back to bounce-back.
  *   R5  Mass m; body force acts on fluid as m*g.
  * parity pinned: every function here is checked by tests/test_oracle_pins.py
  * against known-answer vectors, closed forms, conservation laws and the
@@ -58,6 +62,7 @@ typedef struct {
     double rc, rd, kT, dt, mass;
     double g[3];
     double phi_c;
+    double wall_slip;   /* corrector reflection: 0 bounce-back .. 1 specular */
     double A[ORC_MAXT * ORC_MAXT];
     double B[ORC_MAXT * ORC_MAXT];
     double gamma[ORC_MAXT * ORC_MAXT];
@@ -354,6 +359,29 @@ static void orc_phi_nl(const orc_params *p, int64_t n, const double *x, const ui
     }
 }
 
+/* Wall normal of fluid particle i at positions x (Sec. 2.2, reading R4):
+ * the w_c^2-weighted sum of the unit vectors from its frozen neighbours
+ * within r_c to it, normalised; returns 0 when that sum is zero. */
+static int orc_wall_normal(const orc_params *p, const double *x, const uint8_t *frozen,
+                           const orc_nlist *nl, int64_t i, double nrm[3])
+{
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int32_t k = 0; k < nl->cnt[i]; ++k) {
+        int64_t j = nl->idx[i][k];
+        if (!frozen[j]) continue;
+        double d[3];
+        orc_delta(x, i, j, p->L, d);
+        double r = sqrt(orc_r2(d));
+        if (r == 0.0) continue;
+        double w = 1.0 - r / p->rc;
+        for (int a = 0; a < 3; ++a) s[a] += w * w * d[a] / r;
+    }
+    double len = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    if (!(len > 0.0)) return 0;
+    for (int a = 0; a < 3; ++a) nrm[a] = s[a] / len;
+    return 1;
+}
+
 void orc_phi(const orc_params *p, int64_t n, const double *x, const uint8_t *frozen, double *phi)
 {
     orc_nlist nl;
@@ -506,6 +534,32 @@ orc_system *orc_create(const orc_params *p, int64_t n, const double *x, const do
     return s;
 }
 
+/* The corrector (reading R4) for the fluid particles with phi > phi_c:
+ * back to x(t), half-step velocity negated or reflected. */
+static int64_t orc_correct(orc_system *s)
+{
+    orc_nlist nl;
+    orc_build(s->x, s->n, s->p.L, s->p.rc, s->p.search, &nl);
+    orc_phi_nl(&s->p, s->n, s->x, s->frozen, &nl, s->phi);
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < s->n; ++i) {
+        if (s->frozen[i] || !(s->phi[i] > s->p.phi_c)) continue;
+        double nrm[3];
+        double *v = &s->vh[3 * i];
+        if (s->p.wall_slip > 0.0 && orc_wall_normal(&s->p, s->x, s->frozen, &nl, i, nrm)) {
+            double vn = v[0] * nrm[0] + v[1] * nrm[1] + v[2] * nrm[2];
+            double ft = 2.0 * s->p.wall_slip - 1.0;
+            for (int a = 0; a < 3; ++a) v[a] = ft * (v[a] - vn * nrm[a]) - vn * nrm[a];
+        } else {
+            for (int a = 0; a < 3; ++a) v[a] = -v[a];
+        }
+        for (int a = 0; a < 3; ++a) s->x[3 * i + a] = s->xprev[3 * i + a];
+        cnt++;
+    }
+    orc_nlist_free(&nl);
+    return cnt;
+}
+
 void orc_step(orc_system *s, int64_t nsteps)
 {
     const int64_t n = s->n;
@@ -523,15 +577,7 @@ void orc_step(orc_system *s, int64_t nsteps)
         /* phi for fluid at the predicted positions, then the corrector */
         s->ncorr_last = 0;
         if (s->p.wall_model) {
-            orc_phi(&s->p, n, s->x, s->frozen, s->phi);
-            for (int64_t i = 0; i < n; ++i) {
-                if (s->frozen[i] || !(s->phi[i] > s->p.phi_c)) continue;
-                for (int a = 0; a < 3; ++a) {
-                    s->x[3 * i + a] = s->xprev[3 * i + a];
-                    s->vh[3 * i + a] = -s->vh[3 * i + a];
-                }
-                s->ncorr_last++;
-            }
+            s->ncorr_last = orc_correct(s);
             s->ncorr_total += s->ncorr_last;
         }
         /* rho, f(t+dt), v(t+dt) */

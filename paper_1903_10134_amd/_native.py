@@ -44,6 +44,7 @@ class Params(ctypes.Structure):
         ("ntypes", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("wall_model", ctypes.c_int32),
+        ("wall_slip", ctypes.c_double),
     ]
 
 
@@ -133,7 +134,7 @@ def _is_torch(a) -> bool:
 
 
 def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=(0.0, 0.0, 0.0),
-                seed=0, wall_model=0, phi_c=0.5, precision=FP64) -> Params:
+                seed=0, wall_model=0, phi_c=0.5, precision=FP64, wall_slip=0.0) -> Params:
     """Parameter block; A, B, gamma are scalars or T x T tables."""
     A = np.atleast_2d(np.asarray(A, dtype=np.float64))
     B = np.atleast_2d(np.asarray(B, dtype=np.float64))
@@ -155,6 +156,7 @@ def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=
     p.ntypes = T
     p.precision = int(precision)
     p.wall_model = int(wall_model)
+    p.wall_slip = float(wall_slip)
     return p
 
 

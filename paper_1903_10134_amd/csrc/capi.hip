@@ -80,6 +80,7 @@ struct mdpd_system {
     int n = 0;
     bool fp32 = false;
     bool walls = false;
+    bool slip = false;  // walls reflect with wall_slip > 0 in some replica
     int lanes[3] = {4, 4, 4};  // neighbour list (unused), density (and phi), force: best at 1M particles
     // replicas (a single system is one replica)
     int nrep = 1;
@@ -285,7 +286,7 @@ struct mdpd_system {
             // only if a particle was moved back (gated on the device)
             launch_zero_int(st, corr, 1);
             tic(4);
-            launch_phi(st, lanes[1], n, R, cview(xs[cur]), cview(xprev), xs[cur], vh[cur], tag[cur], cstart, wmask,
+            launch_phi(st, lanes[1], slip, n, R, cview(xs[cur]), cview(xprev), xs[cur], vh[cur], tag[cur], cstart, wmask,
                        corr, ncorr_total);
             toc(4);
             const int o = 1 - cur;
@@ -332,6 +333,8 @@ mdpd_status validate(const mdpd_params *p, int64_t n)
         return fail(MDPD_E_INVALID, "need dt > 0, mass > 0, kT >= 0");
     if (p->wall_model == MDPD_WALL_BVF && !(p->phi_c >= 0.0))
         return fail(MDPD_E_INVALID, "need phi_c >= 0 with MDPD_WALL_BVF (phi_c = %g)", p->phi_c);
+    if (!(p->wall_slip >= 0.0 && p->wall_slip <= 1.0))
+        return fail(MDPD_E_INVALID, "need 0 <= wall_slip <= 1 (wall_slip = %g)", p->wall_slip);
     if (p->precision != MDPD_FP64 && p->precision != MDPD_FP32_FORCES)
         return fail(MDPD_E_INVALID, "unknown precision %d", p->precision);
     if (p->wall_model != MDPD_WALL_OFF && p->wall_model != MDPD_WALL_BVF)
@@ -423,6 +426,7 @@ PairConst make_pair_const(const mdpd_params *p, const double *tab)
     pc.dt = p->dt;
     pc.mass = p->mass;
     pc.phi_c = p->phi_c;
+    pc.slip = p->wall_slip;
     pc.ntypes = p->ntypes;
     const double rdt = 1.0 / sqrt(p->dt);
     pc.A = p->A[0];
@@ -478,6 +482,8 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     s->nrep = nrep;
     s->fp32 = ps[0].precision == MDPD_FP32_FORCES;
     s->walls = ps[0].wall_model == MDPD_WALL_BVF;
+    for (int r = 0; r < nrep; ++r)
+        if (s->walls && ps[r].wall_slip > 0.0) s->slip = true;
     s->params.assign(ps, ps + nrep);
     s->geoms.resize(nrep);
     s->cell_off.assign(nrep + 1, 0);

@@ -70,6 +70,7 @@ struct PairConst {
     double mg[3];       // body force m g on fluid
     double A, B, gamma, sig, Arc2;  // single-type values; sig = sqrt(2 gamma kT / dt)
     double phi_c;
+    double slip;        // wall reflection: tangential factor 2 slip - 1 (0: bounce-back)
     const double *tab;  // ntypes > 1: A | B | gamma | sig | Arc2 planes of 64
     int ntypes;
     uint32_t seed;      // key word 0 of the pair noise
@@ -268,7 +269,8 @@ void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c x
 void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint32_t *tag, uint8_t *wmask);
 // ncorr: [0] corrections of this step (written), [1..n] per-slot flags,
 // then one count per kBlock slots (scratch); ncorr_total accumulates.
-void launch_phi(hipStream_t st, int lanes, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix,
+// slip: some replica reflects with wall_slip > 0 (the wall normal is needed).
+void launch_phi(hipStream_t st, int lanes, bool slip, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix,
                 Soa3 vfix, const uint32_t *tag, const int *cstart, const uint8_t *wmask, int *ncorr,
                 unsigned long long *ncorr_total);
 // stepp: device word holding the noise step (advanced by the main sort).

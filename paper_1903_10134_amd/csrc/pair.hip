@@ -565,15 +565,19 @@ __global__ __launch_bounds__(kBlock) void k_mark_wall_cells(Reps R, Soa3c xs, co
 
 // phi_i = sum_{frozen j} w_c^2 / sum_j w_c^2 over neighbours within r_c at the
 // predicted positions, by a direct scan of the cells (the exact test of the
-// neighbour list); flag[i] = 1 when phi_i > phi_c.  Frozen particles and
-// fluid particles in unmarked sub-cells have flag 0 and are not scanned.  Each
-// wavefront takes 64 slots, packs the ones to scan in LDS, and runs them in
-// rounds of 64 / P particles with P lanes each, so skipped particles leave no
-// idle lanes.
-template <int P>
+// neighbour list); flag[i] = 0 when phi_i <= phi_c, else 1 (bounce-back: the
+// corrector negates the half-step velocity) or, with NRM and wall_slip > 0,
+// 2: the half-step velocity is reflected here about the wall normal
+// n = unit(sum_{frozen j} w_c^2 (x_i - x_j) / r), normal part negated,
+// tangential part times 2 slip - 1 (a zero normal sum gives flag 1).  Frozen
+// particles and fluid particles in unmarked sub-cells have flag 0 and are not
+// scanned.  Each wavefront takes 64 slots, packs the ones to scan in LDS, and
+// runs them in rounds of 64 / P particles with P lanes each, so skipped
+// particles leave no idle lanes.
+template <int P, bool NRM>
 __global__ __launch_bounds__(kBlock) void k_phi(Reps R, Soa3c xs, const uint32_t *__restrict__ tag,
                                                 const int *__restrict__ cstart_all,
-                                                const uint8_t *__restrict__ wmask, int *__restrict__ flag)
+                                                const uint8_t *__restrict__ wmask, int *__restrict__ flag, Soa3 vh)
 {
     __shared__ int pick[kBlock];
     const BlockRep br = block_rep<1>(R, xcd_block());
@@ -605,38 +609,74 @@ __global__ __launch_bounds__(kBlock) void k_phi(Reps R, Soa3c xs, const uint32_t
     for (int q = lane / P; q < cnt; q += 64 / P) {  // uniform over the P lanes of a particle
         const int ii = wp[q];
         const double xi = xs.x[ii], yi = xs.y[ii], zi = xs.z[ii];
-        double num = 0.0, den = 0.0;
+        double num = 0.0, den = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
         for_each_row(g, xi, yi, zi, cstart, [&](int b, int e, double sx, double sy, double sz) {
             for (int j = b + sub; j < e; j += P) {
                 if (j == ii) continue;
-                const double r2 = exact_r2((xi - xs.x[j]) + sx, (yi - xs.y[j]) + sy, (zi - xs.z[j]) + sz);
+                const double dx = (xi - xs.x[j]) + sx, dy = (yi - xs.y[j]) + sy, dz = (zi - xs.z[j]) + sz;
+                const double r2 = exact_r2(dx, dy, dz);
                 if (!(r2 < g.rc2)) continue;
-                const double w = 1.0 - __builtin_sqrt(r2) * pc.inv_rc;
+                const double r = __builtin_sqrt(r2);
+                const double w = 1.0 - r * pc.inv_rc;
                 den += w * w;
-                if (tag[j] & kFrozenBit) num += w * w;
+                if (tag[j] & kFrozenBit) {
+                    num += w * w;
+                    if constexpr (NRM) {
+                        if (r2 > 0.0) {
+                            const double c = w * w / r;
+                            nx += c * dx;
+                            ny += c * dy;
+                            nz += c * dz;
+                        }
+                    }
+                }
             }
         });
         num = group_sum<P>(num);
         den = group_sum<P>(den);
-        if (sub == 0) flag[ii] = (den > 0.0 && num / den > pc.phi_c) ? 1 : 0;
+        const bool hit = den > 0.0 && num / den > pc.phi_c;
+        int f = hit ? 1 : 0;
+        if constexpr (NRM) {
+            nx = group_sum<P>(nx);
+            ny = group_sum<P>(ny);
+            nz = group_sum<P>(nz);
+            const double n2 = nx * nx + ny * ny + nz * nz;
+            if (hit && pc.slip > 0.0 && n2 > 0.0 && sub == 0) {
+                const double inv = 1.0 / __builtin_sqrt(n2);
+                const double ux = nx * inv, uy = ny * inv, uz = nz * inv;
+                const double vx = vh.x[ii], vy = vh.y[ii], vz = vh.z[ii];
+                const double vn = vx * ux + vy * uy + vz * uz;
+                const double tx = vx - vn * ux, ty = vy - vn * uy, tz = vz - vn * uz;
+                const double ft = 2.0 * pc.slip - 1.0;
+                vh.x[ii] = ft * tx - vn * ux;
+                vh.y[ii] = ft * ty - vn * uy;
+                vh.z[ii] = ft * tz - vn * uz;
+                f = 2;
+            }
+        }
+        if (sub == 0) flag[ii] = f;
     }
 }
 
-// Applies the corrector to flagged particles: x <- x(t), v_half <- -v_half;
-// each block writes its number of corrections to part[blockIdx.x].
+// Applies the corrector to flagged particles: x <- x(t), and for flag 1
+// v_half <- -v_half (flag 2: k_phi has reflected v_half already); each block
+// writes its number of corrections to part[blockIdx.x].
 __global__ __launch_bounds__(kBlock) void k_correct(int n, const int *__restrict__ flag, Soa3c xprev,
                                                     Soa3 xs, Soa3 vh, int *__restrict__ part)
 {
     __shared__ int cnt[kWavesPerBlock];
     const int i = blockIdx.x * kBlock + threadIdx.x;
     int hit = 0;
-    if (i < n && flag[i]) {
+    const int f = i < n ? flag[i] : 0;
+    if (f) {
         xs.x[i] = xprev.x[i];
         xs.y[i] = xprev.y[i];
         xs.z[i] = xprev.z[i];
-        vh.x[i] = -vh.x[i];
-        vh.y[i] = -vh.y[i];
-        vh.z[i] = -vh.z[i];
+        if (f == 1) {
+            vh.x[i] = -vh.x[i];
+            vh.y[i] = -vh.y[i];
+            vh.z[i] = -vh.z[i];
+        }
         hit = 1;
     }
     const int w = (int)__popcll(__ballot(hit));
@@ -1141,8 +1181,8 @@ void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint3
     if (R.nblk[0] > 0) k_mark_wall_cells<<<R.nblk[0], kBlock, 0, st>>>(R, xs, tag, wmask);
 }
 
-void launch_phi(hipStream_t st, int lanes, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix, Soa3 vfix,
-                const uint32_t *tag, const int *cstart, const uint8_t *wmask, int *flag_and_count,
+void launch_phi(hipStream_t st, int lanes, bool slip, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix,
+                Soa3 vfix, const uint32_t *tag, const int *cstart, const uint8_t *wmask, int *flag_and_count,
                 unsigned long long *ncorr_total)
 {
     if (n <= 0) return;
@@ -1151,7 +1191,11 @@ void launch_phi(hipStream_t st, int lanes, int n, const Reps &R, Soa3c xs, Soa3c
     int *part = flag + n;              // [n+1 ..]: corrections per block of k_correct
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
-        if (R.nblk[0] > 0) k_phi<L><<<R.nblk[0], kBlock, 0, st>>>(R, xs, tag, cstart, wmask, flag);
+        if (R.nblk[0] <= 0) return;
+        if (slip)
+            k_phi<L, true><<<R.nblk[0], kBlock, 0, st>>>(R, xs, tag, cstart, wmask, flag, vfix);
+        else
+            k_phi<L, false><<<R.nblk[0], kBlock, 0, st>>>(R, xs, tag, cstart, wmask, flag, vfix);
     });
     const int nb = blocks_for(n);
     k_correct<<<nb, kBlock, 0, st>>>(n, flag, xprev, xfix, vfix, part);

@@ -62,6 +62,7 @@ class Workload:
     seed: int = 0
     wall_model: int = 0
     phi_c: float = 0.5
+    wall_slip: float = 0.0
     info: dict = field(default_factory=dict)
 
     @property
@@ -71,7 +72,7 @@ class Workload:
     def param_kwargs(self) -> dict:
         return dict(box=self.box, A=self.A, B=self.B, gamma=self.gamma, rc=self.rc, rd=self.rd,
                     kT=self.kT, dt=self.dt, mass=self.mass, g=self.g, seed=self.seed,
-                    wall_model=self.wall_model, phi_c=self.phi_c)
+                    wall_model=self.wall_model, phi_c=self.phi_c, wall_slip=self.wall_slip)
 
 
 def _maxwell(rng, n, kT, mass, frozen):

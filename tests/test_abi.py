@@ -50,14 +50,15 @@ def test_struct_layouts_match_header(tmp_path):
     c = tmp_path / "sizes.c"
     c.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "mdpd.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(mdpd_params),"
-        " offsetof(mdpd_params, seed), offsetof(mdpd_params, wall_model), sizeof(mdpd_observables),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(mdpd_params),"
+        " offsetof(mdpd_params, seed), offsetof(mdpd_params, wall_model), offsetof(mdpd_params, wall_slip),"
+        " sizeof(mdpd_observables),"
         " offsetof(mdpd_observables, ke), offsetof(mdpd_observables, momentum)); return 0;}\n")
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)])
     vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     P, O = nat.Params, nat.Observables
-    assert vals == [ctypes.sizeof(P), P.seed.offset, P.wall_model.offset, ctypes.sizeof(O),
+    assert vals == [ctypes.sizeof(P), P.seed.offset, P.wall_model.offset, P.wall_slip.offset, ctypes.sizeof(O),
                     O.ke.offset, O.momentum.offset]
 
 

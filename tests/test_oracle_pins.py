@@ -347,3 +347,70 @@ def test_stress_of_a_two_particle_system(orc):
     fc = -40.0 * (1 - r) + 25.0 * 2 * rho * (1 - r / 0.75)
     assert P[0] == pytest.approx(r * fc / L ** 3, rel=1e-13)
     assert np.allclose(P[1:], 0.0, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Wall corrector reflection (Sec. 2.2; bounce-back, partial and full slip)
+# --------------------------------------------------------------------------
+def wall_and_particle(orc, slip, v0):
+    """A flat wall: two frozen square-lattice layers (spacing 0.5) at y = 2
+    and 2.5 of a periodic 8^3 box; one fluid particle at (0.1875, 3.375,
+    0.1875) with velocity v0; no forces (A = B = gamma = kT = 0); dt = 1/16."""
+    g = np.arange(16) * 0.5
+    wall = np.array([[a, y, b] for y in (2.0, 2.5) for a in g for b in g])
+    x = np.vstack([[0.1875, 3.375, 0.1875], wall])
+    v = np.zeros_like(x)
+    v[0] = v0
+    frozen = np.r_[0, np.ones(len(wall))].astype(np.uint8)
+    p = orc.make_params(box=8.0, A=0.0, B=0.0, gamma=0.0, kT=0.0, dt=0.0625, wall_model=1, phi_c=0.5,
+                        wall_slip=slip)
+    return p, x, v, np.zeros(len(x), np.int32), frozen
+
+
+@pytest.mark.parametrize("slip", [0.0, 0.25, 0.5, 1.0])
+def test_wall_reflection_closed_form(orc, slip):
+    """Step 1 predicts (0.25, 3.3125, 0.25), within r_c of the top layer with
+    only frozen neighbours (phi = 1 > phi_c): the step is rejected, x returns
+    to x(0), and the half-step velocity is reflected about the wall normal,
+    +y by the lattice's mirror symmetry about x = 0.25 and z = 0.25:
+    (1, -1, 1) becomes (2s - 1, 1, 2s - 1); s = 0 negates it exactly."""
+    v0 = np.array([1.0, -1.0, 1.0])
+    p, x, v, t, f = wall_and_particle(orc, slip, v0)
+    s = orc.System(p, x, v, t, f)
+    s.step(1)
+    st = s.state()
+    assert s.observables()["ncorr_last"] == 1
+    assert np.array_equal(st["x"][0], x[0])
+    if slip == 0.0:
+        assert np.array_equal(st["v"][0], -v0)
+    else:
+        assert np.allclose(st["v"][0], [2 * slip - 1, 1.0, 2 * slip - 1], atol=1e-12, rtol=0)
+
+
+def test_specular_reflection_keeps_speeds(orc):
+    """Rough wall (uniform-random frozen particles in y in [0, 2)), fluid
+    above it moving towards it, no forces: with wall_slip = 1 every speed is
+    unchanged through corrections (a reflection is an isometry), with 0.5 a
+    corrected particle keeps only its normal speed (never faster), and
+    corrections happen."""
+    rng = np.random.default_rng(4)
+    L = 6.0
+    wall = np.c_[rng.random(400) * L, rng.random(400) * 2.0, rng.random(400) * L]
+    fl = np.c_[rng.random(300) * L, 2.0 + rng.random(300) * 1.5, rng.random(300) * L]
+    x = np.vstack([fl, wall])
+    v = np.zeros_like(x)
+    v[:300] = rng.normal(0.0, 1.0, (300, 3)) + [0.0, -2.0, 0.0]
+    frozen = np.r_[np.zeros(300), np.ones(400)].astype(np.uint8)
+    for slip in (1.0, 0.5):
+        p = orc.make_params(box=L, A=0.0, B=0.0, gamma=0.0, kT=0.0, dt=0.02, wall_model=1, phi_c=0.5,
+                            wall_slip=slip)
+        s = orc.System(p, x, v, np.zeros(700, np.int32), frozen)
+        before = np.linalg.norm(v[:300], axis=1)
+        s.step(20)
+        after = np.linalg.norm(s.state()["v"][:300], axis=1)
+        assert s.observables()["ncorr_total"] > 20
+        if slip == 1.0:
+            assert np.allclose(after, before, rtol=1e-12, atol=0)
+        else:
+            assert np.all(after <= before * (1 + 1e-12))
+            assert np.any(after < 0.9 * before)
