@@ -491,7 +491,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         });
     }
     acc = group_sum<P>(acc);
-    if (sub == 0) {
+    if constexpr (P == 4) {
+        // the four lanes of i write its record together, 16 bytes each
+        // (x y | z vx | vy vz | rho tag typ), so one store instruction
+        // covers 16 whole records
+        const uint32_t tg = tag[i];
+        const bool fz = (tg & kFrozenBit) != 0;
+        const double *pa = sub == 0 ? xs.x : (sub == 1 ? xs.z : vh.y);
+        const double *pb = sub == 0 ? xs.y : (sub == 1 ? vh.x : vh.z);
+        double a = pa[i], b = pb[i];
+        if (fz && sub >= 1) {
+            b = 0.0;
+            if (sub >= 2) a = 0.0;
+        }
+        if (sub == 3) {
+            a = (double)acc;
+            b = __longlong_as_double((long long)((unsigned long long)tg | ((unsigned long long)typ[i] << 32)));
+        }
+        if (sub == 0) rho[i] = acc;
+        reinterpret_cast<double2 *>(rec + i)[sub] = make_double2(a, b);
+    } else if (sub == 0) {
         rho[i] = acc;
         const uint32_t tg = tag[i];
         const bool fz = (tg & kFrozenBit) != 0;
