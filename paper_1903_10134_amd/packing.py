@@ -128,18 +128,29 @@ def apply_symmetry(p: np.ndarray, h: float, sym) -> np.ndarray:
 def fill_patches(surface: np.ndarray, db: PatchDB, seed: int = 0, symmetries: bool = True):
     """Frozen positions of the patch packing: every surface voxel takes patch
     k ~ U{0..K-1} (and a symmetry ~ U{0..47}) from its own draw of the seeded
-    stream.  Returns (positions, patch index per voxel)."""
+    stream; the output lists the voxels in ``argwhere`` order, each with its
+    patch's particles in database order.  Returns (positions, patch index per
+    voxel)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     vox = np.argwhere(surface)
     pick = rng.integers(0, db.count, size=vox.shape[0])
-    syms = rng.integers(0, len(CUBE_SYMMETRIES), size=vox.shape[0]) if symmetries else None
-    out = []
-    for v, (c, k) in enumerate(zip(vox, pick)):
-        p = db.patch(int(k))
-        if symmetries:
-            p = apply_symmetry(p, db.h, CUBE_SYMMETRIES[int(syms[v])])
-        out.append(c * db.h + p)
-    x = np.concatenate(out) if out else np.zeros((0, 3))
+    syms = rng.integers(0, len(CUBE_SYMMETRIES), size=vox.shape[0]) if symmetries else \
+        np.zeros(vox.shape[0], np.int64)
+    counts = np.diff(db.off)[pick]
+    total = int(counts.sum())
+    if total == 0:
+        return np.zeros((0, 3)), pick
+    # source row of every output particle: patch start + rank inside the patch
+    first = np.cumsum(counts) - counts
+    src = np.repeat(db.off[pick], counts) + (np.arange(total) - np.repeat(first, counts))
+    owner = np.repeat(np.arange(vox.shape[0]), counts)
+    sym_of = syms[owner]
+    x = np.empty((total, 3))
+    for k in np.unique(sym_of):
+        sel = sym_of == k
+        p = db.pos[src[sel]]
+        x[sel] = apply_symmetry(p, db.h, CUBE_SYMMETRIES[int(k)]) if symmetries else p
+    x += vox[owner] * db.h
     return x, pick
 
 
