@@ -97,6 +97,28 @@ def test_batch_with_walls(mdpd):
     b.close()
 
 
+def test_batch_with_wall_slip(mdpd):
+    """Replicas with their own wall_slip (0.5 and 1) step exactly as the
+    same systems alone."""
+    reps = [small_channel(seed=5), small_channel(seed=6)]
+    for w, sl in zip(reps, (0.5, 1.0)):
+        w.wall_slip = sl
+    say("batch wall slip")
+    b = mdpd.Batch(reps)
+    b.step(5)
+    xb, vb, _ = b.state()
+    ob = b.observables()
+    assert sum(o["ncorr_total"] for o in ob) > 0
+    for r, w in enumerate(reps):
+        s = mdpd.System(w)
+        s.step(5)
+        x, v, _ = s.state()
+        sl = slice(b.offsets[r], b.offsets[r + 1])
+        assert np.array_equal(xb[sl], x) and np.array_equal(vb[sl], v), r
+        s.close()
+    b.close()
+
+
 def test_batch_checkpoint_and_limits(mdpd):
     reps = W.replicas(count=3, lo=4.0, hi=5.0, seed=5)
     say("batch checkpoint")
