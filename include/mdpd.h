@@ -257,9 +257,12 @@ mdpd_status mdpd_load_checkpoint(mdpd_system *s, const void *buf, uint64_t bytes
 /* Adjoint: gradients of trajectory losses by reverse-mode differentiation
  * of the timestep (Eq. 1 forces, the density of Sec. 2.1 and the
  * velocity-Verlet order of Alg. 1).  The pair noise depends on (seed, step,
- * ids) only and is held fixed.  Walls must be off (MDPD_E_UNSUPPORTED
- * otherwise: the corrector is a discrete event), and the recording starts
- * from the state given to mdpd_create (MDPD_E_STATE after mdpd_step).
+ * ids) only and is held fixed.  With MDPD_WALL_BVF the corrector's
+ * decisions are held fixed as well (events of the recorded trajectory): a
+ * particle sent back keeps its position and carries its negated half-step
+ * velocity, and the derivative follows that; wall_slip must be 0
+ * (MDPD_E_UNSUPPORTED otherwise).  The recording starts from the state given
+ * to mdpd_create (MDPD_E_STATE after mdpd_step).
  *
  * mdpd_forward_record advances nsteps >= 0 steps from step 0, keeping a
  * device checkpoint every `every` >= 1 steps, and returns in loss[3 nrep]

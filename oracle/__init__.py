@@ -283,7 +283,8 @@ def _opt(a, shape):
 def tangent(p: Params, x0, v0, types, frozen, nsteps, w, avg=False, dx0=None, dv0=None, dA=None, dB=None,
             dgamma=None):
     """Loss L and its derivative dL along the direction (dx0, dv0, dA, dB,
-    dgamma) by forward-mode differentiation of the trajectory (walls off).
+    dgamma) by forward-mode differentiation of the trajectory (with walls:
+    bounce-back only, the corrector's decisions held fixed).
     L = w0 mean_fluid(rho) + w1 P + w2 mean_fluid(v_x) of the final state,
     or its mean over steps 1..nsteps when avg."""
     x0 = _c3(x0)

@@ -714,8 +714,11 @@ int orc_num_threads(void)
 /* ------------------------------------------------------------------------ */
 /* Forward-mode derivative (tangent) of a scalar loss of the trajectory.    */
 /*                                                                          */
-/* The state is advanced exactly as orc_step does (walls off: the corrector */
-/* is a discrete event with no derivative), and next to every quantity q    */
+/* The state is advanced exactly as orc_step does (with walls, the         */
+/* bounce-back corrector's decisions are taken on the state and held fixed: */
+/* a corrected particle's position tangent goes back with it and its        */
+/* half-step velocity tangent changes sign; wall_slip must be 0), and next  */
+/* to every quantity q                                                      */
 /* its tangent dq, the derivative along one direction in the inputs: the    */
 /* initial positions and velocities (dx0, dv0, n x 3) and the pair tables   */
 /* (dA, dB, dgamma, ntypes^2; dsigma = kT dgamma / sigma).  Any of them may */
@@ -873,7 +876,7 @@ int orc_tangent(const orc_params *p, int64_t n, const double *x0, const double *
                 const double *dB, const double *dgamma, int64_t nsteps, const double w[3], int avg,
                 double out[2])
 {
-    if (p->wall_model != 0 || nsteps < 0 || (avg && nsteps < 1)) return -1;
+    if ((p->wall_model != 0 && p->wall_slip != 0.0) || nsteps < 0 || (avg && nsteps < 1)) return -1;
     orc_tan_ctx c = {p, n, type, frozen, dA, dB, dgamma};
     size_t nn = (size_t)(n ? n : 1);
     double *x = (double *)malloc(nn * 3 * sizeof(double)), *dx = (double *)malloc(nn * 3 * sizeof(double));
@@ -881,6 +884,8 @@ int orc_tangent(const orc_params *p, int64_t n, const double *x0, const double *
     double *vh = (double *)malloc(nn * 3 * sizeof(double)), *dvh = (double *)malloc(nn * 3 * sizeof(double));
     double *F = (double *)malloc(nn * 3 * sizeof(double)), *dF = (double *)malloc(nn * 3 * sizeof(double));
     double *rho = (double *)malloc(nn * sizeof(double)), *drho = (double *)malloc(nn * sizeof(double));
+    double *xp = (double *)malloc(nn * 3 * sizeof(double)), *dxp = (double *)malloc(nn * 3 * sizeof(double));
+    double *phi = (double *)malloc(nn * sizeof(double));
     const double hdtm = 0.5 * p->dt / p->mass;
     for (int64_t i = 0; i < n; ++i)
         for (int a = 0; a < 3; ++a) {
@@ -899,6 +904,8 @@ int orc_tangent(const orc_params *p, int64_t n, const double *x0, const double *
     orc_tan_forces(&c, x, dx, vh, dvh, rho, drho, 0, &nl, F, dF, &vir, &dvir);
     orc_nlist_free(&nl);
     for (int64_t s = 1; s <= nsteps; ++s) {
+        memcpy(xp, x, nn * 3 * sizeof(double));
+        memcpy(dxp, dx, nn * 3 * sizeof(double));
         for (int64_t i = 0; i < n; ++i) {
             if (frozen[i]) continue;
             for (int a = 0; a < 3; ++a) {
@@ -907,6 +914,24 @@ int orc_tangent(const orc_params *p, int64_t n, const double *x0, const double *
                 dvh[k] = dv[k] + hdtm * dF[k];
                 x[k] = orc_wrap(x[k] + p->dt * vh[k], p->L[a]);
                 dx[k] = dx[k] + p->dt * dvh[k];
+            }
+        }
+        if (p->wall_model) {
+            /* the corrector (reading R4, bounce-back) with its decisions
+             * taken on the primal state: x and its tangent go back, v_half
+             * and its tangent change sign */
+            orc_build(x, n, p->L, p->rc, p->search, &nl);
+            orc_phi_nl(p, n, x, frozen, &nl, phi);
+            orc_nlist_free(&nl);
+            for (int64_t i = 0; i < n; ++i) {
+                if (frozen[i] || !(phi[i] > p->phi_c)) continue;
+                for (int a = 0; a < 3; ++a) {
+                    int k = 3 * (int)i + a;
+                    x[k] = xp[k];
+                    dx[k] = dxp[k];
+                    vh[k] = -vh[k];
+                    dvh[k] = -dvh[k];
+                }
             }
         }
         orc_build(x, n, p->L, p->rc, p->search, &nl);
@@ -930,6 +955,9 @@ int orc_tangent(const orc_params *p, int64_t n, const double *x0, const double *
     if (!avg) orc_tan_loss(&c, v, dv, rho, drho, vir, dvir, w, &L, &dL);
     out[0] = L;
     out[1] = dL;
+    free(xp);
+    free(dxp);
+    free(phi);
     free(x);
     free(dx);
     free(v);

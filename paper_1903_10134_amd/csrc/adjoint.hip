@@ -2,8 +2,9 @@
 // of the pair passes and of velocity-Verlet), for gradients of trajectory
 // losses with respect to the pair tables A, B, gamma and the initial state.
 //
-// Forward recurrence of one step n (walls off), with u_n the half-step
-// velocity v(t_n + dt/2) and h = dt / (2 m):
+// Forward recurrence of one step n, with u_n the half-step velocity
+// v(t_n + dt/2) and h = dt / (2 m) (a particle the bounce-back wall corrector
+// sends back instead keeps x_n = x_{n-1} and moves on with -u_{n-1}):
 //     x_n = x_{n-1} + dt u_{n-1}              (drift, Alg. 1)
 //     rho_n = rho(x_n)                         (Sec. 2.1)
 //     F_n = F(x_n, u_{n-1}, rho_n; theta_n)    (Eq. 1 and Sec. 2.1)
@@ -238,10 +239,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_density(Reps Rp, Soa3c xs, const
 }
 
 // Drift adjoint (U += dt X for fluid) and reorder into input order (the
-// particle with id k of replica r goes to row part_off[r] + k).
+// particle with id k of replica r goes to row part_off[r] + k).  A particle
+// the wall corrector sent back in this step (corr[row] != 0) kept x and had
+// its half-step velocity negated: its U is negated and gets no dt X.
 __global__ __launch_bounds__(kBlock) void k_adj_scatter(Reps Rp, const AdjConst *__restrict__ act,
                                                        const uint32_t *__restrict__ tag, Soa3c X, Soa3c U,
-                                                       Soa3 Xid, Soa3 Uid)
+                                                       Soa3 Xid, Soa3 Uid, const uint8_t *__restrict__ corr)
 {
     const BlockRep br = elem_rep(Rp);
     const int i = br.i0 + (int)threadIdx.x;
@@ -255,6 +258,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_scatter(Reps Rp, const AdjConst 
     Xid.z[id] = z;
     if (tg & kFrozenBit) {
         Uid.x[id] = Uid.y[id] = Uid.z[id] = 0.0;
+    } else if (corr && corr[id]) {
+        Uid.x[id] = -U.x[i];
+        Uid.y[id] = -U.y[i];
+        Uid.z[id] = -U.z[i];
     } else {
         Uid.x[id] = U.x[i] + dt * x;
         Uid.y[id] = U.y[i] + dt * y;
@@ -367,9 +374,9 @@ void launch_adj_density(hipStream_t st, int lanes, const Reps &R, Soa3c xs, cons
 }
 
 void launch_adj_scatter(hipStream_t st, const Reps &R, const AdjConst *ac, const uint32_t *tag, Soa3c X, Soa3c U,
-                        Soa3 Xid, Soa3 Uid)
+                        Soa3 Xid, Soa3 Uid, const uint8_t *corr)
 {
-    if (R.nblk[0] > 0) k_adj_scatter<<<R.nblk[0], kBlock, 0, st>>>(R, ac, tag, X, U, Xid, Uid);
+    if (R.nblk[0] > 0) k_adj_scatter<<<R.nblk[0], kBlock, 0, st>>>(R, ac, tag, X, U, Xid, Uid, corr);
 }
 
 void launch_adj_gather(hipStream_t st, const Reps &R, const uint32_t *tag, Soa3c Xid, Soa3c Uid, Soa3 X, Soa3 U)

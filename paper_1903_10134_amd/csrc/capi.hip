@@ -81,6 +81,7 @@ struct mdpd_system {
     bool fp32 = false;
     bool walls = false;
     bool slip = false;  // walls reflect with wall_slip > 0 in some replica
+    uint8_t *corr_byid = nullptr;  // adjoint recording: the step's wall events by particle id
     int lanes[3] = {4, 4, 4};  // neighbour list (unused), density (and phi), force: best at 1M particles
     // replicas (a single system is one replica)
     int nrep = 1;
@@ -287,7 +288,7 @@ struct mdpd_system {
             launch_zero_int(st, corr, 1);
             tic(4);
             launch_phi(st, lanes[1], slip, n, R, cview(xs[cur]), cview(xprev), xs[cur], vh[cur], tag[cur], cstart, wmask,
-                       corr, ncorr_total);
+                       corr, ncorr_total, corr_byid);
             toc(4);
             const int o = 1 - cur;
             tic(0);
@@ -1210,6 +1211,7 @@ struct TapeEntry {
     int *cstart;
     int *ncnt;
     uint32_t *nl;
+    uint8_t *corr;  // walls: 1 for the particles (by global id) the corrector sent back in this step
 };
 
 uint64_t tape_entry_bytes(mdpd_system *s)
@@ -1217,7 +1219,8 @@ uint64_t tape_entry_bytes(mdpd_system *s)
     const uint64_t N = (uint64_t)(s->n > 0 ? s->n : 1);
     const uint64_t rb = s->fp32 ? 4 : 8;
     return 3 * align_up(24 * N) + align_up(rb * N) + align_up(4 * N) + align_up(N) +
-           align_up(4 * ((uint64_t)s->R.ncells + 1)) + align_up(4 * N) + align_up(4 * N * kListCap);
+           align_up(4 * ((uint64_t)s->R.ncells + 1)) + align_up(4 * N) + align_up(4 * N * kListCap) +
+           (s->walls ? align_up(N) : 0);
 }
 
 TapeEntry tape_entry(mdpd_system *s, int k)
@@ -1243,10 +1246,13 @@ TapeEntry tape_entry(mdpd_system *s, int k)
     e.ncnt = (int *)b;
     b += align_up(4 * N);
     e.nl = (uint32_t *)b;
+    b += align_up(4 * N * kListCap);
+    e.corr = s->walls ? (uint8_t *)b : nullptr;
     return e;
 }
 
-// Restores the system's list buffers when it goes out of scope.
+// Restores the system's list buffers (and stops recording wall events) when
+// it goes out of scope.
 struct ListRedirect {
     mdpd_system *s;
     int *ncnt;
@@ -1255,6 +1261,7 @@ struct ListRedirect {
     {
         s->ncnt = ncnt;
         s->nl = nl;
+        s->corr_byid = nullptr;
     }
 };
 
@@ -1356,7 +1363,8 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
     if (!s || !loss) return fail(MDPD_E_INVALID, "NULL argument");
     if (nsteps < 0 || every < 1) return fail(MDPD_E_INVALID, "need nsteps >= 0 and every >= 1");
     if (average && nsteps < 1) return fail(MDPD_E_INVALID, "a time average needs nsteps >= 1");
-    if (s->walls) return fail(MDPD_E_UNSUPPORTED, "the adjoint does not differentiate the wall corrector");
+    if (s->slip)
+        return fail(MDPD_E_UNSUPPORTED, "the adjoint differentiates the bounce-back wall corrector only (wall_slip = 0)");
     if (s->step != 0) return fail(MDPD_E_STATE, "recording starts from the state given to mdpd_create");
     AdjRec &a = s->adj;
     a.ready = false;
@@ -1499,6 +1507,10 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
                 const TapeEntry e = tape_entry(s, m);
                 s->ncnt = e.ncnt;
                 s->nl = e.nl;
+                if (e.corr) {  // the step's wall events, by particle id
+                    launch_zero_int(s->st, (int *)e.corr, (int)((N + 3) / 4));
+                    s->corr_byid = e.corr;
+                }
                 s->advance(1);
                 HIPCHK(tape_record(s, m, false));
             }
@@ -1507,7 +1519,7 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
             const AdjConst *act = table(s0 + m);
             adjoint_step(s, m, s0 + m, act);
             const TapeEntry cur = tape_entry(s, m), prev = tape_entry(s, m - 1);
-            launch_adj_scatter(s->st, s->R, act, cur.tag, cview(a.X), cview(a.U), a.Xid, a.Uid);
+            launch_adj_scatter(s->st, s->R, act, cur.tag, cview(a.X), cview(a.U), a.Xid, a.Uid, cur.corr);
             launch_adj_gather(s->st, s->R, prev.tag, cview(a.Xid), cview(a.Uid), a.X, a.U);
         }
     }

@@ -270,9 +270,11 @@ void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint3
 // ncorr: [0] corrections of this step (written), [1..n] per-slot flags,
 // then one count per kBlock slots (scratch); ncorr_total accumulates.
 // slip: some replica reflects with wall_slip > 0 (the wall normal is needed).
+// byid (nullable, n bytes by global particle id): set to 1 for every particle
+// corrected in this step (the adjoint's record of the wall events).
 void launch_phi(hipStream_t st, int lanes, bool slip, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix,
                 Soa3 vfix, const uint32_t *tag, const int *cstart, const uint8_t *wmask, int *ncorr,
-                unsigned long long *ncorr_total);
+                unsigned long long *ncorr_total, uint8_t *byid);
 // stepp: device word holding the noise step (advanced by the main sort).
 void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, const uint32_t *stepp,
                   Soa3c xs, Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ,
@@ -294,8 +296,9 @@ void launch_adj_force(hipStream_t st, int lanes, bool fp32, bool mt, int n, int 
                       const uint32_t *nl, Soa3c fb, Soa3 X, Soa3 U, double *rhoA, double *gp);
 void launch_adj_density(hipStream_t st, int lanes, const Reps &R, Soa3c xs, const int *cstart,
                         const int *ncnt, const uint32_t *nl, const double *rhoA, Soa3 X);
+// corr (nullable): the step's wall-event bytes by global particle id.
 void launch_adj_scatter(hipStream_t st, const Reps &R, const AdjConst *ac, const uint32_t *tag, Soa3c X,
-                        Soa3c U, Soa3 Xid, Soa3 Uid);
+                        Soa3c U, Soa3 Xid, Soa3 Uid, const uint8_t *corr);
 void launch_adj_gather(hipStream_t st, const Reps &R, const uint32_t *tag, Soa3c Xid, Soa3c Uid, Soa3 X,
                        Soa3 U);
 int adj_param_partials(const Reps &R, int tmax);

@@ -679,9 +679,11 @@ __global__ __launch_bounds__(kBlock) void k_phi(Reps R, Soa3c xs, const uint32_t
 
 // Applies the corrector to flagged particles: x <- x(t), and for flag 1
 // v_half <- -v_half (flag 2: k_phi has reflected v_half already); each block
-// writes its number of corrections to part[blockIdx.x].
-__global__ __launch_bounds__(kBlock) void k_correct(int n, const int *__restrict__ flag, Soa3c xprev,
-                                                    Soa3 xs, Soa3 vh, int *__restrict__ part)
+// writes its number of corrections to part[blockIdx.x].  With byid (the
+// adjoint's recording) a corrected particle also sets byid[part_off[r] + id].
+__global__ __launch_bounds__(kBlock) void k_correct(Reps R, int n, const int *__restrict__ flag, Soa3c xprev,
+                                                    Soa3 xs, Soa3 vh, int *__restrict__ part,
+                                                    const uint32_t *__restrict__ tag, uint8_t *__restrict__ byid)
 {
     __shared__ int cnt[kWavesPerBlock];
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -696,6 +698,7 @@ __global__ __launch_bounds__(kBlock) void k_correct(int n, const int *__restrict
             vh.y[i] = -vh.y[i];
             vh.z[i] = -vh.z[i];
         }
+        if (byid) byid[(size_t)cload(R.part_off, find_rep(R.part_off, R.nrep, i)) + (tag[i] & kIdMask)] = 1;
         hit = 1;
     }
     const int w = (int)__popcll(__ballot(hit));
@@ -1202,7 +1205,7 @@ void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint3
 
 void launch_phi(hipStream_t st, int lanes, bool slip, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix,
                 Soa3 vfix, const uint32_t *tag, const int *cstart, const uint8_t *wmask, int *flag_and_count,
-                unsigned long long *ncorr_total)
+                unsigned long long *ncorr_total, uint8_t *byid)
 {
     if (n <= 0) return;
     int *ncorr = flag_and_count;       // [0]: corrections this step
@@ -1217,7 +1220,7 @@ void launch_phi(hipStream_t st, int lanes, bool slip, int n, const Reps &R, Soa3
             k_phi<L, false><<<R.nblk[0], kBlock, 0, st>>>(R, xs, tag, cstart, wmask, flag, vfix);
     });
     const int nb = blocks_for(n);
-    k_correct<<<nb, kBlock, 0, st>>>(n, flag, xprev, xfix, vfix, part);
+    k_correct<<<nb, kBlock, 0, st>>>(R, n, flag, xprev, xfix, vfix, part, tag, byid);
     k_correct_sum<<<1, kBlock, 0, st>>>(nb, part, ncorr, ncorr_total);
 }
 

@@ -7,6 +7,9 @@ of each pair table, random directions in the initial positions and
 velocities.  Bars: FP64 form within 1e-8 relative (the two accumulate the
 same derivative in different orders over several steps), FP32-forces form
 within 1e-4 relative (its trajectory itself differs at FP32 rounding).
+The walled case differentiates the bounce-back corrector with its events
+held fixed (the corrected particles' drift is reverted, their half-step
+velocity negated), against the oracle's tangent of the same events.
 Every case prints its name first so that a failing run names it.
 """
 import numpy as np
@@ -35,6 +38,9 @@ def adj_cases():
         "bulk_L6": W.bulk(L=6.0, density=6.0, seed=3),
         "mixed_types": mixed_types(),
         "dense_cluster": dense_cluster(),
+        # bounce-back walls: the corrector's events of the recorded
+        # trajectory are held fixed on both sides
+        "channel_walls": W.channel(Lx=6.0, Ly=4.0, Lz=6.0, wall=1.5, seed=3, gx=0.05),
     }
 
 
@@ -143,9 +149,11 @@ def test_adjoint_errors(mdpd):
         s.forward_record(3)  # not at step 0
     s.close()
     from test_gpu_parity import small_channel
-    c = mdpd.System(small_channel())
+    w = small_channel()
+    w.wall_slip = 0.5
+    c = mdpd.System(w)
     with pytest.raises(mdpd.MdpdError):
-        c.forward_record(2)  # walls on
+        c.forward_record(2)  # reflecting walls
     c.close()
 
 

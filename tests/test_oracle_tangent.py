@@ -30,6 +30,13 @@ def _case(kind):
         kw["gamma"] = np.array([[4.5, 4.0], [4.0, 5.0]])
     elif kind == "frozen":
         frozen = (rng.random(w.x.shape[0]) < 0.15).astype(np.uint8)
+    elif kind == "walls":
+        # a small driven channel with the bounce-back corrector: its events
+        # are held fixed, so central differences with small steps see the
+        # same events as the tangent
+        w = W.channel(Lx=6.0, Ly=4.0, Lz=6.0, wall=1.5, seed=3, gx=0.05)
+        kw = w.param_kwargs()
+        types, frozen = w.types, w.frozen
     return w, kw, types, frozen
 
 
@@ -44,7 +51,7 @@ def _close(dL, fd, rel, floor):
     return abs(dL - fd) <= rel * abs(fd) + floor
 
 
-@pytest.mark.parametrize("kind", ["one_type", "two_types", "frozen"])
+@pytest.mark.parametrize("kind", ["one_type", "two_types", "frozen", "walls"])
 @pytest.mark.parametrize("nsteps,avg", [(0, False), (4, False), (4, True)])
 def test_tangent_matches_finite_differences(orc, kind, nsteps, avg):
     w, kw, types, frozen = _case(kind)
@@ -110,8 +117,17 @@ def test_galilean_boost_and_momentum(orc):
         assert abs(d) < 1e-12
 
 
-def test_tangent_rejects_walls(orc):
-    w, kw, types, frozen = _case("one_type")
-    p = orc.make_params(**{**kw, "wall_model": 1})
+def test_tangent_with_wall_events(orc):
+    """The walled case has corrector events within the differentiated steps,
+    its loss value is the forward loss, and reflecting walls (wall_slip > 0,
+    whose normal would need a derivative) are refused."""
+    w, kw, types, frozen = _case("walls")
+    p = orc.make_params(**kw)
+    s = orc.System(p, w.x, w.v, types, frozen)
+    s.step(4)
+    assert s.observables()["ncorr_total"] > 0
+    L, _ = orc.tangent(p, w.x, w.v, types, frozen, 4, RHO, False)
+    assert L == pytest.approx(orc.loss(p, w.x, w.v, types, frozen, 4, RHO, False), rel=1e-13, abs=1e-13)
+    q = orc.make_params(**{**kw, "wall_slip": 0.5})
     with pytest.raises(ValueError):
-        orc.tangent(p, w.x, w.v, types, frozen, 2, RHO)
+        orc.tangent(q, w.x, w.v, types, frozen, 2, RHO)
