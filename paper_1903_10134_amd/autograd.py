@@ -54,12 +54,15 @@ class TrajectoryLoss(torch.autograd.Function):
 
 
 def trajectory_loss(x0, v0, A, B, gamma, types, frozen, box, nsteps, every=10, average=True, rc=1.0,
-                    rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=(0.0, 0.0, 0.0), seed=0, precision=FP64):
+                    rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=(0.0, 0.0, 0.0), seed=0, precision=FP64,
+                    wall_model=0, phi_c=0.5):
     """Loss terms (mean fluid density, pressure, mean fluid x-velocity) of a
     trajectory of nsteps from (x0, v0); differentiable in x0, v0, A, B, gamma
-    (T x T float64 tensors).  Walls are off (frozen particles stay put)."""
+    (T x T float64 tensors).  Frozen particles stay put; with wall_model = 1
+    the bounce-back corrector's events of the trajectory are held fixed."""
     spec = {
-        "params": dict(box=box, rc=rc, rd=rd, kT=kT, dt=dt, mass=mass, g=g, seed=seed, precision=precision),
+        "params": dict(box=box, rc=rc, rd=rd, kT=kT, dt=dt, mass=mass, g=g, seed=seed, precision=precision,
+                       wall_model=wall_model, phi_c=phi_c),
         "types": torch.as_tensor(types, dtype=torch.int32),
         "frozen": torch.as_tensor(frozen, dtype=torch.uint8),
         "nsteps": int(nsteps),

@@ -157,12 +157,13 @@ def test_adjoint_errors(mdpd):
     c.close()
 
 
-def test_autograd_function(mdpd):
+@pytest.mark.parametrize("name", ["mixed_types", "channel_walls"])
+def test_autograd_function(mdpd, name):
     """torch.autograd: loss.backward() fills the gradients of x0, v0, A, B,
     gamma with what mdpd_backward returns for the same upstream weights."""
     import torch
     from paper_1903_10134_amd.autograd import trajectory_loss
-    w = CASES["mixed_types"]
+    w = CASES[name]
     say("autograd", w.name)
     dev = torch.device("cuda")
     x0 = torch.tensor(w.x, device=dev, requires_grad=True)
@@ -173,7 +174,8 @@ def test_autograd_function(mdpd):
     kw = w.param_kwargs()
     out = trajectory_loss(x0, v0, A, B, G, torch.tensor(w.types), torch.tensor(w.frozen), kw["box"], nsteps=4,
                           every=2, average=True, rc=kw["rc"], rd=kw["rd"], kT=kw["kT"], dt=kw["dt"],
-                          mass=kw["mass"], g=kw["g"], seed=kw["seed"])
+                          mass=kw["mass"], g=kw["g"], seed=kw["seed"], wall_model=kw["wall_model"],
+                          phi_c=kw["phi_c"])
     wts = (0.5, 0.02, -1.0)
     (out * torch.tensor(wts, dtype=torch.float64, device=dev)).sum().backward()
     s = mdpd.System(w)
