@@ -1,0 +1,70 @@
+"""Plane Poiseuille flow between frozen walls (needs an MI355X).
+
+A channel of width 12 (fluid y in [0, 12), frozen slabs of thickness 2 on
+both sides, box 16 x 16 x 8, density 6, g_x = 0.02, bounce-back walls) is
+driven to its steady state and the fluid velocity, temperature and density
+are averaged across the channel in bins of 0.5.  The textbook solution of
+the driven plane channel is a parabola in y with its zeros at the walls
+(Sec. 2.2: no-slip walls with negligible near-wall density and temperature
+fluctuations):
+
+* the mean u_x profile fits a parabola with R^2 > 0.99, opening downward,
+  whose zeros lie within 0.5 of the wall planes y = 0 and y = 12;
+* the kinetic temperature of the velocities relative to the bin mean stays
+  within 2% of kT = 1 in every bin, next to the walls too;
+* the density is flat to 2% away from the walls and dips by less than 10% in
+  the half-width bins touching them.
+Measured: R^2 0.9985, zeros at 0.18 and 11.81, kT 0.999 .. 1.005, density
+5.94 inside and 5.52 / 5.60 in the wall bins.
+"""
+import numpy as np
+import pytest
+
+from paper_1903_10134_amd import workloads as W
+from test_gpu_parity import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mdpd():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1903_10134_amd as m
+    m.lib()
+    return m
+
+
+def test_poiseuille_profile(mdpd):
+    w = W.channel(Lx=16.0, Ly=12.0, Lz=8.0, wall=2.0, gx=0.02, seed=11)
+    say("poiseuille", w.n)
+    s = mdpd.System(w, precision=mdpd.FP32_FORCES)
+    s.step(20000)
+    nb = 32                      # bins of 0.5 over the periodic height 16: fluid in bins 0..23
+    acc = {q: np.zeros(nb) for q in (0, 1, 4)}
+    m = 0
+    for _ in range(1000):
+        s.step(20)
+        for q in acc:
+            acc[q] += s.profile(1, nb, q)
+        m += 1
+    s.close()
+    y = (np.arange(24) + 0.5) * 0.5
+    u = acc[1][:24] / m
+    kt = acc[4][:24] / m
+    rho = acc[0][:24] / m
+    c = np.polyfit(y, u, 2)
+    fit = np.polyval(c, y)
+    r2 = 1.0 - np.sum((u - fit) ** 2) / np.sum((u - u.mean()) ** 2)
+    roots = np.sort(np.roots(c).real)
+    print(f"\nu_x: " + " ".join(f"{v:.3f}" for v in u))
+    print(f"kT:  " + " ".join(f"{v:.3f}" for v in kt))
+    print(f"rho: " + " ".join(f"{v:.2f}" for v in rho))
+    print(f"parabola R^2 {r2:.4f}, zeros at {roots[0]:.3f} and {roots[1]:.3f}, u_max {u.max():.3f}")
+    assert c[0] < 0.0
+    assert r2 > 0.99
+    assert abs(roots[0] - 0.0) < 0.5 and abs(roots[1] - 12.0) < 0.5
+    assert np.all(np.abs(kt - 1.0) < 0.02)
+    inner = rho[1:23]
+    assert np.all(np.abs(inner / inner.mean() - 1.0) < 0.02)
+    assert rho[0] > 0.9 * inner.mean() and rho[23] > 0.9 * inner.mean()
