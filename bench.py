@@ -85,7 +85,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--L", type=float, default=56.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=12,
+                    help="oracle steps of the CPU baseline (about 10 s on 16 cores)")
     ap.add_argument("--lanes", type=str, default="", help="n,d,f lanes per particle")
     ap.add_argument("--forms", type=str, default="fp32_forces,fp64")
     ap.add_argument("--replicas", type=int, default=256, help="replicas of the batched workload (0: skip)")
