@@ -385,11 +385,16 @@ def test_long_run_statistics_match_oracle(mdpd):
 
 
 @pytest.mark.parametrize("case,prec", [("bulk_L10_n6000", "fp32"), ("dense_cluster", "fp64"),
-                                       ("small_channel", "fp64"), ("small_channel", "fp32")])
+                                       ("small_channel", "fp64"), ("small_channel", "fp32"),
+                                       ("slip_channel", "fp32")])
 def test_checkpoint_resume_bitwise(mdpd, case, prec):
     """A checkpoint loaded into a fresh system continues bit for bit: state,
     forces, observables and neighbour sets after more steps."""
-    w = small_channel() if case == "small_channel" else CASES[case]
+    if case == "slip_channel":
+        w = small_channel(seed=9)
+        w.wall_slip = 0.75
+    else:
+        w = small_channel() if case == "small_channel" else CASES[case]
     p = mdpd.FP32_FORCES if prec == "fp32" else mdpd.FP64
     say("checkpoint", case, prec)
     a = mdpd.System(w, precision=p)
