@@ -23,8 +23,8 @@
 //                  parameter derivative (the pair is visited from both ends),
 //                  so no atomics are needed; plus the virial seed's terms
 //   k_adj_density  X_i += sum_j (rhobar_i + rhobar_j) w_rho'(r) e_ij
-//   k_adj_scatter  U += dt X (drift) and reorder X, U by particle id
-//   k_adj_gather   X, U into the sorted order of step n - 1
+//   k_adj_step_back  U += dt X (drift) and X, U into the sorted order of
+//                  step n - 1 through the recorded sort permutation
 // Parameter shares are written per particle (3 x ntypes values, by the type
 // of the neighbour) and reduced per step in a fixed order (k_adj_params).
 // All adjoint arithmetic is FP64.
@@ -238,50 +238,38 @@ __global__ __launch_bounds__(kBlock) void k_adj_density(Reps Rp, Soa3c xs, const
     X.z[i] += az;
 }
 
-// Drift adjoint (U += dt X for fluid) and reorder into input order (the
-// particle with id k of replica r goes to row part_off[r] + k).  A particle
-// the wall corrector sent back in this step (corr[row] != 0) kept x and had
-// its half-step velocity negated: its U is negated and gets no dt X.
-__global__ __launch_bounds__(kBlock) void k_adj_scatter(Reps Rp, const AdjConst *__restrict__ act,
-                                                       const uint32_t *__restrict__ tag, Soa3c X, Soa3c U,
-                                                       Soa3 Xid, Soa3 Uid, const uint8_t *__restrict__ corr)
+// Drift adjoint (U += dt X for fluid) and the reorder from the sorted order
+// of step n to that of step n - 1 through the recorded sort permutation (the
+// particles barely move between steps, so perm is close to the identity and
+// the reads stay almost coalesced).  A particle the wall corrector sent back
+// in step n (corr[part_off[r] + id] != 0) kept x and had its half-step
+// velocity negated: its U is negated and gets no dt X.
+__global__ __launch_bounds__(kBlock) void k_adj_step_back(Reps Rp, const AdjConst *__restrict__ act,
+                                                         const uint32_t *__restrict__ tag_prev,
+                                                         const int *__restrict__ perm, Soa3c X, Soa3c U,
+                                                         Soa3 Xo, Soa3 Uo, const uint8_t *__restrict__ corr)
 {
     const BlockRep br = elem_rep(Rp);
     const int i = br.i0 + (int)threadIdx.x;
     if (i >= br.i1) return;
     const double dt = cload(act, br.r).dt;
-    const uint32_t tg = tag[i];
-    const size_t id = (size_t)cload(Rp.part_off, br.r) + (tg & kIdMask);
-    const double x = X.x[i], y = X.y[i], z = X.z[i];
-    Xid.x[id] = x;
-    Xid.y[id] = y;
-    Xid.z[id] = z;
+    const uint32_t tg = tag_prev[i];
+    const int k = perm[i];
+    const double x = X.x[k], y = X.y[k], z = X.z[k];
+    Xo.x[i] = x;
+    Xo.y[i] = y;
+    Xo.z[i] = z;
     if (tg & kFrozenBit) {
-        Uid.x[id] = Uid.y[id] = Uid.z[id] = 0.0;
-    } else if (corr && corr[id]) {
-        Uid.x[id] = -U.x[i];
-        Uid.y[id] = -U.y[i];
-        Uid.z[id] = -U.z[i];
+        Uo.x[i] = Uo.y[i] = Uo.z[i] = 0.0;
+    } else if (corr && corr[(size_t)cload(Rp.part_off, br.r) + (tg & kIdMask)]) {
+        Uo.x[i] = -U.x[k];
+        Uo.y[i] = -U.y[k];
+        Uo.z[i] = -U.z[k];
     } else {
-        Uid.x[id] = U.x[i] + dt * x;
-        Uid.y[id] = U.y[i] + dt * y;
-        Uid.z[id] = U.z[i] + dt * z;
+        Uo.x[i] = U.x[k] + dt * x;
+        Uo.y[i] = U.y[k] + dt * y;
+        Uo.z[i] = U.z[k] + dt * z;
     }
-}
-
-__global__ __launch_bounds__(kBlock) void k_adj_gather(Reps Rp, const uint32_t *__restrict__ tag, Soa3c Xid,
-                                                      Soa3c Uid, Soa3 X, Soa3 U)
-{
-    const BlockRep br = elem_rep(Rp);
-    const int i = br.i0 + (int)threadIdx.x;
-    if (i >= br.i1) return;
-    const size_t id = (size_t)cload(Rp.part_off, br.r) + (tag[i] & kIdMask);
-    X.x[i] = Xid.x[id];
-    X.y[i] = Xid.y[id];
-    X.z[i] = Xid.z[id];
-    U.x[i] = Uid.x[id];
-    U.y[i] = Uid.y[id];
-    U.z[i] = Uid.z[id];
 }
 
 // Parameter shares, first level: for each replica-aligned block of kBlock
@@ -373,15 +361,10 @@ void launch_adj_density(hipStream_t st, int lanes, const Reps &R, Soa3c xs, cons
     });
 }
 
-void launch_adj_scatter(hipStream_t st, const Reps &R, const AdjConst *ac, const uint32_t *tag, Soa3c X, Soa3c U,
-                        Soa3 Xid, Soa3 Uid, const uint8_t *corr)
+void launch_adj_step_back(hipStream_t st, const Reps &R, const AdjConst *ac, const uint32_t *tag_prev,
+                          const int *perm, Soa3c X, Soa3c U, Soa3 Xo, Soa3 Uo, const uint8_t *corr)
 {
-    if (R.nblk[0] > 0) k_adj_scatter<<<R.nblk[0], kBlock, 0, st>>>(R, ac, tag, X, U, Xid, Uid, corr);
-}
-
-void launch_adj_gather(hipStream_t st, const Reps &R, const uint32_t *tag, Soa3c Xid, Soa3c Uid, Soa3 X, Soa3 U)
-{
-    if (R.nblk[0] > 0) k_adj_gather<<<R.nblk[0], kBlock, 0, st>>>(R, tag, Xid, Uid, X, U);
+    if (R.nblk[0] > 0) k_adj_step_back<<<R.nblk[0], kBlock, 0, st>>>(R, ac, tag_prev, perm, X, U, Xo, Uo, corr);
 }
 
 int adj_param_partials(const Reps &R, int tmax) { return (R.nblk[0] + 1) * 3 * tmax * tmax; }

@@ -9,6 +9,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "mdpd.h"
@@ -65,7 +66,8 @@ struct AdjRec {
     char *tape = nullptr;  // ntape entries of tape_bytes each
     uint64_t tape_bytes = 0;
     int ntape = 0;
-    Soa3 X{}, U{}, fb{}, Xid{}, Uid{};
+    Soa3 X{}, U{}, fb{}, Xo{}, Uo{};  // Xo, Uo: the step-back targets, swapped with X, U each step
+    int *dmap = nullptr;  // walls: the two sort permutations of a recomputed step (2 n)
     double *rhoA = nullptr, *gp = nullptr, *gpart = nullptr, *gtot = nullptr, *loss = nullptr;
     AdjConst *act = nullptr;  // 4 tables of nrep entries: seeded, unseeded, final, creation
     std::vector<AdjConst> host_act;  // host copy (kept alive while the upload may read it)
@@ -82,6 +84,7 @@ struct mdpd_system {
     bool walls = false;
     bool slip = false;  // walls reflect with wall_slip > 0 in some replica
     uint8_t *corr_byid = nullptr;  // adjoint recording: the step's wall events by particle id
+    int *perm_out = nullptr;       // adjoint recording: where the step's sorts move each slot
     int lanes[3] = {4, 4, 4};  // neighbour list (unused), density (and phi), force: best at 1M particles
     // replicas (a single system is one replica)
     int nrep = 1;
@@ -265,7 +268,7 @@ struct mdpd_system {
         tic(0);
         launch_sort(st, n, R, cview(xpred), cview(vpred), walls ? cview(xs[cur]) : Soa3c{nullptr, nullptr, nullptr},
                     tag[cur], typ[cur], xs[o], vh[o], xprev, tag[o], typ[o], key, slot, tmpid, counts,
-                    cstart, bsum, nullptr, ovf, dstep);
+                    cstart, bsum, nullptr, ovf, dstep, perm_out ? (walls ? adj.dmap : perm_out) : nullptr);
         toc(0);
         cur = o;
     }
@@ -294,7 +297,7 @@ struct mdpd_system {
             tic(0);
             launch_sort(st, n, R, cview(xs[cur]), cview(vh[cur]), Soa3c{nullptr, nullptr, nullptr}, tag[cur],
                         typ[cur], xs[o], vh[o], Soa3{nullptr, nullptr, nullptr}, tag[o], typ[o], key, slot,
-                        tmpid, counts, cstart, bsum, corr, nullptr, nullptr);
+                        tmpid, counts, cstart, bsum, corr, nullptr, nullptr, perm_out ? adj.dmap + n : nullptr);
             toc(0);
             cur = o;
         }
@@ -1211,6 +1214,7 @@ struct TapeEntry {
     int *cstart;
     int *ncnt;
     uint32_t *nl;
+    int *perm;      // slot in this state of the particle at slot i of the state before
     uint8_t *corr;  // walls: 1 for the particles (by global id) the corrector sent back in this step
 };
 
@@ -1220,7 +1224,7 @@ uint64_t tape_entry_bytes(mdpd_system *s)
     const uint64_t rb = s->fp32 ? 4 : 8;
     return 3 * align_up(24 * N) + align_up(rb * N) + align_up(4 * N) + align_up(N) +
            align_up(4 * ((uint64_t)s->R.ncells + 1)) + align_up(4 * N) + align_up(4 * N * kListCap) +
-           (s->walls ? align_up(N) : 0);
+           align_up(4 * N) + (s->walls ? align_up(N) : 0);
 }
 
 TapeEntry tape_entry(mdpd_system *s, int k)
@@ -1247,6 +1251,8 @@ TapeEntry tape_entry(mdpd_system *s, int k)
     b += align_up(4 * N);
     e.nl = (uint32_t *)b;
     b += align_up(4 * N * kListCap);
+    e.perm = (int *)b;
+    b += align_up(4 * N);
     e.corr = s->walls ? (uint8_t *)b : nullptr;
     return e;
 }
@@ -1262,6 +1268,7 @@ struct ListRedirect {
         s->ncnt = ncnt;
         s->nl = nl;
         s->corr_byid = nullptr;
+        s->perm_out = nullptr;
     }
 };
 
@@ -1410,10 +1417,11 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
     }
     const size_t nrep = (size_t)s->nrep;
     if (!a.rhoA) {
-        Soa3 *v3[5] = {&a.X, &a.U, &a.fb, &a.Xid, &a.Uid};
+        Soa3 *v3[5] = {&a.X, &a.U, &a.fb, &a.Xo, &a.Uo};
         for (Soa3 *q : v3)
             if ((rc = s->alloc3(q, N))) return rc;
         if ((rc = s->alloc(&a.rhoA, N))) return rc;
+        if (s->walls && (rc = s->alloc(&a.dmap, 2 * N))) return rc;
         if ((rc = s->alloc(&a.gtot, 3 * 64 * nrep))) return rc;
         if ((rc = s->alloc(&a.loss, 3 * nrep + 1))) return rc;
         if ((rc = s->alloc(&a.act, 4 * nrep))) return rc;
@@ -1511,7 +1519,9 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
                     launch_zero_int(s->st, (int *)e.corr, (int)((N + 3) / 4));
                     s->corr_byid = e.corr;
                 }
+                s->perm_out = e.perm;  // where the step's sorts move each slot
                 s->advance(1);
+                if (s->walls) launch_compose(s->st, (int)N, a.dmap, a.dmap + N, e.perm);
                 HIPCHK(tape_record(s, m, false));
             }
         }
@@ -1519,8 +1529,10 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
             const AdjConst *act = table(s0 + m);
             adjoint_step(s, m, s0 + m, act);
             const TapeEntry cur = tape_entry(s, m), prev = tape_entry(s, m - 1);
-            launch_adj_scatter(s->st, s->R, act, cur.tag, cview(a.X), cview(a.U), a.Xid, a.Uid, cur.corr);
-            launch_adj_gather(s->st, s->R, prev.tag, cview(a.Xid), cview(a.Uid), a.X, a.U);
+            launch_adj_step_back(s->st, s->R, act, prev.tag, cur.perm, cview(a.X), cview(a.U), a.Xo, a.Uo,
+                                 cur.corr);
+            std::swap(a.X, a.Xo);
+            std::swap(a.U, a.Uo);
         }
     }
     if (K == 0) {

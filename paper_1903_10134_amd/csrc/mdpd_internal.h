@@ -257,7 +257,10 @@ void launch_sort(hipStream_t st, int n, const Reps &R, Soa3c xin, Soa3c vin, Soa
                  const uint32_t *tag_in, const uint8_t *typ_in, Soa3 xout, Soa3 vout,
                  Soa3 xprev_out, uint32_t *tag_out, uint8_t *typ_out, int *key, int *slot,
                  uint32_t *tmpid, int *counts, int *cstart, int *bsum, const int *gate,
-                 int *ovf_count, uint32_t *step_ctr);
+                 int *ovf_count, uint32_t *step_ctr, int *dmap);
+// dmap (nullable, launch_sort): dmap[i] = the slot particle i (input order)
+// moves to.  launch_compose: out[i] = b[a[i]].
+void launch_compose(hipStream_t st, int n, const int *a, const int *b, int *out);
 void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int *cstart, int *ncnt,
                   uint32_t *nl, void *nlr2, const int *gate);
 // Also writes the packed neighbour records of every slot.
@@ -296,11 +299,12 @@ void launch_adj_force(hipStream_t st, int lanes, bool fp32, bool mt, int n, int 
                       const uint32_t *nl, Soa3c fb, Soa3 X, Soa3 U, double *rhoA, double *gp);
 void launch_adj_density(hipStream_t st, int lanes, const Reps &R, Soa3c xs, const int *cstart,
                         const int *ncnt, const uint32_t *nl, const double *rhoA, Soa3 X);
-// corr (nullable): the step's wall-event bytes by global particle id.
-void launch_adj_scatter(hipStream_t st, const Reps &R, const AdjConst *ac, const uint32_t *tag, Soa3c X,
-                        Soa3c U, Soa3 Xid, Soa3 Uid, const uint8_t *corr);
-void launch_adj_gather(hipStream_t st, const Reps &R, const uint32_t *tag, Soa3c Xid, Soa3c Uid, Soa3 X,
-                       Soa3 U);
+// Drift adjoint and reorder in one pass: perm[i] = slot in step n of the
+// particle at slot i of step n - 1 (tag_prev: its tags); X, U in the order
+// of step n to Xo, Uo in the order of step n - 1; corr (nullable): the
+// step's wall-event bytes by global particle id.
+void launch_adj_step_back(hipStream_t st, const Reps &R, const AdjConst *ac, const uint32_t *tag_prev,
+                          const int *perm, Soa3c X, Soa3c U, Soa3 Xo, Soa3 Uo, const uint8_t *corr);
 int adj_param_partials(const Reps &R, int tmax);
 void launch_adj_params(hipStream_t st, const Reps &R, int n, int tmax, const uint8_t *typ, const double *gp,
                        double *part, double *gtot);

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const int *__rest
                                                         Soa3 vout, Soa3 pout,
                                                         uint32_t *__restrict__ tag_out,
                                                         uint8_t *__restrict__ typ_out,
-                                                        const int *__restrict__ gate)
+                                                        const int *__restrict__ gate, int *__restrict__ dmap)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -199,6 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const int *__rest
         for (int k = b; k < e; ++k) rank += tmpid[k] < id ? 1 : 0;
         dst = b + rank;
     }
+    if (dmap) dmap[i] = dst;
     xout.x[dst] = xin.x[i];
     xout.y[dst] = xin.y[i];
     xout.z[dst] = xin.z[i];
@@ -280,7 +281,7 @@ void launch_ingest(hipStream_t st, const Reps &R, const double *pos, const doubl
 void launch_sort(hipStream_t st, int n, const Reps &R, Soa3c xin, Soa3c vin, Soa3c xprev_in,
                  const uint32_t *tag_in, const uint8_t *typ_in, Soa3 xout, Soa3 vout, Soa3 xprev_out,
                  uint32_t *tag_out, uint8_t *typ_out, int *key, int *slot, uint32_t *tmpid, int *counts,
-                 int *cstart, int *bsum, const int *gate, int *ovf_count, uint32_t *step_ctr)
+                 int *cstart, int *bsum, const int *gate, int *ovf_count, uint32_t *step_ctr, int *dmap)
 {
     const int m = R.ncells;
     const int nb = (m + kScanTile - 1) / kScanTile;
@@ -291,8 +292,20 @@ void launch_sort(hipStream_t st, int n, const Reps &R, Soa3c xin, Soa3c vin, Soa
         k_scatter_id<<<blocks_for(n), kBlock, 0, st>>>(n, key, slot, cstart, tag_in, tmpid, gate);
         k_rank_gather<<<blocks_for(n), kBlock, 0, st>>>(n, key, cstart, tmpid, xin, vin, xprev_in,
                                                         tag_in, typ_in, xout, vout, xprev_out, tag_out,
-                                                        typ_out, gate);
+                                                        typ_out, gate, dmap);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_compose(int n, const int *__restrict__ a, const int *__restrict__ b,
+                                                    int *__restrict__ out)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = b[a[i]];
+}
+
+void launch_compose(hipStream_t st, int n, const int *a, const int *b, int *out)
+{
+    if (n > 0) k_compose<<<blocks_for(n), kBlock, 0, st>>>(n, a, b, out);
 }
 
 }  // namespace mdpd
