@@ -135,7 +135,7 @@ def grf_mask(N=128, corr=6.0, porosity=0.3, seed=0):
     kx, ky, kz = np.meshgrid(k, k, np.fft.rfftfreq(N) * 2.0 * np.pi, indexing="ij")
     s = corr / np.sqrt(2.0)
     filt = np.exp(-0.5 * s * s * (kx * kx + ky * ky + kz * kz))
-    f = np.fft.irfftn(np.fft.rfftn(w) * filt, s=(N, N, N))
+    f = np.fft.irfftn(np.fft.rfftn(w) * filt, s=(N, N, N), axes=(0, 1, 2))
     thr = np.quantile(f, porosity)
     return f <= thr
 
