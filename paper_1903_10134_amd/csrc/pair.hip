@@ -263,9 +263,10 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
         // dy = -1 row and the own row's cells left of the own cell
         const int selfq0 = xin ? rl[3] - rb[4] : pl[6] + pl[7] + left - i0;
         // the sweep over the particles of the cell, with the minimum image
-        // taken only on the axes where the cell touches the boundary (on the
-        // others every stencil candidate is less than L/2 away, where the
-        // minimum image is the identity)
+        // taken only on the axis where a face cell touches the boundary (on
+        // the others every stencil candidate is less than L/2 away, where the
+        // minimum image is the identity); edge and corner cells take it on
+        // all three axes
         auto sweep = [&](auto WX, auto WY, auto WZ) {
             for (int ib = 0; ib < ni; ib += 64) {
                 const int nic = ni - ib < 64 ? ni - ib : 64;
@@ -311,11 +312,8 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
             case 0: sweep(F{}, F{}, F{}); break;
             case 1: sweep(T{}, F{}, F{}); break;
             case 2: sweep(F{}, T{}, F{}); break;
-            case 3: sweep(T{}, T{}, F{}); break;
             case 4: sweep(F{}, F{}, T{}); break;
-            case 5: sweep(T{}, F{}, T{}); break;
-            case 6: sweep(F{}, T{}, T{}); break;
-            default: sweep(T{}, T{}, T{}); break;
+            default: sweep(T{}, T{}, T{}); break;  // edges and corners
             }
         }
         return;
