@@ -46,9 +46,11 @@
  *       part negated, tangential part times (2 wall_slip - 1); a zero normal
  *       sum falls back to bounce-back.
  *   R5  Mass m; body force acts on fluid as m*g.
- * parity pinned: every function here is checked by tests/test_oracle_pins.py
- * against known-answer vectors, closed forms, conservation laws and the
- * equations of state the paper prints.
+ * parity pinned: every function here is checked by tests/test_oracle_pins.py,
+ * tests/test_oracle_pins_phi_profile.py (boundary volume fraction and bin
+ * profiles) and tests/test_oracle_tangent.py against known-answer vectors,
+ * closed forms, conservation laws and the equations of state the paper
+ * prints.
  */
 #include <math.h>
 #include <stdint.h>
