@@ -7,12 +7,19 @@ kT = 1, dt = 0.01, uniform-random start, Maxwell velocities (seed 0).  One
 density pass, force pass with the velocity-Verlet epilogue.
 
 Prints ONE JSON line: particle-steps/s of the FP32-forces form (value) next
-to the all-FP64 form, the roofline of the force kernel (its average launch
-duration measured with HIP events on the library's stream inside the timed
-region), and the FP64 oracle timed on the host's cores on a bounded sample
-(cpu_baseline).
+to the all-FP64 form, timed over `--steps` steps after `--relax` untimed
+steps from the random start and `--warmup` more, with kernel timing off; the
+per-kernel HIP-event times come from a separate pass.  `roofline` is the
+kernel class with the most time per step, priced on its share of the step's
+algorithmic VALU work (pair geometry for the neighbour list, noise and force
+terms plus the velocity-Verlet update for the force pass, the weights for the
+density pass); the step's own VALU and HBM fractions use the whole count and
+the algorithmic bytes (density 29 B, force 105 B, 142 B per re-sort).
+Measured traffic and instruction counts appear as overhead ratios.
+`cpu_baseline` is the FP64 oracle timed on the host's cores on a bounded
+sample.
 
-    python bench.py [--gpus 1] [--steps 1000] [--warmup 100] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 1000] [--warmup 100] [--relax 300] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -33,33 +40,38 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 
-# Algorithmic VALU operations per unique pair within r_c for the force pass
-# (geometry 13, weights 2, conservative 5, dissipative 9, Threefry-2x32-20
-# first word and the noise scaling 77, accumulation into both particles 8),
-# per unique pair within r_d for the density (14) and per particle for the
-# velocity-Verlet update (20).  Derivation in the design notes.
-OPS_FORCE_PAIR = 114
-OPS_DENSITY_PAIR = 14
+# Algorithmic work of one timestep (the count of the survey's measurement
+# section), per unique pair within r_c: pair geometry with the square root
+# 15 ops, Threefry-2x32-20 noise 75, the force terms and their accumulation
+# 30; per unique pair within r_d the density weight 16; per particle the
+# velocity-Verlet update 20.  The geometry is the neighbour list's share,
+# the noise and force terms the force kernel's, so that the kernel shares add
+# up to the step's count (about 1.6 k ops per particle-step at density 6).
+OPS_PAIR_GEOMETRY = 15
+OPS_PAIR_FORCE = 105
+OPS_DENSITY_PAIR = 16
 OPS_VV_PARTICLE = 20
-# Algorithmic VALU operations of the cell-list neighbour search per candidate
-# pair (every particle of the 27-cell stencil): three differences, three
-# squares, two sums and the r_c / r_d comparisons of the exact FP64 test.
-OPS_LIST_CANDIDATE = 10
-# Algorithmic HBM bytes per particle-step of the whole step (every array
-# touched once): read x 24, v_half 24, tag 4, type 1; write x' 24, v 24,
-# v_half' 24, rho 4 (write) + 4 (read), plus the reorder of x, v_half, tag,
-# type (53 read + 53 write): 263 B (FP32 form; +8 for FP64 rho).
-BYTES_STEP_FP32 = 263
-BYTES_STEP_FP64 = 271
-# HBM traffic of one launch of the force kernel (FP32 form, 4 lanes per
-# particle) on this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by
-# a plain 256 MiB copy (x2.000 reads, x1.000 writes): the summary and the
-# commands are in profiles/mdpd_step_bulk56_n1053696.md.  Valid for the
-# kernel as profiled; it must be re-measured when the kernel changes.
-FORCE_TRAFFIC_BYTES = {"read": 414502751, "write": 101510304}
-# The same for the two neighbour-list launches of a step (interior and border
-# cells).
-NLIST_TRAFFIC_BYTES = {"read": 86755077, "write": 183474370}
+# Algorithmic HBM bytes per particle (every array touched once per pass):
+# density pass reads x 24 and type/flags 1 and writes rho 4; force pass
+# reads x 24, v_half 24, rho 4, type 1, id 4 and writes x' 24, v_half' 24;
+# a re-sort moves the state once (142 B).  The FP64 form's rho is 8 bytes
+# (+4 in each pass).  The neighbour list is no algorithmic traffic: its
+# share is the read of x (24 B).
+BYTES_DENSITY = {"fp32_forces": 29, "fp64": 33}
+BYTES_FORCE = {"fp32_forces": 105, "fp64": 109}
+BYTES_RESORT = 142
+BYTES_LIST = 24
+# Measured overheads of the FP32-form kernels on this workload (rocprofv3 on
+# the same command as bench.py's default; profiles/mdpd_step_bulk56_n1053696.md):
+# HBM traffic from FETCH_SIZE / WRITE_SIZE scaled by a plain 256 MiB copy
+# (x2.000 reads, x1.000 writes) and VALU instructions per dispatch
+# (SQ_INSTS_VALU, wave instructions).  Valid for the kernels as profiled;
+# they are re-measured whenever a kernel changes.
+PROFILED = {
+    "nlist": {"read": 86755077, "write": 183474370, "valu_wave_instr": 108.6e6},
+    "force": {"read": 414502751, "write": 101510304, "valu_wave_instr": 85.8e6},
+    "density": {"read": 195000000, "write": 71700000, "valu_wave_instr": 10.9e6},
+}
 
 
 def list_candidates(x, box, rc=1.0):
@@ -87,6 +99,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=12,
                     help="oracle steps of the CPU baseline (about 10 s on 16 cores)")
+    ap.add_argument("--brute-steps", type=int, default=10,
+                    help="oracle steps of the O(N^2) CPU legs on the 6,000-particle box")
+    ap.add_argument("--relax", type=int, default=300,
+                    help="untimed steps from the uniform-random start before the warm-up")
     ap.add_argument("--lanes", type=str, default="", help="n,d,f lanes per particle")
     ap.add_argument("--forms", type=str, default="fp32_forces,fp64")
     ap.add_argument("--replicas", type=int, default=256, help="replicas of the batched workload (0: skip)")
@@ -115,30 +131,38 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_per_launch": n * 4, "launches": 5}), flush=True)
 
 
-def run_form(mdpd, w, precision, steps, warmup, stream, lanes):
+def run_form(mdpd, w, precision, steps, warmup, relax, stream, lanes):
+    """Relax the uniform-random start (untimed), warm up, time `steps` steps
+    with kernel timing off, then take the per-kernel HIP-event times over a
+    separate pass of min(steps, 200) steps."""
     import torch
     s = mdpd.System(w, precision=precision, stream=stream, device_inputs=True)
     if lanes:
         for k, v in enumerate(lanes):
             s.set_lanes(k, v)
-    s.step(warmup)
+    s.step(relax + warmup)
     torch.cuda.synchronize()
-    mdpd.mdpd_set_kernel_timing(s.h, True)
-    for k in range(len(mdpd.KERNELS)):
-        mdpd.mdpd_read_kernel_timing(s.h, k)  # reset
+    obs0 = s.observables()
     t0 = time.perf_counter()
     s.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    obs = s.observables()
+    kt_steps = min(steps, 200)
+    mdpd.mdpd_set_kernel_timing(s.h, True)
+    for k in range(len(mdpd.KERNELS)):
+        mdpd.mdpd_read_kernel_timing(s.h, k)  # reset
+    s.step(kt_steps)
+    torch.cuda.synchronize()
     ktime = {name: mdpd.mdpd_read_kernel_timing(s.h, k) for k, name in enumerate(mdpd.KERNELS)}
     mdpd.mdpd_set_kernel_timing(s.h, False)
-    obs = s.observables()
     cnt_c, _ = s.neighbors(w.rc)
     cnt_d, _ = s.neighbors(w.rd)
     x, _, _ = s.state()
     s.close()
-    return dict(sec=t1 - t0, ktime=ktime, obs=obs, pairs_c=int(cnt_c.sum()) // 2,
-                pairs_d=int(cnt_d.sum()) // 2, candidates=list_candidates(np.asarray(x), w.box, w.rc))
+    return dict(sec=t1 - t0, ktime=ktime, kt_steps=kt_steps, obs=obs, kT_start=obs0["kT"],
+                pairs_c=int(cnt_c.sum()) // 2, pairs_d=int(cnt_d.sum()) // 2,
+                candidates=list_candidates(np.asarray(x), w.box, w.rc))
 
 
 def run_batch(mdpd, W, nrep, steps, every):
@@ -249,19 +273,56 @@ def run_walled_set(mdpd, W, names):
     return out
 
 
-def cpu_baseline(w, nsteps):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, W, nsteps, brute_steps):
+    """The FP64 oracle on the host's cores.  value: its linked-cell search on
+    the benchmark's own workload (the fair O(N) CPU baseline); legs: the
+    brute-force O(N^2) search (the oracle's definition) on the 6,000-particle
+    box on one core and on all cores, and that rate carried to the 1M box by
+    N^2 scaling (extrapolated, not run: one such step would take minutes)."""
     import oracle
+    cores = oracle.num_threads()
     p = oracle.make_params(**w.param_kwargs(), search=1)
     t0 = time.perf_counter()
     o = oracle.System(p, w.x, w.v)
     t1 = time.perf_counter()
     o.step(nsteps)
     t2 = time.perf_counter()
-    return dict(value=w.n * nsteps / (t2 - t1), unit="particle-steps/s", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"{nsteps} steps of the same {w.n}-particle workload with the oracle's "
-                       f"linked-cell search (FP64, OpenMP over particles), after a "
-                       f"{t1 - t0:.1f} s creation")
+    del o
+    out = dict(value=w.n * nsteps / (t2 - t1), unit="particle-steps/s", cores=cores, kind="oracle",
+               cpu_model=cpu_model(),
+               sample=f"{nsteps} steps of the same {w.n}-particle workload with the oracle's "
+                      f"linked-cell search (FP64, OpenMP over particles), after a "
+                      f"{t1 - t0:.1f} s creation")
+    small = W.bulk(L=10.0, seed=0)
+    ps = oracle.make_params(**small.param_kwargs(), search=0)
+    legs = {}
+    for label, threads in (("bruteforce_6000_1core", 1), ("bruteforce_6000_allcores", cores)):
+        oracle.set_num_threads(threads)
+        o = oracle.System(ps, small.x, small.v)
+        t0 = time.perf_counter()
+        o.step(brute_steps)
+        sec = time.perf_counter() - t0
+        del o
+        legs[label] = {"value": small.n * brute_steps / sec, "unit": "particle-steps/s", "cores": threads,
+                       "sample": f"{brute_steps} steps of the 6,000-particle box (L = 10), O(N^2) search"}
+    oracle.set_num_threads(cores)
+    rate = legs["bruteforce_6000_allcores"]["value"]
+    legs["bruteforce_1m_allcores_extrapolated"] = {
+        "value": rate * small.n / w.n, "unit": "particle-steps/s", "cores": cores,
+        "sample": "not run: the all-core O(N^2) rate of the 6,000-particle box scaled by N_small / N"}
+    out["legs"] = legs
+    return out
 
 
 def main():
@@ -289,7 +350,7 @@ def main():
     forms = [f for f in (("fp32_forces", mdpd.FP32_FORCES), ("fp64", mdpd.FP64))
              if f[0] in a.forms.split(",")]
     for name, prec in forms:
-        res[name] = run_form(mdpd, w, prec, a.steps, a.warmup, stream, lanes)
+        res[name] = run_form(mdpd, w, prec, a.steps, a.warmup, a.relax, stream, lanes)
         r = res[name]
         print(f"# {name}: {r['sec'] * 1e3 / a.steps:.3f} ms/step, "
               + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f} us" for k, v in r["ktime"].items() if v[1]),
@@ -300,22 +361,35 @@ def main():
     value = n * a.steps / head["sec"]
     full = n == 1053696 and not lanes  # the profiled configuration
 
-    def kernel_roofline(kind, name, ops, traffic):
+    kt = head["kt_steps"]
+
+    def kernel_roofline(kind, name, ops, alg_bytes):
+        """Roofline of one kernel class on its share of the step's algorithmic
+        VALU work (ops per launch), with the measured overheads as ratios."""
         ms, cnt = head["ktime"][kind]
         avg = ms / max(cnt, 1) * 1e-3
         achieved = ops / avg / 1e12
+        prof = PROFILED.get(kind) if full else None
+        traffic = prof["read"] + prof["write"] if prof else None
         return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": PEAK_VALU_TOPS,
                 "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_VALU_TOPS,
-                "traffic": traffic["read"] + traffic["write"] if full else None,
-                "traffic_read_write": traffic if full else None, "avg_launch_us": avg * 1e6,
-                "ops_per_launch": ops}
+                "traffic": traffic, "avg_launch_us": avg * 1e6, "launches_per_step": cnt / kt,
+                "ops_per_launch": ops, "algorithmic_bytes_per_launch": alg_bytes,
+                "overhead": {
+                    "traffic_over_algorithmic": traffic / alg_bytes if prof else None,
+                    "lane_instr_over_algorithmic": prof["valu_wave_instr"] * 64 / ops if prof else None,
+                }}
 
     rl = {"nlist": kernel_roofline("nlist", "k_nlist_cell + k_nlist_border (FP32 form)",
-                                   head["candidates"] * OPS_LIST_CANDIDATE,
-                                   NLIST_TRAFFIC_BYTES),
+                                   head["pairs_c"] * OPS_PAIR_GEOMETRY, n * BYTES_LIST),
+          "density": kernel_roofline("density", "k_density (FP32 form)",
+                                     head["pairs_d"] * OPS_DENSITY_PAIR, n * BYTES_DENSITY["fp32_forces"]),
           "force": kernel_roofline("force", "k_force (FP32 form)",
-                                   head["pairs_c"] * OPS_FORCE_PAIR + n * OPS_VV_PARTICLE, FORCE_TRAFFIC_BYTES)}
-    dominant = max(rl, key=lambda k: rl[k]["avg_launch_us"])
+                                   head["pairs_c"] * OPS_PAIR_FORCE + n * OPS_VV_PARTICLE,
+                                   n * BYTES_FORCE["fp32_forces"])}
+    rl["nlist"]["overhead"]["candidates_per_particle"] = head["candidates"] / n
+    rl["nlist"]["overhead"]["candidates_over_pairs"] = head["candidates"] / (2 * head["pairs_c"])
+    dominant = max(rl, key=lambda k: rl[k]["avg_launch_us"] * rl[k]["launches_per_step"])
     out = {
         "metric": "mDPD particle-steps/s at 1M particles, FP32 vs FP64 form; adjoint/forward ratio",
         "value": value,
@@ -337,16 +411,21 @@ def main():
         "roofline_kernels": rl,
     }
     for name, r in res.items():
-        bpp = BYTES_STEP_FP32 if name == "fp32_forces" else BYTES_STEP_FP64
         v = n * a.steps / r["sec"]
-        ops_step = r["pairs_c"] * OPS_FORCE_PAIR + r["pairs_d"] * OPS_DENSITY_PAIR + n * OPS_VV_PARTICLE
+        sorts = r["ktime"]["sort"][1] / r["kt_steps"]  # re-sorts per step
+        bpp = BYTES_DENSITY[name] + BYTES_FORCE[name] + BYTES_RESORT * sorts
+        ops_step = (r["pairs_c"] * (OPS_PAIR_GEOMETRY + OPS_PAIR_FORCE) + r["pairs_d"] * OPS_DENSITY_PAIR
+                    + n * OPS_VV_PARTICLE)
         out["forms"][name] = {
             "particle_steps_per_s": v,
             "ms_per_step": r["sec"] * 1e3 / a.steps,
             "kernel_us": {k: (t[0] / max(t[1], 1) * 1e3) for k, t in r["ktime"].items() if t[1]},
+            "algorithmic_ops_per_particle_step": ops_step / n,
+            "algorithmic_bytes_per_particle_step": bpp,
             "step_valu_frac": ops_step / (r["sec"] / a.steps) / 1e12 / PEAK_VALU_TOPS,
             "step_hbm_frac": bpp * v / 1e9 / PEAK_HBM_GBS,
             "pairs_rc": r["pairs_c"], "pairs_rd": r["pairs_d"],
+            "kT_at_timing_start": r["kT_start"],
             "kT": r["obs"]["kT"], "pressure": r["obs"]["pressure"], "mean_rho": r["obs"]["mean_rho"],
         }
     if "fp64" in res:
@@ -368,7 +447,7 @@ def main():
     if not a.no_walls:
         out["walled"] = run_walled_set(mdpd, W, a.walled)
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(w, W, a.cpu_steps, a.brute_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -89,6 +89,8 @@ def lib():
         L.orc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_set_num_threads.restype = None
         L.orc_current_step.argtypes = [ctypes.c_void_p]
         L.orc_current_step.restype = ctypes.c_uint32
         L.orc_tangent.argtypes = [P(Params), i64, P(d), P(d), P(i32), P(u8), P(d), P(d), P(d), P(d), P(d),
@@ -133,6 +135,11 @@ def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=
 def num_threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Set the threads of the oracle's OpenMP loops (for timing on one core)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def threefry2x32_20(ctr, key):

@@ -713,6 +713,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Set the number of threads of the OpenMP loops (ignored without OpenMP). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Forward-mode derivative (tangent) of a scalar loss of the trajectory.    */
 /*                                                                          */
