@@ -180,6 +180,23 @@ mdpd_status mdpd_read_replica_observables(mdpd_system *s, int32_t first, int32_t
  * the stress difference across an interface (Sec. 4.1). */
 mdpd_status mdpd_read_stress(mdpd_system *s, int32_t first, int32_t count, double *out);
 
+/* The pressure tensor of mdpd_read_stress for callers that cannot allocate
+ * memory (code under HIP graph capture, tight serving loops): same result
+ * (within rounding: the per-particle terms are summed per block, then per
+ * replica), but every intermediate lives in a fixed scratch array of 8 MiB
+ * per GPU that the library holds until the process ends, so the call makes
+ * no device or host allocation.  out: 6 doubles per replica first ..
+ * first + count - 1 (xx, yy, zz, xy, xz, yz), in host memory (mem_kind
+ * MDPD_MEM_HOST: the call synchronises the system's stream) or device memory
+ * (MDPD_MEM_DEVICE: the results are written on the system's stream and the
+ * call returns without waiting).  The system's device must be current.
+ * Limit: 6 (blocks + count) doubles, blocks = ceil(4 n_r / 256) summed over
+ * the replicas (about 11 million particles); larger systems give
+ * MDPD_E_UNSUPPORTED.  All calls on one GPU share the scratch: calls that
+ * overlap on one GPU (other threads, other streams) race. */
+mdpd_status mdpd_read_stress_noalloc(mdpd_system *s, int32_t first, int32_t count, double *out,
+                                     int32_t mem_kind);
+
 /* Profile of fluid particles in nbins (1..4096) equal bins of L_axis along
  * axis (0..2).  quantity 0: number density; 1..3: mean velocity x, y, z;
  * 4: kinetic temperature of velocities relative to the bin mean; 5: mean

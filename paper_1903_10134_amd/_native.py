@@ -71,6 +71,8 @@ _SIGS = {
                                       ctypes.c_int32),
     "mdpd_step": ([ctypes.c_void_p, ctypes.c_int64], ctypes.c_int32),
     "mdpd_read_stress": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p], ctypes.c_int32),
+    "mdpd_read_stress_noalloc": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_int32], ctypes.c_int32),
     "mdpd_read_observables": ([ctypes.c_void_p, ctypes.POINTER(Observables)], ctypes.c_int32),
     "mdpd_read_profile": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                            ctypes.c_void_p], ctypes.c_int32),
@@ -237,6 +239,20 @@ def mdpd_read_stress(h, first: int = 0, count: int = 1):
     out = np.zeros(6 * max(count, 1))
     _check(lib().mdpd_read_stress(h, int(first), int(count), out.ctypes.data))
     return out[:6 * count].reshape(count, 6)
+
+
+def mdpd_read_stress_noalloc(h, first: int = 0, count: int = 1, out=None):
+    """The pressure tensor through the entry point that allocates nothing.
+    out: None (host result, shape (count, 6)) or a float64 device tensor of
+    at least 6 count elements that receives the result on the system's
+    stream (returned as given)."""
+    if out is None:
+        res = np.zeros(6 * max(count, 1))
+        _check(lib().mdpd_read_stress_noalloc(h, int(first), int(count), res.ctypes.data, MEM_HOST))
+        return res[:6 * count].reshape(count, 6)
+    _check(lib().mdpd_read_stress_noalloc(h, int(first), int(count), ctypes.c_void_p(out.data_ptr()),
+                                          MEM_DEVICE))
+    return out
 
 
 def mdpd_read_replica_observables(h, first: int, count: int) -> list:

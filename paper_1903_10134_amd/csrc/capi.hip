@@ -79,6 +79,7 @@ struct AdjRec {
 struct mdpd_system {
     mdpd_params p{};
     hipStream_t st = nullptr;
+    int dev = 0;  // the device current at creation (where every buffer lives)
     int n = 0;
     bool fp32 = false;
     bool walls = false;
@@ -482,6 +483,10 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     mdpd_system *s = new mdpd_system();
     s->p = ps[0];
     s->st = (hipStream_t)stream;
+    if (hipGetDevice(&s->dev) != hipSuccess) {
+        delete s;
+        return fail(MDPD_E_HIP, "hipGetDevice failed");
+    }
     s->n = (int)n;
     s->nrep = nrep;
     s->fp32 = ps[0].precision == MDPD_FP32_FORCES;
@@ -809,7 +814,7 @@ mdpd_status mdpd_read_stress(mdpd_system *s, int32_t first, int32_t count, doubl
     double *sums = s->stress + 6 * (N > 0 ? N : 1);
     launch_zero_int(s->st, (int *)sums, 12 * s->nrep);
     launch_stress(s->st, s->fp32, s->mt, s->n, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur],
-                  s->typ[s->cur], s->cstart, s->ncnt, s->nl, s->stress);
+                  s->typ[s->cur], s->cstart, s->ncnt, s->nl, s->stress, false);
     if (N > 0) launch_stress_sum(s->st, s->R, s->n, s->stress, sums);
     std::vector<double> h(6 * (size_t)(count > 0 ? count : 1));
     if (count > 0)
@@ -820,6 +825,77 @@ mdpd_status mdpd_read_stress(mdpd_system *s, int32_t first, int32_t count, doubl
         const mdpd_params &p = s->params[first + k];
         const double V = p.box[0] * p.box[1] * p.box[2];
         for (int a = 0; a < 6; ++a) out[6 * k + a] = h[6 * (size_t)k + a] / V;
+    }
+    return MDPD_OK;
+}
+
+}  // extern "C"
+
+// Scratch of mdpd_read_stress_noalloc: a fixed array in device memory (one
+// copy per GPU, held until the process ends), so that the call allocates
+// nothing.  Host code reaches it only through the address hipGetSymbolAddress
+// returns on each device; the array's own name is not a device address there.
+constexpr size_t kNoallocScratch = (size_t)1 << 20;  // doubles: 8 MiB per GPU
+static __device__ __align__(256) double scratch[kNoallocScratch];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+// The scratch address on the current device, looked up once per device.
+mdpd_status scratch_on_device(int dev, double **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(MDPD_E_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MDPD_E_HIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch[dev] = (double *)p;
+    }
+    *out = g_scratch[dev];
+    return MDPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mdpd_status mdpd_read_stress_noalloc(mdpd_system *s, int32_t first, int32_t count, double *out, int32_t mem_kind)
+{
+    if (!s || !out) return fail(MDPD_E_INVALID, "NULL argument");
+    if (first < 0 || count < 0 || first + count > s->nrep)
+        return fail(MDPD_E_INVALID, "replicas [%d, %d) outside [0, %d)", first, first + count, s->nrep);
+    if (mem_kind != MDPD_MEM_HOST && mem_kind != MDPD_MEM_DEVICE)
+        return fail(MDPD_E_INVALID, "unknown mem_kind %d", mem_kind);
+    if (count == 0) return MDPD_OK;
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != s->dev)
+        return fail(MDPD_E_STATE, "device %d is current; the system lives on device %d", dev, s->dev);
+    const size_t nb = (size_t)s->R.nblk[lanes_index(kStressLanes)];
+    const size_t need = 6 * nb + 6 * (size_t)count;
+    if (need > kNoallocScratch)
+        return fail(MDPD_E_UNSUPPORTED,
+                    "%zu scratch doubles needed (%zu blocks), the fixed scratch holds %zu (about %zu particles)",
+                    need, nb, kNoallocScratch, kNoallocScratch / 6 * (kBlock / kStressLanes));
+    double *ptr = nullptr;
+    mdpd_status rc = scratch_on_device(dev, &ptr);
+    if (rc) return rc;
+    double *parts = ptr, *res = ptr + 6 * nb;
+    // every block writes its partial sums and the reduction writes every
+    // result, so nothing left by an earlier call is read
+    launch_stress(s->st, s->fp32, s->mt, s->n, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur],
+                  s->typ[s->cur], s->cstart, s->ncnt, s->nl, parts, true);
+    launch_stress_part_sum(s->st, s->R, first, count, parts, mem_kind == MDPD_MEM_DEVICE ? out : res);
+    HIPCHK(hipGetLastError());
+    if (mem_kind == MDPD_MEM_HOST) {
+        HIPCHK(hipMemcpyAsync(out, res, 6 * (size_t)count * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
     }
     return MDPD_OK;
 }

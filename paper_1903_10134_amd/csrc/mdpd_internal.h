@@ -328,9 +328,16 @@ void launch_debug_neighbors(hipStream_t st, const Reps &R, double cutoff2, Soa3c
 void launch_zero_int(hipStream_t st, int *p, int n);
 // Pressure tensor: per-slot planes (6 x n, xx yy zz xy xz yz), then per-replica
 // sums into out[6 r + a] (still to be divided by the replica's volume).
+// per_block: instead of planes, six sums per block of kStressLanes lanes per
+// particle (R.nblk[lanes_index(kStressLanes)] blocks, block b at out[6 b]),
+// reduced per replica by launch_stress_part_sum into
+// out[6 k + a] = sum / volume for replicas first + k, k < count.
+constexpr int kStressLanes = 4;
 void launch_stress(hipStream_t st, bool fp32, bool mt, int n, const Reps &R, Soa3c xs, Soa3c v,
                    const void *rho, const uint32_t *tag, const uint8_t *typ, const int *cstart,
-                   const int *ncnt, const uint32_t *nl, double *out);
+                   const int *ncnt, const uint32_t *nl, double *out, bool per_block);
 void launch_stress_sum(hipStream_t st, const Reps &R, int n, const double *planes, double *out);
+void launch_stress_part_sum(hipStream_t st, const Reps &R, int first, int count, const double *parts,
+                            double *out);
 
 }  // namespace mdpd

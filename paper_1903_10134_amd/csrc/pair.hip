@@ -1056,8 +1056,11 @@ __global__ __launch_bounds__(kBlock) void k_force_overflow(Reps Rp, const uint32
 // Pressure tensor per slot (read-out, not part of a step): for fluid i,
 // m v_a v_b + sum_j c_ij d_a d_b / r F^C(r), F^C = A w_c + B (rho_i + rho_j)
 // w_d, c_ij = 1/2 for fluid j and 1 for frozen j; frozen slots give 0.
-// out: six FP64 planes (xx, yy, zz, xy, xz, yz) of n entries.
-template <int P, bool MT, typename R>
+// PART = false: out holds six FP64 planes (xx, yy, zz, xy, xz, yz) of n
+// entries.  PART = true: out holds six sums per block (block b at 6 b, in
+// the fixed order of a tree over the block's particles); every block of the
+// launch writes its six values, so nothing needs clearing first.
+template <int P, bool MT, typename R, bool PART>
 __global__ __launch_bounds__(kBlock) void k_stress(Reps Rp, Soa3c xs, Soa3c v, const R *__restrict__ rho,
                                                    const uint32_t *__restrict__ tag,
                                                    const uint8_t *__restrict__ typ,
@@ -1066,15 +1069,17 @@ __global__ __launch_bounds__(kBlock) void k_stress(Reps Rp, Soa3c xs, Soa3c v, c
                                                    const uint32_t *__restrict__ nl, int n,
                                                    double *__restrict__ out)
 {
-    const BlockRep br = block_rep<P>(Rp, xcd_block());
+    const int blk = xcd_block();
+    const BlockRep br = block_rep<P>(Rp, blk);
     const int i = br.i0 + (int)threadIdx.x / P;
     const int sub = threadIdx.x & (P - 1);
-    if (i >= br.i1) return;
+    const bool live = i < br.i1;
+    if (!PART && !live) return;
     const PairConst pc = cload(Rp.pc, br.r);
     const Geom g = cload(Rp.geom, br.r);
     const int *__restrict__ cstart = cstart_all + cload(Rp.cell_off, br.r);
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    if (!(tag[i] & kFrozenBit)) {
+    if (live && !(tag[i] & kFrozenBit)) {
         const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
         const double rhoi = (double)rho[i];
         const int T = pc.ntypes;
@@ -1113,9 +1118,26 @@ __global__ __launch_bounds__(kBlock) void k_stress(Reps Rp, Soa3c xs, Soa3c v, c
     }
 #pragma unroll
     for (int a = 0; a < 6; ++a) acc[a] = group_sum<P>(acc[a]);
-    if (sub == 0)
+    if constexpr (!PART) {
+        if (sub == 0)
 #pragma unroll
-        for (int a = 0; a < 6; ++a) out[(size_t)a * n + i] = acc[a];
+            for (int a = 0; a < 6; ++a) out[(size_t)a * n + i] = acc[a];
+    } else {
+        // one value per particle (lane sub = 0 of its group), then a tree
+        __shared__ double sh[6][kBlock];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) sh[a][threadIdx.x] = sub == 0 ? acc[a] : 0.0;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w)
+#pragma unroll
+                for (int a = 0; a < 6; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int a = 0; a < 6; ++a) out[6 * (size_t)blk + a] = sh[a][0];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1255,15 +1277,19 @@ void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, 
 
 void launch_stress(hipStream_t st, bool fp32, bool mt, int n, const Reps &R, Soa3c xs, Soa3c v, const void *rho,
                    const uint32_t *tag, const uint8_t *typ, const int *cstart, const int *ncnt, const uint32_t *nl,
-                   double *out)
+                   double *out, bool per_block)
 {
-    constexpr int L = 4;
-    const int nb = R.nblk[lanes_index(L)];
+    const int nb = R.nblk[lanes_index(kStressLanes)];
     if (nb <= 0) return;
     auto go = [&](auto mtc, auto rc) {
         constexpr bool M = decltype(mtc)::value;
         using RT = typename decltype(rc)::type;
-        k_stress<L, M, RT><<<nb, kBlock, 0, st>>>(R, xs, v, (const RT *)rho, tag, typ, cstart, ncnt, nl, n, out);
+        if (per_block)
+            k_stress<kStressLanes, M, RT, true><<<nb, kBlock, 0, st>>>(R, xs, v, (const RT *)rho, tag, typ, cstart,
+                                                                       ncnt, nl, n, out);
+        else
+            k_stress<kStressLanes, M, RT, false><<<nb, kBlock, 0, st>>>(R, xs, v, (const RT *)rho, tag, typ,
+                                                                        cstart, ncnt, nl, n, out);
     };
     if (fp32) {
         if (mt) go(std::true_type{}, Tid<float>{});

@@ -192,6 +192,26 @@ __global__ __launch_bounds__(kRed) void k_stress_sum(Reps Rp, int n, const doubl
         for (int a = 0; a < 6; ++a) out[6 * r + a] = acc[a];
 }
 
+// Pressure tensor from the per-block sums of k_stress: one block per
+// replica r = first + blockIdx.x sums its blocks' partials in a fixed order
+// and divides by the replica's volume.
+__global__ __launch_bounds__(kRed) void k_stress_part_sum(Reps Rp, int first, const double *parts, double *out)
+{
+    __shared__ double sh[6][kRed];
+    const int r = first + (int)blockIdx.x;
+    const int *off = Rp.blk_off + lanes_index(kStressLanes) * (Rp.nrep + 1);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const int b = cload(off, r), e = cload(off, r + 1);
+    for (int k = b + (int)threadIdx.x; k < e; k += kRed)
+        for (int a = 0; a < 6; ++a) acc[a] += parts[6 * (size_t)k + a];
+    block_tree<6>(sh, acc);
+    if (threadIdx.x == 0) {
+        const Geom g = cload(Rp.geom, r);
+        const double V = g.L[0] * g.L[1] * g.L[2];
+        for (int a = 0; a < 6; ++a) out[6 * (size_t)blockIdx.x + a] = acc[a] / V;
+    }
+}
+
 // acc[3r + 0..2] += scale * (mean fluid rho, virial pressure, mean fluid
 // v_x) of replica r from the final sums of k_obs_final.
 __global__ void k_loss_accum(int nrep, const double *obs, const LossConst *lc, double *acc, double scale)
@@ -210,6 +230,13 @@ __global__ void k_loss_accum(int nrep, const double *obs, const LossConst *lc, d
 void launch_stress_sum(hipStream_t st, const Reps &R, int n, const double *planes, double *out)
 {
     k_stress_sum<<<R.nrep, kRed, 0, st>>>(R, n, planes, out);
+}
+
+void launch_stress_part_sum(hipStream_t st, const Reps &R, int first, int count, const double *parts,
+                            double *out)
+{
+    if (count <= 0) return;
+    k_stress_part_sum<<<count, kRed, 0, st>>>(R, first, parts, out);
 }
 
 void launch_loss_accum(hipStream_t st, int nrep, const double *obs, const LossConst *lc, double *acc,
