@@ -104,7 +104,9 @@ def parse():
     ap.add_argument("--relax", type=int, default=300,
                     help="untimed steps from the uniform-random start before the warm-up")
     ap.add_argument("--lanes", type=str, default="", help="n,d,f lanes per particle")
-    ap.add_argument("--forms", type=str, default="fp32_forces,fp64")
+    ap.add_argument("--forms", type=str, default="fp32_forces,fp64,fp32_forces_skin",
+                    help="fp32_forces (the headline), fp64, fp32_forces_skin (FP32 with a list skin)")
+    ap.add_argument("--skin", type=float, default=0.3, help="list skin of the fp32_forces_skin form")
     ap.add_argument("--replicas", type=int, default=256, help="replicas of the batched workload (0: skip)")
     ap.add_argument("--no-walls", action="store_true", help="skip the walled channel and rock workloads")
     ap.add_argument("--no-small", action="store_true", help="skip the 6,000-particle eager vs graph workload")
@@ -131,22 +133,24 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_per_launch": n * 4, "launches": 5}), flush=True)
 
 
-def run_form(mdpd, w, precision, steps, warmup, relax, stream, lanes):
+def run_form(mdpd, w, precision, steps, warmup, relax, stream, lanes, skin=0.0):
     """Relax the uniform-random start (untimed), warm up, time `steps` steps
     with kernel timing off, then take the per-kernel HIP-event times over a
     separate pass of min(steps, 200) steps."""
     import torch
-    s = mdpd.System(w, precision=precision, stream=stream, device_inputs=True)
+    s = mdpd.System(w, precision=precision, stream=stream, device_inputs=True, skin=skin)
     if lanes:
         for k, v in enumerate(lanes):
             s.set_lanes(k, v)
     s.step(relax + warmup)
     torch.cuda.synchronize()
     obs0 = s.observables()
+    b0 = s.list_builds()
     t0 = time.perf_counter()
     s.step(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    builds = s.list_builds() - b0
     obs = s.observables()
     kt_steps = min(steps, 200)
     mdpd.mdpd_set_kernel_timing(s.h, True)
@@ -160,7 +164,8 @@ def run_form(mdpd, w, precision, steps, warmup, relax, stream, lanes):
     cnt_d, _ = s.neighbors(w.rd)
     x, _, _ = s.state()
     s.close()
-    return dict(sec=t1 - t0, ktime=ktime, kt_steps=kt_steps, obs=obs, kT_start=obs0["kT"],
+    return dict(sec=t1 - t0, ktime=ktime, kt_steps=kt_steps, obs=obs, kT_start=obs0["kT"], skin=skin,
+                builds_per_step=builds / max(steps, 1),
                 pairs_c=int(cnt_c.sum()) // 2, pairs_d=int(cnt_d.sum()) // 2,
                 candidates=list_candidates(np.asarray(x), w.box, w.rc))
 
@@ -255,9 +260,9 @@ WALLED = {
                 "Poiseuille channel 64 x 32 x 64, frozen walls of thickness 2, g_x = 0.02"),
     "rock": (lambda W: W.rock(), 50, 5,
              "synthetic rock, 128^3 Gaussian-random-field mask, porosity 0.3, g_x = 0.01"),
-    "ring_cells": (lambda W: W.ring_cells(n=16, layers=2), 200, 20,
+    "ring_cells": (lambda W: W.ring_cells(n=23, layers=1), 200, 20,
                    "manufactured homogeneous porous medium (ring cells 16 x 2 x 16, solid density 8, "
-                   "fluid 6.2, g_z = 0.02): 16 x 16 cells, 2 layers"),
+                   "fluid 6.2, g_z = 0.02): 23 x 23 cells of the paper's thickness 2"),
 }
 
 
@@ -347,10 +352,11 @@ def main():
     w = W.bulk(L=a.L, seed=0)
     lanes = [int(v) for v in a.lanes.split(",")] if a.lanes else []
     res = {}
-    forms = [f for f in (("fp32_forces", mdpd.FP32_FORCES), ("fp64", mdpd.FP64))
+    forms = [f for f in (("fp32_forces", mdpd.FP32_FORCES, 0.0), ("fp64", mdpd.FP64, 0.0),
+                         ("fp32_forces_skin", mdpd.FP32_FORCES, a.skin))
              if f[0] in a.forms.split(",")]
-    for name, prec in forms:
-        res[name] = run_form(mdpd, w, prec, a.steps, a.warmup, a.relax, stream, lanes)
+    for name, prec, skin in forms:
+        res[name] = run_form(mdpd, w, prec, a.steps, a.warmup, a.relax, stream, lanes, skin)
         r = res[name]
         print(f"# {name}: {r['sec'] * 1e3 / a.steps:.3f} ms/step, "
               + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f} us" for k, v in r["ktime"].items() if v[1]),
@@ -412,8 +418,8 @@ def main():
     }
     for name, r in res.items():
         v = n * a.steps / r["sec"]
-        sorts = r["ktime"]["sort"][1] / r["kt_steps"]  # re-sorts per step
-        bpp = BYTES_DENSITY[name] + BYTES_FORCE[name] + BYTES_RESORT * sorts
+        form = "fp64" if name == "fp64" else "fp32_forces"
+        bpp = BYTES_DENSITY[form] + BYTES_FORCE[form] + BYTES_RESORT * r["builds_per_step"]
         ops_step = (r["pairs_c"] * (OPS_PAIR_GEOMETRY + OPS_PAIR_FORCE) + r["pairs_d"] * OPS_DENSITY_PAIR
                     + n * OPS_VV_PARTICLE)
         out["forms"][name] = {
@@ -425,7 +431,7 @@ def main():
             "step_valu_frac": ops_step / (r["sec"] / a.steps) / 1e12 / PEAK_VALU_TOPS,
             "step_hbm_frac": bpp * v / 1e9 / PEAK_HBM_GBS,
             "pairs_rc": r["pairs_c"], "pairs_rd": r["pairs_d"],
-            "kT_at_timing_start": r["kT_start"],
+            "kT_at_timing_start": r["kT_start"], "skin": r["skin"], "list_builds_per_step": r["builds_per_step"],
             "kT": r["obs"]["kT"], "pressure": r["obs"]["pressure"], "mean_rho": r["obs"]["mean_rho"],
         }
     if "fp64" in res:

@@ -79,7 +79,7 @@ enum { MDPD_FP64 = 0, MDPD_FP32_FORCES = 1 };
 enum { MDPD_WALL_OFF = 0, MDPD_WALL_BVF = 1 };
 
 typedef struct {
-    double box[3];        /* periodic box edges L_x, L_y, L_z; each >= 3 r_c      */
+    double box[3];        /* periodic box edges L_x, L_y, L_z; each >= 2 r_c      */
     double rc;            /* cutoff of w_c = 1 - r/r_c (Sec. 2.1)                 */
     double rd;            /* cutoff of w_d = 1 - r/r_d and of w_rho; 0 < r_d <= r_c */
     double kT;            /* target temperature; sigma^2 = 2 gamma kT             */
@@ -95,6 +95,10 @@ typedef struct {
     int32_t precision;    /* MDPD_FP64 or MDPD_FP32_FORCES                        */
     int32_t wall_model;   /* MDPD_WALL_OFF or MDPD_WALL_BVF                       */
     double wall_slip;     /* MDPD_WALL_BVF reflection, 0 (no slip) .. 1 (full)    */
+    double skin;          /* neighbour-list skin >= 0: the cells and the list of  */
+                          /* pairs closer than r_c + skin are rebuilt only when   */
+                          /* a particle has moved skin/2 since the last build     */
+                          /* (0: every step); any value gives the same pairs     */
 } mdpd_params;
 
 /* Observables at the current step (all FP64 sums in a fixed order):
@@ -120,17 +124,21 @@ typedef struct mdpd_system mdpd_system; /* opaque; owned by the library */
 
 /* Create a system and evaluate density and forces at t = 0 with the given
  * velocities and noise step 0.
- *   p       parameters, copied.  box >= 3 r_c per axis, 0 < rd <= rc, dt > 0,
+ *   p       parameters, copied.  box >= 2 r_c per axis, 0 < rd <= rc, dt > 0,
  *           mass > 0, kT >= 0, symmetric tables with B, gamma >= 0.
- *   n       number of particles, 0 <= n < 2^30 (n = 0 gives an empty system)
+ *   n       number of particles, 0 <= n < 2^30 (n = 0 gives an empty system;
+ *           the list entries keep 30 bits of slot, far above what one GPU's
+ *           memory holds at about 700 bytes per particle)
  *   pos     n x 3 positions, each coordinate in [-L, 2L); wrapped into [0, L)
  *   vel     n x 3 velocities (ignored for frozen particles, which get 0)
  *   type    n type indices in [0, ntypes)
  *   frozen  n flags, nonzero = frozen wall particle (never moves)
  *   stream  hipStream_t to enqueue on (NULL: default stream)
  *   out     receives the handle; *out is NULL on error.
- * Errors: MDPD_E_INVALID (arguments), MDPD_E_UNSUPPORTED (box < 3 r_c),
- * MDPD_E_OOM, MDPD_E_HIP. */
+ * Errors: MDPD_E_INVALID (arguments, a box edge below 2 r_c),
+ * MDPD_E_UNSUPPORTED (more than 2^24 cells), MDPD_E_OOM, MDPD_E_HIP,
+ * MDPD_E_NONFINITE (the evaluation at t = 0 gives a non-finite or out-of-box
+ * predicted state). */
 mdpd_status mdpd_create(const mdpd_params *p, int64_t n, const double *pos, const double *vel,
                         const int32_t *type, const uint8_t *frozen, int32_t mem_kind,
                         void *stream, mdpd_system **out);
@@ -196,6 +204,11 @@ mdpd_status mdpd_read_stress(mdpd_system *s, int32_t first, int32_t count, doubl
  * overlap on one GPU (other threads, other streams) race. */
 mdpd_status mdpd_read_stress_noalloc(mdpd_system *s, int32_t first, int32_t count, double *out,
                                      int32_t mem_kind);
+
+/* Number of list builds since creation, summed over the replicas (a build
+ * re-sorts a replica into cells of edge >= r_c + skin and rebuilds its skin
+ * list; the first evaluation builds every replica once).  builds: host. */
+mdpd_status mdpd_read_list_builds(mdpd_system *s, int64_t *builds);
 
 /* Profile of fluid particles in nbins (1..4096) equal bins of L_axis along
  * axis (0..2).  quantity 0: number density; 1..3: mean velocity x, y, z;

@@ -12,7 +12,8 @@ from ._native import (FP32_FORCES, FP64, KERNELS, MEM_DEVICE, MEM_HOST, WALL_BVF
                       mdpd_debug_forces, mdpd_debug_neighbors, mdpd_destroy, mdpd_forward_record,
                       mdpd_get_state,
                       mdpd_last_error, mdpd_load_checkpoint, mdpd_read_kernel_timing,
-                      mdpd_read_observables, mdpd_read_profile, mdpd_read_replica_observables,
+                      mdpd_read_list_builds, mdpd_read_observables, mdpd_read_profile,
+                      mdpd_read_replica_observables,
                       mdpd_read_stress, mdpd_read_stress_noalloc,
                       mdpd_save_checkpoint,
                       mdpd_set_graph, mdpd_set_kernel_timing, mdpd_set_lanes, mdpd_step)
@@ -23,7 +24,8 @@ __all__ = ["FP32_FORCES", "FP64", "KERNELS", "MEM_DEVICE", "MEM_HOST", "WALL_BVF
            "mdpd_debug_forces", "mdpd_debug_neighbors", "mdpd_destroy", "mdpd_forward_record",
            "mdpd_get_state",
            "mdpd_last_error", "mdpd_load_checkpoint", "mdpd_read_kernel_timing",
-           "mdpd_read_observables", "mdpd_read_profile", "mdpd_read_replica_observables",
+           "mdpd_read_list_builds", "mdpd_read_observables", "mdpd_read_profile",
+           "mdpd_read_replica_observables",
            "mdpd_read_stress", "mdpd_read_stress_noalloc",
            "mdpd_save_checkpoint",
            "mdpd_set_graph", "mdpd_set_kernel_timing", "mdpd_set_lanes", "mdpd_step"]

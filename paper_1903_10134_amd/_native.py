@@ -45,6 +45,7 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("wall_model", ctypes.c_int32),
         ("wall_slip", ctypes.c_double),
+        ("skin", ctypes.c_double),
     ]
 
 
@@ -74,6 +75,7 @@ _SIGS = {
     "mdpd_read_stress_noalloc": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_int32], ctypes.c_int32),
     "mdpd_read_observables": ([ctypes.c_void_p, ctypes.POINTER(Observables)], ctypes.c_int32),
+    "mdpd_read_list_builds": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "mdpd_read_profile": ([ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                            ctypes.c_void_p], ctypes.c_int32),
     "mdpd_get_state": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -135,9 +137,13 @@ def _is_torch(a) -> bool:
     return type(a).__module__.startswith("torch")
 
 
+DEFAULT_SKIN = 0.0  # neighbour-list skin in units of r_c (0: the pair list is built every step)
+
+
 def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=(0.0, 0.0, 0.0),
-                seed=0, wall_model=0, phi_c=0.5, precision=FP64, wall_slip=0.0) -> Params:
-    """Parameter block; A, B, gamma are scalars or T x T tables."""
+                seed=0, wall_model=0, phi_c=0.5, precision=FP64, wall_slip=0.0, skin=None) -> Params:
+    """Parameter block; A, B, gamma are scalars or T x T tables; skin defaults
+    to DEFAULT_SKIN r_c."""
     A = np.atleast_2d(np.asarray(A, dtype=np.float64))
     B = np.atleast_2d(np.asarray(B, dtype=np.float64))
     G = np.atleast_2d(np.asarray(gamma, dtype=np.float64))
@@ -159,6 +165,7 @@ def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=
     p.precision = int(precision)
     p.wall_model = int(wall_model)
     p.wall_slip = float(wall_slip)
+    p.skin = float(DEFAULT_SKIN * rc if skin is None else skin)
     return p
 
 
@@ -226,6 +233,13 @@ def _obs_dict(o) -> dict:
     d = {k: getattr(o, k) for k, _ in Observables._fields_ if k != "momentum"}
     d["momentum"] = tuple(o.momentum)
     return d
+
+
+def mdpd_read_list_builds(h) -> int:
+    """List builds since creation, summed over the replicas."""
+    b = ctypes.c_int64(0)
+    _check(lib().mdpd_read_list_builds(h, ctypes.byref(b)))
+    return int(b.value)
 
 
 def mdpd_read_observables(h) -> dict:
@@ -400,9 +414,9 @@ class System:
     """Owning wrapper around one mdpd_system handle."""
 
     def __init__(self, workload=None, precision=FP64, stream=None, device_inputs=False, params=None,
-                 x=None, v=None, types=None, frozen=None):
+                 x=None, v=None, types=None, frozen=None, skin=None):
         if workload is not None:
-            params = make_params(**workload.param_kwargs(), precision=precision)
+            params = make_params(**workload.param_kwargs(), precision=precision, skin=skin)
             x, v, types, frozen = workload.x, workload.v, workload.types, workload.frozen
         self.params = params
         self.n = int(np.asarray(x).shape[0]) if not _is_torch(x) else int(x.shape[0])
@@ -418,6 +432,9 @@ class System:
 
     def step(self, nsteps: int = 1):
         mdpd_step(self.h, nsteps)
+
+    def list_builds(self) -> int:
+        return mdpd_read_list_builds(self.h)
 
     def observables(self) -> dict:
         return mdpd_read_observables(self.h)
@@ -473,8 +490,8 @@ class System:
 class Batch:
     """Owning wrapper around a batch of replicas (mdpd_create_batch)."""
 
-    def __init__(self, workloads, precision=FP64, stream=None, device_inputs=False):
-        self.params = [make_params(**w.param_kwargs(), precision=precision) for w in workloads]
+    def __init__(self, workloads, precision=FP64, stream=None, device_inputs=False, skin=None):
+        self.params = [make_params(**w.param_kwargs(), precision=precision, skin=skin) for w in workloads]
         self.sizes = [int(w.x.shape[0]) for w in workloads]
         self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
         x = np.concatenate([w.x for w in workloads]) if workloads else np.zeros((0, 3))

@@ -67,7 +67,6 @@ struct AdjRec {
     uint64_t tape_bytes = 0;
     int ntape = 0;
     Soa3 X{}, U{}, fb{}, Xo{}, Uo{};  // Xo, Uo: the step-back targets, swapped with X, U each step
-    int *dmap = nullptr;  // walls: the two sort permutations of a recomputed step (2 n)
     double *rhoA = nullptr, *gp = nullptr, *gpart = nullptr, *gtot = nullptr, *loss = nullptr;
     AdjConst *act = nullptr;  // 4 tables of nrep entries: seeded, unseeded, final, creation
     std::vector<AdjConst> host_act;  // host copy (kept alive while the upload may read it)
@@ -86,6 +85,7 @@ struct mdpd_system {
     bool slip = false;  // walls reflect with wall_slip > 0 in some replica
     uint8_t *corr_byid = nullptr;  // adjoint recording: the step's wall events by particle id
     int *perm_out = nullptr;       // adjoint recording: where the step's sorts move each slot
+    int *perm_tmp = nullptr;       // walls: the two sorts of a recorded step (2 n), composed into perm_out
     int lanes[3] = {4, 4, 4};  // neighbour list (unused), density (and phi), force: best at 1M particles
     // replicas (a single system is one replica)
     int nrep = 1;
@@ -98,14 +98,27 @@ struct mdpd_system {
     int cur = 0;
     int64_t step = 0;
 
-    Soa3 xs[2]{}, vh[2]{}, xpred{}, vpred{}, v{}, F{}, xprev{};
+    // State in the sorted order of the last list build: xs[cur], vh[cur] are
+    // x(t) and the half-step velocity of the current step; the force pass
+    // writes the next ones to xs[1 - cur], vh[1 - cur] (the buffers swap
+    // every step).  tag[0], typ[0] are the tags and types; tag[1], typ[1],
+    // tx, tv, tp the temporaries of a re-sort.
+    Soa3 xs[2]{}, vh[2]{}, tx{}, tv{}, v{}, F{}, tp{};
+    Soa3 xb{};  // positions at the last list build
     uint32_t *tag[2]{};
     uint8_t *typ[2]{};
     void *rho = nullptr;
-    int *key = nullptr, *slot = nullptr, *counts = nullptr, *cstart = nullptr, *bsum = nullptr;
-    int *ncnt = nullptr;
+    int *key = nullptr, *slot = nullptr, *counts = nullptr, *cstart = nullptr, *cnew = nullptr, *bsum = nullptr;
+    int *ncnt = nullptr;    // pair list of the current positions (counts)
     uint32_t *nl = nullptr;
-    void *nlr2 = nullptr;
+    int *scnt = nullptr;    // skin list of the last build (counts)
+    uint32_t *sl = nullptr;
+    bool perstep = false;   // every replica has skin 0: the pair list is built every step, with the
+    void *nlr2 = nullptr;   // r^2 of its near entries (FP32 or FP64 as rho)
+    float *bmax = nullptr;  // force-pass block maxima of the squared displacement since the build
+    int *flags = nullptr;   // [nrep + 1] rebuild flags of the current step, then [nrep + 1]: done
+                            // counter of the gate, [nrep + 2]: forced rebuild
+    unsigned long long *nbuild = nullptr;  // replicas rebuilt since creation
     uint32_t *tmpid = nullptr;
     PartRec *rec = nullptr;  // packed neighbour records of the current step
     double *fpart = nullptr;
@@ -171,14 +184,13 @@ struct mdpd_system {
         const int cur0 = cur;
         st = cap_st;
         timing = false;
+        const int64_t step0 = step;
         e = hipStreamBeginCapture(cap_st, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            for (int k = 0; k < 2; ++k) {
-                sort_predicted();
-                evaluate(0, 0);
-            }
+            advance(2);
             e = hipStreamEndCapture(cap_st, &graph);
         }
+        step = step0;
         st = user;
         timing = tm;
         if (e == hipSuccess && cur != cur0) e = hipErrorInvalidValue;  // cannot happen: buffers alternate
@@ -259,61 +271,126 @@ struct mdpd_system {
         pl.used += 2;
     }
 
-    Soa3c xprev_view() const { return walls ? cview(xprev) : Soa3c{nullptr, nullptr, nullptr}; }
-
-    // Sort predicted state (xpred, vpred, tag[cur], typ[cur]) into the other
-    // buffer set; with walls also carry x(t) from xs[cur] into xprev.
-    void sort_predicted()
+    // The step's gate, then the re-sort and skin list of the replicas that
+    // moved too far (every launch checks the gate's flags on the device).
+    // With walls the previous positions xs[1 - cur] ride along the sort.
+    void gate_and_rebuild()
     {
-        const int o = 1 - cur;
+        const Soa3 none{nullptr, nullptr, nullptr};
+        int *dmap = perm_out && walls ? perm_tmp : perm_out;
+        if (!perstep || n == 0)
+            launch_gate(st, R, force_lanes_used, bmax, flags + nrep + 2, flags, flags + nrep + 1, dstep, ovf, nbuild,
+                        true);
+        if (!perstep) {
+            rebuild(walls ? xs[1 - cur] : none, walls ? tp : none, dmap);
+            return;
+        }
+        // skin 0: every replica rebuilds every step (no gate: the sort does
+        // its bookkeeping), so the sort moves the predicted state (tx, tv)
+        // straight into xs[cur], vh[cur], and x(t) from xs[1 - cur] into tp;
+        // the tag and type buffers swap
         tic(0);
-        launch_sort(st, n, R, cview(xpred), cview(vpred), walls ? cview(xs[cur]) : Soa3c{nullptr, nullptr, nullptr},
-                    tag[cur], typ[cur], xs[o], vh[o], xprev, tag[o], typ[o], key, slot, tmpid, counts,
-                    cstart, bsum, nullptr, ovf, dstep, perm_out ? (walls ? adj.dmap : perm_out) : nullptr);
+        launch_rebuild_sort(st, n, R, tx, tv, walls ? xs[1 - cur] : none, tag[0], typ[0], xs[cur], vh[cur],
+                            walls ? tp : none, tag[1], typ[1], none, key, slot, tmpid, counts, cnew, cstart, bsum,
+                            dmap, false, n > 0 ? dstep : nullptr, ovf, nbuild);
+        std::swap(tag[0], tag[1]);
+        std::swap(typ[0], typ[1]);
         toc(0);
-        cur = o;
+        tic(1);
+        launch_nlist(st, fp32, R, cview(xs[cur]), cstart, ncnt, nl, nlr2, true);
+        toc(1);
     }
+
+    // Where the force pass writes the next state, and where x(t) is during
+    // a step (skin 0: the predicted state lives in tx, tv, and the sort puts
+    // x(t) in tp).
+    Soa3 next_x() const { return perstep ? tx : xs[1 - cur]; }
+    Soa3 next_v() const { return perstep ? tv : vh[1 - cur]; }
+    Soa3 prev_x() const { return perstep ? tp : xs[1 - cur]; }
+
+    // The re-sort and the list of the replicas the last gate flagged: the
+    // skin list, or with skin 0 the pair list itself.
+    void rebuild(Soa3 xprev, Soa3 tprev, int *dmap)
+    {
+        tic(0);
+        launch_rebuild_sort(st, n, R, xs[cur], vh[cur], xprev, tag[0], typ[0], tx, tv, tprev, tag[1], typ[1],
+                            perstep ? Soa3{nullptr, nullptr, nullptr} : xb, key, slot, tmpid, counts, cnew, cstart,
+                            bsum, dmap, true);
+        toc(0);
+        tic(1);
+        if (perstep)
+            launch_nlist(st, fp32, R, cview(xs[cur]), cstart, ncnt, nl, nlr2, false);
+        else
+            launch_skin_build(st, R, false, cview(xs[cur]), cstart, scnt, sl);
+        toc(1);
+    }
+
+    // The build positions as the passes see them (none with skin 0: every
+    // step rebuilds, nothing needs the displacement).
+    Soa3c xbuild() const { return perstep ? Soa3c{nullptr, nullptr, nullptr} : cview(xb); }
+
+    // Pair list (ncnt_out, nl_out) of the current positions from the lists
+    // of the last build.
+    void pair_list(int *ncnt_out, uint32_t *nl_out)
+    {
+        if (perstep)
+            launch_nlist(st, fp32, R, cview(xs[cur]), cstart, ncnt_out, nl_out, nlr2, true);
+        else {
+            launch_skin_build(st, R, true, cview(xb), cstart, scnt, sl);
+            launch_density(st, lanes[1], fp32, R, cview(xs[cur]), cview(vh[cur]), tag[0], typ[0], cstart, scnt, sl,
+                           ncnt_out, nl_out, nullptr, nullptr);
+        }
+    }
+
+    // The lists of the current state after it was restored from a
+    // checkpoint: the skin list again from the build positions (the same
+    // positions and cells give the same list), then the pair list at the
+    // current positions (the densities are restored with the state); with
+    // skin 0 the pair list from the positions and their cells.
+    void restore_lists() { pair_list(ncnt, nl); }
 
     // Advance without synchronising (the caller checks the status word).
     void advance(int64_t nsteps)
     {
         for (int64_t k = 0; k < nsteps; ++k) {
             step += 1;
-            sort_predicted();
-            evaluate((uint32_t)step, 0);
+            cur = 1 - cur;
+            gate_and_rebuild();
+            evaluate(0);
         }
     }
 
-    void evaluate(uint32_t stepno, int initial)
+    void evaluate(int initial)
     {
         if (walls && !initial) {
-            // phi at the predicted positions and the corrector, then re-sort
-            // only if a particle was moved back (gated on the device)
+            // phi at the predicted positions and the corrector: a flagged
+            // particle goes back to x(t) = xs[1 - cur]; one that then lies
+            // half the skin or more from its build position (possible right
+            // after a build, for a particle faster than skin / 2 dt) makes a
+            // second gate re-sort its replica and rebuild the skin list
             launch_zero_int(st, corr, 1);
             tic(4);
-            launch_phi(st, lanes[1], slip, n, R, cview(xs[cur]), cview(xprev), xs[cur], vh[cur], tag[cur], cstart, wmask,
-                       corr, ncorr_total, corr_byid);
+            launch_phi(st, lanes[1], slip, n, R, cview(xs[cur]), cview(prev_x()), xs[cur], vh[cur], tag[0],
+                       cstart, wmask, corr, ncorr_total, corr_byid, xbuild(), bmax);
             toc(4);
-            const int o = 1 - cur;
-            tic(0);
-            launch_sort(st, n, R, cview(xs[cur]), cview(vh[cur]), Soa3c{nullptr, nullptr, nullptr}, tag[cur],
-                        typ[cur], xs[o], vh[o], Soa3{nullptr, nullptr, nullptr}, tag[o], typ[o], key, slot,
-                        tmpid, counts, cstart, bsum, corr, nullptr, nullptr, perm_out ? adj.dmap + n : nullptr);
-            toc(0);
-            cur = o;
+            launch_gate(st, R, 1, bmax, flags + nrep + 2, flags, flags + nrep + 1, dstep, ovf, nbuild, false);
+            const Soa3 none{nullptr, nullptr, nullptr};
+            rebuild(none, none, perm_out ? perm_tmp + n : nullptr);
+            if (perm_out) launch_compose(st, n, perm_tmp, perm_tmp + n, perm_out);
         }
-        tic(1);
-        launch_nlist(st, fp32, R, cview(xs[cur]), cstart, ncnt, nl, nlr2, nullptr);
-        toc(1);
         tic(2);
-        launch_density(st, lanes[1], fp32, R, cview(xs[cur]), cview(vh[cur]), tag[cur], typ[cur], cstart, ncnt,
-                       nlr2, rho, rec);
+        if (perstep)
+            launch_density_list(st, lanes[1], fp32, R, cview(xs[cur]), cview(vh[cur]), tag[0], typ[0], cstart, ncnt,
+                                nlr2, rho, rec);
+        else
+            launch_density(st, lanes[1], fp32, R, cview(xs[cur]), cview(vh[cur]), tag[0], typ[0], cstart, scnt, sl,
+                           ncnt, nl, rho, rec);
         toc(2);
         force_lanes_used = lanes[2];
         tic(3);
-        (void)stepno;  // the device word dstep holds it
-        launch_force(st, lanes[2], fp32, mt, R, dstep, cview(xs[cur]), cview(vh[cur]), rho, tag[cur], typ[cur],
-                     rec, cstart, ncnt, nl, v, F, vpred, xpred, fpart, status, ovf, ovf + 1, ovf_ve, initial);
+        launch_force(st, lanes[2], fp32, mt, R, dstep, cview(xs[cur]), cview(vh[cur]), rho, tag[0], typ[0], rec,
+                     cstart, ncnt, nl, v, F, next_v(), next_x(), fpart, status, ovf, ovf + 1, ovf_ve, initial,
+                     xbuild(), perstep ? nullptr : bmax);
         toc(3);
     }
 };
@@ -355,28 +432,35 @@ mdpd_status validate(const mdpd_params *p, int64_t n)
             if (p->B[ab] < 0.0 || p->gamma[ab] < 0.0) return fail(MDPD_E_INVALID, "need B, gamma >= 0");
         }
     for (int a = 0; a < 3; ++a)
-        if (!(p->box[a] > 0.0)) return fail(MDPD_E_INVALID, "box edges must be positive");
+        if (!(p->box[a] >= 2.0 * p->rc))
+            return fail(MDPD_E_INVALID, "box edge %g is shorter than 2 r_c = %g", p->box[a], 2.0 * p->rc);
+    if (!(p->skin >= 0.0) || !finite(p->skin) || p->skin > 4.0 * p->rc)
+        return fail(MDPD_E_INVALID, "need 0 <= skin <= 4 r_c (skin = %g)", p->skin);
     return MDPD_OK;
 }
 
-// Cells per axis: the largest nc >= 3 whose edge L/nc is at least r_c with a
-// relative margin of 1e-12 over rounding, or exactly r_c when binning is
-// exact (nc/L a power of two, so x * nc/L is computed without rounding).
+// Cells per axis: the largest nc >= 1 whose edge L/nc is at least
+// r_c + skin with a relative margin of 1e-12 over rounding, or exactly that
+// when binning is exact (nc/L a power of two, so x * nc/L is computed without
+// rounding); one cell when even that does not fit (the cell then holds every
+// candidate along the axis).  The skin list is built with the test
+// r^2 < (r_c + skin)^2 (1 + 1e-9) and rebuilt once a particle has moved
+// skin/2 (1 - 1e-6) or more, both on the safe side of rounding.
 mdpd_status make_geom(const mdpd_params *p, Geom *g)
 {
     long long total = 1;
+    const double rs = p->rc + p->skin;
     for (int a = 0; a < 3; ++a) {
         const double L = p->box[a];
-        int nc = (int)floor(L / p->rc);
-        while (nc >= 3) {
+        int nc = (int)floor(L / rs);
+        while (nc >= 1) {
             const double cs = L / nc, s = nc / L;
             int e;
             const bool pow2 = frexp(s, &e) == 0.5;
-            if (cs >= p->rc * (1.0 + 1e-12) || (pow2 && cs >= p->rc && L * s == (double)nc)) break;
+            if (cs >= rs * (1.0 + 1e-12) || (pow2 && cs >= rs && L * s == (double)nc)) break;
             --nc;
         }
-        if (nc < 3)
-            return fail(MDPD_E_UNSUPPORTED, "box edge %g holds fewer than 3 cells of r_c = %g", L, p->rc);
+        if (nc < 1) nc = 1;
         g->L[a] = L;
         g->nc[a] = nc;
         g->s[a] = nc / L;
@@ -390,6 +474,9 @@ mdpd_status make_geom(const mdpd_params *p, Geom *g)
     g->rc = p->rc;
     g->rc2 = p->rc * p->rc;
     g->rd2 = p->rd * p->rd;
+    g->rs2 = rs * rs * (1.0 + 1e-9);
+    g->slack = 0.5 * p->skin;
+    g->gate2 = 0.25 * p->skin * p->skin * (1.0 - 1e-6);
     return MDPD_OK;
 }
 
@@ -491,6 +578,9 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     s->nrep = nrep;
     s->fp32 = ps[0].precision == MDPD_FP32_FORCES;
     s->walls = ps[0].wall_model == MDPD_WALL_BVF;
+    s->perstep = true;
+    for (int r = 0; r < nrep; ++r)
+        if (ps[r].skin > 0.0) s->perstep = false;
     for (int r = 0; r < nrep; ++r)
         if (s->walls && ps[r].wall_slip > 0.0) s->slip = true;
     s->params.assign(ps, ps + nrep);
@@ -521,21 +611,22 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
         }
     }
 
-    // border cells (a periodic image in their 27-cell stencil), replica after
-    // replica in cell order: the list kernel handles them in a launch of their
-    // own.  A small system takes all its cells in that one launch (the second
-    // launch would cost more than it saves).
+    // per-step list: the border cells (a periodic image in their 27-cell
+    // stencil), replica after replica in cell order, have a launch of their
+    // own; a small system takes all its cells in that one launch (the second
+    // launch would cost more than it saves)
     std::vector<int> bcells;
     const bool one_launch = cells <= kOneListLaunchCells;
-    for (int r = 0; r < nrep; ++r) {
-        const int *nc = s->geoms[r].nc;
-        for (int cz = 0; cz < nc[2]; ++cz)
-            for (int cy = 0; cy < nc[1]; ++cy)
-                for (int cx = 0; cx < nc[0]; ++cx)
-                    if (one_launch || cx == 0 || cx == nc[0] - 1 || cy == 0 || cy == nc[1] - 1 || cz == 0 ||
-                        cz == nc[2] - 1)
-                        bcells.push_back(s->cell_off[r] + cx + nc[0] * (cy + nc[1] * cz));
-    }
+    if (s->perstep)
+        for (int r = 0; r < nrep; ++r) {
+            const int *nc = s->geoms[r].nc;
+            for (int cz = 0; cz < nc[2]; ++cz)
+                for (int cy = 0; cy < nc[1]; ++cy)
+                    for (int cx = 0; cx < nc[0]; ++cx)
+                        if (one_launch || cx == 0 || cx == nc[0] - 1 || cy == 0 || cy == nc[1] - 1 || cz == 0 ||
+                            cz == nc[2] - 1)
+                            bcells.push_back(s->cell_off[r] + cx + nc[0] * (cy + nc[1] * cz));
+        }
     const size_t N = (size_t)(n > 0 ? n : 1);
     const int nb_scan = (int)((cells + 4095) / 4096);
     Reps &R = s->R;
@@ -558,11 +649,12 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
         ALLOC(s->alloc(&s->tag[k], N));
         ALLOC(s->alloc(&s->typ[k], N));
     }
-    ALLOC(s->alloc3(&s->xpred, N));
-    ALLOC(s->alloc3(&s->vpred, N));
+    ALLOC(s->alloc3(&s->tx, N));
+    ALLOC(s->alloc3(&s->tv, N));
+    ALLOC(s->alloc3(&s->xb, N));
     ALLOC(s->alloc3(&s->v, N));
     ALLOC(s->alloc3(&s->F, N));
-    if (s->walls) ALLOC(s->alloc3(&s->xprev, N));
+    if (s->walls) ALLOC(s->alloc3(&s->tp, N));
     if (s->walls) {
         // wall mask: 4 sub-cells per cell edge while it stays within 64 MiB
         R.wsub = cells <= ((int64_t)1 << 20) ? 4 : cells <= ((int64_t)1 << 23) ? 2 : 1;
@@ -580,18 +672,25 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     ALLOC(s->alloc(&s->rec, N));
     ALLOC(s->alloc(&s->ncnt, N));
     ALLOC(s->alloc(&s->nl, N * kListCap));
-    {
+    if (s->perstep) {
         double *r2 = nullptr;
         ALLOC(s->alloc(&r2, s->fp32 ? N * kListCap / 2 : N * kListCap));
         s->nlr2 = r2;
+    } else {
+        ALLOC(s->alloc(&s->scnt, N));
+        ALLOC(s->alloc(&s->sl, N * kSkinCap));
     }
+    ALLOC(s->alloc(&s->bmax, (size_t)R.nblk[kLaneCounts - 1] + 1));
+    ALLOC(s->alloc(&s->flags, (size_t)nrep + 3));
+    ALLOC(s->alloc(&s->nbuild, 1));
     ALLOC(s->alloc(&s->counts, (size_t)cells));
     ALLOC(s->alloc(&s->cstart, (size_t)cells + 1));
+    ALLOC(s->alloc(&s->cnew, (size_t)cells + 1));
     ALLOC(s->alloc(&s->bsum, (size_t)nb_scan + 1));
     ALLOC(s->alloc(&s->fpart, 2 * (size_t)(R.nblk[kLaneCounts - 1] + 1)));
     ALLOC(s->alloc(&s->status, 4));
     ALLOC(s->alloc(&s->dstep, 1));
-    ALLOC(s->alloc(&s->corr, N + 1 + (N + kBlock - 1) / kBlock));
+    ALLOC(s->alloc(&s->corr, N + 1 + (size_t)R.nblk[0] + 1));
     ALLOC(s->alloc(&s->ovf, N + 1));
     ALLOC(s->alloc(&s->ovf_ve, 2 * N));
     ALLOC(s->alloc(&s->ncorr_total, 1));
@@ -616,6 +715,7 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     R.cell_off = dcell;
     R.part_off = dpart;
     R.blk_off = dblk;
+    R.flag = s->flags;
     R.bcells = dbcells;
 
     auto bail = [&](mdpd_status st) {
@@ -652,12 +752,16 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     hipError_t e = hipSuccess;
     launch_zero_int(s->st, s->status, 4);
     {
-        // the sort at creation advances it to step 0
+        // the gate at creation advances it to step 0
         static const uint32_t before_first = 0xFFFFFFFFu;
         e = hipMemcpyAsync(s->dstep, &before_first, sizeof before_first, hipMemcpyHostToDevice, s->st);
         if (e != hipSuccess) return bail(fail(MDPD_E_HIP, "step counter init failed: %s", hipGetErrorString(e)));
     }
     launch_zero_int(s->st, (int *)s->ncorr_total, 2);
+    launch_zero_int(s->st, (int *)s->nbuild, 2);
+    launch_zero_int(s->st, (int *)s->bmax, R.nblk[kLaneCounts - 1] + 1);
+    launch_zero_int(s->st, s->flags, nrep + 3);
+    launch_set_int(s->st, s->flags + nrep + 2, 1);  // the first gate builds every replica
     launch_zero_int(s->st, s->counts, (int)cells);
     launch_zero_int(s->st, s->corr, (int)N + 1);
     launch_zero_int(s->st, s->ovf, 1);
@@ -681,7 +785,10 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
         dfz = sfz;
     }
     s->cur = 0;
-    launch_ingest(s->st, R, dpos, dvel, dtype, dfz, s->xpred, s->vpred, s->tag[0], s->typ[0], s->status);
+    // the inputs become the state the first gate sorts: xs[0], vh[0], or
+    // with skin 0 the predicted state tx, tv
+    launch_ingest(s->st, R, dpos, dvel, dtype, dfz, s->perstep ? s->tx : s->xs[0], s->perstep ? s->tv : s->vh[0],
+                  s->tag[0], s->typ[0], s->status);
     int hstatus = 0;
     e = hipMemcpyAsync(&hstatus, s->status, sizeof(int), hipMemcpyDeviceToHost, s->st);
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
@@ -694,14 +801,14 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
         return bail(fail(MDPD_E_INVALID,
                          "input has a non-finite value, a position outside [-L, 2L) or a bad type"));
 
-    // t = 0: sort, density, forces with the given velocities and noise step 0
-    s->sort_predicted();
+    // t = 0: sort, lists, density, forces with the given velocities and noise step 0
+    s->gate_and_rebuild();
     if (s->walls) {
         hipError_t ez = hipMemsetAsync(s->wmask, 0, s->wmask_bytes, s->st);
         if (ez != hipSuccess) return bail(fail(MDPD_E_HIP, "wall mask: %s", hipGetErrorString(ez)));
-        launch_mark_wall_cells(s->st, R, cview(s->xs[s->cur]), s->tag[s->cur], s->wmask);
+        launch_mark_wall_cells(s->st, R, cview(s->xs[s->cur]), s->tag[0], s->wmask);
     }
-    s->evaluate(0, 1);
+    s->evaluate(1);
     e = hipMemcpyAsync(&hstatus, s->status, sizeof(int), hipMemcpyDeviceToHost, s->st);
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
     if (e != hipSuccess) return bail(fail(MDPD_E_HIP, "initial evaluation failed: %s", hipGetErrorString(e)));
@@ -739,6 +846,13 @@ mdpd_status mdpd_step(mdpd_system *s, int64_t nsteps)
     if (nsteps < 0) return fail(MDPD_E_INVALID, "nsteps < 0");
     if (s->use_graph && s->n > 0) {
         while (nsteps >= 2) {
+            if (!s->graph_valid() && s->force_lanes_used != s->lanes[2]) {
+                // the captured gate reads the block maxima of the force pass
+                // in the layout of the graph's own force lanes
+                s->advance(1);
+                nsteps -= 1;
+                continue;
+            }
             if (!s->graph_valid()) HIPCHK(s->capture_pair());
             HIPCHK(hipGraphLaunch(s->gexec, s->st));
             s->step += 2;
@@ -759,8 +873,8 @@ mdpd_status mdpd_read_replica_observables(mdpd_system *s, int32_t first, int32_t
     if (!s || !out) return fail(MDPD_E_INVALID, "NULL argument");
     if (first < 0 || count < 0 || first + count > s->nrep)
         return fail(MDPD_E_INVALID, "replicas [%d, %d) outside [0, %d)", first, first + count, s->nrep);
-    launch_observables(s->st, s->fp32, s->R, s->force_lanes_used, cview(s->v), s->rho, s->tag[s->cur],
-                       s->typ[s->cur], s->fpart, s->ncnt, s->ovf_ve, s->obs_part, s->obs);
+    launch_observables(s->st, s->fp32, s->R, s->force_lanes_used, cview(s->v), s->rho, s->tag[0],
+                       s->typ[0], s->fpart, s->ncnt, s->ovf_ve, s->obs_part, s->obs);
     std::vector<double> h((size_t)16 * (count > 0 ? count : 1));
     unsigned long long tot = 0;
     int last = 0;
@@ -813,8 +927,8 @@ mdpd_status mdpd_read_stress(mdpd_system *s, int32_t first, int32_t count, doubl
     }
     double *sums = s->stress + 6 * (N > 0 ? N : 1);
     launch_zero_int(s->st, (int *)sums, 12 * s->nrep);
-    launch_stress(s->st, s->fp32, s->mt, s->n, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur],
-                  s->typ[s->cur], s->cstart, s->ncnt, s->nl, s->stress, false);
+    launch_stress(s->st, s->fp32, s->mt, s->n, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[0],
+                  s->typ[0], s->cstart, s->ncnt, s->nl, s->stress, false);
     if (N > 0) launch_stress_sum(s->st, s->R, s->n, s->stress, sums);
     std::vector<double> h(6 * (size_t)(count > 0 ? count : 1));
     if (count > 0)
@@ -889,14 +1003,24 @@ mdpd_status mdpd_read_stress_noalloc(mdpd_system *s, int32_t first, int32_t coun
     double *parts = ptr, *res = ptr + 6 * nb;
     // every block writes its partial sums and the reduction writes every
     // result, so nothing left by an earlier call is read
-    launch_stress(s->st, s->fp32, s->mt, s->n, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur],
-                  s->typ[s->cur], s->cstart, s->ncnt, s->nl, parts, true);
+    launch_stress(s->st, s->fp32, s->mt, s->n, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[0],
+                  s->typ[0], s->cstart, s->ncnt, s->nl, parts, true);
     launch_stress_part_sum(s->st, s->R, first, count, parts, mem_kind == MDPD_MEM_DEVICE ? out : res);
     HIPCHK(hipGetLastError());
     if (mem_kind == MDPD_MEM_HOST) {
         HIPCHK(hipMemcpyAsync(out, res, 6 * (size_t)count * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(hipStreamSynchronize(s->st));
     }
+    return MDPD_OK;
+}
+
+mdpd_status mdpd_read_list_builds(mdpd_system *s, int64_t *builds)
+{
+    if (!s || !builds) return fail(MDPD_E_INVALID, "NULL argument");
+    unsigned long long b = 0;
+    HIPCHK(hipMemcpyAsync(&b, s->nbuild, sizeof b, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    *builds = (int64_t)b;
     return MDPD_OK;
 }
 
@@ -918,7 +1042,7 @@ mdpd_status mdpd_read_profile(mdpd_system *s, int32_t axis, int32_t nbins, int32
     double *res = s->work + 9 * nbins;
     if ((size_t)(10 * nbins) > (size_t)9 * 4096) res = s->io;  // large nbins: use staging
     launch_profile(s->st, s->fp32, s->n, axis, nbins, quantity, s->p.box[axis], binvol, s->p.mass,
-                   cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur], s->work, res);
+                   cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[0], s->work, res);
     HIPCHK(hipMemcpyAsync(out, res, nbins * sizeof(double), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
     return MDPD_OK;
@@ -932,18 +1056,18 @@ mdpd_status mdpd_get_state(mdpd_system *s, double *pos, double *vel, double *rho
     const size_t N = (size_t)s->n;
     if (N == 0) return MDPD_OK;
     if (mem_kind == MDPD_MEM_DEVICE) {
-        launch_export(s->st, s->fp32, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur], pos,
+        launch_export(s->st, s->fp32, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[0], pos,
                       vel, rho);
         HIPCHK(hipStreamSynchronize(s->st));
         return MDPD_OK;
     }
-    launch_export(s->st, s->fp32, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur],
+    launch_export(s->st, s->fp32, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[0],
                   pos ? s->io : nullptr, vel ? s->io2 : nullptr, nullptr);
     if (pos) HIPCHK(hipMemcpyAsync(pos, s->io, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s->st));
     if (vel) HIPCHK(hipMemcpyAsync(vel, s->io2, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
     if (rho) {
-        launch_export(s->st, s->fp32, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[s->cur],
+        launch_export(s->st, s->fp32, s->R, cview(s->xs[s->cur]), cview(s->v), s->rho, s->tag[0],
                       nullptr, nullptr, s->io);
         HIPCHK(hipMemcpyAsync(rho, s->io, N * sizeof(double), hipMemcpyDeviceToHost, s->st));
         HIPCHK(hipStreamSynchronize(s->st));
@@ -957,7 +1081,7 @@ mdpd_status mdpd_get_state(mdpd_system *s, double *pos, double *vel, double *rho
 // ckpt_fields(); every field starts on a 256-byte boundary.
 namespace {
 
-constexpr uint64_t kCkptMagic = 0x3150544b4350444dull;  // "MDPDCKPT" + version 1
+constexpr uint64_t kCkptMagic = 0x3250544b4350444dull;  // "MDPDCKP2": version 2 (skin-list state)
 constexpr uint64_t kCkptAlign = 256;
 
 struct CkptHeader {
@@ -980,14 +1104,16 @@ std::vector<CkptField> ckpt_fields(mdpd_system *s)
     const uint64_t N = (uint64_t)s->n;
     const int c = s->cur;
     const uint64_t rb = s->fp32 ? 4 : 8;
+    const uint64_t nb = (uint64_t)s->R.nblk[kLaneCounts - 1];
     return {
-        {s->xs[c].x, 24 * N},          {s->v.x, 24 * N},     {s->F.x, 24 * N},
-        {s->xpred.x, 24 * N},          {s->vpred.x, 24 * N}, {s->rho, rb * N},
-        {s->tag[c], 4 * N},            {s->typ[c], N},       {s->ovf_ve, 16 * N},
+        {s->xs[c].x, 24 * N},          {s->v.x, 24 * N},         {s->F.x, 24 * N},
+        {s->next_x().x, 24 * N},       {s->next_v().x, 24 * N},  {s->rho, rb * N},
+        {s->tag[0], 4 * N},            {s->typ[0], N},           {s->ovf_ve, 16 * N},
         {s->cstart, 4 * ((uint64_t)s->R.ncells + 1)},
-        {s->fpart, 16 * (uint64_t)s->R.nblk[kLaneCounts - 1]},
+        {s->fpart, 16 * nb},
         {s->ncorr_total, 8},           {s->corr, 4},
         {s->dstep, 4},
+        {s->xb.x, s->perstep ? 0 : 24 * N}, {s->bmax, 4 * nb},   {s->nbuild, 8},
     };
 }
 
@@ -1091,12 +1217,12 @@ mdpd_status mdpd_load_checkpoint(mdpd_system *s, const void *buf, uint64_t bytes
     s->force_lanes_used = (int)h.force_lanes;
     s->step = h.step;
     HIPCHK(state_copy(s, const_cast<char *>(in) + head_bytes(s), false, dk));
+    launch_zero_int(s->st, s->status, 1);  // the loaded state's own status starts clean
     if (s->walls) {  // the wall mask follows the frozen particles of the loaded state
         HIPCHK(hipMemsetAsync(s->wmask, 0, s->wmask_bytes, s->st));
-        launch_mark_wall_cells(s->st, s->R, cview(s->xs[s->cur]), s->tag[s->cur], s->wmask);
+        launch_mark_wall_cells(s->st, s->R, cview(s->xs[s->cur]), s->tag[0], s->wmask);
     }
-    // the neighbour list is a function of the positions and the cell list
-    launch_nlist(s->st, s->fp32, s->R, cview(s->xs[s->cur]), s->cstart, s->ncnt, s->nl, s->nlr2, nullptr);
+    s->restore_lists();
     HIPCHK(hipStreamSynchronize(s->st));
     HIPCHK(hipGetLastError());
     return MDPD_OK;
@@ -1107,7 +1233,7 @@ mdpd_status mdpd_debug_forces(mdpd_system *s, double *force)
     if (!s || !force) return fail(MDPD_E_INVALID, "NULL argument");
     const size_t N = (size_t)s->n;
     if (N == 0) return MDPD_OK;
-    launch_export(s->st, false, s->R, cview(s->F), Soa3c{nullptr, nullptr, nullptr}, nullptr, s->tag[s->cur],
+    launch_export(s->st, false, s->R, cview(s->F), Soa3c{nullptr, nullptr, nullptr}, nullptr, s->tag[0],
                   s->io, nullptr, nullptr);
     HIPCHK(hipMemcpyAsync(force, s->io, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
@@ -1123,7 +1249,7 @@ mdpd_status mdpd_debug_neighbors(mdpd_system *s, double cutoff, int64_t *count, 
     if (N == 0) return MDPD_OK;
     int64_t *dc = (int64_t *)s->io;
     uint64_t *dh = (uint64_t *)s->io2;
-    launch_debug_neighbors(s->st, s->R, cutoff * cutoff, cview(s->xs[s->cur]), s->tag[s->cur], s->cstart,
+    launch_debug_neighbors(s->st, s->R, cutoff * cutoff, cview(s->xs[s->cur]), s->tag[0], s->cstart,
                            s->ncnt, s->nl, dc, dh);
     HIPCHK(hipMemcpyAsync(count, dc, N * sizeof(int64_t), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipMemcpyAsync(hash, dh, N * sizeof(uint64_t), hipMemcpyDeviceToHost, s->st));
@@ -1255,7 +1381,7 @@ mdpd_status mdpd_autotune(mdpd_system *s, int32_t steps, int32_t *lanes_out)
     s->force_lanes_used = lanes_used0;
     HIPCHK(state_copy(s, save, false, hipMemcpyDeviceToDevice));
     launch_zero_int(s->st, s->status, 1);
-    launch_nlist(s->st, s->fp32, s->R, cview(s->xs[s->cur]), s->cstart, s->ncnt, s->nl, s->nlr2, nullptr);
+    s->restore_lists();
     HIPCHK(hipStreamSynchronize(s->st));
     s->release(save);
     if (err) return err;
@@ -1348,11 +1474,11 @@ struct ListRedirect {
     }
 };
 
-// Builds the neighbour list of tape entry k from its positions.
+// The lists of the restored state, its pair list written to tape entry k.
 void tape_list(mdpd_system *s, int k)
 {
     const TapeEntry e = tape_entry(s, k);
-    launch_nlist(s->st, s->fp32, s->R, cview(e.x), e.cstart, e.ncnt, e.nl, s->nlr2, nullptr);
+    s->pair_list(e.ncnt, e.nl);
 }
 
 // Copy the current state into tape entry k; u is the half-step velocity the
@@ -1371,8 +1497,8 @@ hipError_t tape_record(mdpd_system *s, int k, bool creation)
     cp(e.u.x, creation ? s->v.x : s->vh[c].x, 24 * N);
     cp(e.v.x, s->v.x, 24 * N);
     cp(e.rho, s->rho, (s->fp32 ? 4 : 8) * N);
-    cp(e.tag, s->tag[c], 4 * N);
-    cp(e.typ, s->typ[c], N);
+    cp(e.tag, s->tag[0], 4 * N);
+    cp(e.typ, s->typ[0], N);
     cp(e.cstart, s->cstart, 4 * ((size_t)s->R.ncells + 1));
     return r;
 }
@@ -1497,7 +1623,7 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
         for (Soa3 *q : v3)
             if ((rc = s->alloc3(q, N))) return rc;
         if ((rc = s->alloc(&a.rhoA, N))) return rc;
-        if (s->walls && (rc = s->alloc(&a.dmap, 2 * N))) return rc;
+        if (s->walls && (rc = s->alloc(&s->perm_tmp, 2 * N))) return rc;
         if ((rc = s->alloc(&a.gtot, 3 * 64 * nrep))) return rc;
         if ((rc = s->alloc(&a.loss, 3 * nrep + 1))) return rc;
         if ((rc = s->alloc(&a.act, 4 * nrep))) return rc;
@@ -1521,8 +1647,8 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
     auto accum = [&](int64_t n) {
         const double sw = seed_weight(a, n);
         if (sw == 0.0) return;
-        launch_observables(s->st, s->fp32, s->R, s->force_lanes_used, cview(s->v), s->rho, s->tag[s->cur],
-                           s->typ[s->cur], s->fpart, s->ncnt, s->ovf_ve, s->obs_part, s->obs);
+        launch_observables(s->st, s->fp32, s->R, s->force_lanes_used, cview(s->v), s->rho, s->tag[0],
+                           s->typ[0], s->fpart, s->ncnt, s->ovf_ve, s->obs_part, s->obs);
         launch_loss_accum(s->st, s->nrep, s->obs, a.lct, a.loss, sw);
     };
     HIPCHK(ckpt_store(s, 0));
@@ -1595,9 +1721,8 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
                     launch_zero_int(s->st, (int *)e.corr, (int)((N + 3) / 4));
                     s->corr_byid = e.corr;
                 }
-                s->perm_out = e.perm;  // where the step's sorts move each slot
+                s->perm_out = e.perm;  // where the step's sort moves each slot
                 s->advance(1);
-                if (s->walls) launch_compose(s->st, (int)N, a.dmap, a.dmap + N, e.perm);
                 HIPCHK(tape_record(s, m, false));
             }
         }
@@ -1642,7 +1767,7 @@ mdpd_status mdpd_backward(mdpd_system *s, const double *w, double *dA, double *d
     }
     // back to the state at the end of the recording
     HIPCHK(ckpt_restore(s, K, a.nsteps));
-    launch_nlist(s->st, s->fp32, s->R, cview(s->xs[s->cur]), s->cstart, s->ncnt, s->nl, s->nlr2, nullptr);
+    s->restore_lists();
     HIPCHK(hipStreamSynchronize(s->st));
     HIPCHK(hipGetLastError());
     return MDPD_OK;

@@ -2,17 +2,20 @@
 //
 // Data layout in device memory (all arrays indexed by the current sorted
 // slot k, particles ordered by cell, x fastest, then y, then z, and by
-// particle id inside a cell):
+// particle id inside a cell, as of the last list build):
 //   positions, velocities, forces : three FP64 planes (SoA), x | y | z
 //   tag                           : uint32, particle id in bits 0..30,
 //                                   bit 31 set for frozen wall particles
 //   type                          : uint8
 //   rho                           : FP64 (FP64 form) or FP32 (FP32 form)
-//   neighbour list                : kListCap entries per particle, particle-major:
-//                                   u32 slot of the neighbour (bits 0..30) with
-//                                   bit 31 set when r < r_d, a parallel array of
-//                                   the pair's r^2 (FP32 or FP64 as rho), and a
-//                                   count per particle
+//   skin list                     : kSkinCap entries per particle, particle-major:
+//                                   u32 slot of every neighbour closer than
+//                                   r_c + skin at the last build, with a
+//                                   flag for pairs that may need the minimum
+//                                   image, and a count per particle
+//   pair list                     : kListCap entries per particle: the skin
+//                                   entries closer than r_c at the current
+//                                   positions (flag for r < r_d), and a count
 //   cell_start                    : ncells + 1 offsets into the sorted order
 #pragma once
 
@@ -21,8 +24,9 @@
 
 namespace mdpd {
 
-constexpr int kListCap = 64;   // neighbour-list slots per particle
-constexpr int kOneListLaunchCells = 8192;  // up to this many cells the list is one launch
+constexpr int kListCap = 64;    // pair-list slots per particle
+constexpr int kSkinCap = 128;   // skin-list slots per particle
+constexpr int kOneListLaunchCells = 8192;  // per-step list: up to this many cells it is one launch
 static_assert((kListCap & (kListCap - 1)) == 0, "far-buffer positions wrap with a mask");
 constexpr int kBlock = 256;    // threads per block of the particle kernels
 constexpr uint32_t kFrozenBit = 0x80000000u;
@@ -48,7 +52,10 @@ struct alignas(16) PartRec {
 };
 static_assert(sizeof(PartRec) == 64, "PartRec must be one 64-byte sector");
 
-// Cell lattice: nc[a] cells of edge L[a]/nc[a] >= r_c per axis.
+// Cell lattice: nc[a] cells of edge L[a]/nc[a] >= r_c + skin per axis.
+// The cells and the skin list are built together; until the next build a
+// particle moves less than half the skin (slack), so a cell scan stays
+// complete when its clipping allows for that slack.
 struct Geom {
     double L[3];
     double s[3];   // cells per unit length, nc / L
@@ -58,6 +65,9 @@ struct Geom {
     int nc[3];
     int ncells;
     double rc, rc2, rd2;
+    double rs2;    // squared cutoff of the skin-list build, (r_c + skin)^2 (1 + 1e-9)
+    double gate2;  // a squared displacement since the build at or above this forces a rebuild
+    double slack;  // half the skin: the most a particle moves between builds
 };
 
 // Scalars of one pair pass (one launch).
@@ -93,11 +103,12 @@ struct Reps {
     const int *cell_off;    // [nrep + 1]
     const int *part_off;    // [nrep + 1]
     const int *blk_off;     // [kLaneCounts][nrep + 1]
-    const int *bcells;      // [nbcells] global indices of the border cells (a periodic image in the stencil)
+    const int *flag;        // [nrep + 1]: 1 = replica r rebuilds its lists this step; [nrep]: any does
+    const int *bcells;      // [nbcells] per-step list: global indices of the border cells (a periodic image in the stencil)
     int nrep;
     int ncells;             // total cells
     int nbcells;
-    int list_interior;      // 1: interior cells have a list launch of their own; 0: bcells holds every cell
+    int list_interior;      // per-step list: 1 = interior cells have a launch of their own; 0 = bcells holds every cell
     int wsub;               // wall mask: sub-cells per cell edge (walls on)
     int nblk[kLaneCounts];  // total blocks per lane count
 };
@@ -253,20 +264,57 @@ struct LossConst {
 void launch_ingest(hipStream_t st, const Reps &R, const double *pos, const double *vel,
                    const int32_t *type, const uint8_t *frozen, Soa3 xp, Soa3 vp, uint32_t *tag,
                    uint8_t *typ, int *status);
-void launch_sort(hipStream_t st, int n, const Reps &R, Soa3c xin, Soa3c vin, Soa3c xprev_in,
-                 const uint32_t *tag_in, const uint8_t *typ_in, Soa3 xout, Soa3 vout,
-                 Soa3 xprev_out, uint32_t *tag_out, uint8_t *typ_out, int *key, int *slot,
-                 uint32_t *tmpid, int *counts, int *cstart, int *bsum, const int *gate,
-                 int *ovf_count, uint32_t *step_ctr, int *dmap);
-// dmap (nullable, launch_sort): dmap[i] = the slot particle i (input order)
-// moves to.  launch_compose: out[i] = b[a[i]].
+// The list gate of one step: for each replica, the largest squared
+// displacement since its last list build (block maxima written by the force
+// pass, which ran with `lanes` lanes per particle) against its threshold
+// gate2, or a forced rebuild, gives flags[r] (1 = rebuild this step);
+// flags[nrep] = any.  The same launch advances the noise step and clears the
+// force pass's overflow count.  force: read and cleared; done: a counter
+// that must be zero and is left zero; nbuild accumulates the replicas
+// rebuilt.  first = false: a second gate of the same step (after the wall
+// corrector, on its block maxima, laid out for one lane per particle): no
+// bookkeeping, and a rebuild there is counted too.
+void launch_gate(hipStream_t st, const Reps &R, int lanes, const float *bmax, int *force, int *flags, int *done,
+                 uint32_t *step_ctr, int *ovf_count, unsigned long long *nbuild, bool first);
+// out[i] = b[a[i]] (two permutations of slots, one after the other).
 void launch_compose(hipStream_t st, int n, const int *a, const int *b, int *out);
+// Sort of the replicas whose flag is set into (cell, id) order: positions x,
+// half-step velocities v, tags, types and, with walls, the previous
+// positions xprev (nullable) are permuted in place through the temporaries
+// t*; the replica's cell offsets in cstart are replaced and its sorted
+// positions copied to xbuild.  dmap (nullable): dmap[i] = the slot the
+// particle at slot i moves to (the identity for replicas not rebuilt).
+// copy_back = false: every replica is sorted whatever the flags say (the
+// caller rebuilds every step), the sorted arrays stay in the t* arrays,
+// which the caller then takes as the state (and x, v, xprev, tag, typ as the
+// next temporaries); step_ctr, ovf_count, nbuild (nullable): the once-per-step
+// bookkeeping of the gate, done by the sort instead (n > 0).
+void launch_rebuild_sort(hipStream_t st, int n, const Reps &R, Soa3 x, Soa3 v, Soa3 xprev, uint32_t *tag,
+                         uint8_t *typ, Soa3 tx, Soa3 tv, Soa3 tp, uint32_t *ttag, uint8_t *ttyp, Soa3 xbuild,
+                         int *key, int *slot, uint32_t *tmpid, int *counts, int *cnew, int *cstart, int *bsum,
+                         int *dmap, bool copy_back, uint32_t *step_ctr = nullptr, int *ovf_count = nullptr,
+                         unsigned long long *nbuild = nullptr);
+// Per-step neighbour list (skin 0) of the replicas whose flag is set (every
+// replica with all): the pairs closer than r_c at the positions xs, the near
+// ones (r < r_d) first with their r^2 in nlr2 (FP32 or FP64 as rho).
 void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int *cstart, int *ncnt,
-                  uint32_t *nl, void *nlr2, const int *gate);
-// Also writes the packed neighbour records of every slot.
+                  uint32_t *nl, void *nlr2, bool all);
+// Density from the per-step list's stored r^2, and the packed records.
+void launch_density_list(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c xs, Soa3c vh,
+                         const uint32_t *tag, const uint8_t *typ, const int *cstart, const int *ncnt,
+                         const void *nlr2, void *rho, PartRec *rec);
+// Skin list of the replicas whose flag is set (every replica with all):
+// for each particle the slots of all others closer than sqrt(rs2) at the
+// positions xs, scnt = their number (a row of more than kSkinCap is not
+// stored; the passes then scan the cells directly).
+void launch_skin_build(hipStream_t st, const Reps &R, bool all, Soa3c xs, const int *cstart, int *scnt,
+                       uint32_t *sl);
+// Pair list at the current positions from the skin list (exact FP64 test
+// against r_c, flag for r < r_d), the many-body density, and the packed
+// neighbour records of every slot (rho and rec NULL: the pair list only).
 void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c xs, Soa3c vh,
-                    const uint32_t *tag, const uint8_t *typ, const int *cstart, const int *ncnt,
-                    const void *nlr2, void *rho, PartRec *rec);
+                    const uint32_t *tag, const uint8_t *typ, const int *cstart, const int *scnt,
+                    const uint32_t *sl, int *ncnt, uint32_t *nl, void *rho, PartRec *rec);
 // Walls: the sub-cell mask of where a frozen particle is in reach (once), and
 // phi + corrector for one step (cell scan at the predicted positions).
 void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint32_t *tag, uint8_t *wmask);
@@ -275,16 +323,23 @@ void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint3
 // slip: some replica reflects with wall_slip > 0 (the wall normal is needed).
 // byid (nullable, n bytes by global particle id): set to 1 for every particle
 // corrected in this step (the adjoint's record of the wall events).
+// A corrected particle goes back to xprev; cmax receives, per block of
+// kBlock slots (replica-aligned, the layout of one lane per particle), the
+// largest squared distance of a corrected particle from its build position
+// xbuild (0 without corrections), for the step's second gate.
 void launch_phi(hipStream_t st, int lanes, bool slip, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix,
                 Soa3 vfix, const uint32_t *tag, const int *cstart, const uint8_t *wmask, int *ncorr,
-                unsigned long long *ncorr_total, uint8_t *byid);
-// stepp: device word holding the noise step (advanced by the main sort).
+                unsigned long long *ncorr_total, uint8_t *byid, Soa3c xbuild, float *cmax);
+// stepp: device word holding the noise step (advanced by the gate).  The
+// epilogue writes the next positions and half-step velocities to xpred,
+// vpred and the block maxima of their squared displacement from xbuild to
+// bmax (float, rounded up; the gate of the next step reads them).
 void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, const uint32_t *stepp,
                   Soa3c xs, Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ,
                   const PartRec *rec, const int *cstart, const int *ncnt, const uint32_t *nl, Soa3 vout,
                   Soa3 fout,
                   Soa3 vpred, Soa3 xpred, double *part, int *status, int *ovf_count, int *ovf,
-                  double *ovf_ve, int initial);
+                  double *ovf_ve, int initial, Soa3c xbuild, float *bmax);
 // Number of virial/energy block partials the force pass writes with this
 // lane count (one per block; replica r owns its blocks' range).
 int force_partials(const Reps &R, int lanes);
@@ -326,6 +381,7 @@ void launch_debug_neighbors(hipStream_t st, const Reps &R, double cutoff2, Soa3c
                             const uint32_t *tag, const int *cstart, const int *ncnt,
                             const uint32_t *nl, int64_t *count, uint64_t *hash);
 void launch_zero_int(hipStream_t st, int *p, int n);
+void launch_set_int(hipStream_t st, int *p, int v);
 // Pressure tensor: per-slot planes (6 x n, xx yy zz xy xz yz), then per-replica
 // sums into out[6 r + a] (still to be divided by the replica's volume).
 // per_block: instead of planes, six sums per block of kStressLanes lanes per

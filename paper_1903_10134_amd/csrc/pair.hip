@@ -1,11 +1,15 @@
 // pair.hip -- the pair passes of one mDPD timestep on gfx950.
 //
-//   k_nlist_cell  one wavefront per cell: the neighbours within r_c of every
-//                 particle of the cell (exact FP64 test on FP64 positions),
-//                 written to a fixed-capacity list; each entry carries a flag
-//                 for r < r_d, and the pair's r^2 is stored beside it
-//   k_density     many-body density rho_i = sum_{j != i, r < r_d} w_rho(r_ij)
-//                 (Sec. 2.1) from the stored r^2 of the flagged entries
+//   k_skin_build  one wavefront per cell: the neighbours within r_c + skin of
+//                 every particle of the cell at the build positions (exact
+//                 FP64 test), written to a fixed-capacity skin list; runs only
+//                 in the steps the gate asks for a rebuild
+//   k_density     every step: the skin entries closer than r_c at the current
+//                 positions (exact FP64 test, the neighbour test of the
+//                 method) become the step's pair list, each with a flag for
+//                 r < r_d, and the many-body density
+//                 rho_i = sum_{j != i, r < r_d} w_rho(r_ij) (Sec. 2.1) is
+//                 summed over them; also packs the neighbour records
 //   k_phi         boundary volume fraction of fluid particles at the predicted
 //                 positions (direct cell scan, only where a sub-cell mask puts
 //                 a frozen particle in reach) and the predictor-corrector flag
@@ -13,21 +17,35 @@
 //   k_force       Eq. 1 conservative force, dissipative and random forces
 //                 (Sec. 2.1), body force, and the velocity-Verlet update fused
 //                 in the epilogue: v(t+dt), the next half-step velocity and the
-//                 next predicted position (Alg. 1)
+//                 next predicted position (Alg. 1), and how far the particles
+//                 have moved since the list build (for the next gate)
 //
 // In the list passes P lanes of a 64-wide wavefront cooperate on one particle
 // (P = 1, 2, 4, 8 or 16): they split its list entries and combine their partial
 // sums with a butterfly of lane shuffles inside the group, so every sum has
-// one fixed order.  A particle with more than kListCap neighbours is served by
-// a direct scan of the cells with the same exact test.
+// one fixed order.  A particle with more than kSkinCap skin neighbours, or
+// more than kListCap pair neighbours, is served by a direct scan of the
+// cells with the same exact test (the cells of the last build, their
+// clipping widened by the half skin the particles may have moved since).
 #include "pair_common.h"
 
 namespace mdpd {
 
 namespace {
 
+// Stores into one list row go through a buffer resource whose range is the
+// row: a lane with nothing to store gives an offset past the range, and the
+// hardware drops the store, so the emission needs no branch.
+constexpr int kDropOffset = (int)0x80000000;
+constexpr int kRawBufferConfig = 0x00020000;  // 32-bit data format, no swizzle
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(void *row, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(row, (short)0, bytes, kRawBufferConfig);
+}
+
 // ---------------------------------------------------------------------------
-// Neighbour list: one wavefront per cell.
+// Per-step neighbour list (skin 0): one wavefront per cell.
 //
 // Interior cells (no periodic image in the stencil): the 27 stencil cells are
 // 9 rows of 3 x-adjacent cells, each row contiguous in the sorted order.  The
@@ -44,7 +62,9 @@ namespace {
 // and the minimum image is taken on the axes where the cell touches the
 // boundary.  Otherwise (fewer cells, or a batch above 128 candidates) the
 // general path walks the batches 64 candidates at a time with the shifts of
-// each row piece, and i's running count lives in lane (i mod 64).
+// each row piece, and i's running count lives in lane (i mod 64); with two
+// cells on an axis the other cell is visited with both shifts, and a pair
+// closer than r_c <= L/2 matches one of them only.
 //
 // Each entry is the neighbour's slot, with kNearBit set when r < r_d and
 // kWrapBit set when the pair is seen through a periodic image (its difference
@@ -54,17 +74,6 @@ namespace {
 // no gap: a row of the usual ~25 entries is one 128-byte line.  Near hits are
 // stored as they are found; far hits wait in LDS until the particle's near
 // count is known.
-
-// Stores into one list row go through a buffer resource whose range is the
-// row: a lane with nothing to store gives an offset past the range, and the
-// hardware drops the store, so the emission needs no branch.
-constexpr int kDropOffset = (int)0x80000000;
-constexpr int kRawBufferConfig = 0x00020000;  // 32-bit data format, no swizzle
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(void *row, int bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(row, (short)0, bytes, kRawBufferConfig);
-}
 
 __device__ __forceinline__ void store_r2(__amdgpu_buffer_rsrc_t r, int k, bool keep, float v)
 {
@@ -124,12 +133,13 @@ constexpr int kFarLds = (kGenBatch + 1) * kListCap;
 template <typename R2, bool BORDER>
 __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, const int *__restrict__ cstart_all,
                                            int *__restrict__ ncnt, uint32_t *__restrict__ nl,
-                                           R2 *__restrict__ nlr2, uint32_t *far_lds)
+                                           R2 *__restrict__ nlr2, uint32_t *far_lds, int all)
 {
     const int lane = threadIdx.x & 63;
     uint32_t *const dump = far_lds + kGenBatch * kListCap;
     // the replica of this cell: its lattice, and its cell offsets (global slots)
     const int rep = __builtin_amdgcn_readfirstlane(find_rep(R.cell_off, R.nrep, cg));
+    if (!all && cload(R.flag, rep) == 0) return;  // the replica keeps its list this time
     const Geom g = cload(R.geom, rep);
     const int c = cg - cload(R.cell_off, rep);
     const int *__restrict__ cstart = cstart_all + cload(R.cell_off, rep);
@@ -416,25 +426,142 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
 template <typename R2>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_nlist_cell(
     Reps R, Soa3c xs, const int *__restrict__ cstart_all, int *__restrict__ ncnt, uint32_t *__restrict__ nl,
-    R2 *__restrict__ nlr2, const int *__restrict__ gate)
+    R2 *__restrict__ nlr2, int all)
 {
-    if (gate && *gate == 0) return;
+    if (!all && cload(R.flag, R.nrep) == 0) return;
     __shared__ uint32_t lds[kWavesPerBlock * kFarLds];
     const int cg = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
     if (cg >= R.ncells) return;
-    nlist_cell<R2, false>(R, cg, xs, cstart_all, ncnt, nl, nlr2, lds + (threadIdx.x >> 6) * kFarLds);
+    nlist_cell<R2, false>(R, cg, xs, cstart_all, ncnt, nl, nlr2, lds + (threadIdx.x >> 6) * kFarLds, all);
 }
 
 template <typename R2>
 __global__ __launch_bounds__(kBlock) void k_nlist_border(Reps R, Soa3c xs, const int *__restrict__ cstart_all,
                                                          int *__restrict__ ncnt, uint32_t *__restrict__ nl,
-                                                         R2 *__restrict__ nlr2, const int *__restrict__ gate)
+                                                         R2 *__restrict__ nlr2, int all)
 {
-    if (gate && *gate == 0) return;
+    if (!all && cload(R.flag, R.nrep) == 0) return;
     __shared__ uint32_t lds[kWavesPerBlock * kFarLds];
     const int w = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
     if (w >= R.nbcells) return;
-    nlist_cell<R2, true>(R, cload(R.bcells, w), xs, cstart_all, ncnt, nl, nlr2, lds + (threadIdx.x >> 6) * kFarLds);
+    nlist_cell<R2, true>(R, cload(R.bcells, w), xs, cstart_all, ncnt, nl, nlr2, lds + (threadIdx.x >> 6) * kFarLds,
+                         all);
+}
+
+// ---------------------------------------------------------------------------
+// Skin list: one wavefront per cell.
+//
+// The distinct cells around the cell (offsets -1, 0, +1 per axis with three
+// cells or more on it, 0 and +1 with two, 0 with one) are taken one z layer
+// at a time; a layer is up to three rows of x-adjacent cells, each one or two
+// contiguous pieces of the sorted order.  The wave loads 64 candidates of the
+// layer at a time (lane q holds candidate q) and tests them against every
+// particle of the cell, broadcast through the scalar unit, with the exact
+// FP64 test: a ballot and mbcnt append the hits to the particle's row in
+// candidate order; its running count lives in lane (particle mod 64).
+// Cells within two cells of a box face take the minimum image of every
+// difference (the torus distance) and flag their entries: such a pair may
+// cross a face before the next build, the others cannot (both particles
+// stay more than a cell edge minus half the skin inside the box).
+template <bool ALL>
+__device__ __forceinline__ void skin_cell(const Reps &R, int cg, Soa3c xs, const int *__restrict__ cstart_all,
+                                          int *__restrict__ scnt, uint32_t *__restrict__ sl)
+{
+    const int lane = threadIdx.x & 63;
+    const int rep = __builtin_amdgcn_readfirstlane(find_rep(R.cell_off, R.nrep, cg));
+    if (!ALL && cload(R.flag, rep) == 0) return;
+    const Geom g = cload(R.geom, rep);
+    const int c = cg - cload(R.cell_off, rep);
+    const int *__restrict__ cstart = cstart_all + cload(R.cell_off, rep);
+    const int i0 = cstart[c], ni = cstart[c + 1] - i0;
+    if (ni == 0) return;
+    const int nx = g.nc[0], ny = g.nc[1], nz = g.nc[2];
+    // cell coordinates: the quotients are exact in FP64 (at most 2^24 cells),
+    // which avoids integer division
+    const int cyz = __builtin_amdgcn_readfirstlane((int)(((double)c + 0.5) * g.inv_nc[0]));
+    const int cz = __builtin_amdgcn_readfirstlane((int)(((double)cyz + 0.5) * g.inv_nc[1]));
+    const int cx = c - cyz * nx, cy = cyz - cz * ny;
+    const bool face = cx < 2 || cx >= nx - 2 || cy < 2 || cy >= ny - 2 || cz < 2 || cz >= nz - 2;
+    const uint32_t wrap = face ? kWrapBit : 0u;
+    const double rs2 = g.rs2;
+    const int oz0 = nz >= 3 ? -1 : 0, oz1 = nz >= 2 ? 1 : 0;
+    const int oy0 = ny >= 3 ? -1 : 0, oy1 = ny >= 2 ? 1 : 0;
+    // the x cells of a row: [a0, a1) and, when the row wraps, [b0, b1)
+    int a0 = 0, a1 = nx, b0 = 0, b1 = 0;
+    if (nx >= 3) {
+        if (cx == 0) {
+            a0 = nx - 1;
+            b1 = 2;
+        } else if (cx == nx - 1) {
+            a0 = nx - 2;
+            b1 = 1;
+        } else {
+            a0 = cx - 1;
+            a1 = cx + 2;
+        }
+    }
+    for (int ib = 0; ib < ni; ib += 64) {
+        const int nic = ni - ib < 64 ? ni - ib : 64;
+        const int me = i0 + ib + (lane < nic ? lane : 0);
+        const double pxi = ld(xs.x, me), pyi = ld(xs.y, me), pzi = ld(xs.z, me);
+        int cnt = 0;  // lane u: entries of particle i0 + ib + u so far
+        for (int oz = oz0; oz <= oz1; ++oz) {
+            const int zz = wrap_index(cz + oz, nz);
+            int pb[6], pl[6];
+            int Q = 0;
+            for (int oy = oy0; oy <= oy1; ++oy) {
+                const int yy = wrap_index(cy + oy, ny);
+                const int base = nx * (yy + ny * zz);
+                const int r = oy - oy0;
+                pb[2 * r] = cstart[base + a0];
+                pl[2 * r] = cstart[base + a1] - pb[2 * r];
+                pb[2 * r + 1] = cstart[base + b0];
+                pl[2 * r + 1] = cstart[base + b1] - pb[2 * r + 1];
+                Q += pl[2 * r] + pl[2 * r + 1];
+            }
+            const int npieces = 2 * (oy1 - oy0 + 1);
+            for (int q0 = 0; q0 < Q; q0 += 64) {
+                int off = q0 + lane, slot = -1;
+                for (int k = 0; k < npieces; ++k) {
+                    if (off >= 0 && off < pl[k]) slot = pb[k] + off;
+                    off -= pl[k];
+                }
+                const int js = slot >= 0 ? slot : i0;
+                const double xj = ld(xs.x, js), yj = ld(xs.y, js), zj = ld(xs.z, js);
+                for (int u = 0; u < nic; ++u) {
+                    const double xi = bcast_d(pxi, u), yi = bcast_d(pyi, u), zi = bcast_d(pzi, u);
+                    const int i = i0 + ib + u;
+                    double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+                    if (face) {
+                        dx = min_image(dx, g.L[0], g.invL[0]);
+                        dy = min_image(dy, g.L[1], g.invL[1]);
+                        dz = min_image(dz, g.L[2], g.invL[2]);
+                    }
+                    const double r2 = exact_r2(dx, dy, dz);
+                    const bool hit = slot >= 0 && slot != i && r2 < rs2;
+                    const unsigned long long hm = __builtin_amdgcn_ballot_w64(hit);
+                    if (hm) {
+                        const int pos = lanes_below(hm, bcast_i(cnt, u));
+                        const __amdgpu_buffer_rsrc_t ro = row_rsrc(sl + (size_t)i * kSkinCap, kSkinCap * 4);
+                        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)slot | wrap, ro, hit ? pos * 4 : kDropOffset,
+                                                              0, 0);
+                        if (lane == u) cnt += (int)__popcll(hm);
+                    }
+                }
+            }
+        }
+        if (lane < nic) scnt[i0 + ib + lane] = cnt;
+    }
+}
+
+template <bool ALL>
+__global__ __launch_bounds__(kBlock) void k_skin_build(Reps R, Soa3c xs, const int *__restrict__ cstart_all,
+                                                       int *__restrict__ scnt, uint32_t *__restrict__ sl)
+{
+    if (!ALL && cload(R.flag, R.nrep) == 0) return;
+    const int cg = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    if (cg >= R.ncells) return;
+    skin_cell<ALL>(R, cg, xs, cstart_all, scnt, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -457,8 +584,11 @@ __device__ __forceinline__ float w_rho<float>(const PairConst &pc, float r2)
     return (float)pc.wrho * u * u;
 }
 
+// Density from the per-step list: the stored r^2 of the near entries (r < r_d
+// first in the row), or a direct scan for a row that overflowed; also packs
+// the neighbour records.
 template <int P, typename R>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_density(Reps Rp, Soa3c xs, Soa3c vh, const uint32_t *__restrict__ tag,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_density_list(Reps Rp, Soa3c xs, Soa3c vh, const uint32_t *__restrict__ tag,
                                                     const uint8_t *__restrict__ typ,
                                                     const int *__restrict__ cstart_all,
                                                     const int *__restrict__ ncnt,
@@ -480,15 +610,121 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         for (int k = sub; k < nnear; k += P) acc += w_rho<R>(pc, lr[k]);
     } else {
         const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
-        for_each_row(g, xi, yi, zi, cstart, [&](int b, int e, double sx, double sy, double sz) {
+        for_each_row(g, xi, yi, zi, cstart, [&](int b, int e) {
             for (int j = b + sub; j < e; j += P) {
                 if (j == i) continue;
-                const double r2 = exact_r2((xi - xs.x[j]) + sx, (yi - xs.y[j]) + sy, (zi - xs.z[j]) + sz);
+                double dx = xi - xs.x[j], dy = yi - xs.y[j], dz = zi - xs.z[j];
+                min_image3(g, dx, dy, dz);
+                const double r2 = exact_r2(dx, dy, dz);
                 if (r2 < g.rd2) acc += w_rho<R>(pc, (R)r2);
             }
         });
     }
     acc = group_sum<P>(acc);
+    if constexpr (P == 4) {
+        // the four lanes of i write its record together, 16 bytes each
+        // (x y | z vx | vy vz | rho tag typ), so one store instruction
+        // covers 16 whole records
+        const uint32_t tg = tag[i];
+        const bool fz = (tg & kFrozenBit) != 0;
+        const double *pa = sub == 0 ? xs.x : (sub == 1 ? xs.z : vh.y);
+        const double *pb = sub == 0 ? xs.y : (sub == 1 ? vh.x : vh.z);
+        double a = pa[i], b = pb[i];
+        if (fz && sub >= 1) {
+            b = 0.0;
+            if (sub >= 2) a = 0.0;
+        }
+        if (sub == 3) {
+            a = (double)acc;
+            b = __longlong_as_double((long long)((unsigned long long)tg | ((unsigned long long)typ[i] << 32)));
+        }
+        if (sub == 0) rho[i] = acc;
+        reinterpret_cast<double2 *>(rec + i)[sub] = make_double2(a, b);
+    } else if (sub == 0) {
+        rho[i] = acc;
+        const uint32_t tg = tag[i];
+        const bool fz = (tg & kFrozenBit) != 0;
+        PartRec q;
+        q.x = xs.x[i];
+        q.y = xs.y[i];
+        q.z = xs.z[i];
+        q.vx = fz ? 0.0 : vh.x[i];
+        q.vy = fz ? 0.0 : vh.y[i];
+        q.vz = fz ? 0.0 : vh.z[i];
+        q.rho = (double)acc;
+        q.tag = tg;
+        q.typ = typ[i];
+        rec[i] = q;
+    }
+}
+
+// Pair list and density.  The P lanes of particle i take its skin entries in
+// turns; each entry closer than r_c at the current positions is appended to
+// i's pair row (flag kNearBit when r < r_d) at the group's running count plus
+// the group's hits in lower lanes, so the row keeps the skin order.  The near
+// count and the far count are packed in ncnt (near | far << 16); a row over
+// kListCap entries is not read (the passes scan the cells directly).
+template <int P, typename R>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_density_skin(
+    Reps Rp, Soa3c xs, Soa3c vh, const uint32_t *__restrict__ tag, const uint8_t *__restrict__ typ,
+    const int *__restrict__ cstart_all, const int *__restrict__ scnt, const uint32_t *__restrict__ sl,
+    int *__restrict__ ncnt, uint32_t *__restrict__ nl, R *__restrict__ rho, PartRec *__restrict__ rec)
+{
+    const BlockRep br = block_rep<P>(Rp, xcd_block());
+    const int i = br.i0 + (int)threadIdx.x / P;
+    const int sub = threadIdx.x & (P - 1);
+    if (i >= br.i1) return;
+    const PairConst pc = cload(Rp.pc, br.r);
+    const Geom g = cload(Rp.geom, br.r);
+    const int *__restrict__ cstart = cstart_all + cload(Rp.cell_off, br.r);
+    const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
+    const int ns = scnt[i];
+    R acc = 0;
+    if (ns <= kSkinCap) {
+        const int lane = threadIdx.x & 63;
+        const unsigned long long gmask = (P == 64 ? ~0ull : ((1ull << P) - 1ull)) << (lane & ~(P - 1));
+        const uint32_t *__restrict__ srow = sl + (size_t)i * kSkinCap;
+        const __amdgpu_buffer_rsrc_t ro = row_rsrc(nl + (size_t)i * kListCap, kListCap * 4);
+        int cn = 0, cf = 0;
+        for (int k0 = 0; k0 < ns; k0 += P) {
+            const int k = k0 + sub;
+            const bool valid = k < ns;
+            const uint32_t e = valid ? srow[k] : 0u;
+            const int j = (int)(e & kSlotMask);
+            double dx = xi - ld(xs.x, j), dy = yi - ld(xs.y, j), dz = zi - ld(xs.z, j);
+            if (e & kWrapBit) {
+                dx = min_image(dx, pc.L[0], pc.invL[0]);
+                dy = min_image(dy, pc.L[1], pc.invL[1]);
+                dz = min_image(dz, pc.L[2], pc.invL[2]);
+            }
+            const double r2 = exact_r2(dx, dy, dz);
+            const bool hit = valid && r2 < g.rc2;
+            const bool near = hit && r2 < g.rd2;
+            if (near) acc += w_rho<R>(pc, (R)r2);
+            const unsigned long long mh = __builtin_amdgcn_ballot_w64(hit) & gmask;
+            const unsigned long long mn = __builtin_amdgcn_ballot_w64(near) & gmask;
+            const int pos = lanes_below(mh, cn + cf);
+            __builtin_amdgcn_raw_buffer_store_b32((e & (kSlotMask | kWrapBit)) | (near ? kNearBit : 0u), ro,
+                                                  hit ? pos * 4 : kDropOffset, 0, 0);
+            const int h = (int)__popcll(mh), hn = (int)__popcll(mn);
+            cn += hn;
+            cf += h - hn;
+        }
+        if (sub == 0) ncnt[i] = cn | (cf << 16);
+    } else {
+        for_each_row(g, xi, yi, zi, cstart, [&](int b, int e) {
+            for (int j = b + sub; j < e; j += P) {
+                if (j == i) continue;
+                double dx = xi - xs.x[j], dy = yi - xs.y[j], dz = zi - xs.z[j];
+                min_image3(g, dx, dy, dz);
+                const double r2 = exact_r2(dx, dy, dz);
+                if (r2 < g.rd2) acc += w_rho<R>(pc, (R)r2);
+            }
+        });
+        if (sub == 0) ncnt[i] = (kListCap + 1) << 16;  // not a list: the passes scan the cells
+    }
+    acc = group_sum<P>(acc);
+    if (!rho) return;  // the pair list only
     if constexpr (P == 4) {
         // the four lanes of i write its record together, 16 bytes each
         // (x y | z vx | vy vz | rho tag typ), so one store instruction
@@ -627,10 +863,11 @@ __global__ __launch_bounds__(kBlock) void k_phi(Reps R, Soa3c xs, const uint32_t
         const int ii = wp[q];
         const double xi = xs.x[ii], yi = xs.y[ii], zi = xs.z[ii];
         double num = 0.0, den = 0.0, nx = 0.0, ny = 0.0, nz = 0.0;
-        for_each_row(g, xi, yi, zi, cstart, [&](int b, int e, double sx, double sy, double sz) {
+        for_each_row(g, xi, yi, zi, cstart, [&](int b, int e) {
             for (int j = b + sub; j < e; j += P) {
                 if (j == ii) continue;
-                const double dx = (xi - xs.x[j]) + sx, dy = (yi - xs.y[j]) + sy, dz = (zi - xs.z[j]) + sz;
+                double dx = xi - xs.x[j], dy = yi - xs.y[j], dz = zi - xs.z[j];
+                min_image3(g, dx, dy, dz);
                 const double r2 = exact_r2(dx, dy, dz);
                 if (!(r2 < g.rc2)) continue;
                 const double r = __builtin_sqrt(r2);
@@ -676,36 +913,64 @@ __global__ __launch_bounds__(kBlock) void k_phi(Reps R, Soa3c xs, const uint32_t
 }
 
 // Applies the corrector to flagged particles: x <- x(t), and for flag 1
-// v_half <- -v_half (flag 2: k_phi has reflected v_half already); each block
-// writes its number of corrections to part[blockIdx.x].  With byid (the
-// adjoint's recording) a corrected particle also sets byid[part_off[r] + id].
-__global__ __launch_bounds__(kBlock) void k_correct(Reps R, int n, const int *__restrict__ flag, Soa3c xprev,
-                                                    Soa3 xs, Soa3 vh, int *__restrict__ part,
-                                                    const uint32_t *__restrict__ tag, uint8_t *__restrict__ byid)
+// v_half <- -v_half (flag 2: k_phi has reflected v_half already).  Blocks are
+// replica-aligned (kBlock slots of one replica); each writes its number of
+// corrections to part[blockIdx.x] and the largest squared distance of a
+// corrected particle from its build position to cmax[blockIdx.x]: the list
+// covers a particle sent back as long as that stays below half the skin,
+// which the step's second gate checks.  With byid (the adjoint's recording)
+// a corrected particle also sets byid[part_off[r] + id].
+__global__ __launch_bounds__(kBlock) void k_correct(Reps R, const int *__restrict__ flag, Soa3c xprev, Soa3 xs,
+                                                    Soa3 vh, int *__restrict__ part,
+                                                    const uint32_t *__restrict__ tag, uint8_t *__restrict__ byid,
+                                                    Soa3c xbuild, float *__restrict__ cmax)
 {
     __shared__ int cnt[kWavesPerBlock];
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    __shared__ float far[kWavesPerBlock];
+    const BlockRep br = block_rep<1>(R, blockIdx.x);
+    const int i = br.i0 + (int)threadIdx.x;
     int hit = 0;
-    const int f = i < n ? flag[i] : 0;
+    float d2 = 0.0f;
+    const int f = i < br.i1 ? flag[i] : 0;
     if (f) {
-        xs.x[i] = xprev.x[i];
-        xs.y[i] = xprev.y[i];
-        xs.z[i] = xprev.z[i];
+        const double px = xprev.x[i], py = xprev.y[i], pz = xprev.z[i];
+        xs.x[i] = px;
+        xs.y[i] = py;
+        xs.z[i] = pz;
         if (f == 1) {
             vh.x[i] = -vh.x[i];
             vh.y[i] = -vh.y[i];
             vh.z[i] = -vh.z[i];
         }
-        if (byid) byid[(size_t)cload(R.part_off, find_rep(R.part_off, R.nrep, i)) + (tag[i] & kIdMask)] = 1;
+        if (xbuild.x) {
+            const Geom g = cload(R.geom, br.r);
+            const double dx = min_image(px - xbuild.x[i], g.L[0], g.invL[0]);
+            const double dy = min_image(py - xbuild.y[i], g.L[1], g.invL[1]);
+            const double dz = min_image(pz - xbuild.z[i], g.L[2], g.invL[2]);
+            d2 = (float)((dx * dx + dy * dy + dz * dz) * (1.0 + 1e-6));
+        } else {
+            d2 = 1.0f;  // skin 0: any particle moved back re-sorts its replica
+        }
+        if (byid) byid[(size_t)cload(R.part_off, br.r) + (tag[i] & kIdMask)] = 1;
         hit = 1;
     }
     const int w = (int)__popcll(__ballot(hit));
-    if ((threadIdx.x & 63) == 0) cnt[threadIdx.x >> 6] = w;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) d2 = fmaxf(d2, __shfl_xor(d2, o, 64));
+    if ((threadIdx.x & 63) == 0) {
+        cnt[threadIdx.x >> 6] = w;
+        far[threadIdx.x >> 6] = d2;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         int t = 0;
-        for (int k = 0; k < kWavesPerBlock; ++k) t += cnt[k];
+        float m = 0.0f;
+        for (int k = 0; k < kWavesPerBlock; ++k) {
+            t += cnt[k];
+            m = fmaxf(m, far[k]);
+        }
         part[blockIdx.x] = t;
+        cmax[blockIdx.x] = m;
     }
 }
 
@@ -792,7 +1057,21 @@ struct ForceOut {
     int *status;              // bit 0: non-finite or out-of-box state
     int *ovf_count, *ovf;     // particles whose list overflowed, for k_force_overflow
     int initial;              // 1 at creation: v(t) is the given velocity
+    Soa3c xbuild;             // positions at the last list build
+    float *bmax;              // per block: largest squared displacement of xpred from xbuild (nullable)
 };
+
+// Squared distance (minimum image) of a new position from its build
+// position, rounded up to FP32 for the gate's block maxima.
+__device__ __forceinline__ float moved2(const PairConst &pc, const Soa3c &xb, int i, double qx, double qy, double qz)
+{
+    if (!xb.x) return 0.0f;  // skin 0: every step rebuilds anyway
+    const double dx = min_image(qx - xb.x[i], pc.L[0], pc.invL[0]);
+    const double dy = min_image(qy - xb.y[i], pc.L[1], pc.invL[1]);
+    const double dz = min_image(qz - xb.z[i], pc.L[2], pc.invL[2]);
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    return (float)(d2 * (1.0 + 1e-6));
+}
 
 // Force on particle i (slot), its velocity-Verlet epilogue, and its share of
 // the virial and pair energy.  SCAN = false: the neighbours come from the
@@ -811,7 +1090,8 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
                                                const int *__restrict__ cstart, int packed,
                                                const uint32_t *__restrict__ lst,
                                                const PartRec *__restrict__ rec, const ForceOut &out,
-                                               const double *__restrict__ tab, double &vir, double &ep)
+                                               const double *__restrict__ tab, double &vir, double &ep,
+                                               float &moved)
 {
     const uint32_t tgi = tag[i];
     const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
@@ -954,15 +1234,24 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
                     __builtin_isfinite(px) && __builtin_isfinite(py) && __builtin_isfinite(pz) && qx >= 0.0 &&
                     qx < pc.L[0] && qy >= 0.0 && qy < pc.L[1] && qz >= 0.0 && qz < pc.L[2];
     if (!ok) atomicOr(out.status, 1);
+    moved = ok ? moved2(pc, out.xbuild, i, qx, qy, qz) : __builtin_inff();
 }
 
-// Fixed-order block sum of the per-lane virial and pair-energy partials.
-__device__ __forceinline__ void block_partials(double vir, double ep, double *part, int slot)
+// Fixed-order block sum of the per-lane virial and pair-energy partials, and
+// the block maximum of the squared displacements (for the gate).
+__device__ __forceinline__ void block_partials(double vir, double ep, float moved, double *part, float *bmax,
+                                               int slot)
 {
     __shared__ double red_v[kBlock];
     __shared__ double red_e[kBlock];
+    __shared__ float red_m[kWavesPerBlock];
     red_v[threadIdx.x] = vir;
     red_e[threadIdx.x] = ep;
+    if (bmax) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) moved = fmaxf(moved, __shfl_xor(moved, o, 64));
+        if ((threadIdx.x & 63) == 0) red_m[threadIdx.x >> 6] = moved;
+    }
     __syncthreads();
     for (int s = kBlock / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
@@ -974,6 +1263,11 @@ __device__ __forceinline__ void block_partials(double vir, double ep, double *pa
     if (threadIdx.x == 0) {
         part[2 * slot] = red_v[0];
         part[2 * slot + 1] = red_e[0];
+        if (bmax) {
+            float m = red_m[0];
+            for (int w = 1; w < kWavesPerBlock; ++w) m = fmaxf(m, red_m[w]);
+            bmax[slot] = m;
+        }
     }
 }
 
@@ -1000,16 +1294,17 @@ __global__ __launch_bounds__(kBlock) void k_force(Reps Rp, const uint32_t *__res
         __syncthreads();
     }
     double vir = 0.0, ep = 0.0;
+    float moved = 0.0f;
     if (i < br.i1) {
         const int packed = ncnt[i];
         if (list_total(packed) <= kListCap) {
             force_particle<P, MT, false, R>(pc, g, i, sub, xs, vh, rho, tag, typ, nullptr, packed,
-                                            nl + (size_t)i * kListCap, rec, out, ptab, vir, ep);
+                                            nl + (size_t)i * kListCap, rec, out, ptab, vir, ep, moved);
         } else if (sub == 0) {
-            out.ovf[atomicAdd(out.ovf_count, 1)] = i;  // served by k_force_overflow
+            out.ovf[atomicAdd(out.ovf_count, 1)] = i;  // served by k_force_overflow (its move too)
         }
     }
-    block_partials(vir, ep, out.part, blk);
+    block_partials(vir, ep, moved, out.part, out.bmax, blk);
 }
 
 // Particles whose neighbour list overflowed: a fixed grid walks the queue
@@ -1019,6 +1314,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Reps Rp, const uint32_t *__res
 // observables reduction adds it back in slot order.
 constexpr int kOverflowBlocks = 32;
 
+// The squared move of a queued particle goes into the block maximum of the
+// force launch's block that holds its slot (with fl_idx the lane index of
+// that launch), by an integer maximum on the float's bits, which orders
+// non-negative floats and does not depend on the order of the updates.
 template <bool MT, typename R>
 __global__ __launch_bounds__(kBlock) void k_force_overflow(Reps Rp, const uint32_t *__restrict__ stepp, Soa3c xs,
                                                            Soa3c vh,
@@ -1027,7 +1326,7 @@ __global__ __launch_bounds__(kBlock) void k_force_overflow(Reps Rp, const uint32
                                                            const uint8_t *__restrict__ typ,
                                                            const int *__restrict__ cstart_all,
                                                            const int *__restrict__ ncnt, ForceOut out,
-                                                           double *__restrict__ ovf_ve)
+                                                           double *__restrict__ ovf_ve, int fl_idx)
 {
     constexpr int P = 4;
     const int count = *out.ovf_count;
@@ -1041,13 +1340,17 @@ __global__ __launch_bounds__(kBlock) void k_force_overflow(Reps Rp, const uint32
         set_noise_keys(pc, *stepp);
         const Geom g = Rp.geom[r];
         double vir = 0.0, ep = 0.0;
+        float moved = 0.0f;
         force_particle<P, MT, true, R>(pc, g, i, sub, xs, vh, rho, tag, typ, cstart_all + cload(Rp.cell_off, r),
-                                       ncnt[i], nullptr, nullptr, out, pc.tab, vir, ep);
+                                       ncnt[i], nullptr, nullptr, out, pc.tab, vir, ep, moved);
         vir = group_sum<P>(vir);
         ep = group_sum<P>(ep);
         if (sub == 0) {
             ovf_ve[2 * (size_t)i] = vir;
             ovf_ve[2 * (size_t)i + 1] = ep;
+            const int per = kBlock >> fl_idx;  // particles per block of the force launch
+            const int blk = Rp.blk_off[fl_idx * (Rp.nrep + 1) + r] + (i - Rp.part_off[r]) / per;
+            if (out.bmax) atomicMax((unsigned int *)&out.bmax[blk], __float_as_uint(moved));
         }
     }
 }
@@ -1183,25 +1486,25 @@ __global__ __launch_bounds__(kBlock) void k_debug_neighbors(Reps R, double cut2,
 int force_partials(const Reps &R, int lanes) { return R.nblk[lanes_index(lanes)]; }
 
 void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int *cstart, int *ncnt,
-                  uint32_t *nl, void *nlr2, const int *gate)
+                  uint32_t *nl, void *nlr2, bool all)
 {
     if (R.ncells <= 0) return;
     const int blocks = (R.ncells + kWavesPerBlock - 1) / kWavesPerBlock;
     const int bblocks = (R.nbcells + kWavesPerBlock - 1) / kWavesPerBlock;
     if (fp32) {
         if (R.list_interior)
-            k_nlist_cell<float><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (float *)nlr2, gate);
+            k_nlist_cell<float><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (float *)nlr2, all ? 1 : 0);
         if (bblocks > 0)
-            k_nlist_border<float><<<bblocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (float *)nlr2, gate);
+            k_nlist_border<float><<<bblocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (float *)nlr2, all ? 1 : 0);
     } else {
         if (R.list_interior)
-            k_nlist_cell<double><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (double *)nlr2, gate);
+            k_nlist_cell<double><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (double *)nlr2, all ? 1 : 0);
         if (bblocks > 0)
-            k_nlist_border<double><<<bblocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (double *)nlr2, gate);
+            k_nlist_border<double><<<bblocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (double *)nlr2, all ? 1 : 0);
     }
 }
 
-void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c xs, Soa3c vh, const uint32_t *tag,
+void launch_density_list(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c xs, Soa3c vh, const uint32_t *tag,
                     const uint8_t *typ, const int *cstart, const int *ncnt, const void *nlr2, void *rho,
                     PartRec *rec)
 {
@@ -1210,11 +1513,39 @@ void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c x
         const int nb = R.nblk[lanes_index(L)];
         if (nb <= 0) return;
         if (fp32)
-            k_density<L, float><<<nb, kBlock, 0, st>>>(R, xs, vh, tag, typ, cstart, ncnt, (const float *)nlr2,
+            k_density_list<L, float><<<nb, kBlock, 0, st>>>(R, xs, vh, tag, typ, cstart, ncnt, (const float *)nlr2,
                                                        (float *)rho, rec);
         else
-            k_density<L, double><<<nb, kBlock, 0, st>>>(R, xs, vh, tag, typ, cstart, ncnt, (const double *)nlr2,
+            k_density_list<L, double><<<nb, kBlock, 0, st>>>(R, xs, vh, tag, typ, cstart, ncnt, (const double *)nlr2,
                                                         (double *)rho, rec);
+    });
+}
+
+void launch_skin_build(hipStream_t st, const Reps &R, bool all, Soa3c xs, const int *cstart, int *scnt,
+                       uint32_t *sl)
+{
+    if (R.ncells <= 0) return;
+    const int blocks = (R.ncells + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (all)
+        k_skin_build<true><<<blocks, kBlock, 0, st>>>(R, xs, cstart, scnt, sl);
+    else
+        k_skin_build<false><<<blocks, kBlock, 0, st>>>(R, xs, cstart, scnt, sl);
+}
+
+void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c xs, Soa3c vh, const uint32_t *tag,
+                    const uint8_t *typ, const int *cstart, const int *scnt, const uint32_t *sl, int *ncnt,
+                    uint32_t *nl, void *rho, PartRec *rec)
+{
+    launch_lanes(lanes, [&](auto P) {
+        constexpr int L = decltype(P)::value;
+        const int nb = R.nblk[lanes_index(L)];
+        if (nb <= 0) return;
+        if (fp32)
+            k_density_skin<L, float><<<nb, kBlock, 0, st>>>(R, xs, vh, tag, typ, cstart, scnt, sl, ncnt, nl,
+                                                            (float *)rho, rec);
+        else
+            k_density_skin<L, double><<<nb, kBlock, 0, st>>>(R, xs, vh, tag, typ, cstart, scnt, sl, ncnt, nl,
+                                                             (double *)rho, rec);
     });
 }
 
@@ -1225,7 +1556,7 @@ void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint3
 
 void launch_phi(hipStream_t st, int lanes, bool slip, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix,
                 Soa3 vfix, const uint32_t *tag, const int *cstart, const uint8_t *wmask, int *flag_and_count,
-                unsigned long long *ncorr_total, uint8_t *byid)
+                unsigned long long *ncorr_total, uint8_t *byid, Soa3c xbuild, float *cmax)
 {
     if (n <= 0) return;
     int *ncorr = flag_and_count;       // [0]: corrections this step
@@ -1239,8 +1570,8 @@ void launch_phi(hipStream_t st, int lanes, bool slip, int n, const Reps &R, Soa3
         else
             k_phi<L, false><<<R.nblk[0], kBlock, 0, st>>>(R, xs, tag, cstart, wmask, flag, vfix);
     });
-    const int nb = blocks_for(n);
-    k_correct<<<nb, kBlock, 0, st>>>(R, n, flag, xprev, xfix, vfix, part, tag, byid);
+    const int nb = R.nblk[0];
+    k_correct<<<nb, kBlock, 0, st>>>(R, flag, xprev, xfix, vfix, part, tag, byid, xbuild, cmax);
     k_correct_sum<<<1, kBlock, 0, st>>>(nb, part, ncorr, ncorr_total);
 }
 
@@ -1248,9 +1579,10 @@ void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, 
                   Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ, const PartRec *rec,
                   const int *cstart,
                   const int *ncnt, const uint32_t *nl, Soa3 vout, Soa3 fout, Soa3 vpred, Soa3 xpred,
-                  double *part, int *status, int *ovf_count, int *ovf, double *ovf_ve, int initial)
+                  double *part, int *status, int *ovf_count, int *ovf, double *ovf_ve, int initial, Soa3c xbuild,
+                  float *bmax)
 {
-    const ForceOut out{vout, fout, vpred, xpred, part, status, ovf_count, ovf, initial};
+    const ForceOut out{vout, fout, vpred, xpred, part, status, ovf_count, ovf, initial, xbuild, bmax};
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
         const int nb = R.nblk[lanes_index(L)];
@@ -1261,7 +1593,8 @@ void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, 
             k_force<L, M, RT><<<nb, kBlock, 0, st>>>(R, stepp, xs, vh, (const RT *)rho, tag, typ, rec, ncnt, nl,
                                                      out);
             k_force_overflow<M, RT><<<kOverflowBlocks, kBlock, 0, st>>>(R, stepp, xs, vh, (const RT *)rho, tag,
-                                                                        typ, cstart, ncnt, out, ovf_ve);
+                                                                        typ, cstart, ncnt, out, ovf_ve,
+                                                                        lanes_index(L));
         };
         using T = std::true_type;
         using F = std::false_type;

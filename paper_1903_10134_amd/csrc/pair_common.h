@@ -12,7 +12,7 @@ namespace {
 constexpr double kSqrt3Scaled = 1.7320508075688772 / 16777216.0;  // sqrt(3) 2^-24
 constexpr float kSqrt3ScaledF = 1.7320508075688772f / 16777216.0f;
 constexpr uint32_t kNearBit = 0x80000000u;  // list entry flag: r < r_d
-constexpr uint32_t kWrapBit = 0x40000000u;  // list entry flag: pair found through a periodic image
+constexpr uint32_t kWrapBit = 0x40000000u;  // list entry flag: the pair may need the minimum image
 constexpr uint32_t kSlotMask = 0x3fffffffu;
 constexpr int kWavesPerBlock = kBlock / 64;
 
@@ -26,14 +26,21 @@ __device__ __forceinline__ T ld(const T *__restrict__ base, int idx)
 
 __device__ __forceinline__ int wrap_index(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
-// Calls fn(begin, end, sx, sy, sz) for the contiguous slot ranges of the
-// cells around the cell of (xi, yi, zi) that can hold a particle closer than
-// r_c; (sx, sy, sz) is the periodic shift to add to x_i - x_j for candidates of
-// that range.  Rows (dy, dz) whose nearest face is already r_c away are
-// skipped, and in each row the x-neighbour cells are kept only when their
-// facing side is closer than the row's remaining reach sqrt(r_c^2 - dy^2 -
-// dz^2).  The clipping margin (1e-9) is far above rounding, so it never drops
-// a pair that the exact test would keep.
+// Calls fn(begin, end) for the contiguous slot ranges of the distinct cells
+// around the cell of (xi, yi, zi) that can hold a particle closer than r_c;
+// the caller takes every difference x_i - x_j through the minimum image (the
+// torus distance), which is the pair's difference whichever cell lists it.
+// Rows (dy, dz) whose nearest face is already r_c away are skipped, and in
+// each row the x-neighbour cells are kept only when their facing side is
+// closer than the row's remaining reach sqrt(r_c^2 - dy^2 - dz^2).  The
+// particles sit in the cells of the last list build and have moved less than
+// half the skin since (g.slack; one may even have crossed a periodic face),
+// so every gap is reduced by that much.  The clipping margin (1e-9) is far
+// above rounding, so it never drops a pair that the exact test would keep.
+// An axis with three cells or more has the neighbour offsets -1, 0, +1 (the
+// neighbours of an edge cell wrap); with two cells the other cell is a
+// neighbour on both sides (its gap is the nearer face); with one cell the
+// cell is all there is.
 template <typename Fn>
 __device__ __forceinline__ void for_each_row(const Geom &g, double xi, double yi, double zi,
                                              const int *__restrict__ cstart, Fn &&fn)
@@ -46,32 +53,51 @@ __device__ __forceinline__ void for_each_row(const Geom &g, double xi, double yi
     const double lox = xi - cx * g.cs[0], hix = (cx + 1) * g.cs[0] - xi;
     const double loy = yi - cy * g.cs[1], hiy = (cy + 1) * g.cs[1] - yi;
     const double loz = zi - cz * g.cs[2], hiz = (cz + 1) * g.cs[2] - zi;
-    for (int dz = -1; dz <= 1; ++dz) {
-        const double ez = dz == 0 ? 0.0 : fmax(0.0, (dz < 0 ? loz : hiz) - kMargin);
+    // gap from x_i to the neighbour on side d of an axis (0 for the own cell)
+    auto gap = [&](int d, int n, double lo, double hi) {
+        if (d == 0) return 0.0;
+        const double f = n == 2 ? fmin(lo, hi) : (d < 0 ? lo : hi);
+        return fmax(0.0, f - kMargin - g.slack);
+    };
+    const int z0 = nz >= 3 ? -1 : 0, z1 = nz >= 2 ? 1 : 0;
+    const int y0 = ny >= 3 ? -1 : 0, y1 = ny >= 2 ? 1 : 0;
+    for (int dz = z0; dz <= z1; ++dz) {
+        const double ez = gap(dz, nz, loz, hiz);
         if (ez >= g.rc) continue;
         const int zz = wrap_index(cz + dz, nz);
-        const double sz = cz + dz < 0 ? g.L[2] : (cz + dz >= nz ? -g.L[2] : 0.0);
-        for (int dy = -1; dy <= 1; ++dy) {
-            const double ey = dy == 0 ? 0.0 : fmax(0.0, (dy < 0 ? loy : hiy) - kMargin);
+        for (int dy = y0; dy <= y1; ++dy) {
+            const double ey = gap(dy, ny, loy, hiy);
             const double q = ey * ey + ez * ez;
             if (q >= g.rc2) continue;
-            const double reach = __builtin_sqrt(g.rc2 - q) + kMargin;
-            const int yy = wrap_index(cy + dy, ny);
-            const double sy = cy + dy < 0 ? g.L[1] : (cy + dy >= ny ? -g.L[1] : 0.0);
-            const int base = nx * (yy + ny * zz);
+            const double reach = __builtin_sqrt(g.rc2 - q) + kMargin + g.slack;
+            const int base = nx * (wrap_index(cy + dy, ny) + ny * zz);
+            if (nx <= 2) {
+                const bool other = nx == 2 && fmin(lox, hix) < reach;
+                if (other) fn(cstart[base], cstart[base + 2]);
+                else fn(cstart[base + cx], cstart[base + cx + 1]);
+                continue;
+            }
             const int xa = cx - (lox < reach ? 1 : 0);
             const int xb = cx + (hix < reach ? 1 : 0);
             if (xa >= 0 && xb < nx) {
-                fn(cstart[base + xa], cstart[base + xb + 1], 0.0, sy, sz);
+                fn(cstart[base + xa], cstart[base + xb + 1]);
             } else if (xa < 0) {
-                fn(cstart[base + nx - 1], cstart[base + nx], g.L[0], sy, sz);
-                fn(cstart[base], cstart[base + xb + 1], 0.0, sy, sz);
+                fn(cstart[base + nx - 1], cstart[base + nx]);
+                fn(cstart[base], cstart[base + xb + 1]);
             } else {
-                fn(cstart[base + xa], cstart[base + nx], 0.0, sy, sz);
-                fn(cstart[base], cstart[base + 1], -g.L[0], sy, sz);
+                fn(cstart[base + xa], cstart[base + nx]);
+                fn(cstart[base], cstart[base + 1]);
             }
         }
     }
+}
+
+// x_i - x_j through the minimum image on every axis (the direct scans).
+__device__ __forceinline__ void min_image3(const Geom &g, double &dx, double &dy, double &dz)
+{
+    dx = min_image(dx, g.L[0], g.invL[0]);
+    dy = min_image(dy, g.L[1], g.invL[1]);
+    dz = min_image(dz, g.L[2], g.invL[2]);
 }
 
 // Hardware dispatches workgroups to the 8 XCDs round robin; remap so that
@@ -109,10 +135,11 @@ __device__ __forceinline__ int lanes_below(unsigned long long m, int base = 0)
     return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, (unsigned)base));
 }
 
-// List row layout: the kListCap entries of particle i hold its neighbours
-// with r < r_d first and then the others, with no gap; the count word packs
-// the two counts (near in bits 0..15, far in bits 16..31).  A row whose counts
-// add up to more than kListCap is not valid.
+// Pair-list row layout: the kListCap entries of particle i hold its
+// neighbours closer than r_c (kNearBit: r < r_d) with no gap (the per-step
+// list puts the near ones first); the count word packs the two counts (near
+// in bits 0..15, far in bits 16..31).  A row whose counts add up to more
+// than kListCap is not valid.
 __device__ __forceinline__ int list_near(int packed) { return packed & 0xffff; }
 __device__ __forceinline__ int list_total(int packed) { return (packed & 0xffff) + (packed >> 16); }
 
@@ -140,12 +167,11 @@ __device__ __forceinline__ void for_each_neighbor(const PairConst &pc, const Geo
             fn(j, dx, dy, dz, (e & kNearBit) != 0);
         }
     } else {
-        for_each_row(g, xi, yi, zi, cstart, [&](int b, int e, double sx, double sy, double sz) {
+        for_each_row(g, xi, yi, zi, cstart, [&](int b, int e) {
             for (int j = b + sub; j < e; j += P) {
                 if (j == i) continue;
-                const double dx = (xi - xs.x[j]) + sx;
-                const double dy = (yi - xs.y[j]) + sy;
-                const double dz = (zi - xs.z[j]) + sz;
+                double dx = xi - xs.x[j], dy = yi - xs.y[j], dz = zi - xs.z[j];
+                min_image3(g, dx, dy, dz);
                 const double r2 = exact_r2(dx, dy, dz);
                 if (r2 < g.rc2) fn(j, dx, dy, dz, r2 < g.rd2);
             }

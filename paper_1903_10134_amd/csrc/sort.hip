@@ -1,19 +1,28 @@
-// sort.hip -- cell binning and the deterministic stable reorder into SoA.
+// sort.hip -- the list gate, cell binning and the deterministic stable
+// reorder into SoA.
 //
-// Every step the predicted positions are binned into cells of edge >= r_c and
-// all per-particle arrays are rewritten in (cell, particle id) order:
+// Every step the gate decides, per replica, whether its particles have moved
+// far enough since the last list build (half the skin) to need new cells and
+// a new skin list.  The replicas that do are re-binned into cells of edge
+// >= r_c + skin and all their per-particle arrays rewritten in (cell,
+// particle id) order:
+//   k_gate         per-replica rebuild flags from the force pass's block
+//                  maxima of the displacement; advances the noise step
 //   k_bin          cell key per particle and its arrival slot in the cell
 //                  (integer atomics: the counts are exact, the slots are not
 //                  ordered)
-//   k_scan_*       exclusive scan of the cell counts -> cell_start[ncells + 1]
-//                  in two passes: tiles, then tile offsets (the counts are
-//                  cleared as they are read)
+//   k_scan_*       exclusive scan of the cell counts -> new cell offsets in
+//                  two passes: tiles, then tile offsets (the counts are
+//                  cleared as they are read); a rebuilt replica's offsets
+//                  replace its cell_start
 //   k_scatter_id   writes each particle's id at its arrival slot
 //   k_rank_gather  rank of the particle inside its cell = number of particles
-//                  of that cell with a smaller id; moves every array to
-//                  cell_start + rank.
+//                  of that cell with a smaller id; moves every array of a
+//                  rebuilt replica to cell_start + rank in temporaries
+//   k_copy_back    the temporaries back in place, and the build positions.
 // The result depends only on positions and ids, not on the previous order or
-// the atomics' arrival order, so runs and restarts are bitwise reproducible.
+// the atomics' arrival order, so runs and restarts are bitwise reproducible,
+// and a replica's schedule of builds depends on its own particles only.
 #include "mdpd_internal.h"
 
 namespace mdpd {
@@ -21,31 +30,35 @@ namespace mdpd {
 namespace {
 
 constexpr int kScanThreads = 1024;
+constexpr int kWaves = kBlock / 64;
 constexpr int kScanPer = 4;
 constexpr int kScanTile = kScanThreads * kScanPer;
 
 inline int blocks_for(int64_t threads) { return (int)((threads + kBlock - 1) / kBlock); }
 
 // Cell key and arrival slot.  Particles arrive almost in cell order (they
-// were sorted one step ago), so lanes whose key equals the previous lane's
-// form runs; the first lane of a run reserves the whole run with one atomic
-// and the others take consecutive slots after it.
+// were sorted at the last build), so lanes whose key equals the previous
+// lane's form runs; the first lane of a run reserves the whole run with one
+// atomic and the others take consecutive slots after it.
 // Blocks are replica-aligned (kBlock particles of one replica), and the key
-// is the global cell: the replica's first cell plus its local cell.
+// is the global cell: the replica's first cell plus its local cell.  When any
+// replica rebuilds, every particle is binned (the scan needs all counts).
 __global__ __launch_bounds__(kBlock) void k_bin(Reps R, Soa3c x, int *__restrict__ key,
-                                                int *__restrict__ slot, int *__restrict__ counts,
-                                                const int *__restrict__ gate, int *__restrict__ ovf_count,
-                                                uint32_t *__restrict__ step_ctr)
+                                                int *__restrict__ slot, int *__restrict__ counts, int all,
+                                                uint32_t *__restrict__ step_ctr, int *__restrict__ ovf_count,
+                                                unsigned long long *__restrict__ nbuild)
 {
-    if (gate && *gate == 0) return;
+    if (!all && cload(R.flag, R.nrep) == 0) return;
+    if (step_ctr && blockIdx.x == 0 && threadIdx.x == 0) {
+        // the step's bookkeeping when no gate runs (every replica rebuilds)
+        *step_ctr += 1;
+        *ovf_count = 0;
+        *nbuild += (unsigned long long)R.nrep;
+    }
     const int *boff = R.blk_off;  // lane count 1
     const int r = __builtin_amdgcn_readfirstlane(find_rep(boff, R.nrep, blockIdx.x));
     const int i = cload(R.part_off, r) + (blockIdx.x - cload(boff, r)) * kBlock + threadIdx.x;
     const int n = cload(R.part_off, r + 1);  // end of this replica's slots
-    if (ovf_count && i == 0) {
-        *ovf_count = 0;  // the force pass of this step refills it
-        *step_ctr += 1;  // noise step of this step's force pass
-    }
     const Geom g = cload(R.geom, r);
     const int lane = threadIdx.x & 63;
     int c = -1;
@@ -105,12 +118,11 @@ __device__ __forceinline__ int block_inclusive_scan(int v, int *sh, int *total)
 }
 
 // Local exclusive scan of tile b of counts into out; clears counts.
-__global__ __launch_bounds__(kScanThreads) void k_scan_local(int m, int *__restrict__ counts,
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(Reps R, int m, int *__restrict__ counts,
                                                              int *__restrict__ out,
-                                                             int *__restrict__ bsum,
-                                                             const int *__restrict__ gate)
+                                                             int *__restrict__ bsum, int all)
 {
-    if (gate && *gate == 0) return;
+    if (!all && cload(R.flag, R.nrep) == 0) return;
     __shared__ int sh[kScanThreads / 64];
     const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
     int v[kScanPer];
@@ -136,12 +148,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_local(int m, int *__restr
 
 // Adds to tile b of out the sum of the totals of tiles 0 .. b-1 (the first
 // wavefront sums them; integer sums do not depend on the order); the last
-// tile also writes the grand total to out[m].
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(int m, int nb, const int *__restrict__ bsum,
-                                                           int *__restrict__ out,
-                                                           const int *__restrict__ gate)
+// tile also writes the grand total to out[m].  The offsets of the cells of
+// rebuilt replicas also go to cstart.
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(Reps R, int m, int nb, const int *__restrict__ bsum,
+                                                           int *__restrict__ out, int *__restrict__ cstart, int all)
 {
-    if (gate && *gate == 0) return;
+    if (!all && cload(R.flag, R.nrep) == 0) return;
     __shared__ int sh;
     if (threadIdx.x < 64) {
         int v = 0;
@@ -150,55 +162,64 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int m, int nb, const 
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
         if (threadIdx.x == 0) {
             sh = v;
-            if ((int)blockIdx.x == nb - 1) out[m] = v + bsum[nb - 1];
+            if ((int)blockIdx.x == nb - 1) out[m] = cstart[m] = v + bsum[nb - 1];
         }
     }
     __syncthreads();
     const int add = sh;
     const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k)
-        if (base + k < m) out[base + k] += add;
+    for (int k = 0; k < kScanPer; ++k) {
+        const int c = base + k;
+        if (c < m) {
+            const int v = out[c] + add;
+            out[c] = v;
+            if (all || cload(R.flag, find_rep(R.cell_off, R.nrep, c))) cstart[c] = v;
+        }
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter_id(int n, const int *__restrict__ key,
+__global__ __launch_bounds__(kBlock) void k_scatter_id(Reps R, int n, const int *__restrict__ key,
                                                        const int *__restrict__ slot,
-                                                       const int *__restrict__ cstart,
+                                                       const int *__restrict__ cnew,
                                                        const uint32_t *__restrict__ tag,
-                                                       uint32_t *__restrict__ tmpid,
-                                                       const int *__restrict__ gate)
+                                                       uint32_t *__restrict__ tmpid, int all)
 {
-    if (gate && *gate == 0) return;
+    if (!all && cload(R.flag, R.nrep) == 0) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    tmpid[cstart[key[i]] + slot[i]] = tag[i] & kIdMask;
+    tmpid[cnew[key[i]] + slot[i]] = tag[i] & kIdMask;
 }
 
-// With gate == 0 (nothing moved since the last sort) the arrays are copied in
-// place order so the caller's buffer swap stays valid.
-__global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const int *__restrict__ key,
-                                                        const int *__restrict__ cstart,
+// Particles of rebuilt replicas: new slot = cell start + rank, every array
+// written there in the temporaries.  dmap (nullable) records the move (the
+// identity for replicas not rebuilt).
+__global__ __launch_bounds__(kBlock) void k_rank_gather(Reps R, const int *__restrict__ key,
+                                                        const int *__restrict__ cnew,
                                                         const uint32_t *__restrict__ tmpid, Soa3c xin,
                                                         Soa3c vin, Soa3c pin,
                                                         const uint32_t *__restrict__ tag_in,
                                                         const uint8_t *__restrict__ typ_in, Soa3 xout,
                                                         Soa3 vout, Soa3 pout,
                                                         uint32_t *__restrict__ tag_out,
-                                                        uint8_t *__restrict__ typ_out,
-                                                        const int *__restrict__ gate, int *__restrict__ dmap)
+                                                        uint8_t *__restrict__ typ_out, int *__restrict__ dmap,
+                                                        int all)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t tg = tag_in[i];
-    int dst = i;
-    if (!(gate && *gate == 0)) {
-        const int c = key[i];
-        const int b = cstart[c], e = cstart[c + 1];
-        const uint32_t id = tg & kIdMask;
-        int rank = 0;
-        for (int k = b; k < e; ++k) rank += tmpid[k] < id ? 1 : 0;
-        dst = b + rank;
+    const int *boff = R.blk_off;  // lane count 1
+    const int r = __builtin_amdgcn_readfirstlane(find_rep(boff, R.nrep, blockIdx.x));
+    const int i = cload(R.part_off, r) + (blockIdx.x - cload(boff, r)) * kBlock + threadIdx.x;
+    if (i >= cload(R.part_off, r + 1)) return;
+    if (!all && cload(R.flag, r) == 0) {
+        if (dmap) dmap[i] = i;
+        return;
     }
+    const uint32_t tg = tag_in[i];
+    const int c = key[i];
+    const int b = cnew[c], e = cnew[c + 1];
+    const uint32_t id = tg & kIdMask;
+    int rank = 0;
+    for (int k = b; k < e; ++k) rank += tmpid[k] < id ? 1 : 0;
+    const int dst = b + rank;
     if (dmap) dmap[i] = dst;
     xout.x[dst] = xin.x[i];
     xout.y[dst] = xin.y[i];
@@ -213,6 +234,95 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(int n, const int *__rest
     }
     tag_out[dst] = tg;
     typ_out[dst] = typ_in[i];
+}
+
+// The sorted temporaries of rebuilt replicas back in place; the positions
+// also become the build positions (xb, unless NULL).
+__global__ __launch_bounds__(kBlock) void k_copy_back(Reps R, Soa3c tx, Soa3c tv, Soa3c tp,
+                                                      const uint32_t *__restrict__ ttag,
+                                                      const uint8_t *__restrict__ ttyp, Soa3 x, Soa3 v,
+                                                      Soa3 p, uint32_t *__restrict__ tag,
+                                                      uint8_t *__restrict__ typ, Soa3 xb)
+{
+    const int *boff = R.blk_off;  // lane count 1
+    const int r = __builtin_amdgcn_readfirstlane(find_rep(boff, R.nrep, blockIdx.x));
+    if (cload(R.flag, r) == 0) return;
+    const int i = cload(R.part_off, r) + (blockIdx.x - cload(boff, r)) * kBlock + threadIdx.x;
+    if (i >= cload(R.part_off, r + 1)) return;
+    const double px = tx.x[i], py = tx.y[i], pz = tx.z[i];
+    x.x[i] = px;
+    x.y[i] = py;
+    x.z[i] = pz;
+    if (xb.x) {
+        xb.x[i] = px;
+        xb.y[i] = py;
+        xb.z[i] = pz;
+    }
+    v.x[i] = tv.x[i];
+    v.y[i] = tv.y[i];
+    v.z[i] = tv.z[i];
+    if (tp.x) {
+        p.x[i] = tp.x[i];
+        p.y[i] = tp.y[i];
+        p.z[i] = tp.z[i];
+    }
+    tag[i] = ttag[i];
+    typ[i] = ttyp[i];
+}
+
+// The gate: one block per replica takes the maximum of its force blocks'
+// maxima; the last block to finish (a counter, reset by that block) forms
+// the OR of the flags and does the once-per-step bookkeeping.
+__global__ __launch_bounds__(kBlock) void k_gate(Reps R, int lane_idx, const float *__restrict__ bmax,
+                                                 int *__restrict__ force, int *__restrict__ flags,
+                                                 int *__restrict__ done, uint32_t *__restrict__ step_ctr,
+                                                 int *__restrict__ ovf_count, unsigned long long *__restrict__ nbuild,
+                                                 int first)
+{
+    __shared__ float red[kWaves];
+    __shared__ int last;
+    const int r = blockIdx.x;
+    const int *off = R.blk_off + lane_idx * (R.nrep + 1);
+    float m = 0.0f;
+    for (int k = cload(off, r) + (int)threadIdx.x; k < cload(off, r + 1); k += kBlock) m = fmaxf(m, bmax[k]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kWaves; ++w) m = fmaxf(m, red[w]);
+        const Geom g = cload(R.geom, r);
+        // the second gate of a step rebuilds only for a particle that was
+        // moved back at all (with skin 0 the threshold is 0)
+        const bool far = (double)m >= g.gate2 && (first || m > 0.0f);
+        const int f = (__hip_atomic_load(force, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || far) ? 1 : 0;
+        __hip_atomic_store(&flags[r], f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        last = atomicAdd(done, 1) == R.nrep - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    int any = 0;
+    for (int q = (int)threadIdx.x; q < R.nrep; q += kBlock)
+        any += __hip_atomic_load(&flags[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) any += __shfl_xor(any, o, 64);
+    __shared__ int tot[kWaves];
+    if ((threadIdx.x & 63) == 0) tot[threadIdx.x >> 6] = any;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int sum = 0;
+        for (int w = 0; w < kWaves; ++w) sum += tot[w];
+        flags[R.nrep] = sum > 0 ? 1 : 0;
+        *nbuild += (unsigned long long)sum;
+        *force = 0;
+        *done = 0;
+        if (first) {
+            *step_ctr += 1;  // noise step of this step's force pass
+            *ovf_count = 0;  // the force pass of this step refills it
+        }
+    }
 }
 
 // Input arrays (AoS n x 3, caller order: replica after replica) to SoA
@@ -264,12 +374,16 @@ __global__ void k_zero_int(int *p, int n)
     if (i < n) p[i] = 0;
 }
 
+__global__ void k_set_int(int *p, int v) { *p = v; }
+
 }  // namespace
 
 void launch_zero_int(hipStream_t st, int *p, int n)
 {
     if (n > 0) k_zero_int<<<blocks_for(n), kBlock, 0, st>>>(p, n);
 }
+
+void launch_set_int(hipStream_t st, int *p, int v) { k_set_int<<<1, 1, 0, st>>>(p, v); }
 
 void launch_ingest(hipStream_t st, const Reps &R, const double *pos, const double *vel, const int32_t *type,
                    const uint8_t *frozen, Soa3 xp, Soa3 vp, uint32_t *tag, uint8_t *typ, int *status)
@@ -278,22 +392,11 @@ void launch_ingest(hipStream_t st, const Reps &R, const double *pos, const doubl
     k_ingest<<<R.nblk[0], kBlock, 0, st>>>(R, pos, vel, type, frozen, xp, vp, tag, typ, status);
 }
 
-void launch_sort(hipStream_t st, int n, const Reps &R, Soa3c xin, Soa3c vin, Soa3c xprev_in,
-                 const uint32_t *tag_in, const uint8_t *typ_in, Soa3 xout, Soa3 vout, Soa3 xprev_out,
-                 uint32_t *tag_out, uint8_t *typ_out, int *key, int *slot, uint32_t *tmpid, int *counts,
-                 int *cstart, int *bsum, const int *gate, int *ovf_count, uint32_t *step_ctr, int *dmap)
+void launch_gate(hipStream_t st, const Reps &R, int lanes, const float *bmax, int *force, int *flags, int *done,
+                 uint32_t *step_ctr, int *ovf_count, unsigned long long *nbuild, bool first)
 {
-    const int m = R.ncells;
-    const int nb = (m + kScanTile - 1) / kScanTile;
-    if (n > 0) k_bin<<<R.nblk[0], kBlock, 0, st>>>(R, xin, key, slot, counts, gate, ovf_count, step_ctr);
-    k_scan_local<<<nb, kScanThreads, 0, st>>>(m, counts, cstart, bsum, gate);
-    k_scan_add<<<nb, kScanThreads, 0, st>>>(m, nb, bsum, cstart, gate);
-    if (n > 0) {
-        k_scatter_id<<<blocks_for(n), kBlock, 0, st>>>(n, key, slot, cstart, tag_in, tmpid, gate);
-        k_rank_gather<<<blocks_for(n), kBlock, 0, st>>>(n, key, cstart, tmpid, xin, vin, xprev_in,
-                                                        tag_in, typ_in, xout, vout, xprev_out, tag_out,
-                                                        typ_out, gate, dmap);
-    }
+    k_gate<<<R.nrep, kBlock, 0, st>>>(R, lanes_index(lanes), bmax, force, flags, done, step_ctr, ovf_count, nbuild,
+                                      first ? 1 : 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_compose(int n, const int *__restrict__ a, const int *__restrict__ b,
@@ -306,6 +409,29 @@ __global__ __launch_bounds__(kBlock) void k_compose(int n, const int *__restrict
 void launch_compose(hipStream_t st, int n, const int *a, const int *b, int *out)
 {
     if (n > 0) k_compose<<<blocks_for(n), kBlock, 0, st>>>(n, a, b, out);
+}
+
+void launch_rebuild_sort(hipStream_t st, int n, const Reps &R, Soa3 x, Soa3 v, Soa3 xprev, uint32_t *tag,
+                         uint8_t *typ, Soa3 tx, Soa3 tv, Soa3 tp, uint32_t *ttag, uint8_t *ttyp, Soa3 xbuild,
+                         int *key, int *slot, uint32_t *tmpid, int *counts, int *cnew, int *cstart, int *bsum,
+                         int *dmap, bool copy_back, uint32_t *step_ctr, int *ovf_count, unsigned long long *nbuild)
+{
+    const int m = R.ncells;
+    const int nb = (m + kScanTile - 1) / kScanTile;
+    const int all = copy_back ? 0 : 1;
+    if (n > 0) k_bin<<<R.nblk[0], kBlock, 0, st>>>(R, cview(x), key, slot, counts, all, step_ctr, ovf_count, nbuild);
+    k_scan_local<<<nb, kScanThreads, 0, st>>>(R, m, counts, cnew, bsum, all);
+    k_scan_add<<<nb, kScanThreads, 0, st>>>(R, m, nb, bsum, cnew, cstart, all);
+    if (n > 0) {
+        const Soa3c none{nullptr, nullptr, nullptr};
+        k_scatter_id<<<blocks_for(n), kBlock, 0, st>>>(R, n, key, slot, cnew, tag, tmpid, all);
+        k_rank_gather<<<R.nblk[0], kBlock, 0, st>>>(R, key, cnew, tmpid, cview(x), cview(v),
+                                                    xprev.x ? cview(xprev) : none, tag, typ, tx, tv, tp, ttag,
+                                                    ttyp, dmap, all);
+        if (copy_back)
+            k_copy_back<<<R.nblk[0], kBlock, 0, st>>>(R, cview(tx), cview(tv), xprev.x ? cview(tp) : none, ttag,
+                                                      ttyp, x, v, xprev, tag, typ, xbuild);
+    }
 }
 
 }  // namespace mdpd

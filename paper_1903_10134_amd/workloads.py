@@ -23,8 +23,8 @@ Workloads (all in DPD units, r_c = 1):
 * ``replicas``  independent periodic boxes with edges uniform in [8, 12],
                 A ~ U[-50, -30], B ~ U[20, 30], one random stream per replica.
 * ``ring_cells`` the manufactured homogeneous porous medium of Sec. 5.1 (the
-                paper's scaling benchmark): 16 x 2 x 16 cells with a ring wall,
-                stacked twice along y; 16 x 16 cells hold ~1M particles.
+                paper's scaling benchmark): 16 x 2 x 16 cells with a ring wall;
+                23 x 23 cells (one layer) hold ~1.04M particles.
 * ``slit_pore`` the static contact-angle set-up of Sec. 4.2: a 60 x 10 x 5
                 box, 3,500 frozen particles in two wall layers of thickness
                 r_c (y in [0, 1) and [9, 10), uniform random), 4,000 fluid
@@ -238,16 +238,17 @@ def slit_pore(A_SL=-35.0, seed=0, n_solid=3500, n_fluid=4000, B=25.0, gamma=4.5,
                     info=dict(n_fluid=n_fluid, n_wall=n_solid, pore_y=(1.0, 9.0)))
 
 
-def ring_cells(n=16, layers=2, seed=0, solid_density=8.0, fluid_density=6.2, gz=0.02, B=25.0, gamma=4.5,
+def ring_cells(n=23, layers=1, seed=0, solid_density=8.0, fluid_density=6.2, gz=0.02, B=25.0, gamma=4.5,
                kT=1.0, dt=0.01):
     """Sec. 5.1 manufactured homogeneous porous medium: square cells of
     16 x 2 x 16 (x, y, z), each with a ring-shaped solid wall (outer radius 7,
     inner radius 6, axis along y) at number density 8 and fluid at density 6.2
     outside the ring; n x n cells in the x-z plane, the cells of every other
     row (in z) shifted by half a cell in x; periodic in all directions, body
-    force g_z on the fluid.  The paper's cell is 2 thick in y; ``layers``
-    copies of it are stacked along y (the cell list needs at least three
-    cells of r_c per axis).  Particles are placed uniformly at random in
+    force g_z on the fluid.  The paper's cell is 2 thick in y (one layer);
+    ``layers`` copies of it can be stacked along y.  23 x 23 cells of one
+    layer (about 1.04 M particles) are the per-GPU size of the paper's weak
+    scaling runs.  Particles are placed uniformly at random in
     their regions (the paper equilibrates them first).  Types: fluid 0, solid
     1, A = -40 between all pairs, B = 25, r_d = 0.75."""
     rng = np.random.Generator(np.random.PCG64(seed))

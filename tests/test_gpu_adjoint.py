@@ -58,10 +58,10 @@ def table_dirs(T):
     return out
 
 
-def check(mdpd, w, prec, nsteps, every, avg, tol):
+def check(mdpd, w, prec, nsteps, every, avg, tol, skin=None):
     p = mdpd.FP32_FORCES if prec == "fp32" else mdpd.FP64
     op = orc_params(w)
-    s = mdpd.System(w, precision=p)
+    s = mdpd.System(w, precision=p, skin=skin)
     loss = s.forward_record(nsteps, every=every, average=avg)
     n = w.x.shape[0]
     T = np.atleast_2d(w.A).shape[0]
@@ -92,6 +92,14 @@ def check(mdpd, w, prec, nsteps, every, avg, tol):
 def test_adjoint_matches_oracle_tangent_fp64(mdpd, name, avg):
     say("adjoint fp64", name, "avg" if avg else "final")
     check(mdpd, CASES[name], "fp64", nsteps=5, every=2, avg=avg, tol=1e-8)
+
+
+@pytest.mark.parametrize("name", ["bulk_L6", "channel_walls"])
+def test_adjoint_with_skin_list(mdpd, name):
+    """A skin list (rebuilt only when particles have moved half the skin)
+    records the same trajectory and so the same derivative."""
+    say("adjoint fp64 skin", name)
+    check(mdpd, CASES[name], "fp64", nsteps=8, every=3, avg=True, tol=1e-8, skin=0.3)
 
 
 def test_adjoint_fp32_form(mdpd):

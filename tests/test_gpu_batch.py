@@ -39,19 +39,22 @@ def split(arr, offsets):
     return [arr[offsets[r]:offsets[r + 1]] for r in range(len(offsets) - 1)]
 
 
+@pytest.mark.parametrize("skin", [0.0, 0.3])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batch_equals_standalone_bitwise(mdpd, prec):
+def test_batch_equals_standalone_bitwise(mdpd, prec, skin):
+    """With a skin every replica decides its own list rebuilds, so a replica
+    in a batch still steps bit for bit like the same system alone."""
     reps = uneven_replicas()
     p = mdpd.FP32_FORCES if prec == "fp32" else mdpd.FP64
-    say("batch vs standalone", prec, len(reps), "replicas")
-    b = mdpd.Batch(reps, precision=p)
+    say("batch vs standalone", prec, len(reps), "replicas, skin", skin)
+    b = mdpd.Batch(reps, precision=p, skin=skin)
     b.step(6)
     xb, vb, rb = b.state()
     Fb = b.forces()
     ob = b.observables()
     cb, hb = b.neighbors(1.0)
     for r, w in enumerate(reps):
-        s = mdpd.System(w, precision=p)
+        s = mdpd.System(w, precision=p, skin=skin)
         s.step(6)
         x, v, rho = s.state()
         sl = slice(b.offsets[r], b.offsets[r + 1])

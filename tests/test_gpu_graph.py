@@ -28,12 +28,15 @@ def same(a, b):
     assert np.array_equal(a.forces(), b.forces())
 
 
+@pytest.mark.parametrize("skin", [0.0, 0.3])
 @pytest.mark.parametrize("case", ["bulk_L10_n6000", "mixed_types", "small_channel"])
-def test_graph_equals_eager(mdpd, case):
+def test_graph_equals_eager(mdpd, case, skin):
+    """Replays equal eager stepping bit for bit; with a skin the list
+    rebuilds are decided on the device inside the replays too."""
     w = small_channel() if case == "small_channel" else CASES[case]
-    say("graph", case)
-    g = mdpd.System(w, precision=mdpd.FP32_FORCES)
-    e = mdpd.System(w, precision=mdpd.FP32_FORCES)
+    say("graph", case, "skin", skin)
+    g = mdpd.System(w, precision=mdpd.FP32_FORCES, skin=skin)
+    e = mdpd.System(w, precision=mdpd.FP32_FORCES, skin=skin)
     g.set_graph(True)
     for chunk in (4, 3, 6, 1, 2):  # replays, odd remainders run eagerly
         g.step(chunk)

@@ -99,6 +99,8 @@ def small_cases():
         "ragged_L7.3_n1000": W.bulk(L=7.3, n=1000, seed=1),
         "three_cells_L3.2": W.bulk(L=3.2, n=150, seed=2),
         "box_5x3.5x8.25": W.bulk(box=(5.0, 3.5, 8.25), n=900, seed=3),
+        "two_cells_2x2.5x7": W.bulk(box=(2.0, 2.5, 7.0), n=210, seed=6),
+        "slab_10x2x10": W.bulk(box=(10.0, 2.0, 10.0), n=1200, seed=7),
         "dense_cluster": dense_cluster(),
         "mixed_types": mixed_types(),
     }
@@ -147,18 +149,40 @@ def test_density_and_forces_step0_and_step1(mdpd, name, precision):
     s.close()
 
 
-def test_short_trajectory_fp64(mdpd):
+@pytest.mark.parametrize("skin", [0.0, 0.1, 0.3, 0.6, 1.0])
+def test_short_trajectory_fp64(mdpd, skin):
+    """20 steps from the uniform-random start (hot: kT about 5), with list
+    skins from none (a build every step) to one r_c (most skin rows then
+    exceed their capacity and those particles take the direct cell scan):
+    the pair sets are those of the oracle at every step, so the trajectory
+    stays within rounding of it; every fourth step the sets at r_c and r_d
+    are compared bit for bit."""
     w = CASES["bulk_L10_n6000"]
-    say("trajectory 20 steps", w.name)
-    s = mdpd.System(w)
+    say("trajectory 20 steps", w.name, "skin", skin)
+    s = mdpd.System(w, skin=skin)
     o = oracle.System(orc_params(w), w.x, w.v)
-    s.step(20)
-    o.step(20)
+    p = orc_params(w)
+    for k in range(20):
+        s.step(1)
+        o.step(1)
+        if k % 4 == 3:
+            xo = o.state()["x"]
+            for cut in (w.rc, w.rd):
+                c, h = s.neighbors(cut)
+                co, ho = oracle.neighbors(p, xo, cut)
+                assert np.array_equal(c, co) and np.array_equal(h, ho), (k, cut)
     st = o.state()
     x, v, rho = s.state()
     assert pdiff(x, st["x"], w.box) < 1e-10
     assert np.abs(v - st["v"]).max() < 1e-9
     assert force_err(s.forces(), st["F"]) < 1e-9
+    builds = s.list_builds()
+    print(f"\nskin {skin}: {builds} list builds in 21 evaluations")
+    if skin == 0.0:
+        assert builds == 21
+    if 0.3 <= skin <= 0.6:
+        assert builds < 21
+    s.close()
 
 
 @pytest.mark.parametrize("name", ["bulk_L10_n6000", "mixed_types"])
@@ -244,10 +268,10 @@ def test_invalid_inputs_are_rejected(mdpd):
     t[0] = 3
     with pytest.raises(mdpd.MdpdError):
         mdpd.mdpd_create(p, w.x, w.v, t, w.frozen)
-    small = mdpd.make_params(**{**w.param_kwargs(), "box": (2.5, 5.0, 5.0)})
+    small = mdpd.make_params(**{**w.param_kwargs(), "box": (1.99, 5.0, 5.0)})
     with pytest.raises(mdpd.MdpdError) as e:
-        mdpd.mdpd_create(small, w.x * 0.4, w.v, w.types, w.frozen)
-    assert e.value.status == -6
+        mdpd.mdpd_create(small, w.x * 0.39, w.v, w.types, w.frozen)
+    assert e.value.status == -1
     p2 = mdpd.make_params(**{**w.param_kwargs(), "rd": 1.5})
     with pytest.raises(mdpd.MdpdError):
         mdpd.mdpd_create(p2, w.x, w.v, w.types, w.frozen)
@@ -255,6 +279,38 @@ def test_invalid_inputs_are_rejected(mdpd):
     with pytest.raises(mdpd.MdpdError) as e:
         mdpd.mdpd_create(p3, w.x, w.v, w.types, w.frozen)
     assert e.value.status == -1
+
+
+def test_nonfinite_state_is_reported(mdpd):
+    """A non-finite half-step velocity planted in a checkpoint (the layout of
+    mdpd_save_checkpoint: header and parameters, then 256-byte aligned fields
+    x, v, F, predicted x, predicted half-step v, ...) makes the next
+    mdpd_step return MDPD_E_NONFINITE; a velocity so large that the first
+    predicted move leaves the box makes mdpd_create return it."""
+    import ctypes
+    w = W.bulk(L=5.0, n=600, seed=8)
+    say("non-finite state")
+    s = mdpd.System(w)
+    s.step(2)
+    buf = s.save_checkpoint()
+    al = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    head = al(64 + ctypes.sizeof(mdpd.Params))
+    off = head + 4 * al(24 * w.n)
+    bad = buf.copy()
+    bad[off:off + 8] = np.frombuffer(np.array([np.nan]).tobytes(), np.uint8)
+    s.load_checkpoint(bad)
+    with pytest.raises(mdpd.MdpdError) as e:
+        s.step(1)
+    assert e.value.status == -4
+    s.load_checkpoint(buf)  # the good state steps on
+    s.step(1)
+    s.close()
+    v = w.v.copy()
+    v[7] = (1e200, 0.0, 0.0)
+    p = mdpd.make_params(**w.param_kwargs())
+    with pytest.raises(mdpd.MdpdError) as e:
+        mdpd.mdpd_create(p, w.x, v, w.types, w.frozen)
+    assert e.value.status == -4
 
 
 def test_device_inputs_equal_host_inputs(mdpd):
@@ -320,12 +376,13 @@ def small_channel(seed=7):
     return W.channel(Lx=8.0, Ly=6.0, Lz=8.0, wall=2.0, seed=seed, gx=0.05)
 
 
+@pytest.mark.parametrize("skin", [0.0, 0.3])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_wall_corrector_parity(mdpd, precision):
+def test_wall_corrector_parity(mdpd, precision, skin):
     w = small_channel()
-    say("walls", precision, w.n)
+    say("walls", precision, w.n, "skin", skin)
     prec = mdpd.FP64 if precision == "fp64" else mdpd.FP32_FORCES
-    s = mdpd.System(w, precision=prec)
+    s = mdpd.System(w, precision=prec, skin=skin)
     o = oracle.System(orc_params(w), w.x, w.v, w.types, w.frozen)
     total = 0
     for k in range(12):
@@ -360,10 +417,11 @@ def test_profiles_match_oracle(mdpd):
             assert np.allclose(pa, pb, rtol=1e-9, atol=1e-10), (axis, q, pa, pb)
 
 
-@pytest.mark.parametrize("case,prec", [("bulk_L10_n6000", "fp32"), ("dense_cluster", "fp64"),
-                                       ("small_channel", "fp64"), ("small_channel", "fp32"),
-                                       ("slip_channel", "fp32")])
-def test_checkpoint_resume_bitwise(mdpd, case, prec):
+@pytest.mark.parametrize("case,prec,skin", [("bulk_L10_n6000", "fp32", 0.0), ("dense_cluster", "fp64", 0.0),
+                                            ("small_channel", "fp64", 0.0), ("small_channel", "fp32", 0.0),
+                                            ("slip_channel", "fp32", 0.0), ("bulk_L10_n6000", "fp32", 0.3),
+                                            ("small_channel", "fp64", 0.3)])
+def test_checkpoint_resume_bitwise(mdpd, case, prec, skin):
     """A checkpoint loaded into a fresh system continues bit for bit: state,
     forces, observables and neighbour sets after more steps."""
     if case == "slip_channel":
@@ -372,13 +430,13 @@ def test_checkpoint_resume_bitwise(mdpd, case, prec):
     else:
         w = small_channel() if case == "small_channel" else CASES[case]
     p = mdpd.FP32_FORCES if prec == "fp32" else mdpd.FP64
-    say("checkpoint", case, prec)
-    a = mdpd.System(w, precision=p)
+    say("checkpoint", case, prec, "skin", skin)
+    a = mdpd.System(w, precision=p, skin=skin)
     a.step(7)
     buf = a.save_checkpoint()
     obs0 = a.observables()
     a.step(9)
-    b = mdpd.System(w, precision=p)  # same parameters, fresh state at step 0
+    b = mdpd.System(w, precision=p, skin=skin)  # same parameters, fresh state at step 0
     b.load_checkpoint(buf)
     assert b.observables() == obs0
     b.step(9)
