@@ -65,8 +65,6 @@ def lib():
         d, u8, i32, i64, u64 = (ctypes.c_double, ctypes.c_uint8, ctypes.c_int32,
                                 ctypes.c_int64, ctypes.c_uint64)
         L.orc_threefry2x32_20.argtypes = [P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)]
-        L.orc_threefry2x32.argtypes = [P(ctypes.c_uint32), P(ctypes.c_uint32), ctypes.c_int,
-                                       P(ctypes.c_uint32)]
         L.orc_theta.argtypes = [ctypes.c_uint32] * 4
         L.orc_theta.restype = d
         L.orc_theta_many.argtypes = [ctypes.c_uint32, ctypes.c_uint32, i64, P(ctypes.c_uint32),
@@ -151,15 +149,6 @@ def threefry2x32_20(ctr, key):
     lib().orc_threefry2x32_20(c, k, o)
     return int(o[0]), int(o[1])
 
-
-
-def threefry2x32(ctr, key, rounds):
-    """Threefry-2x32 with the given number of rounds."""
-    c = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in ctr])
-    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
-    o = (ctypes.c_uint32 * 2)()
-    lib().orc_threefry2x32(c, k, int(rounds), o)
-    return (int(o[0]), int(o[1]))
 
 def theta(seed, step, i, j) -> float:
     return float(lib().orc_theta(seed & 0xFFFFFFFF, step & 0xFFFFFFFF, i, j))

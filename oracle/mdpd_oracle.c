@@ -32,10 +32,8 @@
  * Readings where the paper is silent (each is listed with its reason in the
  * design notes of the repository):
  *   R1  xi_ij = theta_ij / sqrt(dt), theta uniform on [-sqrt3, sqrt3] (zero
- *       mean, unit variance), drawn from Threefry-2x32 with 13 rounds
- *       (Salmon et al., SC'11: the Crush-resistant round count they give for
- *       this generator; their default of 20 adds a safety margin) with key
- *       (seed, step) and counter (min(i,j), max(i,j)).
+ *       mean, unit variance), drawn from Threefry-2x32-20 (Salmon et al.,
+ *       SC'11) with key (seed, step) and counter (min(i,j), max(i,j)).
  *   R2  The dissipative force uses the half-step velocity of the standard
  *       velocity-Verlet loop; frozen particles have v = 0.
  *   R3  Cutoffs are strict (r < r_c, r < r_d); a coincident pair (r = 0)
@@ -77,18 +75,13 @@ typedef struct {
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
-/* Threefry-2x32 with a given number of rounds (Salmon, Moraes, Dror, Shaw,  */
-/* SC'11).  Key schedule: ks2 = 0x1BD11BDA ^ k0 ^ k1; key injection after    */
-/* every four rounds adds ks[s%3], ks[(s+1)%3] and the injection counter s.  */
-/* The pair noise uses 13 rounds, the round count the authors              */
-/* give as Crush-resistant for Threefry-2x32 (their default of 20 adds a    */
-/* safety margin); the same routine at 20 rounds reproduces the published   */
-/* known-answer vectors.                                                    */
+/* Threefry-2x32 with 20 rounds (Salmon, Moraes, Dror, Shaw, SC'11).         */
+/* Key schedule: ks2 = 0x1BD11BDA ^ k0 ^ k1; key injection after every four  */
+/* rounds adds ks[s%3], ks[(s+1)%3] and the injection counter s.             */
 /* ------------------------------------------------------------------------ */
-#define ORC_NOISE_ROUNDS 13
 static uint32_t orc_rotl32(uint32_t x, unsigned r) { return (x << r) | (x >> (32u - r)); }
 
-void orc_threefry2x32(const uint32_t ctr[2], const uint32_t key[2], int rounds, uint32_t out[2])
+void orc_threefry2x32_20(const uint32_t ctr[2], const uint32_t key[2], uint32_t out[2])
 {
     static const unsigned rot[8] = {13, 15, 26, 6, 17, 29, 16, 24};
     uint32_t ks[3];
@@ -97,7 +90,7 @@ void orc_threefry2x32(const uint32_t ctr[2], const uint32_t key[2], int rounds, 
     ks[2] = 0x1BD11BDAu ^ key[0] ^ key[1];
     uint32_t x0 = ctr[0] + ks[0];
     uint32_t x1 = ctr[1] + ks[1];
-    for (int r = 0; r < rounds; ++r) {
+    for (int r = 0; r < 20; ++r) {
         x0 += x1;
         x1 = orc_rotl32(x1, rot[r % 8]);
         x1 ^= x0;
@@ -111,13 +104,6 @@ void orc_threefry2x32(const uint32_t ctr[2], const uint32_t key[2], int rounds, 
     out[1] = x1;
 }
 
-/* The 20-round generator (the rounds of the published known-answer
- * vectors). */
-void orc_threefry2x32_20(const uint32_t ctr[2], const uint32_t key[2], uint32_t out[2])
-{
-    orc_threefry2x32(ctr, key, 20, out);
-}
-
 /* theta_ij: the first output word of Threefry with key (seed, step) and
  * counter (min id, max id); its top 24 bits k give the odd-centred uniform
  * t = (2k + 1 - 2^24) / 2^24 in (-1, 1), exact in binary, and
@@ -129,7 +115,7 @@ double orc_theta(uint32_t seed, uint32_t step, uint32_t i, uint32_t j)
     ctr[1] = i < j ? j : i;
     key[0] = seed;
     key[1] = step;
-    orc_threefry2x32(ctr, key, ORC_NOISE_ROUNDS, out);
+    orc_threefry2x32_20(ctr, key, out);
     double k = (double)(out[0] >> 8);
     double t = (2.0 * k + 1.0 - 16777216.0) / 16777216.0;
     return sqrt(3.0) * t;

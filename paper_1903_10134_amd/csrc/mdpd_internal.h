@@ -85,7 +85,7 @@ struct PairConst {
     int ntypes;
     uint32_t seed;      // key word 0 of the pair noise
     uint32_t ks0, ks1;  // Threefry key words added to the counter
-    uint32_t inj0[3], inj1[3];  // Threefry key injections after rounds 4, 8 and 12
+    uint32_t inj0[5], inj1[5];  // Threefry key injections after rounds 4, 8, ..., 20
 };
 
 // Replicas: independent periodic systems stored back to back.  Replica r
@@ -142,15 +142,14 @@ __device__ __forceinline__ int find_rep(const int *__restrict__ off, int nrep, i
 }
 
 // Threefry key schedule for key (seed, step): ks2 = 0x1BD11BDA ^ k0 ^ k1 and
-// the injection after rounds 4s adds (ks[s % 3], ks[(s + 1) % 3] + s); the
-// 13-round generator of the pair noise injects after rounds 4, 8 and 12.
+// the injection after rounds 4s adds (ks[s % 3], ks[(s + 1) % 3] + s).
 __host__ __device__ inline void set_noise_keys(PairConst &pc, uint32_t step)
 {
     const uint32_t k0 = pc.seed, k1 = step;
     const uint32_t ks[3] = {k0, k1, 0x1BD11BDAu ^ k0 ^ k1};
     pc.ks0 = ks[0];
     pc.ks1 = ks[1];
-    for (uint32_t s = 1; s <= 3; ++s) {
+    for (uint32_t s = 1; s <= 5; ++s) {
         pc.inj0[s - 1] = ks[s % 3];
         pc.inj1[s - 1] = ks[(s + 1) % 3] + s;
     }
@@ -204,11 +203,10 @@ __device__ __forceinline__ double rsqrt_f64(double a)
 
 __device__ __forceinline__ uint32_t rotl32(uint32_t x, int r) { return (x << r) | (x >> (32 - r)); }
 
-// First output word of Threefry-2x32 with 13 rounds (Salmon et al., SC'11:
-// the Crush-resistant round count they give for this generator), counter
-// (c0, c1); the key enters through ks0, ks1 and the three injections
+// First output word of Threefry-2x32 with 20 rounds (Salmon et al., SC'11),
+// counter (c0, c1); the key enters through ks0, ks1 and the five injections
 // precomputed on the host from (seed, step).
-__device__ __forceinline__ uint32_t threefry2x32_13_w0(uint32_t c0, uint32_t c1, const PairConst &k)
+__device__ __forceinline__ uint32_t threefry2x32_20_w0(uint32_t c0, uint32_t c1, const PairConst &k)
 {
     uint32_t x0 = c0 + k.ks0, x1 = c1 + k.ks1;
 #define MDPD_TF_ROUND(R) \
@@ -221,7 +219,10 @@ __device__ __forceinline__ uint32_t threefry2x32_13_w0(uint32_t c0, uint32_t c1,
     x0 += k.inj0[1]; x1 += k.inj1[1];
     MDPD_TF_ROUND(13) MDPD_TF_ROUND(15) MDPD_TF_ROUND(26) MDPD_TF_ROUND(6)
     x0 += k.inj0[2]; x1 += k.inj1[2];
-    x0 += x1;  // round 13 (rotation 17): its second word is not used
+    MDPD_TF_ROUND(17) MDPD_TF_ROUND(29) MDPD_TF_ROUND(16) MDPD_TF_ROUND(24)
+    x0 += k.inj0[3]; x1 += k.inj1[3];
+    MDPD_TF_ROUND(13) MDPD_TF_ROUND(15) MDPD_TF_ROUND(26) MDPD_TF_ROUND(6)
+    x0 += k.inj0[4];
 #undef MDPD_TF_ROUND
     return x0;
 }
@@ -233,7 +234,7 @@ __device__ __forceinline__ int theta_int(uint32_t ida, uint32_t idb, const PairC
 {
     uint32_t lo = ida < idb ? ida : idb;
     uint32_t hi = ida < idb ? idb : ida;
-    uint32_t w = threefry2x32_13_w0(lo, hi, k);
+    uint32_t w = threefry2x32_20_w0(lo, hi, k);
     return (int)((w >> 8) << 1) + 1 - 16777216;
 }
 

@@ -34,20 +34,6 @@ def test_threefry_known_answer_vectors(orc):
         assert orc.threefry2x32_20(ctr, key) == out
 
 
-
-def test_noise_uses_thirteen_rounds(orc):
-    """The pair noise takes the first word of the same Threefry routine at 13
-    rounds (reading R1): theta = sqrt(3) (2k + 1 - 2^24) / 2^24 with k its top
-    24 bits, counter (min id, max id), key (seed, step); 20 rounds give the
-    known-answer vectors above and another noise."""
-    for seed, step, i, j in ((0, 0, 0, 1), (7, 123, 900, 5), (0xFFFFFFFF, 4, 2 ** 31 - 2, 3)):
-        w13 = orc.threefry2x32((min(i, j), max(i, j)), (seed, step), 13)[0]
-        w20 = orc.threefry2x32((min(i, j), max(i, j)), (seed, step), 20)[0]
-        t = (2.0 * (w13 >> 8) + 1.0 - 16777216.0) / 16777216.0
-        assert orc.theta(seed, step, i, j) == pytest.approx(3 ** 0.5 * t, rel=0, abs=1e-15)
-        assert w13 != w20
-    assert orc.threefry2x32((0, 0), (0, 0), 20) == orc.threefry2x32_20((0, 0), (0, 0))
-
 def test_theta_symmetric_keyed_and_unit_variance(orc):
     rng = np.random.default_rng(5)
     i = rng.integers(0, 2**31 - 1, 400_000, dtype=np.int64)
