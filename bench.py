@@ -68,9 +68,9 @@ BYTES_LIST = 24
 # (SQ_INSTS_VALU, wave instructions).  Valid for the kernels as profiled;
 # they are re-measured whenever a kernel changes.
 PROFILED = {
-    "nlist": {"read": 86755077, "write": 183474370, "valu_wave_instr": 108.6e6},
-    "force": {"read": 414502751, "write": 101510304, "valu_wave_instr": 85.8e6},
-    "density": {"read": 195000000, "write": 71700000, "valu_wave_instr": 10.9e6},
+    "nlist": {"read": 86777856, "write": 181341184, "valu_wave_instr": 107.1e6},
+    "force": {"read": 400467968, "write": 101454848, "valu_wave_instr": 80.7e6},
+    "density": {"read": 194996224, "write": 71652352, "valu_wave_instr": 12.4e6},
 }
 
 
