@@ -49,6 +49,8 @@ class Params(ctypes.Structure):
         ("ntypes", ctypes.c_int32),
         ("wall_model", ctypes.c_int32),
         ("search", ctypes.c_int32),
+        ("diss_ctrl", ctypes.c_double),
+        ("diss_rho", ctypes.c_double),
     ]
 
 
@@ -78,6 +80,7 @@ def lib():
         L.orc_neighbors.argtypes = [P(Params), i64, P(d), d, P(i64), P(u64)]
         L.orc_density.argtypes = [P(Params), i64, P(d), P(d)]
         L.orc_phi.argtypes = [P(Params), i64, P(d), P(u8), P(d)]
+        L.orc_diss_scale.argtypes = [P(Params), i64, P(d), P(u8), P(d)]
         L.orc_forces.argtypes = [P(Params), i64, P(d), P(d), P(i32), P(u8), P(d), ctypes.c_uint32,
                                  P(d), P(d), P(d)]
         L.orc_create.argtypes = [P(Params), i64, P(d), P(d), P(i32), P(u8)]
@@ -106,8 +109,10 @@ def _ptr(a, ct):
 
 
 def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=(0.0, 0.0, 0.0),
-                seed=0, wall_model=0, phi_c=0.5, search=0, wall_slip=0.0) -> Params:
-    """Build the oracle's parameter block.  A, B, gamma: scalars or T x T."""
+                seed=0, wall_model=0, phi_c=0.5, search=0, wall_slip=0.0, diss_ctrl=0.0,
+                diss_rho=0.0) -> Params:
+    """Build the oracle's parameter block.  A, B, gamma: scalars or T x T.
+    diss_ctrl, diss_rho: the dissipation control (eta, rho_f) of reading R6."""
     A = np.atleast_2d(np.asarray(A, dtype=np.float64))
     B = np.atleast_2d(np.asarray(B, dtype=np.float64))
     G = np.atleast_2d(np.asarray(gamma, dtype=np.float64))
@@ -120,6 +125,8 @@ def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=
     p.g[:] = [float(v) for v in g]
     p.phi_c = phi_c
     p.wall_slip = float(wall_slip)
+    p.diss_ctrl = float(diss_ctrl)
+    p.diss_rho = float(diss_rho)
     for name, M in (("A", A), ("B", B), ("gamma", G)):
         arr = getattr(p, name)
         for a in range(T):
@@ -202,6 +209,16 @@ def phi(p: Params, x, frozen):
     out = np.zeros(x.shape[0])
     lib().orc_phi(ctypes.byref(p), x.shape[0], _ptr(x, ctypes.c_double), _ptr(fz, ctypes.c_uint8),
                   _ptr(out, ctypes.c_double))
+    return out
+
+
+def diss_scale(p: Params, x, frozen):
+    """Dissipation-control factors s_i of the fluid-solid pairs (reading R6)."""
+    x = _c3(x)
+    fz = np.ascontiguousarray(np.asarray(frozen, dtype=np.uint8))
+    out = np.zeros(x.shape[0])
+    lib().orc_diss_scale(ctypes.byref(p), x.shape[0], _ptr(x, ctypes.c_double), _ptr(fz, ctypes.c_uint8),
+                         _ptr(out, ctypes.c_double))
     return out
 
 
@@ -309,7 +326,8 @@ def tangent(p: Params, x0, v0, types, frozen, nsteps, w, avg=False, dx0=None, dv
                            _ptr(fz, ctypes.c_uint8), *ptrs, int(nsteps), _ptr(wv, d), 1 if avg else 0,
                            _ptr(out, d))
     if rc != 0:
-        raise ValueError("orc_tangent: walls must be off and nsteps >= 1 with avg")
+        raise ValueError("orc_tangent: needs bounce-back walls or none, no dissipation control, and "
+                         "nsteps >= 1 with avg")
     return float(out[0]), float(out[1])
 
 

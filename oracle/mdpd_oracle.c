@@ -46,6 +46,18 @@
  *       part negated, tangential part times (2 wall_slip - 1); a zero normal
  *       sum falls back to bounce-back.
  *   R5  Mass m; body force acts on fluid as m*g.
+ *   R6  Control of the effective fluid-solid dissipation (Sec. 2.2), on when
+ *       diss_ctrl = eta > 0: for fluid i, the dissipative weight it gets from
+ *       the solid, E_i = sum_{frozen j, r<r_c} w^D(r_ij), is measured and
+ *       brought to the target T_i = eta rho_f W_D phi_i, the weight that
+ *       fluid of number density rho_f (diss_rho) would give from the share
+ *       phi_i (R4) of i's interaction sphere that the solid fills, with
+ *       W_D = integral of w^D over the sphere = 2 pi r_c^3 / 15.  Each
+ *       fluid-solid pair of i then dissipates with gamma s_i and fluctuates
+ *       with sigma sqrt(s_i), s_i = T_i / E_i (sigma^2 = 2 gamma kT holds
+ *       per pair); fluid-fluid pairs keep gamma.  eta = 1 makes the solid as
+ *       dissipative as fluid at rest in its place (no slip); a smaller eta
+ *       lets the fluid slip.  diss_ctrl = 0: s_i = 1.
  * parity pinned: every function here is checked by tests/test_oracle_pins.py,
  * tests/test_oracle_pins_phi_profile.py (boundary volume fraction and bin
  * profiles) and tests/test_oracle_tangent.py against known-answer vectors,
@@ -72,6 +84,8 @@ typedef struct {
     int32_t ntypes;
     int32_t wall_model; /* 0: no wall treatment, 1: phi + predictor-corrector */
     int32_t search;     /* 0: brute force O(N^2), 1: naive linked cells   */
+    double diss_ctrl;   /* reading R6: eta (0: no dissipation control)    */
+    double diss_rho;    /* reading R6: the fluid number density rho_f     */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -392,16 +406,52 @@ void orc_phi(const orc_params *p, int64_t n, const double *x, const uint8_t *fro
     orc_nlist_free(&nl);
 }
 
+/* Dissipation control (reading R6): the factor s_i of the fluid-solid pairs
+ * of every fluid particle i; 1 for frozen particles, for fluid without a
+ * frozen neighbour and when the control is off.  phi: scratch of n. */
+static void orc_diss_scale_nl(const orc_params *p, int64_t n, const double *x, const uint8_t *frozen,
+                              const orc_nlist *nl, double *phi, double *s)
+{
+    const double WD = 2.0 * M_PI * p->rc * p->rc * p->rc / 15.0;
+    orc_phi_nl(p, n, x, frozen, nl, phi);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        s[i] = 1.0;
+        if (frozen[i] || !(p->diss_ctrl > 0.0)) continue;
+        double E = 0.0;
+        for (int32_t k = 0; k < nl->cnt[i]; ++k) {
+            int64_t j = nl->idx[i][k];
+            if (!frozen[j]) continue;
+            double d[3];
+            orc_delta(x, i, j, p->L, d);
+            double w = 1.0 - sqrt(orc_r2(d)) / p->rc;
+            E += w * w;
+        }
+        if (E > 0.0) s[i] = p->diss_ctrl * p->diss_rho * WD * phi[i] / E;
+    }
+}
+
+void orc_diss_scale(const orc_params *p, int64_t n, const double *x, const uint8_t *frozen, double *s)
+{
+    orc_nlist nl;
+    orc_build(x, n, p->L, p->rc, p->search, &nl);
+    double *phi = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+    orc_diss_scale_nl(p, n, x, frozen, &nl, phi, s);
+    free(phi);
+    orc_nlist_free(&nl);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Pair forces (Sec. 2.1, Eq. 1) on every fluid particle; frozen: 0.        */
 /* virial = sum over fluid i, j in N_c(i) of c_ij r_ij F^C_ij, c_ij = 1/2   */
 /* if j is fluid (pair seen from both sides) and 1 if j is frozen; epair is */
 /* the same weighted sum of the A-term pair potential (A r_c / 2) w_c^2.    */
+/* dsc: the dissipation-control factors s_i of reading R6 (NULL: none).     */
 /* ------------------------------------------------------------------------ */
 static void orc_forces_nl(const orc_params *p, int64_t n, const double *x, const double *vh,
                           const int32_t *type, const uint8_t *frozen, const double *rho,
-                          uint32_t step, const orc_nlist *nl, double *F, double *virial,
-                          double *epair)
+                          uint32_t step, const orc_nlist *nl, const double *dsc, double *F,
+                          double *virial, double *epair)
 {
     const int T = p->ntypes;
     const double rc = p->rc, rd = p->rd, rd2 = rd * rd;
@@ -438,6 +488,11 @@ static void orc_forces_nl(const orc_params *p, int64_t n, const double *x, const
             /* random: sigma w^R xi, sigma^2 = 2 gamma kT, xi = theta / sqrt(dt) */
             double sigma = sqrt(2.0 * p->gamma[tt] * p->kT);
             double fr = sigma * wc * orc_theta(p->seed, step, (uint32_t)i, (uint32_t)j) / sqrt(p->dt);
+            if (dsc && frozen[j]) {
+                /* reading R6: gamma s_i and sigma sqrt(s_i) for a fluid-solid pair */
+                fd *= dsc[i];
+                fr *= sqrt(dsc[i]);
+            }
             double fs = fc + fd + fr;
             for (int a = 0; a < 3; ++a) f[a] += fs * e[a];
             double c = frozen[j] ? 1.0 : 0.5;
@@ -458,7 +513,15 @@ void orc_forces(const orc_params *p, int64_t n, const double *x, const double *v
 {
     orc_nlist nl;
     orc_build(x, n, p->L, p->rc, p->search, &nl);
-    orc_forces_nl(p, n, x, vh, type, frozen, rho, step, &nl, F, virial, epair);
+    double *dsc = NULL, *phi = NULL;
+    if (p->diss_ctrl > 0.0) {
+        dsc = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+        phi = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+        orc_diss_scale_nl(p, n, x, frozen, &nl, phi, dsc);
+    }
+    orc_forces_nl(p, n, x, vh, type, frozen, rho, step, &nl, dsc, F, virial, epair);
+    free(dsc);
+    free(phi);
     orc_nlist_free(&nl);
 }
 
@@ -468,7 +531,7 @@ void orc_forces(const orc_params *p, int64_t n, const double *x, const double *v
 typedef struct {
     orc_params p;
     int64_t n, nfluid;
-    double *x, *v, *vh, *F, *rho, *phi, *xprev;
+    double *x, *v, *vh, *F, *rho, *phi, *xprev, *dsc, *phi2;
     int32_t *type;
     uint8_t *frozen;
     uint32_t step;
@@ -482,7 +545,12 @@ static void orc_eval(orc_system *s)
     orc_nlist nl;
     orc_build(s->x, s->n, s->p.L, s->p.rc, s->p.search, &nl);
     orc_density_nl(&s->p, s->n, s->x, &nl, s->rho);
-    orc_forces_nl(&s->p, s->n, s->x, s->vh, s->type, s->frozen, s->rho, s->step, &nl, s->F,
+    const double *dsc = NULL;
+    if (s->p.diss_ctrl > 0.0) {
+        orc_diss_scale_nl(&s->p, s->n, s->x, s->frozen, &nl, s->phi2, s->dsc);
+        dsc = s->dsc;
+    }
+    orc_forces_nl(&s->p, s->n, s->x, s->vh, s->type, s->frozen, s->rho, s->step, &nl, dsc, s->F,
                   &s->virial, &s->epair);
     orc_nlist_free(&nl);
 }
@@ -496,6 +564,8 @@ void orc_destroy(orc_system *s)
     free(s->F);
     free(s->rho);
     free(s->phi);
+    free(s->phi2);
+    free(s->dsc);
     free(s->xprev);
     free(s->type);
     free(s->frozen);
@@ -518,6 +588,8 @@ orc_system *orc_create(const orc_params *p, int64_t n, const double *x, const do
     s->xprev = (double *)malloc(nn * 3 * sizeof(double));
     s->rho = (double *)malloc(nn * sizeof(double));
     s->phi = (double *)calloc(nn, sizeof(double));
+    s->phi2 = (double *)calloc(nn, sizeof(double));
+    s->dsc = (double *)calloc(nn, sizeof(double));
     s->type = (int32_t *)malloc(nn * sizeof(int32_t));
     s->frozen = (uint8_t *)malloc(nn);
     for (int64_t i = 0; i < n; ++i) {
@@ -888,7 +960,9 @@ int orc_tangent(const orc_params *p, int64_t n, const double *x0, const double *
                 const double *dB, const double *dgamma, int64_t nsteps, const double w[3], int avg,
                 double out[2])
 {
-    if ((p->wall_model != 0 && p->wall_slip != 0.0) || nsteps < 0 || (avg && nsteps < 1)) return -1;
+    if ((p->wall_model != 0 && p->wall_slip != 0.0) || p->diss_ctrl != 0.0 || nsteps < 0 ||
+        (avg && nsteps < 1))
+        return -1;
     orc_tan_ctx c = {p, n, type, frozen, dA, dB, dgamma};
     size_t nn = (size_t)(n ? n : 1);
     double *x = (double *)malloc(nn * 3 * sizeof(double)), *dx = (double *)malloc(nn * 3 * sizeof(double));
