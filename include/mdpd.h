@@ -99,6 +99,22 @@ typedef struct {
                           /* pairs closer than r_c + skin are rebuilt only when   */
                           /* a particle has moved skin/2 since the last build     */
                           /* (0: every step); any value gives the same pairs     */
+    double diss_ctrl;     /* control of the effective fluid-solid dissipation    */
+                          /* (Sec. 2.2), eta >= 0; 0 turns it off.  For a fluid   */
+                          /* particle i with frozen neighbours, E_i = sum over    */
+                          /* frozen j within r_c of w_c^2 is brought to the       */
+                          /* target eta diss_rho W_D phi_i (W_D = 2 pi r_c^3 / 15,*/
+                          /* the integral of w_c^2 over the interaction sphere;   */
+                          /* phi_i as for MDPD_WALL_BVF, at the positions of the  */
+                          /* force evaluation): every fluid-frozen pair of i uses */
+                          /* gamma s_i and sigma sqrt(s_i), s_i = target / E_i,   */
+                          /* which equals eta diss_rho W_D / sum_{j != i, r<r_c}  */
+                          /* w_c^2.  eta = 1: the solid dissipates like fluid at  */
+                          /* rest of density diss_rho in its place (no slip);     */
+                          /* smaller eta lets the fluid slip.  Independent of     */
+                          /* wall_model.                                          */
+    double diss_rho;      /* the fluid number density rho_f of the target; > 0   */
+                          /* when diss_ctrl > 0                                   */
 } mdpd_params;
 
 /* Observables at the current step (all FP64 sums in a fixed order):
@@ -290,8 +306,8 @@ mdpd_status mdpd_load_checkpoint(mdpd_system *s, const void *buf, uint64_t bytes
  * ids) only and is held fixed.  With MDPD_WALL_BVF the corrector's
  * decisions are held fixed as well (events of the recorded trajectory): a
  * particle sent back keeps its position and carries its negated half-step
- * velocity, and the derivative follows that; wall_slip must be 0
- * (MDPD_E_UNSUPPORTED otherwise).  The recording starts from the state given
+ * velocity, and the derivative follows that; wall_slip and diss_ctrl must
+ * be 0 (MDPD_E_UNSUPPORTED otherwise).  The recording starts from the state given
  * to mdpd_create (MDPD_E_STATE after mdpd_step).
  *
  * mdpd_forward_record advances nsteps >= 0 steps from step 0, keeping a

@@ -46,6 +46,8 @@ class Params(ctypes.Structure):
         ("wall_model", ctypes.c_int32),
         ("wall_slip", ctypes.c_double),
         ("skin", ctypes.c_double),
+        ("diss_ctrl", ctypes.c_double),
+        ("diss_rho", ctypes.c_double),
     ]
 
 
@@ -141,9 +143,11 @@ DEFAULT_SKIN = 0.0  # neighbour-list skin in units of r_c (0: the pair list is b
 
 
 def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=(0.0, 0.0, 0.0),
-                seed=0, wall_model=0, phi_c=0.5, precision=FP64, wall_slip=0.0, skin=None) -> Params:
+                seed=0, wall_model=0, phi_c=0.5, precision=FP64, wall_slip=0.0, skin=None, diss_ctrl=0.0,
+                diss_rho=0.0) -> Params:
     """Parameter block; A, B, gamma are scalars or T x T tables; skin defaults
-    to DEFAULT_SKIN r_c."""
+    to DEFAULT_SKIN r_c; diss_ctrl, diss_rho: the fluid-solid dissipation
+    control (eta, rho_f; eta = 0 turns it off)."""
     A = np.atleast_2d(np.asarray(A, dtype=np.float64))
     B = np.atleast_2d(np.asarray(B, dtype=np.float64))
     G = np.atleast_2d(np.asarray(gamma, dtype=np.float64))
@@ -166,6 +170,8 @@ def make_params(box, A, B, gamma, rc=1.0, rd=0.75, kT=1.0, dt=0.01, mass=1.0, g=
     p.wall_model = int(wall_model)
     p.wall_slip = float(wall_slip)
     p.skin = float(DEFAULT_SKIN * rc if skin is None else skin)
+    p.diss_ctrl = float(diss_ctrl)
+    p.diss_rho = float(diss_rho)
     return p
 
 

@@ -83,6 +83,7 @@ struct mdpd_system {
     bool fp32 = false;
     bool walls = false;
     bool slip = false;  // walls reflect with wall_slip > 0 in some replica
+    bool dctl = false;  // some replica controls the fluid-solid dissipation (diss_ctrl > 0)
     uint8_t *corr_byid = nullptr;  // adjoint recording: the step's wall events by particle id
     int *perm_out = nullptr;       // adjoint recording: where the step's sorts move each slot
     int *perm_tmp = nullptr;       // walls: the two sorts of a recorded step (2 n), composed into perm_out
@@ -388,7 +389,7 @@ struct mdpd_system {
         toc(2);
         force_lanes_used = lanes[2];
         tic(3);
-        launch_force(st, lanes[2], fp32, mt, R, dstep, cview(xs[cur]), cview(vh[cur]), rho, tag[0], typ[0], rec,
+        launch_force(st, lanes[2], fp32, mt, dctl, R, dstep, cview(xs[cur]), cview(vh[cur]), rho, tag[0], typ[0], rec,
                      cstart, ncnt, nl, v, F, next_v(), next_x(), fpart, status, ovf, ovf + 1, ovf_ve, initial,
                      xbuild(), perstep ? nullptr : bmax);
         toc(3);
@@ -436,6 +437,10 @@ mdpd_status validate(const mdpd_params *p, int64_t n)
             return fail(MDPD_E_INVALID, "box edge %g is shorter than 2 r_c = %g", p->box[a], 2.0 * p->rc);
     if (!(p->skin >= 0.0) || !finite(p->skin) || p->skin > 4.0 * p->rc)
         return fail(MDPD_E_INVALID, "need 0 <= skin <= 4 r_c (skin = %g)", p->skin);
+    if (!(p->diss_ctrl >= 0.0) || !finite(p->diss_ctrl))
+        return fail(MDPD_E_INVALID, "need diss_ctrl >= 0 (diss_ctrl = %g)", p->diss_ctrl);
+    if (p->diss_ctrl > 0.0 && (!(p->diss_rho > 0.0) || !finite(p->diss_rho)))
+        return fail(MDPD_E_INVALID, "need diss_rho > 0 with diss_ctrl > 0 (diss_rho = %g)", p->diss_rho);
     return MDPD_OK;
 }
 
@@ -519,6 +524,8 @@ PairConst make_pair_const(const mdpd_params *p, const double *tab)
     pc.mass = p->mass;
     pc.phi_c = p->phi_c;
     pc.slip = p->wall_slip;
+    // eta rho_f W_D, W_D = 2 pi r_c^3 / 15 (the integral of w_c^2 over the sphere)
+    pc.dctl = p->diss_ctrl > 0.0 ? p->diss_ctrl * p->diss_rho * 2.0 * M_PI * p->rc * p->rc * p->rc / 15.0 : 0.0;
     pc.ntypes = p->ntypes;
     const double rdt = 1.0 / sqrt(p->dt);
     pc.A = p->A[0];
@@ -583,6 +590,8 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
         if (ps[r].skin > 0.0) s->perstep = false;
     for (int r = 0; r < nrep; ++r)
         if (s->walls && ps[r].wall_slip > 0.0) s->slip = true;
+    for (int r = 0; r < nrep; ++r)
+        if (ps[r].diss_ctrl > 0.0) s->dctl = true;
     s->params.assign(ps, ps + nrep);
     s->geoms.resize(nrep);
     s->cell_off.assign(nrep + 1, 0);
@@ -1574,6 +1583,8 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
     if (average && nsteps < 1) return fail(MDPD_E_INVALID, "a time average needs nsteps >= 1");
     if (s->slip)
         return fail(MDPD_E_UNSUPPORTED, "the adjoint differentiates the bounce-back wall corrector only (wall_slip = 0)");
+    if (s->dctl)
+        return fail(MDPD_E_UNSUPPORTED, "the adjoint does not differentiate the dissipation control (diss_ctrl = 0)");
     if (s->step != 0) return fail(MDPD_E_STATE, "recording starts from the state given to mdpd_create");
     AdjRec &a = s->adj;
     a.ready = false;

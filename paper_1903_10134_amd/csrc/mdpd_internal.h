@@ -81,6 +81,8 @@ struct PairConst {
     double A, B, gamma, sig, Arc2;  // single-type values; sig = sqrt(2 gamma kT / dt)
     double phi_c;
     double slip;        // wall reflection: tangential factor 2 slip - 1 (0: bounce-back)
+    double dctl;        // dissipation control: eta rho_f W_D (0: off); fluid-frozen pairs of
+                        // fluid i take gamma s_i, sigma sqrt(s_i), s_i = dctl / sum_{j, r<r_c} w_c^2
     const double *tab;  // ntypes > 1: A | B | gamma | sig | Arc2 planes of 64
     int ntypes;
     uint32_t seed;      // key word 0 of the pair noise
@@ -334,7 +336,8 @@ void launch_phi(hipStream_t st, int lanes, bool slip, int n, const Reps &R, Soa3
 // epilogue writes the next positions and half-step velocities to xpred,
 // vpred and the block maxima of their squared displacement from xbuild to
 // bmax (float, rounded up; the gate of the next step reads them).
-void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, const uint32_t *stepp,
+// dc: some replica controls the fluid-solid dissipation (PairConst::dctl > 0).
+void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, bool dc, const Reps &R, const uint32_t *stepp,
                   Soa3c xs, Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ,
                   const PartRec *rec, const int *cstart, const int *ncnt, const uint32_t *nl, Soa3 vout,
                   Soa3 fout,

@@ -1004,17 +1004,67 @@ __device__ __forceinline__ double wrap_coord(double x, double L)
     return x;
 }
 
+// Dissipation control (DC): the dissipative and random parts of particle
+// i's fluid-frozen pairs summed apart from the rest, and the sum of w_c^2
+// over all its neighbours that gives s_i = dctl / w2; the parts are scaled
+// by s_i and sqrt(s_i) once the neighbour loop is done.
+template <typename R, bool DC>
+struct WallDiss {};
+template <typename R>
+struct WallDiss<R, true> {
+    R w2 = 0, dx = 0, dy = 0, dz = 0, rx = 0, ry = 0, rz = 0;
+};
+
 // Force of one neighbour j on i (Eq. 1 + dissipative + random), added to f;
 // the conservative virial and the A-term pair energy, with weight c, to vir
 // and ep.  d = x_i - x_j (minimum image), dv = v_half,i - v_half,j.  A
-// coincident pair (r = 0) contributes nothing.
-template <typename R>
+// coincident pair (r = 0) contributes nothing.  DC: w_c^2 goes to wd.w2, and
+// for a fluid-frozen pair under the control (wall) the dissipative and random
+// parts go to wd instead of f.
+template <typename R, bool DC = false>
 __device__ __forceinline__ void pair_force(const PairConst &pc, double A, double B, double gam, double sig,
                                            double Arc2, double dx, double dy, double dz, double dvx,
                                            double dvy, double dvz, bool near, R rhoij, int th, double c,
-                                           R &fx, R &fy, R &fz, double &vir, double &ep)
+                                           R &fx, R &fy, R &fz, double &vir, double &ep,
+                                           WallDiss<R, DC> *wd = nullptr, bool wall = false)
 {
-    if constexpr (sizeof(R) == 8) {
+    if constexpr (DC) {
+        // the same terms as below, kept apart
+        const R r2 = (R)(dx * dx + dy * dy + dz * dz);
+        const bool pos = r2 > (R)0;
+        R rinv;
+        if constexpr (sizeof(R) == 8) rinv = pos ? rsqrt_f64(r2) : 0.0;
+        else rinv = pos ? __builtin_amdgcn_rsqf(r2) : 0.0f;
+        const R r = r2 * rinv;
+        const R wc = (R)1 - r * (R)pc.inv_rc;
+        R fc = (R)A * wc;
+        if (near) fc += (R)B * rhoij * ((R)1 - r * (R)pc.inv_rd);
+        const R ex = (R)dx * rinv, ey = (R)dy * rinv, ez = (R)dz * rinv;
+        const R ev = ex * (R)dvx + ey * (R)dvy + ez * (R)dvz;
+        const R fd = -(R)gam * wc * wc * ev;
+        R fr;
+        if constexpr (sizeof(R) == 8) fr = sig * wc * ((double)th * kSqrt3Scaled);
+        else fr = (float)sig * wc * ((float)th * kSqrt3ScaledF);
+        wd->w2 += wc * wc;
+        if (wall) {
+            wd->dx += fd * ex;
+            wd->dy += fd * ey;
+            wd->dz += fd * ez;
+            wd->rx += fr * ex;
+            wd->ry += fr * ey;
+            wd->rz += fr * ez;
+            fx += fc * ex;
+            fy += fc * ey;
+            fz += fc * ez;
+        } else {
+            const R fs = fc + fd + fr;
+            fx += fs * ex;
+            fy += fs * ey;
+            fz += fs * ez;
+        }
+        vir += c * (double)(fc * r);
+        ep += pos ? c * Arc2 * (double)(wc * wc) : 0.0;
+    } else if constexpr (sizeof(R) == 8) {
         const double r2 = dx * dx + dy * dy + dz * dz;
         const bool pos = r2 > 0.0;
         const double rinv = pos ? rsqrt_f64(r2) : 0.0;
@@ -1082,7 +1132,7 @@ __device__ __forceinline__ float moved2(const PairConst &pc, const Soa3c &xb, in
 // against bank conflicts)
 constexpr int kQuadXch = 4 * 64 + 16;
 
-template <int P, bool MT, bool SCAN, typename R>
+template <int P, bool MT, bool DC, bool SCAN, typename R>
 __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &g, int i, int sub, Soa3c xs,
                                                Soa3c vh, const R *__restrict__ rho,
                                                const uint32_t *__restrict__ tag,
@@ -1112,6 +1162,8 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
     const int T = pc.ntypes;
     const int ti = MT ? (int)typ[i] : 0;
     R fx = 0, fy = 0, fz = 0;
+    WallDiss<R, DC> wd;
+    const bool dc_on = DC && pc.dctl > 0.0;
     // pair arithmetic for one neighbour whose data is already loaded
     auto pair = [&](double dx, double dy, double dz, double vxj, double vyj, double vzj, R rj, uint32_t tgj,
                     int tj, bool near) {
@@ -1126,8 +1178,13 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
         }
         const int th = theta_int(idi, tgj & kIdMask, pc);
         const double c = (tgj & kFrozenBit) ? 1.0 : 0.5;
-        pair_force<R>(pc, A, B, gam, sig, Arc2, dx, dy, dz, vxi - vxj, vyi - vyj, vzi - vzj, near, rhoi + rj, th,
-                      c, fx, fy, fz, vir, ep);
+        if (dc_on) {
+            pair_force<R, DC>(pc, A, B, gam, sig, Arc2, dx, dy, dz, vxi - vxj, vyi - vyj, vzi - vzj, near,
+                              rhoi + rj, th, c, fx, fy, fz, vir, ep, &wd, (tgj & kFrozenBit) != 0);
+        } else {
+            pair_force<R>(pc, A, B, gam, sig, Arc2, dx, dy, dz, vxi - vxj, vyi - vyj, vzi - vzj, near, rhoi + rj,
+                          th, c, fx, fy, fz, vir, ep);
+        }
     };
     if constexpr (SCAN) {
         for_each_neighbor<P>(pc, g, i, sub, xi, yi, zi, xs, cstart, packed, nullptr,
@@ -1205,10 +1262,22 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
     fx = group_sum<P>(fx);
     fy = group_sum<P>(fy);
     fz = group_sum<P>(fz);
+    double Fx = (double)fx + pc.mg[0];
+    double Fy = (double)fy + pc.mg[1];
+    double Fz = (double)fz + pc.mg[2];
+    if constexpr (DC) {
+        if (dc_on) {
+            const R w2 = group_sum<P>(wd.w2);
+            const R dxs = group_sum<P>(wd.dx), dys = group_sum<P>(wd.dy), dzs = group_sum<P>(wd.dz);
+            const R rxs = group_sum<P>(wd.rx), rys = group_sum<P>(wd.ry), rzs = group_sum<P>(wd.rz);
+            const double si = w2 > (R)0 ? pc.dctl / (double)w2 : 1.0;
+            const double ri = __builtin_sqrt(si);
+            Fx += si * (double)dxs + ri * (double)rxs;
+            Fy += si * (double)dys + ri * (double)rys;
+            Fz += si * (double)dzs + ri * (double)rzs;
+        }
+    }
     if (sub != 0) return;
-    const double Fx = (double)fx + pc.mg[0];
-    const double Fy = (double)fy + pc.mg[1];
-    const double Fz = (double)fz + pc.mg[2];
     const double vx = out.initial ? vxi : vxi + pc.hdtm * Fx;
     const double vy = out.initial ? vyi : vyi + pc.hdtm * Fy;
     const double vz = out.initial ? vzi : vzi + pc.hdtm * Fz;
@@ -1271,7 +1340,7 @@ __device__ __forceinline__ void block_partials(double vir, double ep, float move
     }
 }
 
-template <int P, bool MT, typename R>
+template <int P, bool MT, bool DC, typename R>
 __global__ __launch_bounds__(kBlock) void k_force(Reps Rp, const uint32_t *__restrict__ stepp, Soa3c xs, Soa3c vh,
                                                   const R *__restrict__ rho,
                                                   const uint32_t *__restrict__ tag,
@@ -1298,7 +1367,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Reps Rp, const uint32_t *__res
     if (i < br.i1) {
         const int packed = ncnt[i];
         if (list_total(packed) <= kListCap) {
-            force_particle<P, MT, false, R>(pc, g, i, sub, xs, vh, rho, tag, typ, nullptr, packed,
+            force_particle<P, MT, DC, false, R>(pc, g, i, sub, xs, vh, rho, tag, typ, nullptr, packed,
                                             nl + (size_t)i * kListCap, rec, out, ptab, vir, ep, moved);
         } else if (sub == 0) {
             out.ovf[atomicAdd(out.ovf_count, 1)] = i;  // served by k_force_overflow (its move too)
@@ -1318,7 +1387,7 @@ constexpr int kOverflowBlocks = 32;
 // force launch's block that holds its slot (with fl_idx the lane index of
 // that launch), by an integer maximum on the float's bits, which orders
 // non-negative floats and does not depend on the order of the updates.
-template <bool MT, typename R>
+template <bool MT, bool DC, typename R>
 __global__ __launch_bounds__(kBlock) void k_force_overflow(Reps Rp, const uint32_t *__restrict__ stepp, Soa3c xs,
                                                            Soa3c vh,
                                                            const R *__restrict__ rho,
@@ -1341,7 +1410,7 @@ __global__ __launch_bounds__(kBlock) void k_force_overflow(Reps Rp, const uint32
         const Geom g = Rp.geom[r];
         double vir = 0.0, ep = 0.0;
         float moved = 0.0f;
-        force_particle<P, MT, true, R>(pc, g, i, sub, xs, vh, rho, tag, typ, cstart_all + cload(Rp.cell_off, r),
+        force_particle<P, MT, DC, true, R>(pc, g, i, sub, xs, vh, rho, tag, typ, cstart_all + cload(Rp.cell_off, r),
                                        ncnt[i], nullptr, nullptr, out, pc.tab, vir, ep, moved);
         vir = group_sum<P>(vir);
         ep = group_sum<P>(ep);
@@ -1575,8 +1644,8 @@ void launch_phi(hipStream_t st, int lanes, bool slip, int n, const Reps &R, Soa3
     k_correct_sum<<<1, kBlock, 0, st>>>(nb, part, ncorr, ncorr_total);
 }
 
-void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, const uint32_t *stepp, Soa3c xs,
-                  Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ, const PartRec *rec,
+void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, bool dc, const Reps &R, const uint32_t *stepp,
+                  Soa3c xs, Soa3c vh, const void *rho, const uint32_t *tag, const uint8_t *typ, const PartRec *rec,
                   const int *cstart,
                   const int *ncnt, const uint32_t *nl, Soa3 vout, Soa3 fout, Soa3 vpred, Soa3 xpred,
                   double *part, int *status, int *ovf_count, int *ovf, double *ovf_ve, int initial, Soa3c xbuild,
@@ -1587,23 +1656,28 @@ void launch_force(hipStream_t st, int lanes, bool fp32, bool mt, const Reps &R, 
         constexpr int L = decltype(P)::value;
         const int nb = R.nblk[lanes_index(L)];
         if (nb <= 0) return;
-        auto go = [&](auto mtc, auto rc) {
+        auto go = [&](auto mtc, auto dcc, auto rc) {
             constexpr bool M = decltype(mtc)::value;
+            constexpr bool D = decltype(dcc)::value;
             using RT = typename decltype(rc)::type;
-            k_force<L, M, RT><<<nb, kBlock, 0, st>>>(R, stepp, xs, vh, (const RT *)rho, tag, typ, rec, ncnt, nl,
-                                                     out);
-            k_force_overflow<M, RT><<<kOverflowBlocks, kBlock, 0, st>>>(R, stepp, xs, vh, (const RT *)rho, tag,
-                                                                        typ, cstart, ncnt, out, ovf_ve,
-                                                                        lanes_index(L));
+            k_force<L, M, D, RT><<<nb, kBlock, 0, st>>>(R, stepp, xs, vh, (const RT *)rho, tag, typ, rec, ncnt,
+                                                        nl, out);
+            k_force_overflow<M, D, RT><<<kOverflowBlocks, kBlock, 0, st>>>(R, stepp, xs, vh, (const RT *)rho,
+                                                                           tag, typ, cstart, ncnt, out, ovf_ve,
+                                                                           lanes_index(L));
         };
         using T = std::true_type;
         using F = std::false_type;
+        // the control takes the type-table path (its tables hold every
+        // replica's values, one type included)
         if (fp32) {
-            if (mt) go(T{}, Tid<float>{});
-            else go(F{}, Tid<float>{});
+            if (dc) go(T{}, T{}, Tid<float>{});
+            else if (mt) go(T{}, F{}, Tid<float>{});
+            else go(F{}, F{}, Tid<float>{});
         } else {
-            if (mt) go(T{}, Tid<double>{});
-            else go(F{}, Tid<double>{});
+            if (dc) go(T{}, T{}, Tid<double>{});
+            else if (mt) go(T{}, F{}, Tid<double>{});
+            else go(F{}, F{}, Tid<double>{});
         }
     });
 }

@@ -63,6 +63,8 @@ class Workload:
     wall_model: int = 0
     phi_c: float = 0.5
     wall_slip: float = 0.0
+    diss_ctrl: float = 0.0   # control of the effective fluid-solid dissipation (eta; 0: off)
+    diss_rho: float = 0.0    # its fluid density rho_f
     info: dict = field(default_factory=dict)
 
     @property
@@ -72,7 +74,8 @@ class Workload:
     def param_kwargs(self) -> dict:
         return dict(box=self.box, A=self.A, B=self.B, gamma=self.gamma, rc=self.rc, rd=self.rd,
                     kT=self.kT, dt=self.dt, mass=self.mass, g=self.g, seed=self.seed,
-                    wall_model=self.wall_model, phi_c=self.phi_c, wall_slip=self.wall_slip)
+                    wall_model=self.wall_model, phi_c=self.phi_c, wall_slip=self.wall_slip,
+                    diss_ctrl=self.diss_ctrl, diss_rho=self.diss_rho)
 
 
 def _maxwell(rng, n, kT, mass, frozen):

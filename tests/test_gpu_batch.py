@@ -122,6 +122,26 @@ def test_batch_with_wall_slip(mdpd):
     b.close()
 
 
+def test_batch_with_dissipation_control(mdpd):
+    """Replicas with their own fluid-solid dissipation control (eta 1, off,
+    0.5) step exactly as the same systems alone."""
+    reps = [small_channel(seed=5), small_channel(seed=6), small_channel(seed=7)]
+    for w, eta in zip(reps, (1.0, 0.0, 0.5)):
+        w.diss_ctrl, w.diss_rho = eta, 6.0
+    say("batch dissipation control")
+    b = mdpd.Batch(reps)
+    b.step(5)
+    xb, vb, _ = b.state()
+    for r, w in enumerate(reps):
+        s = mdpd.System(w)
+        s.step(5)
+        x, v, _ = s.state()
+        sl = slice(b.offsets[r], b.offsets[r + 1])
+        assert np.array_equal(xb[sl], x) and np.array_equal(vb[sl], v), r
+        s.close()
+    b.close()
+
+
 def test_batch_checkpoint_and_limits(mdpd):
     reps = W.replicas(count=3, lo=4.0, hi=5.0, seed=5)
     say("batch checkpoint")

@@ -404,6 +404,51 @@ def test_wall_corrector_parity(mdpd, precision, skin):
     assert total > 0, "the case should exercise the corrector"
 
 
+@pytest.mark.parametrize("eta", [1.0, 0.4])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dissipation_control_parity(mdpd, precision, eta):
+    """Control of the effective fluid-solid dissipation (diss_ctrl = eta,
+    diss_rho = 6) on the walled channel: forces at creation, then equal
+    corrector counts at every step and the state after 12 steps, against the
+    oracle.  The control must change the near-wall forces (not a no-op)."""
+    w = small_channel(seed=11)
+    w.diss_ctrl, w.diss_rho = eta, 6.0
+    say("dissipation control", precision, eta, w.n)
+    prec = mdpd.FP64 if precision == "fp64" else mdpd.FP32_FORCES
+    s = mdpd.System(w, precision=prec)
+    o = oracle.System(orc_params(w), w.x, w.v, w.types, w.frozen)
+    F0 = o.state()["F"]
+    tol0 = 1e-12 if precision == "fp64" else 2e-5
+    assert force_err(s.forces(), F0) < tol0
+    w_off = small_channel(seed=11)
+    o_off = oracle.System(orc_params(w_off), w_off.x, w_off.v, w_off.types, w_off.frozen)
+    assert force_err(o_off.state()["F"], F0) > 1e-3, "the control should change the near-wall forces"
+    total = 0
+    for k in range(12):
+        s.step(1)
+        o.step(1)
+        a, b = s.observables(), o.observables()
+        assert a["ncorr_last"] == b["ncorr_last"], (k, a["ncorr_last"], b["ncorr_last"])
+        total += b["ncorr_last"]
+    st = o.state()
+    x, v, rho = s.state()
+    if precision == "fp64":
+        assert pdiff(x, st["x"], w.box) < 1e-10
+        assert force_err(s.forces(), st["F"]) < 1e-10
+    else:
+        assert pdiff(x, st["x"], w.box) < 1e-4
+        assert force_err(s.forces(), st["F"]) < 1e-3
+    assert total > 0, "the case should exercise the corrector"
+
+
+def test_dissipation_control_is_refused_by_the_adjoint(mdpd):
+    w = small_channel(seed=11)
+    w.diss_ctrl, w.diss_rho = 1.0, 6.0
+    s = mdpd.System(w)
+    with pytest.raises(RuntimeError, match="dissipation control"):
+        s.forward_record(2)
+
+
 def test_profiles_match_oracle(mdpd):
     w = small_channel(seed=8)
     say("profiles")
