@@ -185,6 +185,15 @@ def run_batch(mdpd, W, nrep, steps, every):
     b.step(steps)
     torch.cuda.synchronize()
     fwd = time.perf_counter() - t0
+    # the same forward steps after the autotuner, replayed as a HIP graph
+    tuned = [int(v) for v in b.autotune(steps=5)]
+    b.set_graph(True)
+    b.step(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    fwd_tg = time.perf_counter() - t0
     b.close()
     # adjoint: a warm-up cycle allocates the checkpoints and the tape, then
     # the state at step 0 is restored and the timed cycle runs
@@ -207,6 +216,8 @@ def run_batch(mdpd, W, nrep, steps, every):
                         f"A ~ U[-50, -30], B ~ U[20, 30], FP32 forces",
             "replicas": nrep, "particles": n, "steps": steps, "checkpoint_every": every,
             "forward_particle_steps_per_s": n * steps / fwd, "forward_ms_per_step": fwd * 1e3 / steps,
+            "tuned_graph_forward_ms_per_step": fwd_tg * 1e3 / steps, "tuned_lanes": tuned,
+            "tuned_graph_particle_steps_per_s": n * steps / fwd_tg,
             "record_s": t1 - t0, "backward_s": t2 - t1, "forward_s": fwd,
             "adjoint_over_forward": (t2 - t1) / fwd,
             "record_plus_adjoint_over_forward": (t2 - t0) / fwd,
@@ -214,14 +225,17 @@ def run_batch(mdpd, W, nrep, steps, every):
 
 
 def run_small(mdpd, W, steps):
-    """The 6,000-particle box (L = 10): launch-bound, so stepping by replaying
-    a captured HIP graph is compared with eager launches."""
+    """The 6,000-particle box (L = 10): latency-bound, so eager launches,
+    a replayed HIP graph, and a graph after the autotuner (list split, lanes
+    of the density and force passes) are compared."""
     import torch
     w = W.bulk(L=10.0, seed=0)
     out = {"workload": "bulk mDPD liquid, periodic 10^3 box, 6000 particles", "particles": w.n, "steps": steps}
-    for mode in ("eager", "graph"):
+    for mode in ("eager", "graph", "tuned_graph"):
         s = mdpd.System(w, precision=mdpd.FP32_FORCES, device_inputs=True)
-        s.set_graph(mode == "graph")
+        if mode == "tuned_graph":
+            out["tuned_lanes"] = [int(v) for v in s.autotune(steps=20)]
+        s.set_graph(mode != "eager")
         s.step(20)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -442,14 +456,16 @@ def main():
         out["batched"] = bt
         out["adjoint_over_forward"] = bt["adjoint_over_forward"]
         print(f"# batched {bt['replicas']} replicas ({bt['particles']} particles): "
-              f"{bt['forward_ms_per_step']:.3f} ms/step forward, adjoint/forward "
+              f"{bt['forward_ms_per_step']:.3f} ms/step forward ({bt['tuned_graph_forward_ms_per_step']:.3f} tuned, "
+              f"graph), adjoint/forward "
               f"{bt['adjoint_over_forward']:.2f} (record+adjoint {bt['record_plus_adjoint_over_forward']:.2f})",
               file=sys.stderr, flush=True)
     if not a.no_small:
         sm = run_small(mdpd, W, 2000)
         out["small"] = sm
         print(f"# small 6000 particles: eager {sm['eager_us_per_step']:.1f} us/step, "
-              f"graph {sm['graph_us_per_step']:.1f} us/step", file=sys.stderr, flush=True)
+              f"graph {sm['graph_us_per_step']:.1f} us/step, tuned graph {sm['tuned_graph_us_per_step']:.1f} "
+              f"us/step (lanes {sm['tuned_lanes']})", file=sys.stderr, flush=True)
     if not a.no_walls:
         out["walled"] = run_walled_set(mdpd, W, a.walled)
     if not a.no_cpu:

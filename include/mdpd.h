@@ -258,10 +258,13 @@ mdpd_status mdpd_set_kernel_timing(mdpd_system *s, int32_t enable);
 mdpd_status mdpd_read_kernel_timing(mdpd_system *s, int32_t kernel, double *total_ms,
                                     int64_t *launches);
 
-/* Work split of the pair passes: lanes (1, 2, 4, 8 or 16) of a 64-wide
- * wavefront cooperate on one particle in pass 0 (neighbour list), 1 (density
- * and wall fraction) or 2 (force).  Results do not depend on pass 0's
- * setting; passes 1 and 2 change only the summation order. */
+/* Work split of the pair passes (lanes = 1, 2, 4, 8 or 16): in pass 1
+ * (density and wall fraction) and pass 2 (force) that many lanes of a
+ * 64-wide wavefront cooperate on one particle; in pass 0 (the per-step
+ * neighbour list, skin 0) that many wavefronts share each cell of the
+ * border launch (every cell of a small system), dealing its particles round
+ * robin.  Results do not depend on pass 0's setting (default 1); passes 1
+ * and 2 (default 4) change only the summation order. */
 mdpd_status mdpd_set_lanes(mdpd_system *s, int32_t pass, int32_t lanes);
 
 /* Graph mode (enable = 1): mdpd_step replays a HIP graph of two captured
@@ -273,8 +276,9 @@ mdpd_status mdpd_set_lanes(mdpd_system *s, int32_t pass, int32_t lanes);
 mdpd_status mdpd_set_graph(mdpd_system *s, int32_t enable);
 
 /* Autotuner: times `steps` >= 1 timesteps (HIP events around each launch on
- * the system's stream) for every lane count of the density pass and then of
- * the force pass, keeps the fastest, and restores the state it started from
+ * the system's stream) for every setting of pass 0 (skin 0 only), then of
+ * the density pass and then of the force pass (see mdpd_set_lanes), keeps
+ * the fastest of each, and restores the state it started from
  * (the trial steps leave no trace; the result only changes summation
  * orders).  The choice is cached for the process per (n, cells, replicas,
  * precision, type count, walls) and reused without timing.  lanes_out
@@ -306,8 +310,10 @@ mdpd_status mdpd_load_checkpoint(mdpd_system *s, const void *buf, uint64_t bytes
  * ids) only and is held fixed.  With MDPD_WALL_BVF the corrector's
  * decisions are held fixed as well (events of the recorded trajectory): a
  * particle sent back keeps its position and carries its negated half-step
- * velocity, and the derivative follows that; wall_slip and diss_ctrl must
- * be 0 (MDPD_E_UNSUPPORTED otherwise).  The recording starts from the state given
+ * velocity, and the derivative follows that; wall_slip must be 0
+ * (MDPD_E_UNSUPPORTED otherwise).  With diss_ctrl > 0 the derivative
+ * includes that of the factor s_i through the positions of i's neighbours.
+ * The recording starts from the state given
  * to mdpd_create (MDPD_E_STATE after mdpd_step).
  *
  * mdpd_forward_record advances nsteps >= 0 steps from step 0, keeping a

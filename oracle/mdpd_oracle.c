@@ -801,8 +801,9 @@ void orc_set_num_threads(int n)
 /* The state is advanced exactly as orc_step does (with walls, the         */
 /* bounce-back corrector's decisions are taken on the state and held fixed: */
 /* a corrected particle's position tangent goes back with it and its        */
-/* half-step velocity tangent changes sign; wall_slip must be 0), and next  */
-/* to every quantity q                                                      */
+/* half-step velocity tangent changes sign; wall_slip must be 0; with the   */
+/* dissipation control of reading R6 the factor s_i carries its tangent     */
+/* through phi_i and E_i), and next to every quantity q                     */
 /* its tangent dq, the derivative along one direction in the inputs: the    */
 /* initial positions and velocities (dx0, dv0, n x 3) and the pair tables   */
 /* (dA, dB, dgamma, ntypes^2; dsigma = kT dgamma / sigma).  Any of them may */
@@ -852,6 +853,42 @@ static void orc_tan_density(const orc_tan_ctx *c, const double *x, const double 
     }
 }
 
+/* The dissipation-control factor s_i of reading R6 and its tangent ds_i for
+ * fluid particle i, from its phi_i and E_i as orc_diss_scale_nl takes them:
+ * s = eta rho_f W_D phi / E with phi = E / S (S: all neighbours, E: frozen
+ * ones, weights w_c^2); s = 1, ds = 0 without frozen neighbours. */
+static void orc_tan_diss_scale(const orc_tan_ctx *c, const double *x, const double *dx, const orc_nlist *nl,
+                               int64_t i, double *s, double *ds)
+{
+    const orc_params *p = c->p;
+    const double K = p->diss_ctrl * p->diss_rho * 2.0 * M_PI * p->rc * p->rc * p->rc / 15.0;
+    double S = 0.0, dS = 0.0, E = 0.0, dE = 0.0;
+    for (int32_t k = 0; k < nl->cnt[i]; ++k) {
+        int64_t j = nl->idx[i][k];
+        double d[3];
+        orc_delta(x, i, j, p->L, d);
+        double r = sqrt(orc_r2(d));
+        double w = 1.0 - r / p->rc, dw = 0.0;
+        if (r > 0.0) {
+            double dr = 0.0;
+            for (int a = 0; a < 3; ++a) dr += d[a] / r * (dx[3 * i + a] - dx[3 * j + a]);
+            dw = -dr / p->rc;
+        }
+        S += w * w;
+        dS += 2.0 * w * dw;
+        if (c->frozen[j]) {
+            E += w * w;
+            dE += 2.0 * w * dw;
+        }
+    }
+    *s = 1.0;
+    *ds = 0.0;
+    if (!(E > 0.0)) return;
+    double phi = E / S, dphi = (dE * S - E * dS) / (S * S);
+    *s = K * phi / E;
+    *ds = K * (dphi * E - phi * dE) / (E * E);
+}
+
 /* Forces and their tangent (fluid particles; frozen get 0), the virial and
  * its tangent. */
 static void orc_tan_forces(const orc_tan_ctx *c, const double *x, const double *dx, const double *vh,
@@ -865,6 +902,8 @@ static void orc_tan_forces(const orc_tan_ctx *c, const double *x, const double *
 #pragma omp parallel for schedule(static) reduction(+ : vir, dvir)
     for (int64_t i = 0; i < c->n; ++i) {
         double f[3] = {0, 0, 0}, df[3] = {0, 0, 0};
+        double si = 1.0, dsi = 0.0;
+        if (!c->frozen[i] && p->diss_ctrl > 0.0) orc_tan_diss_scale(c, x, dx, nl, i, &si, &dsi);
         if (!c->frozen[i]) {
             for (int32_t k = 0; k < nl->cnt[i]; ++k) {
                 int64_t j = nl->idx[i][k];
@@ -910,6 +949,14 @@ static void orc_tan_forces(const orc_tan_ctx *c, const double *x, const double *
                 double dsigma = sigma > 0.0 ? p->kT * dgam / sigma : 0.0;
                 double th = orc_theta(p->seed, step, (uint32_t)i, (uint32_t)j) / sdt;
                 double fr = sigma * wc * th, dfr = (dsigma * wc + sigma * dwc) * th;
+                if (p->diss_ctrl > 0.0 && c->frozen[j]) {
+                    /* reading R6: gamma s_i, sigma sqrt(s_i) on a fluid-solid pair */
+                    double rs = sqrt(si);
+                    dfd = dsi * fd + si * dfd;
+                    fd = si * fd;
+                    dfr = dsi / (2.0 * rs) * fr + rs * dfr;
+                    fr = rs * fr;
+                }
                 double fs = fc + fd + fr, dfs = dfc + dfd + dfr;
                 for (int a = 0; a < 3; ++a) {
                     f[a] += fs * e[a];
@@ -960,9 +1007,7 @@ int orc_tangent(const orc_params *p, int64_t n, const double *x0, const double *
                 const double *dB, const double *dgamma, int64_t nsteps, const double w[3], int avg,
                 double out[2])
 {
-    if ((p->wall_model != 0 && p->wall_slip != 0.0) || p->diss_ctrl != 0.0 || nsteps < 0 ||
-        (avg && nsteps < 1))
-        return -1;
+    if ((p->wall_model != 0 && p->wall_slip != 0.0) || nsteps < 0 || (avg && nsteps < 1)) return -1;
     orc_tan_ctx c = {p, n, type, frozen, dA, dB, dgamma};
     size_t nn = (size_t)(n ? n : 1);
     double *x = (double *)malloc(nn * 3 * sizeof(double)), *dx = (double *)malloc(nn * 3 * sizeof(double));

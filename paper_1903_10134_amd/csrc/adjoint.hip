@@ -23,6 +23,12 @@
 //                  parameter derivative (the pair is visited from both ends),
 //                  so no atomics are needed; plus the virial seed's terms
 //   k_adj_density  X_i += sum_j (rhobar_i + rhobar_j) w_rho'(r) e_ij
+// With the fluid-solid dissipation control (DC) a fluid particle's
+// fluid-solid pairs carry gamma s_i and sigma sqrt(s_i), s_i = dctl / S_i,
+// S_i = sum over its neighbours of w_c^2: k_adj_dscale computes s_i and
+// s_i / S_i per state, k_adj_force scales those pairs and returns
+// a_i = dL/dS_i = -(s_i / S_i) dL/ds_i, and k_adj_density adds
+// X_i += sum_j (a_i + a_j) 2 w_c w_c' e_ij over every neighbour.
 //   k_adj_step_back  U += dt X (drift) and X, U into the sorted order of
 //                  step n - 1 through the recorded sort permutation
 // Parameter shares are written per particle (3 x ntypes values, by the type
@@ -77,7 +83,45 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(Reps Rp, const AdjConst *__
     rhoA[i] = ac.wrho_nf;
 }
 
-template <int P, bool MT, typename R>
+// DC: s_i = dctl / S_i and s_i / S_i of every fluid particle (1 and 0
+// without the control, for frozen particles and for S_i = 0).
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_adj_dscale(Reps Rp, Soa3c xs, const uint32_t *__restrict__ tag,
+                                                      const int *__restrict__ cstart_all,
+                                                      const int *__restrict__ ncnt,
+                                                      const uint32_t *__restrict__ nl, double *__restrict__ sdc,
+                                                      double *__restrict__ qdc)
+{
+    const BlockRep br = block_rep<P>(Rp, xcd_block());
+    const int i = br.i0 + (int)threadIdx.x / P;
+    const int sub = threadIdx.x & (P - 1);
+    if (i >= br.i1) return;
+    const PairConst pc = cload(Rp.pc, br.r);
+    if (!(pc.dctl > 0.0) || (tag[i] & kFrozenBit)) {
+        if (sub == 0) {
+            sdc[i] = 1.0;
+            qdc[i] = 0.0;
+        }
+        return;
+    }
+    const Geom g = cload(Rp.geom, br.r);
+    const int *__restrict__ cstart = cstart_all + cload(Rp.cell_off, br.r);
+    double S = 0.0;
+    for_each_neighbor<P>(pc, g, i, sub, xs.x[i], xs.y[i], xs.z[i], xs, cstart, ncnt[i], nl + (size_t)i * kListCap,
+                         [&](int, double dx, double dy, double dz, bool) {
+        const double r = __builtin_sqrt(dx * dx + dy * dy + dz * dz);
+        const double w = 1.0 - r * pc.inv_rc;
+        S += w * w;
+    });
+    S = group_sum<P>(S);
+    if (sub == 0) {
+        const double si = S > 0.0 ? pc.dctl / S : 1.0;
+        sdc[i] = si;
+        qdc[i] = S > 0.0 ? si / S : 0.0;
+    }
+}
+
+template <int P, bool MT, bool DC, typename R>
 __global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, const AdjConst *__restrict__ act,
                                                      int n, int tmax, Soa3c xs,
                                                      Soa3c u, const R *__restrict__ rho,
@@ -86,7 +130,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, co
                                                      const int *__restrict__ cstart_all,
                                                      const int *__restrict__ ncnt,
                                                      const uint32_t *__restrict__ nl, Soa3c fb, Soa3 X, Soa3 U,
-                                                     double *__restrict__ rhoA, double *__restrict__ gp)
+                                                     double *__restrict__ rhoA, double *__restrict__ gp,
+                                                     const double *__restrict__ sdc,
+                                                     const double *__restrict__ qdc, double *__restrict__ adc)
 {
     constexpr int TM = MT ? MDPD_ADJ_MAX_TYPES : 1;
     const BlockRep br = block_rep<P>(Rp, xcd_block());
@@ -109,6 +155,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, co
     const int ti = MT ? (int)typ[i] : 0;
     const double wP = ac.wP_3V;
     double ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0, ar = 0;
+    double cs = 0.0;  // DC: dL/ds_i over i's fluid-solid pairs
+    const bool dc_on = DC && pc.dctl > 0.0;
+    const double si = dc_on && !fzi ? sdc[i] : 1.0;
     double pA[TM], pB[TM], pG[TM];
 #pragma unroll
     for (int k = 0; k < TM; ++k) pA[k] = pB[k] = pG[k] = 0.0;
@@ -132,13 +181,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, co
         const double Bn = near ? pt.B : 0.0;
         const double ev = ex * vx + ey * vy + ez * vz;
         const double th = (double)theta_int(idi, tgj & kIdMask, pc) * kSqrt3Scaled;
+        // DC: a fluid-solid pair takes gamma s and sigma sqrt(s), s of its fluid end
+        double sp = 1.0;
+        if (dc_on && fzi != fzj) sp = fzj ? si : ld(sdc, j);
+        const double rsp = dc_on ? __builtin_sqrt(sp) : 1.0;
+        const double gam = pt.gam * sp, sig = pt.sig * rsp;
         const double fc = pt.A * wc + Bn * rs * wd;
-        const double fs = fc - pt.gam * wc * wc * ev + pt.sig * wc * th;
+        const double fs = fc - gam * wc * wc * ev + sig * wc * th;
         const double gE = gx * ex + gy * ey + gz * ez;
         // derivatives of fs in r (at fixed e.u_ij) and in e.u_ij
         const double dfc_dr = -pt.A * pc.inv_rc - Bn * rs * pc.inv_rd;
-        const double dfs_dr = dfc_dr + 2.0 * pt.gam * wc * ev * pc.inv_rc - pt.sig * th * pc.inv_rc;
-        const double dfs_dev = -pt.gam * wc * wc;
+        const double dfs_dr = dfc_dr + 2.0 * gam * wc * ev * pc.inv_rc - sig * th * pc.inv_rc;
+        const double dfs_dev = -gam * wc * wc;
         // X_i += gE dfs_dr e + fs (g - gE e) / r + gE dfs_dev (u_ij - ev e) / r
         double ce = gE * dfs_dr - fs * gE * rinv - gE * dfs_dev * ev * rinv;
         const double cg = fs * rinv, cu = gE * dfs_dev * rinv;
@@ -158,7 +212,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, co
         const double dsig = pt.gam > 0.0 ? pt.sig / (2.0 * pt.gam) : 0.0;
         const double sA = 0.5 * wc * (gE + q * r);
         const double sB = 0.5 * rs * wd * (gE + q * r) * (near ? 1.0 : 0.0);
-        const double sG = 0.5 * gE * (-wc * wc * ev + dsig * wc * th);
+        const double sG = 0.5 * gE * (-sp * wc * wc * ev + rsp * dsig * wc * th);
+        if (dc_on && !fzi && fzj)  // d/ds of s (-gamma w^2 ev) + sqrt(s) sigma w th, along g
+            cs += gE * (-pt.gam * wc * wc * ev + 0.5 / rsp * pt.sig * wc * th);
 #pragma unroll
         for (int k = 0; k < TM; ++k) {
             const bool hit = !MT || k == tj;
@@ -174,6 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, co
     by = group_sum<P>(by);
     bz = group_sum<P>(bz);
     ar = group_sum<P>(ar);
+    if (dc_on) cs = group_sum<P>(cs);
 #pragma unroll
     for (int k = 0; k < TM; ++k) {
         pA[k] = group_sum<P>(pA[k]);
@@ -190,6 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, co
         U.z[i] += bz;
     }
     rhoA[i] += ar;
+    if constexpr (DC) adc[i] = dc_on && !fzi ? -qdc[i] * cs : 0.0;  // dL/dS_i
 #pragma unroll
     for (int k = 0; k < TM; ++k) {
         if (k < T) {
@@ -200,11 +258,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_force(Reps Rp, uint32_t step, co
     }
 }
 
-template <int P>
+template <int P, bool DC>
 __global__ __launch_bounds__(kBlock) void k_adj_density(Reps Rp, Soa3c xs, const int *__restrict__ cstart_all,
                                                        const int *__restrict__ ncnt,
                                                        const uint32_t *__restrict__ nl,
-                                                       const double *__restrict__ rhoA, Soa3 X)
+                                                       const double *__restrict__ rhoA, Soa3 X,
+                                                       const double *__restrict__ adc)
 {
     const BlockRep br = block_rep<P>(Rp, xcd_block());
     const int i = br.i0 + (int)threadIdx.x / P;
@@ -216,15 +275,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_density(Reps Rp, Soa3c xs, const
     const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
     const double rai = rhoA[i];
     const double k2 = -2.0 * pc.wrho * pc.inv_rd;  // w_rho'(r) = k2 (1 - r / r_d)
+    const double aai = DC ? adc[i] : 0.0;
     double ax = 0, ay = 0, az = 0;
     for_each_neighbor<P>(pc, g, i, sub, xi, yi, zi, xs, cstart, ncnt[i], nl + (size_t)i * kListCap,
                          [&](int j, double dx, double dy, double dz, bool near) {
-        if (!near) return;
+        if (!DC && !near) return;
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (!(r2 > 0.0)) return;
         const double rinv = rsqrt_f64(r2);
         const double r = r2 * rinv;
-        const double c = (rai + ld(rhoA, j)) * k2 * (1.0 - r * pc.inv_rd) * rinv;
+        double c = near ? (rai + ld(rhoA, j)) * k2 * (1.0 - r * pc.inv_rd) * rinv : 0.0;
+        if constexpr (DC) {
+            // dS/dx through w_c^2: 2 w_c w_c' e, w_c' = -1/r_c
+            c += (aai + ld(adc, j)) * 2.0 * (1.0 - r * pc.inv_rc) * (-pc.inv_rc) * rinv;
+        }
         ax += c * dx;
         ay += c * dy;
         az += c * dz;
@@ -326,38 +390,57 @@ void launch_adj_seed(hipStream_t st, const Reps &R, const AdjConst *ac, Soa3c v,
     if (R.nblk[0] > 0) k_adj_seed<<<R.nblk[0], kBlock, 0, st>>>(R, ac, v, tag, U, fb, rhoA);
 }
 
-void launch_adj_force(hipStream_t st, int lanes, bool fp32, bool mt, int n, int tmax, const Reps &R, uint32_t step,
-                      const AdjConst *ac, Soa3c xs, Soa3c u, const void *rho, const uint32_t *tag,
+void launch_adj_dscale(hipStream_t st, int lanes, const Reps &R, Soa3c xs, const uint32_t *tag, const int *cstart,
+                       const int *ncnt, const uint32_t *nl, double *sdc, double *qdc)
+{
+    launch_lanes(lanes, [&](auto P) {
+        constexpr int L = decltype(P)::value;
+        const int nb = R.nblk[lanes_index(L)];
+        if (nb > 0) k_adj_dscale<L><<<nb, kBlock, 0, st>>>(R, xs, tag, cstart, ncnt, nl, sdc, qdc);
+    });
+}
+
+void launch_adj_force(hipStream_t st, int lanes, bool fp32, bool mt, bool dc, int n, int tmax, const Reps &R,
+                      uint32_t step, const AdjConst *ac, Soa3c xs, Soa3c u, const void *rho, const uint32_t *tag,
                       const uint8_t *typ, const int *cstart, const int *ncnt, const uint32_t *nl, Soa3c fb,
-                      Soa3 X, Soa3 U, double *rhoA, double *gp)
+                      Soa3 X, Soa3 U, double *rhoA, double *gp, const double *sdc, const double *qdc, double *adc)
 {
     if (n <= 0) return;
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
         const int nb = R.nblk[lanes_index(L)];
-        auto go = [&](auto mtc, auto rc) {
+        auto go = [&](auto mtc, auto dcc, auto rc) {
             constexpr bool M = decltype(mtc)::value;
+            constexpr bool D = decltype(dcc)::value;
             using RT = typename decltype(rc)::type;
-            k_adj_force<L, M, RT><<<nb, kBlock, 0, st>>>(R, step, ac, n, tmax, xs, u, (const RT *)rho, tag, typ,
-                                                         cstart, ncnt, nl, fb, X, U, rhoA, gp);
+            k_adj_force<L, M, D, RT><<<nb, kBlock, 0, st>>>(R, step, ac, n, tmax, xs, u, (const RT *)rho, tag, typ,
+                                                            cstart, ncnt, nl, fb, X, U, rhoA, gp, sdc, qdc, adc);
         };
+        using T = std::true_type;
+        using F = std::false_type;
+        // the control takes the type-table path (its tables hold every
+        // replica's values, one type included)
         if (fp32) {
-            if (mt) go(std::true_type{}, Tid<float>{});
-            else go(std::false_type{}, Tid<float>{});
+            if (dc) go(T{}, T{}, Tid<float>{});
+            else if (mt) go(T{}, F{}, Tid<float>{});
+            else go(F{}, F{}, Tid<float>{});
         } else {
-            if (mt) go(std::true_type{}, Tid<double>{});
-            else go(std::false_type{}, Tid<double>{});
+            if (dc) go(T{}, T{}, Tid<double>{});
+            else if (mt) go(T{}, F{}, Tid<double>{});
+            else go(F{}, F{}, Tid<double>{});
         }
     });
 }
 
 void launch_adj_density(hipStream_t st, int lanes, const Reps &R, Soa3c xs, const int *cstart, const int *ncnt,
-                        const uint32_t *nl, const double *rhoA, Soa3 X)
+                        const uint32_t *nl, const double *rhoA, Soa3 X, const double *adc)
 {
     launch_lanes(lanes, [&](auto P) {
         constexpr int L = decltype(P)::value;
         const int nb = R.nblk[lanes_index(L)];
-        if (nb > 0) k_adj_density<L><<<nb, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, rhoA, X);
+        if (nb <= 0) return;
+        if (adc) k_adj_density<L, true><<<nb, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, rhoA, X, adc);
+        else k_adj_density<L, false><<<nb, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, rhoA, X, nullptr);
     });
 }
 

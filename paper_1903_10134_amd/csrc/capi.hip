@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -68,6 +69,7 @@ struct AdjRec {
     int ntape = 0;
     Soa3 X{}, U{}, fb{}, Xo{}, Uo{};  // Xo, Uo: the step-back targets, swapped with X, U each step
     double *rhoA = nullptr, *gp = nullptr, *gpart = nullptr, *gtot = nullptr, *loss = nullptr;
+    double *sdc = nullptr;  // dissipation control: s, s / S and dL/dS per slot (3 n)
     AdjConst *act = nullptr;  // 4 tables of nrep entries: seeded, unseeded, final, creation
     std::vector<AdjConst> host_act;  // host copy (kept alive while the upload may read it)
     LossConst *lct = nullptr;
@@ -87,7 +89,7 @@ struct mdpd_system {
     uint8_t *corr_byid = nullptr;  // adjoint recording: the step's wall events by particle id
     int *perm_out = nullptr;       // adjoint recording: where the step's sorts move each slot
     int *perm_tmp = nullptr;       // walls: the two sorts of a recorded step (2 n), composed into perm_out
-    int lanes[3] = {4, 4, 4};  // neighbour list (unused), density (and phi), force: best at 1M particles
+    int lanes[3] = {1, 4, 4};  // neighbour list (wavefronts per border cell), density (and phi), force
     // replicas (a single system is one replica)
     int nrep = 1;
     bool mt = false;  // some replica has more than one type
@@ -643,6 +645,20 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     R.ncells = (int)cells;
     R.nbcells = (int)bcells.size();
     R.list_interior = one_launch ? 0 : 1;
+    R.list_split = s->lanes[0];
+    // every-step sort in one workgroup per replica when each replica's cell
+    // offsets and ids fit its LDS (64 KiB) and its particles the threads
+    R.sort_small_lds = 0;
+    if (s->perstep) {
+        int64_t need = 0;
+        bool fits = true;
+        for (int r = 0; r < nrep; ++r) {
+            const int64_t nr = offsets[r + 1] - offsets[r], mr = s->geoms[r].ncells;
+            fits = fits && nr <= kSortSmallMaxN && mr <= kSortSmallMaxCells;
+            need = std::max(need, 4 * (mr + 1 + nr));
+        }
+        if (fits && need <= kSortSmallMaxLds) R.sort_small_lds = (int)need;
+    }
     for (int li = 0; li < kLaneCounts; ++li) R.nblk[li] = s->blk_off[(size_t)li * (nrep + 1) + nrep];
 #define ALLOC(call)                 \
     do {                            \
@@ -1309,6 +1325,7 @@ mdpd_status mdpd_set_lanes(mdpd_system *s, int32_t pass, int32_t lanes)
     if (lanes != 1 && lanes != 2 && lanes != 4 && lanes != 8 && lanes != 16)
         return fail(MDPD_E_INVALID, "lanes %d not in {1, 2, 4, 8, 16}", lanes);
     s->lanes[pass] = lanes;
+    s->R.list_split = s->lanes[0];
     return MDPD_OK;
 }
 
@@ -1344,6 +1361,7 @@ mdpd_status mdpd_autotune(mdpd_system *s, int32_t steps, int32_t *lanes_out)
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
             for (int k = 0; k < 3; ++k) s->lanes[k] = it->second[k];
+            s->R.list_split = s->lanes[0];
             if (lanes_out)
                 for (int k = 0; k < 3; ++k) lanes_out[k] = s->lanes[k];
             return MDPD_OK;
@@ -1359,13 +1377,15 @@ mdpd_status mdpd_autotune(mdpd_system *s, int32_t steps, int32_t *lanes_out)
     HIPCHK(state_copy(s, save, true, hipMemcpyDeviceToDevice));
     s->timing = true;
     const int cand[5] = {1, 2, 4, 8, 16};
-    const int passes[2] = {1, 2}, classes[2] = {2, 3};  // density (and phi), force
+    // the list split (skin 0), density (and phi), force
+    const int passes[3] = {0, 1, 2}, classes[3] = {1, 2, 3};
     mdpd_status err = MDPD_OK;
-    for (int q = 0; q < 2 && !err; ++q) {
+    for (int q = s->perstep ? 0 : 1; q < 3 && !err; ++q) {
         double best = 1e300;
         int best_l = s->lanes[passes[q]];
         for (int l : cand) {
             s->lanes[passes[q]] = l;
+            s->R.list_split = s->lanes[0];
             s->advance(1);  // warm-up of this instantiation
             double ms = 0.0;
             int64_t cnt = 0;
@@ -1378,6 +1398,7 @@ mdpd_status mdpd_autotune(mdpd_system *s, int32_t steps, int32_t *lanes_out)
             }
         }
         s->lanes[passes[q]] = best_l;
+        s->R.list_split = s->lanes[0];
     }
     for (int k = 0; k < kTimedKernels; ++k) {
         double ms;
@@ -1394,7 +1415,6 @@ mdpd_status mdpd_autotune(mdpd_system *s, int32_t steps, int32_t *lanes_out)
     HIPCHK(hipStreamSynchronize(s->st));
     s->release(save);
     if (err) return err;
-    s->lanes[0] = s->lanes[1];
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = std::vector<int>{s->lanes[0], s->lanes[1], s->lanes[2]};
@@ -1564,10 +1584,13 @@ void adjoint_step(mdpd_system *s, int k, int64_t n, const AdjConst *act)
     const TapeEntry e = tape_entry(s, k);
     launch_adj_seed(s->st, s->R, act, cview(e.v), e.tag, a.U, a.fb, a.rhoA);
     s->tic(5);
-    launch_adj_force(s->st, s->lanes[2], s->fp32, s->mt, s->n, a.tmax, s->R, (uint32_t)n, act, cview(e.x),
+    if (s->dctl)
+        launch_adj_dscale(s->st, s->lanes[1], s->R, cview(e.x), e.tag, e.cstart, e.ncnt, e.nl, a.sdc, a.sdc + s->n);
+    launch_adj_force(s->st, s->lanes[2], s->fp32, s->mt, s->dctl, s->n, a.tmax, s->R, (uint32_t)n, act, cview(e.x),
                      cview(e.u), e.rho, e.tag, e.typ, e.cstart, e.ncnt, e.nl, cview(a.fb), a.X, a.U, a.rhoA,
-                     a.gp);
-    launch_adj_density(s->st, s->lanes[1], s->R, cview(e.x), e.cstart, e.ncnt, e.nl, a.rhoA, a.X);
+                     a.gp, a.sdc, s->dctl ? a.sdc + s->n : nullptr, s->dctl ? a.sdc + 2 * (size_t)s->n : nullptr);
+    launch_adj_density(s->st, s->lanes[1], s->R, cview(e.x), e.cstart, e.ncnt, e.nl, a.rhoA, a.X,
+                       s->dctl ? a.sdc + 2 * (size_t)s->n : nullptr);
     s->toc(5);
     launch_adj_params(s->st, s->R, s->n, a.tmax, e.typ, a.gp, a.gpart, a.gtot);
 }
@@ -1583,8 +1606,6 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
     if (average && nsteps < 1) return fail(MDPD_E_INVALID, "a time average needs nsteps >= 1");
     if (s->slip)
         return fail(MDPD_E_UNSUPPORTED, "the adjoint differentiates the bounce-back wall corrector only (wall_slip = 0)");
-    if (s->dctl)
-        return fail(MDPD_E_UNSUPPORTED, "the adjoint does not differentiate the dissipation control (diss_ctrl = 0)");
     if (s->step != 0) return fail(MDPD_E_STATE, "recording starts from the state given to mdpd_create");
     AdjRec &a = s->adj;
     a.ready = false;
@@ -1635,6 +1656,7 @@ mdpd_status mdpd_forward_record(mdpd_system *s, int64_t nsteps, int32_t every, i
             if ((rc = s->alloc3(q, N))) return rc;
         if ((rc = s->alloc(&a.rhoA, N))) return rc;
         if (s->walls && (rc = s->alloc(&s->perm_tmp, 2 * N))) return rc;
+        if (s->dctl && (rc = s->alloc(&a.sdc, 3 * N))) return rc;
         if ((rc = s->alloc(&a.gtot, 3 * 64 * nrep))) return rc;
         if ((rc = s->alloc(&a.loss, 3 * nrep + 1))) return rc;
         if ((rc = s->alloc(&a.act, 4 * nrep))) return rc;

@@ -29,6 +29,11 @@ constexpr int kSkinCap = 128;   // skin-list slots per particle
 constexpr int kOneListLaunchCells = 8192;  // per-step list: up to this many cells it is one launch
 static_assert((kListCap & (kListCap - 1)) == 0, "far-buffer positions wrap with a mask");
 constexpr int kBlock = 256;    // threads per block of the particle kernels
+// every-step sort in one workgroup per replica (sort.hip, k_sort_small):
+// limits per replica of particles (12 per thread of 1024), cells, and LDS
+constexpr int kSortSmallMaxN = 12 * 1024;
+constexpr int kSortSmallMaxCells = 4096;
+constexpr int kSortSmallMaxLds = 65536 - 256;
 constexpr uint32_t kFrozenBit = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7fffffffu;
 
@@ -111,6 +116,8 @@ struct Reps {
     int ncells;             // total cells
     int nbcells;
     int list_interior;      // per-step list: 1 = interior cells have a launch of their own; 0 = bcells holds every cell
+    int list_split;         // per-step list: wavefronts per cell of the border launch (its particles dealt round robin)
+    int sort_small_lds;     // > 0: every replica fits one workgroup's sort (LDS bytes it needs); 0: multi-pass sort
     int wsub;               // wall mask: sub-cells per cell edge (walls on)
     int nblk[kLaneCounts];  // total blocks per lane count
 };
@@ -351,12 +358,19 @@ int force_partials(const Reps &R, int lanes);
 // 3 planes of MDPD_ADJ_MAX_TYPES^2 (A, B, gamma) over the backward steps.
 void launch_adj_seed(hipStream_t st, const Reps &R, const AdjConst *ac, Soa3c v, const uint32_t *tag, Soa3 U,
                      Soa3 fb, double *rhoA);
-void launch_adj_force(hipStream_t st, int lanes, bool fp32, bool mt, int n, int tmax, const Reps &R,
+// Dissipation control (dc): sdc[i] = s_i, qdc[i] = s_i / S_i per slot of the
+// state (1 and 0 where the control does not act); the force adjoint then
+// writes adc[i] = dL/dS_i, which the density adjoint (adc non-NULL) turns
+// into the position adjoint of the w_c^2 sums.
+void launch_adj_dscale(hipStream_t st, int lanes, const Reps &R, Soa3c xs, const uint32_t *tag, const int *cstart,
+                       const int *ncnt, const uint32_t *nl, double *sdc, double *qdc);
+void launch_adj_force(hipStream_t st, int lanes, bool fp32, bool mt, bool dc, int n, int tmax, const Reps &R,
                       uint32_t step, const AdjConst *ac, Soa3c xs, Soa3c u, const void *rho,
                       const uint32_t *tag, const uint8_t *typ, const int *cstart, const int *ncnt,
-                      const uint32_t *nl, Soa3c fb, Soa3 X, Soa3 U, double *rhoA, double *gp);
+                      const uint32_t *nl, Soa3c fb, Soa3 X, Soa3 U, double *rhoA, double *gp,
+                      const double *sdc, const double *qdc, double *adc);
 void launch_adj_density(hipStream_t st, int lanes, const Reps &R, Soa3c xs, const int *cstart,
-                        const int *ncnt, const uint32_t *nl, const double *rhoA, Soa3 X);
+                        const int *ncnt, const uint32_t *nl, const double *rhoA, Soa3 X, const double *adc);
 // Drift adjoint and reorder in one pass: perm[i] = slot in step n of the
 // particle at slot i of step n - 1 (tag_prev: its tags); X, U in the order
 // of step n to Xo, Uo in the order of step n - 1; corr (nullable): the

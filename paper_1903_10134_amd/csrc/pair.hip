@@ -130,10 +130,13 @@ constexpr int kFarLds = (kGenBatch + 1) * kListCap;
 // wavefront's kFarLds words of LDS.  The interior instantiation
 // (BORDER = false) returns at once for a border cell; the border one is given
 // the border cells (every cell of a small system, interior ones included).
+// part, nsplit: this wavefront takes the particles part, part + nsplit, ...
+// of the cell (nsplit wavefronts share a cell; each loads the candidates).
 template <typename R2, bool BORDER>
 __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, const int *__restrict__ cstart_all,
                                            int *__restrict__ ncnt, uint32_t *__restrict__ nl,
-                                           R2 *__restrict__ nlr2, uint32_t *far_lds, int all)
+                                           R2 *__restrict__ nlr2, uint32_t *far_lds, int all, int part = 0,
+                                           int nsplit = 1)
 {
     const int lane = threadIdx.x & 63;
     uint32_t *const dump = far_lds + kGenBatch * kListCap;
@@ -282,7 +285,7 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
                 const int nic = ni - ib < 64 ? ni - ib : 64;
                 const int me = i0 + ib + (lane < nic ? lane : 0);
                 const double pxi = ld(xs.x, me), pyi = ld(xs.y, me), pzi = ld(xs.z, me);
-                for (int u = 0; u < nic; ++u) {
+                for (int u = part; u < nic; u += nsplit) {
                     const double xi = bcast_d(pxi, u), yi = bcast_d(pyi, u), zi = bcast_d(pzi, u);
                     const int i = i0 + ib + u;
                     const int sq = selfq0 + i;
@@ -329,6 +332,7 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
         return;
     }
 
+    if (part != 0) return;  // the general path runs the whole cell in one wavefront
     // general path
     const bool wl = cx == 0, wr = cx == nx - 1;  // the row wraps on the left / right
     // particles in batches of kGenBatch, each with its far buffer
@@ -443,9 +447,10 @@ __global__ __launch_bounds__(kBlock) void k_nlist_border(Reps R, Soa3c xs, const
     if (!all && cload(R.flag, R.nrep) == 0) return;
     __shared__ uint32_t lds[kWavesPerBlock * kFarLds];
     const int w = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
-    if (w >= R.nbcells) return;
-    nlist_cell<R2, true>(R, cload(R.bcells, w), xs, cstart_all, ncnt, nl, nlr2, lds + (threadIdx.x >> 6) * kFarLds,
-                         all);
+    const int S = R.list_split;
+    if (w >= R.nbcells * S) return;
+    nlist_cell<R2, true>(R, cload(R.bcells, w / S), xs, cstart_all, ncnt, nl, nlr2,
+                         lds + (threadIdx.x >> 6) * kFarLds, all, w % S, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -1559,7 +1564,7 @@ void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int 
 {
     if (R.ncells <= 0) return;
     const int blocks = (R.ncells + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int bblocks = (R.nbcells + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int bblocks = (R.nbcells * R.list_split + kWavesPerBlock - 1) / kWavesPerBlock;
     if (fp32) {
         if (R.list_interior)
             k_nlist_cell<float><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (float *)nlr2, all ? 1 : 0);

@@ -20,6 +20,9 @@
 //                  of that cell with a smaller id; moves every array of a
 //                  rebuilt replica to cell_start + rank in temporaries
 //   k_copy_back    the temporaries back in place, and the build positions.
+//   k_sort_small   the every-step sort of replicas small enough for one
+//                  workgroup each: binning, scan, id lists and ranks in LDS
+//                  (one launch instead of five, the same order).
 // The result depends only on positions and ids, not on the previous order or
 // the atomics' arrival order, so runs and restarts are bitwise reproducible,
 // and a replica's schedule of builds depends on its own particles only.
@@ -236,6 +239,117 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(Reps R, const int *__res
     typ_out[dst] = typ_in[i];
 }
 
+// Every-step sort of small replicas: one workgroup of kScanThreads threads
+// per replica bins its particles into cells (LDS counts), scans them, lists
+// the ids of every cell in arrival order and ranks each particle inside its
+// cell, all in LDS with workgroup barriers, and moves the arrays to
+// part_off[r] + cell offset + rank -- the (cell, id) order of the multi-pass
+// sort, which it replaces in one launch.  Dynamic LDS: the replica's cell
+// offsets (cells + 1) then its ids (n_r); a thread keeps the keys and arrival
+// slots of its (at most kSmallPer) particles in registers.
+constexpr int kSmallPer = kSortSmallMaxN / kScanThreads;
+static_assert(kSmallPer * kScanThreads == kSortSmallMaxN, "particles per thread of the one-workgroup sort");
+static_assert(kScanPer * kScanThreads >= kSortSmallMaxCells, "the scan takes up to kScanPer cells per thread");
+
+__global__ __launch_bounds__(kScanThreads) void k_sort_small(Reps R, Soa3c xin, Soa3c vin, Soa3c pin,
+                                                            const uint32_t *__restrict__ tag_in,
+                                                            const uint8_t *__restrict__ typ_in, Soa3 xout,
+                                                            Soa3 vout, Soa3 pout, uint32_t *__restrict__ tag_out,
+                                                            uint8_t *__restrict__ typ_out, int *__restrict__ cstart,
+                                                            int *__restrict__ cnew, int *__restrict__ dmap,
+                                                            uint32_t *__restrict__ step_ctr,
+                                                            int *__restrict__ ovf_count,
+                                                            unsigned long long *__restrict__ nbuild)
+{
+    extern __shared__ int lds[];
+    __shared__ int sh[kScanThreads / 64];
+    const int r = blockIdx.x;
+    const int p0 = cload(R.part_off, r), p1 = cload(R.part_off, r + 1);
+    const int c0 = cload(R.cell_off, r), m = cload(R.cell_off, r + 1) - c0;
+    const Geom g = cload(R.geom, r);
+    int *const off = lds;          // [m + 1]: counts, then offsets
+    int *const ids = lds + m + 1;  // [p1 - p0]
+    const int t = (int)threadIdx.x;
+    if (step_ctr && r == 0 && t == 0) {
+        // the step's bookkeeping when no gate runs (every replica rebuilds)
+        *step_ctr += 1;
+        *ovf_count = 0;
+        *nbuild += (unsigned long long)R.nrep;
+    }
+    for (int c = t; c <= m; c += kScanThreads) off[c] = 0;
+    __syncthreads();
+    int key[kSmallPer], slot[kSmallPer];
+#pragma unroll
+    for (int k = 0; k < kSmallPer; ++k) {
+        const int i = p0 + t + k * kScanThreads;
+        key[k] = 0;
+        slot[k] = 0;
+        if (i < p1) {
+            const int cx = cell_coord(xin.x[i], g.s[0], g.nc[0]);
+            const int cy = cell_coord(xin.y[i], g.s[1], g.nc[1]);
+            const int cz = cell_coord(xin.z[i], g.s[2], g.nc[2]);
+            key[k] = cx + g.nc[0] * (cy + g.nc[1] * cz);
+            slot[k] = atomicAdd(&off[key[k]], 1);
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the counts: kScanPer consecutive cells per thread
+    int v[kScanPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int c = t * kScanPer + k;
+        v[k] = c < m ? off[c] : 0;
+        sum += v[k];
+    }
+    int total;
+    int run = block_inclusive_scan(sum, sh, &total) - sum;  // its barriers also end the reads above
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int c = t * kScanPer + k;
+        if (c < m) {
+            off[c] = run;
+            cstart[c0 + c] = cnew[c0 + c] = p0 + run;
+        }
+        run += v[k];
+    }
+    if (t == 0) {
+        off[m] = total;
+        if (r == R.nrep - 1) cstart[c0 + m] = cnew[c0 + m] = p0 + total;  // the grand total
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSmallPer; ++k) {
+        const int i = p0 + t + k * kScanThreads;
+        if (i < p1) ids[off[key[k]] + slot[k]] = (int)(tag_in[i] & kIdMask);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSmallPer; ++k) {
+        const int i = p0 + t + k * kScanThreads;
+        if (i >= p1) continue;
+        const uint32_t tg = tag_in[i];
+        const int id = (int)(tg & kIdMask);
+        const int b = off[key[k]], e = off[key[k] + 1];
+        int rank = 0;
+        for (int q = b; q < e; ++q) rank += ids[q] < id ? 1 : 0;
+        const int dst = p0 + b + rank;
+        if (dmap) dmap[i] = dst;
+        xout.x[dst] = xin.x[i];
+        xout.y[dst] = xin.y[i];
+        xout.z[dst] = xin.z[i];
+        vout.x[dst] = vin.x[i];
+        vout.y[dst] = vin.y[i];
+        vout.z[dst] = vin.z[i];
+        if (pin.x) {
+            pout.x[dst] = pin.x[i];
+            pout.y[dst] = pin.y[i];
+            pout.z[dst] = pin.z[i];
+        }
+        tag_out[dst] = tg;
+        typ_out[dst] = typ_in[i];
+    }
+}
+
 // The sorted temporaries of rebuilt replicas back in place; the positions
 // also become the build positions (xb, unless NULL).
 __global__ __launch_bounds__(kBlock) void k_copy_back(Reps R, Soa3c tx, Soa3c tv, Soa3c tp,
@@ -414,11 +528,18 @@ void launch_compose(hipStream_t st, int n, const int *a, const int *b, int *out)
 void launch_rebuild_sort(hipStream_t st, int n, const Reps &R, Soa3 x, Soa3 v, Soa3 xprev, uint32_t *tag,
                          uint8_t *typ, Soa3 tx, Soa3 tv, Soa3 tp, uint32_t *ttag, uint8_t *ttyp, Soa3 xbuild,
                          int *key, int *slot, uint32_t *tmpid, int *counts, int *cnew, int *cstart, int *bsum,
-                         int *dmap, bool copy_back, uint32_t *step_ctr, int *ovf_count, unsigned long long *nbuild)
+                         int *dmap, bool copy_back, uint32_t *step_ctr, int *ovf_count,
+                         unsigned long long *nbuild)
 {
     const int m = R.ncells;
     const int nb = (m + kScanTile - 1) / kScanTile;
     const int all = copy_back ? 0 : 1;
+    if (!copy_back && R.sort_small_lds > 0) {
+        k_sort_small<<<R.nrep, kScanThreads, R.sort_small_lds, st>>>(
+            R, cview(x), cview(v), xprev.x ? cview(xprev) : Soa3c{nullptr, nullptr, nullptr}, tag, typ, tx, tv, tp,
+            ttag, ttyp, cstart, cnew, dmap, n > 0 ? step_ctr : nullptr, ovf_count, nbuild);
+        return;
+    }
     if (n > 0) k_bin<<<R.nblk[0], kBlock, 0, st>>>(R, cview(x), key, slot, counts, all, step_ctr, ovf_count, nbuild);
     k_scan_local<<<nb, kScanThreads, 0, st>>>(R, m, counts, cnew, bsum, all);
     k_scan_add<<<nb, kScanThreads, 0, st>>>(R, m, nb, bsum, cnew, cstart, all);

@@ -41,7 +41,17 @@ def adj_cases():
         # bounce-back walls: the corrector's events of the recorded
         # trajectory are held fixed on both sides
         "channel_walls": W.channel(Lx=6.0, Ly=4.0, Lz=6.0, wall=1.5, seed=3, gx=0.05),
+        # the same channel with the fluid-solid dissipation control: the
+        # factor s_i of a fluid particle depends on its neighbours' positions
+        "channel_walls_dc": dc_channel(),
     }
+
+
+def dc_channel():
+    w = W.channel(Lx=6.0, Ly=4.0, Lz=6.0, wall=1.5, seed=3, gx=0.05)
+    w.diss_ctrl, w.diss_rho = 0.8, 6.0
+    w.name = "channel_walls_dc"
+    return w
 
 
 CASES = adj_cases()

@@ -142,6 +142,32 @@ def test_batch_with_dissipation_control(mdpd):
     b.close()
 
 
+def test_one_workgroup_sort_equals_the_multi_pass_sort(mdpd):
+    """Replicas of up to 12,288 particles and 4,096 cells are sorted by one
+    workgroup each; a batch holding one larger replica takes the multi-pass
+    sort for all of them.  The small replicas must step bit for bit as
+    standalone systems (one-workgroup sort) in both batches."""
+    small = [W.bulk(L=6.0, seed=21), W.bulk(box=(5.0, 3.5, 8.25), n=700, seed=22)]
+    big = W.bulk(L=14.0, seed=23)
+    assert big.n > 12288
+    say("one-workgroup sort vs multi-pass sort")
+    alone = []
+    for w in small:
+        s = mdpd.System(w)
+        s.step(6)
+        alone.append(s.state())
+        s.close()
+    for reps in (small, small + [big]):
+        b = mdpd.Batch(reps)
+        b.step(6)
+        xb, vb, rb = b.state()
+        for r, (x, v, rho) in enumerate(alone):
+            sl = slice(b.offsets[r], b.offsets[r + 1])
+            assert np.array_equal(xb[sl], x) and np.array_equal(vb[sl], v) and np.array_equal(rb[sl], rho), \
+                (len(reps), r)
+        b.close()
+
+
 def test_batch_checkpoint_and_limits(mdpd):
     reps = W.replicas(count=3, lo=4.0, hi=5.0, seed=5)
     say("batch checkpoint")

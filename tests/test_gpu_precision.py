@@ -57,12 +57,19 @@ def test_observable_errors_per_form(mdpd):
     print("\nstep 1, relative error vs the FP64 oracle")
     for k, errs in rows:
         print(f"  {k:12s} " + "  ".join(f"{q} {e:.1e}" for q, e in errs.items()))
-    # time averages
+    # time averages, and the drift of the total momentum (zero at the start:
+    # the Maxwell velocities have their mean removed; with no walls and no
+    # body force every pair force cancels in exact arithmetic)
     acc = {k: [] for k in ["oracle", *systems]}
+    pmax = {k: 0.0 for k in ["oracle", *systems]}
     for block in range(100):
         o.step(10)
         for s in systems.values():
             s.step(10)
+        ob = o.observables()
+        pmax["oracle"] = max(pmax["oracle"], float(np.abs([ob["px"], ob["py"], ob["pz"]]).max()))
+        for k, s in systems.items():
+            pmax[k] = max(pmax[k], float(np.abs(s.observables()["momentum"]).max()))
         if block >= 20:
             acc["oracle"].append([o.observables()[q] for q in KEYS])
             for k, s in systems.items():
@@ -73,6 +80,10 @@ def test_observable_errors_per_form(mdpd):
     print("time averages over steps 210..1000 (standard error of the mean in brackets)")
     for k, m in mean.items():
         print(f"  {k:12s} " + "  ".join(f"{q} {v:.5g} ({np.sqrt(var[k][q]):.2g})" for q, v in m.items()))
+    print("largest |total momentum component| over 1000 steps (thermal scale sqrt(N m kT) = "
+          f"{np.sqrt(w.n * w.mass * w.kT):.1f}): " + "  ".join(f"{k} {v:.2e}" for k, v in pmax.items()))
+    assert pmax["oracle"] < 1e-9 and pmax["fp64"] < 1e-9, pmax
+    assert pmax["fp32_forces"] < 0.05, pmax
     for k in systems:
         assert rel(mean[k]["kT"], mean["oracle"]["kT"]) < 0.01, k
         assert rel(mean[k]["mean_rho"], mean["oracle"]["mean_rho"]) < 0.01, k

@@ -1,6 +1,6 @@
 """Wall corrector with partial and full slip (Sec. 2.2; needs an MI355X).
 
-A rejected step reflects the half-step velocity about the wall normal
+A rejected step reflects the velocity about the wall normal
 n = unit(sum_{frozen j, r<r_c} w_c^2 (x_i - x_j) / r): normal part negated,
 tangential part times 2 wall_slip - 1 (0: bounce-back, 1: specular).
 
@@ -50,6 +50,27 @@ def test_flat_wall_reflection(mdpd, slip):
     s.close()
 
 
+@pytest.mark.parametrize("slip", [0.0, 0.25, 0.5, 1.0])
+def test_flat_wall_reflection_with_a_tangential_kick(mdpd, slip):
+    """The oracle's closed form with a body force along the wall: the
+    rejected step ends at R v_half + k (the normal kick cancels)."""
+    k = np.array([1.0 / 128.0, 0.0, 1.0 / 64.0])
+    v0 = np.array([1.0, -1.0, 1.0]) - k
+    _, x, v, t, f = wall_and_particle(oracle, slip, v0, g=(0.25, 0.0, 0.5))
+    say("flat wall reflection with a kick", slip)
+    p = mdpd.make_params(box=8.0, A=0.0, B=0.0, gamma=0.0, kT=0.0, dt=0.0625, wall_model=1, phi_c=0.5,
+                         wall_slip=slip, g=(0.25, 0.0, 0.5))
+    s = mdpd.System(params=p, x=x, v=v, types=t, frozen=f)
+    s.step(1)
+    xs, vs, _ = s.state()
+    assert s.observables()["ncorr_last"] == 1
+    assert np.array_equal(xs[0], x[0])
+    ft = 2.0 * slip - 1.0
+    exp = np.array([ft + k[0], 1.0, ft + k[2]]) if slip > 0.0 else -v0
+    assert np.allclose(vs[0], exp, atol=1e-15, rtol=0), (vs[0], exp)
+    s.close()
+
+
 @pytest.mark.parametrize("slip", [0.5, 1.0])
 def test_slip_parity_fp64(mdpd, slip):
     w = W.slit_pore(A_SL=-35.0, seed=1)
@@ -73,7 +94,9 @@ def test_slip_parity_fp64(mdpd, slip):
     s.close()
 
 
-def wall_layer_velocity(mdpd, slip, steps=4000, sample=8000, every=20):
+def channel_profiles(mdpd, slip, steps=4000, sample=8000, every=20):
+    """u_x and kT across a driven channel whose fluid-wall pairs have no
+    dissipative (and so no random) force, in bins of 1 over the fluid."""
     w = W.channel(Lx=16.0, Ly=12.0, Lz=8.0, wall=2.0, gx=0.02, seed=2)
     w.wall_slip = slip
     w.gamma = np.array([[4.5, 0.0], [0.0, 4.5]])
@@ -81,22 +104,37 @@ def wall_layer_velocity(mdpd, slip, steps=4000, sample=8000, every=20):
     s = mdpd.System(w, precision=mdpd.FP32_FORCES)
     s.step(steps)
     nb = 16  # bins of 1 along y over the periodic height 16: fluid in bins 0..11
-    ux = np.zeros(nb)
+    ux, kt = np.zeros(nb), np.zeros(nb)
     m = 0
     for _ in range(sample // every):
         s.step(every)
         ux += s.profile(1, nb, 1)
+        kt += s.profile(1, nb, 4)
         m += 1
     s.close()
-    return ux[:12] / m
+    return ux[:12] / m, kt[:12] / m
 
 
-def test_full_slip_speeds_up_the_wall_layer(mdpd):
-    u0 = wall_layer_velocity(mdpd, 0.0)
-    u1 = wall_layer_velocity(mdpd, 1.0)
-    print("\nu_x across the channel, bounce-back: " + " ".join(f"{u:.3f}" for u in u0))
-    print("u_x across the channel, full slip:   " + " ".join(f"{u:.3f}" for u in u1))
-    wall0 = 0.5 * (u0[0] + u0[-1])
-    wall1 = 0.5 * (u1[0] + u1[-1])
-    assert np.all(u0 > 0.0) and np.all(u1 > 0.0)
-    assert wall1 > wall0
+def test_slip_channel_flow_and_temperature(mdpd):
+    """The fluid flows with every reflection (u_x > 0 off the wall bins,
+    mean above 0.1) and stays at the bulk temperature away from the walls;
+    bounce-back keeps the wall bins at the bulk temperature too.  Next to
+    the walls full slip lets the fluid move faster than bounce-back, which
+    holds it back.  The wall bins' kT with slip is printed: a particle the
+    corrector rejects several steps in a row receives the tangential impulse
+    of the step (forces from the rough frozen wall included) without moving,
+    which heats the first fluid layer.  Half slip drops the tangential
+    velocity of a corrected particle."""
+    rows = {}
+    for slip in (0.0, 0.5, 1.0):
+        u, kt = channel_profiles(mdpd, slip)
+        rows[slip] = u
+        print(f"\nslip {slip}: u_x " + " ".join(f"{v:.3f}" for v in u) + f"  (mean {u.mean():.4f})")
+        print(f"slip {slip}: kT  " + " ".join(f"{v:.3f}" for v in kt))
+        assert np.all(u[1:-1] > 0.0) and u.mean() > 0.1, (slip, u)
+        assert np.all(np.abs(kt[1:-1] - 1.0) < 0.05), (slip, kt)
+        if slip == 0.0:
+            assert np.all(np.abs(kt - 1.0) < 0.05), (slip, kt)
+    wall0 = 0.5 * (rows[0.0][0] + rows[0.0][-1])
+    wall1 = 0.5 * (rows[1.0][0] + rows[1.0][-1])
+    assert wall1 > wall0, (wall0, wall1)

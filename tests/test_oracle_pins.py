@@ -352,18 +352,19 @@ def test_stress_of_a_two_particle_system(orc):
 # --------------------------------------------------------------------------
 # Wall corrector reflection (Sec. 2.2; bounce-back, partial and full slip)
 # --------------------------------------------------------------------------
-def wall_and_particle(orc, slip, v0):
+def wall_and_particle(orc, slip, v0, g=(0.0, 0.0, 0.0)):
     """A flat wall: two frozen square-lattice layers (spacing 0.5) at y = 2
     and 2.5 of a periodic 8^3 box; one fluid particle at (0.1875, 3.375,
-    0.1875) with velocity v0; no forces (A = B = gamma = kT = 0); dt = 1/16."""
-    g = np.arange(16) * 0.5
-    wall = np.array([[a, y, b] for y in (2.0, 2.5) for a in g for b in g])
+    0.1875) with velocity v0; no pair forces (A = B = gamma = kT = 0), body
+    force g; dt = 1/16."""
+    grid = np.arange(16) * 0.5
+    wall = np.array([[a, y, b] for y in (2.0, 2.5) for a in grid for b in grid])
     x = np.vstack([[0.1875, 3.375, 0.1875], wall])
     v = np.zeros_like(x)
     v[0] = v0
     frozen = np.r_[0, np.ones(len(wall))].astype(np.uint8)
     p = orc.make_params(box=8.0, A=0.0, B=0.0, gamma=0.0, kT=0.0, dt=0.0625, wall_model=1, phi_c=0.5,
-                        wall_slip=slip)
+                        wall_slip=slip, g=g)
     return p, x, v, np.zeros(len(x), np.int32), frozen
 
 
@@ -385,6 +386,29 @@ def test_wall_reflection_closed_form(orc, slip):
         assert np.array_equal(st["v"][0], -v0)
     else:
         assert np.allclose(st["v"][0], [2 * slip - 1, 1.0, 2 * slip - 1], atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("slip", [0.0, 0.25, 0.5, 1.0])
+def test_wall_reflection_with_a_tangential_kick(orc, slip):
+    """The same wall with a body force g = (0.25, 0, 0.5) along the wall:
+    the half kick k = dt g / 2 = (1/128, 0, 1/64) and v(0) = (1, -1, 1) - k
+    make the half-step velocity exactly (1, -1, 1), so the prediction and
+    the normal (+y) are those of the case above.  The rejected step reflects
+    the half-step velocity and the second half kick follows: it ends at
+    R v_half + k, i.e. along the wall (2s - 1)(1, 1) + k of the x and z
+    components, and -v_normal(0) = +1 across it (the normal kick cancels);
+    bounce-back ends at -v(0).  x is back at x(0)."""
+    k = np.array([1.0 / 128.0, 0.0, 1.0 / 64.0])
+    v0 = np.array([1.0, -1.0, 1.0]) - k
+    p, x, v, t, f = wall_and_particle(orc, slip, v0, g=(0.25, 0.0, 0.5))
+    s = orc.System(p, x, v, t, f)
+    s.step(1)
+    st = s.state()
+    assert s.observables()["ncorr_last"] == 1
+    assert np.array_equal(st["x"][0], x[0])
+    ft = 2.0 * slip - 1.0
+    exp = np.array([ft + k[0], 1.0, ft + k[2]]) if slip > 0.0 else -v0
+    assert np.allclose(st["v"][0], exp, atol=1e-15, rtol=0)
 
 
 def test_specular_reflection_keeps_speeds(orc):

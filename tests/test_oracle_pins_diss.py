@@ -144,7 +144,26 @@ def test_random_force_takes_sqrt_of_scale(orc):
     assert np.abs(wrong - F[0]).max() > 1e-3
 
 
-def test_tangent_refuses_the_control(orc):
+def test_tangent_of_the_scale_by_finite_differences(orc):
+    """The tangent of the force at creation (nsteps = 0, loss: virial
+    pressure) of the three-particle system along a position direction equals
+    central differences: the force on i moves with s_i, whose tangent the
+    oracle takes through phi_i and E_i.  A state with A = B = 0 and kT = 0
+    makes the dissipative force (and so s_i) the only pressure-free term, so
+    the loss is the mean x-velocity after one step instead."""
     x, fz = three()
-    with pytest.raises(ValueError):
-        orc.tangent(params(orc), x, np.zeros((3, 3)), np.zeros(3, np.int32), fz, 1, [1.0, 0.0, 0.0])
+    v = np.array([[0.7, -0.4, 0.3], [0.0, 0.0, 0.0], [-0.2, 0.5, 0.1]])
+    kw = dict(box=L, A=0.0, B=0.0, gamma=4.5, rc=RC, rd=RD, kT=0.0, wall_model=0, diss_ctrl=ETA,
+              diss_rho=RHO_F)
+    p = orc.make_params(**kw)
+    t = np.zeros(3, np.int32)
+    dx = np.array([[0.3, -0.2, 0.5], [0.1, 0.4, -0.3], [-0.6, 0.2, 0.1]])
+    wts = (0.0, 0.0, 1.0)
+    _, dL = orc.tangent(p, x, v, t, fz, 1, wts, False, dx0=dx)
+    h = 1e-6
+    fd = (orc.loss(p, x + h * dx, v, t, fz, 1, wts) - orc.loss(p, x - h * dx, v, t, fz, 1, wts)) / (2 * h)
+    assert abs(dL - fd) <= 1e-6 * abs(fd) + 1e-10, (dL, fd)
+    # the control's share: the same derivative without the control differs
+    q = orc.make_params(**{**kw, "diss_ctrl": 0.0})
+    _, d0 = orc.tangent(q, x, v, t, fz, 1, wts, False, dx0=dx)
+    assert abs(dL - d0) > 1e-3 * abs(fd)

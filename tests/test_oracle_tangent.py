@@ -37,6 +37,13 @@ def _case(kind):
         w = W.channel(Lx=6.0, Ly=4.0, Lz=6.0, wall=1.5, seed=3, gx=0.05)
         kw = w.param_kwargs()
         types, frozen = w.types, w.frozen
+    elif kind == "walls_dc":
+        # the same channel with the fluid-solid dissipation control (its
+        # factor s_i depends on the positions and has a tangent of its own)
+        w = W.channel(Lx=6.0, Ly=4.0, Lz=6.0, wall=1.5, seed=3, gx=0.05)
+        w.diss_ctrl, w.diss_rho = 0.8, 6.0
+        kw = w.param_kwargs()
+        types, frozen = w.types, w.frozen
     return w, kw, types, frozen
 
 
@@ -51,7 +58,7 @@ def _close(dL, fd, rel, floor):
     return abs(dL - fd) <= rel * abs(fd) + floor
 
 
-@pytest.mark.parametrize("kind", ["one_type", "two_types", "frozen", "walls"])
+@pytest.mark.parametrize("kind", ["one_type", "two_types", "frozen", "walls", "walls_dc"])
 @pytest.mark.parametrize("nsteps,avg", [(0, False), (4, False), (4, True)])
 def test_tangent_matches_finite_differences(orc, kind, nsteps, avg):
     w, kw, types, frozen = _case(kind)
@@ -75,7 +82,7 @@ def test_tangent_matches_finite_differences(orc, kind, nsteps, avg):
         "x0": (dict(dx0=dx), lambda k, x, v, e: (k, x + e * dx, v), 1e-7),
         "v0": (dict(dv0=dv), lambda k, x, v, e: (k, x, v + e * dv), 1e-6),
     }
-    for wts in (RHO, PRES):
+    for wts in (RHO, PRES) + ((VX,) if kind == "walls_dc" else ()):
         for name, (kwargs, shift, h) in dirs.items():
             L, dL = orc.tangent(p, w.x, w.v, types, frozen, nsteps, wts, avg, **kwargs)
             fd = _fd(orc, kw, w.x, w.v, types, frozen, nsteps, wts, avg, h, shift)
