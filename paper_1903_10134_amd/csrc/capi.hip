@@ -277,7 +277,9 @@ struct mdpd_system {
     // The step's gate, then the re-sort and skin list of the replicas that
     // moved too far (every launch checks the gate's flags on the device).
     // With walls the previous positions xs[1 - cur] ride along the sort.
-    void gate_and_rebuild()
+    // list_later (skin 0): the pair list is built after the wall corrector
+    // (which may move particles back and re-sort them), not here.
+    void gate_and_rebuild(bool list_later = false)
     {
         const Soa3 none{nullptr, nullptr, nullptr};
         int *dmap = perm_out && walls ? perm_tmp : perm_out;
@@ -299,6 +301,7 @@ struct mdpd_system {
         std::swap(tag[0], tag[1]);
         std::swap(typ[0], typ[1]);
         toc(0);
+        if (list_later) return;
         tic(1);
         launch_nlist(st, fp32, R, cview(xs[cur]), cstart, ncnt, nl, nlr2, true);
         toc(1);
@@ -312,8 +315,9 @@ struct mdpd_system {
     Soa3 prev_x() const { return perstep ? tp : xs[1 - cur]; }
 
     // The re-sort and the list of the replicas the last gate flagged: the
-    // skin list, or with skin 0 the pair list itself.
-    void rebuild(Soa3 xprev, Soa3 tprev, int *dmap)
+    // skin list, or with skin 0 the pair list itself (of every replica with
+    // list_all).
+    void rebuild(Soa3 xprev, Soa3 tprev, int *dmap, bool list_all = false)
     {
         tic(0);
         launch_rebuild_sort(st, n, R, xs[cur], vh[cur], xprev, tag[0], typ[0], tx, tv, tprev, tag[1], typ[1],
@@ -322,7 +326,7 @@ struct mdpd_system {
         toc(0);
         tic(1);
         if (perstep)
-            launch_nlist(st, fp32, R, cview(xs[cur]), cstart, ncnt, nl, nlr2, false);
+            launch_nlist(st, fp32, R, cview(xs[cur]), cstart, ncnt, nl, nlr2, list_all);
         else
             launch_skin_build(st, R, false, cview(xs[cur]), cstart, scnt, sl);
         toc(1);
@@ -358,7 +362,7 @@ struct mdpd_system {
         for (int64_t k = 0; k < nsteps; ++k) {
             step += 1;
             cur = 1 - cur;
-            gate_and_rebuild();
+            gate_and_rebuild(walls);
             evaluate(0);
         }
     }
@@ -378,7 +382,9 @@ struct mdpd_system {
             toc(4);
             launch_gate(st, R, 1, bmax, flags + nrep + 2, flags, flags + nrep + 1, dstep, ovf, nbuild, false);
             const Soa3 none{nullptr, nullptr, nullptr};
-            rebuild(none, none, perm_out ? perm_tmp + n : nullptr);
+            // with skin 0 the pair list of every replica is built here, once
+            // per step, after the corrector and the re-sort it may need
+            rebuild(none, none, perm_out ? perm_tmp + n : nullptr, perstep);
             if (perm_out) launch_compose(st, n, perm_tmp, perm_tmp + n, perm_out);
         }
         tic(2);

@@ -121,6 +121,36 @@ __device__ __forceinline__ void flush_far(__amdgpu_buffer_rsrc_t ro, const uint3
     __builtin_amdgcn_raw_buffer_store_b32(e, ro, lane < cf ? (cn + lane) * 4 : kDropOffset, 0, 0);
 }
 
+// Row assembly in LDS (the single-particle sweep): near hits go to nb[0 ..
+// 64) with their r^2 in rb, far hits to fb; flush_row then writes the whole
+// row (near, then far) and the near r^2 with one store each.  A row past
+// kListCap entries is never read; its excess goes to the lane's dump slot.
+template <typename R2>
+__device__ __forceinline__ void stage_hits(uint32_t *nb, R2 *rb, uint32_t *fb, uint32_t *dump,
+                                           unsigned long long mn, unsigned long long mf, int cn, int cf,
+                                           uint32_t e, double r2)
+{
+    const int lane = threadIdx.x & 63;
+    const bool near = __builtin_amdgcn_inverse_ballot_w64(mn);
+    const bool far = __builtin_amdgcn_inverse_ballot_w64(mf);
+    const int pn = lanes_below(mn, cn);
+    const int pf = lanes_below(mf, cf) & (kListCap - 1);
+    const bool keep = near && pn < kListCap;
+    *(keep ? nb + pn : dump + lane) = e | kNearBit;
+    if (keep) rb[pn] = (R2)r2;
+    *(far ? fb + pf : dump + lane) = e;
+}
+
+template <typename R2>
+__device__ __forceinline__ void flush_row(__amdgpu_buffer_rsrc_t ro, __amdgpu_buffer_rsrc_t rr, const uint32_t *nb,
+                                          const R2 *rb, const uint32_t *fb, int cn, int cf)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t e = lane < cn ? nb[lane] : fb[(lane - cn) & (kListCap - 1)];
+    __builtin_amdgcn_raw_buffer_store_b32(e, ro, lane < cn + cf ? lane * 4 : kDropOffset, 0, 0);
+    store_r2(rr, lane, lane < cn, rb[lane]);
+}
+
 // LDS of one wavefront: the far buffers of up to kGenBatch particles (one in
 // the interior path) and one slot per lane for lanes without a far hit.
 constexpr int kGenBatch = 8;
@@ -164,8 +194,14 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
     // if it is, so the minimum image by rounding picks exactly the pairs
     // through a boundary and gives the same difference as the general path's
     // explicit shift (a pair whose difference rounds to L/2 itself is more
-    // than r_c apart either way).
-    bool fast = interior || (nx >= 4 && ny >= 4 && nz >= 4);
+    // than r_c apart either way).  A thin y or z axis (one or two cells)
+    // takes it too: each distinct cell of the axis is visited once (offsets
+    // 0 and +1 with two cells, 0 with one), every difference is taken through
+    // the minimum image on that axis (every cell touches its boundary), and
+    // the rows off the own cell on it -- with one cell, all rows -- carry the
+    // wrap flag, since such a pair may be closest through the boundary.
+    const bool thin_y = ny <= 2, thin_z = nz <= 2;
+    bool fast = interior || (nx >= 4 && (ny >= 4 || thin_y) && (nz >= 4 || thin_z));
     // away from the x faces the stencil is 9 rows of 3 x-adjacent cells, each
     // contiguous in the sorted order
     const bool xin = cx > 0 && cx < nx - 1;
@@ -180,11 +216,15 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
         // the (wrapped) row cy + dy, cz + dz
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
-            const int yy = cy + r % 3 - 1, zz = cz + r / 3 - 1;
-            const bool w = yy < 0 || yy >= ny || zz < 0 || zz >= nz;
+            const int dy = r % 3 - 1, dz = r / 3 - 1;
+            const int yy = cy + dy, zz = cz + dz;
+            const bool skip = (ny == 1 && dy != 0) || (ny == 2 && dy < 0) || (nz == 1 && dz != 0) ||
+                              (nz == 2 && dz < 0);
+            const bool w = yy < 0 || yy >= ny || zz < 0 || zz >= nz || (thin_y && (dy != 0 || ny == 1)) ||
+                           (thin_z && (dz != 0 || nz == 1));
             const int base = cx + nx * (wrap_index(yy, ny) + ny * wrap_index(zz, nz));
             rb[r] = cstart[base - 1];
-            rl[r] = cstart[base + 2] - rb[r];
+            rl[r] = skip ? 0 : cstart[base + 2] - rb[r];
             rwrap |= (w ? 1u : 0u) << r;
         }
 #pragma unroll
@@ -193,12 +233,16 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
         // the rows of a cell on an x face: a row that wraps in x is two pieces
 #pragma unroll
         for (int z = 0; z < 3; ++z) {
-            const int zz = wrap_index(cz + z - 1, nz);
-            const bool wz = cz + z - 1 < 0 || cz + z - 1 >= nz;
+            const int dz = z - 1;
+            const int zz = wrap_index(cz + dz, nz);
+            const bool wz = cz + dz < 0 || cz + dz >= nz || (thin_z && (dz != 0 || nz == 1));
+            const bool skz = (nz == 1 && dz != 0) || (nz == 2 && dz < 0);
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
-                const int yy = wrap_index(cy + r - 1, ny);
-                const bool wy = cy + r - 1 < 0 || cy + r - 1 >= ny;
+                const int dy = r - 1;
+                const int yy = wrap_index(cy + dy, ny);
+                const bool wy = cy + dy < 0 || cy + dy >= ny || (thin_y && (dy != 0 || ny == 1));
+                const bool skip = skz || (ny == 1 && dy != 0) || (ny == 2 && dy < 0);
                 const int base = nx * (yy + ny * zz);
                 int a0, a1, b0, b1;
                 bool wa = wz || wy, wb = wz || wy;
@@ -221,9 +265,9 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
                 }
                 const int k = 6 * z + 2 * r;
                 pb[k] = cstart[a0];
-                pl[k] = cstart[a1] - pb[k];
+                pl[k] = skip ? 0 : cstart[a1] - pb[k];
                 pb[k + 1] = cstart[b0];
-                pl[k + 1] = cstart[b1] - pb[k + 1];
+                pl[k + 1] = skip ? 0 : cstart[b1] - pb[k + 1];
                 pwrap |= (wa ? 1u : 0u) << k;
                 pwrap |= (wb ? 1u : 0u) << (k + 1);
                 qz[z] += pl[k] + pl[k + 1];
@@ -272,6 +316,10 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
             cyj[s] = ld(xs.y, js);
             czj[s] = ld(xs.z, js);
         }
+        // the single-particle sweep assembles each row in the wavefront's
+        // LDS past its far buffer (the batch buffers of the general path)
+        uint32_t *const near_lds = far_lds + kListCap;
+        R2 *const near_r2 = reinterpret_cast<R2 *>(far_lds + 2 * kListCap);
         // particle i is candidate selfq0 + i of the dz = 0 batch: after the
         // dy = -1 row and the own row's cells left of the own cell
         const int selfq0 = xin ? rl[3] - rb[4] : pl[6] + pl[7] + left - i0;
@@ -304,11 +352,11 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
                         if ((s >> 1) == 1 && (sq >> 6) == (s & 1)) hm &= ~(1ull << (sq & 63));
                         const unsigned long long nm = __builtin_amdgcn_ballot_w64(r2 < rd2);
                         const unsigned long long mn = hm & nm, mf = hm & ~nm;
-                        emit_hits<R2>(ro, rr, far_lds, dump, mn, mf, cn, cf, (uint32_t)cs[s], r2);
+                        stage_hits<R2>(near_lds, near_r2, far_lds, dump, mn, mf, cn, cf, (uint32_t)cs[s], r2);
                         cn += __popcll(mn);
                         cf += __popcll(mf);
                     }
-                    flush_far(ro, far_lds, cn, cf);
+                    flush_row<R2>(ro, rr, near_lds, near_r2, far_lds, cn, cf);
                     if (lane == 0) ncnt[i] = cn | (cf << 16);
                 }
             }
@@ -433,7 +481,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     R2 *__restrict__ nlr2, int all)
 {
     if (!all && cload(R.flag, R.nrep) == 0) return;
-    __shared__ uint32_t lds[kWavesPerBlock * kFarLds];
+    __shared__ __align__(16) uint32_t lds[kWavesPerBlock * kFarLds];
     const int cg = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
     if (cg >= R.ncells) return;
     nlist_cell<R2, false>(R, cg, xs, cstart_all, ncnt, nl, nlr2, lds + (threadIdx.x >> 6) * kFarLds, all);
@@ -445,7 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist_border(Reps R, Soa3c xs, const
                                                          R2 *__restrict__ nlr2, int all)
 {
     if (!all && cload(R.flag, R.nrep) == 0) return;
-    __shared__ uint32_t lds[kWavesPerBlock * kFarLds];
+    __shared__ __align__(16) uint32_t lds[kWavesPerBlock * kFarLds];
     const int w = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
     const int S = R.list_split;
     if (w >= R.nbcells * S) return;

@@ -101,6 +101,7 @@ def small_cases():
         "box_5x3.5x8.25": W.bulk(box=(5.0, 3.5, 8.25), n=900, seed=3),
         "two_cells_2x2.5x7": W.bulk(box=(2.0, 2.5, 7.0), n=210, seed=6),
         "slab_10x2x10": W.bulk(box=(10.0, 2.0, 10.0), n=1200, seed=7),
+        "slab_8x8x2.5": W.bulk(box=(8.0, 8.0, 2.5), n=960, seed=8),
         "dense_cluster": dense_cluster(),
         "mixed_types": mixed_types(),
     }
