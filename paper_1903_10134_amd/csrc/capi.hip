@@ -652,10 +652,14 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     R.nbcells = (int)bcells.size();
     R.list_interior = one_launch ? 0 : 1;
     R.list_split = s->lanes[0];
-    // every-step sort in one workgroup per replica when each replica's cell
-    // offsets and ids fit its LDS (64 KiB) and its particles the threads
+    // every-step sort in one workgroup per replica for a batch of many
+    // replicas (measured: 256 replicas of 3,000 to 10,000 particles 1.021
+    // against 1.033 ms per step; a single 6,000-particle system 47 against
+    // 41 us, one workgroup being slower than five launches over the whole
+    // chip), when each replica's cell offsets and ids fit its LDS (64 KiB)
+    // and its particles the threads
     R.sort_small_lds = 0;
-    if (s->perstep) {
+    if (s->perstep && nrep >= kSortSmallMinReplicas) {
         int64_t need = 0;
         bool fits = true;
         for (int r = 0; r < nrep; ++r) {

@@ -34,6 +34,7 @@ constexpr int kBlock = 256;    // threads per block of the particle kernels
 constexpr int kSortSmallMaxN = 12 * 1024;
 constexpr int kSortSmallMaxCells = 4096;
 constexpr int kSortSmallMaxLds = 65536 - 256;
+constexpr int kSortSmallMinReplicas = 64;  // below that the multi-pass sort is faster
 constexpr uint32_t kFrozenBit = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7fffffffu;
 

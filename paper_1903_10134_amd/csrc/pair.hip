@@ -200,7 +200,9 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
     // the minimum image on that axis (every cell touches its boundary), and
     // the rows off the own cell on it -- with one cell, all rows -- carry the
     // wrap flag, since such a pair may be closest through the boundary.
-    const bool thin_y = ny <= 2, thin_z = nz <= 2;
+    // (interior cells need three cells per axis, so only the border
+    // instantiation can see a thin axis)
+    const bool thin_y = BORDER && ny <= 2, thin_z = BORDER && nz <= 2;
     bool fast = interior || (nx >= 4 && (ny >= 4 || thin_y) && (nz >= 4 || thin_z));
     // away from the x faces the stencil is 9 rows of 3 x-adjacent cells, each
     // contiguous in the sorted order
@@ -218,8 +220,7 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
         for (int r = 0; r < 9; ++r) {
             const int dy = r % 3 - 1, dz = r / 3 - 1;
             const int yy = cy + dy, zz = cz + dz;
-            const bool skip = (ny == 1 && dy != 0) || (ny == 2 && dy < 0) || (nz == 1 && dz != 0) ||
-                              (nz == 2 && dz < 0);
+            const bool skip = (thin_y && (ny == 1 ? dy != 0 : dy < 0)) || (thin_z && (nz == 1 ? dz != 0 : dz < 0));
             const bool w = yy < 0 || yy >= ny || zz < 0 || zz >= nz || (thin_y && (dy != 0 || ny == 1)) ||
                            (thin_z && (dz != 0 || nz == 1));
             const int base = cx + nx * (wrap_index(yy, ny) + ny * wrap_index(zz, nz));
@@ -236,13 +237,13 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
             const int dz = z - 1;
             const int zz = wrap_index(cz + dz, nz);
             const bool wz = cz + dz < 0 || cz + dz >= nz || (thin_z && (dz != 0 || nz == 1));
-            const bool skz = (nz == 1 && dz != 0) || (nz == 2 && dz < 0);
+            const bool skz = thin_z && (nz == 1 ? dz != 0 : dz < 0);
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
                 const int dy = r - 1;
                 const int yy = wrap_index(cy + dy, ny);
                 const bool wy = cy + dy < 0 || cy + dy >= ny || (thin_y && (dy != 0 || ny == 1));
-                const bool skip = skz || (ny == 1 && dy != 0) || (ny == 2 && dy < 0);
+                const bool skip = skz || (thin_y && (ny == 1 ? dy != 0 : dy < 0));
                 const int base = nx * (yy + ny * zz);
                 int a0, a1, b0, b1;
                 bool wa = wz || wy, wb = wz || wy;
