@@ -74,8 +74,9 @@ enum { MDPD_FP64 = 0, MDPD_FP32_FORCES = 1 };
  *                   the predicted position, the normal part is negated and
  *                   the tangential part scaled by 2 wall_slip - 1: 1 gives
  *                   specular reflection (full slip), 0.5 drops the
- *                   tangential velocity (a zero normal sum falls back to
- *                   bounce-back). */
+ *                   tangential velocity (a zero normal sum, and a particle
+ *                   also sent back in the step before, fall back to
+ *                   bounce-back, so it leaves the wall the way it came). */
 enum { MDPD_WALL_OFF = 0, MDPD_WALL_BVF = 1 };
 
 typedef struct {

@@ -44,7 +44,8 @@
  *       wall_slip > 0 v_half is reflected about the unit wall normal
  *       n = unit(sum_{frozen j, r<r_c} w_c^2 (x_i - x_j)/r) at x*: normal
  *       part negated, tangential part times (2 wall_slip - 1); a zero normal
- *       sum falls back to bounce-back.
+ *       sum, and a particle that was also sent back in the step before, fall
+ *       back to bounce-back (it leaves the wall the way it came).
  *   R5  Mass m; body force acts on fluid as m*g.
  *   R6  Control of the effective fluid-solid dissipation (Sec. 2.2), on when
  *       diss_ctrl = eta > 0: for fluid i, the dissipative weight it gets from
@@ -534,6 +535,7 @@ typedef struct {
     double *x, *v, *vh, *F, *rho, *phi, *xprev, *dsc, *phi2;
     int32_t *type;
     uint8_t *frozen;
+    uint8_t *rej;  /* reading R4 with wall_slip > 0: sent back in the last step */
     uint32_t step;
     int64_t ncorr_last, ncorr_total;
     double virial, epair;
@@ -569,6 +571,7 @@ void orc_destroy(orc_system *s)
     free(s->xprev);
     free(s->type);
     free(s->frozen);
+    free(s->rej);
     free(s);
 }
 
@@ -592,6 +595,7 @@ orc_system *orc_create(const orc_params *p, int64_t n, const double *x, const do
     s->dsc = (double *)calloc(nn, sizeof(double));
     s->type = (int32_t *)malloc(nn * sizeof(int32_t));
     s->frozen = (uint8_t *)malloc(nn);
+    s->rej = (uint8_t *)calloc(nn, 1);
     for (int64_t i = 0; i < n; ++i) {
         s->type[i] = type[i];
         s->frozen[i] = frozen[i] ? 1 : 0;
@@ -617,10 +621,13 @@ static int64_t orc_correct(orc_system *s)
     orc_phi_nl(&s->p, s->n, s->x, s->frozen, &nl, s->phi);
     int64_t cnt = 0;
     for (int64_t i = 0; i < s->n; ++i) {
-        if (s->frozen[i] || !(s->phi[i] > s->p.phi_c)) continue;
+        const int hit = !s->frozen[i] && s->phi[i] > s->p.phi_c;
+        const int again = s->rej[i];
+        s->rej[i] = (uint8_t)hit;
+        if (!hit) continue;
         double nrm[3];
         double *v = &s->vh[3 * i];
-        if (s->p.wall_slip > 0.0 && orc_wall_normal(&s->p, s->x, s->frozen, &nl, i, nrm)) {
+        if (s->p.wall_slip > 0.0 && !again && orc_wall_normal(&s->p, s->x, s->frozen, &nl, i, nrm)) {
             double vn = v[0] * nrm[0] + v[1] * nrm[1] + v[2] * nrm[2];
             double ft = 2.0 * s->p.wall_slip - 1.0;
             for (int a = 0; a < 3; ++a) v[a] = ft * (v[a] - vn * nrm[a]) - vn * nrm[a];

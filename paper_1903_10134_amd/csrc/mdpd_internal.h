@@ -36,7 +36,10 @@ constexpr int kSortSmallMaxCells = 4096;
 constexpr int kSortSmallMaxLds = 65536 - 256;
 constexpr int kSortSmallMinReplicas = 64;  // below that the multi-pass sort is faster
 constexpr uint32_t kFrozenBit = 0x80000000u;
-constexpr uint32_t kIdMask = 0x7fffffffu;
+// wall slip: the particle was sent back by the corrector in the last step
+// (ids are below 2^30, so bit 30 is free)
+constexpr uint32_t kRejectBit = 0x40000000u;
+constexpr uint32_t kIdMask = 0x3fffffffu;
 
 struct Soa3 {
     double *x, *y, *z;
@@ -330,7 +333,8 @@ void launch_density(hipStream_t st, int lanes, bool fp32, const Reps &R, Soa3c x
 void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint32_t *tag, uint8_t *wmask);
 // ncorr: [0] corrections of this step (written), [1..n] per-slot flags,
 // then one count per kBlock slots (scratch); ncorr_total accumulates.
-// slip: some replica reflects with wall_slip > 0 (the wall normal is needed).
+// slip: some replica reflects with wall_slip > 0 (the wall normal is needed;
+// the corrector keeps kRejectBit of each fluid tag up to date).
 // byid (nullable, n bytes by global particle id): set to 1 for every particle
 // corrected in this step (the adjoint's record of the wall events).
 // A corrected particle goes back to xprev; cmax receives, per block of
@@ -338,7 +342,7 @@ void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint3
 // largest squared distance of a corrected particle from its build position
 // xbuild (0 without corrections), for the step's second gate.
 void launch_phi(hipStream_t st, int lanes, bool slip, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix,
-                Soa3 vfix, const uint32_t *tag, const int *cstart, const uint8_t *wmask, int *ncorr,
+                Soa3 vfix, uint32_t *tag, const int *cstart, const uint8_t *wmask, int *ncorr,
                 unsigned long long *ncorr_total, uint8_t *byid, Soa3c xbuild, float *cmax);
 // stepp: device word holding the noise step (advanced by the gate).  The
 // epilogue writes the next positions and half-step velocities to xpred,

@@ -949,7 +949,9 @@ __global__ __launch_bounds__(kBlock) void k_phi(Reps R, Soa3c xs, const uint32_t
             ny = group_sum<P>(ny);
             nz = group_sum<P>(nz);
             const double n2 = nx * nx + ny * ny + nz * nz;
-            if (hit && pc.slip > 0.0 && n2 > 0.0 && sub == 0) {
+            // a particle also sent back in the last step is bounced back
+            // (flag 1) so that it leaves the wall the way it came
+            if (hit && pc.slip > 0.0 && n2 > 0.0 && sub == 0 && !(tag[ii] & kRejectBit)) {
                 const double inv = 1.0 / __builtin_sqrt(n2);
                 const double ux = nx * inv, uy = ny * inv, uz = nz * inv;
                 const double vx = vh.x[ii], vy = vh.y[ii], vz = vh.z[ii];
@@ -976,7 +978,7 @@ __global__ __launch_bounds__(kBlock) void k_phi(Reps R, Soa3c xs, const uint32_t
 // a corrected particle also sets byid[part_off[r] + id].
 __global__ __launch_bounds__(kBlock) void k_correct(Reps R, const int *__restrict__ flag, Soa3c xprev, Soa3 xs,
                                                     Soa3 vh, int *__restrict__ part,
-                                                    const uint32_t *__restrict__ tag, uint8_t *__restrict__ byid,
+                                                    uint32_t *__restrict__ tag, uint8_t *__restrict__ byid,
                                                     Soa3c xbuild, float *__restrict__ cmax)
 {
     __shared__ int cnt[kWavesPerBlock];
@@ -986,6 +988,12 @@ __global__ __launch_bounds__(kBlock) void k_correct(Reps R, const int *__restric
     int hit = 0;
     float d2 = 0.0f;
     const int f = i < br.i1 ? flag[i] : 0;
+    if (i < br.i1 && cload(R.pc, br.r).slip > 0.0) {
+        // wall slip: remember which fluid particles were sent back this step
+        const uint32_t tg = tag[i];
+        if (!(tg & kFrozenBit) && ((tg & kRejectBit) != 0) != (f != 0))
+            tag[i] = f ? (tg | kRejectBit) : (tg & ~kRejectBit);
+    }
     if (f) {
         const double px = xprev.x[i], py = xprev.y[i], pz = xprev.z[i];
         xs.x[i] = px;
@@ -1678,7 +1686,7 @@ void launch_mark_wall_cells(hipStream_t st, const Reps &R, Soa3c xs, const uint3
 }
 
 void launch_phi(hipStream_t st, int lanes, bool slip, int n, const Reps &R, Soa3c xs, Soa3c xprev, Soa3 xfix,
-                Soa3 vfix, const uint32_t *tag, const int *cstart, const uint8_t *wmask, int *flag_and_count,
+                Soa3 vfix, uint32_t *tag, const int *cstart, const uint8_t *wmask, int *flag_and_count,
                 unsigned long long *ncorr_total, uint8_t *byid, Soa3c xbuild, float *cmax)
 {
     if (n <= 0) return;

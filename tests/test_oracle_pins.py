@@ -411,6 +411,29 @@ def test_wall_reflection_with_a_tangential_kick(orc, slip):
     assert np.allclose(st["v"][0], exp, atol=1e-15, rtol=0)
 
 
+@pytest.mark.parametrize("slip", [0.25, 1.0])
+def test_reflection_twice_in_a_row_bounces_back(orc, slip):
+    """The same wall, a particle held against it by a body force along the
+    normal, g = (0, -0.5, 0): its half kick k = (0, -1/64, 0) with v(0) =
+    (1, 0, 1) makes every prediction land at (x, z) = (0.25, 0.25) +- the
+    tangential step, within reach of the wall only (phi = 1), so every step
+    is rejected.  The first rejection reflects (the normal kick cancels,
+    v(1) = ((2s - 1), 0, (2s - 1))); a particle sent back again in the next
+    step is bounced back instead (v(2) = -v(1)), and so on, with x fixed.
+    Reflecting every time would keep v(2) = ((2s - 1)^2, 0, (2s - 1)^2)."""
+    v0 = np.array([1.0, 0.0, 1.0])
+    p, x, v, t, f = wall_and_particle(orc, slip, v0, g=(0.0, -0.5, 0.0))
+    s = orc.System(p, x, v, t, f)
+    ft = 2.0 * slip - 1.0
+    v1 = np.array([ft, 0.0, ft])
+    for k, exp in enumerate((v1, -v1, v1, -v1)):
+        s.step(1)
+        st = s.state()
+        assert s.observables()["ncorr_last"] == 1, k
+        assert np.array_equal(st["x"][0], x[0]), k
+        assert np.allclose(st["v"][0], exp, atol=1e-15, rtol=0), (k, st["v"][0], exp)
+
+
 def test_specular_reflection_keeps_speeds(orc):
     """Rough wall (uniform-random frozen particles in y in [0, 2)), fluid
     above it moving towards it, no forces: with wall_slip = 1 every speed is
