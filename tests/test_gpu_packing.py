@@ -109,28 +109,37 @@ def test_slab_pore_walls(mdpd, db):
 
 def test_porous_geometry_patch_walls(mdpd, db):
     """An irregular pore space (a 24^3 Gaussian-random-field mask at porosity
-    0.4) walled by the patch packing, driven along x: after 2,000 steps no
+    0.4) walled by the patch packing, driven along x: after 3,000 steps no
     fluid particle sits in a solid voxel beyond the surface layer (the deeper
     solid is empty and must stay unreachable), the fluid moves along the
-    force, and its temperature stays at kT = 1 within 3%."""
+    force, and its temperature stays at kT = 1 within 3%.  The flow is the
+    fluid's mean v_x averaged over the last 2,000 steps (a single snapshot's
+    mean has a thermal spread of about 1 / sqrt(n_fluid) = 0.0055, above the
+    Darcy velocity of these narrow pores); it must exceed three standard
+    errors of that average (from the means of ten 200-step blocks)."""
     from paper_1903_10134_amd import workloads as Wk
     pore = Wk.grf_mask(24, corr=3.0, porosity=0.4, seed=2)
     w = K.voxel_workload(pore, h=1.0, fluid_density=6.0, wall="patch", db=db, seed=3, g=(0.02, 0.0, 0.0))
     say("porous patch walls", w.n)
     surf = K.surface_wall_voxels(pore, 1)
+    nf = w.info["n_fluid"]
     s = mdpd.System(w, precision=mdpd.FP32_FORCES)
-    s.step(2000)
+    s.step(1000)
+    vx = []
+    for _ in range(100):
+        s.step(20)
+        vx.append(s.state()[1][:nf, 0].mean())
     x, v, _ = s.state()
     ob = s.observables()
     s.close()
-    nf = w.info["n_fluid"]
     c = np.floor(x[:nf]).astype(int) % 24
     inside = pore[c[:, 0], c[:, 1], c[:, 2]] | surf[c[:, 0], c[:, 1], c[:, 2]]
-    vx = v[:nf, 0].mean()
+    blocks = np.asarray(vx).reshape(10, 10).mean(axis=1)
+    u, se = blocks.mean(), blocks.std(ddof=1) / np.sqrt(len(blocks))
     print(f"\nporous: {nf} fluid, {w.info['n_wall']} wall particles, {int(surf.sum())} surface voxels; "
           f"fluid in deep solid {int((~inside).sum())}, in surface voxels "
-          f"{int(surf[c[:, 0], c[:, 1], c[:, 2]].sum())}; mean v_x {vx:.4f}; kT {ob['kT']:.3f}; "
-          f"corrections {ob['ncorr_total']}")
+          f"{int(surf[c[:, 0], c[:, 1], c[:, 2]].sum())}; mean v_x {u:.4f} +- {se:.4f} (last snapshot "
+          f"{vx[-1]:.4f}); kT {ob['kT']:.3f}; corrections {ob['ncorr_total']}")
     assert np.all(inside)
-    assert vx > 0.0
+    assert u > 3.0 * se
     assert abs(ob["kT"] - 1.0) < 0.03
