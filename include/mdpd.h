@@ -59,7 +59,10 @@ enum { MDPD_MEM_HOST = 0, MDPD_MEM_DEVICE = 1 };
  * neighbour sets do not depend on the form, and positions, velocities,
  * velocity-Verlet and global sums are FP64.
  *   MDPD_FP64         pair math, density and per-particle force sums in FP64
- *   MDPD_FP32_FORCES  pair math, density and per-particle force sums in FP32 */
+ *   MDPD_FP32_FORCES  pair math, density and per-particle force sums in FP32;
+ *                     the force pass takes each pair's position difference
+ *                     from fixed-point coordinates (resolution box / 2^32 per
+ *                     axis) and its velocity difference from FP32 copies */
 enum { MDPD_FP64 = 0, MDPD_FP32_FORCES = 1 };
 
 /* Wall treatment (Sec. 2.2, Sec. 3.2):

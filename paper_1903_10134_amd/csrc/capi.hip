@@ -519,6 +519,8 @@ PairConst make_pair_const(const mdpd_params *p, const double *tab)
     for (int a = 0; a < 3; ++a) {
         pc.L[a] = p->box[a];
         pc.invL[a] = 1.0 / p->box[a];
+        pc.qs[a] = 4294967296.0 / p->box[a];
+        pc.qd[a] = (float)(p->box[a] / 4294967296.0);
         pc.mg[a] = p->mass * p->body_force[a];
     }
     pc.rc = p->rc;

@@ -61,6 +61,19 @@ struct alignas(16) PartRec {
 };
 static_assert(sizeof(PartRec) == 64, "PartRec must be one 64-byte sector");
 
+// The neighbour record of the FP32 form: half the bytes per gathered
+// neighbour (the type, with several types, comes from the type array).  The position is fixed point in units of L / 2^32 per
+// axis (q = round(x 2^32 / L) mod 2^32): the difference of two, read as a
+// signed 32-bit integer, is the minimum-image difference, exact, with a
+// resolution of L / 2^32 (1.3e-8 at L = 56).
+struct alignas(32) PartRec32 {
+    uint32_t qx, qy, qz;  // fixed-point position
+    float vx, vy, vz;     // half-step velocity (0 for frozen particles)
+    float rho;            // many-body density
+    uint32_t tag;         // id | flag bits
+};
+static_assert(sizeof(PartRec32) == 32, "PartRec32 must be one 32-byte sector");
+
 // Cell lattice: nc[a] cells of edge L[a]/nc[a] >= r_c + skin per axis.
 // The cells and the skin list are built together; until the next build a
 // particle moves less than half the skin (slack), so a cell scan stays
@@ -90,6 +103,8 @@ struct PairConst {
     double A, B, gamma, sig, Arc2;  // single-type values; sig = sqrt(2 gamma kT / dt)
     double phi_c;
     double slip;        // wall reflection: tangential factor 2 slip - 1 (0: bounce-back)
+    double qs[3];       // 2^32 / L: fixed-point scale of the 32-byte records
+    float qd[3];        // L / 2^32
     double dctl;        // dissipation control: eta rho_f W_D (0: off); fluid-frozen pairs of
                         // fluid i take gamma s_i, sigma sqrt(s_i), s_i = dctl / sum_{j, r<r_c} w_c^2
     const double *tab;  // ntypes > 1: A | B | gamma | sig | Arc2 planes of 64

@@ -638,6 +638,77 @@ __device__ __forceinline__ float w_rho<float>(const PairConst &pc, float r2)
     return (float)pc.wrho * u * u;
 }
 
+// ---------------------------------------------------------------------------
+// The neighbour record of slot i and its density rho_i, written by the P lanes
+// of i (sub = lane in the group).  The FP32 form writes the 32-byte
+// fixed-point record, the FP64 form the 64-byte one.  With P = 4 the four
+// lanes write a quarter of the record each, so one store instruction covers
+// 16 whole records.
+template <int P, typename R>
+__device__ __forceinline__ void put_record(const PairConst &pc, int i, int sub, Soa3c xs, Soa3c vh,
+                                           const uint32_t *__restrict__ tag, const uint8_t *__restrict__ typ,
+                                           R acc, R *__restrict__ rho, PartRec *__restrict__ rec)
+{
+    if (sub == 0) rho[i] = acc;
+    const uint32_t tg = tag[i];
+    const bool fz = (tg & kFrozenBit) != 0;
+    if constexpr (sizeof(R) == 4) {
+        // qx qy | qz vx | vy vz | rho tag
+        PartRec32 *const r32 = reinterpret_cast<PartRec32 *>(rec);
+        auto vel = [&](double u) { return __float_as_uint(fz ? 0.0f : (float)u); };
+        if constexpr (P == 4) {
+            const double *pa = sub == 0 ? xs.x : (sub == 1 ? xs.z : vh.y);
+            const double *pb = sub == 0 ? xs.y : (sub == 1 ? vh.x : vh.z);
+            uint2 w;
+            if (sub < 3) {
+                const double a = pa[i], b = pb[i];
+                w.x = sub < 2 ? qfix(a, sub == 0 ? pc.qs[0] : pc.qs[2]) : vel(a);
+                w.y = sub == 0 ? qfix(b, pc.qs[1]) : vel(b);
+            } else {
+                w = make_uint2(__float_as_uint((float)acc), tg);
+            }
+            reinterpret_cast<uint2 *>(r32 + i)[sub] = w;
+        } else if (sub == 0) {
+            PartRec32 o;
+            o.qx = qfix(xs.x[i], pc.qs[0]);
+            o.qy = qfix(xs.y[i], pc.qs[1]);
+            o.qz = qfix(xs.z[i], pc.qs[2]);
+            o.vx = __uint_as_float(vel(vh.x[i]));
+            o.vy = __uint_as_float(vel(vh.y[i]));
+            o.vz = __uint_as_float(vel(vh.z[i]));
+            o.rho = (float)acc;
+            o.tag = tg;
+            r32[i] = o;
+        }
+    } else if constexpr (P == 4) {
+        // x y | z vx | vy vz | rho tag typ
+        const double *pa = sub == 0 ? xs.x : (sub == 1 ? xs.z : vh.y);
+        const double *pb = sub == 0 ? xs.y : (sub == 1 ? vh.x : vh.z);
+        double a = pa[i], b = pb[i];
+        if (fz && sub >= 1) {
+            b = 0.0;
+            if (sub >= 2) a = 0.0;
+        }
+        if (sub == 3) {
+            a = (double)acc;
+            b = __longlong_as_double((long long)((unsigned long long)tg | ((unsigned long long)typ[i] << 32)));
+        }
+        reinterpret_cast<double2 *>(rec + i)[sub] = make_double2(a, b);
+    } else if (sub == 0) {
+        PartRec o;
+        o.x = xs.x[i];
+        o.y = xs.y[i];
+        o.z = xs.z[i];
+        o.vx = fz ? 0.0 : vh.x[i];
+        o.vy = fz ? 0.0 : vh.y[i];
+        o.vz = fz ? 0.0 : vh.z[i];
+        o.rho = (double)acc;
+        o.tag = tg;
+        o.typ = typ[i];
+        rec[i] = o;
+    }
+}
+
 // Density from the per-step list: the stored r^2 of the near entries (r < r_d
 // first in the row), or a direct scan for a row that overflowed; also packs
 // the neighbour records.
@@ -675,41 +746,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         });
     }
     acc = group_sum<P>(acc);
-    if constexpr (P == 4) {
-        // the four lanes of i write its record together, 16 bytes each
-        // (x y | z vx | vy vz | rho tag typ), so one store instruction
-        // covers 16 whole records
-        const uint32_t tg = tag[i];
-        const bool fz = (tg & kFrozenBit) != 0;
-        const double *pa = sub == 0 ? xs.x : (sub == 1 ? xs.z : vh.y);
-        const double *pb = sub == 0 ? xs.y : (sub == 1 ? vh.x : vh.z);
-        double a = pa[i], b = pb[i];
-        if (fz && sub >= 1) {
-            b = 0.0;
-            if (sub >= 2) a = 0.0;
-        }
-        if (sub == 3) {
-            a = (double)acc;
-            b = __longlong_as_double((long long)((unsigned long long)tg | ((unsigned long long)typ[i] << 32)));
-        }
-        if (sub == 0) rho[i] = acc;
-        reinterpret_cast<double2 *>(rec + i)[sub] = make_double2(a, b);
-    } else if (sub == 0) {
-        rho[i] = acc;
-        const uint32_t tg = tag[i];
-        const bool fz = (tg & kFrozenBit) != 0;
-        PartRec q;
-        q.x = xs.x[i];
-        q.y = xs.y[i];
-        q.z = xs.z[i];
-        q.vx = fz ? 0.0 : vh.x[i];
-        q.vy = fz ? 0.0 : vh.y[i];
-        q.vz = fz ? 0.0 : vh.z[i];
-        q.rho = (double)acc;
-        q.tag = tg;
-        q.typ = typ[i];
-        rec[i] = q;
-    }
+    put_record<P, R>(pc, i, sub, xs, vh, tag, typ, acc, rho, rec);
 }
 
 // Pair list and density.  The P lanes of particle i take its skin entries in
@@ -779,41 +816,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     }
     acc = group_sum<P>(acc);
     if (!rho) return;  // the pair list only
-    if constexpr (P == 4) {
-        // the four lanes of i write its record together, 16 bytes each
-        // (x y | z vx | vy vz | rho tag typ), so one store instruction
-        // covers 16 whole records
-        const uint32_t tg = tag[i];
-        const bool fz = (tg & kFrozenBit) != 0;
-        const double *pa = sub == 0 ? xs.x : (sub == 1 ? xs.z : vh.y);
-        const double *pb = sub == 0 ? xs.y : (sub == 1 ? vh.x : vh.z);
-        double a = pa[i], b = pb[i];
-        if (fz && sub >= 1) {
-            b = 0.0;
-            if (sub >= 2) a = 0.0;
-        }
-        if (sub == 3) {
-            a = (double)acc;
-            b = __longlong_as_double((long long)((unsigned long long)tg | ((unsigned long long)typ[i] << 32)));
-        }
-        if (sub == 0) rho[i] = acc;
-        reinterpret_cast<double2 *>(rec + i)[sub] = make_double2(a, b);
-    } else if (sub == 0) {
-        rho[i] = acc;
-        const uint32_t tg = tag[i];
-        const bool fz = (tg & kFrozenBit) != 0;
-        PartRec q;
-        q.x = xs.x[i];
-        q.y = xs.y[i];
-        q.z = xs.z[i];
-        q.vx = fz ? 0.0 : vh.x[i];
-        q.vy = fz ? 0.0 : vh.y[i];
-        q.vz = fz ? 0.0 : vh.z[i];
-        q.rho = (double)acc;
-        q.tag = tg;
-        q.typ = typ[i];
-        rec[i] = q;
-    }
+    put_record<P, R>(pc, i, sub, xs, vh, tag, typ, acc, rho, rec);
 }
 
 // ---------------------------------------------------------------------------
@@ -1227,7 +1230,8 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
     WallDiss<R, DC> wd;
     const bool dc_on = DC && pc.dctl > 0.0;
     // pair arithmetic for one neighbour whose data is already loaded
-    auto pair = [&](double dx, double dy, double dz, double vxj, double vyj, double vzj, R rj, uint32_t tgj,
+    // (dv = v_half,i - v_half,j)
+    auto pair = [&](double dx, double dy, double dz, double dvx, double dvy, double dvz, R rj, uint32_t tgj,
                     int tj, bool near) {
         double A = pc.A, B = pc.B, gam = pc.gamma, sig = pc.sig, Arc2 = pc.Arc2;
         if (MT) {
@@ -1241,17 +1245,46 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
         const int th = theta_int(idi, tgj & kIdMask, pc);
         const double c = (tgj & kFrozenBit) ? 1.0 : 0.5;
         if (dc_on) {
-            pair_force<R, DC>(pc, A, B, gam, sig, Arc2, dx, dy, dz, vxi - vxj, vyi - vyj, vzi - vzj, near,
-                              rhoi + rj, th, c, fx, fy, fz, vir, ep, &wd, (tgj & kFrozenBit) != 0);
+            pair_force<R, DC>(pc, A, B, gam, sig, Arc2, dx, dy, dz, dvx, dvy, dvz, near, rhoi + rj, th, c, fx, fy,
+                              fz, vir, ep, &wd, (tgj & kFrozenBit) != 0);
         } else {
-            pair_force<R>(pc, A, B, gam, sig, Arc2, dx, dy, dz, vxi - vxj, vyi - vyj, vzi - vzj, near, rhoi + rj,
-                          th, c, fx, fy, fz, vir, ep);
+            pair_force<R>(pc, A, B, gam, sig, Arc2, dx, dy, dz, dvx, dvy, dvz, near, rhoi + rj, th, c, fx, fy, fz,
+                          vir, ep);
         }
     };
-    if constexpr (SCAN) {
+    // the FP32 form reads the 32-byte fixed-point records (the type of a
+    // neighbour, with several types, from the type array)
+    constexpr bool Q = sizeof(R) == 4;
+    if constexpr (Q && !SCAN) {
+        const PartRec32 *__restrict__ r32 = reinterpret_cast<const PartRec32 *>(rec);
+        const uint32_t qxi = qfix(xi, pc.qs[0]), qyi = qfix(yi, pc.qs[1]), qzi = qfix(zi, pc.qs[2]);
+        const float vxf = (float)vxi, vyf = (float)vyi, vzf = (float)vzi;
+        // Each lane loads its own neighbour's record: two 16-byte loads of one
+        // 32-byte sector (regrouping a quad's four records through LDS, as
+        // the 64-byte records do, measured slower here: force pass 166
+        // against 159 us at 1M particles).  The next entry and its record are
+        // loaded one iteration ahead (155 against 159 us).  Entries past the
+        // row stand in as slot 0.
+        const int cnt = list_total(packed);
+        uint32_t e = sub < cnt ? lst[sub] : 0u;
+        uint4 p0 = ((const uint4 *)(r32 + (int)(e & kSlotMask)))[0];  // qx qy qz vx
+        uint4 p1 = ((const uint4 *)(r32 + (int)(e & kSlotMask)))[1];  // vy vz rho tag
+        for (int k = sub; k < cnt; k += P) {
+            const uint32_t en = k + P < cnt ? lst[k + P] : 0u;
+            const uint4 *rn = (const uint4 *)(r32 + (int)(en & kSlotMask));
+            const uint4 n0 = rn[0], n1 = rn[1];
+            pair(qdiff(qxi, p0.x, pc.qd[0]), qdiff(qyi, p0.y, pc.qd[1]), qdiff(qzi, p0.z, pc.qd[2]),
+                 vxf - __uint_as_float(p0.w), vyf - __uint_as_float(p1.x), vzf - __uint_as_float(p1.y),
+                 __uint_as_float(p1.z), p1.w, MT ? (int)typ[e & kSlotMask] : 0, (e & kNearBit) != 0);
+            e = en;
+            p0 = n0;
+            p1 = n1;
+        }
+    } else if constexpr (SCAN) {
         for_each_neighbor<P>(pc, g, i, sub, xi, yi, zi, xs, cstart, packed, nullptr,
                              [&](int j, double dx, double dy, double dz, bool near) {
-                                 pair(dx, dy, dz, ld(vh.x, j), ld(vh.y, j), ld(vh.z, j), ld(rho, j), ld(tag, j),
+                                 pair(dx, dy, dz, vxi - ld(vh.x, j), vyi - ld(vh.y, j), vzi - ld(vh.z, j),
+                                      ld(rho, j), ld(tag, j),
                                       MT ? (int)ld(typ, j) : 0, near);
                              });
     } else if constexpr (P >= 4) {
@@ -1293,7 +1326,7 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
                     dy = min_image(dy, pc.L[1], pc.invL[1]);
                     dz = min_image(dz, pc.L[2], pc.invL[2]);
                 }
-                pair(dx, dy, dz, b.y, c.x, c.y, rj, tgj, tj, (e & kNearBit) != 0);
+                pair(dx, dy, dz, vxi - b.y, vyi - c.x, vzi - c.y, rj, tgj, tj, (e & kNearBit) != 0);
             }
         }
     } else {
@@ -1317,7 +1350,7 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
                 dy = min_image(dy, pc.L[1], pc.invL[1]);
                 dz = min_image(dz, pc.L[2], pc.invL[2]);
             }
-            pair(dx, dy, dz, b.y, c.x, c.y, rj, tgj, tj, (e & kNearBit) != 0);
+            pair(dx, dy, dz, vxi - b.y, vyi - c.x, vzi - c.y, rj, tgj, tj, (e & kNearBit) != 0);
             e = en;
         }
     }

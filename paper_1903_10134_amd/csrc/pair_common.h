@@ -100,6 +100,20 @@ __device__ __forceinline__ void min_image3(const Geom &g, double &dx, double &dy
     dz = min_image(dz, g.L[2], g.invL[2]);
 }
 
+// Fixed-point coordinate of a 32-byte record: x in [0, L) (s = 2^32 / L) as
+// round(x s) mod 2^32 (a coordinate that rounds up to 2^32 wraps to 0, the
+// same point of the periodic box).
+__device__ __forceinline__ uint32_t qfix(double x, double s)
+{
+    return (uint32_t)(unsigned long long)(long long)__builtin_rint(x * s);
+}
+
+// x_i - x_j of two fixed-point coordinates: the minimum image, in FP32.
+__device__ __forceinline__ float qdiff(uint32_t qi, uint32_t qj, float d)
+{
+    return (float)(int)(qi - qj) * d;
+}
+
 // Hardware dispatches workgroups to the 8 XCDs round robin; remap so that
 // each XCD (and its L2) works through one contiguous chunk of the sorted
 // particles, whose neighbour data it then reuses.
