@@ -68,12 +68,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(void *row, int bytes)
 //
 // Each entry is the neighbour's slot, with kNearBit set when r < r_d and
 // kWrapBit set when the pair is seen through a periodic image (its difference
-// then needs the minimum-image shift).  A row holds the entries with r < r_d
-// first, their exact r^2 at the same positions of a parallel array (R2 = FP32
-// or FP64, the arithmetic of the density pass), then the other entries, with
-// no gap: a row of the usual ~25 entries is one 128-byte line.  Near hits are
-// stored as they are found; far hits wait in LDS until the particle's near
-// count is known.
+// then needs the minimum-image shift).  A row holds its entries with no gap
+// (a row of the usual ~25 entries is one 128-byte line): in candidate order
+// from the register path, near entries first from the general path.  The
+// exact r^2 of the near entries go back to back into a parallel row (R2 =
+// FP32 or FP64, the arithmetic of the density pass), which is all the
+// density pass reads.  In the general path near hits are stored as they are
+// found and far hits wait in LDS until the particle's near count is known.
 
 __device__ __forceinline__ void store_r2(__amdgpu_buffer_rsrc_t r, int k, bool keep, float v)
 {
@@ -121,33 +122,33 @@ __device__ __forceinline__ void flush_far(__amdgpu_buffer_rsrc_t ro, const uint3
     __builtin_amdgcn_raw_buffer_store_b32(e, ro, lane < cf ? (cn + lane) * 4 : kDropOffset, 0, 0);
 }
 
-// Row assembly in LDS (the single-particle sweep): near hits go to nb[0 ..
-// 64) with their r^2 in rb, far hits to fb; flush_row then writes the whole
-// row (near, then far) and the near r^2 with one store each.  A row past
-// kListCap entries is never read; its excess goes to the lane's dump slot.
+// Row assembly in LDS (the single-particle sweep).  The hits of one
+// 64-candidate test (hm: within r_c) go to row positions ct + (hits in lower
+// lanes) of nb, in candidate order, flagged kNearBit when within r_d (mn);
+// the near hits' r^2 go to rb at cn + (near hits in lower lanes), so the
+// density pass reads them back to back.  ct / cn are the row's entries / near
+// entries before this test.  flush_row then writes the row and the near r^2
+// with one store each.  A row past kListCap entries is never read; its
+// excess goes to the lane's dump slot.
 template <typename R2>
-__device__ __forceinline__ void stage_hits(uint32_t *nb, R2 *rb, uint32_t *fb, uint32_t *dump,
-                                           unsigned long long mn, unsigned long long mf, int cn, int cf,
-                                           uint32_t e, double r2)
+__device__ __forceinline__ void stage_hits(uint32_t *nb, R2 *rb, uint32_t *dump, unsigned long long hm,
+                                           unsigned long long mn, int ct, int cn, uint32_t e, double r2)
 {
     const int lane = threadIdx.x & 63;
+    const bool hit = __builtin_amdgcn_inverse_ballot_w64(hm);
     const bool near = __builtin_amdgcn_inverse_ballot_w64(mn);
-    const bool far = __builtin_amdgcn_inverse_ballot_w64(mf);
+    const int p = lanes_below(hm, ct);
     const int pn = lanes_below(mn, cn);
-    const int pf = lanes_below(mf, cf) & (kListCap - 1);
-    const bool keep = near && pn < kListCap;
-    *(keep ? nb + pn : dump + lane) = e | kNearBit;
-    if (keep) rb[pn] = (R2)r2;
-    *(far ? fb + pf : dump + lane) = e;
+    *(hit && p < kListCap ? nb + p : dump + lane) = near ? e | kNearBit : e;
+    if (near && pn < kListCap) rb[pn] = (R2)r2;
 }
 
 template <typename R2>
 __device__ __forceinline__ void flush_row(__amdgpu_buffer_rsrc_t ro, __amdgpu_buffer_rsrc_t rr, const uint32_t *nb,
-                                          const R2 *rb, const uint32_t *fb, int cn, int cf)
+                                          const R2 *rb, int ct, int cn)
 {
     const int lane = threadIdx.x & 63;
-    const uint32_t e = lane < cn ? nb[lane] : fb[(lane - cn) & (kListCap - 1)];
-    __builtin_amdgcn_raw_buffer_store_b32(e, ro, lane < cn + cf ? lane * 4 : kDropOffset, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(nb[lane], ro, lane < ct ? lane * 4 : kDropOffset, 0, 0);
     store_r2(rr, lane, lane < cn, rb[lane]);
 }
 
@@ -318,8 +319,8 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
             czj[s] = ld(xs.z, js);
         }
         // the single-particle sweep assembles each row in the wavefront's
-        // LDS past its far buffer (the batch buffers of the general path)
-        uint32_t *const near_lds = far_lds + kListCap;
+        // LDS (where the general path keeps its batch buffers)
+        uint32_t *const row_lds = far_lds;
         R2 *const near_r2 = reinterpret_cast<R2 *>(far_lds + 2 * kListCap);
         // particle i is candidate selfq0 + i of the dz = 0 batch: after the
         // dy = -1 row and the own row's cells left of the own cell
@@ -340,7 +341,7 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
                     const int sq = selfq0 + i;
                     const __amdgpu_buffer_rsrc_t ro = row_rsrc(nl + (size_t)i * kListCap, kListCap * 4);
                     const __amdgpu_buffer_rsrc_t rr = row_rsrc(nlr2 + (size_t)i * kListCap, kListCap * (int)sizeof(R2));
-                    int cn = 0, cf = 0;
+                    int ct = 0, cn = 0;  // row entries, near entries
 #pragma unroll
                     for (int s = 0; s < 6; ++s) {
                         if ((s & 1) && qz[s >> 1] <= 64) continue;
@@ -351,14 +352,13 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
                         const double r2 = exact_r2(dx, dy, dz);
                         unsigned long long hm = __builtin_amdgcn_ballot_w64(r2 < rc2) & vm[s];
                         if ((s >> 1) == 1 && (sq >> 6) == (s & 1)) hm &= ~(1ull << (sq & 63));
-                        const unsigned long long nm = __builtin_amdgcn_ballot_w64(r2 < rd2);
-                        const unsigned long long mn = hm & nm, mf = hm & ~nm;
-                        stage_hits<R2>(near_lds, near_r2, far_lds, dump, mn, mf, cn, cf, (uint32_t)cs[s], r2);
+                        const unsigned long long mn = hm & __builtin_amdgcn_ballot_w64(r2 < rd2);
+                        stage_hits<R2>(row_lds, near_r2, dump, hm, mn, ct, cn, (uint32_t)cs[s], r2);
+                        ct += __popcll(hm);
                         cn += __popcll(mn);
-                        cf += __popcll(mf);
                     }
-                    flush_row<R2>(ro, rr, near_lds, near_r2, far_lds, cn, cf);
-                    if (lane == 0) ncnt[i] = cn | (cf << 16);
+                    flush_row<R2>(ro, rr, row_lds, near_r2, ct, cn);
+                    if (lane == 0) ncnt[i] = cn | ((ct - cn) << 16);
                 }
             }
         };
