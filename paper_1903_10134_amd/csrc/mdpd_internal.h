@@ -49,9 +49,10 @@ struct Soa3c {
 };
 inline Soa3c cview(const Soa3 &a) { return Soa3c{a.x, a.y, a.z}; }
 
-// Everything the force pass reads of a neighbour, packed in one 64-byte
-// record per slot (written by the density pass), so that one neighbour
-// costs one cache-line sector instead of eight scattered ones.
+// Everything the force pass reads of a neighbour, packed in one record per
+// slot (written by the density pass), so that one neighbour costs one
+// sector instead of eight scattered loads: 64 bytes in the FP64 form (this
+// one), 32 in the FP32 form (PartRec32 below).
 struct alignas(16) PartRec {
     double x, y, z;     // position
     double vx, vy, vz;  // half-step velocity (0 for frozen particles)
