@@ -634,17 +634,21 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     // stencil), replica after replica in cell order, have a launch of their
     // own; a small system takes all its cells in that one launch (the second
     // launch would cost more than it saves)
-    std::vector<int> bcells;
+    std::vector<int> bcells, icells;
     const bool one_launch = cells <= kOneListLaunchCells;
     if (s->perstep)
         for (int r = 0; r < nrep; ++r) {
             const int *nc = s->geoms[r].nc;
             for (int cz = 0; cz < nc[2]; ++cz)
                 for (int cy = 0; cy < nc[1]; ++cy)
-                    for (int cx = 0; cx < nc[0]; ++cx)
+                    for (int cx = 0; cx < nc[0]; ++cx) {
+                        const int c = s->cell_off[r] + cx + nc[0] * (cy + nc[1] * cz);
                         if (one_launch || cx == 0 || cx == nc[0] - 1 || cy == 0 || cy == nc[1] - 1 || cz == 0 ||
                             cz == nc[2] - 1)
-                            bcells.push_back(s->cell_off[r] + cx + nc[0] * (cy + nc[1] * cz));
+                            bcells.push_back(c);
+                        else
+                            icells.push_back(c);
+                    }
         }
     const size_t N = (size_t)(n > 0 ? n : 1);
     const int nb_scan = (int)((cells + 4095) / 4096);
@@ -739,8 +743,19 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     ALLOC(s->alloc(&s->work, 9 * 4096));
     Geom *dgeom = nullptr;
     PairConst *dpc = nullptr;
-    int *dcell = nullptr, *dpart = nullptr, *dblk = nullptr, *dbcells = nullptr;
+    int *dcell = nullptr, *dpart = nullptr, *dblk = nullptr, *dbcells = nullptr, *dcrep = nullptr;
     ALLOC(s->alloc(&dbcells, bcells.size() + 1));
+    int *dicells = nullptr;
+    ALLOC(s->alloc(&dicells, icells.size() + 1));
+    // the replica of each cell, for the kernels with one wavefront per cell
+    // (a table lookup instead of a binary search over the cell offsets)
+    std::vector<int> cell_rep;
+    if (nrep > 1) {
+        cell_rep.resize((size_t)cells);
+        for (int r = 0; r < nrep; ++r)
+            for (int c = s->cell_off[r]; c < s->cell_off[r + 1]; ++c) cell_rep[(size_t)c] = r;
+        ALLOC(s->alloc(&dcrep, cell_rep.size()));
+    }
     ALLOC(s->alloc(&dgeom, (size_t)nrep));
     ALLOC(s->alloc(&dpc, (size_t)nrep));
     ALLOC(s->alloc(&dcell, (size_t)nrep + 1));
@@ -750,10 +765,13 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     R.geom = dgeom;
     R.pc = dpc;
     R.cell_off = dcell;
+    R.cell_rep = dcrep;
     R.part_off = dpart;
     R.blk_off = dblk;
     R.flag = s->flags;
     R.bcells = dbcells;
+    R.icells = dicells;
+    R.nicells = (int)icells.size();
 
     auto bail = [&](mdpd_status st) {
         delete s;
@@ -782,6 +800,11 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
                                s->st);
         if (e == hipSuccess && !bcells.empty())
             e = hipMemcpyAsync(dbcells, bcells.data(), bcells.size() * sizeof(int), hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess && !icells.empty())
+            e = hipMemcpyAsync(dicells, icells.data(), icells.size() * sizeof(int), hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess && !cell_rep.empty())
+            e = hipMemcpyAsync(dcrep, cell_rep.data(), cell_rep.size() * sizeof(int), hipMemcpyHostToDevice,
+                               s->st);
         if (e == hipSuccess) e = hipStreamSynchronize(s->st);
         if (e != hipSuccess) return bail(fail(MDPD_E_HIP, "upload of replica tables failed: %s", hipGetErrorString(e)));
     }

@@ -128,10 +128,13 @@ struct Reps {
     const Geom *geom;       // [nrep]
     const PairConst *pc;    // [nrep]; noise keys are set per launch from (seed, step)
     const int *cell_off;    // [nrep + 1]
+    const int *cell_rep;    // [ncells] replica of each global cell (NULL with one replica)
     const int *part_off;    // [nrep + 1]
     const int *blk_off;     // [kLaneCounts][nrep + 1]
     const int *flag;        // [nrep + 1]: 1 = replica r rebuilds its lists this step; [nrep]: any does
     const int *bcells;      // [nbcells] per-step list: global indices of the border cells (a periodic image in the stencil)
+    const int *icells;      // [nicells] per-step list: global indices of the other (interior) cells
+    int nicells;
     int nrep;
     int ncells;             // total cells
     int nbcells;

@@ -172,7 +172,7 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
     const int lane = threadIdx.x & 63;
     uint32_t *const dump = far_lds + kGenBatch * kListCap;
     // the replica of this cell: its lattice, and its cell offsets (global slots)
-    const int rep = __builtin_amdgcn_readfirstlane(find_rep(R.cell_off, R.nrep, cg));
+    const int rep = R.cell_rep ? cload(R.cell_rep, cg) : 0;
     if (!all && cload(R.flag, rep) == 0) return;  // the replica keeps its list this time
     const Geom g = cload(R.geom, rep);
     const int c = cg - cload(R.cell_off, rep);
@@ -483,8 +483,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 {
     if (!all && cload(R.flag, R.nrep) == 0) return;
     __shared__ __align__(16) uint32_t lds[kWavesPerBlock * kFarLds];
-    const int cg = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
-    if (cg >= R.ncells) return;
+    const int w = __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    if (w >= R.nicells) return;
+    const int cg = cload(R.icells, w);
     nlist_cell<R2, false>(R, cg, xs, cstart_all, ncnt, nl, nlr2, lds + (threadIdx.x >> 6) * kFarLds, all);
 }
 
@@ -522,7 +523,7 @@ __device__ __forceinline__ void skin_cell(const Reps &R, int cg, Soa3c xs, const
                                           int *__restrict__ scnt, uint32_t *__restrict__ sl)
 {
     const int lane = threadIdx.x & 63;
-    const int rep = __builtin_amdgcn_readfirstlane(find_rep(R.cell_off, R.nrep, cg));
+    const int rep = R.cell_rep ? cload(R.cell_rep, cg) : 0;
     if (!ALL && cload(R.flag, rep) == 0) return;
     const Geom g = cload(R.geom, rep);
     const int c = cg - cload(R.cell_off, rep);
@@ -1653,15 +1654,15 @@ void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int 
                   uint32_t *nl, void *nlr2, bool all)
 {
     if (R.ncells <= 0) return;
-    const int blocks = (R.ncells + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int blocks = (R.nicells + kWavesPerBlock - 1) / kWavesPerBlock;
     const int bblocks = (R.nbcells * R.list_split + kWavesPerBlock - 1) / kWavesPerBlock;
     if (fp32) {
-        if (R.list_interior)
+        if (R.list_interior && blocks > 0)
             k_nlist_cell<float><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (float *)nlr2, all ? 1 : 0);
         if (bblocks > 0)
             k_nlist_border<float><<<bblocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (float *)nlr2, all ? 1 : 0);
     } else {
-        if (R.list_interior)
+        if (R.list_interior && blocks > 0)
             k_nlist_cell<double><<<blocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (double *)nlr2, all ? 1 : 0);
         if (bblocks > 0)
             k_nlist_border<double><<<bblocks, kBlock, 0, st>>>(R, xs, cstart, ncnt, nl, (double *)nlr2, all ? 1 : 0);
