@@ -749,12 +749,20 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     ALLOC(s->alloc(&dicells, icells.size() + 1));
     // the replica of each cell, for the kernels with one wavefront per cell
     // (a table lookup instead of a binary search over the cell offsets)
-    std::vector<int> cell_rep;
+    // and of each block of the particle launches, lane count after lane count
+    std::vector<int> cell_rep, blk_rep;
+    int *dbrep = nullptr;
     if (nrep > 1) {
         cell_rep.resize((size_t)cells);
         for (int r = 0; r < nrep; ++r)
             for (int c = s->cell_off[r]; c < s->cell_off[r + 1]; ++c) cell_rep[(size_t)c] = r;
         ALLOC(s->alloc(&dcrep, cell_rep.size()));
+        for (int li = 0; li < kLaneCounts; ++li) {
+            const int *bo = &s->blk_off[(size_t)li * (nrep + 1)];
+            for (int r = 0; r < nrep; ++r)
+                for (int b = bo[r]; b < bo[r + 1]; ++b) blk_rep.push_back(r);
+        }
+        ALLOC(s->alloc(&dbrep, blk_rep.size() + 1));
     }
     ALLOC(s->alloc(&dgeom, (size_t)nrep));
     ALLOC(s->alloc(&dpc, (size_t)nrep));
@@ -766,6 +774,7 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
     R.pc = dpc;
     R.cell_off = dcell;
     R.cell_rep = dcrep;
+    R.blk_rep = dbrep;
     R.part_off = dpart;
     R.blk_off = dblk;
     R.flag = s->flags;
@@ -802,6 +811,8 @@ mdpd_status create_impl(int32_t nrep, const mdpd_params *ps, const int64_t *offs
             e = hipMemcpyAsync(dbcells, bcells.data(), bcells.size() * sizeof(int), hipMemcpyHostToDevice, s->st);
         if (e == hipSuccess && !icells.empty())
             e = hipMemcpyAsync(dicells, icells.data(), icells.size() * sizeof(int), hipMemcpyHostToDevice, s->st);
+        if (e == hipSuccess && !blk_rep.empty())
+            e = hipMemcpyAsync(dbrep, blk_rep.data(), blk_rep.size() * sizeof(int), hipMemcpyHostToDevice, s->st);
         if (e == hipSuccess && !cell_rep.empty())
             e = hipMemcpyAsync(dcrep, cell_rep.data(), cell_rep.size() * sizeof(int), hipMemcpyHostToDevice,
                                s->st);

@@ -129,6 +129,7 @@ struct Reps {
     const PairConst *pc;    // [nrep]; noise keys are set per launch from (seed, step)
     const int *cell_off;    // [nrep + 1]
     const int *cell_rep;    // [ncells] replica of each global cell (NULL with one replica)
+    const int *blk_rep;     // per lane count, replica of each block (NULL with one replica)
     const int *part_off;    // [nrep + 1]
     const int *blk_off;     // [kLaneCounts][nrep + 1]
     const int *flag;        // [nrep + 1]: 1 = replica r rebuilds its lists this step; [nrep]: any does
@@ -171,6 +172,17 @@ __device__ __forceinline__ int find_rep(const int *__restrict__ off, int nrep, i
         else hi = mid;
     }
     return lo;
+}
+
+// The replica of block blk of a launch with lane count index li (off: that
+// lane count's block offsets): a table lookup with several replicas (one
+// scalar load instead of a search of dependent loads), 0 with one.
+__device__ __forceinline__ int block_replica(const Reps &R, int li, const int *off, int blk)
+{
+    if (!R.blk_rep) return __builtin_amdgcn_readfirstlane(find_rep(off, R.nrep, blk));
+    int base = 0;
+    for (int l = 0; l < li; ++l) base += R.nblk[l];
+    return cload(R.blk_rep, base + blk);
 }
 
 // Threefry key schedule for key (seed, step): ks2 = 0x1BD11BDA ^ k0 ^ k1 and

@@ -150,9 +150,8 @@ __device__ __forceinline__ int lanes_below(unsigned long long m, int base = 0)
 }
 
 // Pair-list row layout: the kListCap entries of particle i hold its
-// neighbours closer than r_c (kNearBit: r < r_d) with no gap (the per-step
-// list puts the near ones first); the count word packs the two counts (near
-// in bits 0..15, far in bits 16..31).  A row whose counts add up to more
+// neighbours closer than r_c (kNearBit: r < r_d) with no gap; the count
+// word packs the two counts (near in bits 0..15, far in bits 16..31).  A row whose counts add up to more
 // than kListCap is not valid.
 __device__ __forceinline__ int list_near(int packed) { return packed & 0xffff; }
 __device__ __forceinline__ int list_total(int packed) { return (packed & 0xffff) + (packed >> 16); }
@@ -203,7 +202,7 @@ template <int P>
 __device__ __forceinline__ BlockRep block_rep(const Reps &R, int blk)
 {
     const int *off = R.blk_off + lanes_index(P) * (R.nrep + 1);
-    const int r = __builtin_amdgcn_readfirstlane(find_rep(off, R.nrep, blk));
+    const int r = block_replica(R, lanes_index(P), off, blk);
     return BlockRep{r, cload(R.part_off, r) + (blk - cload(off, r)) * (kBlock / P), cload(R.part_off, r + 1)};
 }
 

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kRed) void k_obs_partial(Reps Rp, Soa3c v, const R 
     __shared__ double sh[kObs][kRed];
     double acc[kObs] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int *boff = Rp.blk_off;  // lane count 1
-    const int r = __builtin_amdgcn_readfirstlane(find_rep(boff, Rp.nrep, blockIdx.x));
+    const int r = block_replica(Rp, 0, boff, blockIdx.x);
     const int i = cload(Rp.part_off, r) + (blockIdx.x - cload(boff, r)) * kRed + threadIdx.x;
     const PairConst pc = cload(Rp.pc, r);
     if (i < cload(Rp.part_off, r + 1)) {
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_export(Reps Rp, Soa3c x, Soa3c v, co
                                                    double *rho_out)
 {
     const int *boff = Rp.blk_off;  // lane count 1
-    const int r = __builtin_amdgcn_readfirstlane(find_rep(boff, Rp.nrep, blockIdx.x));
+    const int r = block_replica(Rp, 0, boff, blockIdx.x);
     const int i = cload(Rp.part_off, r) + (blockIdx.x - cload(boff, r)) * kBlock + threadIdx.x;
     if (i >= cload(Rp.part_off, r + 1)) return;
     const size_t id = (size_t)cload(Rp.part_off, r) + (tag[i] & kIdMask);

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(Reps R, Soa3c x, int *__restrict
         *nbuild += (unsigned long long)R.nrep;
     }
     const int *boff = R.blk_off;  // lane count 1
-    const int r = __builtin_amdgcn_readfirstlane(find_rep(boff, R.nrep, blockIdx.x));
+    const int r = block_replica(R, 0, boff, blockIdx.x);
     const int i = cload(R.part_off, r) + (blockIdx.x - cload(boff, r)) * kBlock + threadIdx.x;
     const int n = cload(R.part_off, r + 1);  // end of this replica's slots
     const Geom g = cload(R.geom, r);
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_gather(Reps R, const int *__res
                                                         int all)
 {
     const int *boff = R.blk_off;  // lane count 1
-    const int r = __builtin_amdgcn_readfirstlane(find_rep(boff, R.nrep, blockIdx.x));
+    const int r = block_replica(R, 0, boff, blockIdx.x);
     const int i = cload(R.part_off, r) + (blockIdx.x - cload(boff, r)) * kBlock + threadIdx.x;
     if (i >= cload(R.part_off, r + 1)) return;
     if (!all && cload(R.flag, r) == 0) {
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_copy_back(Reps R, Soa3c tx, Soa3c tv
                                                       uint8_t *__restrict__ typ, Soa3 xb)
 {
     const int *boff = R.blk_off;  // lane count 1
-    const int r = __builtin_amdgcn_readfirstlane(find_rep(boff, R.nrep, blockIdx.x));
+    const int r = block_replica(R, 0, boff, blockIdx.x);
     if (cload(R.flag, r) == 0) return;
     const int i = cload(R.part_off, r) + (blockIdx.x - cload(boff, r)) * kBlock + threadIdx.x;
     if (i >= cload(R.part_off, r + 1)) return;
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_ingest(Reps R, const double *__restr
                                                    uint8_t *__restrict__ typ, int *__restrict__ status)
 {
     const int *boff = R.blk_off;  // lane count 1
-    const int r = __builtin_amdgcn_readfirstlane(find_rep(boff, R.nrep, blockIdx.x));
+    const int r = block_replica(R, 0, boff, blockIdx.x);
     const int i = cload(R.part_off, r) + (blockIdx.x - cload(boff, r)) * kBlock + threadIdx.x;
     if (i >= cload(R.part_off, r + 1)) return;
     const Geom g = cload(R.geom, r);
