@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(Reps R, int m, int nb
         if (c < m) {
             const int v = out[c] + add;
             out[c] = v;
-            if (all || cload(R.flag, find_rep(R.cell_off, R.nrep, c))) cstart[c] = v;
+            if (all || cload(R.flag, R.cell_rep ? R.cell_rep[c] : 0)) cstart[c] = v;
         }
     }
 }
