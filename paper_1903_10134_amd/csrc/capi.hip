@@ -474,6 +474,13 @@ mdpd_status make_geom(const mdpd_params *p, Geom *g)
             --nc;
         }
         if (nc < 1) nc = 1;
+        // two cells on the y or z axis are each other's neighbours on both
+        // sides, so a cell's search spans the whole axis either way: one cell
+        // of twice the size gives the same candidates with half the cells
+        // (the per-step list then sweeps twice the particles per wavefront
+        // against one load of its candidates).  The x axis keeps two: the
+        // list's row pieces along x need a cell on either side.
+        if (nc == 2 && a > 0) nc = 1;
         g->L[a] = L;
         g->nc[a] = nc;
         g->s[a] = nc / L;

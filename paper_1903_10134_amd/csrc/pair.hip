@@ -195,7 +195,8 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
     // if it is, so the minimum image by rounding picks exactly the pairs
     // through a boundary and gives the same difference as the general path's
     // explicit shift (a pair whose difference rounds to L/2 itself is more
-    // than r_c apart either way).  A thin y or z axis (one or two cells)
+    // than r_c apart either way).  A thin y or z axis (one cell; two are
+    // merged into one when the lattice is made, but also handled here)
     // takes it too: each distinct cell of the axis is visited once (offsets
     // 0 and +1 with two cells, 0 with one), every difference is taken through
     // the minimum image on that axis (every cell touches its boundary), and
