@@ -120,10 +120,14 @@ __device__ __forceinline__ int block_inclusive_scan(int v, int *sh, int *total)
     return v;
 }
 
-// Local exclusive scan of tile b of counts into out; clears counts.
+// Local exclusive scan of tile b of counts into out; clears counts.  With a
+// single tile (cstart set) the scan is complete here: the offsets also go to
+// cstart (of rebuilt replicas) and the total to out[m] and cstart[m], as
+// k_scan_add would write them.
 __global__ __launch_bounds__(kScanThreads) void k_scan_local(Reps R, int m, int *__restrict__ counts,
                                                              int *__restrict__ out,
-                                                             int *__restrict__ bsum, int all)
+                                                             int *__restrict__ bsum, int all,
+                                                             int *__restrict__ cstart)
 {
     if (!all && cload(R.flag, R.nrep) == 0) return;
     __shared__ int sh[kScanThreads / 64];
@@ -143,10 +147,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_local(Reps R, int m, int 
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
         const int idx = base + k;
-        if (idx < m) out[idx] = run;
+        if (idx < m) {
+            out[idx] = run;
+            if (cstart && (all || cload(R.flag, R.cell_rep ? R.cell_rep[idx] : 0))) cstart[idx] = run;
+        }
         run += v[k];
     }
-    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+    if (threadIdx.x == 0) {
+        bsum[blockIdx.x] = total;
+        if (cstart) out[m] = cstart[m] = total;
+    }
 }
 
 // Adds to tile b of out the sum of the totals of tiles 0 .. b-1 (the first
@@ -541,8 +551,9 @@ void launch_rebuild_sort(hipStream_t st, int n, const Reps &R, Soa3 x, Soa3 v, S
         return;
     }
     if (n > 0) k_bin<<<R.nblk[0], kBlock, 0, st>>>(R, cview(x), key, slot, counts, all, step_ctr, ovf_count, nbuild);
-    k_scan_local<<<nb, kScanThreads, 0, st>>>(R, m, counts, cnew, bsum, all);
-    k_scan_add<<<nb, kScanThreads, 0, st>>>(R, m, nb, bsum, cnew, cstart, all);
+    // one tile: the local scan is the whole scan
+    k_scan_local<<<nb, kScanThreads, 0, st>>>(R, m, counts, cnew, bsum, all, nb == 1 ? cstart : nullptr);
+    if (nb > 1) k_scan_add<<<nb, kScanThreads, 0, st>>>(R, m, nb, bsum, cnew, cstart, all);
     if (n > 0) {
         const Soa3c none{nullptr, nullptr, nullptr};
         k_scatter_id<<<blocks_for(n), kBlock, 0, st>>>(R, n, key, slot, cnew, tag, tmpid, all);
