@@ -1,15 +1,24 @@
 // pair.hip -- the pair passes of one mDPD timestep on gfx950.
 //
-//   k_skin_build  one wavefront per cell: the neighbours within r_c + skin of
-//                 every particle of the cell at the build positions (exact
-//                 FP64 test), written to a fixed-capacity skin list; runs only
-//                 in the steps the gate asks for a rebuild
-//   k_density     every step: the skin entries closer than r_c at the current
-//                 positions (exact FP64 test, the neighbour test of the
-//                 method) become the step's pair list, each with a flag for
-//                 r < r_d, and the many-body density
-//                 rho_i = sum_{j != i, r < r_d} w_rho(r_ij) (Sec. 2.1) is
-//                 summed over them; also packs the neighbour records
+//   k_nlist_cell, k_nlist_border
+//                 skin 0, every step: one wavefront per cell builds the pair
+//                 list of its particles from the candidates of the cells
+//                 around it (exact FP64 test), each entry flagged for
+//                 r < r_d, and stores the near entries' r^2
+//   k_density_list
+//                 skin 0: the many-body density
+//                 rho_i = sum_{j != i, r < r_d} w_rho(r_ij) (Sec. 2.1) from
+//                 the stored r^2; packs the neighbour records the force pass
+//                 gathers (32 bytes in the FP32 form, 64 in the FP64 form)
+//   k_skin_build  skin > 0: one wavefront per cell: the neighbours within
+//                 r_c + skin of every particle of the cell at the build
+//                 positions (exact FP64 test), written to a fixed-capacity
+//                 skin list; runs only in the steps the gate asks for a
+//                 rebuild
+//   k_density     skin > 0, every step: the skin entries closer than r_c at
+//                 the current positions (the same exact test) become the
+//                 step's pair list, each with a flag for r < r_d, and the
+//                 density is summed over them; also packs the records
 //   k_phi         boundary volume fraction of fluid particles at the predicted
 //                 positions (direct cell scan, only where a sub-cell mask puts
 //                 a frozen particle in reach) and the predictor-corrector flag
