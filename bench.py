@@ -68,11 +68,10 @@ BYTES_LIST = 24
 # (SQ_INSTS_VALU, wave instructions).  Valid for the kernels as profiled;
 # they are re-measured whenever a kernel changes.
 PROFILED = {
-    "nlist": {"read": 88428544, "write": 181342208, "valu_wave_instr": 112.3e6},
-    "force": {"read": 300699648, "write": 101424128, "valu_wave_instr": 74.1e6},
-    "density": {"read": 193949696, "write": 37934080, "valu_wave_instr": 14.2e6},
+    "nlist": {"read": 80076800, "write": 181343232, "valu_wave_instr": 116.0e6},
+    "force": {"read": 300763136, "write": 101424128, "valu_wave_instr": 74.1e6},
+    "density": {"read": 126658560, "write": 37933056, "valu_wave_instr": 14.2e6},
 }
-
 
 def list_candidates(x, box, rc=1.0):
     """Number of (i, j != i) candidate pairs the cell-list search tests: every

@@ -340,7 +340,8 @@ void launch_rebuild_sort(hipStream_t st, int n, const Reps &R, Soa3 x, Soa3 v, S
                          unsigned long long *nbuild = nullptr);
 // Per-step neighbour list (skin 0) of the replicas whose flag is set (every
 // replica with all): the pairs closer than r_c at the positions xs, the near
-// ones (r < r_d) first with their r^2 in nlr2 (FP32 or FP64 as rho).
+// ones (r < r_d) flagged, with their r^2 in nlr2 (FP32 or FP64 as rho; FP32
+// rows split into 16-entry heads and a tail area, n slots x 64 entries in all).
 void launch_nlist(hipStream_t st, bool fp32, const Reps &R, Soa3c xs, const int *cstart, int *ncnt,
                   uint32_t *nl, void *nlr2, bool all);
 // Density from the per-step list's stored r^2, and the packed records.

@@ -81,9 +81,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(void *row, int bytes)
 // (a row of the usual ~25 entries is one 128-byte line): in candidate order
 // from the register path, near entries first from the general path.  The
 // exact r^2 of the near entries go back to back into a parallel row (R2 =
-// FP32 or FP64, the arithmetic of the density pass), which is all the
-// density pass reads.  In the general path near hits are stored as they are
-// found and far hits wait in LDS until the particle's near count is known.
+// FP32 or FP64, the arithmetic of the density pass; layout at R2Row), which
+// is all the density pass reads.  In the general path near hits are stored
+// as they are found and far hits wait in LDS until the particle's near count
+// is known.
 
 __device__ __forceinline__ void store_r2(__amdgpu_buffer_rsrc_t r, int k, bool keep, float v)
 {
@@ -98,6 +99,63 @@ __device__ __forceinline__ void store_r2(__amdgpu_buffer_rsrc_t r, int k, bool k
     __builtin_amdgcn_raw_buffer_store_b64(w, r, keep ? k * 8 : kDropOffset, 0, 0);
 }
 
+// The near-r^2 row of particle i (n: the slots of all replicas).  FP64: the
+// kListCap entries at i kListCap.  FP32: the first kR2Head entries of every
+// row side by side, 64 bytes a particle, so two neighbouring particles share
+// a 128-byte line and the density pass fetches half a line for a row of the
+// usual ten or so entries (a full line with rows kListCap apart); entries
+// kR2Head and up of particle i in a tail area after the n heads.
+constexpr int kR2Head = 16;
+
+template <typename R2>
+struct R2Row {
+    static constexpr bool kSplit = sizeof(R2) == 4;
+    __amdgpu_buffer_rsrc_t head, tail;
+    __device__ __forceinline__ R2Row(R2 *base, size_t n, int i)
+    {
+        if constexpr (kSplit) {
+            head = row_rsrc(base + (size_t)i * kR2Head, kR2Head * 4);
+            tail = row_rsrc(base + n * kR2Head + (size_t)i * (kListCap - kR2Head), (kListCap - kR2Head) * 4);
+        } else {
+            head = tail = row_rsrc(base + (size_t)i * kListCap, kListCap * 8);
+        }
+    }
+    // this lane's entry k, when keep
+    __device__ __forceinline__ void put(int k, bool keep, R2 v) const
+    {
+        if constexpr (kSplit) {
+            store_r2(head, k, keep && k < kR2Head, v);
+            store_r2(tail, k - kR2Head, keep && k >= kR2Head, v);
+        } else {
+            store_r2(head, k, keep, v);
+        }
+    }
+    // a whole row: lane k holds entry k, count entries (wave-uniform)
+    __device__ __forceinline__ void put_row(int count, R2 v) const
+    {
+        const int lane = threadIdx.x & 63;
+        if constexpr (kSplit) {
+            store_r2(head, lane, lane < count && lane < kR2Head, v);
+            if (count > kR2Head) store_r2(tail, lane - kR2Head, lane >= kR2Head && lane < count, v);
+        } else {
+            store_r2(head, lane, lane < count, v);
+        }
+    }
+};
+
+// Where the density pass reads entry k of particle i's near-r^2 row: head + k
+// below kR2Head, tail + k from there (the same pointer twice in FP64).
+template <typename R2>
+__device__ __forceinline__ void r2_row_ptrs(const R2 *base, size_t n, int i, const R2 *&head, const R2 *&tail)
+{
+    if constexpr (sizeof(R2) == 4) {
+        head = base + (size_t)i * kR2Head;
+        tail = base + n * kR2Head + (size_t)i * (kListCap - kR2Head) - kR2Head;
+    } else {
+        head = tail = base + (size_t)i * kListCap;
+    }
+}
+
 // Hits of one 64-candidate test for particle i: mn marks the lanes whose
 // candidate is within r_d, mf those within r_c but not r_d; cn / cf are i's
 // near / far counts before this test.  A near hit goes to row position
@@ -108,7 +166,7 @@ __device__ __forceinline__ void store_r2(__amdgpu_buffer_rsrc_t r, int k, bool k
 // the row are dropped by the store range check, and the far buffer index is
 // kept inside the buffer.
 template <typename R2>
-__device__ __forceinline__ void emit_hits(__amdgpu_buffer_rsrc_t ro, __amdgpu_buffer_rsrc_t rr, uint32_t *fb,
+__device__ __forceinline__ void emit_hits(__amdgpu_buffer_rsrc_t ro, const R2Row<R2> &rr, uint32_t *fb,
                                           uint32_t *dump, unsigned long long mn, unsigned long long mf, int cn,
                                           int cf, uint32_t e, double r2)
 {
@@ -118,7 +176,7 @@ __device__ __forceinline__ void emit_hits(__amdgpu_buffer_rsrc_t ro, __amdgpu_bu
     const int pn = lanes_below(mn, cn);
     const int pf = lanes_below(mf, cf) & (kListCap - 1);
     __builtin_amdgcn_raw_buffer_store_b32(e | kNearBit, ro, near ? pn * 4 : kDropOffset, 0, 0);
-    store_r2(rr, pn, near, (R2)r2);
+    rr.put(pn, near, (R2)r2);
     *(far ? fb + pf : dump + lane) = e;
 }
 
@@ -153,12 +211,12 @@ __device__ __forceinline__ void stage_hits(uint32_t *nb, R2 *rb, uint32_t *dump,
 }
 
 template <typename R2>
-__device__ __forceinline__ void flush_row(__amdgpu_buffer_rsrc_t ro, __amdgpu_buffer_rsrc_t rr, const uint32_t *nb,
+__device__ __forceinline__ void flush_row(__amdgpu_buffer_rsrc_t ro, const R2Row<R2> &rr, const uint32_t *nb,
                                           const R2 *rb, int ct, int cn)
 {
     const int lane = threadIdx.x & 63;
     __builtin_amdgcn_raw_buffer_store_b32(nb[lane], ro, lane < ct ? lane * 4 : kDropOffset, 0, 0);
-    store_r2(rr, lane, lane < cn, rb[lane]);
+    rr.put_row(cn, rb[lane]);
 }
 
 // LDS of one wavefront: the far buffers of up to kGenBatch particles (one in
@@ -183,6 +241,7 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
     // the replica of this cell: its lattice, and its cell offsets (global slots)
     const int rep = R.cell_rep ? cload(R.cell_rep, cg) : 0;
     if (!all && cload(R.flag, rep) == 0) return;  // the replica keeps its list this time
+    const size_t nslots = (size_t)cload(R.part_off, R.nrep);
     const Geom g = cload(R.geom, rep);
     const int c = cg - cload(R.cell_off, rep);
     const int *__restrict__ cstart = cstart_all + cload(R.cell_off, rep);
@@ -350,7 +409,7 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
                     const int i = i0 + ib + u;
                     const int sq = selfq0 + i;
                     const __amdgpu_buffer_rsrc_t ro = row_rsrc(nl + (size_t)i * kListCap, kListCap * 4);
-                    const __amdgpu_buffer_rsrc_t rr = row_rsrc(nlr2 + (size_t)i * kListCap, kListCap * (int)sizeof(R2));
+                    const R2Row<R2> rr(nlr2, nslots, i);
                     int ct = 0, cn = 0;  // row entries, near entries
 #pragma unroll
                     for (int s = 0; s < 6; ++s) {
@@ -466,8 +525,7 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
                         const unsigned long long nm = __builtin_amdgcn_ballot_w64(r2 < rd2);
                         const unsigned long long mn = hm & nm, mf = hm & ~nm;
                         const int base = bcast_i(cnt, u);
-                        emit_hits<R2>(row_rsrc(nl + (size_t)i * kListCap, kListCap * 4),
-                                      row_rsrc(nlr2 + (size_t)i * kListCap, kListCap * (int)sizeof(R2)),
+                        emit_hits<R2>(row_rsrc(nl + (size_t)i * kListCap, kListCap * 4), R2Row<R2>(nlr2, nslots, i),
                                       far_lds + u * kListCap, dump, mn, mf, base & 0xffff, base >> 16,
                                       (uint32_t)slot | (sx != 0.0 || sy != 0.0 || sz != 0.0 ? kWrapBit : 0u), r2);
                         if (lane == u) cnt += __popcll(mn) + (__popcll(mf) << 16);
@@ -742,8 +800,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     R acc = 0;
     if (list_total(packed) <= kListCap) {
         const int nnear = list_near(packed);
-        const R *lr = nlr2 + (size_t)i * kListCap;
-        for (int k = sub; k < nnear; k += P) acc += w_rho<R>(pc, lr[k]);
+        const R *hd, *tl;
+        r2_row_ptrs<R>(nlr2, (size_t)cload(Rp.part_off, Rp.nrep), i, hd, tl);
+        for (int k = sub; k < nnear; k += P) acc += w_rho<R>(pc, *(k < kR2Head ? hd + k : tl + k));
     } else {
         const double xi = xs.x[i], yi = xs.y[i], zi = xs.z[i];
         for_each_row(g, xi, yi, zi, cstart, [&](int b, int e) {
