@@ -194,8 +194,8 @@ __device__ __forceinline__ void flush_far(__amdgpu_buffer_rsrc_t ro, const uint3
 // lanes) of nb, in candidate order, flagged kNearBit when within r_d (mn);
 // the near hits' r^2 go to rb at cn + (near hits in lower lanes), so the
 // density pass reads them back to back.  ct / cn are the row's entries / near
-// entries before this test.  flush_row then writes the row and the near r^2
-// with one store each.  A row past kListCap entries is never read; its
+// entries before this test.  flush_row (BatchRows::flush in the interior
+// kernel) then writes the row and the near r^2 with one store each.  A row past kListCap entries is never read; its
 // excess goes to the lane's dump slot.
 template <typename R2>
 __device__ __forceinline__ void stage_hits(uint32_t *nb, R2 *rb, uint32_t *dump, unsigned long long hm,
@@ -218,6 +218,52 @@ __device__ __forceinline__ void flush_row(__amdgpu_buffer_rsrc_t ro, const R2Row
     __builtin_amdgcn_raw_buffer_store_b32(nb[lane], ro, lane < ct ? lane * 4 : kDropOffset, 0, 0);
     rr.put_row(cn, rb[lane]);
 }
+
+// The rows of the particles i0 .. i0 + nb - 1 (nb <= 64, one batch of a
+// cell's sweep) behind one buffer resource per array, whose range is the
+// batch: particle u's row starts at the scalar offset u times the row's
+// bytes, and a lane's entry k at the vector offset k times the entry's, so
+// the sweep builds no descriptor and no address per particle.  A kept entry
+// lies inside the batch and a dropped one (kDropOffset) beyond it however
+// the range check counts the scalar offset.
+template <typename R2>
+struct BatchRows {
+    static constexpr bool kSplit = sizeof(R2) == 4;
+    __amdgpu_buffer_rsrc_t nlr, head, tail;
+    __device__ __forceinline__ BatchRows(uint32_t *nl, R2 *nlr2, size_t n, int i0, int nb)
+    {
+        nlr = row_rsrc(nl + (size_t)i0 * kListCap, nb * kListCap * 4);
+        if constexpr (kSplit) {
+            head = row_rsrc(nlr2 + (size_t)i0 * kR2Head, nb * kR2Head * 4);
+            tail = row_rsrc(nlr2 + n * kR2Head + (size_t)i0 * (kListCap - kR2Head), nb * (kListCap - kR2Head) * 4);
+        } else {
+            head = tail = row_rsrc(nlr2 + (size_t)i0 * kListCap, nb * kListCap * 8);
+        }
+    }
+    // particle u's row staged in LDS: entries nb[0 .. ct), near r^2 rb[0 .. cn)
+    __device__ __forceinline__ void flush(int u, const uint32_t *nb, const R2 *rb, int ct, int cn) const
+    {
+        const int lane = threadIdx.x & 63;
+        __builtin_amdgcn_raw_buffer_store_b32(nb[lane], nlr, lane < ct ? lane * 4 : kDropOffset, u * kListCap * 4,
+                                              0);
+        const R2 v = rb[lane];
+        if constexpr (kSplit) {
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), head,
+                                                  lane < cn && lane < kR2Head ? lane * 4 : kDropOffset,
+                                                  u * kR2Head * 4, 0);
+            if (cn > kR2Head)
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), tail,
+                                                      lane < cn && lane >= kR2Head ? (lane - kR2Head) * 4
+                                                                                   : kDropOffset,
+                                                      u * (kListCap - kR2Head) * 4, 0);
+        } else {
+            typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+            const unsigned long long b = (unsigned long long)__double_as_longlong((double)v);
+            const u32x2 w = {(unsigned)b, (unsigned)(b >> 32)};
+            __builtin_amdgcn_raw_buffer_store_b64(w, head, lane < cn ? lane * 8 : kDropOffset, u * kListCap * 8, 0);
+        }
+    }
+};
 
 // LDS of one wavefront: the far buffers of up to kGenBatch particles (one in
 // the interior path) and one slot per lane for lanes without a far hit.
@@ -404,13 +450,12 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
                 const int nic = ni - ib < 64 ? ni - ib : 64;
                 const int me = i0 + ib + (lane < nic ? lane : 0);
                 const double pxi = ld(xs.x, me), pyi = ld(xs.y, me), pzi = ld(xs.z, me);
-                for (int u = part; u < nic; u += nsplit) {
+                // stages particle u's row in LDS: ct entries, cn of them near
+                auto test = [&](int u, int &ct, int &cn) {
                     const double xi = bcast_d(pxi, u), yi = bcast_d(pyi, u), zi = bcast_d(pzi, u);
-                    const int i = i0 + ib + u;
-                    const int sq = selfq0 + i;
-                    const __amdgpu_buffer_rsrc_t ro = row_rsrc(nl + (size_t)i * kListCap, kListCap * 4);
-                    const R2Row<R2> rr(nlr2, nslots, i);
-                    int ct = 0, cn = 0;  // row entries, near entries
+                    const int sq = selfq0 + i0 + ib + u;
+                    ct = 0;
+                    cn = 0;
 #pragma unroll
                     for (int s = 0; s < 6; ++s) {
                         if ((s & 1) && qz[s >> 1] <= 64) continue;
@@ -426,8 +471,31 @@ __device__ __forceinline__ void nlist_cell(const Reps &R, int cg, Soa3c xs, cons
                         ct += __popcll(hm);
                         cn += __popcll(mn);
                     }
-                    flush_row<R2>(ro, rr, row_lds, near_r2, ct, cn);
-                    if (lane == 0) ncnt[i] = cn | ((ct - cn) << 16);
+                };
+                if constexpr (!BORDER) {
+                    // interior cells: the batch's rows behind one descriptor
+                    // per array, and its counts stored once (lane u holds
+                    // particle u's); the border kernel, which holds more
+                    // scalar state across this loop, would spill those
+                    // descriptors, so there each particle builds its own
+                    const BatchRows<R2> rows(nl, nlr2, nslots, i0 + ib, nic);
+                    int counts = 0;
+                    for (int u = part; u < nic; u += nsplit) {
+                        int ct, cn;
+                        test(u, ct, cn);
+                        rows.flush(u, row_lds, near_r2, ct, cn);
+                        if (lane == u) counts = cn | ((ct - cn) << 16);
+                    }
+                    if (lane < nic && lane >= part && (lane - part) % nsplit == 0) ncnt[i0 + ib + lane] = counts;
+                } else {
+                    for (int u = part; u < nic; u += nsplit) {
+                        const int i = i0 + ib + u;
+                        int ct, cn;
+                        test(u, ct, cn);
+                        flush_row<R2>(row_rsrc(nl + (size_t)i * kListCap, kListCap * 4), R2Row<R2>(nlr2, nslots, i),
+                                      row_lds, near_r2, ct, cn);
+                        if (lane == 0) ncnt[i] = cn | ((ct - cn) << 16);
+                    }
                 }
             }
         };
