@@ -104,6 +104,10 @@ def small_cases():
         "slab_8x8x2.5": W.bulk(box=(8.0, 8.0, 2.5), n=960, seed=8),
         "dense_cluster": dense_cluster(),
         "mixed_types": mixed_types(),
+        # density 12: about 21 neighbours within r_d per particle, so most
+        # FP32 near-r^2 rows run past their 16-entry head into the tail
+        # area, and about 50 within r_c, so some rows overflow
+        "dense_L6_rho12": W.bulk(L=6.0, density=12.0, seed=9),
     }
 
 
