@@ -68,9 +68,9 @@ BYTES_LIST = 24
 # (SQ_INSTS_VALU, wave instructions).  Valid for the kernels as profiled;
 # they are re-measured whenever a kernel changes.
 PROFILED = {
-    "nlist": {"read": 79728640, "write": 181342208, "valu_wave_instr": 120.9e6},
-    "force": {"read": 300763136, "write": 101424128, "valu_wave_instr": 74.1e6},
-    "density": {"read": 126658560, "write": 37933056, "valu_wave_instr": 14.2e6},
+    "nlist": {"read": 79714304, "write": 181342208, "valu_wave_instr": 120.9e6},
+    "force": {"read": 300464128, "write": 101422080, "valu_wave_instr": 75.7e6},
+    "density": {"read": 126672896, "write": 37933056, "valu_wave_instr": 14.2e6},
 }
 
 def list_candidates(x, box, rc=1.0):

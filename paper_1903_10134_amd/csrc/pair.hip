@@ -1400,21 +1400,24 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
         // Each lane loads its own neighbour's record: two 16-byte loads of one
         // 32-byte sector (regrouping a quad's four records through LDS, as
         // the 64-byte records do, measured slower here: force pass 166
-        // against 159 us at 1M particles).  The next entry and its record are
-        // loaded one iteration ahead (155 against 159 us).  Entries past the
-        // row stand in as slot 0.
+        // against 159 us at 1M particles).  The next record is loaded one
+        // iteration ahead (155 against 159 us) and the entry after it two
+        // ahead, so the record loads never wait on the row (146 against 147
+        // us).  Entries past the row stand in as slot 0.
         const int cnt = list_total(packed);
         uint32_t e = sub < cnt ? lst[sub] : 0u;
+        uint32_t en = sub + P < cnt ? lst[sub + P] : 0u;
         uint4 p0 = ((const uint4 *)(r32 + (int)(e & kSlotMask)))[0];  // qx qy qz vx
         uint4 p1 = ((const uint4 *)(r32 + (int)(e & kSlotMask)))[1];  // vy vz rho tag
         for (int k = sub; k < cnt; k += P) {
-            const uint32_t en = k + P < cnt ? lst[k + P] : 0u;
+            const uint32_t enn = k + 2 * P < cnt ? lst[k + 2 * P] : 0u;
             const uint4 *rn = (const uint4 *)(r32 + (int)(en & kSlotMask));
             const uint4 n0 = rn[0], n1 = rn[1];
             pair(qdiff(qxi, p0.x, pc.qd[0]), qdiff(qyi, p0.y, pc.qd[1]), qdiff(qzi, p0.z, pc.qd[2]),
                  vxf - __uint_as_float(p0.w), vyf - __uint_as_float(p1.x), vzf - __uint_as_float(p1.y),
                  __uint_as_float(p1.z), p1.w, MT ? (int)typ[e & kSlotMask] : 0, (e & kNearBit) != 0);
             e = en;
+            en = enn;
             p0 = n0;
             p1 = n1;
         }
