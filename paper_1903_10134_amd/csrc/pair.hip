@@ -1439,9 +1439,14 @@ __device__ __forceinline__ void force_particle(const PairConst &pc, const Geom &
         unsigned char *const qb = xch + (threadIdx.x >> 2) * kQuadXch;
         const int q = threadIdx.x & 3;
         const int cnt = list_total(packed);
+        // the next entry is loaded one iteration ahead (two types, ring cells
+        // at 1M particles: 227 against 201 us); slot 0 stands in for a
+        // missing entry
+        uint32_t en = sub < cnt ? lst[sub] : 0u;
         for (int k0 = 0; k0 < cnt; k0 += P) {
             const int k = k0 + sub;
-            const uint32_t e = k < cnt ? lst[k] : 0u;  // slot 0 stands in for a missing entry
+            const uint32_t e = en;
+            en = k + P < cnt ? lst[k + P] : 0u;
             const int j = (int)(e & kSlotMask);
             const int jq[4] = {__builtin_amdgcn_mov_dpp(j, 0x00, 0xF, 0xF, false),
                                __builtin_amdgcn_mov_dpp(j, 0x55, 0xF, 0xF, false),
