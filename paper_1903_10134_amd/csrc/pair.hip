@@ -1022,8 +1022,11 @@ __global__ __launch_bounds__(kBlock) void k_mark_wall_cells(Reps R, Soa3c xs, co
 // scanned.  Each wavefront takes 64 slots, packs the ones to scan in LDS, and
 // runs them in rounds of 64 / P particles with P lanes each, so skipped
 // particles leave no idle lanes.
+// Without the wall normal the kernel fits the budget of six waves per SIMD
+// (80 VGPRs, no spills, against 92 and five waves unbounded: ring cells at
+// 1M particles 174 -> 167 us per step for phi and the corrector).
 template <int P, bool NRM>
-__global__ __launch_bounds__(kBlock) void k_phi(Reps R, Soa3c xs, const uint32_t *__restrict__ tag,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NRM ? 1 : 6))) void k_phi(Reps R, Soa3c xs, const uint32_t *__restrict__ tag,
                                                 const int *__restrict__ cstart_all,
                                                 const uint8_t *__restrict__ wmask, int *__restrict__ flag, Soa3 vh)
 {
